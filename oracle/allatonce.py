@@ -1,0 +1,170 @@
+"""The all-at-once system of eq. (2.4): layout, operator, right-hand side.
+
+Test infrastructure only (see ``oracle/__init__.py``).
+
+Paper, Sec. 2: with v = [v_0, ..., v_nt] (each N values) and
+V = [V_0, ..., V_{nt-1}], V_n = [V_{n,1}, ..., V_{n,s}], the system is
+
+    [ Phi   Psi1 ] [v]   [b]
+    [ Psi2  Theta] [V] = [f]
+
+    Phi   : block lower bidiagonal, M on the diagonal, -M below it
+    Psi1  : -(tau b^T (x) M) in block (n+1, n), zero first block row
+    Psi2  : (e (x) K) in block (n, n), zero last block column
+    Theta : I_nt (x) (I_s (x) M + tau A (x) K)
+
+with M = I here (finite differences).  b holds the initial condition:
+b_0 = u0 and b_{n>=1} = 0 for homogeneous Dirichlet data.  The stage right
+hand side is f_{n,i} = f(x, t_n + c_i tau), t_n = n tau.
+
+The vector of unknowns is x = [v; V]: (nt+1) blocks of v, then nt*s blocks of
+V in (step, stage) order; U = N (nt (s+1) + 1) values in total.
+
+Pinned by: the layout formula against the DoF counts of Table 1; the dense
+operator against sequential stepping (eq. (2.2)-(2.3)) and against the block
+apply (tests/test_oracle_allatonce.py).
+"""
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import grid, tableau
+
+
+@dataclass
+class Problem:
+    n: int                 # interior nodes per axis
+    dim: int               # 2 or 3
+    s: int                 # Radau IIA stages
+    nt: int                # time steps
+    T: float = 1.0         # final time
+    kappa: Optional[np.ndarray] = None   # nodal diffusivity (N,), None = 1
+
+    A: np.ndarray = field(init=False, repr=False)
+    b: np.ndarray = field(init=False, repr=False)
+    c: np.ndarray = field(init=False, repr=False)
+
+    def __post_init__(self):
+        self.A, self.b, self.c = tableau.radau_iia(self.s)
+
+    @property
+    def N(self):
+        return self.n ** self.dim
+
+    @property
+    def tau(self):
+        return self.T / self.nt
+
+    @property
+    def h(self):
+        return grid.spacing(self.n)
+
+    @property
+    def U(self):
+        return self.N * (self.nt * (self.s + 1) + 1)
+
+    @property
+    def UV(self):
+        return self.N * self.nt * self.s
+
+    def stage_times(self):
+        """(nt, s) array of t_n + c_i tau."""
+        return (np.arange(self.nt)[:, None] + self.c[None, :]) * self.tau
+
+    def K(self):
+        return grid.stiffness(self.n, self.dim, self.kappa)
+
+
+def unknowns(N, nt, s):
+    """Number of unknowns of eq. (2.4): (nt+1) v-blocks plus nt*s stage blocks."""
+    return N * (nt * (s + 1) + 1)
+
+
+def split(prob, x):
+    """View x as v of shape (nt+1, N) and V of shape (nt, s, N)."""
+    N, nt, s = prob.N, prob.nt, prob.s
+    v = x[: (nt + 1) * N].reshape(nt + 1, N)
+    V = x[(nt + 1) * N:].reshape(nt, s, N)
+    return v, V
+
+
+def join(v, V):
+    return np.concatenate([np.asarray(v).ravel(), np.asarray(V).ravel()])
+
+
+def rhs(prob, f, u0):
+    """Right-hand side [b; f]: b_0 = u0, b_{n>=1} = 0, f in (nt, s, N) order."""
+    v = np.zeros((prob.nt + 1, prob.N))
+    v[0] = u0
+    return join(v, np.asarray(f, float).reshape(prob.nt, prob.s, prob.N))
+
+
+def blocks(prob, sparse=True):
+    """The four blocks (Phi, Psi1, Psi2, Theta) of eq. (2.4) as Kronecker products."""
+    kr = sp.kron if sparse else np.kron
+    eye = (lambda m: sp.identity(m, format="csr")) if sparse else np.eye
+    N, nt, s, tau = prob.N, prob.nt, prob.s, prob.tau
+    K = prob.K() if sparse else prob.K().toarray()
+    IN = eye(N)
+    sub = np.eye(nt + 1, k=-1)                    # ones at (n+1, n)
+    Phi = kr(np.eye(nt + 1) - sub, IN)
+    Esub = np.zeros((nt + 1, nt))
+    Esub[np.arange(1, nt + 1), np.arange(nt)] = 1.0
+    Psi1 = -kr(Esub, kr(tau * prob.b[None, :], IN))
+    Ediag = np.zeros((nt, nt + 1))
+    Ediag[np.arange(nt), np.arange(nt)] = 1.0
+    Psi2 = kr(Ediag, kr(np.ones((s, 1)), K))
+    Theta_hat = kr(np.eye(s), IN) + tau * kr(prob.A, K)
+    Theta = kr(np.eye(nt), Theta_hat)
+    return Phi, Psi1, Psi2, Theta
+
+
+def operator(prob, sparse=True):
+    """The all-at-once matrix of eq. (2.4), dense (tiny problems) or sparse."""
+    Phi, Psi1, Psi2, Theta = blocks(prob, sparse)
+    if sparse:
+        return sp.bmat([[Phi, Psi1], [Psi2, Theta]], format="csr")
+    return np.block([[Phi, Psi1], [Psi2, Theta]])
+
+
+def theta_hat(prob, K=None):
+    """The stage matrix I_s (x) I + tau A (x) K of eq. (2.3), sparse."""
+    K = prob.K() if K is None else K
+    return (sp.kron(sp.identity(prob.s), sp.identity(prob.N))
+            + prob.tau * sp.kron(prob.A, K)).tocsc()
+
+
+def apply_blockwise(prob, x, K=None, transpose=False):
+    """y = A x (or A^T x) one block row at a time, never forming A.
+
+    Forward rows:  y_{v,0} = v_0;
+                   y_{v,n+1} = v_{n+1} - v_n - tau sum_i b_i V_{n,i};
+                   y_{V,n,i} = V_{n,i} + K (v_n + tau sum_j a_ij V_{n,j}).
+    Transposed rows follow from the transposed blocks:
+                   y_{v,n} = x_{v,n} - x_{v,n+1} + K sum_i x_{V,n,i}  (n < nt),
+                   y_{v,nt} = x_{v,nt};
+                   y_{V,n,j} = x_{V,n,j} + tau K sum_i a_ij x_{V,n,i}
+                               - tau b_j x_{v,n+1}.
+    """
+    K = prob.K() if K is None else K
+    tau, A, b = prob.tau, prob.A, prob.b
+    v, V = split(prob, np.asarray(x, float))
+    yv = np.empty_like(v)
+    yV = np.empty_like(V)
+    if not transpose:
+        yv[0] = v[0]
+        for n in range(prob.nt):
+            yv[n + 1] = v[n + 1] - v[n] - tau * np.tensordot(b, V[n], axes=(0, 0))
+            for i in range(prob.s):
+                w = v[n] + tau * np.tensordot(A[i], V[n], axes=(0, 0))
+                yV[n, i] = V[n, i] + K @ w
+    else:
+        yv[prob.nt] = v[prob.nt]
+        for n in range(prob.nt):
+            yv[n] = v[n] - v[n + 1] + K @ V[n].sum(axis=0)
+            for j in range(prob.s):
+                mix = tau * np.tensordot(A[:, j], V[n], axes=(0, 0))
+                yV[n, j] = V[n, j] + K @ mix - tau * b[j] * v[n + 1]
+    return join(yv, yV)

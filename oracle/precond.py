@@ -1,0 +1,212 @@
+"""Block preconditioners of Sec. 3 and FGMRES (Algorithm 1, right preconditioning).
+
+Test infrastructure only (see ``oracle/__init__.py``).
+
+Ideal preconditioner, eq. (3.1):  P = [[S, Psi1], [0, Theta]] with the Schur
+complement S = Phi - Psi1 Theta^{-1} Psi2.  With M = I, S is block lower
+bidiagonal with identity diagonal blocks and sub-diagonal blocks -I + X,
+X = tau (b^T (x) I) Theta_hat^{-1} (e (x) K).
+
+Practical preconditioner, eqs. (3.2)-(3.3): Theta is replaced by
+Theta-tilde -- a fixed number k of GMRES iterations on each step's stage
+matrix Theta_hat from a zero guess, right-preconditioned by Rana's
+block-lower-triangular stage preconditioner -- and S by S-tilde built with
+the same Theta-tilde:  S-tilde = blockdiag(M) [[I], [-I + X~, I], ...],
+X~ = tau (b^T (x) I) Theta-tilde^{-1} (e (x) K).
+
+Applying z = P^{-1} r is block back-substitution:
+    z_V = Theta^{-1} r_V                          (independent per step)
+    t_{v,0} = r_{v,0},  t_{v,n+1} = r_{v,n+1} + tau sum_i b_i z_{V,n,i}
+    z_{v,0} = t_{v,0},  z_{v,n+1} = t_{v,n+1} + z_{v,n} - X z_{v,n}
+(the M^{-1} step of S-tilde is the identity since M = I).
+
+Rana's stage preconditioner (cited, not defined, in the paper; reading): the
+Crout factor A_RK = L U (U unit upper) gives P_int = I_s (x) M + tau L (x) K,
+solved by forward substitution over the stages with the diagonal blocks
+M + tau L_ii K inverted by ``cycles`` multigrid V-cycles (or exactly).
+
+Pinned by: (A P^{-1} - I)^2 = 0 (minimal polynomial of degree two, Sec. 3) on
+dense tiny systems; FGMRES with the exact P converging in at most two steps;
+the inner GMRES against a brute-force Krylov least-squares minimiser; Rana
+with s = 1 being exact (tests/test_oracle_precond.py).
+"""
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from . import allatonce, multigrid, tableau
+
+
+# ----------------------------------------------------------------------------
+# GMRES (Algorithm 1 with P_L = I; modified Gram-Schmidt Arnoldi)
+# ----------------------------------------------------------------------------
+def gmres(apply_op, apply_prec, b, k, tol=0.0):
+    """k iterations of right-preconditioned GMRES from x = 0 (no restart).
+
+    Returns (x, iterations).  Stops early on an exact breakdown or when the
+    least-squares residual drops to tol * beta.
+    """
+    beta = np.linalg.norm(b)
+    if beta == 0.0:
+        return np.zeros_like(b), 0
+    Vb = [b / beta]
+    Z = []
+    H = np.zeros((k + 1, k))
+    m = 0
+    for j in range(k):
+        z = apply_prec(Vb[j])
+        Z.append(z)
+        w = apply_op(z)
+        for i in range(j + 1):
+            H[i, j] = Vb[i] @ w
+            w = w - H[i, j] * Vb[i]
+        H[j + 1, j] = np.linalg.norm(w)
+        m = j + 1
+        e1 = np.zeros(m + 1)
+        e1[0] = beta
+        y, *_ = np.linalg.lstsq(H[: m + 1, :m], e1, rcond=None)
+        res = np.linalg.norm(e1 - H[: m + 1, :m] @ y)
+        if H[j + 1, j] == 0.0 or res <= tol * beta:
+            break
+        Vb.append(w / H[j + 1, j])
+    e1 = np.zeros(m + 1)
+    e1[0] = beta
+    y, *_ = np.linalg.lstsq(H[: m + 1, :m], e1, rcond=None)
+    x = np.zeros_like(b)
+    for i in range(m):
+        x = x + y[i] * Z[i]
+    return x, m
+
+
+# ----------------------------------------------------------------------------
+# Stage-level pieces
+# ----------------------------------------------------------------------------
+class StageOps:
+    """Theta_hat, Rana's preconditioner and the shifted-block solvers of one problem."""
+
+    def __init__(self, prob, inner_k=3, inner_tol=0.0, cycles=1, omega=None,
+                 nu1=1, nu2=1, exact_blocks=False):
+        self.prob = prob
+        self.K = prob.K()
+        self.Th = allatonce.theta_hat(prob, self.K)
+        self.L, _ = tableau.crout(prob.A)
+        self.inner_k = inner_k
+        self.inner_tol = inner_tol
+        self.cycles = cycles
+        self.omega = omega if omega is not None else (0.8 if prob.dim == 2 else 6.0 / 7.0)
+        self.nu1, self.nu2 = nu1, nu2
+        self.exact_blocks = exact_blocks
+        tau = prob.tau
+        self.hier = [multigrid.Hierarchy(self.K, prob.n, prob.dim, tau * self.L[i, i])
+                     for i in range(prob.s)]
+        self._lu_blocks = None
+        self._lu_theta = None
+
+    def block_solve(self, i, rhs):
+        """Inexact (or exact) inverse of I + tau L_ii K."""
+        if self.exact_blocks:
+            if self._lu_blocks is None:
+                self._lu_blocks = [spla.splu(h.ops[0].tocsc()) for h in self.hier]
+            return self._lu_blocks[i].solve(rhs)
+        return multigrid.solve(self.hier[i], rhs, self.cycles, self.omega, self.nu1, self.nu2)
+
+    def rana(self, r):
+        """Forward substitution with I_s (x) I + tau L (x) K; r, z shape (s, N)."""
+        s, tau = self.prob.s, self.prob.tau
+        z = np.zeros_like(r)
+        for i in range(s):
+            rhs = r[i].copy()
+            for l in range(i):
+                rhs -= tau * self.L[i, l] * (self.K @ z[l])
+            z[i] = self.block_solve(i, rhs)
+        return z
+
+    def theta_apply(self, x):
+        return self.Th @ x
+
+    def theta_tilde_inv(self, r):
+        """Theta-tilde^{-1} r for one step: inner GMRES(k) with Rana."""
+        s, N = self.prob.s, self.prob.N
+        x, _ = gmres(self.theta_apply,
+                     lambda v: self.rana(v.reshape(s, N)).ravel(),
+                     np.asarray(r, float).ravel(), self.inner_k, self.inner_tol)
+        return x.reshape(s, N)
+
+    def theta_inv(self, r):
+        """Exact Theta_hat^{-1} r for one step."""
+        if self._lu_theta is None:
+            self._lu_theta = spla.splu(self.Th)
+        return self._lu_theta.solve(np.asarray(r, float).ravel()).reshape(self.prob.s, self.prob.N)
+
+
+def apply_preconditioner(ops, r, exact=False):
+    """z = P-tilde^{-1} r (or P^{-1} r when exact=True) by block back-substitution."""
+    prob = ops.prob
+    nt, s, N, tau = prob.nt, prob.s, prob.N, prob.tau
+    rv, rV = allatonce.split(prob, np.asarray(r, float))
+    solve_step = ops.theta_inv if exact else ops.theta_tilde_inv
+    zV = np.empty((nt, s, N))
+    for n in range(nt):
+        zV[n] = solve_step(rV[n])
+    tv = rv.copy()
+    for n in range(nt):
+        tv[n + 1] = rv[n + 1] + tau * np.tensordot(prob.b, zV[n], axes=(0, 0))
+    zv = np.empty_like(tv)
+    zv[0] = tv[0]
+    for n in range(nt):
+        y = solve_step(np.tile(ops.K @ zv[n], (s, 1)))
+        Xz = tau * np.tensordot(prob.b, y, axes=(0, 0))
+        zv[n + 1] = tv[n + 1] + zv[n] - Xz
+    return allatonce.join(zv, zV)
+
+
+def dense_ideal_preconditioner(prob):
+    """The matrix P of eq. (3.1) for tiny problems (dense)."""
+    Phi, Psi1, Psi2, Theta = [np.asarray(B.toarray() if hasattr(B, "toarray") else B)
+                              for B in allatonce.blocks(prob, sparse=True)]
+    S = Phi - Psi1 @ np.linalg.solve(Theta, Psi2)
+    Z = np.zeros((Theta.shape[0], Phi.shape[1]))
+    return np.block([[S, Psi1], [Z, Theta]])
+
+
+# ----------------------------------------------------------------------------
+# Outer FGMRES (Algorithm 1, P_L = I, FP64), restarted
+# ----------------------------------------------------------------------------
+def fgmres(apply_A, apply_P, rhs, restart=30, tol=1e-8, maxit=100, x0=None):
+    """Right-preconditioned restarted FGMRES; stops on the true relative residual.
+
+    Returns (x, iterations, history of true relative residuals at exits).
+    """
+    x = np.zeros_like(rhs) if x0 is None else np.array(x0, float)
+    nb = np.linalg.norm(rhs)
+    its = 0
+    hist = []
+    while True:
+        r = rhs - apply_A(x)
+        rel = np.linalg.norm(r) / nb if nb > 0 else 0.0
+        hist.append(rel)
+        if rel <= tol or its >= maxit:
+            return x, its, hist
+        beta = np.linalg.norm(r)
+        Vb = [r / beta]
+        Z = []
+        H = np.zeros((restart + 1, restart))
+        m = 0
+        for j in range(restart):
+            its += 1
+            z = apply_P(Vb[j])
+            Z.append(z)
+            w = apply_A(z)
+            for i in range(j + 1):
+                H[i, j] = Vb[i] @ w
+                w = w - H[i, j] * Vb[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            m = j + 1
+            e1 = np.zeros(m + 1)
+            e1[0] = beta
+            y, *_ = np.linalg.lstsq(H[: m + 1, :m], e1, rcond=None)
+            est = np.linalg.norm(e1 - H[: m + 1, :m] @ y)
+            if est <= tol * nb or H[j + 1, j] == 0.0 or its >= maxit:
+                break
+            Vb.append(w / H[j + 1, j])
+        for i in range(m):
+            x = x + y[i] * Z[i]
