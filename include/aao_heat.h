@@ -1,0 +1,187 @@
+/*
+ * aao_heat.h -- C ABI of the MI355X all-at-once Radau IIA heat solver.
+ *
+ * Problem (paper Sec. 2, eq. (2.1)): u_t - div(kappa grad u) = f on the unit
+ * square (dim = 2) or cube (dim = 3), homogeneous Dirichlet data, u(0) = u0.
+ * Space: 5/7-point finite differences on n interior nodes per axis,
+ * h = 1/(n+1), so the mass matrix is M = I and K = -div(kappa grad)_h.
+ * Time: s-stage Radau IIA, nt steps of tau = T/nt.  Collecting the update
+ * eq. (2.2) and the stage systems eq. (2.3) of every step gives the
+ * all-at-once system eq. (2.4),  A x = [b; f].
+ *
+ * VECTOR LAYOUT (every double* vector argument below, length U):
+ *   x = [v_0, ..., v_nt, V_{0,1}, ..., V_{0,s}, ..., V_{nt-1,s}]
+ *   U = N (nt (s+1) + 1),  N = n^dim; each block is N contiguous FP64 values
+ *   with x fastest: node (i, j[, k]) (0-based) at index i + n j (+ n^2 k),
+ *   coordinates ((i+1)h, (j+1)h[, (k+1)h]).
+ *
+ * OWNERSHIP: vector arguments are caller-owned DEVICE pointers (HBM of the
+ * current HIP device), never retained after the call returns.  The handle
+ * owns host metadata only; its device memory is one caller-provided
+ * workspace (aao_set_workspace), which must outlive the handle's use.
+ * Host pointers are marked "host".
+ *
+ * STREAMS: all work is enqueued on the handle's stream (aao_set_stream;
+ * default: the null stream).  aao_apply_* and aao_assemble_rhs return once
+ * enqueued.  aao_solve / aao_solve_adjoint synchronise the stream once per
+ * outer iteration and return when finished.
+ *
+ * ERRORS: every entry point returns an aao_status and never throws;
+ * aao_last_error() gives a message for the last failure on a handle.
+ * Calls on one handle must not overlap (one host thread at a time).
+ */
+#ifndef AAO_HEAT_H
+#define AAO_HEAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum aao_status {
+  AAO_OK = 0,
+  AAO_NOT_CONVERGED = 1,       /* maxit reached; x holds the last iterate     */
+  AAO_INVALID_ARG = -1,        /* bad size, null pointer, unsupported option  */
+  AAO_HIP_ERROR = -2,          /* a HIP runtime call failed                   */
+  AAO_NONFINITE = -3,          /* NaN/Inf met in the Krylov recurrence        */
+  AAO_WORKSPACE_TOO_SMALL = -4,
+  AAO_NO_WORKSPACE = -5        /* a device call before aao_set_workspace      */
+} aao_status;
+
+/* Precision in which the preconditioner P-tilde is applied (Sec. 4,
+ * approaches A1/A2/A5).  The system itself, the outer FGMRES and its
+ * residuals are always FP64.  BF16/FP16 store the multigrid vectors of the
+ * shifted-block solves in 16 bits with FP32 arithmetic; the inner GMRES,
+ * Rana coupling and the S-tilde sweep then run in FP32. */
+typedef enum aao_precision {
+  AAO_PREC_FP64 = 0,
+  AAO_PREC_FP32 = 1,
+  AAO_PREC_BF16 = 2,
+  AAO_PREC_FP16 = 3
+} aao_precision;
+
+/* Problem description (Sec. 2).  kappa: host pointer to N nodal
+ * diffusivities (> 0), copied at creation, or NULL for kappa = 1.  A face
+ * between two interior nodes carries their harmonic mean, a face to the
+ * boundary the interior node's value. */
+typedef struct aao_desc {
+  int dim;                 /* 2 or 3                                          */
+  int n;                   /* interior nodes per axis, >= 2                   */
+  int s;                   /* Radau IIA stages, 1..3                          */
+  int nt;                  /* time steps, >= 1                                */
+  double T;                /* final time, > 0                                 */
+  const double* kappa;     /* host, N values, or NULL                          */
+} aao_desc;
+
+/* Solver options.  Fill with aao_default_opts, then override. */
+typedef struct aao_opts {
+  int restart;             /* outer FGMRES restart length (Algorithm 1)       */
+  int maxit;               /* maximum outer iterations                        */
+  double tol;              /* stop when ||rhs - A x|| <= tol ||rhs|| (FP64)    */
+  int inner_k;             /* GMRES iterations per Theta-tilde application    */
+  int cycles;              /* V-cycles per shifted-block solve                 */
+  int nu1, nu2;            /* Jacobi sweeps before / after coarse correction  */
+  double omega;            /* Jacobi weight; 0 = 0.8 (2D) or 6/7 (3D)         */
+  int precision;           /* aao_precision of P-tilde                         */
+} aao_opts;
+
+/* Solve statistics (host struct filled by aao_solve*). */
+typedef struct aao_stats {
+  int outer_iterations;    /* total FGMRES iterations (preconditioner calls)  */
+  int restarts;            /* restart cycles begun                            */
+  double relres;           /* final true relative residual, FP64              */
+  double time_ms;          /* wall time of the solve (device work included)   */
+  double precond_ms;       /* time inside P-tilde applications                */
+  double history[128];     /* relative residual estimate per iteration        */
+  int history_len;
+} aao_stats;
+
+typedef struct aao_problem aao_problem;   /* opaque handle */
+
+/* Defaults: restart 30, maxit 100, tol 1e-8, inner_k 3, cycles 1,
+ * nu1 = nu2 = 2, omega 0, precision FP64. */
+void aao_default_opts(aao_opts* o);
+
+/* Build a handle: Radau IIA tableau by collocation, Crout factor of A_RK
+ * (Rana's stage preconditioner), multigrid hierarchy of the shifted blocks
+ * I + tau L_ii K.  Host-only work; no device memory is touched.
+ * Returns AAO_INVALID_ARG for unsupported sizes or options. */
+int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out);
+
+/* Bytes of device workspace needed by every call on this handle. */
+int aao_workspace_size(const aao_problem* h, size_t* bytes);
+
+/* Hand over a device workspace of at least aao_workspace_size bytes
+ * (alignment 256).  Uploads the handle's constant tables into it, on the
+ * handle's stream.  The workspace stays caller-owned. */
+int aao_set_workspace(aao_problem* h, void* dev_ptr, size_t bytes);
+
+/* Stream for all later work (a hipStream_t; NULL = default stream). */
+int aao_set_stream(aao_problem* h, void* stream);
+
+/* Release host metadata and pinned host buffers.  The workspace is not freed. */
+int aao_destroy(aao_problem* h);
+
+/* Host copies of the tableau: A (s*s, row-major), b (s), c (s).  Any of the
+ * pointers may be NULL. */
+int aao_get_tableau(const aao_problem* h, double* A, double* b, double* c);
+
+/* N = n^dim and U = N (nt (s+1) + 1). */
+int aao_sizes(const aao_problem* h, int64_t* N, int64_t* U);
+
+/* y = A x, eq. (2.4), matrix-free in FP64.  x, y: device, U values, must
+ * not overlap. */
+int aao_apply_A(aao_problem* h, const double* x, double* y);
+
+/* y = A^T x (the transposed blocks of eq. (2.4)).  Same conventions. */
+int aao_apply_AT(aao_problem* h, const double* x, double* y);
+
+/* z = P-tilde^{-1} r, eqs. (3.2)-(3.3): Theta-tilde (inner GMRES with Rana's
+ * preconditioner and multigrid block solves) for all steps at once, the
+ * Psi1 coupling, then the S-tilde forward sweep in time.  Computed in the
+ * handle's precision; r and z are FP64 at the boundary.  The map is
+ * nonlinear in r (inner GMRES).  r, z: device, U values, must not overlap. */
+int aao_apply_P(aao_problem* h, const double* r, double* z);
+
+/* aao_apply_P with the inner settings overridden for this call: inner_k
+ * GMRES iterations per Theta-tilde application (1 <= inner_k <= the
+ * handle's opts.inner_k, which sizes the workspace) and `cycles` V-cycles
+ * per shifted-block solve (>= 1).  As they grow, P-tilde tends to the
+ * ideal P of eq. (3.1), for which A P^{-1} - I is nilpotent of degree two
+ * (Sec. 3). */
+int aao_apply_P_with(aao_problem* h, const double* r, double* z, int inner_k, int cycles);
+
+/* rhs = [b; f] of eq. (2.4): b_0 = u0, b_{n>=1} = 0, then f.
+ * f: device, nt*s*N values in (step, stage, node) order, f_{n,i} sampled
+ * at t_n + c_i tau; u0: device, N values; rhs: device, U values. */
+int aao_assemble_rhs(aao_problem* h, const double* f, const double* u0, double* rhs);
+
+/* Solve A x = rhs by right-preconditioned restarted FGMRES (Algorithm 1 with
+ * P_L = I) in FP64 with P-tilde applied in the handle's precision.
+ * x: device, U values, initial guess on entry, solution on exit.
+ * st: host, may be NULL.  Returns AAO_OK or AAO_NOT_CONVERGED (x holds the
+ * last iterate, st filled) or an error. */
+int aao_solve(aao_problem* h, const double* rhs, double* x, aao_stats* st);
+
+/* Solve A^T lam = g the same way with the transposed preconditioner.
+ * g, lam: device, U values; lam holds the initial guess on entry. */
+int aao_solve_adjoint(aao_problem* h, const double* g, double* lam, aao_stats* st);
+
+/* Gradient of a loss with respect to theta = log kappa at the nodes, given
+ * the forward solution x and the adjoint lam = A^{-T} dL/dx:
+ * g_p = - sum_{n,i} lam_{V,n,i}^T (dK/dtheta_p) w_{n,i},
+ * w_{n,i} = v_n + tau sum_j a_ij V_{n,j}.  x, lam: device, U values;
+ * g: device, N values (overwritten). */
+int aao_grad_logkappa(aao_problem* h, const double* x, const double* lam, double* g);
+
+/* Message of the last failure on h (or of the last failed creation if h is
+ * NULL).  Valid until the next call on h. */
+const char* aao_last_error(const aao_problem* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AAO_HEAT_H */

@@ -136,6 +136,41 @@ def theta_hat(prob, K=None):
             + prob.tau * sp.kron(prob.A, K)).tocsc()
 
 
+def apply_rows(prob, x, rows, K=None):
+    """Selected entries of y = A x, each computed from its own row of eq. (2.4).
+
+    For full-size problems where A x cannot be formed on the host: row r of
+    the v part (block n, node p) or of a stage block (n, i, node p) uses only
+    the K-row of p.  ``rows`` are global indices into the layout of x.
+    """
+    K = prob.K() if K is None else K
+    N, nt, s, tau = prob.N, prob.nt, prob.s, prob.tau
+    x = np.asarray(x)
+    out = np.empty(len(rows))
+    nv = (nt + 1) * N
+
+    def krow(base, p):
+        lo, hi = K.indptr[p], K.indptr[p + 1]
+        return float(K.data[lo:hi] @ x[base + K.indices[lo:hi]])
+
+    for t, r in enumerate(rows):
+        r = int(r)
+        if r < nv:
+            n, p = divmod(r, N)
+            if n == 0:
+                out[t] = x[p]
+            else:
+                Vb = nv + (n - 1) * s * N
+                out[t] = x[r] - x[r - N] - tau * sum(prob.b[j] * x[Vb + j * N + p] for j in range(s))
+        else:
+            q, p = divmod(r - nv, N)
+            n, i = divmod(q, s)
+            Vb = nv + n * s * N
+            kw = krow(n * N, p) + tau * sum(prob.A[i, j] * krow(Vb + j * N, p) for j in range(s))
+            out[t] = x[r] + kw
+    return out
+
+
 def apply_blockwise(prob, x, K=None, transpose=False):
     """y = A x (or A^T x) one block row at a time, never forming A.
 

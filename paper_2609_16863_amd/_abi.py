@@ -1,0 +1,73 @@
+"""ctypes declarations of the C ABI in include/aao_heat.h (argument marshalling only)."""
+import ctypes
+import os
+
+LIB_NAME = "libaao_heat.so"
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), LIB_NAME)
+
+c_int, c_double, c_void_p, c_size_t = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+c_int64 = ctypes.c_int64
+
+AAO_OK = 0
+AAO_NOT_CONVERGED = 1
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "HIP_ERROR", -3: "NONFINITE",
+                -4: "WORKSPACE_TOO_SMALL", -5: "NO_WORKSPACE"}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("dim", c_int), ("n", c_int), ("s", c_int), ("nt", c_int), ("T", c_double),
+                ("kappa", c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("restart", c_int), ("maxit", c_int), ("tol", c_double), ("inner_k", c_int),
+                ("cycles", c_int), ("nu1", c_int), ("nu2", c_int), ("omega", c_double),
+                ("precision", c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("outer_iterations", c_int), ("restarts", c_int), ("relres", c_double),
+                ("time_ms", c_double), ("precond_ms", c_double), ("history", c_double * 128),
+                ("history_len", c_int)]
+
+
+# name -> (restype, argtypes); every entry point declared in include/aao_heat.h
+SIGNATURES = {
+    "aao_default_opts": (None, [ctypes.POINTER(Opts)]),
+    "aao_create_problem": (c_int, [ctypes.POINTER(Desc), ctypes.POINTER(Opts), ctypes.POINTER(c_void_p)]),
+    "aao_workspace_size": (c_int, [c_void_p, ctypes.POINTER(c_size_t)]),
+    "aao_set_workspace": (c_int, [c_void_p, c_void_p, c_size_t]),
+    "aao_set_stream": (c_int, [c_void_p, c_void_p]),
+    "aao_destroy": (c_int, [c_void_p]),
+    "aao_get_tableau": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "aao_sizes": (c_int, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int64)]),
+    "aao_apply_A": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "aao_apply_AT": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "aao_apply_P": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "aao_apply_P_with": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int]),
+    "aao_assemble_rhs": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "aao_solve": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(Stats)]),
+    "aao_solve_adjoint": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(Stats)]),
+    "aao_grad_logkappa": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "aao_last_error": (ctypes.c_char_p, [c_void_p]),
+}
+
+_lib = None
+
+
+def load():
+    """Load the in-tree HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_NAME} is not built; run paper_2609_16863_amd.build.build() "
+                           "(hipcc, gfx950) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

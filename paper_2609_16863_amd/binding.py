@@ -1,0 +1,179 @@
+"""Python binding of the all-at-once heat solver (argument marshalling only).
+
+Every operation runs in the HIP library (libaao_heat.so); PyTorch supplies
+device memory (the workspace and the caller's vectors) and the stream.  There
+is no fallback: a missing library or GPU raises.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _abi
+
+
+class AAOError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_abi.STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class HeatProblem:
+    """All-at-once Radau IIA system for the heat equation on one GPU.
+
+    Parameters follow the paper's problem statement (Sec. 2): ``dim``-D unit
+    domain with ``n`` interior nodes per axis, ``s``-stage Radau IIA, ``nt``
+    steps to final time ``T``; ``kappa`` optional nodal diffusivity (N values,
+    2D only).  Solver options: FGMRES ``restart``/``maxit``/``tol``, inner
+    GMRES iterations ``inner_k``, V-cycles ``cycles`` with ``nu1``/``nu2``
+    Jacobi sweeps, and the preconditioner ``precision``
+    ("fp64" | "fp32" | "bf16" | "fp16").
+    """
+
+    def __init__(self, dim, n, s, nt, T=1.0, kappa=None, *, restart=30, maxit=100, tol=1e-8,
+                 inner_k=3, cycles=1, nu1=2, nu2=2, omega=0.0, precision="fp64", device="cuda"):
+        self._lib = _abi.load()
+        self.dim, self.n, self.s, self.nt, self.T = dim, n, s, nt, float(T)
+        self._kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
+        desc = _abi.Desc(dim, n, s, nt, float(T),
+                         None if self._kappa is None else self._kappa.ctypes.data)
+        opts = _abi.Opts()
+        self._lib.aao_default_opts(ctypes.byref(opts))
+        opts.restart, opts.maxit, opts.tol = restart, maxit, tol
+        opts.inner_k, opts.cycles, opts.nu1, opts.nu2 = inner_k, cycles, nu1, nu2
+        opts.omega = omega
+        opts.precision = _abi.PRECISIONS[precision]
+        self.precision = precision
+        h = ctypes.c_void_p()
+        code = self._lib.aao_create_problem(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h))
+        if code != 0:
+            raise AAOError(code, self._lib.aao_last_error(None).decode())
+        self._h = h
+        Nv, Uv = ctypes.c_int64(), ctypes.c_int64()
+        self._lib.aao_sizes(h, ctypes.byref(Nv), ctypes.byref(Uv))
+        self.N, self.U = Nv.value, Uv.value
+        self.device = torch.device(device)
+        self._ws = None
+        if self.device.type == "cuda":
+            self._attach_workspace()
+
+    # -- lifecycle -----------------------------------------------------------
+    def workspace_bytes(self):
+        b = ctypes.c_size_t()
+        self._check(self._lib.aao_workspace_size(self._h, ctypes.byref(b)))
+        return b.value
+
+    def _attach_workspace(self):
+        nbytes = self.workspace_bytes()
+        self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        self._sync_stream()
+        self._check(self._lib.aao_set_workspace(self._h, _ptr(self._ws), nbytes))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            self._lib.aao_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers -------------------------------------------------------------
+    def _check(self, code):
+        if code not in (0, 1):
+            raise AAOError(code, self._lib.aao_last_error(self._h).decode())
+        return code
+
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self._lib.aao_set_stream(self._h, ctypes.c_void_p(s))
+
+    def _vec(self, t, numel, name):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and t.is_contiguous() and t.numel() == numel):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor with {numel} values")
+        return t
+
+    def tableau(self):
+        A = np.zeros(self.s * self.s)
+        b = np.zeros(self.s)
+        c = np.zeros(self.s)
+        self._check(self._lib.aao_get_tableau(self._h, A.ctypes.data, b.ctypes.data, c.ctypes.data))
+        return A.reshape(self.s, self.s), b, c
+
+    def stage_times(self):
+        _, _, c = self.tableau()
+        tau = self.T / self.nt
+        return (np.arange(self.nt)[:, None] + c[None, :]) * tau
+
+    def empty(self):
+        return torch.empty(self.U, dtype=torch.float64, device=self.device)
+
+    # -- operators -----------------------------------------------------------
+    def apply_A(self, x, out=None):
+        x = self._vec(x, self.U, "x")
+        out = self.empty() if out is None else self._vec(out, self.U, "out")
+        self._sync_stream()
+        self._check(self._lib.aao_apply_A(self._h, _ptr(x), _ptr(out)))
+        return out
+
+    def apply_AT(self, x, out=None):
+        x = self._vec(x, self.U, "x")
+        out = self.empty() if out is None else self._vec(out, self.U, "out")
+        self._sync_stream()
+        self._check(self._lib.aao_apply_AT(self._h, _ptr(x), _ptr(out)))
+        return out
+
+    def apply_P(self, r, out=None, inner_k=None, cycles=None):
+        r = self._vec(r, self.U, "r")
+        out = self.empty() if out is None else self._vec(out, self.U, "out")
+        self._sync_stream()
+        if inner_k is None and cycles is None:
+            self._check(self._lib.aao_apply_P(self._h, _ptr(r), _ptr(out)))
+        else:
+            self._check(self._lib.aao_apply_P_with(self._h, _ptr(r), _ptr(out), int(inner_k),
+                                                   int(cycles)))
+        return out
+
+    def assemble_rhs(self, f, u0, out=None):
+        f = self._vec(f, self.N * self.nt * self.s, "f")
+        u0 = self._vec(u0, self.N, "u0")
+        out = self.empty() if out is None else self._vec(out, self.U, "out")
+        self._sync_stream()
+        self._check(self._lib.aao_assemble_rhs(self._h, _ptr(f), _ptr(u0), _ptr(out)))
+        return out
+
+    def _solve(self, fn, rhs, x0):
+        rhs = self._vec(rhs, self.U, "rhs")
+        x = torch.zeros_like(rhs) if x0 is None else self._vec(x0, self.U, "x0").clone()
+        st = _abi.Stats()
+        self._sync_stream()
+        code = self._check(fn(self._h, _ptr(rhs), _ptr(x), ctypes.byref(st)))
+        stats = {"outer_iterations": st.outer_iterations, "restarts": st.restarts,
+                 "relres": st.relres, "time_ms": st.time_ms, "precond_ms": st.precond_ms,
+                 "history": list(st.history[: st.history_len]), "converged": code == 0}
+        return x, stats
+
+    def solve(self, rhs, x0=None):
+        """FGMRES solve of A x = rhs; returns (x, stats)."""
+        return self._solve(self._lib.aao_solve, rhs, x0)
+
+    def solve_adjoint(self, g, lam0=None):
+        """FGMRES solve of A^T lam = g; returns (lam, stats)."""
+        return self._solve(self._lib.aao_solve_adjoint, g, lam0)
+
+    def grad_logkappa(self, x, lam, out=None):
+        x = self._vec(x, self.U, "x")
+        lam = self._vec(lam, self.U, "lam")
+        out = (torch.empty(self.N, dtype=torch.float64, device=self.device) if out is None
+               else self._vec(out, self.N, "out"))
+        self._sync_stream()
+        self._check(self._lib.aao_grad_logkappa(self._h, _ptr(x), _ptr(lam), _ptr(out)))
+        return out

@@ -1,0 +1,164 @@
+// Internal declarations of the all-at-once heat solver library (not part of
+// the C ABI).  Kernels live in kern_*.hip, host orchestration in solver.hip,
+// the ABI in api.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/aao_heat.h"
+
+namespace aao {
+
+constexpr int SMAX = 3;          // Radau IIA stages supported by the kernels
+constexpr int KMAX = 12;         // inner GMRES iterations per application
+constexpr int MMAX = 120;        // outer FGMRES restart length
+constexpr int DOTS_PER_PASS = 16;
+constexpr int RED_THREADS = 256;
+
+// ---------------------------------------------------------------------------
+// Parameters passed to kernels by value
+// ---------------------------------------------------------------------------
+struct Tab {                     // Runge--Kutta data (Sec. 2)
+  int s;
+  double tau;
+  double A[SMAX * SMAX];         // A_RK, row-major
+  double b[SMAX];
+  double L[SMAX * SMAX];         // Crout lower factor (Rana's preconditioner)
+};
+
+// Face diffusivities for variable kappa: minus/plus side of every node along
+// each axis (already divided by h^2 is NOT applied here).  All null when
+// kappa = 1.
+template <class C>
+struct Faces {
+  const C* m[3];
+  const C* p[3];
+};
+
+// One multigrid level's operator.  Level 0: I + a K (matrix-free 5/7-point).
+// Level >= 1, constant kappa: Galerkin operator M(x)M(x..) + a sum T(x)M..,
+// from 1D tridiagonal factors tri = [Mlo, Md, Mup, Tlo, Td, Tup] (each n).
+template <class C>
+struct LevelOp {
+  int n;
+  int64_t N;
+  C a;             // shift tau * L_ii
+  C ih2;           // 1/h^2 (level 0 only)
+  const C* tri;    // 6 * n (level >= 1)
+  Faces<C> faces;  // level 0, variable kappa
+};
+
+// Precision of storage types.
+template <class T> struct Acc { using type = float; };
+template <> struct Acc<double> { using type = double; };
+
+template <class T> __host__ __device__ inline float to_f(T v);
+template <> __host__ __device__ inline float to_f<float>(float v) { return v; }
+template <> __host__ __device__ inline float to_f<double>(double v) { return (float)v; }
+
+template <class T, class C> __device__ __forceinline__ C ld(const T* p) { return (C)(*p); }
+template <> __device__ __forceinline__ float ld<__half, float>(const __half* p) { return __half2float(*p); }
+template <> __device__ __forceinline__ float ld<__hip_bfloat16, float>(const __hip_bfloat16* p) {
+  return __bfloat162float(*p);
+}
+template <class T, class C> __device__ __forceinline__ void st(T* p, C v) { *p = (T)v; }
+template <> __device__ __forceinline__ void st<__half, float>(__half* p, float v) { *p = __float2half_rn(v); }
+template <> __device__ __forceinline__ void st<__hip_bfloat16, float>(__hip_bfloat16* p, float v) {
+  *p = __float2bfloat16(v);
+}
+
+// Strided batch of vectors: instance b starts at ptr + b * stride.
+template <class T>
+struct BVec {
+  T* ptr;
+  int64_t stride;
+  __host__ __device__ T* at(int b) const { return ptr + (int64_t)b * stride; }
+};
+
+}  // namespace aao
+
+// ---------------------------------------------------------------------------
+// Handle
+// ---------------------------------------------------------------------------
+struct aao_problem {
+  int dim = 2, n = 0, s = 1, nt = 1;
+  double T = 1.0, tau = 1.0, h = 1.0, ih2 = 1.0;
+  int64_t N = 0, U = 0, UV = 0;
+  aao::Tab tab{};
+  double c[aao::SMAX] = {0, 0, 0};
+  double LT[aao::SMAX * aao::SMAX] = {0};   // Crout lower factor of A_RK^T
+  aao_opts opts{};
+  double omega = 0.8;
+  bool vark = false;
+  std::vector<double> kappa;                 // host copy (N) when vark
+
+  // multigrid levels (sizes per axis), shared by all stages
+  std::vector<int> lev_n;
+  std::vector<int64_t> lev_N;
+  std::vector<double> tri_host;              // concatenated 6*n_l per level >= 1
+  std::vector<size_t> tri_off;               // element offset per level (0 for level 0)
+  std::vector<double> faces_host;            // 2*dim*N when vark
+
+  // workspace plan (byte offsets)
+  size_t ws_need = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  struct Plan {
+    size_t tri_d, tri_f, faces_d, faces_f;
+    size_t outV, outZ, outW, outY;           // outer FGMRES
+    size_t inV, inZ, inW, inX;               // inner GMRES (nt instances)
+    size_t rana;                              // Rana right-hand side (nt*N)
+    size_t schurRhs, schurY;                  // S-tilde sweep (s*N)
+    std::vector<size_t> mgX, mgT, mgB, mgR;   // per level, nt instances
+    size_t partial, dscal;                    // reductions / device scalars
+    size_t partial_bytes, dscal_bytes;
+  } plan{};
+  int pi_bytes = 8;                           // inner (GMRES) storage bytes
+  int pm_bytes = 8;                           // multigrid storage bytes
+
+  hipStream_t stream = nullptr;
+  double* hpin = nullptr;                     // pinned host scalars
+  std::string err;
+};
+
+// ---------------------------------------------------------------------------
+// Host-side helpers implemented in setup.cpp / solver.hip / kern_*.hip
+// ---------------------------------------------------------------------------
+namespace aao {
+
+// setup.cpp (host only)
+bool radau_iia(int s, double* A, double* b, double* c);
+void crout_lower(int s, const double* A, double* L);
+void galerkin_1d(int n, double h, std::vector<int>& sizes, std::vector<std::vector<double>>& tri);
+void face_coefficients(int dim, int n, const double* kappa, std::vector<double>& faces);
+
+int status_from_hip(aao_problem* h, hipError_t e, const char* what);
+
+// kern_allatonce.hip
+template <class TX>
+hipError_t launch_apply_A(const aao_problem* h, const TX* x, double* y, hipStream_t st);
+template <class TX>
+hipError_t launch_apply_AT(const aao_problem* h, const TX* x, double* y, hipStream_t st);
+hipError_t launch_sub_from(const double* a, double* y, int64_t n, hipStream_t st);
+template <class TY, class TX>
+hipError_t launch_scale(TY* y, const TX* x, double alpha, int64_t n, hipStream_t st);
+hipError_t launch_assemble_rhs(const aao_problem* h, const double* f, const double* u0, double* rhs,
+                               hipStream_t st);
+hipError_t launch_grad_logkappa(const aao_problem* h, const double* x, const double* lam, double* g,
+                                hipStream_t st);
+template <class TD, class TS>
+hipError_t launch_copy_cast(TD* dst, const TS* src, int64_t n, hipStream_t st);
+template <class T>
+hipError_t launch_fill(T* dst, T v, int64_t n, hipStream_t st);
+
+// solver.hip
+int apply_P(aao_problem* h, const double* r, double* z, int inner_k, int cycles, bool transpose);
+int solve(aao_problem* h, const double* rhs, double* x, aao_stats* st, bool transpose);
+
+}  // namespace aao

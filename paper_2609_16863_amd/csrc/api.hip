@@ -1,0 +1,327 @@
+// C ABI of the all-at-once heat solver (declared in include/aao_heat.h).
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "aao_internal.h"
+
+namespace {
+
+std::string g_create_error;
+
+int fail(aao_problem* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Lay out every device buffer of the handle inside one workspace.
+void plan_workspace(aao_problem* h) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = align256(off);
+    off = o + align256(bytes);
+    return o;
+  };
+  auto& P = h->plan;
+  const int64_t N = h->N, U = h->U, UV = h->UV;
+  const int L = (int)h->lev_n.size();
+  P.tri_d = take(h->tri_host.size() * sizeof(double));
+  P.tri_f = take(h->tri_host.size() * sizeof(float));
+  // faces (2*dim*N) followed by nodal kappa (N)
+  P.faces_d = take(h->vark ? (size_t)(2 * h->dim + 1) * N * sizeof(double) : 0);
+  P.faces_f = take(h->vark ? (size_t)(2 * h->dim + 1) * N * sizeof(float) : 0);
+  const int m = h->opts.restart;
+  const int k = h->opts.inner_k;
+  const size_t pi = (size_t)h->pi_bytes, pm = (size_t)h->pm_bytes;
+  P.outV = take((size_t)(m + 1) * U * sizeof(double));
+  P.outZ = take((size_t)m * U * pi);
+  P.outW = take((size_t)U * sizeof(double));
+  P.outY = take((size_t)U * pi);
+  P.inV = take((size_t)(k + 1) * UV * pi);
+  P.inZ = take((size_t)k * UV * pi);
+  P.inW = take((size_t)UV * pi);
+  P.inX = take((size_t)UV * pi);
+  P.rana = take((size_t)h->nt * N * pi);
+  P.schurRhs = take((size_t)h->s * N * pi);
+  P.schurY = take((size_t)h->s * N * pi);
+  P.mgX.assign(L, 0);
+  P.mgT.assign(L, 0);
+  P.mgB.assign(L, 0);
+  P.mgR.assign(L, 0);
+  for (int l = 0; l < L; ++l) {
+    const size_t bytes = (size_t)h->nt * h->lev_N[l] * (l == 0 ? pi : pm);
+    if (l > 0) {
+      P.mgX[l] = take(bytes);
+      P.mgB[l] = take(bytes);
+    }
+    P.mgT[l] = take(bytes);
+    P.mgR[l] = take(bytes);
+  }
+  P.partial_bytes = (size_t)8192 * aao::DOTS_PER_PASS * sizeof(double) + (size_t)h->nt * 64 *
+                    (aao::KMAX + 2) * sizeof(double);
+  P.partial = take(P.partial_bytes);
+  P.dscal_bytes = (size_t)(h->nt + 1) * 512 * sizeof(double) + (aao::MMAX + 8) * 8 * sizeof(double);
+  P.dscal = take(P.dscal_bytes);
+  h->ws_need = align256(off);
+}
+
+bool valid_opts(const aao_opts* o, std::string& why) {
+  if (o->restart < 1 || o->restart > aao::MMAX) { why = "restart must be in [1, 120]"; return false; }
+  if (o->maxit < 1) { why = "maxit must be >= 1"; return false; }
+  if (!(o->tol > 0.0)) { why = "tol must be > 0"; return false; }
+  if (o->inner_k < 1 || o->inner_k > aao::KMAX) { why = "inner_k must be in [1, 12]"; return false; }
+  if (o->cycles < 1 || o->cycles > 64) { why = "cycles must be in [1, 64]"; return false; }
+  if (o->nu1 < 1 || o->nu2 < 1 || o->nu1 > 16 || o->nu2 > 16) { why = "nu1, nu2 must be in [1, 16]"; return false; }
+  if (o->precision < AAO_PREC_FP64 || o->precision > AAO_PREC_FP16) { why = "unknown precision"; return false; }
+  if (o->omega < 0.0 || o->omega >= 2.0) { why = "omega must be in [0, 2)"; return false; }
+  return true;
+}
+
+}  // namespace
+
+namespace aao {
+int status_from_hip(aao_problem* h, hipError_t e, const char* what) {
+  if (e == hipSuccess) return AAO_OK;
+  return fail(h, AAO_HIP_ERROR, std::string(what) + ": " + hipGetErrorString(e));
+}
+}  // namespace aao
+
+extern "C" {
+
+void aao_default_opts(aao_opts* o) {
+  if (!o) return;
+  o->restart = 30;
+  o->maxit = 100;
+  o->tol = 1e-8;
+  o->inner_k = 3;
+  o->cycles = 1;
+  o->nu1 = 2;
+  o->nu2 = 2;
+  o->omega = 0.0;
+  o->precision = AAO_PREC_FP64;
+}
+
+int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) {
+  if (!d || !out) return fail(nullptr, AAO_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (d->dim != 2 && d->dim != 3) return fail(nullptr, AAO_INVALID_ARG, "dim must be 2 or 3");
+  if (d->n < 2) return fail(nullptr, AAO_INVALID_ARG, "n must be >= 2");
+  if (d->s < 1 || d->s > aao::SMAX) return fail(nullptr, AAO_INVALID_ARG, "s must be 1, 2 or 3");
+  if (d->nt < 1 || d->nt > 65535) return fail(nullptr, AAO_INVALID_ARG, "nt must be in [1, 65535]");
+  if (!(d->T > 0.0) || !std::isfinite(d->T)) return fail(nullptr, AAO_INVALID_ARG, "T must be > 0");
+  const double Nd = std::pow((double)d->n, d->dim);
+  if (Nd > 1.5e9) return fail(nullptr, AAO_INVALID_ARG, "grid too large (N must fit in int32)");
+  aao_opts opts;
+  aao_default_opts(&opts);
+  if (o) opts = *o;
+  std::string why;
+  if (!valid_opts(&opts, why)) return fail(nullptr, AAO_INVALID_ARG, why);
+
+  aao_problem* h = new (std::nothrow) aao_problem();
+  if (!h) return fail(nullptr, AAO_INVALID_ARG, "out of host memory");
+  h->dim = d->dim;
+  h->n = d->n;
+  h->s = d->s;
+  h->nt = d->nt;
+  h->T = d->T;
+  h->tau = d->T / d->nt;
+  h->h = 1.0 / (d->n + 1);
+  h->ih2 = 1.0 / (h->h * h->h);
+  h->N = (int64_t)std::llround(Nd);
+  h->U = h->N * ((int64_t)d->nt * (d->s + 1) + 1);
+  h->UV = h->N * (int64_t)d->nt * d->s;
+  h->opts = opts;
+  h->omega = opts.omega > 0.0 ? opts.omega : (d->dim == 2 ? 0.8 : 6.0 / 7.0);
+  h->pi_bytes = opts.precision == AAO_PREC_FP64 ? 8 : 4;
+  h->pm_bytes = opts.precision == AAO_PREC_FP64 ? 8 : (opts.precision == AAO_PREC_FP32 ? 4 : 2);
+
+  h->tab.s = d->s;
+  h->tab.tau = h->tau;
+  if (!aao::radau_iia(d->s, h->tab.A, h->tab.b, h->c)) {
+    delete h;
+    return fail(nullptr, AAO_INVALID_ARG, "Radau IIA construction failed");
+  }
+  aao::crout_lower(d->s, h->tab.A, h->tab.L);
+  double At[aao::SMAX * aao::SMAX];
+  for (int i = 0; i < d->s; ++i)
+    for (int j = 0; j < d->s; ++j) At[i * d->s + j] = h->tab.A[j * d->s + i];
+  aao::crout_lower(d->s, At, h->LT);
+  for (int i = 0; i < d->s; ++i)
+    if (!(h->tab.L[i * d->s + i] > 0.0) || !(h->LT[i * d->s + i] > 0.0)) {
+      delete h;
+      return fail(nullptr, AAO_INVALID_ARG, "non-positive Crout pivot");
+    }
+
+  if (d->kappa) {
+    h->vark = true;
+    h->kappa.assign(d->kappa, d->kappa + h->N);
+    for (double kv : h->kappa)
+      if (!(kv > 0.0) || !std::isfinite(kv)) {
+        delete h;
+        return fail(nullptr, AAO_INVALID_ARG, "kappa must be finite and > 0");
+      }
+    aao::face_coefficients(d->dim, d->n, d->kappa, h->faces_host);
+    if (d->dim == 3) {
+      delete h;
+      return fail(nullptr, AAO_INVALID_ARG, "variable kappa is supported in 2D only");
+    }
+  }
+
+  std::vector<std::vector<double>> tri;
+  aao::galerkin_1d(d->n, h->h, h->lev_n, tri);
+  h->lev_N.resize(h->lev_n.size());
+  h->tri_off.assign(h->lev_n.size(), 0);
+  for (size_t l = 0; l < h->lev_n.size(); ++l) {
+    h->lev_N[l] = (int64_t)std::llround(std::pow((double)h->lev_n[l], d->dim));
+    h->tri_off[l] = h->tri_host.size();
+    h->tri_host.insert(h->tri_host.end(), tri[l].begin(), tri[l].end());
+  }
+  plan_workspace(h);
+  *out = h;
+  return AAO_OK;
+}
+
+int aao_workspace_size(const aao_problem* h, size_t* bytes) {
+  if (!h || !bytes) return AAO_INVALID_ARG;
+  *bytes = h->ws_need;
+  return AAO_OK;
+}
+
+int aao_set_workspace(aao_problem* h, void* dev_ptr, size_t bytes) {
+  if (!h) return AAO_INVALID_ARG;
+  if (!dev_ptr) return fail(h, AAO_INVALID_ARG, "null workspace");
+  if (((uintptr_t)dev_ptr & 255) != 0) return fail(h, AAO_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (bytes < h->ws_need) return fail(h, AAO_WORKSPACE_TOO_SMALL, "workspace too small");
+  hipError_t e = hipSuccess;
+  if (!h->hpin) {
+    e = hipHostMalloc((void**)&h->hpin, 4096 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+      h->hpin = nullptr;
+      return aao::status_from_hip(h, e, "pinned host scalars");
+    }
+  }
+  h->ws = static_cast<char*>(dev_ptr);
+  h->ws_bytes = bytes;
+  if (!h->tri_host.empty()) {
+    e = hipMemcpyAsync(h->ws + h->plan.tri_d, h->tri_host.data(), h->tri_host.size() * sizeof(double),
+                       hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = aao::launch_copy_cast<float, double>(reinterpret_cast<float*>(h->ws + h->plan.tri_f),
+                                               reinterpret_cast<const double*>(h->ws + h->plan.tri_d),
+                                               (int64_t)h->tri_host.size(), h->stream);
+  }
+  if (e == hipSuccess && h->vark) {
+    const size_t nf = h->faces_host.size();
+    e = hipMemcpyAsync(h->ws + h->plan.faces_d, h->faces_host.data(), nf * sizeof(double),
+                       hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h->ws + h->plan.faces_d + nf * sizeof(double), h->kappa.data(),
+                         h->N * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = aao::launch_copy_cast<float, double>(reinterpret_cast<float*>(h->ws + h->plan.faces_f),
+                                               reinterpret_cast<const double*>(h->ws + h->plan.faces_d),
+                                               (int64_t)(nf + h->N), h->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    h->ws = nullptr;
+    return aao::status_from_hip(h, e, "workspace upload");
+  }
+  return AAO_OK;
+}
+
+int aao_set_stream(aao_problem* h, void* stream) {
+  if (!h) return AAO_INVALID_ARG;
+  h->stream = static_cast<hipStream_t>(stream);
+  return AAO_OK;
+}
+
+int aao_destroy(aao_problem* h) {
+  if (!h) return AAO_INVALID_ARG;
+  if (h->hpin) (void)hipHostFree(h->hpin);
+  delete h;
+  return AAO_OK;
+}
+
+int aao_get_tableau(const aao_problem* h, double* A, double* b, double* c) {
+  if (!h) return AAO_INVALID_ARG;
+  for (int i = 0; i < h->s; ++i) {
+    if (b) b[i] = h->tab.b[i];
+    if (c) c[i] = h->c[i];
+    for (int j = 0; j < h->s; ++j)
+      if (A) A[i * h->s + j] = h->tab.A[i * h->s + j];
+  }
+  return AAO_OK;
+}
+
+int aao_sizes(const aao_problem* h, int64_t* N, int64_t* U) {
+  if (!h) return AAO_INVALID_ARG;
+  if (N) *N = h->N;
+  if (U) *U = h->U;
+  return AAO_OK;
+}
+
+int aao_apply_A(aao_problem* h, const double* x, double* y) {
+  if (!h) return AAO_INVALID_ARG;
+  if (!x || !y || x == y) return fail(h, AAO_INVALID_ARG, "x, y must be distinct device pointers");
+  if (h->vark && !h->ws) return fail(h, AAO_NO_WORKSPACE, "variable kappa needs the workspace");
+  return aao::status_from_hip(h, aao::launch_apply_A<double>(h, x, y, h->stream), "apply_A");
+}
+
+int aao_apply_AT(aao_problem* h, const double* x, double* y) {
+  if (!h) return AAO_INVALID_ARG;
+  if (!x || !y || x == y) return fail(h, AAO_INVALID_ARG, "x, y must be distinct device pointers");
+  if (h->vark && !h->ws) return fail(h, AAO_NO_WORKSPACE, "variable kappa needs the workspace");
+  return aao::status_from_hip(h, aao::launch_apply_AT<double>(h, x, y, h->stream), "apply_AT");
+}
+
+int aao_apply_P(aao_problem* h, const double* r, double* z) {
+  if (!h) return AAO_INVALID_ARG;
+  return aao_apply_P_with(h, r, z, h->opts.inner_k, h->opts.cycles);
+}
+
+int aao_apply_P_with(aao_problem* h, const double* r, double* z, int inner_k, int cycles) {
+  if (!h) return AAO_INVALID_ARG;
+  if (!r || !z || r == z) return fail(h, AAO_INVALID_ARG, "r, z must be distinct device pointers");
+  if (inner_k < 1 || inner_k > h->opts.inner_k) return fail(h, AAO_INVALID_ARG, "inner_k out of range");
+  if (cycles < 1 || cycles > 64) return fail(h, AAO_INVALID_ARG, "cycles out of range");
+  if (!h->ws) return fail(h, AAO_NO_WORKSPACE, "aao_set_workspace first");
+  return aao::apply_P(h, r, z, inner_k, cycles, false);
+}
+
+int aao_assemble_rhs(aao_problem* h, const double* f, const double* u0, double* rhs) {
+  if (!h) return AAO_INVALID_ARG;
+  if (!f || !u0 || !rhs) return fail(h, AAO_INVALID_ARG, "null pointer");
+  return aao::status_from_hip(h, aao::launch_assemble_rhs(h, f, u0, rhs, h->stream), "assemble_rhs");
+}
+
+int aao_solve(aao_problem* h, const double* rhs, double* x, aao_stats* st) {
+  if (!h) return AAO_INVALID_ARG;
+  if (!rhs || !x || rhs == x) return fail(h, AAO_INVALID_ARG, "rhs, x must be distinct device pointers");
+  if (!h->ws) return fail(h, AAO_NO_WORKSPACE, "aao_set_workspace first");
+  return aao::solve(h, rhs, x, st, false);
+}
+
+int aao_solve_adjoint(aao_problem* h, const double* g, double* lam, aao_stats* st) {
+  if (!h) return AAO_INVALID_ARG;
+  if (!g || !lam || g == lam) return fail(h, AAO_INVALID_ARG, "g, lam must be distinct device pointers");
+  if (!h->ws) return fail(h, AAO_NO_WORKSPACE, "aao_set_workspace first");
+  return aao::solve(h, g, lam, st, true);
+}
+
+int aao_grad_logkappa(aao_problem* h, const double* x, const double* lam, double* g) {
+  if (!h) return AAO_INVALID_ARG;
+  if (!x || !lam || !g) return fail(h, AAO_INVALID_ARG, "null pointer");
+  if (h->vark && !h->ws) return fail(h, AAO_NO_WORKSPACE, "aao_set_workspace first");
+  return aao::status_from_hip(h, aao::launch_grad_logkappa(h, x, lam, g, h->stream), "grad_logkappa");
+}
+
+const char* aao_last_error(const aao_problem* h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,281 @@
+// All-at-once operator of eq. (2.4) and its transpose, matrix-free in FP64.
+//
+// One thread owns one grid node p of one time step n and produces every
+// output row touching (n, p): the s stage rows of step n and the update row
+// of v_{n+1}.  The s x s Runge--Kutta mixing is done in registers on K applied
+// to each input block (K is linear, so K w_i = K v_n + tau sum_j a_ij K V_j).
+// Stencil neighbours come through the L1/L2 caches: consecutive lanes own
+// consecutive x, and a workgroup covers whole rows, so each value is fetched
+// from HBM about once per launch.
+#include "aao_internal.h"
+#include "stencil.h"
+
+namespace aao {
+
+namespace {
+
+constexpr int TPB = 256;
+
+template <int DIM, int S, bool VK, class TX>
+__global__ __launch_bounds__(TPB) void k_apply_A(const TX* __restrict__ x, double* __restrict__ y,
+                                                 int n, int N, int nt, double ih2, Tab tab,
+                                                 Faces<double> fc) {
+  const int p = blockIdx.x * TPB + threadIdx.x;
+  if (p >= N) return;
+  const int step = blockIdx.y;
+  int i, j, k;
+  node_coords<DIM>(p, n, i, j, k);
+  const int64_t NN = N;
+  const TX* v = x + (int64_t)step * NN;
+  const TX* V = x + ((int64_t)(nt + 1) + (int64_t)step * S) * NN;
+  const double Kv = ih2 * stencil_K<DIM, VK, TX, double>(v, p, i, j, k, n, N, fc);
+  double KV[S], Vp[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    KV[q] = ih2 * stencil_K<DIM, VK, TX, double>(V + q * NN, p, i, j, k, n, N, fc);
+    Vp[q] = ld<TX, double>(V + q * NN + p);
+  }
+  double* yV = y + ((int64_t)(nt + 1) + (int64_t)step * S) * NN;
+  double upd = 0.0;
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    double mix = 0.0;
+#pragma unroll
+    for (int q = 0; q < S; ++q) mix += tab.A[r * S + q] * KV[q];
+    yV[r * NN + p] = Vp[r] + Kv + tab.tau * mix;
+    upd += tab.b[r] * Vp[r];
+  }
+  const double vp = ld<TX, double>(v + p);
+  y[(int64_t)(step + 1) * NN + p] = ld<TX, double>(v + NN + p) - vp - tab.tau * upd;
+  if (step == 0) y[p] = vp;
+}
+
+// Transposed rows:  y_{v,n} = x_{v,n} - x_{v,n+1} + K sum_i x_{V,n,i}  (n < nt)
+//                   y_{v,nt} = x_{v,nt}
+//                   y_{V,n,j} = x_{V,n,j} + tau K sum_i a_ij x_{V,n,i} - tau b_j x_{v,n+1}
+template <int DIM, int S, bool VK, class TX>
+__global__ __launch_bounds__(TPB) void k_apply_AT(const TX* __restrict__ x, double* __restrict__ y,
+                                                  int n, int N, int nt, double ih2, Tab tab,
+                                                  Faces<double> fc) {
+  const int p = blockIdx.x * TPB + threadIdx.x;
+  if (p >= N) return;
+  const int step = blockIdx.y;
+  int i, j, k;
+  node_coords<DIM>(p, n, i, j, k);
+  const int64_t NN = N;
+  const TX* V = x + ((int64_t)(nt + 1) + (int64_t)step * S) * NN;
+  double KX[S];
+  double sumK = 0.0;
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    KX[q] = ih2 * stencil_K<DIM, VK, TX, double>(V + q * NN, p, i, j, k, n, N, fc);
+    sumK += KX[q];
+  }
+  const double xv = ld<TX, double>(x + (int64_t)step * NN + p);
+  const double xvn = ld<TX, double>(x + (int64_t)(step + 1) * NN + p);
+  y[(int64_t)step * NN + p] = xv - xvn + sumK;
+  double* yV = y + ((int64_t)(nt + 1) + (int64_t)step * S) * NN;
+#pragma unroll
+  for (int c = 0; c < S; ++c) {
+    double mix = 0.0;
+#pragma unroll
+    for (int r = 0; r < S; ++r) mix += tab.A[r * S + c] * KX[r];
+    yV[c * NN + p] = ld<TX, double>(V + c * NN + p) + tab.tau * mix - tab.tau * tab.b[c] * xvn;
+  }
+  if (step == nt - 1) y[(int64_t)nt * NN + p] = xvn;
+}
+
+// g_p = - sum_{n,i} sum_{faces f of p} dkappa_f/dtheta_p (lam_p - lam_q)(w_p - w_q) / h^2,
+// w_{n,i} = v_n + tau sum_j a_ij V_{n,j}; lam_q = w_q = 0 across boundary faces.
+template <int DIM, int S>
+__global__ __launch_bounds__(TPB) void k_grad_logkappa(const double* __restrict__ x,
+                                                       const double* __restrict__ lam,
+                                                       const double* __restrict__ kappa,
+                                                       double* __restrict__ g, int n, int N, int nt,
+                                                       double ih2, Tab tab) {
+  const int p = blockIdx.x * TPB + threadIdx.x;
+  if (p >= N) return;
+  int c[3];
+  node_coords<DIM>(p, n, c[0], c[1], c[2]);
+  const int64_t NN = N;
+  const int strides[3] = {1, n, n * n};
+  const double kp = kappa ? kappa[p] : 1.0;
+  double dk[2 * DIM];          // dkappa_f / dtheta_p per face (minus, plus per axis)
+  int nb[2 * DIM];             // neighbour index or -1
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const bool inside = sd == 0 ? c[a] > 0 : c[a] + 1 < n;
+      const int q = sd == 0 ? p - strides[a] : p + strides[a];
+      nb[2 * a + sd] = inside ? q : -1;
+      if (inside) {
+        const double kq = kappa ? kappa[q] : 1.0;
+        dk[2 * a + sd] = kp * 2.0 * kq * kq / ((kp + kq) * (kp + kq));
+      } else {
+        dk[2 * a + sd] = kp;
+      }
+    }
+  }
+  double acc = 0.0;
+  for (int step = 0; step < nt; ++step) {
+    const double* v = x + (int64_t)step * NN;
+    const double* V = x + ((int64_t)(nt + 1) + (int64_t)step * S) * NN;
+    const double* L = lam + ((int64_t)(nt + 1) + (int64_t)step * S) * NN;
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      auto wat = [&](int q) {
+        double m = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < S; ++jj) m += tab.A[r * S + jj] * V[jj * NN + q];
+        return v[q] + tab.tau * m;
+      };
+      const double wp = wat(p);
+      const double lp = L[r * NN + p];
+#pragma unroll
+      for (int f = 0; f < 2 * DIM; ++f) {
+        const int q = nb[f];
+        const double wq = q >= 0 ? wat(q) : 0.0;
+        const double lq = q >= 0 ? L[r * NN + q] : 0.0;
+        acc += dk[f] * (lp - lq) * (wp - wq);
+      }
+    }
+  }
+  g[p] = -acc * ih2;
+}
+
+template <class TD, class TS>
+__global__ void k_copy_cast(TD* __restrict__ d, const TS* __restrict__ s, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    st<TD, typename Acc<TD>::type>(d + i, (typename Acc<TD>::type)ld<TS, double>(s + i));
+}
+
+// y = a - y
+__global__ void k_sub_from(const double* __restrict__ a, double* __restrict__ y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a[i] - y[i];
+}
+
+// y = alpha x
+template <class TY, class TX>
+__global__ void k_scale(TY* __restrict__ y, const TX* __restrict__ x, double alpha, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    st<TY, typename Acc<TY>::type>(y + i, (typename Acc<TY>::type)(alpha * ld<TX, double>(x + i)));
+}
+
+template <class T>
+__global__ void k_fill(T* __restrict__ d, T v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = v;
+}
+
+inline unsigned grid1d(int64_t n) {
+  int64_t b = (n + TPB - 1) / TPB;
+  return (unsigned)(b < 16384 ? (b > 0 ? b : 1) : 16384);
+}
+
+Faces<double> face_ptrs(const aao_problem* h) {
+  Faces<double> f{};
+  if (h->vark) {
+    const double* base = reinterpret_cast<const double*>(h->ws + h->plan.faces_d);
+    for (int a = 0; a < h->dim; ++a) {
+      f.m[a] = base + (2 * a) * h->N;
+      f.p[a] = base + (2 * a + 1) * h->N;
+    }
+  }
+  return f;
+}
+
+}  // namespace
+
+template <class TX>
+hipError_t launch_apply_A(const aao_problem* h, const TX* x, double* y, hipStream_t st) {
+  dim3 grid((unsigned)((h->N + TPB - 1) / TPB), (unsigned)h->nt);
+  const int n = h->n, N = (int)h->N, nt = h->nt;
+  Faces<double> fc = face_ptrs(h);
+#define AAO_LAUNCH_A(D, S, V) \
+  hipLaunchKernelGGL((k_apply_A<D, S, V, TX>), grid, dim3(TPB), 0, st, x, y, n, N, nt, h->ih2, h->tab, fc)
+  DISPATCH_DSV(h->dim, h->s, h->vark, AAO_LAUNCH_A);
+#undef AAO_LAUNCH_A
+  return hipGetLastError();
+}
+
+template <class TX>
+hipError_t launch_apply_AT(const aao_problem* h, const TX* x, double* y, hipStream_t st) {
+  dim3 grid((unsigned)((h->N + TPB - 1) / TPB), (unsigned)h->nt);
+  const int n = h->n, N = (int)h->N, nt = h->nt;
+  Faces<double> fc = face_ptrs(h);
+#define AAO_LAUNCH_AT(D, S, V) \
+  hipLaunchKernelGGL((k_apply_AT<D, S, V, TX>), grid, dim3(TPB), 0, st, x, y, n, N, nt, h->ih2, h->tab, fc)
+  DISPATCH_DSV(h->dim, h->s, h->vark, AAO_LAUNCH_AT);
+#undef AAO_LAUNCH_AT
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_logkappa(const aao_problem* h, const double* x, const double* lam, double* g,
+                                hipStream_t st) {
+  dim3 grid((unsigned)((h->N + TPB - 1) / TPB));
+  const int n = h->n, N = (int)h->N, nt = h->nt;
+  const double* kap = h->vark ? reinterpret_cast<const double*>(h->ws + h->plan.faces_d) +
+                                    (int64_t)2 * h->dim * h->N
+                              : nullptr;
+#define AAO_LAUNCH_G(D, S, V) \
+  hipLaunchKernelGGL((k_grad_logkappa<D, S>), grid, dim3(TPB), 0, st, x, lam, kap, g, n, N, nt, h->ih2, h->tab)
+  DISPATCH_DSV(h->dim, h->s, false, AAO_LAUNCH_G);
+#undef AAO_LAUNCH_G
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_rhs(const aao_problem* h, const double* f, const double* u0, double* rhs,
+                               hipStream_t st) {
+  const int64_t N = h->N;
+  hipError_t e = hipMemcpyAsync(rhs, u0, N * sizeof(double), hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  e = launch_fill<double>(rhs + N, 0.0, (int64_t)h->nt * N, st);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(rhs + (int64_t)(h->nt + 1) * N, f, (size_t)h->UV * sizeof(double),
+                        hipMemcpyDeviceToDevice, st);
+}
+
+template <class TD, class TS>
+hipError_t launch_copy_cast(TD* dst, const TS* src, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_copy_cast<TD, TS>), dim3(grid1d(n)), dim3(TPB), 0, st, dst, src, n);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fill(T* dst, T v, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_fill<T>), dim3(grid1d(n)), dim3(TPB), 0, st, dst, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_from(const double* a, double* y, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_sub_from, dim3(grid1d(n)), dim3(TPB), 0, st, a, y, n);
+  return hipGetLastError();
+}
+
+template <class TY, class TX>
+hipError_t launch_scale(TY* y, const TX* x, double alpha, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_scale<TY, TX>), dim3(grid1d(n)), dim3(TPB), 0, st, y, x, alpha, n);
+  return hipGetLastError();
+}
+
+template hipError_t launch_scale<double, double>(double*, const double*, double, int64_t, hipStream_t);
+template hipError_t launch_scale<float, float>(float*, const float*, double, int64_t, hipStream_t);
+template hipError_t launch_scale<float, double>(float*, const double*, double, int64_t, hipStream_t);
+template hipError_t launch_apply_AT<double>(const aao_problem*, const double*, double*, hipStream_t);
+template hipError_t launch_apply_AT<float>(const aao_problem*, const float*, double*, hipStream_t);
+template hipError_t launch_apply_A<double>(const aao_problem*, const double*, double*, hipStream_t);
+template hipError_t launch_apply_A<float>(const aao_problem*, const float*, double*, hipStream_t);
+template hipError_t launch_copy_cast<double, float>(double*, const float*, int64_t, hipStream_t);
+template hipError_t launch_copy_cast<float, double>(float*, const double*, int64_t, hipStream_t);
+template hipError_t launch_copy_cast<double, double>(double*, const double*, int64_t, hipStream_t);
+template hipError_t launch_copy_cast<float, float>(float*, const float*, int64_t, hipStream_t);
+template hipError_t launch_fill<double>(double*, double, int64_t, hipStream_t);
+template hipError_t launch_fill<float>(float*, float, int64_t, hipStream_t);
+
+}  // namespace aao

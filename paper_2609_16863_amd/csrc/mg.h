@@ -1,0 +1,43 @@
+// Geometric multigrid V-cycles for the shifted blocks I + a K (a = tau L_ii),
+// batched over many right-hand sides (one per time step) in one launch per
+// level operation.
+#pragma once
+
+#include "aao_internal.h"
+
+namespace aao {
+
+// TI: storage of the finest level (the inner-GMRES vectors); TM: storage of
+// the coarse levels.  Arithmetic is in Acc<TI>::type.
+template <class TI, class TM>
+class Multigrid {
+ public:
+  using C = typename Acc<TI>::type;
+
+  // L: lower Crout factor (s x s, row-major) whose diagonal gives the shifts.
+  Multigrid(aao_problem* h, hipStream_t st, const double* L);
+
+  // x_b <- (`cycles` V-cycles from zero) ~ (I + tau L_ii K)^{-1} rhs_b for
+  // b = 0..B-1.  x and rhs are level-0 vectors with their own instance
+  // strides; B <= nt.
+  hipError_t solve(int stage, BVec<TI> x, BVec<const TI> rhs, int B, int cycles);
+
+ private:
+  struct Vec {
+    void* ptr;
+    int64_t stride;
+  };
+  hipError_t vcycle(int l, int stage, Vec x, Vec b, bool zero_init, int B, Vec* result);
+  hipError_t smooth(int l, int stage, Vec xin, Vec xout, Vec b, bool zero_init, int B);
+  hipError_t residual(int l, int stage, Vec x, Vec b, Vec r, int B);
+  hipError_t restrict_to(int l, Vec r, Vec bc, int B);
+  hipError_t prolong(int l, Vec xin, Vec ec, Vec xout, int B);
+  hipError_t coarsest(int l, int stage, Vec b, Vec x, int B);
+
+  aao_problem* h_;
+  hipStream_t st_;
+  double a_[SMAX];
+  int levels_;
+};
+
+}  // namespace aao

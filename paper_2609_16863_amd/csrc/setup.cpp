@@ -1,0 +1,200 @@
+// Host-side setup: Radau IIA tableau, Crout factor for Rana's stage
+// preconditioner, 1D Galerkin factors of the multigrid hierarchy, and face
+// diffusivities.  No device code.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "aao_internal.h"
+
+namespace aao {
+
+namespace {
+
+// Legendre polynomial P_k(t) by the three-term recurrence.
+double legendre(int k, double t) {
+  if (k == 0) return 1.0;
+  double p0 = 1.0, p1 = t;
+  for (int m = 1; m < k; ++m) {
+    double p2 = ((2.0 * m + 1.0) * t * p1 - m * p0) / (m + 1.0);
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+// Right Radau polynomial on [-1, 1]: its zeros map to the Radau IIA nodes.
+double radau_poly(int s, double t) { return legendre(s, t) - legendre(s - 1, t); }
+
+// Solve the dense s x s system M x = r in place (partial pivoting).
+bool dense_solve(int s, std::vector<double> M, std::vector<double>& r) {
+  for (int k = 0; k < s; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < s; ++i)
+      if (std::fabs(M[i * s + k]) > std::fabs(M[piv * s + k])) piv = i;
+    if (M[piv * s + k] == 0.0) return false;
+    if (piv != k) {
+      for (int j = 0; j < s; ++j) std::swap(M[k * s + j], M[piv * s + j]);
+      std::swap(r[k], r[piv]);
+    }
+    for (int i = k + 1; i < s; ++i) {
+      double f = M[i * s + k] / M[k * s + k];
+      for (int j = k; j < s; ++j) M[i * s + j] -= f * M[k * s + j];
+      r[i] -= f * r[k];
+    }
+  }
+  for (int k = s - 1; k >= 0; --k) {
+    double acc = r[k];
+    for (int j = k + 1; j < s; ++j) acc -= M[k * s + j] * r[j];
+    r[k] = acc / M[k * s + k];
+  }
+  return true;
+}
+
+}  // namespace
+
+// Radau IIA: nodes are the zeros of P_s(t) - P_{s-1}(t) mapped by x = (1+t)/2
+// (the last one is x = 1); the coefficients satisfy the collocation
+// conditions sum_j a_ij c_j^{q-1} = c_i^q / q, q = 1..s; b = last row of A.
+bool radau_iia(int s, double* A, double* b, double* c) {
+  if (s < 1 || s > SMAX) return false;
+  std::vector<double> nodes;
+  const int samples = 20000;
+  double tprev = -1.0, fprev = radau_poly(s, tprev);
+  for (int k = 1; k <= samples && (int)nodes.size() < s - 1; ++k) {
+    double t = -1.0 + 2.0 * k / samples * (1.0 - 1e-6);
+    double f = radau_poly(s, t);
+    if (fprev == 0.0) {
+      nodes.push_back(tprev);
+    } else if (fprev * f < 0.0) {
+      double lo = tprev, hi = t, flo = fprev;
+      for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi), fm = radau_poly(s, mid);
+        if (fm == 0.0) { lo = hi = mid; break; }
+        if ((fm < 0) == (flo < 0)) { lo = mid; flo = fm; } else { hi = mid; }
+      }
+      nodes.push_back(0.5 * (lo + hi));
+    }
+    tprev = t;
+    fprev = f;
+  }
+  if ((int)nodes.size() != s - 1) return false;
+  nodes.push_back(1.0);
+  for (int i = 0; i < s; ++i) c[i] = 0.5 * (1.0 + nodes[i]);
+  c[s - 1] = 1.0;
+  // collocation: rows i of A from the transposed Vandermonde system
+  std::vector<double> Vt(s * s);
+  for (int q = 0; q < s; ++q)
+    for (int j = 0; j < s; ++j) Vt[q * s + j] = std::pow(c[j], q);
+  for (int i = 0; i < s; ++i) {
+    std::vector<double> r(s);
+    for (int q = 0; q < s; ++q) r[q] = std::pow(c[i], q + 1) / (q + 1);
+    if (!dense_solve(s, Vt, r)) return false;
+    for (int j = 0; j < s; ++j) A[i * s + j] = r[j];
+  }
+  for (int j = 0; j < s; ++j) b[j] = A[(s - 1) * s + j];
+  return true;
+}
+
+// Crout: A = L U with U unit upper triangular; returns L (row-major s x s).
+void crout_lower(int s, const double* A, double* L) {
+  std::vector<double> U(s * s, 0.0);
+  for (int i = 0; i < s * s; ++i) L[i] = 0.0;
+  for (int i = 0; i < s; ++i) U[i * s + i] = 1.0;
+  for (int j = 0; j < s; ++j) {
+    for (int i = j; i < s; ++i) {
+      double acc = A[i * s + j];
+      for (int k = 0; k < j; ++k) acc -= L[i * s + k] * U[k * s + j];
+      L[i * s + j] = acc;
+    }
+    for (int i = j + 1; i < s; ++i) {
+      double acc = A[j * s + i];
+      for (int k = 0; k < j; ++k) acc -= L[j * s + k] * U[k * s + i];
+      U[j * s + i] = acc / L[j * s + j];
+    }
+  }
+}
+
+// 1D Galerkin factors of the hierarchy.  Level 0: M_0 = I,
+// T_0 = tridiag(-1, 2, -1)/h^2 on n nodes.  Coarse nodes are the fine nodes
+// 2, 4, ..., 2 floor(n/2) (1-based), P is linear interpolation (zero
+// boundary values), and M_{l+1} = P^T M_l P / 2, T_{l+1} = P^T T_l P / 2, so
+// that in d dimensions R = P^T / 2^d and the Galerkin operator R A_l P of
+// A_l = M(x)M + a (T(x)M + M(x)T) is again of that form.  Coarsening stops at
+// one node.  tri[l] (l >= 1) = [Mlo, Md, Mup, Tlo, Td, Tup], each n_l long.
+void galerkin_1d(int n, double h, std::vector<int>& sizes, std::vector<std::vector<double>>& tri) {
+  sizes.assign(1, n);
+  tri.assign(1, std::vector<double>());
+  int nf = n;
+  std::vector<double> M(nf * nf, 0.0), T(nf * nf, 0.0);
+  for (int i = 0; i < nf; ++i) {
+    M[i * nf + i] = 1.0;
+    T[i * nf + i] = 2.0 / (h * h);
+    if (i > 0) T[i * nf + i - 1] = -1.0 / (h * h);
+    if (i + 1 < nf) T[i * nf + i + 1] = -1.0 / (h * h);
+  }
+  while (nf > 1) {
+    int nc = nf / 2;
+    // P: nf x nc, coarse J at fine 2J+1 (0-based), neighbours 2J and 2J+2
+    std::vector<double> P(nf * nc, 0.0);
+    for (int J = 0; J < nc; ++J) {
+      int f = 2 * J + 1;
+      P[f * nc + J] = 1.0;
+      P[(f - 1) * nc + J] = 0.5;
+      if (f + 1 < nf) P[(f + 1) * nc + J] = 0.5;
+    }
+    auto rap = [&](const std::vector<double>& X) {
+      std::vector<double> XP(nf * nc, 0.0), out(nc * nc, 0.0);
+      for (int i = 0; i < nf; ++i)
+        for (int k = std::max(0, i - 1); k <= std::min(nf - 1, i + 1); ++k) {
+          double x = X[i * nf + k];
+          if (x == 0.0) continue;
+          for (int J = 0; J < nc; ++J) XP[i * nc + J] += x * P[k * nc + J];
+        }
+      for (int I = 0; I < nc; ++I)
+        for (int i = 0; i < nf; ++i) {
+          double p = P[i * nc + I];
+          if (p == 0.0) continue;
+          for (int J = 0; J < nc; ++J) out[I * nc + J] += 0.5 * p * XP[i * nc + J];
+        }
+      return out;
+    };
+    std::vector<double> Mc = rap(M), Tc = rap(T);
+    std::vector<double> t(6 * nc, 0.0);
+    for (int i = 0; i < nc; ++i) {
+      t[0 * nc + i] = i > 0 ? Mc[i * nc + i - 1] : 0.0;
+      t[1 * nc + i] = Mc[i * nc + i];
+      t[2 * nc + i] = i + 1 < nc ? Mc[i * nc + i + 1] : 0.0;
+      t[3 * nc + i] = i > 0 ? Tc[i * nc + i - 1] : 0.0;
+      t[4 * nc + i] = Tc[i * nc + i];
+      t[5 * nc + i] = i + 1 < nc ? Tc[i * nc + i + 1] : 0.0;
+    }
+    sizes.push_back(nc);
+    tri.push_back(t);
+    M.swap(Mc);
+    T.swap(Tc);
+    nf = nc;
+  }
+}
+
+// Face diffusivities (not divided by h^2): harmonic mean between interior
+// nodes, the node's own value on faces to the boundary.
+// faces[(2a) N + p] = minus side of p along axis a, faces[(2a+1) N + p] = plus side.
+void face_coefficients(int dim, int n, const double* kappa, std::vector<double>& faces) {
+  int64_t N = 1;
+  for (int a = 0; a < dim; ++a) N *= n;
+  faces.assign((size_t)2 * dim * N, 0.0);
+  int64_t strides[3] = {1, n, (int64_t)n * n};
+  for (int64_t p = 0; p < N; ++p) {
+    int64_t coord[3] = {p % n, (p / n) % n, dim == 3 ? p / ((int64_t)n * n) : 0};
+    for (int a = 0; a < dim; ++a) {
+      double kp = kappa[p];
+      double km = coord[a] > 0 ? kappa[p - strides[a]] : kp;
+      double kq = coord[a] + 1 < n ? kappa[p + strides[a]] : kp;
+      faces[(2 * a) * N + p] = coord[a] > 0 ? 2.0 * kp * km / (kp + km) : kp;
+      faces[(2 * a + 1) * N + p] = coord[a] + 1 < n ? 2.0 * kp * kq / (kp + kq) : kp;
+    }
+  }
+}
+
+}  // namespace aao

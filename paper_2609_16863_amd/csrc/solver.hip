@@ -1,0 +1,375 @@
+// Host orchestration of the preconditioner P-tilde (eqs. (3.2)-(3.3)) and of
+// the outer FP64 FGMRES (Algorithm 1 with P_L = I, restarted).
+//
+// P-tilde^{-1} r by block back-substitution:
+//   z_V = Theta-tilde^{-1} r_V         one batched inner GMRES over all steps
+//   t_v = r_v - Psi1 z_V              t_{v,n+1} = r_{v,n+1} + tau sum_i b_i z_{V,n,i}
+//   z_v = S-tilde^{-1} t_v            forward sweep in time:
+//        z_{v,n+1} = t_{v,n+1} + z_{v,n} - tau (b^T (x) I) Theta-tilde^{-1} (e (x) K) z_{v,n}
+// Theta-tilde^{-1} is k right-preconditioned GMRES iterations from zero on the
+// stage matrix Theta_hat = I_s (x) I + tau A (x) K, preconditioned by Rana's
+// block-lower-triangular I_s (x) I + tau L (x) K (A_RK = L U, U unit upper)
+// whose diagonal blocks I + tau L_ii K get `cycles` multigrid V-cycles.
+//
+// The transpose P-tilde^{-T} (used by the adjoint solve) is the same
+// back-substitution on the transposed blocks: the S-tilde^T sweep runs
+// backwards in time first, then Theta-tilde^{-T} (GMRES on Theta_hat^T with
+// Rana's factor of A_RK^T).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "aao_internal.h"
+#include "krylov.h"
+#include "mg.h"
+
+namespace aao {
+
+#define TRY(...)                         \
+  do {                                   \
+    hipError_t e_ = (__VA_ARGS__);       \
+    if (e_ != hipSuccess) return e_;     \
+  } while (0)
+
+namespace {
+
+using S = InnerSlots;
+
+template <class TI, class TM>
+class Precond {
+ public:
+  Precond(aao_problem* h, bool transpose, int k, int cycles)
+      : h_(h), st_(h->stream), transpose_(transpose), k_(k), cycles_(cycles),
+        mg_(h, h->stream, transpose ? h->LT : h->tab.L) {
+    tab_ = h->tab;
+    if (transpose) {
+      const int s = h->s;
+      for (int i = 0; i < s; ++i)
+        for (int j = 0; j < s; ++j) tab_.A[i * s + j] = h->tab.A[j * s + i];
+    }
+    Lc_ = transpose ? h->LT : h->tab.L;
+    char* ws = h->ws;
+    inV_ = reinterpret_cast<TI*>(ws + h->plan.inV);
+    inZ_ = reinterpret_cast<TI*>(ws + h->plan.inZ);
+    inW_ = reinterpret_cast<TI*>(ws + h->plan.inW);
+    inX_ = reinterpret_cast<TI*>(ws + h->plan.inX);
+    rana_ = reinterpret_cast<TI*>(ws + h->plan.rana);
+    srhs_ = reinterpret_cast<TI*>(ws + h->plan.schurRhs);
+    sy_ = reinterpret_cast<TI*>(ws + h->plan.schurY);
+    partial_ = reinterpret_cast<double*>(ws + h->plan.partial);
+    slots_ = reinterpret_cast<double*>(ws + h->plan.dscal);
+  }
+
+  // out_b = Theta-tilde^{-1} rhs_b for B instances (rhs, out: s*N each).
+  template <class TR>
+  hipError_t inner(const TR* rhs, int64_t srhs, TI* out, int64_t sout, int B) {
+    const int64_t N = h_->N, sN = (int64_t)h_->s * N, UV = h_->UV;
+    const int nblk = seg_blocks(sN, B);
+    TRY(seg_dots<TR, TR>(rhs, srhs, rhs, 0, srhs, 0, true, sN, B, partial_, nblk, st_));
+    TRY(seg_finish(partial_, nblk, 0, S::WW, B, slots_, S::STRIDE, 0, st_));
+    TRY(inner_init(slots_, B, st_));
+    TRY(seg_scale<TR, TI>(rhs, srhs, inV_, sN, slots_, S::STRIDE, S::INV, sN, B, st_));
+    for (int j = 0; j < k_; ++j) {
+      TI* Vj = inV_ + (int64_t)j * UV;
+      TI* Zj = inZ_ + (int64_t)j * UV;
+      // Rana: forward substitution over the stages
+      for (int i = 0; i < h_->s; ++i) {
+        BVec<const TI> b{Vj, sN};
+        if (i > 0) {
+          TRY(rana_rhs<TI>(h_, Lc_, i, Vj + (int64_t)i * N, sN, Zj, sN, rana_, N, B, st_));
+          b = BVec<const TI>{rana_, N};
+        }
+        TRY(mg_.solve(i, BVec<TI>{Zj + (int64_t)i * N, sN}, b, B, cycles_));
+      }
+      TRY(theta_apply<TI>(h_, tab_, Zj, sN, inW_, sN, B, st_));
+      // classical Gram-Schmidt, applied twice
+      const int nd = j + 1;
+      TRY(seg_dots<TI, TI>(inW_, sN, inV_, UV, sN, nd, false, sN, B, partial_, nblk, st_));
+      TRY(seg_finish(partial_, nblk, nd, -1, B, slots_, S::STRIDE, S::H1, st_));
+      TRY(seg_axpy<TI, TI>(inW_, sN, inV_, UV, sN, nd, slots_, S::STRIDE, S::H1, -1.0, sN, B, st_));
+      TRY(seg_dots<TI, TI>(inW_, sN, inV_, UV, sN, nd, true, sN, B, partial_, nblk, st_));
+      TRY(seg_finish(partial_, nblk, nd, S::WW, B, slots_, S::STRIDE, S::H2, st_));
+      TRY(seg_axpy<TI, TI>(inW_, sN, inV_, UV, sN, nd, slots_, S::STRIDE, S::H2, -1.0, sN, B, st_));
+      TRY(inner_givens(slots_, B, j, st_));
+      if (j + 1 < k_)
+        TRY(seg_scale<TI, TI>(inW_, sN, inV_ + (int64_t)(j + 1) * UV, sN, slots_, S::STRIDE, S::INV, sN, B, st_));
+    }
+    TRY(inner_backsolve(slots_, B, k_, st_));
+    TRY(seg_combine<TI, TI>(out, sout, inZ_, UV, sN, k_, slots_, S::STRIDE, S::Y, sN, B, st_));
+    return hipSuccess;
+  }
+
+  // z (TI, U values) = P-tilde^{-1} r (FP64) or its transpose.
+  hipError_t apply(const double* r, TI* z) {
+    const int64_t N = h_->N, sN = (int64_t)h_->s * N;
+    const int nt = h_->nt;
+    TI* zv = z;
+    TI* zV = z + (int64_t)(nt + 1) * N;
+    const double* rV = r + (int64_t)(nt + 1) * N;
+    if (!transpose_) {
+      TRY(inner<double>(rV, sN, zV, sN, nt));
+      TRY(schur_coupling<TI>(h_, r, z, st_));
+      for (int n = 0; n < nt; ++n) {
+        TRY(schur_kz<TI>(h_, zv + (int64_t)n * N, srhs_, st_));
+        TRY(inner<TI>(srhs_, sN, sy_, sN, 1));
+        TI* znext = zv + (int64_t)(n + 1) * N;
+        TRY(schur_update<TI>(h_, znext, zv + (int64_t)n * N, sy_, znext, st_));
+      }
+    } else {
+      TRY(launch_copy_cast<TI, double>(zv + (int64_t)nt * N, r + (int64_t)nt * N, N, st_));
+      for (int n = nt - 1; n >= 0; --n) {
+        TRY(schurT_bw<TI>(h_, zv + (int64_t)(n + 1) * N, srhs_, st_));
+        TRY(inner<TI>(srhs_, sN, sy_, sN, 1));
+        TRY(schurT_update<TI>(h_, r + (int64_t)n * N, zv + (int64_t)(n + 1) * N, sy_, zv + (int64_t)n * N, st_));
+      }
+      TRY(thetaT_rhs<TI>(h_, r, z, inX_, st_));
+      TRY(inner<TI>(inX_, sN, zV, sN, nt));
+    }
+    return hipSuccess;
+  }
+
+ private:
+  aao_problem* h_;
+  hipStream_t st_;
+  bool transpose_;
+  int k_, cycles_;
+  Multigrid<TI, TM> mg_;
+  Tab tab_;
+  const double* Lc_;
+  TI *inV_, *inZ_, *inW_, *inX_, *rana_, *srhs_, *sy_;
+  double *partial_, *slots_;
+};
+
+template <class TI, class TM>
+hipError_t apply_P_typed(aao_problem* h, const double* r, TI* z, int k, int cycles, bool transpose) {
+  Precond<TI, TM> P(h, transpose, k, cycles);
+  return P.apply(r, z);
+}
+
+// Dispatch on the handle's precision; z is TI-typed storage (double for FP64).
+hipError_t apply_P_any(aao_problem* h, const double* r, void* z, int k, int cycles, bool transpose) {
+  switch (h->opts.precision) {
+    case AAO_PREC_FP64: return apply_P_typed<double, double>(h, r, (double*)z, k, cycles, transpose);
+    case AAO_PREC_FP32: return apply_P_typed<float, float>(h, r, (float*)z, k, cycles, transpose);
+    case AAO_PREC_FP16: return apply_P_typed<float, __half>(h, r, (float*)z, k, cycles, transpose);
+    default: return apply_P_typed<float, __hip_bfloat16>(h, r, (float*)z, k, cycles, transpose);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Outer FGMRES
+// ---------------------------------------------------------------------------
+template <class TI>
+class Fgmres {
+ public:
+  Fgmres(aao_problem* h, bool transpose) : h_(h), st_(h->stream), transpose_(transpose) {
+    char* ws = h->ws;
+    V_ = reinterpret_cast<double*>(ws + h->plan.outV);
+    Z_ = reinterpret_cast<TI*>(ws + h->plan.outZ);
+    w_ = reinterpret_cast<double*>(ws + h->plan.outW);
+    partial_ = reinterpret_cast<double*>(ws + h->plan.partial);
+    oslots_ = reinterpret_cast<double*>(ws + h->plan.dscal) + (int64_t)(h->nt + 1) * S::STRIDE;
+  }
+
+  template <class TX>
+  hipError_t op(const TX* x, double* y) {
+    return transpose_ ? launch_apply_AT<TX>(h_, x, y, st_) : launch_apply_A<TX>(h_, x, y, st_);
+  }
+
+  // ||x||^2 of a U-vector, synchronous.
+  hipError_t norm2(const double* x, double* out) {
+    const int nblk = seg_blocks(h_->U, 1);
+    TRY(seg_dots<double, double>(x, 0, x, 0, 0, 0, true, h_->U, 1, partial_, nblk, st_));
+    TRY(seg_finish(partial_, nblk, 0, 0, 1, oslots_, 0, 0, st_));
+    TRY(hipMemcpyAsync(h_->hpin, oslots_, sizeof(double), hipMemcpyDeviceToHost, st_));
+    TRY(hipStreamSynchronize(st_));
+    *out = h_->hpin[0];
+    return hipSuccess;
+  }
+
+  // Gram-Schmidt of w against V_0..V_{nd-1} (twice); leaves h1+h2 in hcol
+  // and <w,w> after the first pass in ww (host).
+  hipError_t orthogonalize(int nd, std::vector<double>& hcol, double& h2sq, double& ww) {
+    const int64_t U = h_->U;
+    const int nblk = seg_blocks(U, 1);
+    double* H1 = oslots_ + 8;
+    double* H2 = H1 + MMAX + 8;
+    double* WW = H2 + MMAX + 8;
+    for (int pass = 0; pass < 2; ++pass) {
+      double* H = pass == 0 ? H1 : H2;
+      for (int c0 = 0; c0 < nd; c0 += DOTS_PER_PASS) {
+        const int cnt = std::min(DOTS_PER_PASS, nd - c0);
+        const bool self = pass == 1 && c0 + cnt >= nd;
+        TRY(seg_dots<double, double>(w_, 0, V_ + (int64_t)c0 * U, U, 0, cnt, self, U, 1, partial_, nblk, st_));
+        TRY(seg_finish(partial_, nblk, cnt, self ? (int)(WW - oslots_) : -1, 1, oslots_, 0, (int)(H - oslots_) + c0,
+                       st_));
+      }
+      for (int c0 = 0; c0 < nd; c0 += DOTS_PER_PASS) {
+        const int cnt = std::min(DOTS_PER_PASS, nd - c0);
+        TRY(seg_axpy<double, double>(w_, 0, V_ + (int64_t)c0 * U, U, 0, cnt, H + c0, 0, 0, -1.0, U, 1, st_));
+      }
+    }
+    double* hp = h_->hpin;
+    TRY(hipMemcpyAsync(hp, H1, sizeof(double) * (size_t)(WW - H1 + 1), hipMemcpyDeviceToHost, st_));
+    TRY(hipStreamSynchronize(st_));
+    hcol.assign(nd, 0.0);
+    h2sq = 0.0;
+    for (int i = 0; i < nd; ++i) {
+      const double a = hp[i], b = hp[(H2 - H1) + i];
+      hcol[i] = a + b;
+      h2sq += b * b;
+    }
+    ww = hp[WW - H1];
+    return hipSuccess;
+  }
+
+  int run(const double* rhs, double* x, aao_stats* stats) {
+    const int64_t U = h_->U;
+    const int m = h_->opts.restart;
+    auto t0 = std::chrono::steady_clock::now();
+    hipEvent_t pe0, pe1;
+    bool ev = hipEventCreate(&pe0) == hipSuccess && hipEventCreate(&pe1) == hipSuccess;
+    double precond_ms = 0.0;
+    aao_stats local{};
+    aao_stats& stt = stats ? *stats : local;
+    stt = aao_stats{};
+    double nb2 = 0.0;
+    hipError_t e = norm2(rhs, &nb2);
+    if (e != hipSuccess) return status_from_hip(h_, e, "solve");
+    const double nb = std::sqrt(nb2);
+    if (!(nb > 0.0)) {       // zero right-hand side: x = 0 is the solution
+      e = launch_fill<double>(x, 0.0, U, st_);
+      if (e == hipSuccess) e = hipStreamSynchronize(st_);
+      stt.relres = 0.0;
+      return e == hipSuccess ? AAO_OK : status_from_hip(h_, e, "solve");
+    }
+    int its = 0;
+    int status = AAO_NOT_CONVERGED;
+    std::vector<double> R((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m), hcol;
+    while (true) {
+      // r = rhs - A x
+      if ((e = op<double>(x, w_)) != hipSuccess) break;
+      if ((e = launch_sub_from(rhs, w_, U, st_)) != hipSuccess) break;
+      double b2;
+      if ((e = norm2(w_, &b2)) != hipSuccess) break;
+      const double beta = std::sqrt(b2);
+      stt.relres = beta / nb;
+      if (!std::isfinite(beta)) { status = AAO_NONFINITE; break; }
+      if (stt.relres <= h_->opts.tol) { status = AAO_OK; break; }
+      if (its >= h_->opts.maxit) { status = AAO_NOT_CONVERGED; break; }
+      stt.restarts++;
+      if ((e = launch_scale<double, double>(V_, w_, 1.0 / beta, U, st_)) != hipSuccess) break;
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int mm = 0;
+      bool stop = false;
+      for (int j = 0; j < m && !stop; ++j) {
+        its++;
+        if (ev) hipEventRecord(pe0, st_);
+        if ((e = apply_P_any(h_, V_ + (int64_t)j * U, Z_ + (int64_t)j * U, h_->opts.inner_k, h_->opts.cycles,
+                             transpose_)) != hipSuccess)
+          break;
+        if (ev) hipEventRecord(pe1, st_);
+        if ((e = op<TI>(Z_ + (int64_t)j * U, w_)) != hipSuccess) break;
+        double h2sq, ww;
+        if ((e = orthogonalize(j + 1, hcol, h2sq, ww)) != hipSuccess) break;
+        if (ev) {
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, pe0, pe1) == hipSuccess) precond_ms += ms;
+        }
+        const double nrm2 = ww - h2sq;
+        const double hn = nrm2 > 0.0 ? std::sqrt(nrm2) : 0.0;
+        std::vector<double> col(hcol);
+        col.push_back(hn);
+        for (int i = 0; i < j; ++i) {
+          const double a = col[i], b = col[i + 1];
+          col[i] = cs[i] * a + sn[i] * b;
+          col[i + 1] = -sn[i] * a + cs[i] * b;
+        }
+        const double rho = std::hypot(col[j], col[j + 1]);
+        if (!std::isfinite(rho) || !std::isfinite(hn)) { status = AAO_NONFINITE; stop = true; break; }
+        if (rho == 0.0) { stop = true; break; }
+        cs[j] = col[j] / rho;
+        sn[j] = col[j + 1] / rho;
+        col[j] = rho;
+        for (int i = 0; i <= j; ++i) R[(size_t)j * (m + 1) + i] = col[i];
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        mm = j + 1;
+        const double est = std::fabs(g[j + 1]) / nb;
+        if (stt.history_len < 128) stt.history[stt.history_len++] = est;
+        if (est <= h_->opts.tol || hn == 0.0 || its >= h_->opts.maxit) stop = true;
+        if (!stop && j + 1 < m)
+          if ((e = launch_scale<double, double>(V_ + (int64_t)(j + 1) * U, w_, 1.0 / hn, U, st_)) != hipSuccess)
+            break;
+      }
+      if (e != hipSuccess || status == AAO_NONFINITE) break;
+      // x += Z y
+      for (int i = mm - 1; i >= 0; --i) {
+        double acc = g[i];
+        for (int jj = i + 1; jj < mm; ++jj) acc -= R[(size_t)jj * (m + 1) + i] * y[jj];
+        y[i] = acc / R[(size_t)i * (m + 1) + i];
+      }
+      double* ydev = oslots_ + 4 * (MMAX + 8);
+      if (mm > 0) {
+        for (int i = 0; i < mm; ++i) h_->hpin[i] = y[i];
+        if ((e = hipMemcpyAsync(ydev, h_->hpin, sizeof(double) * mm, hipMemcpyHostToDevice, st_)) != hipSuccess)
+          break;
+        for (int c0 = 0; c0 < mm; c0 += DOTS_PER_PASS) {
+          const int cnt = std::min(DOTS_PER_PASS, mm - c0);
+          if ((e = seg_axpy<double, TI>(x, 0, Z_ + (int64_t)c0 * U, U, 0, cnt, ydev + c0, 0, 0, 1.0, U, 1, st_)) !=
+              hipSuccess)
+            break;
+        }
+        if (e != hipSuccess) break;
+        // the host buffer is reused by the next iteration: wait for the copy
+        if ((e = hipStreamSynchronize(st_)) != hipSuccess) break;
+      }
+    }
+    if (ev) {
+      hipEventDestroy(pe0);
+      hipEventDestroy(pe1);
+    }
+    stt.outer_iterations = its;
+    stt.precond_ms = precond_ms;
+    stt.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (e != hipSuccess) return status_from_hip(h_, e, transpose_ ? "solve_adjoint" : "solve");
+    if (status == AAO_NONFINITE) h_->err = "non-finite value in the Krylov recurrence";
+    if (status == AAO_NOT_CONVERGED) h_->err = "maximum number of iterations reached";
+    return status;
+  }
+
+ private:
+  aao_problem* h_;
+  hipStream_t st_;
+  bool transpose_;
+  double *V_, *w_, *partial_, *oslots_;
+  TI* Z_;
+};
+
+}  // namespace
+
+int apply_P(aao_problem* h, const double* r, double* z, int inner_k, int cycles, bool transpose) {
+  hipError_t e;
+  if (h->opts.precision == AAO_PREC_FP64) {
+    e = apply_P_any(h, r, z, inner_k, cycles, transpose);
+  } else {
+    float* zp = reinterpret_cast<float*>(h->ws + h->plan.outY);
+    e = apply_P_any(h, r, zp, inner_k, cycles, transpose);
+    if (e == hipSuccess) e = launch_copy_cast<double, float>(z, zp, h->U, h->stream);
+  }
+  return status_from_hip(h, e, "apply_P");
+}
+
+int solve(aao_problem* h, const double* rhs, double* x, aao_stats* st, bool transpose) {
+  if (h->opts.precision == AAO_PREC_FP64) {
+    Fgmres<double> F(h, transpose);
+    return F.run(rhs, x, st);
+  }
+  Fgmres<float> F(h, transpose);
+  return F.run(rhs, x, st);
+}
+
+}  // namespace aao

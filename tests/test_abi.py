@@ -1,0 +1,112 @@
+"""The C-ABI library: exported symbols and host-side logic (not gpu).
+
+No device work happens here: creating a handle, reading its tableau and sizes
+and rejecting bad arguments are host-only calls.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import tableau as otab
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "aao_heat.h")
+
+
+def _lib():
+    from paper_2609_16863_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_2609_16863_amd import build
+        build.build(verbose=False)
+    return _abi, _abi.load()
+
+
+def declared_entry_points():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|void|const char\*)\s+(aao_\w+)\s*\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    abi, lib = _lib()
+    names = declared_entry_points()
+    assert len(names) >= 17
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in abi.SIGNATURES, name
+
+
+def _create(abi, lib, dim=2, n=8, s=2, nt=4, T=1.0, kappa=None, **over):
+    opts = abi.Opts()
+    lib.aao_default_opts(ctypes.byref(opts))
+    for k, v in over.items():
+        setattr(opts, k, v)
+    kap = None if kappa is None else np.ascontiguousarray(kappa, float)
+    desc = abi.Desc(dim, n, s, nt, T, None if kap is None else kap.ctypes.data)
+    h = ctypes.c_void_p()
+    code = lib.aao_create_problem(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h))
+    return code, h
+
+
+@pytest.mark.parametrize("s", [1, 2, 3])
+def test_library_tableau_matches_oracle(s):
+    abi, lib = _lib()
+    code, h = _create(abi, lib, s=s)
+    assert code == 0
+    A = np.zeros(s * s)
+    b = np.zeros(s)
+    c = np.zeros(s)
+    assert lib.aao_get_tableau(h, A.ctypes.data, b.ctypes.data, c.ctypes.data) == 0
+    Ao, bo, co = otab.radau_iia(s)
+    assert np.allclose(A.reshape(s, s), Ao, atol=1e-14)
+    assert np.allclose(b, bo, atol=1e-14) and np.allclose(c, co, atol=1e-14)
+    lib.aao_destroy(h)
+
+
+def test_sizes_and_workspace():
+    abi, lib = _lib()
+    code, h = _create(abi, lib, dim=3, n=6, s=3, nt=5)
+    assert code == 0
+    N, U = ctypes.c_int64(), ctypes.c_int64()
+    lib.aao_sizes(h, ctypes.byref(N), ctypes.byref(U))
+    assert N.value == 216 and U.value == 216 * (5 * 4 + 1)
+    nbytes = ctypes.c_size_t()
+    assert lib.aao_workspace_size(h, ctypes.byref(nbytes)) == 0
+    # at least the outer Krylov basis: (restart + 1) FP64 vectors
+    assert nbytes.value >= 31 * U.value * 8
+    lib.aao_destroy(h)
+
+
+@pytest.mark.parametrize("bad", [dict(dim=4), dict(n=1), dict(s=4), dict(nt=0), dict(T=-1.0),
+                                 dict(restart=0), dict(inner_k=13), dict(precision=7), dict(nu1=0)])
+def test_invalid_arguments_are_rejected(bad):
+    abi, lib = _lib()
+    desc_keys = {"dim", "n", "s", "nt", "T"}
+    d = {k: v for k, v in bad.items() if k in desc_keys}
+    o = {k: v for k, v in bad.items() if k not in desc_keys}
+    code, h = _create(abi, lib, **d, **o)
+    assert code == -1
+    assert lib.aao_last_error(None)
+    assert not h.value
+
+
+def test_device_calls_without_workspace_fail_cleanly():
+    abi, lib = _lib()
+    code, h = _create(abi, lib)
+    assert code == 0
+    dummy = ctypes.c_void_p(1 << 20)
+    assert lib.aao_apply_P(h, dummy, ctypes.c_void_p(2 << 20)) == -5
+    assert lib.aao_solve(h, dummy, ctypes.c_void_p(2 << 20), None) == -5
+    assert lib.aao_apply_A(h, dummy, dummy) == -1          # aliasing rejected
+    assert b"workspace" in lib.aao_last_error(h) or b"distinct" in lib.aao_last_error(h)
+    lib.aao_destroy(h)
+
+
+def test_bad_kappa_rejected():
+    abi, lib = _lib()
+    k = np.ones(64)
+    k[3] = -1.0
+    code, _ = _create(abi, lib, n=8, kappa=k)
+    assert code == -1

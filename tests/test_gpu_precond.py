@@ -1,0 +1,77 @@
+"""GPU parity of the preconditioner P-tilde (eqs. (3.2)-(3.3)) against the oracle.
+
+FP64: the GPU applies the same algorithm as the oracle (inner GMRES(k) with
+Rana's stage preconditioner, Galerkin V-cycles with weighted Jacobi), so the
+outputs agree to rounding (the map is nonlinear but smooth: the inner
+least-squares problems are well conditioned).  Tolerance 1e-10 relative:
+FP64 rounding (~1e-16) amplified by the inner Krylov recurrences and the
+nt-step S-tilde recursion.  Lower precisions are compared against the FP64
+oracle with tolerances set by their unit roundoff (FP32 ~6e-8, BF16 ~4e-3,
+FP16 ~5e-4) times the same amplification.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import announce, rel_err, require_gpu, to_dev, to_host
+from oracle import allatonce, precond
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(dim, n, s, nt, precision="fp64", k=3, cycles=1, nu=2, seed=0, transpose=False):
+    from paper_2609_16863_amd import HeatProblem
+    p = allatonce.Problem(n, dim, s, nt, 1.0)
+    hp = HeatProblem(dim, n, s, nt, 1.0, inner_k=k, cycles=cycles, nu1=nu, nu2=nu, precision=precision)
+    ops = precond.StageOps(p, inner_k=k, cycles=cycles, nu1=nu, nu2=nu)
+    return p, hp, ops, np.random.default_rng(seed)
+
+
+@pytest.mark.parametrize("dim,n,s,nt", [(2, 16, 2, 4), (2, 13, 3, 3), (2, 32, 1, 3), (3, 8, 2, 2), (3, 7, 3, 2)])
+def test_apply_P_fp64_matches_oracle(dim, n, s, nt):
+    require_gpu()
+    p, hp, ops, rng = _pair(dim, n, s, nt, seed=n)
+    r = rng.standard_normal(p.U)
+    announce("apply_P fp64", dim, n, s, nt)
+    z = to_host(hp.apply_P(to_dev(r)))
+    ref = precond.apply_preconditioner(ops, r)
+    assert rel_err(z, ref) <= 1e-10
+    assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-4), ("bf16", 5e-2), ("fp16", 2e-2)])
+def test_apply_P_low_precision_close_to_fp64_oracle(precision, tol):
+    require_gpu()
+    p, hp, ops, rng = _pair(2, 24, 3, 4, precision=precision, seed=5)
+    r = rng.standard_normal(p.U)
+    announce("apply_P", precision)
+    z = to_host(hp.apply_P(to_dev(r)))
+    ref = precond.apply_preconditioner(ops, r)
+    assert np.all(np.isfinite(z))
+    assert rel_err(z, ref) <= tol
+
+
+def test_apply_P_tends_to_ideal_preconditioner():
+    """Many inner iterations and cycles: P-tilde -> P of eq. (3.1) (Sec. 3)."""
+    require_gpu()
+    p, hp, _, rng = _pair(2, 12, 2, 3, k=12, cycles=6, seed=3)
+    exact = precond.StageOps(p)
+    r = rng.standard_normal(p.U)
+    announce("apply_P ideal limit")
+    z = to_host(hp.apply_P(to_dev(r)))
+    ref = precond.apply_preconditioner(exact, r, exact=True)
+    assert rel_err(z, ref) <= 1e-7
+
+
+@pytest.mark.parametrize("dim,n,s,nt", [(2, 12, 2, 3), (2, 9, 3, 2)])
+def test_adjoint_with_near_exact_transposed_preconditioner(dim, n, s, nt):
+    """P-tilde^T with near-exact inner solves -> P^T: the adjoint FGMRES needs <= 2 steps (Sec. 3)."""
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    p = allatonce.Problem(n, dim, s, nt, 1.0)
+    hp = HeatProblem(dim, n, s, nt, 1.0, inner_k=12, cycles=6, tol=1e-9)
+    r = np.random.default_rng(11).standard_normal(p.U)
+    announce("adjoint near-exact", dim, n, s, nt)
+    lam, st = hp.solve_adjoint(to_dev(r))
+    Ad = allatonce.operator(p, sparse=False)
+    assert st["converged"] and st["outer_iterations"] <= 3
+    assert rel_err(to_host(lam), np.linalg.solve(Ad.T, r)) <= 1e-7

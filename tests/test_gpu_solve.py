@@ -1,0 +1,93 @@
+"""GPU parity of the full all-at-once solve (FGMRES + P-tilde) against the oracle.
+
+The solve's result is unique (x* = A^{-1} [b; f], equal to sequential
+stepping), so the bar is the forward error against the oracle: <= 1e-8
+relative, reached by running the FP64 FGMRES to a tighter residual
+tolerance (the condition number of A grows like tau/h^2, so a residual of
+1e-8 does not by itself bound the forward error by 1e-8).
+"""
+import numpy as np
+import pytest
+
+import heat_inputs
+from gpu_util import announce, rel_err, require_gpu, to_dev, to_host
+from oracle import allatonce, mms, precond, stepping
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(hp, p, f, u0):
+    rhs = hp.assemble_rhs(to_dev(np.ravel(f)), to_dev(u0))
+    x, st = hp.solve(rhs)
+    return to_host(x), st
+
+
+def test_config0_closed_form_fp64():
+    """32x32, s=2, nt=16, manufactured sin-sin-exp solution, FP64 preconditioner."""
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    w = heat_inputs.WORKLOADS["heat2d_n32_s2_nt16_mms"]
+    hp = HeatProblem(2, w.n, w.s, w.nt, w.T, restart=30, tol=1e-12)
+    p = allatonce.Problem(w.n, 2, w.s, w.nt, w.T)
+    f, u0 = heat_inputs.workload_inputs(w, hp.stage_times())
+    announce("solve config0")
+    x, st = _solve(hp, p, f, u0)
+    assert st["converged"] and st["relres"] <= 1e-12
+    xs = mms.solution(p, u0)
+    v, V = allatonce.split(p, x)
+    vs, Vs = allatonce.split(p, xs)
+    assert rel_err(v, vs) <= 1e-8 and rel_err(V, Vs) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("dim,n,s,nt", [(2, 48, 3, 8), (2, 33, 2, 6), (3, 16, 2, 4)])
+def test_solve_matches_stepping(dim, n, s, nt, precision):
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    p = allatonce.Problem(n, dim, s, nt, 1.0)
+    hp = HeatProblem(dim, n, s, nt, 1.0, tol=1e-11, precision=precision)
+    rng = np.random.default_rng(1001)
+    f = heat_inputs.bump_source(rng, n, dim, hp.stage_times())
+    u0 = heat_inputs.smooth_initial(rng, n, dim)
+    announce("solve", dim, n, s, nt, precision)
+    x, st = _solve(hp, p, f, u0)
+    assert st["converged"]
+    xs = stepping.solve(p, f, u0)
+    assert rel_err(x, xs) <= 1e-8, st
+
+
+def test_iteration_counts_track_oracle_fgmres():
+    """Same preconditioner settings: GPU FP64 FGMRES iterations within +-1 of the oracle's."""
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    n, s, nt = 24, 3, 6
+    p = allatonce.Problem(n, 2, s, nt, 1.0)
+    hp = HeatProblem(2, n, s, nt, 1.0, tol=1e-8)
+    rng = np.random.default_rng(77)
+    f = heat_inputs.bump_source(rng, n, 2, hp.stage_times())
+    u0 = heat_inputs.smooth_initial(rng, n, 2)
+    announce("iteration counts")
+    _, st = _solve(hp, p, f, u0)
+    ops = precond.StageOps(p, inner_k=3, cycles=1, nu1=2, nu2=2)
+    K = p.K()
+    _, its, _ = precond.fgmres(lambda y: allatonce.apply_blockwise(p, y, K),
+                               lambda r: precond.apply_preconditioner(ops, r),
+                               allatonce.rhs(p, f, u0), restart=30, tol=1e-8)
+    assert abs(st["outer_iterations"] - its) <= 1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_adjoint_solve_matches_oracle(precision):
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    from oracle import adjoint
+    n, s, nt = 20, 2, 5
+    rng = np.random.default_rng(31)
+    kappa = heat_inputs.lognormal_kappa(rng, n, 2)
+    p = allatonce.Problem(n, 2, s, nt, 1.0, kappa=kappa)
+    hp = HeatProblem(2, n, s, nt, 1.0, kappa=kappa, tol=1e-11, precision=precision)
+    g = rng.standard_normal(p.U)
+    announce("adjoint", precision)
+    lam, st = hp.solve_adjoint(to_dev(g))
+    assert st["converged"]
+    assert rel_err(to_host(lam), adjoint.solve(p, g)) <= 1e-8

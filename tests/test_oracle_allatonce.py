@@ -61,6 +61,15 @@ def test_blockwise_apply_equals_dense(dim, n, s, nt, vk):
     assert abs(Ax @ y - x @ ATy) <= 1e-13 * np.abs(Ad).max() * np.linalg.norm(x) * np.linalg.norm(y)
 
 
+@pytest.mark.parametrize("dim,n,s,nt,vk", CASES)
+def test_row_apply_equals_blockwise(dim, n, s, nt, vk):
+    p, _, _ = _random_problem(dim, n, s, nt, vk, 13)
+    x = np.random.default_rng(4).standard_normal(p.U)
+    rows = np.arange(p.U)
+    assert np.allclose(allatonce.apply_rows(p, x, rows), allatonce.apply_blockwise(p, x),
+                       rtol=1e-13, atol=1e-12 * np.abs(x).max() / p.h ** 2)
+
+
 def test_first_rows_are_initial_condition():
     p, f, u0 = _random_problem(2, 3, 2, 3, False, 5)
     Ad = allatonce.operator(p, sparse=False)
