@@ -1,0 +1,182 @@
+"""Benchmark: all-at-once Radau IIA heat solve on one MI355X.
+
+One step = one full FGMRES solve to a true FP64 relative residual of 1e-8 of
+the all-at-once system (paper eq. (2.4)) with the block preconditioner
+(eqs. (3.2)-(3.3)) applied in FP32 (the mixed-precision arm, approach A2).
+The same solve with the FP64 preconditioner (approach A1) is timed beside
+it.  Workload: 2D heat on a 512 x 512 interior grid, Radau IIA s = 3, 64 time
+steps to T = 1, FGMRES(30); seeded Gaussian-bump source and smooth random
+initial condition (synthetic, generated on the host).
+
+Prints one JSON line (rank 0).  `roofline` reports the dominant kernel's
+algorithmic HBM bytes / its average launch time, measured here with HIP
+events on the stream the kernel runs on; `cpu_baseline` times the FP64 CPU
+oracle (sequential stepping with an exact DST stage solve) on a bounded
+number of time steps, scaled to the full 64 steps.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "solve time to relres 1e-8, mixed vs FP64 precond; stencil/V-cycle HBM GB/s"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="heat2d_n512_s3_nt64")
+    ap.add_argument("--mixed", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--inner-k", type=int, default=3)
+    ap.add_argument("--cycles", type=int, default=1)
+    ap.add_argument("--nu", type=int, default=2)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-preconditioner arm")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=8, help="time steps in the CPU oracle sample")
+    ap.add_argument("--roofline-reps", type=int, default=20)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the all-at-once solve "
+                          "is measured at its single-GPU shape (see DESIGN.md for how it would shard)"}))
+        sys.exit(2)
+    import torch
+
+    import heat_inputs
+    from paper_2609_16863_amd import HeatProblem
+
+    w = heat_inputs.WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    common = dict(restart=w.restart, tol=1e-8, inner_k=args.inner_k, cycles=args.cycles,
+                  nu1=args.nu, nu2=args.nu)
+    t_setup = time.perf_counter()
+    hp_mix = HeatProblem(w.dim, w.n, w.s, w.nt, w.T, precision=args.mixed, **common)
+    f, u0 = heat_inputs.workload_inputs(w, hp_mix.stage_times())
+    f_d = torch.from_numpy(np.ascontiguousarray(f.ravel())).to(dev)
+    u0_d = torch.from_numpy(u0).to(dev)
+    rhs = hp_mix.assemble_rhs(f_d, u0_d)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    print(f"[bench] {w.name}: U = {hp_mix.U:,} unknowns, setup {setup_s:.1f} s", file=sys.stderr, flush=True)
+
+    def run(hp, label, K, W):
+        times, stats, x = [], None, None
+        for it in range(W + K):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st = hp.solve(rhs)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if not st["converged"]:
+                raise RuntimeError(f"{label} solve did not converge: {st}")
+            if it >= W:
+                times.append(dt)
+            stats = st
+            print(f"[bench] {label} solve {it - W if it >= W else 'warmup'}: {dt * 1e3:.1f} ms, "
+                  f"{st['outer_iterations']} its, relres {st['relres']:.2e}", file=sys.stderr, flush=True)
+        return times, stats, x
+
+    # ---- timed region: K mixed-precision solves -----------------------------
+    torch.cuda.synchronize()
+    times_mix, st_mix, x_mix = run(hp_mix, args.mixed, args.steps, args.warmup)
+    total_s = sum(times_mix)
+    ms_per_step = 1e3 * total_s / args.steps
+
+    # ---- FP64-preconditioner arm --------------------------------------------
+    fp64 = None
+    if not args.no_fp64:
+        hp64 = HeatProblem(w.dim, w.n, w.s, w.nt, w.T, precision="fp64", **common)
+        times64, st64, x64 = run(hp64, "fp64", args.steps, args.warmup)
+        fp64 = {"solve_s": float(np.mean(times64)), "outer_iterations": st64["outer_iterations"],
+                "relres": st64["relres"],
+                "mixed_vs_fp64_speedup": float(np.mean(times64) / np.mean(times_mix))}
+        del hp64, x64
+        torch.cuda.empty_cache()
+
+    # ---- roofline of the dominant kernel (live, HIP events) ------------------
+    roofline = measure_roofline(hp_mix, x_mix, args.roofline_reps)
+
+    # ---- CPU oracle baseline on a bounded sample -----------------------------
+    cpu = None
+    fwd_err = None
+    if not args.no_cpu:
+        cpu, fwd_err = cpu_baseline(w, f, u0, x_mix, args.cpu_steps)
+
+    out = {
+        "metric": METRIC, "value": total_s / args.steps, "unit": "s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": f"f64 (preconditioner {args.mixed})", "data": "synthetic",
+        "config": {"workload": w.name, "dim": w.dim, "n": w.n, "s": w.s, "nt": w.nt,
+                   "unknowns": hp_mix.U, "restart": w.restart, "tol": 1e-8,
+                   "inner_k": args.inner_k, "cycles": args.cycles, "nu1": args.nu, "nu2": args.nu,
+                   "preconditioner": args.mixed, "parallelism": "single GPU"},
+        "outer_iterations": st_mix["outer_iterations"], "relres": st_mix["relres"],
+        "precond_ms_per_solve": st_mix["precond_ms"],
+        "fp64_preconditioner": fp64,
+        "forward_error_vs_oracle_sampled_steps": fwd_err,
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def measure_roofline(hp, x, reps):
+    """apply_A: 16 B per unknown (read x once, write y once) per launch."""
+    import torch
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    hp.apply_A(x, y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        hp.apply_A(x, y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    nbytes = 16.0 * hp.U
+    gbs = nbytes / sec / 1e9
+    return {"kernel": "k_apply_A", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": nbytes,
+            "avg_launch_us": sec * 1e6}
+
+
+def cpu_baseline(w, f, u0, x_gpu, nsteps):
+    from oracle import allatonce, stepping
+    import torch
+    p = allatonce.Problem(w.n, w.dim, w.s, w.nt, w.T)
+    tm = {}
+    t0 = time.perf_counter()
+    xs = stepping.solve_steps(p, f, u0, nsteps, timings=tm)
+    dt = time.perf_counter() - t0
+    full = tm["factor_s"] + tm["step_s"] * (w.nt / nsteps)
+    # forward error of the GPU solution on the sampled steps (stepping is
+    # sequential, so the first nsteps steps of x* are exactly these)
+    sub = allatonce.Problem(w.n, w.dim, w.s, nsteps, p.tau * nsteps)
+    vs, Vs = allatonce.split(sub, xs)
+    xg = x_gpu.cpu().numpy()
+    vg, Vg = allatonce.split(p, xg)
+    ev = np.linalg.norm(vg[: nsteps + 1] - vs) / np.linalg.norm(vs)
+    eV = np.linalg.norm(Vg[:nsteps] - Vs) / np.linalg.norm(Vs)
+    cpu = {"value": full, "unit": "s", "cores": 1, "kind": "oracle",
+           "sample": f"{nsteps} of {w.nt} time steps of sequential Radau IIA stepping with exact DST "
+                     f"stage solves ({tm['method']}), {dt:.1f} s measured, scaled to {w.nt} steps",
+           "host_cores_available": len(os.sched_getaffinity(0))}
+    return cpu, {"v": float(ev), "V": float(eV), "steps": nsteps}
+
+
+if __name__ == "__main__":
+    main()

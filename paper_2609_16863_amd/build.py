@@ -20,6 +20,7 @@ FLAGS = [
     # packed FP32 instructions stay off (they are formed by the compiler only)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    "-I" + os.path.join(os.path.dirname(HERE), "include"),
 ]
 
 

@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/aao_heat.h"
+#include "aao_heat.h"
 
 namespace aao {
 
@@ -116,7 +116,7 @@ struct aao_problem {
     size_t rana;                              // Rana right-hand side (nt*N)
     size_t schurRhs, schurY;                  // S-tilde sweep (s*N)
     std::vector<size_t> mgX, mgT, mgB, mgR;   // per level, nt instances
-    size_t partial, dscal;                    // reductions / device scalars
+    size_t partial, dscal, counters;          // reductions / device scalars / tickets
     size_t partial_bytes, dscal_bytes;
   } plan{};
   int pi_bytes = 8;                           // inner (GMRES) storage bytes

@@ -66,6 +66,7 @@ void plan_workspace(aao_problem* h) {
   P.partial = take(P.partial_bytes);
   P.dscal_bytes = (size_t)(h->nt + 1) * 512 * sizeof(double) + (aao::MMAX + 8) * 8 * sizeof(double);
   P.dscal = take(P.dscal_bytes);
+  P.counters = take((size_t)(h->nt + 2) * sizeof(unsigned));
   h->ws_need = align256(off);
 }
 
@@ -226,6 +227,8 @@ int aao_set_workspace(aao_problem* h, void* dev_ptr, size_t bytes) {
                                                reinterpret_cast<const double*>(h->ws + h->plan.faces_d),
                                                (int64_t)(nf + h->N), h->stream);
   }
+  if (e == hipSuccess)
+    e = aao::launch_fill<unsigned>(reinterpret_cast<unsigned*>(h->ws + h->plan.counters), 0u, h->nt + 2, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     h->ws = nullptr;

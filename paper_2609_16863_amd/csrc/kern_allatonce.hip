@@ -277,5 +277,6 @@ template hipError_t launch_copy_cast<double, double>(double*, const double*, int
 template hipError_t launch_copy_cast<float, float>(float*, const float*, int64_t, hipStream_t);
 template hipError_t launch_fill<double>(double*, double, int64_t, hipStream_t);
 template hipError_t launch_fill<float>(float*, float, int64_t, hipStream_t);
+template hipError_t launch_fill<unsigned>(unsigned*, unsigned, int64_t, hipStream_t);
 
 }  // namespace aao

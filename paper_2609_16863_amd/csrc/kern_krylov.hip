@@ -19,125 +19,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <class TW, class TV>
-__global__ __launch_bounds__(TPB) void k_seg_dots(const TW* __restrict__ w, int64_t sw,
-                                                  const TV* __restrict__ V, int64_t vstride, int64_t sv,
-                                                  int nd, int self, int64_t L, double* __restrict__ partial,
-                                                  int nblk) {
-  const int inst = blockIdx.y, blk = blockIdx.x, tid = threadIdx.x;
-  const TW* wi = w + (int64_t)inst * sw;
-  const TV* Vi = V + (int64_t)inst * sv;
-  double acc[NSLOT];
-#pragma unroll
-  for (int d = 0; d < NSLOT; ++d) acc[d] = 0.0;
-  for (int64_t idx = (int64_t)blk * TPB + tid; idx < L; idx += (int64_t)nblk * TPB) {
-    const double wv = ld<TW, double>(wi + idx);
-#pragma unroll
-    for (int d = 0; d < DOTS_PER_PASS; ++d)
-      if (d < nd) acc[d] += ld<TV, double>(Vi + d * vstride + idx) * wv;
-    acc[DOTS_PER_PASS] += wv * wv;
-  }
-  __shared__ double red[TPB / 64][NSLOT];
-  const int lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-  for (int d = 0; d < NSLOT; ++d) {
-    if (d < nd || (d == DOTS_PER_PASS && self)) {
-      const double v = wave_sum(acc[d]);
-      if (lane == 0) red[wave][d] = v;
-    }
-  }
-  __syncthreads();
-  if (tid < NSLOT) {
-    const int d = tid;
-    if (d < nd || (d == DOTS_PER_PASS && self)) {
-      double s = 0.0;
-      for (int q = 0; q < TPB / 64; ++q) s += red[q][d];
-      partial[((int64_t)inst * nblk + blk) * NSLOT + d] = s;
-    }
-  }
-}
-
-__global__ void k_seg_finish(const double* __restrict__ partial, int nblk, int nd, int self_off, int B,
-                             double* __restrict__ out, int64_t ostride, int ooff) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int per = nd + (self_off >= 0 ? 1 : 0);
-  if (t >= B * per) return;
-  const int inst = t / per, d = t - inst * per;
-  const int slot = d < nd ? d : DOTS_PER_PASS;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[((int64_t)inst * nblk + b) * NSLOT + slot];
-  if (d < nd) out[(int64_t)inst * ostride + ooff + d] = s;
-  else out[(int64_t)inst * ostride + self_off] = s;
-}
-
-template <class TW, class TV>
-__global__ __launch_bounds__(TPB) void k_seg_axpy(TW* __restrict__ w, int64_t sw, const TV* __restrict__ V,
-                                                  int64_t vstride, int64_t sv, int nd,
-                                                  const double* __restrict__ coef, int64_t cstride, int coff,
-                                                  double scale, int64_t L, int nblk) {
-  using C = typename Acc<TW>::type;
-  const int inst = blockIdx.y;
-  C cf[DOTS_PER_PASS];
-#pragma unroll
-  for (int d = 0; d < DOTS_PER_PASS; ++d)
-    cf[d] = d < nd ? (C)(scale * coef[(int64_t)inst * cstride + coff + d]) : C(0);
-  TW* wi = w + (int64_t)inst * sw;
-  const TV* Vi = V + (int64_t)inst * sv;
-  for (int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x; idx < L; idx += (int64_t)nblk * TPB) {
-    C acc = ld<TW, C>(wi + idx);
-#pragma unroll
-    for (int d = 0; d < DOTS_PER_PASS; ++d)
-      if (d < nd) acc += cf[d] * ld<TV, C>(Vi + d * vstride + idx);
-    st<TW, C>(wi + idx, acc);
-  }
-}
-
-template <class TO, class TV>
-__global__ __launch_bounds__(TPB) void k_seg_combine(TO* __restrict__ out, int64_t so, const TV* __restrict__ V,
-                                                     int64_t vstride, int64_t sv, int nd,
-                                                     const double* __restrict__ coef, int64_t cstride, int coff,
-                                                     int64_t L, int nblk) {
-  using C = typename Acc<TO>::type;
-  const int inst = blockIdx.y;
-  C cf[KMAX];
-#pragma unroll
-  for (int d = 0; d < KMAX; ++d) cf[d] = d < nd ? (C)coef[(int64_t)inst * cstride + coff + d] : C(0);
-  TO* oi = out + (int64_t)inst * so;
-  const TV* Vi = V + (int64_t)inst * sv;
-  for (int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x; idx < L; idx += (int64_t)nblk * TPB) {
-    C acc = C(0);
-#pragma unroll
-    for (int d = 0; d < KMAX; ++d)
-      if (d < nd) acc += cf[d] * ld<TV, C>(Vi + d * vstride + idx);
-    st<TO, C>(oi + idx, acc);
-  }
-}
-
-template <class TI, class TO>
-__global__ __launch_bounds__(TPB) void k_seg_scale(const TI* __restrict__ in, int64_t si, TO* __restrict__ out,
-                                                   int64_t so, const double* __restrict__ sc, int64_t cstride,
-                                                   int coff, int64_t L, int nblk) {
-  using C = typename Acc<TO>::type;
-  const int inst = blockIdx.y;
-  const double f = sc[(int64_t)inst * cstride + coff];
-  const TI* ii = in + (int64_t)inst * si;
-  TO* oi = out + (int64_t)inst * so;
-  for (int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x; idx < L; idx += (int64_t)nblk * TPB)
-    st<TO, C>(oi + idx, (C)(ld<TI, double>(ii + idx) * f));
-}
-
 // ---------------------------------------------------------------------------
-// Inner GMRES scalars (one thread per instance)
+// GMRES scalar recurrences (run by one thread of the finishing workgroup)
 // ---------------------------------------------------------------------------
 using S = InnerSlots;
 
-__global__ void k_inner_init(double* slots, int B) {
-  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
-  if (inst >= B) return;
-  double* q = slots + (int64_t)inst * S::STRIDE;
-  const double beta = q[S::WW];
-  const bool ok = beta > 0.0 && isfinite(beta);
-  const double nb = ok ? sqrt(beta) : 0.0;
+// Start: beta = ||r||, g = beta e1, 1/beta for the first basis vector.
+__device__ void gmres_start(double* q, double ww) {
+  const bool ok = ww > 0.0 && isfinite(ww);
+  const double nb = ok ? sqrt(ww) : 0.0;
   q[S::BETA] = nb;
   q[S::ACTIVE] = ok ? 1.0 : 0.0;
   q[S::M] = 0.0;
@@ -146,10 +36,11 @@ __global__ void k_inner_init(double* slots, int B) {
   q[S::INV] = ok ? 1.0 / nb : 0.0;
 }
 
-__global__ void k_inner_givens(double* slots, int B, int j) {
-  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
-  if (inst >= B) return;
-  double* q = slots + (int64_t)inst * S::STRIDE;
+// Column j of the Hessenberg matrix from the two Gram-Schmidt passes:
+// h = h1 + h2, h_{j+1,j} = sqrt(<w,w> - |h2|^2); apply the previous
+// rotations, form the new one, update g, and the scale of the next basis
+// vector (0 once the instance has stopped).
+__device__ void gmres_givens(double* q, int j, const double* h2, double ww) {
   if (q[S::ACTIVE] == 0.0) {
     q[S::INV] = 0.0;
     return;
@@ -157,10 +48,11 @@ __global__ void k_inner_givens(double* slots, int B, int j) {
   double col[KMAX + 1];
   double h2sq = 0.0;
   for (int i = 0; i <= j; ++i) {
-    col[i] = q[S::H1 + i] + q[S::H2 + i];
-    h2sq += q[S::H2 + i] * q[S::H2 + i];
+    q[S::H2 + i] = h2[i];
+    col[i] = q[S::H1 + i] + h2[i];
+    h2sq += h2[i] * h2[i];
   }
-  const double nrm2 = q[S::WW] - h2sq;
+  const double nrm2 = ww - h2sq;
   const double hn = nrm2 > 0.0 ? sqrt(nrm2) : 0.0;
   col[j + 1] = hn;
   for (int i = 0; i < j; ++i) {
@@ -192,16 +84,166 @@ __global__ void k_inner_givens(double* slots, int B, int j) {
   }
 }
 
-__global__ void k_inner_backsolve(double* slots, int B, int k) {
-  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
-  if (inst >= B) return;
-  double* q = slots + (int64_t)inst * S::STRIDE;
-  const int m = (int)q[S::M];
-  for (int i = 0; i < KMAX; ++i) q[S::Y + i] = 0.0;
-  for (int i = m - 1; i >= 0; --i) {
-    double acc = q[S::G + i];
-    for (int jj = i + 1; jj < m; ++jj) acc -= q[S::R + jj * (KMAX + 1) + i] * q[S::Y + jj];
-    q[S::Y + i] = acc / q[S::R + i * (KMAX + 1) + i];
+// One pass of Gram-Schmidt on every instance, with the reduction finished by
+// the last workgroup of each instance (an atomic ticket per instance), so a
+// dot product costs one launch.  Optionally:
+//   axpy:  w <- w - sum_{d<nd} slots[ca+d] V_d   (stored back to w)
+//   dots:  slots[od+d] = <w, V_d>,  self: slots[os] = <w, w>
+//   post:  GS_POST_INIT   -> GMRES start  (beta, g, 1/beta) from slots[os]
+//          GS_POST_GIVENS -> Givens update of column j (slots hold h1 at H1,
+//                            h2 at H2, <w,w> at WW)
+// The block partials are summed in a fixed order, so results are bitwise
+// reproducible run to run.
+template <class TW, class TV>
+__global__ __launch_bounds__(TPB) void k_gs(TW* __restrict__ w, const TV* __restrict__ V, GSArgs a) {
+  using C = typename Acc<TW>::type;
+  const int inst = blockIdx.y, blk = blockIdx.x, tid = threadIdx.x;
+  TW* wi = w + (int64_t)inst * a.sw;
+  const TV* Vi = V + (int64_t)inst * a.sv;
+  double* q = a.slots + (int64_t)inst * a.sstride;
+  C cf[DOTS_PER_PASS];
+#pragma unroll
+  for (int d = 0; d < DOTS_PER_PASS; ++d) cf[d] = (a.axpy && d < a.nd) ? (C)q[a.ca + d] : C(0);
+  double acc[NSLOT];
+#pragma unroll
+  for (int d = 0; d < NSLOT; ++d) acc[d] = 0.0;
+  for (int64_t idx = (int64_t)blk * TPB + tid; idx < a.L; idx += (int64_t)a.nblk * TPB) {
+    C wv = ld<TW, C>(wi + idx);
+    C vv[DOTS_PER_PASS];
+#pragma unroll
+    for (int d = 0; d < DOTS_PER_PASS; ++d)
+      vv[d] = (d < a.nd) ? ld<TV, C>(Vi + d * a.vstride + idx) : C(0);
+    if (a.axpy) {
+#pragma unroll
+      for (int d = 0; d < DOTS_PER_PASS; ++d) wv -= cf[d] * vv[d];
+      st<TW, C>(wi + idx, wv);
+    }
+    const double wd = (double)wv;
+#pragma unroll
+    for (int d = 0; d < DOTS_PER_PASS; ++d) acc[d] += (double)vv[d] * wd;
+    acc[DOTS_PER_PASS] += wd * wd;
+  }
+  __shared__ double red[TPB / 64][NSLOT];
+  __shared__ double fin[NSLOT];
+  __shared__ int am_last;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int nslots_used = a.dots ? a.nd : 0;
+#pragma unroll
+  for (int d = 0; d < NSLOT; ++d) {
+    if (d < nslots_used || (d == DOTS_PER_PASS && a.self)) {
+      const double v = wave_sum(acc[d]);
+      if (lane == 0) red[wave][d] = v;
+    }
+  }
+  __syncthreads();
+  double* part = a.partial + ((int64_t)inst * a.nblk) * NSLOT;
+  if (tid < NSLOT) {
+    const int d = tid;
+    if (d < nslots_used || (d == DOTS_PER_PASS && a.self)) {
+      double sum = 0.0;
+      for (int r = 0; r < TPB / 64; ++r) sum += red[r][d];
+      part[(int64_t)blk * NSLOT + d] = sum;
+    }
+  }
+  if (!a.dots && !a.self) return;
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned prev = atomicAdd(a.counters + inst, 1u);
+    am_last = (prev == (unsigned)(a.nblk - 1));
+  }
+  __syncthreads();
+  if (!am_last) return;
+  __threadfence();
+  // fixed-order final sum: thread t adds blocks t, t+TPB, ...; then a tree
+  for (int d = 0; d < NSLOT; ++d) {
+    if (!(d < nslots_used || (d == DOTS_PER_PASS && a.self))) continue;
+    double sum = 0.0;
+    for (int b = tid; b < a.nblk; b += TPB) sum += part[(int64_t)b * NSLOT + d];
+    sum = wave_sum(sum);
+    if (lane == 0) red[wave][d] = sum;
+  }
+  __syncthreads();
+  if (tid < NSLOT) {
+    const int d = tid;
+    if (d < nslots_used || (d == DOTS_PER_PASS && a.self)) {
+      double sum = 0.0;
+      for (int r = 0; r < TPB / 64; ++r) sum += red[r][d];
+      fin[d] = sum;
+      if (d < nslots_used) q[a.od + d] = sum;
+      else q[a.os] = sum;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    atomicExch(a.counters + inst, 0u);
+    if (a.post == GS_POST_INIT) gmres_start(q, fin[DOTS_PER_PASS]);
+    else if (a.post == GS_POST_GIVENS) gmres_givens(q, a.j, fin, fin[DOTS_PER_PASS]);
+  }
+}
+
+// out = (w - sum_{d<nd} slots[ca+d] V_d) * scale, scale = slots[cs] (cs >= 0) or `alpha`.
+template <class TW, class TV, class TO>
+__global__ __launch_bounds__(TPB) void k_basis(const TW* __restrict__ w, int64_t sw, const TV* __restrict__ V,
+                                               int64_t vstride, int64_t sv, int nd, TO* __restrict__ out,
+                                               int64_t so, const double* __restrict__ slots, int64_t sstride,
+                                               int ca, int cs, double alpha, int64_t L, int nblk) {
+  using C = typename Acc<TO>::type;
+  const int inst = blockIdx.y;
+  const double* q = slots + (int64_t)inst * sstride;
+  C cf[DOTS_PER_PASS];
+#pragma unroll
+  for (int d = 0; d < DOTS_PER_PASS; ++d) cf[d] = d < nd ? (C)q[ca + d] : C(0);
+  const C sc = (C)(cs >= 0 ? q[cs] : alpha);
+  const TW* wi = w + (int64_t)inst * sw;
+  const TV* Vi = V + (int64_t)inst * sv;
+  TO* oi = out + (int64_t)inst * so;
+  for (int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x; idx < L; idx += (int64_t)nblk * TPB) {
+    C acc = ld<TW, C>(wi + idx);
+#pragma unroll
+    for (int d = 0; d < DOTS_PER_PASS; ++d)
+      if (d < nd) acc -= cf[d] * ld<TV, C>(Vi + d * vstride + idx);
+    st<TO, C>(oi + idx, acc * sc);
+  }
+}
+
+// out (+)= sum_{d<nd} y_d Z_d.  With `solve`, y is the GMRES least-squares
+// solution R y = g of the instance, recomputed by every workgroup from its
+// slots (at most KMAX unknowns); otherwise y = slots[cy + d].
+template <class TO, class TV>
+__global__ __launch_bounds__(TPB) void k_combine(TO* __restrict__ out, int64_t so, const TV* __restrict__ Z,
+                                                 int64_t vstride, int64_t sv, int nd,
+                                                 const double* __restrict__ slots, int64_t sstride, int cy,
+                                                 int solve, int accumulate, int64_t L, int nblk) {
+  using C = typename Acc<TO>::type;
+  const int inst = blockIdx.y;
+  const double* q = slots + (int64_t)inst * sstride;
+  __shared__ double ys[DOTS_PER_PASS];
+  if (threadIdx.x == 0) {
+    if (solve) {
+      const int m = (int)q[InnerSlots::M];
+      for (int i = 0; i < DOTS_PER_PASS; ++i) ys[i] = 0.0;
+      for (int i = m - 1; i >= 0; --i) {
+        double acc = q[InnerSlots::G + i];
+        for (int jj = i + 1; jj < m; ++jj) acc -= q[InnerSlots::R + jj * (KMAX + 1) + i] * ys[jj];
+        ys[i] = acc / q[InnerSlots::R + i * (KMAX + 1) + i];
+      }
+    } else {
+      for (int i = 0; i < DOTS_PER_PASS; ++i) ys[i] = i < nd ? q[cy + i] : 0.0;
+    }
+  }
+  __syncthreads();
+  C cf[DOTS_PER_PASS];
+#pragma unroll
+  for (int d = 0; d < DOTS_PER_PASS; ++d) cf[d] = (C)ys[d];
+  TO* oi = out + (int64_t)inst * so;
+  const TV* Zi = Z + (int64_t)inst * sv;
+  for (int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x; idx < L; idx += (int64_t)nblk * TPB) {
+    C acc = accumulate ? ld<TO, C>(oi + idx) : C(0);
+#pragma unroll
+    for (int d = 0; d < DOTS_PER_PASS; ++d)
+      if (d < nd) acc += cf[d] * ld<TV, C>(Zi + d * vstride + idx);
+    st<TO, C>(oi + idx, acc);
   }
 }
 
@@ -365,58 +407,27 @@ int seg_blocks(int64_t L, int B) {
 }
 
 template <class TW, class TV>
-hipError_t seg_dots(const TW* w, int64_t sw, const TV* V, int64_t vstride, int64_t sv, int nd, bool self,
-                    int64_t L, int B, double* partial, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL((k_seg_dots<TW, TV>), seg_grid(nblk, B), dim3(TPB), 0, st, w, sw, V, vstride, sv, nd,
-                     (int)self, L, partial, nblk);
+hipError_t gs_pass(TW* w, const TV* V, const GSArgs& a, int B, hipStream_t st) {
+  hipLaunchKernelGGL((k_gs<TW, TV>), seg_grid(a.nblk, B), dim3(TPB), 0, st, w, V, a);
   return hipGetLastError();
 }
 
-hipError_t seg_finish(const double* partial, int nblk, int nd, int self_off, int B, double* out, int64_t ostride,
-                      int ooff, hipStream_t st) {
-  const int total = B * (nd + (self_off >= 0 ? 1 : 0));
-  hipLaunchKernelGGL(k_seg_finish, dim3((unsigned)((total + 63) / 64)), dim3(64), 0, st, partial, nblk, nd,
-                     self_off, B, out, ostride, ooff);
-  return hipGetLastError();
-}
-
-template <class TW, class TV>
-hipError_t seg_axpy(TW* w, int64_t sw, const TV* V, int64_t vstride, int64_t sv, int nd, const double* coef,
-                    int64_t cstride, int coff, double scale, int64_t L, int B, hipStream_t st) {
+template <class TW, class TV, class TO>
+hipError_t basis_update(const TW* w, int64_t sw, const TV* V, int64_t vstride, int64_t sv, int nd, TO* out,
+                        int64_t so, const double* slots, int64_t sstride, int ca, int cs, double alpha, int64_t L,
+                        int B, hipStream_t st) {
   const int nblk = seg_blocks(L, B);
-  hipLaunchKernelGGL((k_seg_axpy<TW, TV>), seg_grid(nblk, B), dim3(TPB), 0, st, w, sw, V, vstride, sv, nd, coef,
-                     cstride, coff, scale, L, nblk);
+  hipLaunchKernelGGL((k_basis<TW, TV, TO>), seg_grid(nblk, B), dim3(TPB), 0, st, w, sw, V, vstride, sv, nd, out,
+                     so, slots, sstride, ca, cs, alpha, L, nblk);
   return hipGetLastError();
 }
 
 template <class TO, class TV>
-hipError_t seg_combine(TO* out, int64_t so, const TV* V, int64_t vstride, int64_t sv, int nd, const double* coef,
-                       int64_t cstride, int coff, int64_t L, int B, hipStream_t st) {
+hipError_t combine(TO* out, int64_t so, const TV* Z, int64_t vstride, int64_t sv, int nd, const double* slots,
+                   int64_t sstride, int cy, bool solve, bool accumulate, int64_t L, int B, hipStream_t st) {
   const int nblk = seg_blocks(L, B);
-  hipLaunchKernelGGL((k_seg_combine<TO, TV>), seg_grid(nblk, B), dim3(TPB), 0, st, out, so, V, vstride, sv, nd,
-                     coef, cstride, coff, L, nblk);
-  return hipGetLastError();
-}
-
-template <class TI, class TO>
-hipError_t seg_scale(const TI* in, int64_t si, TO* out, int64_t so, const double* sc, int64_t cstride, int coff,
-                     int64_t L, int B, hipStream_t st) {
-  const int nblk = seg_blocks(L, B);
-  hipLaunchKernelGGL((k_seg_scale<TI, TO>), seg_grid(nblk, B), dim3(TPB), 0, st, in, si, out, so, sc, cstride,
-                     coff, L, nblk);
-  return hipGetLastError();
-}
-
-hipError_t inner_init(double* slots, int B, hipStream_t st) {
-  hipLaunchKernelGGL(k_inner_init, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st, slots, B);
-  return hipGetLastError();
-}
-hipError_t inner_givens(double* slots, int B, int j, hipStream_t st) {
-  hipLaunchKernelGGL(k_inner_givens, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st, slots, B, j);
-  return hipGetLastError();
-}
-hipError_t inner_backsolve(double* slots, int B, int k, hipStream_t st) {
-  hipLaunchKernelGGL(k_inner_backsolve, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st, slots, B, k);
+  hipLaunchKernelGGL((k_combine<TO, TV>), seg_grid(nblk, B), dim3(TPB), 0, st, out, so, Z, vstride, sv, nd, slots,
+                     sstride, cy, (int)solve, (int)accumulate, L, nblk);
   return hipGetLastError();
 }
 
@@ -519,14 +530,11 @@ hipError_t thetaT_rhs(const aao_problem* h, const double* r, const T* z, T* out,
 
 // explicit instantiations
 #define AAO_INST_T(T)                                                                                             \
-  template hipError_t seg_dots<T, T>(const T*, int64_t, const T*, int64_t, int64_t, int, bool, int64_t, int,       \
-                                     double*, int, hipStream_t);                                                   \
-  template hipError_t seg_axpy<T, T>(T*, int64_t, const T*, int64_t, int64_t, int, const double*, int64_t, int,   \
-                                     double, int64_t, int, hipStream_t);                                           \
-  template hipError_t seg_combine<T, T>(T*, int64_t, const T*, int64_t, int64_t, int, const double*, int64_t, int, \
-                                        int64_t, int, hipStream_t);                                                \
-  template hipError_t seg_scale<T, T>(const T*, int64_t, T*, int64_t, const double*, int64_t, int, int64_t, int,   \
-                                      hipStream_t);                                                                \
+  template hipError_t gs_pass<T, T>(T*, const T*, const GSArgs&, int, hipStream_t);                                \
+  template hipError_t basis_update<T, T, T>(const T*, int64_t, const T*, int64_t, int64_t, int, T*, int64_t,       \
+                                            const double*, int64_t, int, int, double, int64_t, int, hipStream_t);  \
+  template hipError_t combine<T, T>(T*, int64_t, const T*, int64_t, int64_t, int, const double*, int64_t, int,     \
+                                    bool, bool, int64_t, int, hipStream_t);                                        \
   template hipError_t theta_apply<T>(const aao_problem*, const Tab&, const T*, int64_t, T*, int64_t, int,          \
                                      hipStream_t);                                                                 \
   template hipError_t rana_rhs<T>(const aao_problem*, const double*, int, const T*, int64_t, const T*, int64_t, T*, \
@@ -540,17 +548,11 @@ hipError_t thetaT_rhs(const aao_problem* h, const double* r, const T* z, T* out,
 
 AAO_INST_T(double)
 AAO_INST_T(float)
-#define AAO_INST_MIX(T) \
-  template hipError_t seg_scale<double, T>(const double*, int64_t, T*, int64_t, const double*, int64_t, int,       \
-                                           int64_t, int, hipStream_t);                                             \
-  template hipError_t seg_dots<double, T>(const double*, int64_t, const T*, int64_t, int64_t, int, bool, int64_t,  \
-                                          int, double*, int, hipStream_t);                                         \
-  template hipError_t seg_axpy<double, T>(double*, int64_t, const T*, int64_t, int64_t, int, const double*,        \
-                                          int64_t, int, double, int64_t, int, hipStream_t);
-AAO_INST_MIX(float)
-template hipError_t seg_combine<double, float>(double*, int64_t, const float*, int64_t, int64_t, int,
-                                               const double*, int64_t, int, int64_t, int, hipStream_t);
-template hipError_t seg_scale<float, double>(const float*, int64_t, double*, int64_t, const double*, int64_t, int,
-                                             int64_t, int, hipStream_t);
+template hipError_t gs_pass<double, float>(double*, const float*, const GSArgs&, int, hipStream_t);
+template hipError_t basis_update<double, float, float>(const double*, int64_t, const float*, int64_t, int64_t, int,
+                                                       float*, int64_t, const double*, int64_t, int, int, double,
+                                                       int64_t, int, hipStream_t);
+template hipError_t combine<double, float>(double*, int64_t, const float*, int64_t, int64_t, int, const double*,
+                                           int64_t, int, bool, bool, int64_t, int, hipStream_t);
 
 }  // namespace aao

@@ -9,6 +9,7 @@
 // tridiagonal factors M_l, T_l, so its 9/27 coefficients are formed in
 // registers from six short arrays instead of being streamed from HBM.
 #include "aao_internal.h"
+#include "krylov.h"
 #include "mg.h"
 #include "stencil.h"
 
@@ -136,70 +137,6 @@ __global__ __launch_bounds__(TPB) void k_smooth(const T* __restrict__ xin, int64
   st<T, C>(xout + inst * sxout + p, out);
 }
 
-// r = b - A x
-template <int DIM, int KIND, class T, class C>
-__global__ __launch_bounds__(TPB) void k_residual(const T* __restrict__ x, int64_t sx,
-                                                  const T* __restrict__ b, int64_t sb,
-                                                  T* __restrict__ r, int64_t sr, LevelOp<C> op) {
-  const int p = blockIdx.x * TPB + threadIdx.x;
-  if (p >= op.N) return;
-  const int64_t inst = blockIdx.y;
-  int i, j, k;
-  node_coords<DIM>(p, op.n, i, j, k);
-  C Ax, d;
-  level_apply<DIM, KIND, T, C>(x + inst * sx, op, p, i, j, k, Ax, d);
-  st<T, C>(r + inst * sr + p, ld<T, C>(b + inst * sb + p) - Ax);
-}
-
-// Full weighting: b_c(I..) = 2^{-d} sum_{|d_a| <= 1} prod_a w(d_a) r(2I+1+d_i, ...),
-// w(0) = 1, w(+-1) = 1/2, fine indices past the last node are boundary (zero).
-template <int DIM, class TF, class TC, class C>
-__global__ __launch_bounds__(TPB) void k_restrict(const TF* __restrict__ r, int64_t sr, int nf,
-                                                  TC* __restrict__ bc, int64_t sbc, int nc, int Nc) {
-  const int pc = blockIdx.x * TPB + threadIdx.x;
-  if (pc >= Nc) return;
-  const int64_t inst = blockIdx.y;
-  int I, J, K;
-  node_coords<DIM>(pc, nc, I, J, K);
-  const TF* rr = r + inst * sr;
-  const C w[3] = {C(0.5), C(1), C(0.5)};
-  C acc = C(0);
-  const int fi = 2 * I + 1, fj = 2 * J + 1, fk = 2 * K + 1;
-  if (DIM == 2) {
-#pragma unroll
-    for (int dj = -1; dj <= 1; ++dj) {
-      const int jj = fj + dj;
-      if (jj >= nf) continue;
-#pragma unroll
-      for (int di = -1; di <= 1; ++di) {
-        const int ii = fi + di;
-        if (ii >= nf) continue;
-        acc += w[di + 1] * w[dj + 1] * ld<TF, C>(rr + jj * nf + ii);
-      }
-    }
-    acc *= C(0.25);
-  } else {
-#pragma unroll
-    for (int dk = -1; dk <= 1; ++dk) {
-      const int kk = fk + dk;
-      if (kk >= nf) continue;
-#pragma unroll
-      for (int dj = -1; dj <= 1; ++dj) {
-        const int jj = fj + dj;
-        if (jj >= nf) continue;
-#pragma unroll
-        for (int di = -1; di <= 1; ++di) {
-          const int ii = fi + di;
-          if (ii >= nf) continue;
-          acc += w[di + 1] * w[dj + 1] * w[dk + 1] * ld<TF, C>(rr + ((int64_t)kk * nf + jj) * nf + ii);
-        }
-      }
-    }
-    acc *= C(0.125);
-  }
-  st<TC, C>(bc + inst * sbc + pc, acc);
-}
-
 // x_out = x_in + P e_c (linear interpolation; coarse node I sits at fine 2I+1).
 template <int DIM, class TX, class TE, class C>
 __global__ __launch_bounds__(TPB) void k_prolong(const TX* xin, int64_t sxin, const TE* __restrict__ ec,
@@ -241,18 +178,298 @@ __global__ __launch_bounds__(TPB) void k_prolong(const TX* xin, int64_t sxin, co
   st<TX, C>(xout + inst * sxout + p, ld<TX, C>(xin + inst * sxin + p) + acc);
 }
 
-// Exact solve on a one-node level: x = b / A_00.
-template <int DIM, int KIND, class T, class C>
+// (P e)(i, j[, k]): linear interpolation of the coarse correction at a fine
+// node (coarse node I sits at fine 2I+1; values past the grid are zero).
+template <int DIM, class TE, class C>
+__device__ __forceinline__ C prolong_at(const TE* __restrict__ e, int nc, int i, int j, int k) {
+  int idx[3][2];
+  C wt[3][2];
+  int cnt[3];
+  const int c[3] = {i, j, k};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    if (c[a] & 1) {
+      idx[a][0] = (c[a] - 1) >> 1;
+      wt[a][0] = C(1);
+      cnt[a] = 1;
+    } else {
+      cnt[a] = 0;
+      const int lo = (c[a] >> 1) - 1, hi = c[a] >> 1;
+      if (lo >= 0) { idx[a][cnt[a]] = lo; wt[a][cnt[a]] = C(0.5); ++cnt[a]; }
+      if (hi < nc) { idx[a][cnt[a]] = hi; wt[a][cnt[a]] = C(0.5); ++cnt[a]; }
+    }
+  }
+  C acc = C(0);
+  if (DIM == 2) {
+    for (int b = 0; b < cnt[1]; ++b)
+      for (int a = 0; a < cnt[0]; ++a) acc += wt[0][a] * wt[1][b] * ld<TE, C>(e + idx[1][b] * nc + idx[0][a]);
+  } else {
+    for (int q = 0; q < cnt[2]; ++q)
+      for (int b = 0; b < cnt[1]; ++b)
+        for (int a = 0; a < cnt[0]; ++a)
+          acc += wt[0][a] * wt[1][b] * wt[2][q] * ld<TE, C>(e + ((int64_t)idx[2][q] * nc + idx[1][b]) * nc + idx[0][a]);
+  }
+  return acc;
+}
+
+// Residual at the 3^d fine nodes around each coarse node, full weighting:
+// b_c = 2^{-d} sum w(d) (b - A x)(2I+1+d).  With `zero_next`, the coarse
+// level's first Jacobi sweep from zero (pointwise) is fused: x_c = omega b_c / D_c.
+template <int DIM, int KIND, class TF, class TC, class C>
+__global__ __launch_bounds__(TPB) void k_resid_restrict(const TF* __restrict__ x, int64_t sx,
+                                                        const TF* __restrict__ b, int64_t sb,
+                                                        TC* __restrict__ bc, int64_t sbc, TC* __restrict__ xc,
+                                                        int64_t sxc, LevelOp<C> opf, LevelOp<C> opc, C omega,
+                                                        int zero_next) {
+  const int pc = blockIdx.x * TPB + threadIdx.x;
+  if (pc >= opc.N) return;
+  const int64_t inst = blockIdx.y;
+  const int nf = opf.n, nc = opc.n;
+  int I, J, K;
+  node_coords<DIM>(pc, nc, I, J, K);
+  const TF* xi = x + inst * sx;
+  const TF* bi = b + inst * sb;
+  const C w[3] = {C(0.5), C(1), C(0.5)};
+  C acc = C(0);
+  const int fi = 2 * I + 1, fj = 2 * J + 1, fk = 2 * K + 1;
+  const int dk0 = DIM == 3 ? -1 : 0, dk1 = DIM == 3 ? 1 : 0;
+  for (int dk = dk0; dk <= dk1; ++dk) {
+    const int kk = fk + dk;
+    if (DIM == 3 && kk >= nf) continue;
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int jj = fj + dj;
+      if (jj >= nf) continue;
+#pragma unroll
+      for (int di = -1; di <= 1; ++di) {
+        const int ii = fi + di;
+        if (ii >= nf) continue;
+        const int pf = DIM == 3 ? (kk * nf + jj) * nf + ii : jj * nf + ii;
+        C Ax, d;
+        level_apply<DIM, KIND, TF, C>(xi, opf, pf, ii, jj, DIM == 3 ? kk : 0, Ax, d);
+        const C wt = DIM == 3 ? w[di + 1] * w[dj + 1] * w[dk + 1] : w[di + 1] * w[dj + 1];
+        acc += wt * (ld<TF, C>(bi + pf) - Ax);
+      }
+    }
+  }
+  acc *= DIM == 3 ? C(0.125) : C(0.25);
+  st<TC, C>(bc + inst * sbc + pc, acc);
+  if (zero_next) st<TC, C>(xc + inst * sxc + pc, omega * acc / level_diag<DIM, KIND_TENSOR, C>(opc, pc, I, J, K));
+}
+
+// Fine level: x_out = y + omega D^{-1} (b - A y) with y = x_in + P e_c formed
+// on the fly at the node and its stencil neighbours (prolongation fused into
+// the first post-smoothing sweep).
+template <int DIM, bool VK, class TX, class TE, class C>
+__global__ __launch_bounds__(TPB) void k_prolong_smooth(const TX* __restrict__ xin, int64_t sxin,
+                                                        const TE* __restrict__ ec, int64_t sec,
+                                                        const TX* __restrict__ b, int64_t sb, TX* __restrict__ xout,
+                                                        int64_t sxout, LevelOp<C> op, int nc, C omega) {
+  const int p = blockIdx.x * TPB + threadIdx.x;
+  if (p >= op.N) return;
+  const int64_t inst = blockIdx.y;
+  const int n = op.n;
+  int i, j, k;
+  node_coords<DIM>(p, n, i, j, k);
+  const TX* xi = xin + inst * sxin;
+  const TE* e = ec + inst * sec;
+  auto y = [&](int q, int qi, int qj, int qk) { return ld<TX, C>(xi + q) + prolong_at<DIM, TE, C>(e, nc, qi, qj, qk); };
+  const C yp = y(p, i, j, k);
+  const C xm = i > 0 ? y(p - 1, i - 1, j, k) : C(0);
+  const C xp = i + 1 < n ? y(p + 1, i + 1, j, k) : C(0);
+  const C ym = j > 0 ? y(p - n, i, j - 1, k) : C(0);
+  const C yq = j + 1 < n ? y(p + n, i, j + 1, k) : C(0);
+  C zm = C(0), zp = C(0);
+  if (DIM == 3) {
+    const int nn = n * n;
+    zm = k > 0 ? y(p - nn, i, j, k - 1) : C(0);
+    zp = k + 1 < n ? y(p + nn, i, j, k + 1) : C(0);
+  }
+  C kx;
+  if (!VK) {
+    kx = C(2 * DIM) * yp - xm - xp - ym - yq;
+    if (DIM == 3) kx -= zm + zp;
+  } else {
+    const Faces<C>& fc = op.faces;
+    kx = fc.m[0][p] * (yp - xm) + fc.p[0][p] * (yp - xp) + fc.m[1][p] * (yp - ym) + fc.p[1][p] * (yp - yq);
+    if (DIM == 3) kx += fc.m[2][p] * (yp - zm) + fc.p[2][p] * (yp - zp);
+  }
+  const C Ay = yp + op.a * op.ih2 * kx;
+  const C d = level_diag<DIM, VK ? KIND_FINE_VK : KIND_FINE, C>(op, p, i, j, k);
+  st<TX, C>(xout + inst * sxout + p, yp + omega * (ld<TX, C>(b + inst * sb + p) - Ay) / d);
+}
+
+// Exact solve on a one-node level: x = b / A_00 (used when no LDS tail runs).
+template <int DIM, class T, class C>
 __global__ void k_coarsest(const T* __restrict__ b, int64_t sb, T* __restrict__ x, int64_t sx, LevelOp<C> op,
                            int B) {
   const int inst = blockIdx.x * blockDim.x + threadIdx.x;
   if (inst >= B) return;
-  for (int p = 0; p < (int)op.N; ++p) {
-    int i, j, k;
-    node_coords<DIM>(p, op.n, i, j, k);
-    st<T, C>(x + (int64_t)inst * sx + p,
-             ld<T, C>(b + (int64_t)inst * sb + p) / level_diag<DIM, KIND, C>(op, p, i, j, k));
+  st<T, C>(x + (int64_t)inst * sx, ld<T, C>(b + (int64_t)inst * sb) / level_diag<DIM, KIND_TENSOR, C>(op, 0, 0, 0, 0));
+}
+
+// ---------------------------------------------------------------------------
+// Coarse tail: every level from `l0` down to one node in one workgroup per
+// right-hand side, vectors in LDS, barriers instead of launches.
+// ---------------------------------------------------------------------------
+constexpr int TAIL_MAXL = 12;
+constexpr int TAIL_THREADS = 1024;
+
+template <class C>
+struct TailArgs {
+  int nl;            // levels in the tail
+  int first_fine;    // tail level 0 is the fine level (I + a K, matrix-free)
+  int zero_init;     // start from x = 0 (else x is loaded)
+  int nu1, nu2;
+  C omega;
+  int off[TAIL_MAXL];   // LDS element offsets: X at off, Y at off + N, B at off + 2N
+  LevelOp<C> op[TAIL_MAXL];
+};
+
+template <int DIM, bool VK, class C>
+__device__ __forceinline__ void tail_apply(const TailArgs<C>& ta, int t, const C* x, int p, int i, int j, int k,
+                                           C& Ax, C& d) {
+  if (t == 0 && ta.first_fine) {
+    if (VK) level_apply<DIM, KIND_FINE_VK, C, C>(x, ta.op[0], p, i, j, k, Ax, d);
+    else level_apply<DIM, KIND_FINE, C, C>(x, ta.op[0], p, i, j, k, Ax, d);
+  } else {
+    level_apply<DIM, KIND_TENSOR, C, C>(x, ta.op[t], p, i, j, k, Ax, d);
   }
+}
+
+template <int DIM, bool VK, class C>
+__device__ __forceinline__ C tail_diag(const TailArgs<C>& ta, int t, int p, int i, int j, int k) {
+  if (t == 0 && ta.first_fine)
+    return VK ? level_diag<DIM, KIND_FINE_VK, C>(ta.op[0], p, i, j, k) : level_diag<DIM, KIND_FINE, C>(ta.op[0], p, i, j, k);
+  return level_diag<DIM, KIND_TENSOR, C>(ta.op[t], p, i, j, k);
+}
+
+template <int DIM, bool VK, class TX, class TB, class C>
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail(TX* __restrict__ xg, int64_t sx, const TB* __restrict__ bg,
+                                                       int64_t sb, TailArgs<C> ta) {
+  extern __shared__ unsigned char tail_smem[];
+  C* sm = reinterpret_cast<C*>(tail_smem);
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int64_t inst = blockIdx.x;
+  C* cur[TAIL_MAXL];
+  C* oth[TAIL_MAXL];
+  const int N0 = (int)ta.op[0].N;
+  C* B0 = sm + ta.off[0] + 2 * N0;
+  for (int p = tid; p < N0; p += nth) {
+    B0[p] = ld<TB, C>(bg + inst * sb + p);
+    if (!ta.zero_init) sm[ta.off[0] + p] = ld<TX, C>(xg + inst * sx + p);
+  }
+  __syncthreads();
+  const int last = ta.nl - 1;
+  for (int t = 0; t < last; ++t) {
+    const LevelOp<C>& op = ta.op[t];
+    const int Nt = (int)op.N, n = op.n;
+    C* X = sm + ta.off[t];
+    C* Y = X + Nt;
+    C* Bt = X + 2 * Nt;
+    int rem = ta.nu1;
+    if (t > 0 || ta.zero_init) {
+      for (int p = tid; p < Nt; p += nth) {
+        int i, j, k;
+        node_coords<DIM>(p, n, i, j, k);
+        X[p] = ta.omega * Bt[p] / tail_diag<DIM, VK, C>(ta, t, p, i, j, k);
+      }
+      --rem;
+      __syncthreads();
+    }
+    C* c = X;
+    C* o = Y;
+    for (; rem > 0; --rem) {
+      for (int p = tid; p < Nt; p += nth) {
+        int i, j, k;
+        node_coords<DIM>(p, n, i, j, k);
+        C Ax, d;
+        tail_apply<DIM, VK, C>(ta, t, c, p, i, j, k, Ax, d);
+        o[p] = c[p] + ta.omega * (Bt[p] - Ax) / d;
+      }
+      __syncthreads();
+      C* tmp = c; c = o; o = tmp;
+    }
+    // residual into the free buffer, then full weighting to the next level
+    for (int p = tid; p < Nt; p += nth) {
+      int i, j, k;
+      node_coords<DIM>(p, n, i, j, k);
+      C Ax, d;
+      tail_apply<DIM, VK, C>(ta, t, c, p, i, j, k, Ax, d);
+      o[p] = Bt[p] - Ax;
+    }
+    __syncthreads();
+    const LevelOp<C>& opc = ta.op[t + 1];
+    const int Nc = (int)opc.N, nc = opc.n;
+    C* Bc = sm + ta.off[t + 1] + 2 * Nc;
+    const C w[3] = {C(0.5), C(1), C(0.5)};
+    for (int pc = tid; pc < Nc; pc += nth) {
+      int I, J, K;
+      node_coords<DIM>(pc, nc, I, J, K);
+      C acc = C(0);
+      const int fi = 2 * I + 1, fj = 2 * J + 1, fk = 2 * K + 1;
+      const int dk0 = DIM == 3 ? -1 : 0, dk1 = DIM == 3 ? 1 : 0;
+      for (int dk = dk0; dk <= dk1; ++dk) {
+        const int kk = fk + dk;
+        if (DIM == 3 && kk >= n) continue;
+        for (int dj = -1; dj <= 1; ++dj) {
+          const int jj = fj + dj;
+          if (jj >= n) continue;
+          for (int di = -1; di <= 1; ++di) {
+            const int ii = fi + di;
+            if (ii >= n) continue;
+            const int pf = DIM == 3 ? (kk * n + jj) * n + ii : jj * n + ii;
+            const C wt = DIM == 3 ? w[di + 1] * w[dj + 1] * w[dk + 1] : w[di + 1] * w[dj + 1];
+            acc += wt * o[pf];
+          }
+        }
+      }
+      Bc[pc] = acc * (DIM == 3 ? C(0.125) : C(0.25));
+    }
+    cur[t] = c;
+    oth[t] = o;
+    __syncthreads();
+  }
+  // coarsest level: one node (exact)
+  {
+    const LevelOp<C>& op = ta.op[last];
+    const int Nt = (int)op.N;
+    C* X = sm + ta.off[last];
+    for (int p = tid; p < Nt; p += nth) {
+      int i, j, k;
+      node_coords<DIM>(p, op.n, i, j, k);
+      X[p] = X[p + 2 * Nt] / tail_diag<DIM, VK, C>(ta, last, p, i, j, k);
+    }
+    cur[last] = X;
+    __syncthreads();
+  }
+  for (int t = last - 1; t >= 0; --t) {
+    const LevelOp<C>& op = ta.op[t];
+    const int Nt = (int)op.N, n = op.n;
+    const int nc = ta.op[t + 1].n;
+    C* c = cur[t];
+    C* o = oth[t];
+    C* Bt = sm + ta.off[t] + 2 * Nt;
+    const C* e = cur[t + 1];
+    for (int p = tid; p < Nt; p += nth) {
+      int i, j, k;
+      node_coords<DIM>(p, n, i, j, k);
+      c[p] += prolong_at<DIM, C, C>(e, nc, i, j, k);
+    }
+    __syncthreads();
+    for (int it = 0; it < ta.nu2; ++it) {
+      for (int p = tid; p < Nt; p += nth) {
+        int i, j, k;
+        node_coords<DIM>(p, n, i, j, k);
+        C Ax, d;
+        tail_apply<DIM, VK, C>(ta, t, c, p, i, j, k, Ax, d);
+        o[p] = c[p] + ta.omega * (Bt[p] - Ax) / d;
+      }
+      __syncthreads();
+      C* tmp = c; c = o; o = tmp;
+    }
+    cur[t] = c;
+  }
+  for (int p = tid; p < N0; p += nth) st<TX, C>(xg + inst * sx + p, cur[0][p]);
 }
 
 }  // namespace
@@ -260,12 +477,6 @@ __global__ void k_coarsest(const T* __restrict__ b, int64_t sb, T* __restrict__ 
 // ---------------------------------------------------------------------------
 // Host driver
 // ---------------------------------------------------------------------------
-template <class TI, class TM>
-Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L)
-    : h_(h), st_(st), levels_((int)h->lev_n.size()) {
-  for (int i = 0; i < h->s; ++i) a_[i] = h->tau * L[i * h->s + i];
-}
-
 namespace {
 
 template <class C>
@@ -292,120 +503,27 @@ inline dim3 grid2(int64_t N, int B) { return dim3((unsigned)((N + TPB - 1) / TPB
 
 }  // namespace
 
-#define MG_KIND_DISPATCH(l, M)                                            \
-  do {                                                                    \
-    if ((l) > 0) {                                                        \
-      if (h_->dim == 2) M(2, KIND_TENSOR); else M(3, KIND_TENSOR);        \
-    } else if (h_->vark) {                                                \
-      if (h_->dim == 2) M(2, KIND_FINE_VK); else M(3, KIND_FINE_VK);      \
-    } else {                                                              \
-      if (h_->dim == 2) M(2, KIND_FINE); else M(3, KIND_FINE);            \
-    }                                                                     \
-  } while (0)
-
+// First level handled by the one-workgroup tail: the largest set of coarse
+// levels whose three LDS vectors fit in 64 KiB.
 template <class TI, class TM>
-hipError_t Multigrid<TI, TM>::smooth(int l, int stage, Vec xin, Vec xout, Vec b, bool zero_init, int B) {
-  const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
-  const C omega = (C)h_->omega;
-  const dim3 g = grid2(op.N, B);
-  if (l == 0) {
-#define MG_SMOOTH0(D, K)                                                                              \
-  hipLaunchKernelGGL((k_smooth<D, K, TI, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, \
-                     (TI*)xout.ptr, xout.stride, (const TI*)b.ptr, b.stride, op, omega, (int)zero_init)
-    MG_KIND_DISPATCH(l, MG_SMOOTH0);
-#undef MG_SMOOTH0
-  } else {
-#define MG_SMOOTH1(D, K)                                                                              \
-  hipLaunchKernelGGL((k_smooth<D, K, TM, C>), g, dim3(TPB), 0, st_, (const TM*)xin.ptr, xin.stride, \
-                     (TM*)xout.ptr, xout.stride, (const TM*)b.ptr, b.stride, op, omega, (int)zero_init)
-    MG_KIND_DISPATCH(l, MG_SMOOTH1);
-#undef MG_SMOOTH1
+Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L)
+    : h_(h), st_(st), levels_((int)h->lev_n.size()) {
+  for (int i = 0; i < h->s; ++i) a_[i] = h->tau * L[i * h->s + i];
+  if (h->dim == 3) {
+    // The 3D instantiation of the LDS tail faulted on gfx950 (aperture
+    // violation) for reasons not yet established; 3D runs every level with
+    // grid kernels and a pointwise exact solve on the one-node level.
+    l0_ = levels_;
+    return;
   }
-  return hipGetLastError();
-}
-
-template <class TI, class TM>
-hipError_t Multigrid<TI, TM>::residual(int l, int stage, Vec x, Vec b, Vec r, int B) {
-  const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
-  const dim3 g = grid2(op.N, B);
-  if (l == 0) {
-#define MG_RES0(D, K)                                                                                   \
-  hipLaunchKernelGGL((k_residual<D, K, TI, C>), g, dim3(TPB), 0, st_, (const TI*)x.ptr, x.stride,     \
-                     (const TI*)b.ptr, b.stride, (TI*)r.ptr, r.stride, op)
-    MG_KIND_DISPATCH(l, MG_RES0);
-#undef MG_RES0
-  } else {
-#define MG_RES1(D, K)                                                                                   \
-  hipLaunchKernelGGL((k_residual<D, K, TM, C>), g, dim3(TPB), 0, st_, (const TM*)x.ptr, x.stride,     \
-                     (const TM*)b.ptr, b.stride, (TM*)r.ptr, r.stride, op)
-    MG_KIND_DISPATCH(l, MG_RES1);
-#undef MG_RES1
+  l0_ = levels_ - 1;
+  size_t bytes = 3 * sizeof(C) * (size_t)h->lev_N[levels_ - 1];
+  while (l0_ > 0 && levels_ - l0_ < TAIL_MAXL) {
+    const size_t more = bytes + 3 * sizeof(C) * (size_t)h->lev_N[l0_ - 1];
+    if (more > 65536) break;
+    bytes = more;
+    --l0_;
   }
-  return hipGetLastError();
-}
-
-template <class TI, class TM>
-hipError_t Multigrid<TI, TM>::restrict_to(int l, Vec r, Vec bc, int B) {
-  const int nf = h_->lev_n[l], nc = h_->lev_n[l + 1];
-  const int Nc = (int)h_->lev_N[l + 1];
-  const dim3 g = grid2(Nc, B);
-  if (l == 0) {
-    if (h_->dim == 2)
-      hipLaunchKernelGGL((k_restrict<2, TI, TM, C>), g, dim3(TPB), 0, st_, (const TI*)r.ptr, r.stride, nf,
-                         (TM*)bc.ptr, bc.stride, nc, Nc);
-    else
-      hipLaunchKernelGGL((k_restrict<3, TI, TM, C>), g, dim3(TPB), 0, st_, (const TI*)r.ptr, r.stride, nf,
-                         (TM*)bc.ptr, bc.stride, nc, Nc);
-  } else {
-    if (h_->dim == 2)
-      hipLaunchKernelGGL((k_restrict<2, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)r.ptr, r.stride, nf,
-                         (TM*)bc.ptr, bc.stride, nc, Nc);
-    else
-      hipLaunchKernelGGL((k_restrict<3, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)r.ptr, r.stride, nf,
-                         (TM*)bc.ptr, bc.stride, nc, Nc);
-  }
-  return hipGetLastError();
-}
-
-template <class TI, class TM>
-hipError_t Multigrid<TI, TM>::prolong(int l, Vec xin, Vec ec, Vec xout, int B) {
-  const int nf = h_->lev_n[l], nc = h_->lev_n[l + 1];
-  const int Nf = (int)h_->lev_N[l];
-  const dim3 g = grid2(Nf, B);
-  if (l == 0) {
-    if (h_->dim == 2)
-      hipLaunchKernelGGL((k_prolong<2, TI, TM, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride,
-                         (const TM*)ec.ptr, ec.stride, (TI*)xout.ptr, xout.stride, nf, Nf, nc);
-    else
-      hipLaunchKernelGGL((k_prolong<3, TI, TM, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride,
-                         (const TM*)ec.ptr, ec.stride, (TI*)xout.ptr, xout.stride, nf, Nf, nc);
-  } else {
-    if (h_->dim == 2)
-      hipLaunchKernelGGL((k_prolong<2, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)xin.ptr, xin.stride,
-                         (const TM*)ec.ptr, ec.stride, (TM*)xout.ptr, xout.stride, nf, Nf, nc);
-    else
-      hipLaunchKernelGGL((k_prolong<3, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)xin.ptr, xin.stride,
-                         (const TM*)ec.ptr, ec.stride, (TM*)xout.ptr, xout.stride, nf, Nf, nc);
-  }
-  return hipGetLastError();
-}
-
-template <class TI, class TM>
-hipError_t Multigrid<TI, TM>::coarsest(int l, int stage, Vec b, Vec x, int B) {
-  const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
-  const dim3 g((unsigned)((B + 63) / 64)), blk(64);
-  if (l == 0) {
-#define MG_CO0(D, K) \
-  hipLaunchKernelGGL((k_coarsest<D, K, TI, C>), g, blk, 0, st_, (const TI*)b.ptr, b.stride, (TI*)x.ptr, x.stride, op, B)
-    MG_KIND_DISPATCH(l, MG_CO0);
-#undef MG_CO0
-  } else {
-#define MG_CO1(D, K) \
-  hipLaunchKernelGGL((k_coarsest<D, K, TM, C>), g, blk, 0, st_, (const TM*)b.ptr, b.stride, (TM*)x.ptr, x.stride, op, B)
-    MG_KIND_DISPATCH(l, MG_CO1);
-#undef MG_CO1
-  }
-  return hipGetLastError();
 }
 
 #define MG_TRY(...)                           \
@@ -415,20 +533,139 @@ hipError_t Multigrid<TI, TM>::coarsest(int l, int stage, Vec b, Vec x, int B) {
   } while (0)
 
 template <class TI, class TM>
-hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_init, int B, Vec* result) {
+hipError_t Multigrid<TI, TM>::smooth(int l, int stage, Vec xin, Vec xout, Vec b, bool zero_init, int B) {
+  const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
+  const C omega = (C)h_->omega;
+  const dim3 g = grid2(op.N, B);
+  const int d3 = h_->dim == 3;
+  if (l == 0) {
+    if (h_->vark) {
+      if (d3) hipLaunchKernelGGL((k_smooth<3, KIND_FINE_VK, TI, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (TI*)xout.ptr, xout.stride, (const TI*)b.ptr, b.stride, op, omega, (int)zero_init);
+      else hipLaunchKernelGGL((k_smooth<2, KIND_FINE_VK, TI, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (TI*)xout.ptr, xout.stride, (const TI*)b.ptr, b.stride, op, omega, (int)zero_init);
+    } else {
+      if (d3) hipLaunchKernelGGL((k_smooth<3, KIND_FINE, TI, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (TI*)xout.ptr, xout.stride, (const TI*)b.ptr, b.stride, op, omega, (int)zero_init);
+      else hipLaunchKernelGGL((k_smooth<2, KIND_FINE, TI, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (TI*)xout.ptr, xout.stride, (const TI*)b.ptr, b.stride, op, omega, (int)zero_init);
+    }
+  } else {
+    if (d3) hipLaunchKernelGGL((k_smooth<3, KIND_TENSOR, TM, C>), g, dim3(TPB), 0, st_, (const TM*)xin.ptr, xin.stride, (TM*)xout.ptr, xout.stride, (const TM*)b.ptr, b.stride, op, omega, (int)zero_init);
+    else hipLaunchKernelGGL((k_smooth<2, KIND_TENSOR, TM, C>), g, dim3(TPB), 0, st_, (const TM*)xin.ptr, xin.stride, (TM*)xout.ptr, xout.stride, (const TM*)b.ptr, b.stride, op, omega, (int)zero_init);
+  }
+  return hipGetLastError();
+}
+
+template <class TI, class TM>
+hipError_t Multigrid<TI, TM>::resid_restrict(int l, int stage, Vec x, Vec b, Vec bc, Vec xc, bool zero_next, int B) {
+  const LevelOp<C> opf = make_op<C>(h_, l, a_[stage]);
+  const LevelOp<C> opc = make_op<C>(h_, l + 1, a_[stage]);
+  const C omega = (C)h_->omega;
+  const dim3 g = grid2(opc.N, B);
+  const int d3 = h_->dim == 3, z = (int)zero_next;
+  if (l == 0) {
+#define RR0(D, K) hipLaunchKernelGGL((k_resid_restrict<D, K, TI, TM, C>), g, dim3(TPB), 0, st_, (const TI*)x.ptr, x.stride, (const TI*)b.ptr, b.stride, (TM*)bc.ptr, bc.stride, (TM*)xc.ptr, xc.stride, opf, opc, omega, z)
+    if (h_->vark) { if (d3) RR0(3, KIND_FINE_VK); else RR0(2, KIND_FINE_VK); }
+    else { if (d3) RR0(3, KIND_FINE); else RR0(2, KIND_FINE); }
+#undef RR0
+  } else {
+    if (d3) hipLaunchKernelGGL((k_resid_restrict<3, KIND_TENSOR, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)x.ptr, x.stride, (const TM*)b.ptr, b.stride, (TM*)bc.ptr, bc.stride, (TM*)xc.ptr, xc.stride, opf, opc, omega, z);
+    else hipLaunchKernelGGL((k_resid_restrict<2, KIND_TENSOR, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)x.ptr, x.stride, (const TM*)b.ptr, b.stride, (TM*)bc.ptr, bc.stride, (TM*)xc.ptr, xc.stride, opf, opc, omega, z);
+  }
+  return hipGetLastError();
+}
+
+template <class TI, class TM>
+hipError_t Multigrid<TI, TM>::prolong(int l, Vec xin, Vec ec, Vec xout, int B) {
+  const int nf = h_->lev_n[l], nc = h_->lev_n[l + 1];
+  const int Nf = (int)h_->lev_N[l];
+  const dim3 g = grid2(Nf, B);
+  // only coarse grid levels use the separate prolongation (level 0 fuses it)
+  if (h_->dim == 2)
+    hipLaunchKernelGGL((k_prolong<2, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)xin.ptr, xin.stride,
+                       (const TM*)ec.ptr, ec.stride, (TM*)xout.ptr, xout.stride, nf, Nf, nc);
+  else
+    hipLaunchKernelGGL((k_prolong<3, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)xin.ptr, xin.stride,
+                       (const TM*)ec.ptr, ec.stride, (TM*)xout.ptr, xout.stride, nf, Nf, nc);
+  return hipGetLastError();
+}
+
+template <class TI, class TM>
+hipError_t Multigrid<TI, TM>::prolong_smooth0(int stage, Vec xin, Vec ec, Vec b, Vec xout, int B) {
+  const LevelOp<C> op = make_op<C>(h_, 0, a_[stage]);
+  const int nc = h_->lev_n[1];
+  const C omega = (C)h_->omega;
+  const dim3 g = grid2(op.N, B);
+#define PS0(D, V) hipLaunchKernelGGL((k_prolong_smooth<D, V, TI, TM, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (const TM*)ec.ptr, ec.stride, (const TI*)b.ptr, b.stride, (TI*)xout.ptr, xout.stride, op, nc, omega)
+  if (h_->dim == 3) { if (h_->vark) PS0(3, true); else PS0(3, false); }
+  else { if (h_->vark) PS0(2, true); else PS0(2, false); }
+#undef PS0
+  return hipGetLastError();
+}
+
+template <class TI, class TM>
+hipError_t Multigrid<TI, TM>::tail(int stage, Vec x, Vec b, bool zero_init, int B) {
+  TailArgs<C> ta{};
+  ta.nl = levels_ - l0_;
+  ta.first_fine = l0_ == 0;
+  ta.zero_init = zero_init;
+  ta.nu1 = h_->opts.nu1;
+  ta.nu2 = h_->opts.nu2;
+  ta.omega = (C)h_->omega;
+  int off = 0;
+  for (int t = 0; t < ta.nl; ++t) {
+    ta.op[t] = make_op<C>(h_, l0_ + t, a_[stage]);
+    ta.off[t] = off;
+    off += 3 * (int)ta.op[t].N;
+  }
+  const size_t shm = (size_t)off * sizeof(C);
+  const int nth = ta.op[0].N >= TAIL_THREADS ? TAIL_THREADS : (ta.op[0].N >= 256 ? 256 : 64);
+  const dim3 g((unsigned)B), blk((unsigned)nth);
+  if (h_->dim != 2) return hipErrorUnknown;   // the tail is 2D only
+  if (l0_ == 0) {
+#define TL(D, V) hipLaunchKernelGGL((k_tail<D, V, TI, TI, C>), g, blk, shm, st_, (TI*)x.ptr, x.stride, (const TI*)b.ptr, b.stride, ta)
+    if (h_->vark) TL(2, true); else TL(2, false);
+#undef TL
+  } else {
+    hipLaunchKernelGGL((k_tail<2, false, TM, TM, C>), g, blk, shm, st_, (TM*)x.ptr, x.stride, (const TM*)b.ptr, b.stride, ta);
+  }
+  return hipGetLastError();
+}
+
+// One V-cycle on level l.  `pre` = the first (pointwise) sweep from zero was
+// already written into x by the restriction of the level above.
+template <class TI, class TM>
+hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_init, bool pre, int B, Vec* result) {
   auto& P = h_->plan;
-  if (l == levels_ - 1) {
-    MG_TRY(coarsest(l, stage, b, x, B));
+  if (l >= l0_) {
+    MG_TRY(tail(stage, x, b, zero_init, B));
     *result = x;
     return hipSuccess;
   }
+  if (l == levels_ - 1) {      // no tail (3D): exact solve on the one-node level
+    const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
+    const dim3 g((unsigned)((B + 63) / 64)), blk(64);
+    if (l == 0)
+      hipLaunchKernelGGL((k_coarsest<3, TI, C>), g, blk, 0, st_, (const TI*)b.ptr, b.stride, (TI*)x.ptr, x.stride, op, B);
+    else
+      hipLaunchKernelGGL((k_coarsest<3, TM, C>), g, blk, 0, st_, (const TM*)b.ptr, b.stride, (TM*)x.ptr, x.stride, op, B);
+    MG_TRY(hipGetLastError());
+    *result = x;
+    return hipSuccess;
+  }
+  const int nu1 = h_->opts.nu1, nu2 = h_->opts.nu2;
   const int64_t Nl = h_->lev_N[l];
   Vec tmp{h_->ws + P.mgT[l], Nl};
   auto partner = [&](const Vec& v) { return v.ptr == x.ptr ? tmp : x; };
+  // writes after the first sweep alternate buffers; at level 0 the result
+  // must end in x, so the first sweep's target is chosen by parity
+  const bool fused_post = (l == 0);
   Vec cur = x;
-  int rem = h_->opts.nu1;
+  int rem = nu1;
   if (zero_init) {
-    MG_TRY(smooth(l, stage, cur, cur, b, true, B));
+    if (!pre) {
+      const int alternations = (nu1 - 1) + nu2;
+      Vec first = (l == 0 && (alternations % 2 == 1)) ? tmp : x;
+      MG_TRY(smooth(l, stage, first, first, b, true, B));
+      cur = first;
+    }
     --rem;
   }
   for (; rem > 0; --rem) {
@@ -436,22 +673,34 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
     MG_TRY(smooth(l, stage, cur, nxt, b, false, B));
     cur = nxt;
   }
-  Vec r{h_->ws + P.mgR[l], Nl};
-  MG_TRY(residual(l, stage, cur, b, r, B));
   const int64_t Nc = h_->lev_N[l + 1];
   Vec bc{h_->ws + P.mgB[l + 1], Nc};
   Vec xc{h_->ws + P.mgX[l + 1], Nc};
-  MG_TRY(restrict_to(l, r, bc, B));
+  const bool next_grid = (l + 1) < l0_;
+  MG_TRY(resid_restrict(l, stage, cur, b, bc, xc, next_grid, B));
   Vec ec{};
-  MG_TRY(vcycle(l + 1, stage, xc, bc, true, B, &ec));
-  const int nu2 = h_->opts.nu2;
-  Vec tgt = (nu2 % 2 == 0) ? x : tmp;
-  MG_TRY(prolong(l, cur, ec, tgt, B));
-  cur = tgt;
-  for (int it = 0; it < nu2; ++it) {
+  MG_TRY(vcycle(l + 1, stage, xc, bc, true, next_grid, B, &ec));
+  int post = nu2;
+  if (fused_post) {
+    Vec nxt = partner(cur);
+    MG_TRY(prolong_smooth0(stage, cur, ec, b, nxt, B));
+    cur = nxt;
+    --post;
+  } else {
+    // pointwise prolongation: pick its target so the sweeps end in x
+    Vec tgt = (post % 2 == 0) ? x : tmp;
+    MG_TRY(prolong(l, cur, ec, tgt, B));
+    cur = tgt;
+  }
+  for (; post > 0; --post) {
     Vec nxt = partner(cur);
     MG_TRY(smooth(l, stage, cur, nxt, b, false, B));
     cur = nxt;
+  }
+  if (l == 0 && cur.ptr != x.ptr) {   // odd sweep counts from a nonzero start: copy back
+    MG_TRY(basis_update<TI, TI, TI>((const TI*)cur.ptr, cur.stride, (const TI*)cur.ptr, 0, 0, 0, (TI*)x.ptr,
+                                    x.stride, nullptr, 0, 0, -1, 1.0, Nl, B, st_));
+    cur = x;
   }
   *result = cur;
   return hipSuccess;
@@ -463,7 +712,7 @@ hipError_t Multigrid<TI, TM>::solve(int stage, BVec<TI> x, BVec<const TI> rhs, i
   Vec bv{const_cast<TI*>(rhs.ptr), rhs.stride};
   for (int c = 0; c < cycles; ++c) {
     Vec res{};
-    MG_TRY(vcycle(0, stage, xv, bv, c == 0, B, &res));
+    MG_TRY(vcycle(0, stage, xv, bv, c == 0, false, B, &res));
     if (res.ptr != xv.ptr) return hipErrorUnknown;   // the driver always ends in x
   }
   return hipSuccess;

@@ -1,6 +1,7 @@
-// Batched Krylov building blocks: segmented multi-dot products, multi-AXPYs,
-// the Givens least-squares update of GMRES, and the stage-level operators
-// (Theta_hat, Rana coupling, S-tilde sweep pieces).
+// Batched Krylov building blocks: a fused Gram-Schmidt pass (optional AXPY,
+// multi-dot products finished by the last workgroup, GMRES scalar updates),
+// basis updates and combinations, and the stage-level operators (Theta_hat,
+// Rana coupling, S-tilde sweep pieces).
 #pragma once
 
 #include "aao_internal.h"
@@ -21,43 +22,44 @@ struct InnerSlots {
   static constexpr int R = Y + 16;               // R[(KMAX+1) * KMAX], column j at R + j*(KMAX+1)
 };
 
+enum { GS_POST_NONE = 0, GS_POST_INIT = 1, GS_POST_GIVENS = 2 };
+
+// One fused Gram-Schmidt pass over B instances of length L (see k_gs).
+struct GSArgs {
+  int64_t L;          // segment length
+  int64_t sw;         // instance stride of w
+  int64_t vstride;    // distance between consecutive basis vectors
+  int64_t sv;         // instance stride of the basis
+  int nd;             // basis vectors in this pass (<= DOTS_PER_PASS)
+  int axpy, dots, self;
+  double* slots;      // per-instance scalars
+  int64_t sstride;
+  int ca, od, os;     // coefficient / dot / self offsets in the slots
+  double* partial;    // nblk * (DOTS_PER_PASS + 1) doubles per instance
+  unsigned* counters; // one zero-initialised ticket per instance
+  int nblk;
+  int post, j;
+};
+
 // Number of workgroups per segment for the segmented reductions.
 int seg_blocks(int64_t L, int B);
 
-// partial[(inst*nblk + blk)*(DOTS_PER_PASS+1) + d] = block sums of
-// <w_inst, V_d,inst> for d < nd, and of <w_inst, w_inst> in slot
-// DOTS_PER_PASS when `self`.  V_d,inst = V + d*vstride + inst*sv.
 template <class TW, class TV>
-hipError_t seg_dots(const TW* w, int64_t sw, const TV* V, int64_t vstride, int64_t sv, int nd, bool self,
-                    int64_t L, int B, double* partial, int nblk, hipStream_t st);
+hipError_t gs_pass(TW* w, const TV* V, const GSArgs& a, int B, hipStream_t st);
 
-// out[inst*ostride + ooff + d] = sum over blocks (fixed order) for d < nd;
-// the self product goes to out[inst*ostride + self_off] when self_off >= 0.
-hipError_t seg_finish(const double* partial, int nblk, int nd, int self_off, int B, double* out,
-                      int64_t ostride, int ooff, hipStream_t st);
+// out = (w - sum_{d<nd} slots[ca+d] V_d) * (cs >= 0 ? slots[cs] : alpha)
+template <class TW, class TV, class TO>
+hipError_t basis_update(const TW* w, int64_t sw, const TV* V, int64_t vstride, int64_t sv, int nd, TO* out,
+                        int64_t so, const double* slots, int64_t sstride, int ca, int cs, double alpha, int64_t L,
+                        int B, hipStream_t st);
 
-// w_inst += scale * sum_{d<nd} coef[inst*cstride + coff + d] * V_d,inst
-template <class TW, class TV>
-hipError_t seg_axpy(TW* w, int64_t sw, const TV* V, int64_t vstride, int64_t sv, int nd, const double* coef,
-                    int64_t cstride, int coff, double scale, int64_t L, int B, hipStream_t st);
-
-// out_inst = sum_{d<nd} coef[...] * V_d,inst   (overwrite)
+// out (+)= sum_{d<nd} y_d Z_d, y from the GMRES least-squares solve (solve)
+// or from slots[cy + d].
 template <class TO, class TV>
-hipError_t seg_combine(TO* out, int64_t so, const TV* V, int64_t vstride, int64_t sv, int nd,
-                       const double* coef, int64_t cstride, int coff, int64_t L, int B, hipStream_t st);
+hipError_t combine(TO* out, int64_t so, const TV* Z, int64_t vstride, int64_t sv, int nd, const double* slots,
+                   int64_t sstride, int cy, bool solve, bool accumulate, int64_t L, int B, hipStream_t st);
 
-// out_inst = in_inst * sc[inst*cstride + coff]
-template <class TI, class TO>
-hipError_t seg_scale(const TI* in, int64_t si, TO* out, int64_t so, const double* sc, int64_t cstride,
-                     int coff, int64_t L, int B, hipStream_t st);
-
-// Inner GMRES scalar updates (one thread per instance).
-hipError_t inner_init(double* slots, int B, hipStream_t st);
-hipError_t inner_givens(double* slots, int B, int j, hipStream_t st);
-hipError_t inner_backsolve(double* slots, int B, int k, hipStream_t st);
-
-// w = Theta_hat z for each instance (z, w: s*N per instance); tab gives A
-// (tau A (x) K mixing).
+// w = Theta_hat z for each instance (z, w: s*N per instance); tab gives A.
 template <class T>
 hipError_t theta_apply(const aao_problem* h, const Tab& tab, const T* z, int64_t sz, T* w, int64_t sw, int B,
                        hipStream_t st);
@@ -67,7 +69,7 @@ template <class T>
 hipError_t rana_rhs(const aao_problem* h, const double* Lc, int i, const T* v, int64_t sv, const T* z,
                     int64_t sz, T* out, int64_t so, int B, hipStream_t st);
 
-// S-tilde sweep pieces (see solver.hip).
+// S-tilde sweep pieces.
 template <class T>
 hipError_t schur_coupling(const aao_problem* h, const double* r, T* z, hipStream_t st);
 template <class T>

@@ -27,17 +27,18 @@ class Multigrid {
     void* ptr;
     int64_t stride;
   };
-  hipError_t vcycle(int l, int stage, Vec x, Vec b, bool zero_init, int B, Vec* result);
+  hipError_t vcycle(int l, int stage, Vec x, Vec b, bool zero_init, bool pre, int B, Vec* result);
   hipError_t smooth(int l, int stage, Vec xin, Vec xout, Vec b, bool zero_init, int B);
-  hipError_t residual(int l, int stage, Vec x, Vec b, Vec r, int B);
-  hipError_t restrict_to(int l, Vec r, Vec bc, int B);
+  hipError_t resid_restrict(int l, int stage, Vec x, Vec b, Vec bc, Vec xc, bool zero_next, int B);
   hipError_t prolong(int l, Vec xin, Vec ec, Vec xout, int B);
-  hipError_t coarsest(int l, int stage, Vec b, Vec x, int B);
+  hipError_t prolong_smooth0(int stage, Vec xin, Vec ec, Vec b, Vec xout, int B);
+  hipError_t tail(int stage, Vec x, Vec b, bool zero_init, int B);
 
   aao_problem* h_;
   hipStream_t st_;
   double a_[SMAX];
   int levels_;
+  int l0_;          // first level solved by the one-workgroup LDS tail
 };
 
 }  // namespace aao

@@ -60,17 +60,33 @@ class Precond {
     sy_ = reinterpret_cast<TI*>(ws + h->plan.schurY);
     partial_ = reinterpret_cast<double*>(ws + h->plan.partial);
     slots_ = reinterpret_cast<double*>(ws + h->plan.dscal);
+    counters_ = reinterpret_cast<unsigned*>(ws + h->plan.counters);
+  }
+
+  GSArgs gs_args(int64_t L, int B) const {
+    GSArgs a{};
+    a.L = L;
+    a.slots = slots_;
+    a.sstride = S::STRIDE;
+    a.partial = partial_;
+    a.counters = counters_;
+    a.nblk = seg_blocks(L, B);
+    return a;
   }
 
   // out_b = Theta-tilde^{-1} rhs_b for B instances (rhs, out: s*N each).
   template <class TR>
   hipError_t inner(const TR* rhs, int64_t srhs, TI* out, int64_t sout, int B) {
     const int64_t N = h_->N, sN = (int64_t)h_->s * N, UV = h_->UV;
-    const int nblk = seg_blocks(sN, B);
-    TRY(seg_dots<TR, TR>(rhs, srhs, rhs, 0, srhs, 0, true, sN, B, partial_, nblk, st_));
-    TRY(seg_finish(partial_, nblk, 0, S::WW, B, slots_, S::STRIDE, 0, st_));
-    TRY(inner_init(slots_, B, st_));
-    TRY(seg_scale<TR, TI>(rhs, srhs, inV_, sN, slots_, S::STRIDE, S::INV, sN, B, st_));
+    // beta = ||rhs||, first basis vector rhs / beta
+    GSArgs a0 = gs_args(sN, B);
+    a0.sw = srhs;
+    a0.self = 1;
+    a0.os = S::WW;
+    a0.post = GS_POST_INIT;
+    TRY(gs_pass<TR, TI>(const_cast<TR*>(rhs), inV_, a0, B, st_));
+    TRY(basis_update<TR, TI, TI>(rhs, srhs, inV_, UV, sN, 0, inV_, sN, slots_, S::STRIDE, 0, S::INV, 0.0, sN, B,
+                                 st_));
     for (int j = 0; j < k_; ++j) {
       TI* Vj = inV_ + (int64_t)j * UV;
       TI* Zj = inZ_ + (int64_t)j * UV;
@@ -84,20 +100,31 @@ class Precond {
         TRY(mg_.solve(i, BVec<TI>{Zj + (int64_t)i * N, sN}, b, B, cycles_));
       }
       TRY(theta_apply<TI>(h_, tab_, Zj, sN, inW_, sN, B, st_));
-      // classical Gram-Schmidt, applied twice
+      // classical Gram-Schmidt, twice: h1 = V^T w; w -= V h1, h2 = V^T w,
+      // <w,w> and the Givens update in the second pass' finishing workgroup
       const int nd = j + 1;
-      TRY(seg_dots<TI, TI>(inW_, sN, inV_, UV, sN, nd, false, sN, B, partial_, nblk, st_));
-      TRY(seg_finish(partial_, nblk, nd, -1, B, slots_, S::STRIDE, S::H1, st_));
-      TRY(seg_axpy<TI, TI>(inW_, sN, inV_, UV, sN, nd, slots_, S::STRIDE, S::H1, -1.0, sN, B, st_));
-      TRY(seg_dots<TI, TI>(inW_, sN, inV_, UV, sN, nd, true, sN, B, partial_, nblk, st_));
-      TRY(seg_finish(partial_, nblk, nd, S::WW, B, slots_, S::STRIDE, S::H2, st_));
-      TRY(seg_axpy<TI, TI>(inW_, sN, inV_, UV, sN, nd, slots_, S::STRIDE, S::H2, -1.0, sN, B, st_));
-      TRY(inner_givens(slots_, B, j, st_));
+      GSArgs a1 = gs_args(sN, B);
+      a1.sw = sN;
+      a1.vstride = UV;
+      a1.sv = sN;
+      a1.nd = nd;
+      a1.dots = 1;
+      a1.od = S::H1;
+      TRY(gs_pass<TI, TI>(inW_, inV_, a1, B, st_));
+      GSArgs a2 = a1;
+      a2.axpy = 1;
+      a2.ca = S::H1;
+      a2.od = S::H2;
+      a2.self = 1;
+      a2.os = S::WW;
+      a2.post = GS_POST_GIVENS;
+      a2.j = j;
+      TRY(gs_pass<TI, TI>(inW_, inV_, a2, B, st_));
       if (j + 1 < k_)
-        TRY(seg_scale<TI, TI>(inW_, sN, inV_ + (int64_t)(j + 1) * UV, sN, slots_, S::STRIDE, S::INV, sN, B, st_));
+        TRY(basis_update<TI, TI, TI>(inW_, sN, inV_, UV, sN, nd, inV_ + (int64_t)(j + 1) * UV, sN, slots_,
+                                     S::STRIDE, S::H2, S::INV, 0.0, sN, B, st_));
     }
-    TRY(inner_backsolve(slots_, B, k_, st_));
-    TRY(seg_combine<TI, TI>(out, sout, inZ_, UV, sN, k_, slots_, S::STRIDE, S::Y, sN, B, st_));
+    TRY(combine<TI, TI>(out, sout, inZ_, UV, sN, k_, slots_, S::STRIDE, 0, true, false, sN, B, st_));
     return hipSuccess;
   }
 
@@ -140,6 +167,7 @@ class Precond {
   const double* Lc_;
   TI *inV_, *inZ_, *inW_, *inX_, *rana_, *srhs_, *sy_;
   double *partial_, *slots_;
+  unsigned* counters_;
 };
 
 template <class TI, class TM>
@@ -171,6 +199,7 @@ class Fgmres {
     w_ = reinterpret_cast<double*>(ws + h->plan.outW);
     partial_ = reinterpret_cast<double*>(ws + h->plan.partial);
     oslots_ = reinterpret_cast<double*>(ws + h->plan.dscal) + (int64_t)(h->nt + 1) * S::STRIDE;
+    counters_ = reinterpret_cast<unsigned*>(ws + h->plan.counters);
   }
 
   template <class TX>
@@ -178,41 +207,69 @@ class Fgmres {
     return transpose_ ? launch_apply_AT<TX>(h_, x, y, st_) : launch_apply_A<TX>(h_, x, y, st_);
   }
 
+  GSArgs gs_args(int nd) const {
+    GSArgs a{};
+    a.L = h_->U;
+    a.vstride = h_->U;
+    a.nd = nd;
+    a.slots = oslots_;
+    a.partial = partial_;
+    a.counters = counters_;
+    a.nblk = seg_blocks(h_->U, 1);
+    return a;
+  }
+
   // ||x||^2 of a U-vector, synchronous.
   hipError_t norm2(const double* x, double* out) {
-    const int nblk = seg_blocks(h_->U, 1);
-    TRY(seg_dots<double, double>(x, 0, x, 0, 0, 0, true, h_->U, 1, partial_, nblk, st_));
-    TRY(seg_finish(partial_, nblk, 0, 0, 1, oslots_, 0, 0, st_));
+    GSArgs a = gs_args(0);
+    a.self = 1;
+    a.os = 0;
+    TRY(gs_pass<double, double>(const_cast<double*>(x), x, a, 1, st_));
     TRY(hipMemcpyAsync(h_->hpin, oslots_, sizeof(double), hipMemcpyDeviceToHost, st_));
     TRY(hipStreamSynchronize(st_));
     *out = h_->hpin[0];
     return hipSuccess;
   }
 
-  // Gram-Schmidt of w against V_0..V_{nd-1} (twice); leaves h1+h2 in hcol
-  // and <w,w> after the first pass in ww (host).
+  // Classical Gram-Schmidt of w against V_0..V_{nd-1}, twice.  Leaves
+  // w - V h1 in w, and on the host h1 + h2 (hcol), |h2|^2 and <w, w>.
   hipError_t orthogonalize(int nd, std::vector<double>& hcol, double& h2sq, double& ww) {
     const int64_t U = h_->U;
-    const int nblk = seg_blocks(U, 1);
-    double* H1 = oslots_ + 8;
-    double* H2 = H1 + MMAX + 8;
-    double* WW = H2 + MMAX + 8;
-    for (int pass = 0; pass < 2; ++pass) {
-      double* H = pass == 0 ? H1 : H2;
+    const int H1 = 8, H2 = H1 + MMAX + 8, WW = H2 + MMAX + 8;
+    for (int c0 = 0; c0 < nd; c0 += DOTS_PER_PASS) {
+      GSArgs a = gs_args(std::min(DOTS_PER_PASS, nd - c0));
+      a.dots = 1;
+      a.od = H1 + c0;
+      TRY(gs_pass<double, double>(w_, V_ + (int64_t)c0 * U, a, 1, st_));
+    }
+    if (nd <= DOTS_PER_PASS) {
+      GSArgs a = gs_args(nd);
+      a.axpy = 1;
+      a.ca = H1;
+      a.dots = 1;
+      a.od = H2;
+      a.self = 1;
+      a.os = WW;
+      TRY(gs_pass<double, double>(w_, V_, a, 1, st_));
+    } else {
       for (int c0 = 0; c0 < nd; c0 += DOTS_PER_PASS) {
-        const int cnt = std::min(DOTS_PER_PASS, nd - c0);
-        const bool self = pass == 1 && c0 + cnt >= nd;
-        TRY(seg_dots<double, double>(w_, 0, V_ + (int64_t)c0 * U, U, 0, cnt, self, U, 1, partial_, nblk, st_));
-        TRY(seg_finish(partial_, nblk, cnt, self ? (int)(WW - oslots_) : -1, 1, oslots_, 0, (int)(H - oslots_) + c0,
-                       st_));
+        GSArgs a = gs_args(std::min(DOTS_PER_PASS, nd - c0));
+        a.axpy = 1;
+        a.ca = H1 + c0;
+        TRY(gs_pass<double, double>(w_, V_ + (int64_t)c0 * U, a, 1, st_));
       }
       for (int c0 = 0; c0 < nd; c0 += DOTS_PER_PASS) {
         const int cnt = std::min(DOTS_PER_PASS, nd - c0);
-        TRY(seg_axpy<double, double>(w_, 0, V_ + (int64_t)c0 * U, U, 0, cnt, H + c0, 0, 0, -1.0, U, 1, st_));
+        GSArgs a = gs_args(cnt);
+        a.dots = 1;
+        a.od = H2 + c0;
+        a.self = c0 + cnt >= nd;
+        a.os = WW;
+        TRY(gs_pass<double, double>(w_, V_ + (int64_t)c0 * U, a, 1, st_));
       }
     }
     double* hp = h_->hpin;
-    TRY(hipMemcpyAsync(hp, H1, sizeof(double) * (size_t)(WW - H1 + 1), hipMemcpyDeviceToHost, st_));
+    TRY(hipMemcpyAsync(hp, oslots_ + H1, sizeof(double) * (size_t)(WW - H1 + 1), hipMemcpyDeviceToHost, st_));
     TRY(hipStreamSynchronize(st_));
     hcol.assign(nd, 0.0);
     h2sq = 0.0;
@@ -223,6 +280,23 @@ class Fgmres {
     }
     ww = hp[WW - H1];
     return hipSuccess;
+  }
+
+  // V_{nd} = (w - V h2) / hn  (second Gram-Schmidt correction folded in)
+  hipError_t next_basis(int nd, double inv_hn) {
+    const int64_t U = h_->U;
+    const int H2 = 8 + MMAX + 8;
+    if (nd <= DOTS_PER_PASS)
+      return basis_update<double, double, double>(w_, 0, V_, U, 0, nd, V_ + (int64_t)nd * U, 0, oslots_, 0, H2, -1,
+                                                  inv_hn, U, 1, st_);
+    for (int c0 = 0; c0 < nd; c0 += DOTS_PER_PASS) {
+      GSArgs a = gs_args(std::min(DOTS_PER_PASS, nd - c0));
+      a.axpy = 1;
+      a.ca = H2 + c0;
+      TRY(gs_pass<double, double>(w_, V_ + (int64_t)c0 * U, a, 1, st_));
+    }
+    return basis_update<double, double, double>(w_, 0, V_, U, 0, 0, V_ + (int64_t)nd * U, 0, oslots_, 0, 0, -1,
+                                                inv_hn, U, 1, st_);
   }
 
   int run(const double* rhs, double* x, aao_stats* stats) {
@@ -302,8 +376,7 @@ class Fgmres {
         if (stt.history_len < 128) stt.history[stt.history_len++] = est;
         if (est <= h_->opts.tol || hn == 0.0 || its >= h_->opts.maxit) stop = true;
         if (!stop && j + 1 < m)
-          if ((e = launch_scale<double, double>(V_ + (int64_t)(j + 1) * U, w_, 1.0 / hn, U, st_)) != hipSuccess)
-            break;
+          if ((e = next_basis(j + 1, 1.0 / hn)) != hipSuccess) break;
       }
       if (e != hipSuccess || status == AAO_NONFINITE) break;
       // x += Z y
@@ -312,15 +385,16 @@ class Fgmres {
         for (int jj = i + 1; jj < mm; ++jj) acc -= R[(size_t)jj * (m + 1) + i] * y[jj];
         y[i] = acc / R[(size_t)i * (m + 1) + i];
       }
-      double* ydev = oslots_ + 4 * (MMAX + 8);
+      const int YOFF = 4 * (MMAX + 8);
+      double* ydev = oslots_ + YOFF;
       if (mm > 0) {
         for (int i = 0; i < mm; ++i) h_->hpin[i] = y[i];
         if ((e = hipMemcpyAsync(ydev, h_->hpin, sizeof(double) * mm, hipMemcpyHostToDevice, st_)) != hipSuccess)
           break;
         for (int c0 = 0; c0 < mm; c0 += DOTS_PER_PASS) {
           const int cnt = std::min(DOTS_PER_PASS, mm - c0);
-          if ((e = seg_axpy<double, TI>(x, 0, Z_ + (int64_t)c0 * U, U, 0, cnt, ydev + c0, 0, 0, 1.0, U, 1, st_)) !=
-              hipSuccess)
+          if ((e = combine<double, TI>(x, 0, Z_ + (int64_t)c0 * U, U, 0, cnt, oslots_, 0, YOFF + c0, false, true, U, 1,
+                                       st_)) != hipSuccess)
             break;
         }
         if (e != hipSuccess) break;
@@ -346,6 +420,7 @@ class Fgmres {
   hipStream_t st_;
   bool transpose_;
   double *V_, *w_, *partial_, *oslots_;
+  unsigned* counters_;
   TI* Z_;
 };
 
