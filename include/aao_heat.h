@@ -85,6 +85,7 @@ typedef struct aao_opts {
   int nu1, nu2;            /* Jacobi sweeps before / after coarse correction  */
   double omega;            /* Jacobi weight; 0 = 0.8 (2D) or 6/7 (3D)         */
   int precision;           /* aao_precision of P-tilde                         */
+  int use_graph;           /* 1: replay P-tilde as a captured HIP graph        */
 } aao_opts;
 
 /* Solve statistics (host struct filled by aao_solve*). */
@@ -101,7 +102,11 @@ typedef struct aao_stats {
 typedef struct aao_problem aao_problem;   /* opaque handle */
 
 /* Defaults: restart 30, maxit 100, tol 1e-8, inner_k 3, cycles 1,
- * nu1 = nu2 = 2, omega 0, precision FP64. */
+ * nu1 = nu2 = 2, omega 0, precision FP64, use_graph 1.  With use_graph the
+ * first application of P-tilde for a given (inner_k, cycles, transpose) is
+ * captured into a HIP graph on a private stream and later applications
+ * replay it on the handle's stream (inputs and outputs pass through fixed
+ * workspace buffers); results are bitwise identical to direct launches. */
 void aao_default_opts(aao_opts* o);
 
 /* Build a handle: Radau IIA tableau by collocation, Crout factor of A_RK

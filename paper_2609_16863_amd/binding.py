@@ -31,11 +31,13 @@ class HeatProblem:
     2D only).  Solver options: FGMRES ``restart``/``maxit``/``tol``, inner
     GMRES iterations ``inner_k``, V-cycles ``cycles`` with ``nu1``/``nu2``
     Jacobi sweeps, and the preconditioner ``precision``
-    ("fp64" | "fp32" | "bf16" | "fp16").
+    ("fp64" | "fp32" | "bf16" | "fp16"); ``use_graph`` replays the
+    preconditioner as a captured HIP graph.
     """
 
     def __init__(self, dim, n, s, nt, T=1.0, kappa=None, *, restart=30, maxit=100, tol=1e-8,
-                 inner_k=3, cycles=1, nu1=2, nu2=2, omega=0.0, precision="fp64", device="cuda"):
+                 inner_k=3, cycles=1, nu1=2, nu2=2, omega=0.0, precision="fp64", use_graph=True,
+                 device="cuda"):
         self._lib = _abi.load()
         self.dim, self.n, self.s, self.nt, self.T = dim, n, s, nt, float(T)
         self._kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
@@ -47,6 +49,7 @@ class HeatProblem:
         opts.inner_k, opts.cycles, opts.nu1, opts.nu2 = inner_k, cycles, nu1, nu2
         opts.omega = omega
         opts.precision = _abi.PRECISIONS[precision]
+        opts.use_graph = int(bool(use_graph))
         self.precision = precision
         h = ctypes.c_void_p()
         code = self._lib.aao_create_problem(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h))

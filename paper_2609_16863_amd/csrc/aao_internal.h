@@ -112,6 +112,7 @@ struct aao_problem {
   struct Plan {
     size_t tri_d, tri_f, faces_d, faces_f;
     size_t outV, outZ, outW, outY;           // outer FGMRES
+    size_t gIn, gOut;                        // fixed input/output of the captured P-tilde
     size_t inV, inZ, inW, inX;               // inner GMRES (nt instances)
     size_t rana;                              // Rana right-hand side (nt*N)
     size_t schurRhs, schurY;                  // S-tilde sweep (s*N)
@@ -123,6 +124,15 @@ struct aao_problem {
   int pm_bytes = 8;                           // multigrid storage bytes
 
   hipStream_t stream = nullptr;
+  size_t lds_budget = 65536;                  // LDS bytes per workgroup for the multigrid tail
+  struct GraphEntry {
+    bool transpose;
+    int k, cycles;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;             // captured P-tilde applications
+  hipStream_t capture_stream = nullptr;
   double* hpin = nullptr;                     // pinned host scalars
   std::string err;
 };
@@ -157,7 +167,11 @@ hipError_t launch_copy_cast(TD* dst, const TS* src, int64_t n, hipStream_t st);
 template <class T>
 hipError_t launch_fill(T* dst, T v, int64_t n, hipStream_t st);
 
+// kern_mg.hip
+size_t mg_configure_lds();
+
 // solver.hip
+void release_graphs(aao_problem* h);
 int apply_P(aao_problem* h, const double* r, double* z, int inner_k, int cycles, bool transpose);
 int solve(aao_problem* h, const double* rhs, double* x, aao_stats* st, bool transpose);
 

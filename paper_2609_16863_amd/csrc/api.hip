@@ -41,6 +41,8 @@ void plan_workspace(aao_problem* h) {
   P.outZ = take((size_t)m * U * pi);
   P.outW = take((size_t)U * sizeof(double));
   P.outY = take((size_t)U * pi);
+  P.gIn = take(h->opts.use_graph ? (size_t)U * sizeof(double) : 0);
+  P.gOut = take(h->opts.use_graph ? (size_t)U * pi : 0);
   P.inV = take((size_t)(k + 1) * UV * pi);
   P.inZ = take((size_t)k * UV * pi);
   P.inW = take((size_t)UV * pi);
@@ -104,6 +106,7 @@ void aao_default_opts(aao_opts* o) {
   o->nu2 = 2;
   o->omega = 0.0;
   o->precision = AAO_PREC_FP64;
+  o->use_graph = 1;
 }
 
 int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) {
@@ -207,6 +210,7 @@ int aao_set_workspace(aao_problem* h, void* dev_ptr, size_t bytes) {
   }
   h->ws = static_cast<char*>(dev_ptr);
   h->ws_bytes = bytes;
+  h->lds_budget = aao::mg_configure_lds();
   if (!h->tri_host.empty()) {
     e = hipMemcpyAsync(h->ws + h->plan.tri_d, h->tri_host.data(), h->tri_host.size() * sizeof(double),
                        hipMemcpyHostToDevice, h->stream);
@@ -245,6 +249,7 @@ int aao_set_stream(aao_problem* h, void* stream) {
 
 int aao_destroy(aao_problem* h) {
   if (!h) return AAO_INVALID_ARG;
+  aao::release_graphs(h);
   if (h->hpin) (void)hipHostFree(h->hpin);
   delete h;
   return AAO_OK;

@@ -84,9 +84,8 @@ __device__ void gmres_givens(double* q, int j, const double* h2, double ww) {
   }
 }
 
-// One pass of Gram-Schmidt on every instance, with the reduction finished by
-// the last workgroup of each instance (an atomic ticket per instance), so a
-// dot product costs one launch.  Optionally:
+// One pass of Gram-Schmidt on every instance; block partials of the dot
+// products go to `partial` and k_gs_finish completes them.  Optionally:
 //   axpy:  w <- w - sum_{d<nd} slots[ca+d] V_d   (stored back to w)
 //   dots:  slots[od+d] = <w, V_d>,  self: slots[os] = <w, w>
 //   post:  GS_POST_INIT   -> GMRES start  (beta, g, 1/beta) from slots[os]
@@ -123,9 +122,8 @@ __global__ __launch_bounds__(TPB) void k_gs(TW* __restrict__ w, const TV* __rest
     for (int d = 0; d < DOTS_PER_PASS; ++d) acc[d] += (double)vv[d] * wd;
     acc[DOTS_PER_PASS] += wd * wd;
   }
+  if (!a.dots && !a.self) return;
   __shared__ double red[TPB / 64][NSLOT];
-  __shared__ double fin[NSLOT];
-  __shared__ int am_last;
   const int lane = tid & 63, wave = tid >> 6;
   const int nslots_used = a.dots ? a.nd : 0;
 #pragma unroll
@@ -145,17 +143,19 @@ __global__ __launch_bounds__(TPB) void k_gs(TW* __restrict__ w, const TV* __rest
       part[(int64_t)blk * NSLOT + d] = sum;
     }
   }
-  if (!a.dots && !a.self) return;
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    const unsigned prev = atomicAdd(a.counters + inst, 1u);
-    am_last = (prev == (unsigned)(a.nblk - 1));
-  }
-  __syncthreads();
-  if (!am_last) return;
-  __threadfence();
-  // fixed-order final sum: thread t adds blocks t, t+TPB, ...; then a tree
+}
+
+// Second pass of a Gram-Schmidt reduction: one workgroup per instance sums
+// the block partials in a fixed order (thread t takes blocks t, t+TPB, ...,
+// then a tree), stores the results and runs the GMRES scalar update.
+__global__ __launch_bounds__(TPB) void k_gs_finish(GSArgs a) {
+  const int inst = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  double* q = a.slots + (int64_t)inst * a.sstride;
+  const double* part = a.partial + ((int64_t)inst * a.nblk) * NSLOT;
+  const int nslots_used = a.dots ? a.nd : 0;
+  __shared__ double red[TPB / 64][NSLOT];
+  __shared__ double fin[NSLOT];
   for (int d = 0; d < NSLOT; ++d) {
     if (!(d < nslots_used || (d == DOTS_PER_PASS && a.self))) continue;
     double sum = 0.0;
@@ -176,7 +176,6 @@ __global__ __launch_bounds__(TPB) void k_gs(TW* __restrict__ w, const TV* __rest
   }
   __syncthreads();
   if (tid == 0) {
-    atomicExch(a.counters + inst, 0u);
     if (a.post == GS_POST_INIT) gmres_start(q, fin[DOTS_PER_PASS]);
     else if (a.post == GS_POST_GIVENS) gmres_givens(q, a.j, fin, fin[DOTS_PER_PASS]);
   }
@@ -409,6 +408,7 @@ int seg_blocks(int64_t L, int B) {
 template <class TW, class TV>
 hipError_t gs_pass(TW* w, const TV* V, const GSArgs& a, int B, hipStream_t st) {
   hipLaunchKernelGGL((k_gs<TW, TV>), seg_grid(a.nblk, B), dim3(TPB), 0, st, w, V, a);
+  if (a.dots || a.self) hipLaunchKernelGGL(k_gs_finish, dim3((unsigned)B), dim3(TPB), 0, st, a);
   return hipGetLastError();
 }
 

@@ -308,168 +308,199 @@ __global__ void k_coarsest(const T* __restrict__ b, int64_t sb, T* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Coarse tail: every level from `l0` down to one node in one workgroup per
-// right-hand side, vectors in LDS, barriers instead of launches.
+// Coarse tail (2D): every level from `l0` down to one node in one workgroup
+// per right-hand side.  Vectors and the 1D Galerkin factors live in LDS and
+// are addressed by element offsets (so every access is an LDS instruction);
+// barriers replace kernel launches.
 // ---------------------------------------------------------------------------
 constexpr int TAIL_MAXL = 12;
 constexpr int TAIL_THREADS = 1024;
 
 template <class C>
 struct TailArgs {
-  int nl;            // levels in the tail
-  int first_fine;    // tail level 0 is the fine level (I + a K, matrix-free)
-  int zero_init;     // start from x = 0 (else x is loaded)
+  int nl;               // levels in the tail
+  int first_fine;       // tail level 0 is the fine level (I + a K, matrix-free)
+  int zero_init;        // start from x = 0 (else x is loaded)
   int nu1, nu2;
   C omega;
-  int off[TAIL_MAXL];   // LDS element offsets: X at off, Y at off + N, B at off + 2N
+  int off[TAIL_MAXL];   // LDS offsets: X at off, Y at off + N, B at off + 2N
+  int toff[TAIL_MAXL];  // LDS offset of the level's 6*n factor copy
   LevelOp<C> op[TAIL_MAXL];
 };
 
-template <int DIM, bool VK, class C>
-__device__ __forceinline__ void tail_apply(const TailArgs<C>& ta, int t, const C* x, int p, int i, int j, int k,
-                                           C& Ax, C& d) {
+// node p -> (i, j) on an n x n level; exact for p < 2^20, n <= 2^10:
+// (p + 1/2) / n is never within 1/(2n) of an integer.
+__device__ __forceinline__ void tail_ij(int p, int n, float inv_n, int& i, int& j) {
+  j = (int)(((float)p + 0.5f) * inv_n);
+  i = p - j * n;
+}
+
+// (A x)_p and A_pp for the 2D tensor Galerkin level with factors in LDS.
+template <class C>
+__device__ __forceinline__ void tail_tensor(const C* __restrict__ x, const C* __restrict__ tri, int n, C a, int p,
+                                            int i, int j, C& Ax, C& d) {
+  C mi[3], ti[3], mj[3], tj[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    mi[q] = tri[q * n + i];
+    ti[q] = tri[(3 + q) * n + i];
+    mj[q] = tri[q * n + j];
+    tj[q] = tri[(3 + q) * n + j];
+  }
+  C acc = C(0);
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj) {
+    const int jj = j + dj;
+    if (jj < 0 || jj >= n) continue;
+    C pv = C(0), qv = C(0);
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      const int ii = i + di;
+      if (ii < 0 || ii >= n) continue;
+      const C xv = x[p + dj * n + di];
+      pv += (mi[di + 1] + a * ti[di + 1]) * xv;
+      qv += mi[di + 1] * xv;
+    }
+    acc += mj[dj + 1] * pv + a * tj[dj + 1] * qv;
+  }
+  Ax = acc;
+  d = mi[1] * mj[1] + a * (ti[1] * mj[1] + mi[1] * tj[1]);
+}
+
+// Level t of the tail: tensor Galerkin, or the fine operator when the tail
+// starts at level 0.
+template <bool VK, class C>
+__device__ __forceinline__ void tail_op(const TailArgs<C>& ta, const C* sm, int t, const C* x, int p, int i, int j,
+                                        C& Ax, C& d) {
   if (t == 0 && ta.first_fine) {
-    if (VK) level_apply<DIM, KIND_FINE_VK, C, C>(x, ta.op[0], p, i, j, k, Ax, d);
-    else level_apply<DIM, KIND_FINE, C, C>(x, ta.op[0], p, i, j, k, Ax, d);
+    if (VK) level_apply<2, KIND_FINE_VK, C, C>(x, ta.op[0], p, i, j, 0, Ax, d);
+    else level_apply<2, KIND_FINE, C, C>(x, ta.op[0], p, i, j, 0, Ax, d);
   } else {
-    level_apply<DIM, KIND_TENSOR, C, C>(x, ta.op[t], p, i, j, k, Ax, d);
+    tail_tensor<C>(x, sm + ta.toff[t], ta.op[t].n, ta.op[t].a, p, i, j, Ax, d);
   }
 }
 
-template <int DIM, bool VK, class C>
-__device__ __forceinline__ C tail_diag(const TailArgs<C>& ta, int t, int p, int i, int j, int k) {
-  if (t == 0 && ta.first_fine)
-    return VK ? level_diag<DIM, KIND_FINE_VK, C>(ta.op[0], p, i, j, k) : level_diag<DIM, KIND_FINE, C>(ta.op[0], p, i, j, k);
-  return level_diag<DIM, KIND_TENSOR, C>(ta.op[t], p, i, j, k);
-}
-
-template <int DIM, bool VK, class TX, class TB, class C>
+template <bool VK, class TX, class TB, class C>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TX* __restrict__ xg, int64_t sx, const TB* __restrict__ bg,
                                                        int64_t sb, TailArgs<C> ta) {
   extern __shared__ unsigned char tail_smem[];
   C* sm = reinterpret_cast<C*>(tail_smem);
   const int tid = threadIdx.x, nth = blockDim.x;
   const int64_t inst = blockIdx.x;
-  C* cur[TAIL_MAXL];
-  C* oth[TAIL_MAXL];
+  const int last = ta.nl - 1;
+  // stage the factors of the tensor levels and the right-hand side
+  for (int t = (ta.first_fine ? 1 : 0); t <= last; ++t) {
+    const int n6 = 6 * ta.op[t].n;
+    for (int q = tid; q < n6; q += nth) sm[ta.toff[t] + q] = ta.op[t].tri[q];
+  }
   const int N0 = (int)ta.op[0].N;
-  C* B0 = sm + ta.off[0] + 2 * N0;
   for (int p = tid; p < N0; p += nth) {
-    B0[p] = ld<TB, C>(bg + inst * sb + p);
+    sm[ta.off[0] + 2 * N0 + p] = ld<TB, C>(bg + inst * sb + p);
     if (!ta.zero_init) sm[ta.off[0] + p] = ld<TX, C>(xg + inst * sx + p);
   }
   __syncthreads();
-  const int last = ta.nl - 1;
+  unsigned cur_y = 0;   // bit t set: the level-t iterate is in Y (else X)
   for (int t = 0; t < last; ++t) {
-    const LevelOp<C>& op = ta.op[t];
-    const int Nt = (int)op.N, n = op.n;
-    C* X = sm + ta.off[t];
-    C* Y = X + Nt;
-    C* Bt = X + 2 * Nt;
+    const int Nt = (int)ta.op[t].N, n = ta.op[t].n;
+    const float inv_n = 1.0f / (float)n;
+    const int X = ta.off[t], Y = X + Nt, Bt = X + 2 * Nt;
     int rem = ta.nu1;
     if (t > 0 || ta.zero_init) {
       for (int p = tid; p < Nt; p += nth) {
-        int i, j, k;
-        node_coords<DIM>(p, n, i, j, k);
-        X[p] = ta.omega * Bt[p] / tail_diag<DIM, VK, C>(ta, t, p, i, j, k);
+        int i, j;
+        tail_ij(p, n, inv_n, i, j);
+        C Ax, d;
+        tail_op<VK, C>(ta, sm, t, sm + X, p, i, j, Ax, d);   // only d is used
+        sm[X + p] = ta.omega * sm[Bt + p] / d;
       }
       --rem;
       __syncthreads();
     }
-    C* c = X;
-    C* o = Y;
+    int c = X, o = Y;
     for (; rem > 0; --rem) {
       for (int p = tid; p < Nt; p += nth) {
-        int i, j, k;
-        node_coords<DIM>(p, n, i, j, k);
+        int i, j;
+        tail_ij(p, n, inv_n, i, j);
         C Ax, d;
-        tail_apply<DIM, VK, C>(ta, t, c, p, i, j, k, Ax, d);
-        o[p] = c[p] + ta.omega * (Bt[p] - Ax) / d;
+        tail_op<VK, C>(ta, sm, t, sm + c, p, i, j, Ax, d);
+        sm[o + p] = sm[c + p] + ta.omega * (sm[Bt + p] - Ax) / d;
       }
       __syncthreads();
-      C* tmp = c; c = o; o = tmp;
+      const int tmp = c; c = o; o = tmp;
     }
-    // residual into the free buffer, then full weighting to the next level
-    for (int p = tid; p < Nt; p += nth) {
-      int i, j, k;
-      node_coords<DIM>(p, n, i, j, k);
+    for (int p = tid; p < Nt; p += nth) {            // residual into the free buffer
+      int i, j;
+      tail_ij(p, n, inv_n, i, j);
       C Ax, d;
-      tail_apply<DIM, VK, C>(ta, t, c, p, i, j, k, Ax, d);
-      o[p] = Bt[p] - Ax;
+      tail_op<VK, C>(ta, sm, t, sm + c, p, i, j, Ax, d);
+      sm[o + p] = sm[Bt + p] - Ax;
     }
     __syncthreads();
-    const LevelOp<C>& opc = ta.op[t + 1];
-    const int Nc = (int)opc.N, nc = opc.n;
-    C* Bc = sm + ta.off[t + 1] + 2 * Nc;
-    const C w[3] = {C(0.5), C(1), C(0.5)};
-    for (int pc = tid; pc < Nc; pc += nth) {
-      int I, J, K;
-      node_coords<DIM>(pc, nc, I, J, K);
+    const int Nc = (int)ta.op[t + 1].N, nc = ta.op[t + 1].n;
+    const float inv_nc = 1.0f / (float)nc;
+    const int Bc = ta.off[t + 1] + 2 * Nc;
+    for (int pc = tid; pc < Nc; pc += nth) {          // full weighting
+      int I, J;
+      tail_ij(pc, nc, inv_nc, I, J);
+      const int fi = 2 * I + 1, fj = 2 * J + 1;
       C acc = C(0);
-      const int fi = 2 * I + 1, fj = 2 * J + 1, fk = 2 * K + 1;
-      const int dk0 = DIM == 3 ? -1 : 0, dk1 = DIM == 3 ? 1 : 0;
-      for (int dk = dk0; dk <= dk1; ++dk) {
-        const int kk = fk + dk;
-        if (DIM == 3 && kk >= n) continue;
-        for (int dj = -1; dj <= 1; ++dj) {
-          const int jj = fj + dj;
-          if (jj >= n) continue;
-          for (int di = -1; di <= 1; ++di) {
-            const int ii = fi + di;
-            if (ii >= n) continue;
-            const int pf = DIM == 3 ? (kk * n + jj) * n + ii : jj * n + ii;
-            const C wt = DIM == 3 ? w[di + 1] * w[dj + 1] * w[dk + 1] : w[di + 1] * w[dj + 1];
-            acc += wt * o[pf];
-          }
+#pragma unroll
+      for (int dj = -1; dj <= 1; ++dj) {
+        const int jj = fj + dj;
+        if (jj >= n) continue;
+        const C wj = dj == 0 ? C(1) : C(0.5);
+#pragma unroll
+        for (int di = -1; di <= 1; ++di) {
+          const int ii = fi + di;
+          if (ii >= n) continue;
+          acc += (di == 0 ? wj : C(0.5) * wj) * sm[o + jj * n + ii];
         }
       }
-      Bc[pc] = acc * (DIM == 3 ? C(0.125) : C(0.25));
+      sm[Bc + pc] = C(0.25) * acc;
     }
-    cur[t] = c;
-    oth[t] = o;
+    if (c != X) cur_y |= 1u << t;
     __syncthreads();
   }
-  // coarsest level: one node (exact)
-  {
-    const LevelOp<C>& op = ta.op[last];
-    const int Nt = (int)op.N;
-    C* X = sm + ta.off[last];
+  {                                                   // one-node level: exact
+    const int X = ta.off[last], Nt = (int)ta.op[last].N;
     for (int p = tid; p < Nt; p += nth) {
-      int i, j, k;
-      node_coords<DIM>(p, op.n, i, j, k);
-      X[p] = X[p + 2 * Nt] / tail_diag<DIM, VK, C>(ta, last, p, i, j, k);
+      C Ax, d;
+      tail_op<VK, C>(ta, sm, last, sm + X, p, 0, 0, Ax, d);
+      sm[X + p] = sm[X + 2 * Nt + p] / d;
     }
-    cur[last] = X;
     __syncthreads();
   }
   for (int t = last - 1; t >= 0; --t) {
-    const LevelOp<C>& op = ta.op[t];
-    const int Nt = (int)op.N, n = op.n;
+    const int Nt = (int)ta.op[t].N, n = ta.op[t].n;
+    const float inv_n = 1.0f / (float)n;
     const int nc = ta.op[t + 1].n;
-    C* c = cur[t];
-    C* o = oth[t];
-    C* Bt = sm + ta.off[t] + 2 * Nt;
-    const C* e = cur[t + 1];
+    const int X = ta.off[t], Y = X + Nt, Bt = X + 2 * Nt;
+    int c = (cur_y >> t) & 1u ? Y : X;
+    int o = c == X ? Y : X;
+    const int Nc1 = (int)ta.op[t + 1].N;
+    const int e = ((cur_y >> (t + 1)) & 1u) ? ta.off[t + 1] + Nc1 : ta.off[t + 1];
     for (int p = tid; p < Nt; p += nth) {
-      int i, j, k;
-      node_coords<DIM>(p, n, i, j, k);
-      c[p] += prolong_at<DIM, C, C>(e, nc, i, j, k);
+      int i, j;
+      tail_ij(p, n, inv_n, i, j);
+      sm[c + p] += prolong_at<2, C, C>(sm + e, nc, i, j, 0);
     }
     __syncthreads();
     for (int it = 0; it < ta.nu2; ++it) {
       for (int p = tid; p < Nt; p += nth) {
-        int i, j, k;
-        node_coords<DIM>(p, n, i, j, k);
+        int i, j;
+        tail_ij(p, n, inv_n, i, j);
         C Ax, d;
-        tail_apply<DIM, VK, C>(ta, t, c, p, i, j, k, Ax, d);
-        o[p] = c[p] + ta.omega * (Bt[p] - Ax) / d;
+        tail_op<VK, C>(ta, sm, t, sm + c, p, i, j, Ax, d);
+        sm[o + p] = sm[c + p] + ta.omega * (sm[Bt + p] - Ax) / d;
       }
       __syncthreads();
-      C* tmp = c; c = o; o = tmp;
+      const int tmp = c; c = o; o = tmp;
     }
-    cur[t] = c;
+    if (c != X) cur_y |= 1u << t;
+    else cur_y &= ~(1u << t);
   }
-  for (int p = tid; p < N0; p += nth) st<TX, C>(xg + inst * sx + p, cur[0][p]);
+  const int res = (cur_y & 1u) ? ta.off[0] + N0 : ta.off[0];
+  for (int p = tid; p < N0; p += nth) st<TX, C>(xg + inst * sx + p, sm[res + p]);
 }
 
 }  // namespace
@@ -503,8 +534,9 @@ inline dim3 grid2(int64_t N, int B) { return dim3((unsigned)((N + TPB - 1) / TPB
 
 }  // namespace
 
-// First level handled by the one-workgroup tail: the largest set of coarse
-// levels whose three LDS vectors fit in 64 KiB.
+// First level handled by the one-workgroup tail (2D): the largest set of
+// coarse levels whose three LDS vectors and factor copies fit the device's
+// LDS per workgroup (at most 128 KiB).
 template <class TI, class TM>
 Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L)
     : h_(h), st_(st), levels_((int)h->lev_n.size()) {
@@ -514,16 +546,20 @@ Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L)
     // violation) for reasons not yet established; 3D runs every level with
     // grid kernels and a pointwise exact solve on the one-node level.
     l0_ = levels_;
+    tail_bytes_ = 0;
     return;
   }
+  const size_t budget = h->lds_budget;
+  auto cost = [&](int l) { return sizeof(C) * (3 * (size_t)h->lev_N[l] + 6 * (size_t)h->lev_n[l]); };
   l0_ = levels_ - 1;
-  size_t bytes = 3 * sizeof(C) * (size_t)h->lev_N[levels_ - 1];
+  size_t bytes = cost(levels_ - 1);
   while (l0_ > 0 && levels_ - l0_ < TAIL_MAXL) {
-    const size_t more = bytes + 3 * sizeof(C) * (size_t)h->lev_N[l0_ - 1];
-    if (more > 65536) break;
+    const size_t more = bytes + cost(l0_ - 1);
+    if (more > budget) break;
     bytes = more;
     --l0_;
   }
+  tail_bytes_ = bytes;
 }
 
 #define MG_TRY(...)                           \
@@ -602,6 +638,7 @@ hipError_t Multigrid<TI, TM>::prolong_smooth0(int stage, Vec xin, Vec ec, Vec b,
 
 template <class TI, class TM>
 hipError_t Multigrid<TI, TM>::tail(int stage, Vec x, Vec b, bool zero_init, int B) {
+  if (h_->dim != 2) return hipErrorUnknown;   // the tail is 2D only
   TailArgs<C> ta{};
   ta.nl = levels_ - l0_;
   ta.first_fine = l0_ == 0;
@@ -615,16 +652,20 @@ hipError_t Multigrid<TI, TM>::tail(int stage, Vec x, Vec b, bool zero_init, int 
     ta.off[t] = off;
     off += 3 * (int)ta.op[t].N;
   }
+  for (int t = 0; t < ta.nl; ++t) {
+    ta.toff[t] = off;
+    off += 6 * ta.op[t].n;
+  }
   const size_t shm = (size_t)off * sizeof(C);
   const int nth = ta.op[0].N >= TAIL_THREADS ? TAIL_THREADS : (ta.op[0].N >= 256 ? 256 : 64);
   const dim3 g((unsigned)B), blk((unsigned)nth);
-  if (h_->dim != 2) return hipErrorUnknown;   // the tail is 2D only
   if (l0_ == 0) {
-#define TL(D, V) hipLaunchKernelGGL((k_tail<D, V, TI, TI, C>), g, blk, shm, st_, (TI*)x.ptr, x.stride, (const TI*)b.ptr, b.stride, ta)
-    if (h_->vark) TL(2, true); else TL(2, false);
-#undef TL
+    if (h_->vark)
+      hipLaunchKernelGGL((k_tail<true, TI, TI, C>), g, blk, shm, st_, (TI*)x.ptr, x.stride, (const TI*)b.ptr, b.stride, ta);
+    else
+      hipLaunchKernelGGL((k_tail<false, TI, TI, C>), g, blk, shm, st_, (TI*)x.ptr, x.stride, (const TI*)b.ptr, b.stride, ta);
   } else {
-    hipLaunchKernelGGL((k_tail<2, false, TM, TM, C>), g, blk, shm, st_, (TM*)x.ptr, x.stride, (const TM*)b.ptr, b.stride, ta);
+    hipLaunchKernelGGL((k_tail<false, TM, TM, C>), g, blk, shm, st_, (TM*)x.ptr, x.stride, (const TM*)b.ptr, b.stride, ta);
   }
   return hipGetLastError();
 }
@@ -716,6 +757,28 @@ hipError_t Multigrid<TI, TM>::solve(int stage, BVec<TI> x, BVec<const TI> rhs, i
     if (res.ptr != xv.ptr) return hipErrorUnknown;   // the driver always ends in x
   }
   return hipSuccess;
+}
+
+// Largest dynamic LDS allocation the tail may use on the current device
+// (opt-in above 64 KiB where the device allows it), capped at 128 KiB.
+size_t mg_configure_lds() {
+  int dev = 0, optin = 0, base = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&base, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) base = 65536;
+  if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) optin = base;
+  size_t want = (size_t)(optin > base ? optin : base);
+  if (want > 131072) want = 131072;
+  if (want <= 65536) return want < 65536 ? want : 65536;
+  const void* kernels[] = {
+      (const void*)k_tail<false, double, double, double>, (const void*)k_tail<true, double, double, double>,
+      (const void*)k_tail<false, float, float, float>, (const void*)k_tail<true, float, float, float>,
+      (const void*)k_tail<false, __half, __half, float>, (const void*)k_tail<false, __hip_bfloat16, __hip_bfloat16, float>};
+  for (const void* k : kernels)
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) != hipSuccess) {
+      (void)hipGetLastError();
+      return 65536;
+    }
+  return want;
 }
 
 template class Multigrid<double, double>;

@@ -39,6 +39,7 @@ class Multigrid {
   double a_[SMAX];
   int levels_;
   int l0_;          // first level solved by the one-workgroup LDS tail
+  size_t tail_bytes_;
 };
 
 }  // namespace aao

@@ -186,6 +186,49 @@ hipError_t apply_P_any(aao_problem* h, const double* r, void* z, int k, int cycl
   }
 }
 
+// Apply P-tilde directly, or by replaying a HIP graph captured on the first
+// call for this (transpose, k, cycles).  The graph reads its input from and
+// writes its output to fixed workspace buffers; the copies in and out run on
+// the handle's stream around the replay.
+hipError_t precond_apply(aao_problem* h, const double* r, void* z, int k, int cycles, bool transpose) {
+  if (!h->opts.use_graph) return apply_P_any(h, r, z, k, cycles, transpose);
+  const int64_t U = h->U;
+  double* gin = reinterpret_cast<double*>(h->ws + h->plan.gIn);
+  void* gout = h->ws + h->plan.gOut;
+  aao_problem::GraphEntry* ent = nullptr;
+  for (auto& g : h->graphs)
+    if (g.transpose == transpose && g.k == k && g.cycles == cycles) ent = &g;
+  if (!ent) {
+    if (!h->capture_stream) TRY(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+    hipStream_t saved = h->stream;
+    h->stream = h->capture_stream;
+    hipError_t e = hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+      h->stream = saved;
+      return e;
+    }
+    e = apply_P_any(h, gin, gout, k, cycles, transpose);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(h->capture_stream, &graph);
+    h->stream = saved;
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return e != hipSuccess ? e : e2;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return e;
+    }
+    h->graphs.push_back(aao_problem::GraphEntry{transpose, k, cycles, graph, exec});
+    ent = &h->graphs.back();
+  }
+  TRY(hipMemcpyAsync(gin, r, (size_t)U * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  TRY(hipGraphLaunch(ent->exec, h->stream));
+  return hipMemcpyAsync(z, gout, (size_t)U * h->pi_bytes, hipMemcpyDeviceToDevice, h->stream);
+}
+
 // ---------------------------------------------------------------------------
 // Outer FGMRES
 // ---------------------------------------------------------------------------
@@ -342,8 +385,8 @@ class Fgmres {
       for (int j = 0; j < m && !stop; ++j) {
         its++;
         if (ev) hipEventRecord(pe0, st_);
-        if ((e = apply_P_any(h_, V_ + (int64_t)j * U, Z_ + (int64_t)j * U, h_->opts.inner_k, h_->opts.cycles,
-                             transpose_)) != hipSuccess)
+        if ((e = precond_apply(h_, V_ + (int64_t)j * U, Z_ + (int64_t)j * U, h_->opts.inner_k, h_->opts.cycles,
+                               transpose_)) != hipSuccess)
           break;
         if (ev) hipEventRecord(pe1, st_);
         if ((e = op<TI>(Z_ + (int64_t)j * U, w_)) != hipSuccess) break;
@@ -426,13 +469,23 @@ class Fgmres {
 
 }  // namespace
 
+void release_graphs(aao_problem* h) {
+  for (auto& g : h->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  h->graphs.clear();
+  if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+  h->capture_stream = nullptr;
+}
+
 int apply_P(aao_problem* h, const double* r, double* z, int inner_k, int cycles, bool transpose) {
   hipError_t e;
   if (h->opts.precision == AAO_PREC_FP64) {
-    e = apply_P_any(h, r, z, inner_k, cycles, transpose);
+    e = precond_apply(h, r, z, inner_k, cycles, transpose);
   } else {
     float* zp = reinterpret_cast<float*>(h->ws + h->plan.outY);
-    e = apply_P_any(h, r, zp, inner_k, cycles, transpose);
+    e = precond_apply(h, r, zp, inner_k, cycles, transpose);
     if (e == hipSuccess) e = launch_copy_cast<double, float>(z, zp, h->U, h->stream);
   }
   return status_from_hip(h, e, "apply_P");
