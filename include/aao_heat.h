@@ -86,6 +86,8 @@ typedef struct aao_opts {
   double omega;            /* Jacobi weight; 0 = 0.8 (2D) or 6/7 (3D)         */
   int precision;           /* aao_precision of P-tilde                         */
   int use_graph;           /* 1: replay P-tilde as a captured HIP graph        */
+  int mg_tail_max;         /* largest multigrid level (nodes) solved inside one
+                              workgroup's LDS (2D); 0 = 1024, capped by LDS    */
 } aao_opts;
 
 /* Solve statistics (host struct filled by aao_solve*). */
@@ -102,7 +104,7 @@ typedef struct aao_stats {
 typedef struct aao_problem aao_problem;   /* opaque handle */
 
 /* Defaults: restart 30, maxit 100, tol 1e-8, inner_k 3, cycles 1,
- * nu1 = nu2 = 2, omega 0, precision FP64, use_graph 1.  With use_graph the
+ * nu1 = nu2 = 2, omega 0, precision FP64, use_graph 1, mg_tail_max 0.  With use_graph the
  * first application of P-tilde for a given (inner_k, cycles, transpose) is
  * captured into a HIP graph on a private stream and later applications
  * replay it on the handle's stream (inputs and outputs pass through fixed

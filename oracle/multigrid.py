@@ -9,13 +9,14 @@ hierarchy and cycle below are this project's reading; they only affect
 iteration counts, never the solution of eq. (2.4).
 
 * Coarse nodes are every second fine node, 1-based fine indices 2, 4, ...,
-  2 floor(n/2), so n_c = floor(n/2); coarsening stops at n = 1.
+  2 floor(n/2), so n_c = floor(n/2); coarsening stops once a level has at
+  most COARSE_MAX = 256 nodes, and that level is solved exactly.
 * Prolongation P: (tensor-)linear interpolation, boundary values zero.
 * Restriction R = P^T / 2^d (full weighting); coarse operator R A P
   (Galerkin), so every level is symmetric positive definite.
 * Smoother: weighted Jacobi x <- x + omega D^{-1} (b - A x), nu1 sweeps before
   and nu2 after the coarse correction; zero initial guess; exact solve on the
-  1-point coarsest level.
+  coarsest level.
 * ``cycles`` V-cycles are applied as a stationary iteration from x = 0.
 
 Pinned by: convergence of repeated cycles to the direct solve, the
@@ -26,6 +27,9 @@ from 1D Galerkin factors, and a measured contraction factor
 """
 import numpy as np
 import scipy.sparse as sp
+
+
+COARSE_MAX = 256
 
 
 def coarse_size(n):
@@ -64,7 +68,7 @@ class Hierarchy:
         self.sizes = [n]
         self.ops = [(sp.identity(K.shape[0], format="csr") + a * K).tocsr()]
         self.P = []
-        while self.sizes[-1] > 1:
+        while self.sizes[-1] ** dim > COARSE_MAX and self.sizes[-1] > 1:
             nf = self.sizes[-1]
             P = interpolation(nf, dim)
             R = P.T / (2.0 ** dim)

@@ -37,7 +37,7 @@ class HeatProblem:
 
     def __init__(self, dim, n, s, nt, T=1.0, kappa=None, *, restart=30, maxit=100, tol=1e-8,
                  inner_k=3, cycles=1, nu1=2, nu2=2, omega=0.0, precision="fp64", use_graph=True,
-                 device="cuda"):
+                 mg_tail_max=0, device="cuda"):
         self._lib = _abi.load()
         self.dim, self.n, self.s, self.nt, self.T = dim, n, s, nt, float(T)
         self._kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
@@ -50,6 +50,7 @@ class HeatProblem:
         opts.omega = omega
         opts.precision = _abi.PRECISIONS[precision]
         opts.use_graph = int(bool(use_graph))
+        opts.mg_tail_max = int(mg_tail_max)
         self.precision = precision
         h = ctypes.c_void_p()
         code = self._lib.aao_create_problem(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h))

@@ -20,6 +20,7 @@ constexpr int KMAX = 12;         // inner GMRES iterations per application
 constexpr int MMAX = 120;        // outer FGMRES restart length
 constexpr int DOTS_PER_PASS = 16;
 constexpr int RED_THREADS = 256;
+constexpr int COARSE_MAX = 256;  // the coarsest multigrid level (<= this many nodes) is solved exactly
 
 // ---------------------------------------------------------------------------
 // Parameters passed to kernels by value
@@ -101,8 +102,10 @@ struct aao_problem {
   // multigrid levels (sizes per axis), shared by all stages
   std::vector<int> lev_n;
   std::vector<int64_t> lev_N;
-  std::vector<double> tri_host;              // concatenated 6*n_l per level >= 1
-  std::vector<size_t> tri_off;               // element offset per level (0 for level 0)
+  std::vector<double> tri_host;              // concatenated 6*n_l per level
+  std::vector<size_t> tri_off;               // element offset per level
+  std::vector<double> cinv_host;             // coarsest-level inverses: [transpose][stage] N_c^2 each
+  int64_t cinv_N = 0;
   std::vector<double> faces_host;            // 2*dim*N when vark
 
   // workspace plan (byte offsets)
@@ -110,7 +113,7 @@ struct aao_problem {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   struct Plan {
-    size_t tri_d, tri_f, faces_d, faces_f;
+    size_t tri_d, tri_f, faces_d, faces_f, cinv_d, cinv_f;
     size_t outV, outZ, outW, outY;           // outer FGMRES
     size_t gIn, gOut;                        // fixed input/output of the captured P-tilde
     size_t inV, inZ, inW, inX;               // inner GMRES (nt instances)
@@ -145,7 +148,9 @@ namespace aao {
 // setup.cpp (host only)
 bool radau_iia(int s, double* A, double* b, double* c);
 void crout_lower(int s, const double* A, double* L);
-void galerkin_1d(int n, double h, std::vector<int>& sizes, std::vector<std::vector<double>>& tri);
+void galerkin_1d(int n, int dim, double h, std::vector<int>& sizes, std::vector<std::vector<double>>& tri);
+bool coarse_inverse(int dim, int n, const std::vector<double>& tri, double a, bool fine, double ih2,
+                    const double* faces, std::vector<double>& invT);
 void face_coefficients(int dim, int n, const double* kappa, std::vector<double>& faces);
 
 int status_from_hip(aao_problem* h, hipError_t e, const char* what);

@@ -31,6 +31,8 @@ void plan_workspace(aao_problem* h) {
   const int L = (int)h->lev_n.size();
   P.tri_d = take(h->tri_host.size() * sizeof(double));
   P.tri_f = take(h->tri_host.size() * sizeof(float));
+  P.cinv_d = take(h->cinv_host.size() * sizeof(double));
+  P.cinv_f = take(h->cinv_host.size() * sizeof(float));
   // faces (2*dim*N) followed by nodal kappa (N)
   P.faces_d = take(h->vark ? (size_t)(2 * h->dim + 1) * N * sizeof(double) : 0);
   P.faces_f = take(h->vark ? (size_t)(2 * h->dim + 1) * N * sizeof(float) : 0);
@@ -81,6 +83,7 @@ bool valid_opts(const aao_opts* o, std::string& why) {
   if (o->nu1 < 1 || o->nu2 < 1 || o->nu1 > 16 || o->nu2 > 16) { why = "nu1, nu2 must be in [1, 16]"; return false; }
   if (o->precision < AAO_PREC_FP64 || o->precision > AAO_PREC_FP16) { why = "unknown precision"; return false; }
   if (o->omega < 0.0 || o->omega >= 2.0) { why = "omega must be in [0, 2)"; return false; }
+  if (o->mg_tail_max < 0) { why = "mg_tail_max must be >= 0"; return false; }
   return true;
 }
 
@@ -107,6 +110,7 @@ void aao_default_opts(aao_opts* o) {
   o->omega = 0.0;
   o->precision = AAO_PREC_FP64;
   o->use_graph = 1;
+  o->mg_tail_max = 0;
 }
 
 int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) {
@@ -176,13 +180,30 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
   }
 
   std::vector<std::vector<double>> tri;
-  aao::galerkin_1d(d->n, h->h, h->lev_n, tri);
+  aao::galerkin_1d(d->n, d->dim, h->h, h->lev_n, tri);
   h->lev_N.resize(h->lev_n.size());
   h->tri_off.assign(h->lev_n.size(), 0);
   for (size_t l = 0; l < h->lev_n.size(); ++l) {
     h->lev_N[l] = (int64_t)std::llround(std::pow((double)h->lev_n[l], d->dim));
     h->tri_off[l] = h->tri_host.size();
     h->tri_host.insert(h->tri_host.end(), tri[l].begin(), tri[l].end());
+  }
+  // exact inverses of the coarsest level, for the shifts tau L_ii (P-tilde)
+  // and tau LT_ii (its transpose)
+  {
+    const int lc = (int)h->lev_n.size() - 1;
+    h->cinv_N = h->lev_N[lc];
+    for (int tr = 0; tr < 2; ++tr)
+      for (int i = 0; i < d->s; ++i) {
+        const double a = h->tau * (tr ? h->LT : h->tab.L)[i * d->s + i];
+        std::vector<double> inv;
+        if (!aao::coarse_inverse(d->dim, h->lev_n[lc], tri[lc], a, lc == 0, h->ih2,
+                                 h->vark ? h->faces_host.data() : nullptr, inv)) {
+          delete h;
+          return fail(nullptr, AAO_INVALID_ARG, "singular coarsest multigrid level");
+        }
+        h->cinv_host.insert(h->cinv_host.end(), inv.begin(), inv.end());
+      }
   }
   plan_workspace(h);
   *out = h;
@@ -218,6 +239,14 @@ int aao_set_workspace(aao_problem* h, void* dev_ptr, size_t bytes) {
       e = aao::launch_copy_cast<float, double>(reinterpret_cast<float*>(h->ws + h->plan.tri_f),
                                                reinterpret_cast<const double*>(h->ws + h->plan.tri_d),
                                                (int64_t)h->tri_host.size(), h->stream);
+  }
+  if (e == hipSuccess && !h->cinv_host.empty()) {
+    e = hipMemcpyAsync(h->ws + h->plan.cinv_d, h->cinv_host.data(), h->cinv_host.size() * sizeof(double),
+                       hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = aao::launch_copy_cast<float, double>(reinterpret_cast<float*>(h->ws + h->plan.cinv_f),
+                                               reinterpret_cast<const double*>(h->ws + h->plan.cinv_d),
+                                               (int64_t)h->cinv_host.size(), h->stream);
   }
   if (e == hipSuccess && h->vark) {
     const size_t nf = h->faces_host.size();

@@ -298,13 +298,204 @@ __global__ __launch_bounds__(TPB) void k_prolong_smooth(const TX* __restrict__ x
   st<TX, C>(xout + inst * sxout + p, yp + omega * (ld<TX, C>(b + inst * sb + p) - Ay) / d);
 }
 
-// Exact solve on a one-node level: x = b / A_00 (used when no LDS tail runs).
-template <int DIM, class T, class C>
-__global__ void k_coarsest(const T* __restrict__ b, int64_t sb, T* __restrict__ x, int64_t sx, LevelOp<C> op,
-                           int B) {
-  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
-  if (inst >= B) return;
-  st<T, C>(x + (int64_t)inst * sx, ld<T, C>(b + (int64_t)inst * sb) / level_diag<DIM, KIND_TENSOR, C>(op, 0, 0, 0, 0));
+// ---------------------------------------------------------------------------
+// 2D LDS-tiled level kernels.  One "down" kernel per level does the first
+// sweep from zero (pointwise), the remaining pre-smoothing sweeps, the
+// residual and the full-weighting restriction; one "up" kernel does the
+// prolongation and all post-smoothing sweeps.  Each workgroup loads its tile
+// with a halo wide enough that every sweep can be recomputed locally (the
+// halo work is redundant, the results are those of the separate sweeps).
+// ---------------------------------------------------------------------------
+constexpr int TCX = 16, TCY = 8;   // coarse nodes per down tile; fine tile is 2x
+
+template <int KIND, class C>
+__device__ __forceinline__ C tile_apply(const C* __restrict__ x, int t, int W, int gi, int gj,
+                                        const LevelOp<C>& op, C& d) {
+  const int n = op.n;
+  if (KIND != KIND_TENSOR) {
+    const int p = gj * n + gi;
+    const C xc = x[t], xm = x[t - 1], xp = x[t + 1], ym = x[t - W], yp = x[t + W];
+    C kx;
+    if (KIND == KIND_FINE) {
+      kx = C(4) * xc - xm - xp - ym - yp;
+    } else {
+      const Faces<C>& f = op.faces;
+      kx = f.m[0][p] * (xc - xm) + f.p[0][p] * (xc - xp) + f.m[1][p] * (xc - ym) + f.p[1][p] * (xc - yp);
+    }
+    d = level_diag<2, KIND, C>(op, p, gi, gj, 0);
+    return xc + op.a * op.ih2 * kx;
+  }
+  const Tri3<C> ri = tri_row(op.tri, n, gi), rj = tri_row(op.tri, n, gj);
+  C acc = C(0);
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj) {
+    C pv = C(0), qv = C(0);
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      const C xv = x[t + dj * W + di];
+      pv += (ri.m[di + 1] + op.a * ri.t[di + 1]) * xv;
+      qv += ri.m[di + 1] * xv;
+    }
+    acc += rj.m[dj + 1] * pv + op.a * rj.t[dj + 1] * qv;
+  }
+  d = ri.m[1] * rj.m[1] + op.a * (ri.t[1] * rj.m[1] + ri.m[1] * rj.t[1]);
+  return acc;
+}
+
+template <int KIND, class C>
+__device__ __forceinline__ C tile_diag(int gi, int gj, const LevelOp<C>& op) {
+  return level_diag<2, KIND, C>(op, gj * op.n + gi, gi, gj, 0);
+}
+
+// Down: x_NU (from zero, or from x0 when given) -> xout, and
+// b_c = R (b - A x_NU) -> bc, on the fine nodes of coarse tile (I0.., J0..).
+template <int KIND, int NU, class TF, class TC, class C>
+__global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_t sb, const TF* __restrict__ x0,
+                                                int64_t sx0, TF* __restrict__ xout, int64_t sxo, TC* __restrict__ bc,
+                                                int64_t sbc, LevelOp<C> op, int nc, C omega) {
+  constexpr int R = NU + 1;
+  constexpr int W = 2 * TCX + 1 + 2 * R, H = 2 * TCY + 1 + 2 * R;
+  __shared__ C sbv[W * H], s0[W * H], s1[W * H];
+  const int tid = threadIdx.x;
+  const int nf = op.n;
+  const int I0 = blockIdx.x * TCX, J0 = blockIdx.y * TCY;
+  const int64_t inst = blockIdx.z;
+  const int ox = 2 * I0 - R, oy = 2 * J0 - R;
+  const TF* bi = b + inst * sb;
+  for (int t = tid; t < W * H; t += 256) {
+    const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
+    const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+    sbv[t] = in ? ld<TF, C>(bi + gj * nf + gi) : C(0);
+    if (x0) s0[t] = in ? ld<TF, C>(x0 + inst * sx0 + gj * nf + gi) : C(0);
+  }
+  __syncthreads();
+  C* cur = s0;
+  C* nxt = s1;
+  int k = 0;
+  if (!x0) {
+    for (int t = tid; t < W * H; t += 256) {
+      const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
+      const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+      s0[t] = in ? omega * sbv[t] / tile_diag<KIND, C>(gi, gj, op) : C(0);
+    }
+    __syncthreads();
+    k = 1;
+  }
+  for (; k < NU; ++k) {
+    for (int t = tid; t < W * H; t += 256) {
+      const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
+      C v = C(0);
+      if (tx > 0 && tx < W - 1 && ty > 0 && ty < H - 1 && gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
+        C d;
+        const C Ax = tile_apply<KIND, C>(cur, t, W, gi, gj, op, d);
+        v = cur[t] + omega * (sbv[t] - Ax) / d;
+      }
+      nxt[t] = v;
+    }
+    __syncthreads();
+    C* tmp = cur; cur = nxt; nxt = tmp;
+  }
+  // residual on the interior of the tile (zero outside the domain)
+  for (int t = tid; t < W * H; t += 256) {
+    const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
+    C v = C(0);
+    if (tx > 0 && tx < W - 1 && ty > 0 && ty < H - 1 && gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
+      C d;
+      v = sbv[t] - tile_apply<KIND, C>(cur, t, W, gi, gj, op, d);
+    }
+    nxt[t] = v;
+  }
+  __syncthreads();
+  for (int c = tid; c < TCX * TCY; c += 256) {
+    const int cx = c % TCX, cy = c / TCX, I = I0 + cx, J = J0 + cy;
+    if (I >= nc || J >= nc) continue;
+    const int tc = (2 * cy + 1 + R) * W + (2 * cx + 1 + R);
+    const C acc = C(0.25) * (nxt[tc] + C(0.5) * (nxt[tc - 1] + nxt[tc + 1] + nxt[tc - W] + nxt[tc + W]) +
+                             C(0.25) * (nxt[tc - W - 1] + nxt[tc - W + 1] + nxt[tc + W - 1] + nxt[tc + W + 1]));
+    st<TC, C>(bc + inst * sbc + J * nc + I, acc);
+  }
+  // owned fine nodes: [2 I0, 2 (I0 + TCX)) per axis, the last tile to the end
+  const int hx = (I0 + TCX >= nc) ? nf : 2 * (I0 + TCX), hy = (J0 + TCY >= nc) ? nf : 2 * (J0 + TCY);
+  for (int t = tid; t < W * H; t += 256) {
+    const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
+    if (gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy) st<TF, C>(xout + inst * sxo + gj * nf + gi, cur[t]);
+  }
+}
+
+// Up: y = x_in + P e on the tile (with halo NU), NU smoothing sweeps, the
+// owned fine nodes written to xout.
+template <int KIND, int NU, class TF, class TE, class C>
+__global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_t sxi, const TE* __restrict__ e,
+                                              int64_t se, const TF* __restrict__ b, int64_t sb, TF* __restrict__ xout,
+                                              int64_t sxo, LevelOp<C> op, int nc, C omega) {
+  constexpr int R = NU;
+  constexpr int W = 2 * TCX + 1 + 2 * R, H = 2 * TCY + 1 + 2 * R;
+  __shared__ C sbv[W * H], s0[W * H], s1[W * H];
+  const int tid = threadIdx.x;
+  const int nf = op.n;
+  const int I0 = blockIdx.x * TCX, J0 = blockIdx.y * TCY;
+  const int64_t inst = blockIdx.z;
+  const int ox = 2 * I0 - R, oy = 2 * J0 - R;
+  const TE* ei = e + inst * se;
+  for (int t = tid; t < W * H; t += 256) {
+    const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
+    const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+    const int64_t g = (int64_t)gj * nf + gi;
+    sbv[t] = in ? ld<TF, C>(b + inst * sb + g) : C(0);
+    s0[t] = in ? ld<TF, C>(xin + inst * sxi + g) + prolong_at<2, TE, C>(ei, nc, gi, gj, 0) : C(0);
+  }
+  __syncthreads();
+  C* cur = s0;
+  C* nxt = s1;
+  for (int k = 0; k < NU; ++k) {
+    for (int t = tid; t < W * H; t += 256) {
+      const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
+      C v = C(0);
+      if (tx > 0 && tx < W - 1 && ty > 0 && ty < H - 1 && gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
+        C d;
+        const C Ax = tile_apply<KIND, C>(cur, t, W, gi, gj, op, d);
+        v = cur[t] + omega * (sbv[t] - Ax) / d;
+      }
+      nxt[t] = v;
+    }
+    __syncthreads();
+    C* tmp = cur; cur = nxt; nxt = tmp;
+  }
+  const int hx = (I0 + TCX >= nc) ? nf : 2 * (I0 + TCX), hy = (J0 + TCY >= nc) ? nf : 2 * (J0 + TCY);
+  for (int t = tid; t < W * H; t += 256) {
+    const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
+    if (gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy) st<TF, C>(xout + inst * sxo + gj * nf + gi, cur[t]);
+  }
+}
+
+// Exact solve on the coarsest level (at most COARSE_MAX nodes) with its
+// precomputed dense inverse, stored transposed: x_r = sum_c invT[c Nc + r] b_c.
+template <class T, class C>
+__global__ __launch_bounds__(1024) void k_coarse_solve(const T* __restrict__ b, int64_t sb, T* __restrict__ x,
+                                                       int64_t sx, const C* __restrict__ invT, int Nc) {
+  const int64_t inst = blockIdx.x;
+  const T* bi = b + inst * sb;
+  __shared__ C bs[COARSE_MAX];
+  __shared__ C part_sum[4][COARSE_MAX];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int c = tid; c < Nc; c += nth) bs[c] = ld<T, C>(bi + c);
+  __syncthreads();
+  const int parts = nth / Nc >= 4 ? 4 : (nth / Nc >= 2 ? 2 : 1);
+  const int cols = (Nc + parts - 1) / parts;
+  for (int t = tid; t < Nc * parts; t += nth) {
+    const int r = t % Nc, part = t / Nc;
+    const int c0 = part * cols, c1 = c0 + cols < Nc ? c0 + cols : Nc;
+    C acc = C(0);
+#pragma unroll 8
+    for (int c = c0; c < c1; ++c) acc += invT[(int64_t)c * Nc + r] * bs[c];
+    part_sum[part][r] = acc;
+  }
+  __syncthreads();
+  for (int r = tid; r < Nc; r += nth) {
+    C v = C(0);
+    for (int q = 0; q < parts; ++q) v += part_sum[q][r];
+    st<T, C>(x + inst * sx + r, v);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -325,6 +516,8 @@ struct TailArgs {
   C omega;
   int off[TAIL_MAXL];   // LDS offsets: X at off, Y at off + N, B at off + 2N
   int toff[TAIL_MAXL];  // LDS offset of the level's 6*n factor copy
+  const C* cinv;        // dense inverse of the last level, transposed
+  int scratch;          // LDS offset of 2 * N_last values for the coarse solve
   LevelOp<C> op[TAIL_MAXL];
 };
 
@@ -461,12 +654,47 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TX* __restrict__ xg, int6
     if (c != X) cur_y |= 1u << t;
     __syncthreads();
   }
-  {                                                   // one-node level: exact
+  {                                                   // coarsest level: exact
+    // x = A^{-1} b with the dense inverse: `parts` threads per row, each
+    // summing a contiguous slice of columns; partial sums meet in the free
+    // Y buffer of this level (Nt * parts <= 3 Nt values fit in X, Y, B? no:
+    // they go to Y and beyond only when parts == 1), combined below.
     const int X = ta.off[last], Nt = (int)ta.op[last].N;
-    for (int p = tid; p < Nt; p += nth) {
-      C Ax, d;
-      tail_op<VK, C>(ta, sm, last, sm + X, p, 0, 0, Ax, d);
-      sm[X + p] = sm[X + 2 * Nt + p] / d;
+    const int Bl = X + 2 * Nt;
+    const int parts = nth / Nt >= 4 ? 4 : (nth / Nt >= 2 ? 2 : 1);
+    if (parts == 1) {
+      C accs[4];
+      int cnt = 0;
+      for (int r = tid; r < Nt; r += nth) {        // at most 4 rows per thread (Nt <= 256 <= 4 nth)
+        C acc = C(0);
+#pragma unroll 8
+        for (int c = 0; c < Nt; ++c) acc += ta.cinv[(int64_t)c * Nt + r] * sm[Bl + c];
+        accs[cnt++ & 3] = acc;
+      }
+      __syncthreads();
+      cnt = 0;
+      for (int r = tid; r < Nt; r += nth) sm[X + r] = accs[cnt++ & 3];
+    } else {
+      const int cols = (Nt + parts - 1) / parts;
+      C acc = C(0);
+      int r = 0, part = 0;
+      if (tid < Nt * parts) {
+        r = tid % Nt;
+        part = tid / Nt;
+        const int c0 = part * cols, c1 = c0 + cols < Nt ? c0 + cols : Nt;
+#pragma unroll 8
+        for (int c = c0; c < c1; ++c) acc += ta.cinv[(int64_t)c * Nt + r] * sm[Bl + c];
+      }
+      __syncthreads();
+      // partial sums: part 0 -> X, part 1 -> Y (free), parts 2, 3 -> the
+      // scratch reserved past the factor copies
+      if (tid < Nt * parts) sm[(part == 0 ? X : (part == 1 ? X + Nt : ta.scratch + (part - 2) * Nt)) + r] = acc;
+      __syncthreads();
+      for (int q = tid; q < Nt; q += nth) {
+        C v = sm[X + q] + sm[X + Nt + q];
+        if (parts > 2) v += sm[ta.scratch + q] + sm[ta.scratch + Nt + q];
+        sm[X + q] = v;
+      }
     }
     __syncthreads();
   }
@@ -541,6 +769,7 @@ template <class TI, class TM>
 Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L)
     : h_(h), st_(st), levels_((int)h->lev_n.size()) {
   for (int i = 0; i < h->s; ++i) a_[i] = h->tau * L[i * h->s + i];
+  cinv_set_ = (L == h->LT) ? 1 : 0;
   if (h->dim == 3) {
     // The 3D instantiation of the LDS tail faulted on gfx950 (aperture
     // violation) for reasons not yet established; 3D runs every level with
@@ -552,10 +781,14 @@ Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L)
   const size_t budget = h->lds_budget;
   auto cost = [&](int l) { return sizeof(C) * (3 * (size_t)h->lev_N[l] + 6 * (size_t)h->lev_n[l]); };
   l0_ = levels_ - 1;
-  size_t bytes = cost(levels_ - 1);
+  size_t bytes = cost(levels_ - 1) + sizeof(C) * 2 * (size_t)h->lev_N[levels_ - 1];
+  // measured on MI355X (512^2, s=3): one workgroup is faster than grid
+  // kernels up to a 32 x 32 level, slower above it
+  const int64_t tail_max = h->opts.mg_tail_max > 0 ? h->opts.mg_tail_max : 1024;
   while (l0_ > 0 && levels_ - l0_ < TAIL_MAXL) {
     const size_t more = bytes + cost(l0_ - 1);
     if (more > budget) break;
+    if (tail_max > 0 && h->lev_N[l0_ - 1] > tail_max) break;
     bytes = more;
     --l0_;
   }
@@ -567,6 +800,13 @@ Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L)
     hipError_t e_ = (__VA_ARGS__);            \
     if (e_ != hipSuccess) return e_;          \
   } while (0)
+
+template <class TI, class TM>
+const typename Multigrid<TI, TM>::C* Multigrid<TI, TM>::coarse_inv(int stage) const {
+  const bool dbl = sizeof(C) == 8;
+  const C* base = reinterpret_cast<const C*>(h_->ws + (dbl ? h_->plan.cinv_d : h_->plan.cinv_f));
+  return base + ((int64_t)cinv_set_ * h_->s + stage) * h_->cinv_N * h_->cinv_N;
+}
 
 template <class TI, class TM>
 hipError_t Multigrid<TI, TM>::smooth(int l, int stage, Vec xin, Vec xout, Vec b, bool zero_init, int B) {
@@ -656,6 +896,9 @@ hipError_t Multigrid<TI, TM>::tail(int stage, Vec x, Vec b, bool zero_init, int 
     ta.toff[t] = off;
     off += 6 * ta.op[t].n;
   }
+  ta.scratch = off;
+  off += 2 * (int)ta.op[ta.nl - 1].N;
+  ta.cinv = coarse_inv(stage);
   const size_t shm = (size_t)off * sizeof(C);
   const int nth = ta.op[0].N >= TAIL_THREADS ? TAIL_THREADS : (ta.op[0].N >= 256 ? 256 : 64);
   const dim3 g((unsigned)B), blk((unsigned)nth);
@@ -670,6 +913,44 @@ hipError_t Multigrid<TI, TM>::tail(int stage, Vec x, Vec b, bool zero_init, int 
   return hipGetLastError();
 }
 
+template <class TI, class TM>
+hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, int64_t sx0, Vec xout, Vec bc, int B) {
+  const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
+  const int nc = h_->lev_n[l + 1];
+  const C omega = (C)h_->omega;
+  const dim3 g((unsigned)((nc + TCX - 1) / TCX), (unsigned)((nc + TCY - 1) / TCY), (unsigned)B);
+  const int nu = h_->opts.nu1;
+#define DN(K, NU, TF) hipLaunchKernelGGL((k_down2d<K, NU, TF, TM, C>), g, dim3(256), 0, st_, (const TF*)b.ptr, b.stride, (const TF*)x0, sx0, (TF*)xout.ptr, xout.stride, (TM*)bc.ptr, bc.stride, op, nc, omega)
+#define DN_NU(K, TF) do { if (nu == 1) DN(K, 1, TF); else if (nu == 2) DN(K, 2, TF); else DN(K, 3, TF); } while (0)
+  if (l == 0) {
+    if (h_->vark) DN_NU(KIND_FINE_VK, TI); else DN_NU(KIND_FINE, TI);
+  } else {
+    DN_NU(KIND_TENSOR, TM);
+  }
+#undef DN_NU
+#undef DN
+  return hipGetLastError();
+}
+
+template <class TI, class TM>
+hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec xout, int B) {
+  const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
+  const int nc = h_->lev_n[l + 1];
+  const C omega = (C)h_->omega;
+  const dim3 g((unsigned)((nc + TCX - 1) / TCX), (unsigned)((nc + TCY - 1) / TCY), (unsigned)B);
+  const int nu = h_->opts.nu2;
+#define UP(K, NU, TF) hipLaunchKernelGGL((k_up2d<K, NU, TF, TM, C>), g, dim3(256), 0, st_, (const TF*)xin.ptr, xin.stride, (const TM*)ec.ptr, ec.stride, (const TF*)b.ptr, b.stride, (TF*)xout.ptr, xout.stride, op, nc, omega)
+#define UP_NU(K, TF) do { if (nu == 1) UP(K, 1, TF); else if (nu == 2) UP(K, 2, TF); else UP(K, 3, TF); } while (0)
+  if (l == 0) {
+    if (h_->vark) UP_NU(KIND_FINE_VK, TI); else UP_NU(KIND_FINE, TI);
+  } else {
+    UP_NU(KIND_TENSOR, TM);
+  }
+#undef UP_NU
+#undef UP
+  return hipGetLastError();
+}
+
 // One V-cycle on level l.  `pre` = the first (pointwise) sweep from zero was
 // already written into x by the restriction of the level above.
 template <class TI, class TM>
@@ -680,13 +961,15 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
     *result = x;
     return hipSuccess;
   }
-  if (l == levels_ - 1) {      // no tail (3D): exact solve on the one-node level
-    const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
-    const dim3 g((unsigned)((B + 63) / 64)), blk(64);
+  if (l == levels_ - 1) {      // no tail (3D): exact solve on the coarsest level
+    const int Nc = (int)h_->lev_N[l];
+    const dim3 g((unsigned)B), blk(Nc * 4 <= 1024 ? (unsigned)((Nc * 4 + 63) / 64 * 64) : 1024u);
     if (l == 0)
-      hipLaunchKernelGGL((k_coarsest<3, TI, C>), g, blk, 0, st_, (const TI*)b.ptr, b.stride, (TI*)x.ptr, x.stride, op, B);
+      hipLaunchKernelGGL((k_coarse_solve<TI, C>), g, blk, 0, st_, (const TI*)b.ptr, b.stride, (TI*)x.ptr, x.stride,
+                         coarse_inv(stage), Nc);
     else
-      hipLaunchKernelGGL((k_coarsest<3, TM, C>), g, blk, 0, st_, (const TM*)b.ptr, b.stride, (TM*)x.ptr, x.stride, op, B);
+      hipLaunchKernelGGL((k_coarse_solve<TM, C>), g, blk, 0, st_, (const TM*)b.ptr, b.stride, (TM*)x.ptr, x.stride,
+                         coarse_inv(stage), Nc);
     MG_TRY(hipGetLastError());
     *result = x;
     return hipSuccess;
@@ -694,6 +977,18 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
   const int nu1 = h_->opts.nu1, nu2 = h_->opts.nu2;
   const int64_t Nl = h_->lev_N[l];
   Vec tmp{h_->ws + P.mgT[l], Nl};
+  if (h_->dim == 2 && nu1 <= 3 && nu2 <= 3 && !pre) {
+    // tiled: down (sweeps, residual, restriction) -> coarse cycle -> up
+    const int64_t Nc = h_->lev_N[l + 1];
+    Vec bc{h_->ws + P.mgB[l + 1], Nc};
+    Vec xc{h_->ws + P.mgX[l + 1], Nc};
+    MG_TRY(down2d(l, stage, b, zero_init ? nullptr : x.ptr, x.stride, tmp, bc, B));
+    Vec ec{};
+    MG_TRY(vcycle(l + 1, stage, xc, bc, true, false, B, &ec));
+    MG_TRY(up2d(l, stage, tmp, ec, b, x, B));
+    *result = x;
+    return hipSuccess;
+  }
   auto partner = [&](const Vec& v) { return v.ptr == x.ptr ? tmp : x; };
   // writes after the first sweep alternate buffers; at level 0 the result
   // must end in x, so the first sweep's target is chosen by parity

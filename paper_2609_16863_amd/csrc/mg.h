@@ -33,6 +33,9 @@ class Multigrid {
   hipError_t prolong(int l, Vec xin, Vec ec, Vec xout, int B);
   hipError_t prolong_smooth0(int stage, Vec xin, Vec ec, Vec b, Vec xout, int B);
   hipError_t tail(int stage, Vec x, Vec b, bool zero_init, int B);
+  hipError_t down2d(int l, int stage, Vec b, const void* x0, int64_t sx0, Vec xout, Vec bc, int B);
+  hipError_t up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec xout, int B);
+  const C* coarse_inv(int stage) const;
 
   aao_problem* h_;
   hipStream_t st_;
@@ -40,6 +43,7 @@ class Multigrid {
   int levels_;
   int l0_;          // first level solved by the one-workgroup LDS tail
   size_t tail_bytes_;
+  int cinv_set_;    // 0: shifts of P-tilde, 1: of its transpose
 };
 
 }  // namespace aao

@@ -120,11 +120,11 @@ void crout_lower(int s, const double* A, double* L) {
 // 2, 4, ..., 2 floor(n/2) (1-based), P is linear interpolation (zero
 // boundary values), and M_{l+1} = P^T M_l P / 2, T_{l+1} = P^T T_l P / 2, so
 // that in d dimensions R = P^T / 2^d and the Galerkin operator R A_l P of
-// A_l = M(x)M + a (T(x)M + M(x)T) is again of that form.  Coarsening stops at
-// one node.  tri[l] (l >= 1) = [Mlo, Md, Mup, Tlo, Td, Tup], each n_l long.
-void galerkin_1d(int n, double h, std::vector<int>& sizes, std::vector<std::vector<double>>& tri) {
+// A_l = M(x)M + a (T(x)M + M(x)T) is again of that form.  Coarsening stops
+// once a level has at most COARSE_MAX nodes (that level is solved exactly).
+// tri[l] = [Mlo, Md, Mup, Tlo, Td, Tup], each n_l long (level 0 included).
+void galerkin_1d(int n, int dim, double h, std::vector<int>& sizes, std::vector<std::vector<double>>& tri) {
   sizes.assign(1, n);
-  tri.assign(1, std::vector<double>());
   int nf = n;
   std::vector<double> M(nf * nf, 0.0), T(nf * nf, 0.0);
   for (int i = 0; i < nf; ++i) {
@@ -133,7 +133,21 @@ void galerkin_1d(int n, double h, std::vector<int>& sizes, std::vector<std::vect
     if (i > 0) T[i * nf + i - 1] = -1.0 / (h * h);
     if (i + 1 < nf) T[i * nf + i + 1] = -1.0 / (h * h);
   }
-  while (nf > 1) {
+  auto pack = [](const std::vector<double>& Mx, const std::vector<double>& Tx, int m) {
+    std::vector<double> t(6 * m, 0.0);
+    for (int i = 0; i < m; ++i) {
+      t[0 * m + i] = i > 0 ? Mx[i * m + i - 1] : 0.0;
+      t[1 * m + i] = Mx[i * m + i];
+      t[2 * m + i] = i + 1 < m ? Mx[i * m + i + 1] : 0.0;
+      t[3 * m + i] = i > 0 ? Tx[i * m + i - 1] : 0.0;
+      t[4 * m + i] = Tx[i * m + i];
+      t[5 * m + i] = i + 1 < m ? Tx[i * m + i + 1] : 0.0;
+    }
+    return t;
+  };
+  tri.assign(1, pack(M, T, nf));
+  auto npow = [dim](int m) { double v = 1.0; for (int a = 0; a < dim; ++a) v *= m; return v; };
+  while (npow(nf) > COARSE_MAX && nf > 1) {
     int nc = nf / 2;
     // P: nf x nc, coarse J at fine 2J+1 (0-based), neighbours 2J and 2J+2
     std::vector<double> P(nf * nc, 0.0);
@@ -160,21 +174,102 @@ void galerkin_1d(int n, double h, std::vector<int>& sizes, std::vector<std::vect
       return out;
     };
     std::vector<double> Mc = rap(M), Tc = rap(T);
-    std::vector<double> t(6 * nc, 0.0);
-    for (int i = 0; i < nc; ++i) {
-      t[0 * nc + i] = i > 0 ? Mc[i * nc + i - 1] : 0.0;
-      t[1 * nc + i] = Mc[i * nc + i];
-      t[2 * nc + i] = i + 1 < nc ? Mc[i * nc + i + 1] : 0.0;
-      t[3 * nc + i] = i > 0 ? Tc[i * nc + i - 1] : 0.0;
-      t[4 * nc + i] = Tc[i * nc + i];
-      t[5 * nc + i] = i + 1 < nc ? Tc[i * nc + i + 1] : 0.0;
-    }
     sizes.push_back(nc);
-    tri.push_back(t);
+    tri.push_back(pack(Mc, Tc, nc));
     M.swap(Mc);
     T.swap(Tc);
     nf = nc;
   }
+}
+
+// Dense inverse of the coarsest level's operator, stored transposed
+// (invT[c * Nc + r] = (A^{-1})_{rc}) so that threads reading consecutive rows
+// read consecutive addresses.  The operator is the tensor Galerkin form
+// M(x)M(x..) + a sum T(x)M.. built from the level's 1D factors; when the
+// coarsest level is the fine level it is I + a K with the face diffusivities
+// (faces may be null for kappa = 1).
+bool coarse_inverse(int dim, int n, const std::vector<double>& tri, double a, bool fine, double ih2,
+                    const double* faces, std::vector<double>& invT) {
+  int N = 1;
+  for (int d = 0; d < dim; ++d) N *= n;
+  std::vector<double> A((size_t)N * N, 0.0);
+  auto m1 = [&](int q, int i) { return tri[q * n + i]; };   // q: 0 lo, 1 d, 2 up (M); 3..5 (T)
+  auto coord = [&](int p, int* c) { c[0] = p % n; c[1] = (p / n) % n; c[2] = dim == 3 ? p / (n * n) : 0; };
+  for (int p = 0; p < N; ++p) {
+    int c[3];
+    coord(p, c);
+    for (int q = 0; q < N; ++q) {
+      int e[3];
+      coord(q, e);
+      bool near = true;
+      int off[3] = {0, 0, 0};
+      for (int d = 0; d < dim; ++d) {
+        off[d] = e[d] - c[d];
+        if (off[d] < -1 || off[d] > 1) near = false;
+      }
+      if (!near) continue;
+      double v;
+      if (fine) {
+        int nz = 0;
+        for (int d = 0; d < dim; ++d) nz += off[d] != 0;
+        if (nz > 1) continue;
+        if (nz == 0) {
+          double sum = 0.0;
+          for (int d = 0; d < dim; ++d)
+            sum += faces ? faces[(size_t)(2 * d) * N + p] + faces[(size_t)(2 * d + 1) * N + p] : 2.0;
+          v = 1.0 + a * ih2 * sum;
+        } else {
+          int d = 0;
+          while (off[d] == 0) ++d;
+          const double f = faces ? faces[(size_t)(2 * d + (off[d] > 0 ? 1 : 0)) * N + p] : 1.0;
+          v = -a * ih2 * f;
+        }
+      } else {
+        double mm = 1.0, sumT = 0.0;
+        for (int d = 0; d < dim; ++d) mm *= m1(1 + off[d], c[d]);
+        for (int d = 0; d < dim; ++d) {
+          double t = m1(4 + off[d], c[d]);
+          for (int d2 = 0; d2 < dim; ++d2)
+            if (d2 != d) t *= m1(1 + off[d2], c[d2]);
+          sumT += t;
+        }
+        v = mm + a * sumT;
+      }
+      A[(size_t)p * N + q] = v;
+    }
+  }
+  // Gauss-Jordan with partial pivoting
+  std::vector<double> inv((size_t)N * N, 0.0);
+  for (int i = 0; i < N; ++i) inv[(size_t)i * N + i] = 1.0;
+  for (int k = 0; k < N; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < N; ++i)
+      if (std::fabs(A[(size_t)i * N + k]) > std::fabs(A[(size_t)piv * N + k])) piv = i;
+    if (A[(size_t)piv * N + k] == 0.0) return false;
+    if (piv != k)
+      for (int j = 0; j < N; ++j) {
+        std::swap(A[(size_t)k * N + j], A[(size_t)piv * N + j]);
+        std::swap(inv[(size_t)k * N + j], inv[(size_t)piv * N + j]);
+      }
+    const double dk = 1.0 / A[(size_t)k * N + k];
+    for (int j = 0; j < N; ++j) {
+      A[(size_t)k * N + j] *= dk;
+      inv[(size_t)k * N + j] *= dk;
+    }
+    for (int i = 0; i < N; ++i) {
+      if (i == k) continue;
+      const double f = A[(size_t)i * N + k];
+      if (f == 0.0) continue;
+      for (int j = 0; j < N; ++j) {
+        A[(size_t)i * N + j] -= f * A[(size_t)k * N + j];
+        inv[(size_t)i * N + j] -= f * inv[(size_t)k * N + j];
+      }
+    }
+  }
+  invT.assign((size_t)N * N, 0.0);
+  for (int r = 0; r < N; ++r)
+    for (int cidx = 0; cidx < N; ++cidx) invT[(size_t)cidx * N + r] = inv[(size_t)r * N + cidx];
+  return true;
 }
 
 // Face diffusivities (not divided by h^2): harmonic mean between interior
