@@ -50,6 +50,259 @@ __global__ __launch_bounds__(TPB) void k_apply_A(const TX* __restrict__ x, doubl
   if (step == 0) y[p] = vp;
 }
 
+// 2D variant: each thread owns W adjacent x positions of one step and
+// marches along y over ROWS rows with a register window of rows j-1 .. j+2 of
+// every input field (row j+2 is fetched while row j is computed), so each
+// value is read from HBM once per launch.  W = 2 uses 16-byte loads and
+// stores (n even).  The x neighbours are taken from the adjacent lanes of the
+// wave; only lanes 0 and 63 load the value beyond their wave.
+#ifndef AAO_APPLY_ROWS
+#define AAO_APPLY_ROWS 64
+#endif
+constexpr int ROWS = AAO_APPLY_ROWS;
+
+template <int W, class TX>
+__device__ __forceinline__ void ldw(const TX* p, double* out) {
+  if constexpr (W == 1) {
+    out[0] = ld<TX, double>(p);
+  } else if constexpr (std::is_same<TX, double>::value) {
+    const double2 t = *reinterpret_cast<const double2*>(p);
+    out[0] = t.x;
+    out[1] = t.y;
+  } else if constexpr (std::is_same<TX, float>::value) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    out[0] = t.x;
+    out[1] = t.y;
+  } else {
+    out[0] = ld<TX, double>(p);
+    out[1] = ld<TX, double>(p + 1);
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void stw(double* p, const double* v) {
+  if constexpr (W == 1) {
+    p[0] = v[0];
+  } else {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  }
+}
+
+template <int W>
+struct March2D {
+  int n, i, lane, j0, j1, eoff;
+  bool live, edge;
+  __device__ explicit March2D(int n_) : n(n_) {
+    i = (blockIdx.x * TPB + threadIdx.x) * W;
+    lane = threadIdx.x & 63;
+    live = i < n;  // W = 2 only for even n: both columns live or neither
+    eoff = lane == 0 ? -1 : W;
+    edge = live && ((lane == 0 && i > 0) || (lane == 63 && i + W < n));
+    j0 = blockIdx.y * ROWS;
+    j1 = j0 + ROWS < n ? j0 + ROWS : n;
+  }
+  // whole wave beyond the last column: nothing to do (wave-uniform)
+  __device__ bool idle() const { return (int)((blockIdx.x * TPB + (threadIdx.x & ~63)) * W) >= n; }
+  // row jr of field f at this thread's columns (zero outside the grid and past jmax)
+  template <class TX>
+  __device__ void row(const TX* f, int jr, int jmax, double* out) const {
+    if (live && jr >= 0 && jr <= jmax && jr < n) {
+      ldw<W>(f + (int64_t)jr * n + i, out);
+    } else {
+#pragma unroll
+      for (int c = 0; c < W; ++c) out[c] = 0.0;
+    }
+  }
+  template <class TX>
+  __device__ double row1(const TX* f, int jr, int jmax) const {
+    return (live && jr <= jmax) ? ld<TX, double>(f + (int64_t)jr * n + i) : 0.0;
+  }
+  // edge lanes: the neighbour outside the wave on row jr
+  template <class TX>
+  __device__ double edge_val(const TX* f, int jr, int jmax) const {
+    return (edge && jr <= jmax) ? ld<TX, double>(f + (int64_t)jr * n + i + eoff) : 0.0;
+  }
+  // x neighbours of column c given this thread's row values r and edge value e
+  __device__ double left(const double* r, double e, int c) const {
+    if (c > 0) return r[c - 1];
+    const double s = __shfl_up(r[W - 1], 1);
+    return lane == 0 ? e : s;
+  }
+  __device__ double right(const double* r, double e, int c) const {
+    if (c < W - 1) return r[c + 1];
+    const double s = __shfl_down(r[0], 1);
+    return lane == 63 ? e : s;
+  }
+};
+
+template <bool VK>
+__device__ __forceinline__ double k5(double c, double xm, double xp, double ym, double yp, double ih2,
+                                     const Faces<double>& fc, int64_t p) {
+  if (!VK) return ih2 * (4.0 * c - xm - xp - ym - yp);
+  return ih2 * (fc.m[0][p] * (c - xm) + fc.p[0][p] * (c - xp) + fc.m[1][p] * (c - ym) + fc.p[1][p] * (c - yp));
+}
+
+template <int S, bool VK, int W, class TX>
+__global__ __launch_bounds__(TPB) void k_apply_A_2d(const TX* __restrict__ x, double* __restrict__ y, int n, int nt,
+                                                    double ih2, Tab tab, Faces<double> fc) {
+  const March2D<W> m(n);
+  if (m.idle()) return;
+  const int step = blockIdx.z;
+  const int64_t N = (int64_t)n * n;
+  constexpr int F = S + 1;  // v_n and the S stage fields
+  const TX* fld[F];
+  fld[0] = x + (int64_t)step * N;
+#pragma unroll
+  for (int q = 0; q < S; ++q) fld[q + 1] = x + ((int64_t)(nt + 1) + (int64_t)step * S + q) * N;
+  const TX* vn = x + (int64_t)(step + 1) * N;
+  double* yV = y + ((int64_t)(nt + 1) + (int64_t)step * S) * N;
+  double* yv = y + (int64_t)(step + 1) * N;
+  const int jl = m.j1;  // last row any window needs
+  double r0[F][W], r1[F][W], r2[F][W], r3[F][W], e0[F], e1[F], w0[W], w1[W];
+#pragma unroll
+  for (int q = 0; q < F; ++q) {
+    m.row(fld[q], m.j0 - 1, jl, r0[q]);
+    m.row(fld[q], m.j0, jl, r1[q]);
+    m.row(fld[q], m.j0 + 1, jl, r2[q]);
+    e0[q] = m.edge_val(fld[q], m.j0, jl);
+  }
+  m.row(vn, m.j0, jl, w0);
+  for (int j = m.j0; j < m.j1; ++j) {
+#pragma unroll
+    for (int q = 0; q < F; ++q) {
+      m.row(fld[q], j + 2, jl, r3[q]);
+      e1[q] = m.edge_val(fld[q], j + 1, m.j1 - 1);
+    }
+    m.row(vn, j + 1, m.j1 - 1, w1);
+    const int64_t p = (int64_t)j * n + m.i;
+    double KF[F][W];
+#pragma unroll
+    for (int q = 0; q < F; ++q)
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+        KF[q][c] = k5<VK>(r1[q][c], m.left(r1[q], e0[q], c), m.right(r1[q], e0[q], c), r0[q][c], r2[q][c], ih2, fc,
+                          m.live ? p + c : 0);
+    if (m.live) {
+      double yvv[W];
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        double upd = 0.0;
+#pragma unroll
+        for (int r = 0; r < S; ++r) upd += tab.b[r] * r1[r + 1][c];
+        yvv[c] = w0[c] - r1[0][c] - tab.tau * upd;
+      }
+#pragma unroll
+      for (int r = 0; r < S; ++r) {
+        double out[W];
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+          double mix = 0.0;
+#pragma unroll
+          for (int q = 0; q < S; ++q) mix += tab.A[r * S + q] * KF[q + 1][c];
+          out[c] = r1[r + 1][c] + KF[0][c] + tab.tau * mix;
+        }
+        stw<W>(yV + (int64_t)r * N + p, out);
+      }
+      stw<W>(yv + p, yvv);
+      if (step == 0) stw<W>(y + p, r1[0]);
+    }
+#pragma unroll
+    for (int q = 0; q < F; ++q) {
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        r0[q][c] = r1[q][c];
+        r1[q][c] = r2[q][c];
+        r2[q][c] = r3[q][c];
+      }
+      e0[q] = e1[q];
+    }
+#pragma unroll
+    for (int c = 0; c < W; ++c) w0[c] = w1[c];
+  }
+}
+
+// Transposed, 2D marching form (see k_apply_A_2d).
+template <int S, bool VK, int W, class TX>
+__global__ __launch_bounds__(TPB) void k_apply_AT_2d(const TX* __restrict__ x, double* __restrict__ y, int n, int nt,
+                                                     double ih2, Tab tab, Faces<double> fc) {
+  const March2D<W> m(n);
+  if (m.idle()) return;
+  const int step = blockIdx.z;
+  const int64_t N = (int64_t)n * n;
+  const TX* fld[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) fld[q] = x + ((int64_t)(nt + 1) + (int64_t)step * S + q) * N;
+  const TX* xv = x + (int64_t)step * N;
+  const TX* xvn = x + (int64_t)(step + 1) * N;
+  double* yV = y + ((int64_t)(nt + 1) + (int64_t)step * S) * N;
+  double* yv = y + (int64_t)step * N;
+  const int jl = m.j1;
+  double r0[S][W], r1[S][W], r2[S][W], r3[S][W], e0[S], e1[S], a0[W], b0[W], a1[W], b1[W];
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    m.row(fld[q], m.j0 - 1, jl, r0[q]);
+    m.row(fld[q], m.j0, jl, r1[q]);
+    m.row(fld[q], m.j0 + 1, jl, r2[q]);
+    e0[q] = m.edge_val(fld[q], m.j0, jl);
+  }
+  m.row(xv, m.j0, jl, a0);
+  m.row(xvn, m.j0, jl, b0);
+  for (int j = m.j0; j < m.j1; ++j) {
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      m.row(fld[q], j + 2, jl, r3[q]);
+      e1[q] = m.edge_val(fld[q], j + 1, m.j1 - 1);
+    }
+    m.row(xv, j + 1, m.j1 - 1, a1);
+    m.row(xvn, j + 1, m.j1 - 1, b1);
+    const int64_t p = (int64_t)j * n + m.i;
+    double KX[S][W], sumK[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) sumK[c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        KX[q][c] = k5<VK>(r1[q][c], m.left(r1[q], e0[q], c), m.right(r1[q], e0[q], c), r0[q][c], r2[q][c], ih2, fc,
+                          m.live ? p + c : 0);
+        sumK[c] += KX[q][c];
+      }
+    if (m.live) {
+      double out[W];
+#pragma unroll
+      for (int c = 0; c < W; ++c) out[c] = a0[c] - b0[c] + sumK[c];
+      stw<W>(yv + p, out);
+#pragma unroll
+      for (int cs = 0; cs < S; ++cs) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+          double mix = 0.0;
+#pragma unroll
+          for (int r = 0; r < S; ++r) mix += tab.A[r * S + cs] * KX[r][c];
+          out[c] = r1[cs][c] + tab.tau * mix - tab.tau * tab.b[cs] * b0[c];
+        }
+        stw<W>(yV + (int64_t)cs * N + p, out);
+      }
+      if (step == nt - 1) stw<W>(y + (int64_t)nt * N + p, b0);
+    }
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        r0[q][c] = r1[q][c];
+        r1[q][c] = r2[q][c];
+        r2[q][c] = r3[q][c];
+      }
+      e0[q] = e1[q];
+    }
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      a0[c] = a1[c];
+      b0[c] = b1[c];
+    }
+  }
+}
+
 // Transposed rows:  y_{v,n} = x_{v,n} - x_{v,n+1} + K sum_i x_{V,n,i}  (n < nt)
 //                   y_{v,nt} = x_{v,nt}
 //                   y_{V,n,j} = x_{V,n,j} + tau K sum_i a_ij x_{V,n,i} - tau b_j x_{v,n+1}
@@ -192,11 +445,39 @@ Faces<double> face_ptrs(const aao_problem* h) {
 
 }  // namespace
 
+// The two-column 2D kernels need even n and 16-byte aligned x and y rows.
+template <class TX>
+static bool two_columns(int n, const TX* x, const double* y) {
+#ifdef AAO_APPLY_ONE_COLUMN
+  return false;
+#endif
+  return n % 2 == 0 && reinterpret_cast<uintptr_t>(x) % (2 * sizeof(TX)) == 0 &&
+         reinterpret_cast<uintptr_t>(y) % 16 == 0;
+}
+
+#define DISPATCH_SV(s_, vk_, M)                                          \
+  do {                                                                   \
+    if (vk_) { if ((s_) == 1) M(1, true); else if ((s_) == 2) M(2, true); else M(3, true); }       \
+    else { if ((s_) == 1) M(1, false); else if ((s_) == 2) M(2, false); else M(3, false); }        \
+  } while (0)
+
 template <class TX>
 hipError_t launch_apply_A(const aao_problem* h, const TX* x, double* y, hipStream_t st) {
-  dim3 grid((unsigned)((h->N + TPB - 1) / TPB), (unsigned)h->nt);
   const int n = h->n, N = (int)h->N, nt = h->nt;
   Faces<double> fc = face_ptrs(h);
+  if (h->dim == 2) {
+    const int W = two_columns(n, x, y) ? 2 : 1;
+    const dim3 g2((unsigned)((n + TPB * W - 1) / (TPB * W)), (unsigned)((n + ROWS - 1) / ROWS), (unsigned)nt);
+#define AAO_A2(S, V)                                                                                          \
+  do {                                                                                                     \
+    if (W == 2) hipLaunchKernelGGL((k_apply_A_2d<S, V, 2, TX>), g2, dim3(TPB), 0, st, x, y, n, nt, h->ih2, h->tab, fc); \
+    else hipLaunchKernelGGL((k_apply_A_2d<S, V, 1, TX>), g2, dim3(TPB), 0, st, x, y, n, nt, h->ih2, h->tab, fc);        \
+  } while (0)
+    DISPATCH_SV(h->s, h->vark, AAO_A2);
+#undef AAO_A2
+    return hipGetLastError();
+  }
+  dim3 grid((unsigned)((h->N + TPB - 1) / TPB), (unsigned)h->nt);
 #define AAO_LAUNCH_A(D, S, V) \
   hipLaunchKernelGGL((k_apply_A<D, S, V, TX>), grid, dim3(TPB), 0, st, x, y, n, N, nt, h->ih2, h->tab, fc)
   DISPATCH_DSV(h->dim, h->s, h->vark, AAO_LAUNCH_A);
@@ -206,9 +487,21 @@ hipError_t launch_apply_A(const aao_problem* h, const TX* x, double* y, hipStrea
 
 template <class TX>
 hipError_t launch_apply_AT(const aao_problem* h, const TX* x, double* y, hipStream_t st) {
-  dim3 grid((unsigned)((h->N + TPB - 1) / TPB), (unsigned)h->nt);
   const int n = h->n, N = (int)h->N, nt = h->nt;
   Faces<double> fc = face_ptrs(h);
+  if (h->dim == 2) {
+    const int W = two_columns(n, x, y) ? 2 : 1;
+    const dim3 g2((unsigned)((n + TPB * W - 1) / (TPB * W)), (unsigned)((n + ROWS - 1) / ROWS), (unsigned)nt);
+#define AAO_AT2(S, V)                                                                                          \
+  do {                                                                                                     \
+    if (W == 2) hipLaunchKernelGGL((k_apply_AT_2d<S, V, 2, TX>), g2, dim3(TPB), 0, st, x, y, n, nt, h->ih2, h->tab, fc); \
+    else hipLaunchKernelGGL((k_apply_AT_2d<S, V, 1, TX>), g2, dim3(TPB), 0, st, x, y, n, nt, h->ih2, h->tab, fc);        \
+  } while (0)
+    DISPATCH_SV(h->s, h->vark, AAO_AT2);
+#undef AAO_AT2
+    return hipGetLastError();
+  }
+  dim3 grid((unsigned)((h->N + TPB - 1) / TPB), (unsigned)h->nt);
 #define AAO_LAUNCH_AT(D, S, V) \
   hipLaunchKernelGGL((k_apply_AT<D, S, V, TX>), grid, dim3(TPB), 0, st, x, y, n, N, nt, h->ih2, h->tab, fc)
   DISPATCH_DSV(h->dim, h->s, h->vark, AAO_LAUNCH_AT);

@@ -10,7 +10,9 @@ pytestmark = pytest.mark.gpu
 
 # tiny (dense), ragged tails (N not a multiple of the 256-thread tile), 3D
 CASES = [(2, 3, 1, 3, False), (2, 4, 2, 4, True), (2, 5, 3, 2, False), (3, 3, 2, 3, False),
-         (3, 3, 3, 2, True), (2, 37, 3, 5, False), (2, 37, 2, 5, True), (3, 11, 3, 3, False)]
+         (3, 3, 3, 2, True), (2, 37, 3, 5, False), (2, 37, 2, 5, True), (3, 11, 3, 3, False),
+         # 2D row-marching tiles (64 rows; 512 columns for even n, 256 for odd n), ragged in x and y
+         (2, 300, 3, 2, False), (2, 270, 2, 2, True), (2, 530, 1, 1, False), (2, 301, 1, 2, True)]
 
 
 def _setup(dim, n, s, nt, vk, seed):
