@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=8, help="time steps in the CPU oracle sample")
     ap.add_argument("--roofline-reps", type=int, default=20)
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the roofline launches (apply_A, V-cycle, a 1 GiB device copy); for counter runs")
     return ap.parse_args()
 
 
@@ -73,6 +75,13 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
     print(f"[bench] {w.name}: U = {hp_mix.U:,} unknowns, setup {setup_s:.1f} s", file=sys.stderr, flush=True)
+    if args.roofline_only:
+        x = torch.randn(hp_mix.U, dtype=torch.float64, device=dev)
+        out = {"roofline": measure_roofline(hp_mix, x, args.roofline_reps),
+               "roofline_vcycle": measure_vcycle(hp_mix, args.mixed, args.roofline_reps),
+               "copy_reference": measure_copy(1 << 30, 5)}
+        print(json.dumps(out))
+        return
 
     def run(hp, label, K, W):
         times, stats, x = [], None, None
@@ -111,6 +120,8 @@ def main():
     # ---- roofline of the dominant kernel (live, HIP events) ------------------
     roofline = measure_roofline(hp_mix, x_mix, args.roofline_reps)
 
+    roofline_vcycle = measure_vcycle(hp_mix, args.mixed, args.roofline_reps)
+
     # ---- CPU oracle baseline on a bounded sample -----------------------------
     cpu = None
     fwd_err = None
@@ -131,7 +142,7 @@ def main():
         "precond_ms_per_solve": st_mix["precond_ms"],
         "fp64_preconditioner": fp64,
         "forward_error_vs_oracle_sampled_steps": fwd_err,
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "roofline_vcycle": roofline_vcycle, "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 
@@ -140,21 +151,70 @@ def measure_roofline(hp, x, reps):
     """apply_A: 16 B per unknown (read x once, write y once) per launch."""
     import torch
     y = torch.empty_like(x)
+    sec = _event_time(lambda: hp.apply_A(x, y), reps)
+    nbytes = 16.0 * hp.U
+    gbs = nbytes / sec / 1e9
+    return {"kernel": "k_apply_A_2d", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": nbytes,
+            "avg_launch_us": sec * 1e6}
+
+
+def _event_time(fn, reps):
+    """Average seconds per call of fn over reps calls, by HIP events on the
+    current stream (the library runs on it: the binding sets the handle's
+    stream to torch's current stream before each call)."""
+    import torch
     stream = torch.cuda.current_stream()
-    hp.apply_A(x, y)
+    fn()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        hp.apply_A(x, y)
+        fn()
     e1.record(stream)
     torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) / 1e3 / reps
-    nbytes = 16.0 * hp.U
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def measure_vcycle(hp, precision, reps):
+    """One V-cycle (from zero) on all nt stage blocks of stage 0, the batched
+    shifted-block solve of Theta-tilde.  Algorithmic bytes of the fused 2D
+    level kernels, per block: level l above the LDS tail moves
+    5 N_l p_l + 2 N_{l+1} p_{l+1} (pre-smooth + restriction read b_l and write
+    the smoothed x_l and b_{l+1}; prolongation + post-smoothing read x_l, the
+    correction and b_l and write x_l); the tail reads b and writes x at its
+    first level.  p_l: 8 (FP64), 4 (FP32, and level 0 of BF16/FP16), 2 (BF16/FP16
+    coarse levels)."""
+    import torch
+    nodes, l0 = hp.mg_levels()
+    L = len(nodes)
+    pw = 8 if precision == "fp64" else 4
+    pc = {"fp64": 8, "fp32": 4}.get(precision, 2)
+    p = [pw] + [pc] * (L - 1)
+    per_block = 0
+    for l in range(min(l0, L - 1)):
+        per_block += 5 * nodes[l] * p[l] + 2 * nodes[l + 1] * p[l + 1]
+    if l0 < L:
+        per_block += 2 * nodes[l0] * p[l0]
+    B = hp.nt
+    r = torch.randn(B * hp.N, dtype=hp.working_dtype(), device="cuda")
+    z = torch.empty_like(r)
+    sec = _event_time(lambda: hp.apply_mg(r, 0, out=z, cycles=1), reps)
+    nbytes = float(per_block * B)
     gbs = nbytes / sec / 1e9
-    return {"kernel": "k_apply_A", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": nbytes,
-            "avg_launch_us": sec * 1e6}
+    return {"kernel": "V-cycle: k_down2d per level, k_tail, k_up2d per level", "bound": "hbm",
+            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": None, "bytes_per_launch": nbytes, "avg_launch_us": sec * 1e6,
+            "blocks": B, "levels": nodes, "tail_level": l0}
+
+
+def measure_copy(nbytes, reps):
+    """Reference: a plain device-to-device copy of nbytes (read + write)."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").normal_()
+    b = torch.empty_like(a)
+    sec = _event_time(lambda: b.copy_(a), reps)
+    return {"bytes": nbytes, "avg_launch_us": sec * 1e6, "GBs": 2 * nbytes / sec / 1e9}
 
 
 def cpu_baseline(w, f, u0, x_gpu, nsteps):

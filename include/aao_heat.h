@@ -160,6 +160,30 @@ int aao_apply_P(aao_problem* h, const double* r, double* z);
  * (Sec. 3). */
 int aao_apply_P_with(aao_problem* h, const double* r, double* z, int inner_k, int cycles);
 
+/* z_b = (`cycles` geometric multigrid V-cycles from zero) applied to
+ * (I + a K) z_b = r_b for the blocks b = 0 .. count-1: the shifted-block
+ * solve inside Rana's preconditioner (Sec. 4), with a = tau L_ii, L the
+ * lower Crout factor of the Radau IIA matrix A (transpose = 0) or of A^T
+ * (transpose = 1, the adjoint preconditioner), i = `stage`.
+ * The hierarchy, smoother and coarse solve are the handle's (opts.nu1,
+ * nu2, omega; coarsening to at most 256 nodes, solved exactly).
+ * r, z: device, count * N values each, block b at offset b * N, in the
+ * preconditioner's working type: double for AAO_PREC_FP64, float for
+ * FP32, BF16 and FP16 (the 16-bit formats are the coarse levels' storage).
+ * 1 <= count <= nt, 0 <= stage < s, 1 <= cycles <= 64; r and z must not
+ * overlap.  Asynchronous on the handle's stream. */
+int aao_apply_mg(aao_problem* h, int transpose, int stage, int count, int cycles, const void* r, void* z);
+
+/* The multigrid hierarchy: *levels levels, level l with nodes[l] grid
+ * nodes (written for l < cap; nodes may be NULL when cap == 0).  Level
+ * l+1 keeps every second node of level l along each axis; the last level
+ * has at most 256 nodes and is solved exactly.  Levels >= *tail_level
+ * run inside one workgroup's LDS (2D; *tail_level = *levels when none
+ * do); that split depends on the device, so it needs the workspace set
+ * (AAO_NO_WORKSPACE otherwise, with *levels and nodes still filled).
+ * Host-only. */
+int aao_mg_levels(const aao_problem* h, int cap, int64_t* nodes, int* levels, int* tail_level);
+
 /* rhs = [b; f] of eq. (2.4): b_0 = u0, b_{n>=1} = 0, then f.
  * f: device, nt*s*N values in (step, stage, node) order, f_{n,i} sampled
  * at t_n + c_i tau; u0: device, N values; rhs: device, U values. */

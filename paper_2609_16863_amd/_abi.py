@@ -46,6 +46,8 @@ SIGNATURES = {
     "aao_apply_AT": (c_int, [c_void_p, c_void_p, c_void_p]),
     "aao_apply_P": (c_int, [c_void_p, c_void_p, c_void_p]),
     "aao_apply_P_with": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int]),
+    "aao_apply_mg": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_void_p]),
+    "aao_mg_levels": (c_int, [c_void_p, c_int, c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "aao_assemble_rhs": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "aao_solve": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(Stats)]),
     "aao_solve_adjoint": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(Stats)]),

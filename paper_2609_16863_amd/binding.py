@@ -146,6 +146,33 @@ class HeatProblem:
                                                    int(cycles)))
         return out
 
+    def working_dtype(self):
+        """Element type of the preconditioner's vectors (apply_mg operands)."""
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def mg_levels(self):
+        """(nodes per level, first level solved in one workgroup's LDS)."""
+        nodes = np.zeros(64, dtype=np.int64)
+        L, t = ctypes.c_int(), ctypes.c_int()
+        self._check(self._lib.aao_mg_levels(self._h, 64, nodes.ctypes.data, ctypes.byref(L), ctypes.byref(t)))
+        return [int(v) for v in nodes[: L.value]], t.value
+
+    def apply_mg(self, r, stage, out=None, cycles=1, transpose=False):
+        """`cycles` V-cycles on the blocks of r (count x N) for I + tau L_ii K, i = stage."""
+        dt = self.working_dtype()
+        if not (isinstance(r, torch.Tensor) and r.is_cuda and r.dtype == dt and r.is_contiguous()
+                and r.numel() % self.N == 0 and r.numel() > 0):
+            raise ValueError(f"r must be a contiguous {dt} CUDA tensor of count * {self.N} values")
+        count = r.numel() // self.N
+        if out is None:
+            out = torch.empty_like(r)
+        elif not (out.is_cuda and out.dtype == dt and out.is_contiguous() and out.numel() == r.numel()):
+            raise ValueError("out must match r")
+        self._sync_stream()
+        self._check(self._lib.aao_apply_mg(self._h, int(bool(transpose)), int(stage), count, int(cycles),
+                                           _ptr(r), _ptr(out)))
+        return out
+
     def assemble_rhs(self, f, u0, out=None):
         f = self._vec(f, self.N * self.nt * self.s, "f")
         u0 = self._vec(u0, self.N, "u0")

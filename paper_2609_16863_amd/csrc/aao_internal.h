@@ -179,5 +179,10 @@ size_t mg_configure_lds();
 void release_graphs(aao_problem* h);
 int apply_P(aao_problem* h, const double* r, double* z, int inner_k, int cycles, bool transpose);
 int solve(aao_problem* h, const double* rhs, double* x, aao_stats* st, bool transpose);
+// `cycles` V-cycles on count blocks of (I + tau L_ii K), L = Crout factor of
+// A (or A^T); r, z in the preconditioner's working type.
+hipError_t apply_mg(aao_problem* h, bool transpose, int stage, int count, int cycles, const void* r, void* z);
+// First multigrid level handled by the one-workgroup tail.
+int mg_tail_level(aao_problem* h);
 
 }  // namespace aao

@@ -330,6 +330,33 @@ int aao_apply_P_with(aao_problem* h, const double* r, double* z, int inner_k, in
   return aao::apply_P(h, r, z, inner_k, cycles, false);
 }
 
+int aao_mg_levels(const aao_problem* h, int cap, int64_t* nodes, int* levels, int* tail_level) {
+  if (!h) return AAO_INVALID_ARG;
+  aao_problem* hm = const_cast<aao_problem*>(h);
+  if (!levels || !tail_level || cap < 0 || (cap > 0 && !nodes)) return fail(hm, AAO_INVALID_ARG, "null pointer");
+  const int L = (int)h->lev_N.size();
+  *levels = L;
+  for (int l = 0; l < L && l < cap; ++l) nodes[l] = h->lev_N[l];
+  if (!h->ws) return fail(hm, AAO_NO_WORKSPACE, "the tail level depends on the device: aao_set_workspace first");
+  *tail_level = aao::mg_tail_level(hm);
+  return AAO_OK;
+}
+
+int aao_apply_mg(aao_problem* h, int transpose, int stage, int count, int cycles, const void* r, void* z) {
+  if (!h) return AAO_INVALID_ARG;
+  if (!r || !z) return fail(h, AAO_INVALID_ARG, "null pointer");
+  if (transpose != 0 && transpose != 1) return fail(h, AAO_INVALID_ARG, "transpose must be 0 or 1");
+  if (stage < 0 || stage >= h->s) return fail(h, AAO_INVALID_ARG, "stage out of range");
+  if (count < 1 || count > h->nt) return fail(h, AAO_INVALID_ARG, "count must be in [1, nt]");
+  if (cycles < 1 || cycles > 64) return fail(h, AAO_INVALID_ARG, "cycles out of range");
+  const size_t bytes = (size_t)count * (size_t)h->N * (size_t)h->pi_bytes;
+  const char* rb = static_cast<const char*>(r);
+  const char* zb = static_cast<const char*>(z);
+  if (rb < zb + bytes && zb < rb + bytes) return fail(h, AAO_INVALID_ARG, "r and z overlap");
+  if (!h->ws) return fail(h, AAO_NO_WORKSPACE, "aao_set_workspace first");
+  return aao::status_from_hip(h, aao::apply_mg(h, transpose == 1, stage, count, cycles, r, z), "apply_mg");
+}
+
 int aao_assemble_rhs(aao_problem* h, const double* f, const double* u0, double* rhs) {
   if (!h) return AAO_INVALID_ARG;
   if (!f || !u0 || !rhs) return fail(h, AAO_INVALID_ARG, "null pointer");

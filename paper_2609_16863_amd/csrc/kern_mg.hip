@@ -308,43 +308,151 @@ __global__ __launch_bounds__(TPB) void k_prolong_smooth(const TX* __restrict__ x
 // ---------------------------------------------------------------------------
 constexpr int TCX = 16, TCY = 8;   // coarse nodes per down tile; fine tile is 2x
 
-template <int KIND, class C>
-__device__ __forceinline__ C tile_apply(const C* __restrict__ x, int t, int W, int gi, int gj,
-                                        const LevelOp<C>& op, C& d) {
-  const int n = op.n;
-  if (KIND != KIND_TENSOR) {
-    const int p = gj * n + gi;
-    const C xc = x[t], xm = x[t - 1], xp = x[t + 1], ym = x[t - W], yp = x[t + W];
-    C kx;
-    if (KIND == KIND_FINE) {
-      kx = C(4) * xc - xm - xp - ym - yp;
-    } else {
-      const Faces<C>& f = op.faces;
-      kx = f.m[0][p] * (xc - xm) + f.p[0][p] * (xc - xp) + f.m[1][p] * (xc - ym) + f.p[1][p] * (xc - yp);
-    }
-    d = level_diag<2, KIND, C>(op, p, gi, gj, 0);
-    return xc + op.a * op.ih2 * kx;
-  }
-  const Tri3<C> ri = tri_row(op.tri, n, gi), rj = tri_row(op.tri, n, gj);
-  C acc = C(0);
+// Shared memory of one tile with halo R: right-hand side, two iterates, and
+// the operator staged for the sweeps (omega / diagonal per node; face
+// coefficients times a/h^2 for variable kappa; the 1D Galerkin factor rows of
+// the tile's columns and rows for tensor levels).  Every global load of a
+// tile is issued up front, so a workgroup waits for memory once.
+template <int KIND, int R, class C>
+struct Tile {
+  static constexpr int W = 2 * TCX + 1 + 2 * R, H = 2 * TCY + 1 + 2 * R, NE = W * H;
+  static constexpr int IT = (NE + 255) / 256;
+  static constexpr bool VK = KIND == KIND_FINE_VK, TEN = KIND == KIND_TENSOR;
+  C b[NE], x0[NE], x1[NE];
+  C idg[KIND == KIND_FINE ? 1 : NE];
+  C f[VK ? 4 * NE : 1];
+  C cx[TEN ? 6 * W : 1];  // per column: (M + a T)(i, i+d), M(i, i+d), d = -1, 0, 1
+  C cy[TEN ? 6 * H : 1];  // per row:    M(j, j+d), a T(j, j+d)
+};
+
+// Stage the operator of the tile whose origin is (ox, oy) into LDS.  Loads
+// only; the caller synchronizes.
+template <int KIND, int R, class C>
+__device__ __forceinline__ void tile_stage_op(Tile<KIND, R, C>& sm, const LevelOp<C>& op, int ox, int oy) {
+  using T = Tile<KIND, R, C>;
+  constexpr int W = T::W, H = T::H;
+  const int tid = threadIdx.x, n = op.n;
+  if constexpr (T::VK) {
+    const C s = op.a * op.ih2;
+    C fv[4][T::IT];
 #pragma unroll
-  for (int dj = -1; dj <= 1; ++dj) {
-    C pv = C(0), qv = C(0);
-#pragma unroll
-    for (int di = -1; di <= 1; ++di) {
-      const C xv = x[t + dj * W + di];
-      pv += (ri.m[di + 1] + op.a * ri.t[di + 1]) * xv;
-      qv += ri.m[di + 1] * xv;
+    for (int it = 0; it < T::IT; ++it) {
+      const int t = tid + it * 256, gi = ox + t % W, gj = oy + t / W;
+      const bool in = t < T::NE && gi >= 0 && gi < n && gj >= 0 && gj < n;
+      const int64_t g = in ? (int64_t)gj * n + gi : 0;
+      fv[0][it] = in ? op.faces.m[0][g] : C(0);
+      fv[1][it] = in ? op.faces.p[0][g] : C(0);
+      fv[2][it] = in ? op.faces.m[1][g] : C(0);
+      fv[3][it] = in ? op.faces.p[1][g] : C(0);
     }
-    acc += rj.m[dj + 1] * pv + op.a * rj.t[dj + 1] * qv;
+#pragma unroll
+    for (int it = 0; it < T::IT; ++it) {
+      const int t = tid + it * 256;
+      if (t < T::NE) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sm.f[q * T::NE + t] = s * fv[q][it];
+      }
+    }
   }
-  d = ri.m[1] * rj.m[1] + op.a * (ri.t[1] * rj.m[1] + ri.m[1] * rj.t[1]);
-  return acc;
+  if constexpr (T::TEN) {
+    // columns: 6 W values, rows: 6 H values (W, H < 256 for R <= 4)
+    for (int t = tid; t < 3 * W + 3 * H; t += 256) {
+      if (t < 3 * W) {
+        const int d = t / W, c = t % W, gi = ox + c;
+        const bool in = gi >= 0 && gi < n;
+        const C m = in ? op.tri[d * n + gi] : C(0), tt = in ? op.tri[(3 + d) * n + gi] : C(0);
+        sm.cx[d * W + c] = m + op.a * tt;
+        sm.cx[(3 + d) * W + c] = m;
+      } else {
+        const int u = t - 3 * W, d = u / H, r = u % H, gj = oy + r;
+        const bool in = gj >= 0 && gj < n;
+        sm.cy[d * H + r] = in ? op.tri[d * n + gj] : C(0);
+        sm.cy[(3 + d) * H + r] = in ? op.a * op.tri[(3 + d) * n + gj] : C(0);
+      }
+    }
+  }
 }
 
-template <int KIND, class C>
-__device__ __forceinline__ C tile_diag(int gi, int gj, const LevelOp<C>& op) {
-  return level_diag<2, KIND, C>(op, gj * op.n + gi, gi, gj, 0);
+// Diagonal of the level operator at tile node (tx, ty) from the staged data.
+template <int KIND, int R, class C>
+__device__ __forceinline__ C tile_diag(const Tile<KIND, R, C>& sm, const LevelOp<C>& op, int t, int tx, int ty) {
+  using T = Tile<KIND, R, C>;
+  if constexpr (KIND == KIND_FINE) return C(1) + op.a * op.ih2 * C(4);
+  else if constexpr (T::VK)
+    return C(1) + sm.f[t] + sm.f[T::NE + t] + sm.f[2 * T::NE + t] + sm.f[3 * T::NE + t];
+  else
+    // M_j(0) (M + a T)_i(0) + a T_j(0) M_i(0)
+    return sm.cy[1 * T::H + ty] * sm.cx[1 * T::W + tx] + sm.cy[4 * T::H + ty] * sm.cx[4 * T::W + tx];
+}
+
+// (A x)_t for an interior tile node (all 8 neighbours inside the tile).
+template <int KIND, int R, class C>
+__device__ __forceinline__ C tile_Ax(const Tile<KIND, R, C>& sm, const C* __restrict__ x, const LevelOp<C>& op, int t,
+                                     int tx, int ty) {
+  using T = Tile<KIND, R, C>;
+  constexpr int W = T::W;
+  const C c = x[t];
+  if constexpr (KIND == KIND_FINE) {
+    return c + op.a * op.ih2 * (C(4) * c - x[t - 1] - x[t + 1] - x[t - W] - x[t + W]);
+  } else if constexpr (T::VK) {
+    return c + sm.f[t] * (c - x[t - 1]) + sm.f[T::NE + t] * (c - x[t + 1]) + sm.f[2 * T::NE + t] * (c - x[t - W]) +
+           sm.f[3 * T::NE + t] * (c - x[t + W]);
+  } else {
+    // sum_dj M_j(dj) sum_di (M + aT)_i(di) x + a T_j(dj) sum_di M_i(di) x
+    C acc = C(0);
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj) {
+      C pv = C(0), qv = C(0);
+#pragma unroll
+      for (int di = -1; di <= 1; ++di) {
+        const C xv = x[t + dj * W + di];
+        pv += sm.cx[(di + 1) * W + tx] * xv;
+        qv += sm.cx[(4 + di) * W + tx] * xv;
+      }
+      acc += sm.cy[(dj + 1) * T::H + ty] * pv + sm.cy[(4 + dj) * T::H + ty] * qv;
+    }
+    return acc;
+  }
+}
+
+// One weighted Jacobi sweep cur -> nxt over the tile (border and
+// out-of-domain nodes stay zero).
+template <int KIND, int R, class C>
+__device__ __forceinline__ void tile_sweep(Tile<KIND, R, C>& sm, const C* cur, C* nxt, const LevelOp<C>& op, int ox,
+                                           int oy, C omega) {
+  using T = Tile<KIND, R, C>;
+  constexpr int W = T::W, H = T::H;
+  const int n = op.n;
+#pragma unroll
+  for (int it = 0; it < T::IT; ++it) {
+    const int t = threadIdx.x + it * 256;
+    if (t < T::NE) {
+      const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
+      C v = C(0);
+      if (tx > 0 && tx < W - 1 && ty > 0 && ty < H - 1 && gi >= 0 && gi < n && gj >= 0 && gj < n) {
+        const C id = KIND == KIND_FINE ? omega / (C(1) + op.a * op.ih2 * C(4)) : sm.idg[KIND == KIND_FINE ? 0 : t];
+        v = cur[t] + id * (sm.b[t] - tile_Ax<KIND, R, C>(sm, cur, op, t, tx, ty));
+      }
+      nxt[t] = v;
+    }
+  }
+}
+
+// omega / diagonal for every in-domain tile node (after the operator is staged).
+template <int KIND, int R, class C>
+__device__ __forceinline__ void tile_inv_diag(Tile<KIND, R, C>& sm, const LevelOp<C>& op, int ox, int oy, C omega) {
+  using T = Tile<KIND, R, C>;
+  if constexpr (KIND != KIND_FINE) {
+#pragma unroll
+    for (int it = 0; it < T::IT; ++it) {
+      const int t = threadIdx.x + it * 256;
+      if (t < T::NE) {
+        const int tx = t % T::W, ty = t / T::W, gi = ox + tx, gj = oy + ty;
+        const bool in = gi >= 0 && gi < op.n && gj >= 0 && gj < op.n;
+        sm.idg[t] = in ? omega / tile_diag<KIND, R, C>(sm, op, t, tx, ty) : C(0);
+      }
+    }
+  }
 }
 
 // Down: x_NU (from zero, or from x0 when given) -> xout, and
@@ -352,58 +460,74 @@ __device__ __forceinline__ C tile_diag(int gi, int gj, const LevelOp<C>& op) {
 template <int KIND, int NU, class TF, class TC, class C>
 __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_t sb, const TF* __restrict__ x0,
                                                 int64_t sx0, TF* __restrict__ xout, int64_t sxo, TC* __restrict__ bc,
-                                                int64_t sbc, LevelOp<C> op, int nc, C omega) {
+                                                int64_t sbc, LevelOp<C> op, int nc, C omega, int gx, int gy) {
   constexpr int R = NU + 1;
-  constexpr int W = 2 * TCX + 1 + 2 * R, H = 2 * TCY + 1 + 2 * R;
-  __shared__ C sbv[W * H], s0[W * H], s1[W * H];
+  using T = Tile<KIND, R, C>;
+  constexpr int W = T::W, H = T::H;
+  __shared__ T sm;
   const int tid = threadIdx.x;
   const int nf = op.n;
-  const int I0 = blockIdx.x * TCX, J0 = blockIdx.y * TCY;
-  const int64_t inst = blockIdx.z;
+  const int L = xcd_tile((int)blockIdx.x, (int)gridDim.x);  // grid: gx * gy tiles per block
+  const int I0 = (L % gx) * TCX, J0 = ((L / gx) % gy) * TCY;
+  const int64_t inst = L / (gx * gy);
   const int ox = 2 * I0 - R, oy = 2 * J0 - R;
   const TF* bi = b + inst * sb;
-  for (int t = tid; t < W * H; t += 256) {
-    const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
-    const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
-    sbv[t] = in ? ld<TF, C>(bi + gj * nf + gi) : C(0);
-    if (x0) s0[t] = in ? ld<TF, C>(x0 + inst * sx0 + gj * nf + gi) : C(0);
+  const TF* xi = x0 ? x0 + inst * sx0 : nullptr;
+  C bv[T::IT], xv[T::IT];
+#pragma unroll
+  for (int it = 0; it < T::IT; ++it) {
+    const int t = tid + it * 256, gi = ox + t % W, gj = oy + t / W;
+    const bool in = t < T::NE && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+    const int64_t g = in ? (int64_t)gj * nf + gi : 0;
+    bv[it] = in ? ld<TF, C>(bi + g) : C(0);
+    xv[it] = (in && xi) ? ld<TF, C>(xi + g) : C(0);
+  }
+  tile_stage_op<KIND, R, C>(sm, op, ox, oy);
+#pragma unroll
+  for (int it = 0; it < T::IT; ++it) {
+    const int t = tid + it * 256;
+    if (t < T::NE) {
+      sm.b[t] = bv[it];
+      sm.x0[t] = xv[it];
+    }
   }
   __syncthreads();
-  C* cur = s0;
-  C* nxt = s1;
+  tile_inv_diag<KIND, R, C>(sm, op, ox, oy, omega);
+  C* cur = sm.x0;
+  C* nxt = sm.x1;
   int k = 0;
   if (!x0) {
-    for (int t = tid; t < W * H; t += 256) {
-      const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
-      const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
-      s0[t] = in ? omega * sbv[t] / tile_diag<KIND, C>(gi, gj, op) : C(0);
-    }
+    // first sweep from zero is pointwise: x = omega D^{-1} b
     __syncthreads();
+#pragma unroll
+    for (int it = 0; it < T::IT; ++it) {
+      const int t = tid + it * 256;
+      if (t < T::NE) {
+        const C id = KIND == KIND_FINE ? omega / (C(1) + op.a * op.ih2 * C(4)) : sm.idg[KIND == KIND_FINE ? 0 : t];
+        const int gi = ox + t % W, gj = oy + t / W;
+        const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+        sm.x0[t] = in ? id * sm.b[t] : C(0);
+      }
+    }
     k = 1;
   }
+  __syncthreads();
   for (; k < NU; ++k) {
-    for (int t = tid; t < W * H; t += 256) {
-      const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
-      C v = C(0);
-      if (tx > 0 && tx < W - 1 && ty > 0 && ty < H - 1 && gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
-        C d;
-        const C Ax = tile_apply<KIND, C>(cur, t, W, gi, gj, op, d);
-        v = cur[t] + omega * (sbv[t] - Ax) / d;
-      }
-      nxt[t] = v;
-    }
+    tile_sweep<KIND, R, C>(sm, cur, nxt, op, ox, oy, omega);
     __syncthreads();
     C* tmp = cur; cur = nxt; nxt = tmp;
   }
   // residual on the interior of the tile (zero outside the domain)
-  for (int t = tid; t < W * H; t += 256) {
-    const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
-    C v = C(0);
-    if (tx > 0 && tx < W - 1 && ty > 0 && ty < H - 1 && gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
-      C d;
-      v = sbv[t] - tile_apply<KIND, C>(cur, t, W, gi, gj, op, d);
+#pragma unroll
+  for (int it = 0; it < T::IT; ++it) {
+    const int t = tid + it * 256;
+    if (t < T::NE) {
+      const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
+      C v = C(0);
+      if (tx > 0 && tx < W - 1 && ty > 0 && ty < H - 1 && gi >= 0 && gi < nf && gj >= 0 && gj < nf)
+        v = sm.b[t] - tile_Ax<KIND, R, C>(sm, cur, op, t, tx, ty);
+      nxt[t] = v;
     }
-    nxt[t] = v;
   }
   __syncthreads();
   for (int c = tid; c < TCX * TCY; c += 256) {
@@ -416,55 +540,103 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
   }
   // owned fine nodes: [2 I0, 2 (I0 + TCX)) per axis, the last tile to the end
   const int hx = (I0 + TCX >= nc) ? nf : 2 * (I0 + TCX), hy = (J0 + TCY >= nc) ? nf : 2 * (J0 + TCY);
-  for (int t = tid; t < W * H; t += 256) {
-    const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
-    if (gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy) st<TF, C>(xout + inst * sxo + gj * nf + gi, cur[t]);
+#pragma unroll
+  for (int it = 0; it < T::IT; ++it) {
+    const int t = tid + it * 256;
+    const int gi = ox + t % W, gj = oy + t / W;
+    if (t < T::NE && gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy)
+      st<TF, C>(xout + inst * sxo + (int64_t)gj * nf + gi, cur[t]);
   }
 }
 
+// floor(v / 2) for any sign
+__device__ __forceinline__ int floor_half(int v) { return v >= 0 ? v / 2 : -((1 - v) / 2); }
+
 // Up: y = x_in + P e on the tile (with halo NU), NU smoothing sweeps, the
-// owned fine nodes written to xout.
+// owned fine nodes written to xout.  The coarse correction of the tile is
+// staged in LDS; fine node g takes lo = floor((g - 1) / 2) with weight 1
+// (odd g) or lo and lo + 1 with weights 1/2 (even g) along each axis.
 template <int KIND, int NU, class TF, class TE, class C>
 __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_t sxi, const TE* __restrict__ e,
                                               int64_t se, const TF* __restrict__ b, int64_t sb, TF* __restrict__ xout,
-                                              int64_t sxo, LevelOp<C> op, int nc, C omega) {
+                                              int64_t sxo, LevelOp<C> op, int nc, C omega, int gx, int gy) {
   constexpr int R = NU;
-  constexpr int W = 2 * TCX + 1 + 2 * R, H = 2 * TCY + 1 + 2 * R;
-  __shared__ C sbv[W * H], s0[W * H], s1[W * H];
+  using T = Tile<KIND, R, C>;
+  constexpr int W = T::W, H = T::H;
+  constexpr int CW = TCX + R + 3, CH = TCY + R + 3, CNE = CW * CH, CIT = (CNE + 255) / 256;
+  __shared__ T sm;
+  __shared__ C sec[CNE];
   const int tid = threadIdx.x;
   const int nf = op.n;
-  const int I0 = blockIdx.x * TCX, J0 = blockIdx.y * TCY;
-  const int64_t inst = blockIdx.z;
+  const int L = xcd_tile((int)blockIdx.x, (int)gridDim.x);  // grid: gx * gy tiles per block
+  const int I0 = (L % gx) * TCX, J0 = ((L / gx) % gy) * TCY;
+  const int64_t inst = L / (gx * gy);
   const int ox = 2 * I0 - R, oy = 2 * J0 - R;
-  const TE* ei = e + inst * se;
-  for (int t = tid; t < W * H; t += 256) {
-    const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
-    const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
-    const int64_t g = (int64_t)gj * nf + gi;
-    sbv[t] = in ? ld<TF, C>(b + inst * sb + g) : C(0);
-    s0[t] = in ? ld<TF, C>(xin + inst * sxi + g) + prolong_at<2, TE, C>(ei, nc, gi, gj, 0) : C(0);
+  const int cx0 = floor_half(ox - 1), cy0 = floor_half(oy - 1);
+  C bv[T::IT], xv[T::IT], ev[CIT];
+#pragma unroll
+  for (int it = 0; it < T::IT; ++it) {
+    const int t = tid + it * 256, gi = ox + t % W, gj = oy + t / W;
+    const bool in = t < T::NE && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+    const int64_t g = in ? (int64_t)gj * nf + gi : 0;
+    bv[it] = in ? ld<TF, C>(b + inst * sb + g) : C(0);
+    xv[it] = in ? ld<TF, C>(xin + inst * sxi + g) : C(0);
+  }
+#pragma unroll
+  for (int it = 0; it < CIT; ++it) {
+    const int t = tid + it * 256, I = cx0 + t % CW, J = cy0 + t / CW;
+    const bool in = t < CNE && I >= 0 && I < nc && J >= 0 && J < nc;
+    ev[it] = in ? ld<TE, C>(e + inst * se + (int64_t)J * nc + I) : C(0);
+  }
+  tile_stage_op<KIND, R, C>(sm, op, ox, oy);
+#pragma unroll
+  for (int it = 0; it < T::IT; ++it) {
+    const int t = tid + it * 256;
+    if (t < T::NE) {
+      sm.b[t] = bv[it];
+      sm.x1[t] = xv[it];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < CIT; ++it) {
+    const int t = tid + it * 256;
+    if (t < CNE) sec[t] = ev[it];
   }
   __syncthreads();
-  C* cur = s0;
-  C* nxt = s1;
-  for (int k = 0; k < NU; ++k) {
-    for (int t = tid; t < W * H; t += 256) {
-      const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
+  tile_inv_diag<KIND, R, C>(sm, op, ox, oy, omega);
+#pragma unroll
+  for (int it = 0; it < T::IT; ++it) {
+    const int t = tid + it * 256;
+    if (t < T::NE) {
+      const int gi = ox + t % W, gj = oy + t / W;
+      const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
       C v = C(0);
-      if (tx > 0 && tx < W - 1 && ty > 0 && ty < H - 1 && gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
-        C d;
-        const C Ax = tile_apply<KIND, C>(cur, t, W, gi, gj, op, d);
-        v = cur[t] + omega * (sbv[t] - Ax) / d;
+      if (in) {
+        const int li = floor_half(gi - 1), lj = floor_half(gj - 1);
+        const C wi0 = (gi & 1) ? C(1) : C(0.5), wi1 = (gi & 1) ? C(0) : C(0.5);
+        const C wj0 = (gj & 1) ? C(1) : C(0.5), wj1 = (gj & 1) ? C(0) : C(0.5);
+        const int c = (lj - cy0) * CW + (li - cx0);
+        const C pe = wj0 * (wi0 * sec[c] + wi1 * sec[c + 1]) + wj1 * (wi0 * sec[c + CW] + wi1 * sec[c + CW + 1]);
+        v = sm.x1[t] + pe;
       }
-      nxt[t] = v;
+      sm.x0[t] = v;
     }
+  }
+  __syncthreads();
+  C* cur = sm.x0;
+  C* nxt = sm.x1;
+  for (int k = 0; k < NU; ++k) {
+    tile_sweep<KIND, R, C>(sm, cur, nxt, op, ox, oy, omega);
     __syncthreads();
     C* tmp = cur; cur = nxt; nxt = tmp;
   }
   const int hx = (I0 + TCX >= nc) ? nf : 2 * (I0 + TCX), hy = (J0 + TCY >= nc) ? nf : 2 * (J0 + TCY);
-  for (int t = tid; t < W * H; t += 256) {
-    const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
-    if (gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy) st<TF, C>(xout + inst * sxo + gj * nf + gi, cur[t]);
+#pragma unroll
+  for (int it = 0; it < T::IT; ++it) {
+    const int t = tid + it * 256;
+    const int gi = ox + t % W, gj = oy + t / W;
+    if (t < T::NE && gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy)
+      st<TF, C>(xout + inst * sxo + (int64_t)gj * nf + gi, cur[t]);
   }
 }
 
@@ -918,9 +1090,10 @@ hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, in
   const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
   const int nc = h_->lev_n[l + 1];
   const C omega = (C)h_->omega;
-  const dim3 g((unsigned)((nc + TCX - 1) / TCX), (unsigned)((nc + TCY - 1) / TCY), (unsigned)B);
+  const int gx = (nc + TCX - 1) / TCX, gy = (nc + TCY - 1) / TCY;
+  const dim3 g((unsigned)(gx * gy * B));
   const int nu = h_->opts.nu1;
-#define DN(K, NU, TF) hipLaunchKernelGGL((k_down2d<K, NU, TF, TM, C>), g, dim3(256), 0, st_, (const TF*)b.ptr, b.stride, (const TF*)x0, sx0, (TF*)xout.ptr, xout.stride, (TM*)bc.ptr, bc.stride, op, nc, omega)
+#define DN(K, NU, TF) hipLaunchKernelGGL((k_down2d<K, NU, TF, TM, C>), g, dim3(256), 0, st_, (const TF*)b.ptr, b.stride, (const TF*)x0, sx0, (TF*)xout.ptr, xout.stride, (TM*)bc.ptr, bc.stride, op, nc, omega, gx, gy)
 #define DN_NU(K, TF) do { if (nu == 1) DN(K, 1, TF); else if (nu == 2) DN(K, 2, TF); else DN(K, 3, TF); } while (0)
   if (l == 0) {
     if (h_->vark) DN_NU(KIND_FINE_VK, TI); else DN_NU(KIND_FINE, TI);
@@ -937,9 +1110,10 @@ hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec
   const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
   const int nc = h_->lev_n[l + 1];
   const C omega = (C)h_->omega;
-  const dim3 g((unsigned)((nc + TCX - 1) / TCX), (unsigned)((nc + TCY - 1) / TCY), (unsigned)B);
+  const int gx = (nc + TCX - 1) / TCX, gy = (nc + TCY - 1) / TCY;
+  const dim3 g((unsigned)(gx * gy * B));
   const int nu = h_->opts.nu2;
-#define UP(K, NU, TF) hipLaunchKernelGGL((k_up2d<K, NU, TF, TM, C>), g, dim3(256), 0, st_, (const TF*)xin.ptr, xin.stride, (const TM*)ec.ptr, ec.stride, (const TF*)b.ptr, b.stride, (TF*)xout.ptr, xout.stride, op, nc, omega)
+#define UP(K, NU, TF) hipLaunchKernelGGL((k_up2d<K, NU, TF, TM, C>), g, dim3(256), 0, st_, (const TF*)xin.ptr, xin.stride, (const TM*)ec.ptr, ec.stride, (const TF*)b.ptr, b.stride, (TF*)xout.ptr, xout.stride, op, nc, omega, gx, gy)
 #define UP_NU(K, TF) do { if (nu == 1) UP(K, 1, TF); else if (nu == 2) UP(K, 2, TF); else UP(K, 3, TF); } while (0)
   if (l == 0) {
     if (h_->vark) UP_NU(KIND_FINE_VK, TI); else UP_NU(KIND_FINE, TI);

@@ -22,6 +22,9 @@ class Multigrid {
   // strides; B <= nt.
   hipError_t solve(int stage, BVec<TI> x, BVec<const TI> rhs, int B, int cycles);
 
+  // First level solved by the one-workgroup LDS tail (= levels when none).
+  int tail_level() const { return l0_; }
+
  private:
   struct Vec {
     void* ptr;

@@ -186,6 +186,14 @@ hipError_t apply_P_any(aao_problem* h, const double* r, void* z, int k, int cycl
   }
 }
 
+template <class TI, class TM>
+hipError_t apply_mg_typed(aao_problem* h, bool transpose, int stage, int count, int cycles, const void* r, void* z) {
+  Multigrid<TI, TM> mg(h, h->stream, transpose ? h->LT : h->tab.L);
+  const int64_t N = h->N;
+  return mg.solve(stage, BVec<TI>{static_cast<TI*>(z), N}, BVec<const TI>{static_cast<const TI*>(r), N}, count,
+                  cycles);
+}
+
 // Apply P-tilde directly, or by replaying a HIP graph captured on the first
 // call for this (transpose, k, cycles).  The graph reads its input from and
 // writes its output to fixed workspace buffers; the copies in and out run on
@@ -477,6 +485,24 @@ void release_graphs(aao_problem* h) {
   h->graphs.clear();
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
   h->capture_stream = nullptr;
+}
+
+int mg_tail_level(aao_problem* h) {
+  switch (h->opts.precision) {
+    case AAO_PREC_FP64: return Multigrid<double, double>(h, h->stream, h->tab.L).tail_level();
+    case AAO_PREC_FP32: return Multigrid<float, float>(h, h->stream, h->tab.L).tail_level();
+    case AAO_PREC_FP16: return Multigrid<float, __half>(h, h->stream, h->tab.L).tail_level();
+    default: return Multigrid<float, __hip_bfloat16>(h, h->stream, h->tab.L).tail_level();
+  }
+}
+
+hipError_t apply_mg(aao_problem* h, bool transpose, int stage, int count, int cycles, const void* r, void* z) {
+  switch (h->opts.precision) {
+    case AAO_PREC_FP64: return apply_mg_typed<double, double>(h, transpose, stage, count, cycles, r, z);
+    case AAO_PREC_FP32: return apply_mg_typed<float, float>(h, transpose, stage, count, cycles, r, z);
+    case AAO_PREC_FP16: return apply_mg_typed<float, __half>(h, transpose, stage, count, cycles, r, z);
+    default: return apply_mg_typed<float, __hip_bfloat16>(h, transpose, stage, count, cycles, r, z);
+  }
 }
 
 int apply_P(aao_problem* h, const double* r, double* z, int inner_k, int cycles, bool transpose) {

@@ -47,6 +47,18 @@ __device__ __forceinline__ C stencil_K(const T* __restrict__ f, int p, int i, in
   return acc;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
+// XCD b mod 8, each XCD with its own L2).  xcd_tile(b, B) is the logical
+// tile of workgroup b of B such that each XCD walks one contiguous range of
+// logical tiles: tiles that share halo lines (neighbours in the same block)
+// then meet in one L2.  A bijection on [0, B).
+constexpr int NXCD = 8;
+
+__device__ __forceinline__ int xcd_tile(int b, int B) {
+  const int q = B / NXCD, r = B % NXCD, k = b % NXCD;
+  return k * q + (k < r ? k : r) + b / NXCD;
+}
+
 // Diagonal of h^2 K at p.
 template <int DIM, bool VK, class C>
 __device__ __forceinline__ C stencil_K_diag(int p, const Faces<C>& fc) {

@@ -110,3 +110,39 @@ def test_bad_kappa_rejected():
     k[3] = -1.0
     code, _ = _create(abi, lib, n=8, kappa=k)
     assert code == -1
+
+
+def test_apply_mg_arguments_are_checked_on_the_host():
+    abi, lib = _lib()
+    code, h = _create(abi, lib)
+    assert code == 0
+    N, U = ctypes.c_int64(), ctypes.c_int64()
+    lib.aao_sizes(h, ctypes.byref(N), ctypes.byref(U))
+    r, z = ctypes.c_void_p(1 << 20), ctypes.c_void_p((1 << 20) + 8 * N.value)   # adjacent, no overlap
+    desc_nt = 4
+    bad = [(0, -1, 1, 1, r, z), (0, 3, 1, 1, r, z), (2, 0, 1, 1, r, z), (0, 0, 0, 1, r, z),
+           (0, 0, desc_nt + 1, 1, r, z), (0, 0, 1, 0, r, z), (0, 0, 1, 65, r, z),
+           (0, 0, 2, 1, r, z),                       # two blocks: r's second block is z's first
+           (0, 0, 1, 1, r, r), (0, 0, 1, 1, None, z)]
+    for args in bad:
+        assert lib.aao_apply_mg(h, *args) == -1, args
+    assert lib.aao_apply_mg(h, 1, 1, 1, 2, r, z) == -5     # valid, but no workspace yet
+    lib.aao_destroy(h)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 512), (2, 33), (2, 13), (3, 128), (3, 17)])
+def test_mg_levels_match_oracle_hierarchy_sizes(dim, n):
+    """Level sizes follow the oracle's coarsening rule (n_c = floor(n/2) until
+    at most 256 nodes); the tail split needs the device, hence -5 here."""
+    from oracle import multigrid
+    abi, lib = _lib()
+    code, h = _create(abi, lib, dim=dim, n=n, s=1, nt=1)
+    assert code == 0
+    nodes = np.zeros(32, dtype=np.int64)
+    L, t = ctypes.c_int(), ctypes.c_int()
+    assert lib.aao_mg_levels(h, 32, nodes.ctypes.data, ctypes.byref(L), ctypes.byref(t)) == -5
+    sizes = [n]
+    while sizes[-1] ** dim > multigrid.COARSE_MAX and sizes[-1] > 1:
+        sizes.append(multigrid.coarse_size(sizes[-1]))
+    assert list(nodes[: L.value]) == [m ** dim for m in sizes]
+    lib.aao_destroy(h)

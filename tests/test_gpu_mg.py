@@ -1,0 +1,98 @@
+"""GPU parity of the multigrid block solve (aao_apply_mg) against the oracle.
+
+The shifted blocks I + a K of Rana's preconditioner (Sec. 4), a = tau L_ii
+with L the Crout factor of A (or of A^T for the adjoint), are solved by
+`cycles` V-cycles: Galerkin coarse levels down to at most 256 nodes (solved
+exactly), weighted Jacobi with nu1 = nu2 = 2.  The GPU runs the same
+algorithm, so FP64 agrees with the oracle to rounding (1e-12 relative: a few
+hundred roundings through a contraction).  FP32 is held to 2e-5 (unit
+roundoff 6e-8 times the same amplification); with BF16 / FP16 coarse-level
+storage the cycle's output differs from the exact-arithmetic cycle by about
+the 16-bit roundoff times the coarse-correction share, bounded here by
+3e-2 / 4e-3.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import announce, rel_err, require_gpu
+from oracle import allatonce, multigrid, tableau
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _oracle(p, transpose, stage, r_blocks, cycles, nu=2):
+    A = p.A.T if transpose else p.A
+    L, _ = tableau.crout(A)
+    H = multigrid.Hierarchy(p.K(), p.n, p.dim, p.tau * L[stage, stage])
+    omega = 0.8 if p.dim == 2 else 6.0 / 7.0
+    return np.stack([multigrid.solve(H, b, cycles, omega, nu, nu) for b in r_blocks])
+
+
+def _run(hp, r, stage, cycles, transpose):
+    dt = hp.working_dtype()
+    rd = torch.from_numpy(np.ascontiguousarray(r.ravel())).to(dt).cuda()
+    z = hp.apply_mg(rd, stage, cycles=cycles, transpose=transpose)
+    torch.cuda.synchronize()
+    return z.double().cpu().numpy().reshape(r.shape)
+
+
+# exact coarse only (16), grid levels + LDS tail (33, 130), deeper and ragged
+# (300: 300 -> 150 -> 75 -> 37 -> 18; 257 odd), 3D (12, 17)
+CASES = [(2, 16, 2, 2), (2, 33, 3, 3), (2, 130, 3, 2), (2, 300, 2, 2), (2, 257, 1, 2), (3, 12, 2, 2),
+         (3, 17, 3, 2)]
+
+
+@pytest.mark.parametrize("dim,n,s,nt", CASES)
+@pytest.mark.parametrize("transpose", [False, True])
+def test_apply_mg_fp64_matches_oracle(dim, n, s, nt, transpose):
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    p = allatonce.Problem(n, dim, s, nt, 1.0)
+    hp = HeatProblem(dim, n, s, nt, 1.0)
+    rng = np.random.default_rng(7 * n + s)
+    for stage in range(s):
+        cycles = 1 + stage % 2
+        r = rng.standard_normal((nt, p.N))
+        announce("apply_mg fp64", dim, n, s, nt, "transpose", transpose, "stage", stage, "cycles", cycles)
+        z = _run(hp, r, stage, cycles, transpose)
+        ref = _oracle(p, transpose, stage, r, cycles)
+        assert rel_err(z, ref) <= 1e-12, (stage, rel_err(z, ref))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-5), ("fp16", 4e-3), ("bf16", 3e-2)])
+def test_apply_mg_low_precision(precision, tol):
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    dim, n, s, nt = 2, 130, 3, 3
+    p = allatonce.Problem(n, dim, s, nt, 1.0)
+    hp = HeatProblem(dim, n, s, nt, 1.0, precision=precision)
+    rng = np.random.default_rng(11)
+    r = rng.standard_normal((nt, p.N))
+    for stage in range(s):
+        announce("apply_mg", precision, dim, n, s, nt, "stage", stage)
+        z = _run(hp, r.astype(np.float32).astype(np.float64), stage, 2, False)
+        ref = _oracle(p, False, stage, r.astype(np.float32).astype(np.float64), 2)
+        assert rel_err(z, ref) <= tol, (stage, rel_err(z, ref))
+
+
+def test_apply_mg_full_size_sampled_blocks():
+    """512^2, s = 3, nt = 64 (the benchmark's shape), FP32: all 64 blocks in one
+    call; blocks 0, 31 and 63 are checked against the oracle one by one."""
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    dim, n, s, nt = 2, 512, 3, 64
+    p = allatonce.Problem(n, dim, s, nt, 1.0)
+    hp = HeatProblem(dim, n, s, nt, 1.0, precision="fp32", restart=2)
+    rng = np.random.default_rng(12)
+    r = rng.standard_normal((nt, p.N)).astype(np.float32).astype(np.float64)
+    announce("apply_mg fp32 full size", dim, n, s, nt)
+    z = _run(hp, r, 0, 1, False)
+    sample = [0, 31, 63]
+    ref = _oracle(p, False, 0, r[sample], 1)
+    assert rel_err(z[sample], ref) <= 2e-5
+    # blocks are independent: a permuted batch gives permuted results
+    perm = rng.permutation(nt)
+    zp = _run(hp, r[perm], 0, 1, False)
+    assert np.array_equal(zp, z[perm])
