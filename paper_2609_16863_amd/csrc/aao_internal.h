@@ -52,6 +52,7 @@ struct LevelOp {
   C a;             // shift tau * L_ii
   C ih2;           // 1/h^2 (level 0 only)
   const C* tri;    // 6 * n (level >= 1)
+  const C* st9;    // level >= 1, variable kappa (2D): 9 * N Galerkin stencil of K, else null
   Faces<C> faces;  // level 0, variable kappa
 };
 
@@ -107,13 +108,15 @@ struct aao_problem {
   std::vector<double> cinv_host;             // coarsest-level inverses: [transpose][stage] N_c^2 each
   int64_t cinv_N = 0;
   std::vector<double> faces_host;            // 2*dim*N when vark
+  std::vector<double> st9_host;              // Galerkin stencils of K, levels >= 1 (2D, vark)
+  std::vector<size_t> st9_off;               // element offset per level (levels >= 1)
 
   // workspace plan (byte offsets)
   size_t ws_need = 0;
   char* ws = nullptr;
   size_t ws_bytes = 0;
   struct Plan {
-    size_t tri_d, tri_f, faces_d, faces_f, cinv_d, cinv_f;
+    size_t tri_d, tri_f, faces_d, faces_f, cinv_d, cinv_f, st9_d, st9_f;
     size_t outV, outZ, outW, outY;           // outer FGMRES
     size_t gIn, gOut;                        // fixed input/output of the captured P-tilde
     size_t inV, inZ, inW, inX;               // inner GMRES (nt instances)
@@ -149,8 +152,10 @@ namespace aao {
 bool radau_iia(int s, double* A, double* b, double* c);
 void crout_lower(int s, const double* A, double* L);
 void galerkin_1d(int n, int dim, double h, std::vector<int>& sizes, std::vector<std::vector<double>>& tri);
+void galerkin_stencils_2d(const std::vector<int>& sizes, const std::vector<double>& faces, double ih2,
+                          std::vector<std::vector<double>>& st9);
 bool coarse_inverse(int dim, int n, const std::vector<double>& tri, double a, bool fine, double ih2,
-                    const double* faces, std::vector<double>& invT);
+                    const double* faces, const double* st9, std::vector<double>& invT);
 void face_coefficients(int dim, int n, const double* kappa, std::vector<double>& faces);
 
 int status_from_hip(aao_problem* h, hipError_t e, const char* what);

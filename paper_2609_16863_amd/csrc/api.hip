@@ -33,6 +33,8 @@ void plan_workspace(aao_problem* h) {
   P.tri_f = take(h->tri_host.size() * sizeof(float));
   P.cinv_d = take(h->cinv_host.size() * sizeof(double));
   P.cinv_f = take(h->cinv_host.size() * sizeof(float));
+  P.st9_d = take(h->st9_host.size() * sizeof(double));
+  P.st9_f = take(h->st9_host.size() * sizeof(float));
   // faces (2*dim*N) followed by nodal kappa (N)
   P.faces_d = take(h->vark ? (size_t)(2 * h->dim + 1) * N * sizeof(double) : 0);
   P.faces_f = take(h->vark ? (size_t)(2 * h->dim + 1) * N * sizeof(float) : 0);
@@ -188,6 +190,15 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
     h->tri_off[l] = h->tri_host.size();
     h->tri_host.insert(h->tri_host.end(), tri[l].begin(), tri[l].end());
   }
+  std::vector<std::vector<double>> st9;
+  if (h->vark) {
+    aao::galerkin_stencils_2d(h->lev_n, h->faces_host, h->ih2, st9);
+    h->st9_off.assign(h->lev_n.size(), 0);
+    for (size_t l = 1; l < h->lev_n.size(); ++l) {
+      h->st9_off[l] = h->st9_host.size();
+      h->st9_host.insert(h->st9_host.end(), st9[l].begin(), st9[l].end());
+    }
+  }
   // exact inverses of the coarsest level, for the shifts tau L_ii (P-tilde)
   // and tau LT_ii (its transpose)
   {
@@ -198,7 +209,8 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
         const double a = h->tau * (tr ? h->LT : h->tab.L)[i * d->s + i];
         std::vector<double> inv;
         if (!aao::coarse_inverse(d->dim, h->lev_n[lc], tri[lc], a, lc == 0, h->ih2,
-                                 h->vark ? h->faces_host.data() : nullptr, inv)) {
+                                 h->vark ? h->faces_host.data() : nullptr,
+                                 (h->vark && lc > 0) ? st9[lc].data() : nullptr, inv)) {
           delete h;
           return fail(nullptr, AAO_INVALID_ARG, "singular coarsest multigrid level");
         }
@@ -247,6 +259,14 @@ int aao_set_workspace(aao_problem* h, void* dev_ptr, size_t bytes) {
       e = aao::launch_copy_cast<float, double>(reinterpret_cast<float*>(h->ws + h->plan.cinv_f),
                                                reinterpret_cast<const double*>(h->ws + h->plan.cinv_d),
                                                (int64_t)h->cinv_host.size(), h->stream);
+  }
+  if (e == hipSuccess && !h->st9_host.empty()) {
+    e = hipMemcpyAsync(h->ws + h->plan.st9_d, h->st9_host.data(), h->st9_host.size() * sizeof(double),
+                       hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = aao::launch_copy_cast<float, double>(reinterpret_cast<float*>(h->ws + h->plan.st9_f),
+                                               reinterpret_cast<const double*>(h->ws + h->plan.st9_d),
+                                               (int64_t)h->st9_host.size(), h->stream);
   }
   if (e == hipSuccess && h->vark) {
     const size_t nf = h->faces_host.size();

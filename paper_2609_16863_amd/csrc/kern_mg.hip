@@ -18,7 +18,11 @@ namespace aao {
 namespace {
 
 constexpr int TPB = 256;
-enum { KIND_FINE = 0, KIND_FINE_VK = 1, KIND_TENSOR = 2 };
+// KIND_TENSOR: Galerkin level; its K part comes from the 1D factors, or from
+// the stored 9-point stencil op.st9 when that is set (2D, variable kappa).
+// KIND_STENCIL9: the same level in the LDS-tiled kernels, which keep the
+// stencil coefficients of their nodes in registers.
+enum { KIND_FINE = 0, KIND_FINE_VK = 1, KIND_TENSOR = 2, KIND_STENCIL9 = 3 };
 
 template <class C>
 struct Tri3 {
@@ -42,6 +46,7 @@ __device__ __forceinline__ C level_diag(const LevelOp<C>& op, int p, int i, int 
   if (KIND == KIND_FINE) return C(1) + op.a * op.ih2 * C(2 * DIM);
   if (KIND == KIND_FINE_VK) return C(1) + op.a * op.ih2 * stencil_K_diag<DIM, true, C>(p, op.faces);
   const Tri3<C> ri = tri_row(op.tri, op.n, i), rj = tri_row(op.tri, op.n, j);
+  if (DIM == 2 && op.st9) return ri.m[1] * rj.m[1] + op.a * op.st9[4 * op.N + p];
   if (DIM == 2) return ri.m[1] * rj.m[1] + op.a * (ri.t[1] * rj.m[1] + ri.m[1] * rj.t[1]);
   const Tri3<C> rk = tri_row(op.tri, op.n, k);
   return ri.m[1] * rj.m[1] * rk.m[1] +
@@ -79,6 +84,24 @@ __device__ __forceinline__ void level_apply(const T* __restrict__ x, const Level
     }
   };
   C acc = C(0);
+  if (DIM == 2 && op.st9) {
+    // M(x)M from the factors plus a times the stored stencil of K
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int jj = j + dj;
+      if (jj < 0 || jj >= n) continue;
+#pragma unroll
+      for (int di = -1; di <= 1; ++di) {
+        const int ii = i + di;
+        if (ii < 0 || ii >= n) continue;
+        const C coef = rj.m[dj + 1] * ri.m[di + 1] + op.a * op.st9[((dj + 1) * 3 + di + 1) * op.N + p];
+        acc += coef * ld<T, C>(x + p + dj * n + di);
+      }
+    }
+    Ax = acc;
+    diag = ri.m[1] * rj.m[1] + op.a * op.st9[4 * op.N + p];
+    return;
+  }
   if (DIM == 2) {
 #pragma unroll
     for (int dj = -1; dj <= 1; ++dj) {
@@ -317,13 +340,37 @@ template <int KIND, int R, class C>
 struct Tile {
   static constexpr int W = 2 * TCX + 1 + 2 * R, H = 2 * TCY + 1 + 2 * R, NE = W * H;
   static constexpr int IT = (NE + 255) / 256;
-  static constexpr bool VK = KIND == KIND_FINE_VK, TEN = KIND == KIND_TENSOR;
+  static constexpr bool VK = KIND == KIND_FINE_VK, TEN = KIND == KIND_TENSOR, S9 = KIND == KIND_STENCIL9;
   C b[NE], x0[NE], x1[NE];
   C idg[KIND == KIND_FINE ? 1 : NE];
   C f[VK ? 4 * NE : 1];
-  C cx[TEN ? 6 * W : 1];  // per column: (M + a T)(i, i+d), M(i, i+d), d = -1, 0, 1
-  C cy[TEN ? 6 * H : 1];  // per row:    M(j, j+d), a T(j, j+d)
+  C cx[TEN ? 6 * W : (S9 ? 3 * W : 1)];  // per column: (M + a T)(i, i+d), M(i, i+d), d = -1, 0, 1 (S9: M only)
+  C cy[TEN ? 6 * H : (S9 ? 3 * H : 1)];  // per row:    M(j, j+d), a T(j, j+d) (S9: M only)
 };
+
+// Stencil coefficients (times a) of the nodes a thread sweeps, for
+// KIND_STENCIL9: element it of the thread is tile node threadIdx.x + 256 it.
+template <int KIND, int IT, class C>
+struct Coef9 {
+  C v[IT][KIND == KIND_STENCIL9 ? 9 : 1];
+};
+
+template <int KIND, int R, class C>
+__device__ __forceinline__ void tile_load_coef(Coef9<KIND, Tile<KIND, R, C>::IT, C>& k9, const LevelOp<C>& op, int ox,
+                                               int oy) {
+  using T = Tile<KIND, R, C>;
+  if constexpr (T::S9) {
+    const int n = op.n;
+#pragma unroll
+    for (int it = 0; it < T::IT; ++it) {
+      const int t = threadIdx.x + it * 256, gi = ox + t % T::W, gj = oy + t / T::W;
+      const bool in = t < T::NE && gi >= 0 && gi < n && gj >= 0 && gj < n;
+      const int64_t g = in ? (int64_t)gj * n + gi : 0;
+#pragma unroll
+      for (int d = 0; d < 9; ++d) k9.v[it][d] = in ? op.a * op.st9[d * op.N + g] : C(0);
+    }
+  }
+}
 
 // Stage the operator of the tile whose origin is (ox, oy) into LDS.  Loads
 // only; the caller synchronizes.
@@ -354,6 +401,17 @@ __device__ __forceinline__ void tile_stage_op(Tile<KIND, R, C>& sm, const LevelO
       }
     }
   }
+  if constexpr (T::S9) {
+    for (int t = tid; t < 3 * W + 3 * H; t += 256) {
+      if (t < 3 * W) {
+        const int d = t / W, c = t % W, gi = ox + c;
+        sm.cx[d * W + c] = (gi >= 0 && gi < n) ? op.tri[d * n + gi] : C(0);
+      } else {
+        const int u = t - 3 * W, d = u / H, r = u % H, gj = oy + r;
+        sm.cy[d * H + r] = (gj >= 0 && gj < n) ? op.tri[d * n + gj] : C(0);
+      }
+    }
+  }
   if constexpr (T::TEN) {
     // columns: 6 W values, rows: 6 H values (W, H < 256 for R <= 4)
     for (int t = tid; t < 3 * W + 3 * H; t += 256) {
@@ -375,9 +433,12 @@ __device__ __forceinline__ void tile_stage_op(Tile<KIND, R, C>& sm, const LevelO
 
 // Diagonal of the level operator at tile node (tx, ty) from the staged data.
 template <int KIND, int R, class C>
-__device__ __forceinline__ C tile_diag(const Tile<KIND, R, C>& sm, const LevelOp<C>& op, int t, int tx, int ty) {
+__device__ __forceinline__ C tile_diag(const Tile<KIND, R, C>& sm, const LevelOp<C>& op, int t, int tx, int ty,
+                                       const C* kc) {
   using T = Tile<KIND, R, C>;
   if constexpr (KIND == KIND_FINE) return C(1) + op.a * op.ih2 * C(4);
+  else if constexpr (T::S9)
+    return sm.cy[1 * T::H + ty] * sm.cx[1 * T::W + tx] + kc[4];
   else if constexpr (T::VK)
     return C(1) + sm.f[t] + sm.f[T::NE + t] + sm.f[2 * T::NE + t] + sm.f[3 * T::NE + t];
   else
@@ -388,11 +449,20 @@ __device__ __forceinline__ C tile_diag(const Tile<KIND, R, C>& sm, const LevelOp
 // (A x)_t for an interior tile node (all 8 neighbours inside the tile).
 template <int KIND, int R, class C>
 __device__ __forceinline__ C tile_Ax(const Tile<KIND, R, C>& sm, const C* __restrict__ x, const LevelOp<C>& op, int t,
-                                     int tx, int ty) {
+                                     int tx, int ty, const C* kc) {
   using T = Tile<KIND, R, C>;
   constexpr int W = T::W;
   const C c = x[t];
-  if constexpr (KIND == KIND_FINE) {
+  if constexpr (T::S9) {
+    C acc = C(0);
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+      for (int di = -1; di <= 1; ++di)
+        acc += (sm.cy[(dj + 1) * T::H + ty] * sm.cx[(di + 1) * W + tx] + kc[(dj + 1) * 3 + di + 1]) *
+               x[t + dj * W + di];
+    return acc;
+  } else if constexpr (KIND == KIND_FINE) {
     return c + op.a * op.ih2 * (C(4) * c - x[t - 1] - x[t + 1] - x[t - W] - x[t + W]);
   } else if constexpr (T::VK) {
     return c + sm.f[t] * (c - x[t - 1]) + sm.f[T::NE + t] * (c - x[t + 1]) + sm.f[2 * T::NE + t] * (c - x[t - W]) +
@@ -419,7 +489,7 @@ __device__ __forceinline__ C tile_Ax(const Tile<KIND, R, C>& sm, const C* __rest
 // out-of-domain nodes stay zero).
 template <int KIND, int R, class C>
 __device__ __forceinline__ void tile_sweep(Tile<KIND, R, C>& sm, const C* cur, C* nxt, const LevelOp<C>& op, int ox,
-                                           int oy, C omega) {
+                                           int oy, C omega, const Coef9<KIND, Tile<KIND, R, C>::IT, C>& k9) {
   using T = Tile<KIND, R, C>;
   constexpr int W = T::W, H = T::H;
   const int n = op.n;
@@ -431,7 +501,7 @@ __device__ __forceinline__ void tile_sweep(Tile<KIND, R, C>& sm, const C* cur, C
       C v = C(0);
       if (tx > 0 && tx < W - 1 && ty > 0 && ty < H - 1 && gi >= 0 && gi < n && gj >= 0 && gj < n) {
         const C id = KIND == KIND_FINE ? omega / (C(1) + op.a * op.ih2 * C(4)) : sm.idg[KIND == KIND_FINE ? 0 : t];
-        v = cur[t] + id * (sm.b[t] - tile_Ax<KIND, R, C>(sm, cur, op, t, tx, ty));
+        v = cur[t] + id * (sm.b[t] - tile_Ax<KIND, R, C>(sm, cur, op, t, tx, ty, k9.v[it]));
       }
       nxt[t] = v;
     }
@@ -440,7 +510,8 @@ __device__ __forceinline__ void tile_sweep(Tile<KIND, R, C>& sm, const C* cur, C
 
 // omega / diagonal for every in-domain tile node (after the operator is staged).
 template <int KIND, int R, class C>
-__device__ __forceinline__ void tile_inv_diag(Tile<KIND, R, C>& sm, const LevelOp<C>& op, int ox, int oy, C omega) {
+__device__ __forceinline__ void tile_inv_diag(Tile<KIND, R, C>& sm, const LevelOp<C>& op, int ox, int oy, C omega,
+                                              const Coef9<KIND, Tile<KIND, R, C>::IT, C>& k9) {
   using T = Tile<KIND, R, C>;
   if constexpr (KIND != KIND_FINE) {
 #pragma unroll
@@ -449,7 +520,7 @@ __device__ __forceinline__ void tile_inv_diag(Tile<KIND, R, C>& sm, const LevelO
       if (t < T::NE) {
         const int tx = t % T::W, ty = t / T::W, gi = ox + tx, gj = oy + ty;
         const bool in = gi >= 0 && gi < op.n && gj >= 0 && gj < op.n;
-        sm.idg[t] = in ? omega / tile_diag<KIND, R, C>(sm, op, t, tx, ty) : C(0);
+        sm.idg[t] = in ? omega / tile_diag<KIND, R, C>(sm, op, t, tx, ty, k9.v[it]) : C(0);
       }
     }
   }
@@ -473,6 +544,8 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
   const int ox = 2 * I0 - R, oy = 2 * J0 - R;
   const TF* bi = b + inst * sb;
   const TF* xi = x0 ? x0 + inst * sx0 : nullptr;
+  Coef9<KIND, T::IT, C> k9;
+  tile_load_coef<KIND, R, C>(k9, op, ox, oy);
   C bv[T::IT], xv[T::IT];
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
@@ -492,7 +565,7 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
     }
   }
   __syncthreads();
-  tile_inv_diag<KIND, R, C>(sm, op, ox, oy, omega);
+  tile_inv_diag<KIND, R, C>(sm, op, ox, oy, omega, k9);
   C* cur = sm.x0;
   C* nxt = sm.x1;
   int k = 0;
@@ -513,7 +586,7 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
   }
   __syncthreads();
   for (; k < NU; ++k) {
-    tile_sweep<KIND, R, C>(sm, cur, nxt, op, ox, oy, omega);
+    tile_sweep<KIND, R, C>(sm, cur, nxt, op, ox, oy, omega, k9);
     __syncthreads();
     C* tmp = cur; cur = nxt; nxt = tmp;
   }
@@ -525,7 +598,7 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
       const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
       C v = C(0);
       if (tx > 0 && tx < W - 1 && ty > 0 && ty < H - 1 && gi >= 0 && gi < nf && gj >= 0 && gj < nf)
-        v = sm.b[t] - tile_Ax<KIND, R, C>(sm, cur, op, t, tx, ty);
+        v = sm.b[t] - tile_Ax<KIND, R, C>(sm, cur, op, t, tx, ty, k9.v[it]);
       nxt[t] = v;
     }
   }
@@ -573,6 +646,8 @@ __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_
   const int64_t inst = L / (gx * gy);
   const int ox = 2 * I0 - R, oy = 2 * J0 - R;
   const int cx0 = floor_half(ox - 1), cy0 = floor_half(oy - 1);
+  Coef9<KIND, T::IT, C> k9;
+  tile_load_coef<KIND, R, C>(k9, op, ox, oy);
   C bv[T::IT], xv[T::IT], ev[CIT];
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
@@ -603,7 +678,7 @@ __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_
     if (t < CNE) sec[t] = ev[it];
   }
   __syncthreads();
-  tile_inv_diag<KIND, R, C>(sm, op, ox, oy, omega);
+  tile_inv_diag<KIND, R, C>(sm, op, ox, oy, omega, k9);
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
     const int t = tid + it * 256;
@@ -626,7 +701,7 @@ __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_
   C* cur = sm.x0;
   C* nxt = sm.x1;
   for (int k = 0; k < NU; ++k) {
-    tile_sweep<KIND, R, C>(sm, cur, nxt, op, ox, oy, omega);
+    tile_sweep<KIND, R, C>(sm, cur, nxt, op, ox, oy, omega, k9);
     __syncthreads();
     C* tmp = cur; cur = nxt; nxt = tmp;
   }
@@ -732,6 +807,30 @@ __device__ __forceinline__ void tail_tensor(const C* __restrict__ x, const C* __
   d = mi[1] * mj[1] + a * (ti[1] * mj[1] + mi[1] * tj[1]);
 }
 
+// (A x)_p and A_pp for a 2D Galerkin level with a stored stencil of K: the
+// M(x)M part from the LDS factor copy, the stencil from global memory.
+template <class C>
+__device__ __forceinline__ void tail_stencil9(const C* __restrict__ x, const C* __restrict__ tri, const LevelOp<C>& op,
+                                              int p, int i, int j, C& Ax, C& d) {
+  const int n = op.n;
+  C acc = C(0);
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj) {
+    const int jj = j + dj;
+    if (jj < 0 || jj >= n) continue;
+    const C mj = tri[(dj + 1) * n + j];
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      const int ii = i + di;
+      if (ii < 0 || ii >= n) continue;
+      const C coef = mj * tri[(di + 1) * n + i] + op.a * op.st9[((dj + 1) * 3 + di + 1) * op.N + p];
+      acc += coef * x[p + dj * n + di];
+    }
+  }
+  Ax = acc;
+  d = tri[n + i] * tri[n + j] + op.a * op.st9[4 * op.N + p];
+}
+
 // Level t of the tail: tensor Galerkin, or the fine operator when the tail
 // starts at level 0.
 template <bool VK, class C>
@@ -740,6 +839,8 @@ __device__ __forceinline__ void tail_op(const TailArgs<C>& ta, const C* sm, int 
   if (t == 0 && ta.first_fine) {
     if (VK) level_apply<2, KIND_FINE_VK, C, C>(x, ta.op[0], p, i, j, 0, Ax, d);
     else level_apply<2, KIND_FINE, C, C>(x, ta.op[0], p, i, j, 0, Ax, d);
+  } else if (ta.op[t].st9) {
+    tail_stencil9<C>(x, sm + ta.toff[t], ta.op[t], p, i, j, Ax, d);
   } else {
     tail_tensor<C>(x, sm + ta.toff[t], ta.op[t].n, ta.op[t].a, p, i, j, Ax, d);
   }
@@ -920,6 +1021,11 @@ LevelOp<C> make_op(const aao_problem* h, int l, double a) {
   const bool dbl = sizeof(C) == 8;
   const char* tri = h->ws + (dbl ? h->plan.tri_d : h->plan.tri_f);
   op.tri = reinterpret_cast<const C*>(tri) + h->tri_off[l];
+  op.st9 = nullptr;
+  if (h->vark && l > 0) {
+    const char* st9 = h->ws + (dbl ? h->plan.st9_d : h->plan.st9_f);
+    op.st9 = reinterpret_cast<const C*>(st9) + h->st9_off[l];
+  }
   if (h->vark && l == 0) {
     const C* base = reinterpret_cast<const C*>(h->ws + (dbl ? h->plan.faces_d : h->plan.faces_f));
     for (int d = 0; d < h->dim; ++d) {
@@ -1098,7 +1204,7 @@ hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, in
   if (l == 0) {
     if (h_->vark) DN_NU(KIND_FINE_VK, TI); else DN_NU(KIND_FINE, TI);
   } else {
-    DN_NU(KIND_TENSOR, TM);
+    if (h_->vark) DN_NU(KIND_STENCIL9, TM); else DN_NU(KIND_TENSOR, TM);
   }
 #undef DN_NU
 #undef DN
@@ -1118,7 +1224,7 @@ hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec
   if (l == 0) {
     if (h_->vark) UP_NU(KIND_FINE_VK, TI); else UP_NU(KIND_FINE, TI);
   } else {
-    UP_NU(KIND_TENSOR, TM);
+    if (h_->vark) UP_NU(KIND_STENCIL9, TM); else UP_NU(KIND_TENSOR, TM);
   }
 #undef UP_NU
 #undef UP

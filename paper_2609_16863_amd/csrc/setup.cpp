@@ -182,14 +182,88 @@ void galerkin_1d(int n, int dim, double h, std::vector<int>& sizes, std::vector<
   }
 }
 
+// Galerkin stencils of K on the coarse levels for variable diffusivity (2D).
+// K_0 is the 5-point operator with the face diffusivities (scaled by 1/h^2);
+// K_{l+1} = P^T K_l P / 4 with the tensor-linear interpolation P of
+// galerkin_1d (coarse node J at fine 2J+1, weights 1/2, 1, 1/2), so level l
+// applies I-part M_l (x) M_l (from the 1D factors) plus a K_l.  A 9-point
+// stencil stays 9-point under this product.  st9[l] (l >= 1) holds 9 N_l
+// values: entry (dj+1)*3 + (di+1) of node p at [((dj+1)*3 + di+1) N_l + p];
+// st9[0] is left empty (the fine level applies the faces directly).
+void galerkin_stencils_2d(const std::vector<int>& sizes, const std::vector<double>& faces, double ih2,
+                          std::vector<std::vector<double>>& st9) {
+  const int L = (int)sizes.size();
+  st9.assign(L, {});
+  int n = sizes[0];
+  int64_t N = (int64_t)n * n;
+  std::vector<double> K((size_t)9 * N, 0.0);
+  for (int64_t p = 0; p < N; ++p) {
+    const int i = (int)(p % n), j = (int)(p / n);
+    const double m0 = faces[p], p0 = faces[N + p], m1 = faces[2 * N + p], p1 = faces[3 * N + p];
+    K[4 * N + p] = ih2 * (m0 + p0 + m1 + p1);
+    if (i > 0) K[3 * N + p] = -ih2 * m0;
+    if (i + 1 < n) K[5 * N + p] = -ih2 * p0;
+    if (j > 0) K[1 * N + p] = -ih2 * m1;
+    if (j + 1 < n) K[7 * N + p] = -ih2 * p1;
+  }
+  // coarse nodes whose interpolation reaches fine index i, with weights
+  auto coarse_of = [](int i, int nc, int* I, double* w) {
+    if (i & 1) {
+      I[0] = (i - 1) / 2;
+      w[0] = 1.0;
+      return 1;
+    }
+    int c = 0;
+    if (i / 2 - 1 >= 0) { I[c] = i / 2 - 1; w[c] = 0.5; ++c; }
+    if (i / 2 < nc) { I[c] = i / 2; w[c] = 0.5; ++c; }
+    return c;
+  };
+  for (int l = 1; l < L; ++l) {
+    const int nc = sizes[l];
+    const int64_t Nc = (int64_t)nc * nc;
+    std::vector<double> Kc((size_t)9 * Nc, 0.0);
+    for (int64_t f = 0; f < N; ++f) {
+      const int i = (int)(f % n), j = (int)(f / n);
+      int Ix[2], Jy[2];
+      double wx[2], wy[2];
+      const int cxn = coarse_of(i, nc, Ix, wx), cyn = coarse_of(j, nc, Jy, wy);
+      if (cxn == 0 || cyn == 0) continue;
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+          const double kv = K[(size_t)((dj + 1) * 3 + di + 1) * N + f];
+          if (kv == 0.0) continue;
+          const int gi = i + di, gj = j + dj;
+          int Gx[2], Gy[2];
+          double gx[2], gy[2];
+          const int gxn = coarse_of(gi, nc, Gx, gx), gyn = coarse_of(gj, nc, Gy, gy);
+          for (int a = 0; a < cyn; ++a)
+            for (int b = 0; b < cxn; ++b) {
+              const int64_t C = (int64_t)Jy[a] * nc + Ix[b];
+              const double wf = 0.25 * wy[a] * wx[b] * kv;
+              for (int c = 0; c < gyn; ++c)
+                for (int e = 0; e < gxn; ++e) {
+                  const int dJ = Gy[c] - Jy[a], dI = Gx[e] - Ix[b];
+                  Kc[(size_t)((dJ + 1) * 3 + dI + 1) * Nc + C] += wf * gy[c] * gx[e];
+                }
+            }
+        }
+    }
+    st9[l] = Kc;
+    K.swap(Kc);
+    n = nc;
+    N = Nc;
+  }
+}
+
 // Dense inverse of the coarsest level's operator, stored transposed
 // (invT[c * Nc + r] = (A^{-1})_{rc}) so that threads reading consecutive rows
 // read consecutive addresses.  The operator is the tensor Galerkin form
 // M(x)M(x..) + a sum T(x)M.. built from the level's 1D factors; when the
 // coarsest level is the fine level it is I + a K with the face diffusivities
-// (faces may be null for kappa = 1).
+// (faces may be null for kappa = 1); with a Galerkin stencil st9 of K (2D,
+// variable kappa) it is M(x)M + a K.
 bool coarse_inverse(int dim, int n, const std::vector<double>& tri, double a, bool fine, double ih2,
-                    const double* faces, std::vector<double>& invT) {
+                    const double* faces, const double* st9, std::vector<double>& invT) {
   int N = 1;
   for (int d = 0; d < dim; ++d) N *= n;
   std::vector<double> A((size_t)N * N, 0.0);
@@ -224,6 +298,9 @@ bool coarse_inverse(int dim, int n, const std::vector<double>& tri, double a, bo
           const double f = faces ? faces[(size_t)(2 * d + (off[d] > 0 ? 1 : 0)) * N + p] : 1.0;
           v = -a * ih2 * f;
         }
+      } else if (st9) {      // 2D Galerkin level with a stencil for K
+        const double mm = m1(1 + off[0], c[0]) * m1(1 + off[1], c[1]);
+        v = mm + a * st9[(size_t)((off[1] + 1) * 3 + off[0] + 1) * N + p];
       } else {
         double mm = 1.0, sumT = 0.0;
         for (int d = 0; d < dim; ++d) mm *= m1(1 + off[d], c[d]);

@@ -96,3 +96,40 @@ def test_apply_mg_full_size_sampled_blocks():
     perm = rng.permutation(nt)
     zp = _run(hp, r[perm], 0, 1, False)
     assert np.array_equal(zp, z[perm])
+
+
+# Variable diffusivity: coarse levels are the Galerkin products R A P of the
+# face-coefficient operator (9-point stencils), as in the oracle hierarchy.
+# 72: tiled stencil level + tail stencil levels; 130: several tiled levels;
+# nu = 4 runs the separate (untiled) smoothing kernels.
+@pytest.mark.parametrize("n,s,nt,nu", [(20, 2, 2, 2), (72, 3, 2, 2), (130, 2, 2, 2), (72, 2, 2, 4)])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_apply_mg_variable_kappa_fp64(n, s, nt, nu, transpose):
+    require_gpu()
+    import heat_inputs
+    from paper_2609_16863_amd import HeatProblem
+    rng = np.random.default_rng(31 * n + nu)
+    kappa = heat_inputs.lognormal_kappa(rng, n, 2)
+    p = allatonce.Problem(n, 2, s, nt, 1.0, kappa=kappa)
+    hp = HeatProblem(2, n, s, nt, 1.0, kappa=kappa, nu1=nu, nu2=nu)
+    for stage in range(s):
+        r = rng.standard_normal((nt, p.N))
+        announce("apply_mg vk fp64", n, s, nt, "nu", nu, "transpose", transpose, "stage", stage)
+        z = _run(hp, r, stage, 2, transpose)
+        ref = _oracle(p, transpose, stage, r, 2, nu=nu)
+        assert rel_err(z, ref) <= 1e-12, (stage, rel_err(z, ref))
+
+
+def test_constant_kappa_array_matches_kappa_one():
+    """kappa = 1 passed as an array takes the face/stencil code path; its
+    Galerkin stencils equal the tensor form, so the results agree to rounding."""
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    n, s, nt = 72, 2, 2
+    hp1 = HeatProblem(2, n, s, nt, 1.0)
+    hpk = HeatProblem(2, n, s, nt, 1.0, kappa=np.ones(n * n))
+    r = np.random.default_rng(5).standard_normal((nt, n * n))
+    announce("apply_mg kappa array vs none", n)
+    a = _run(hp1, r, 1, 2, False)
+    b = _run(hpk, r, 1, 2, False)
+    assert rel_err(b, a) <= 1e-13

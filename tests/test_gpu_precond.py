@@ -41,6 +41,25 @@ def test_apply_P_fp64_matches_oracle(dim, n, s, nt):
     assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("n,s,nt", [(40, 2, 3), (72, 3, 2)])
+def test_apply_P_variable_kappa_fp64_matches_oracle(n, s, nt):
+    """Lognormal patch diffusivity: face coefficients on the fine level,
+    Galerkin 9-point stencils on the coarse levels, as in the oracle."""
+    require_gpu()
+    import heat_inputs
+    from paper_2609_16863_amd import HeatProblem
+    rng = np.random.default_rng(17 + n)
+    kappa = heat_inputs.lognormal_kappa(rng, n, 2)
+    p = allatonce.Problem(n, 2, s, nt, 1.0, kappa=kappa)
+    hp = HeatProblem(2, n, s, nt, 1.0, kappa=kappa, nu1=2, nu2=2)
+    ops = precond.StageOps(p, inner_k=3, cycles=1, nu1=2, nu2=2)
+    r = rng.standard_normal(p.U)
+    announce("apply_P vk fp64", n, s, nt)
+    z = to_host(hp.apply_P(to_dev(r)))
+    ref = precond.apply_preconditioner(ops, r)
+    assert rel_err(z, ref) <= 1e-10
+
+
 @pytest.mark.parametrize("precision,tol", [("fp32", 2e-4), ("bf16", 5e-2), ("fp16", 2e-2)])
 def test_apply_P_low_precision_close_to_fp64_oracle(precision, tol):
     require_gpu()
