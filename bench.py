@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="heat2d_n512_s3_nt64")
     ap.add_argument("--mixed", default="fp32", choices=["fp32", "bf16", "fp16"])
-    ap.add_argument("--inner-k", type=int, default=3)
+    ap.add_argument("--inner-k", type=int, default=4)
     ap.add_argument("--cycles", type=int, default=1)
     ap.add_argument("--nu", type=int, default=2)
     ap.add_argument("--tail-max", type=int, default=0,

@@ -24,5 +24,5 @@ coordinates ((i+1) h, ...), h = 1/(n+1).
 from .generators import (  # noqa: F401
     WORKLOADS, Workload, nodes, sin_product, mms_source, bump_source,
     smooth_initial, lognormal_kappa, workload_inputs, batch_problem_specs,
-    gradient_problem_specs,
+    gradient_problem_specs, spec_inputs, spec_target_inputs,
 )

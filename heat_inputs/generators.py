@@ -135,3 +135,21 @@ def gradient_problem_specs(count=8, seed=1004, target_seed=2004):
     """Batch of 2D problems for the gradient check (n=256, s=2, nt=64)."""
     return [{"n": 256, "s": 2, "nt": 64, "T": 1.0, "seed": seed * 1000 + i,
              "target_seed": target_seed * 1000 + i} for i in range(count)]
+
+
+def spec_inputs(spec, times, dim=2):
+    """(kappa, f, u0) of one batch/gradient problem spec, from its seed:
+    lognormal patch diffusivity, bump source at the stage ``times`` (shape
+    (nt, s)) and smooth initial condition, drawn in that order."""
+    rng = np.random.default_rng(spec["seed"])
+    kappa = lognormal_kappa(rng, spec["n"], dim).ravel()
+    f = bump_source(rng, spec["n"], dim, np.asarray(times, float))
+    u0 = smooth_initial(rng, spec["n"], dim)
+    return kappa, f, u0
+
+
+def spec_target_inputs(spec, times, dim=2):
+    """(f, u0) generating the tracking target of a gradient problem spec
+    (its ``target_seed``; the diffusivity is the problem's own)."""
+    rng = np.random.default_rng(spec["target_seed"])
+    return bump_source(rng, spec["n"], dim, np.asarray(times, float)), smooth_initial(rng, spec["n"], dim)

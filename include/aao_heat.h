@@ -211,6 +211,73 @@ int aao_grad_logkappa(aao_problem* h, const double* x, const double* lam, double
  * NULL).  Valid until the next call on h. */
 const char* aao_last_error(const aao_problem* h);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent problems
+ *
+ * Many all-at-once problems (each with its own grid, stages, steps and
+ * diffusivity; the same options) are handled as one batch: batch vectors
+ * are single device buffers holding the problems' vectors back to back, at
+ * the offsets reported by aao_batch_offsets.  A batch call runs the
+ * problems on `streams` HIP streams driven by host threads, largest problem
+ * first, so that independent solves overlap on the device (Sec. 5: the
+ * method's time-parallel phase is one batch dimension; separate problems
+ * are another).  Batch calls start after the work already queued on the
+ * batch's stream (aao_batch_set_stream; default: the null stream), return
+ * once every problem is done, and leave that stream waiting for them.
+ * ------------------------------------------------------------------------ */
+typedef struct aao_batch aao_batch;   /* opaque */
+
+/* Create a batch of `count` problems described by descs[0..count-1], all
+ * with the options *opts (NULL: defaults), to be run on `streams` streams
+ * (1..16).  Errors as aao_create_problem, with the failing problem named in
+ * aao_batch_last_error(NULL). */
+int aao_create_batch(const aao_desc* descs, int count, const aao_opts* opts, int streams, aao_batch** out);
+
+/* Number of problems in the batch (0 for NULL). */
+int aao_batch_count(const aao_batch* b);
+
+/* Prefix offsets (count + 1 values each, any pointer may be NULL): problem
+ * i's unknowns occupy [unknowns[i], unknowns[i+1]) of a batch vector (U_i
+ * values), its nodes [nodes[i], nodes[i+1]) of a batch node field (u0,
+ * log-kappa gradients; N_i values) and its forcing values [forcing[i],
+ * forcing[i+1]) of a batch forcing buffer (nt_i s_i N_i values). */
+int aao_batch_offsets(const aao_batch* b, int64_t* unknowns, int64_t* nodes, int64_t* forcing);
+
+/* Device bytes of the batch workspace (the problems' workspaces back to
+ * back), and attaching it (256-byte aligned, caller-owned, device current
+ * at this call is the batch's device).  Creates the batch's streams. */
+int aao_batch_workspace_size(const aao_batch* b, size_t* bytes);
+int aao_batch_set_workspace(aao_batch* b, void* dev_ptr, size_t bytes);
+
+/* Stream the batch calls are ordered after (and that waits for them). */
+int aao_batch_set_stream(aao_batch* b, void* stream);
+
+/* Borrow problem i's handle (owned by the batch; valid until
+ * aao_batch_destroy), e.g. for its tableau or single-problem calls. */
+int aao_batch_problem(aao_batch* b, int i, aao_problem** h);
+
+/* aao_assemble_rhs for every problem: f, u0, rhs are batch buffers laid out
+ * by the forcing, node and unknown offsets. */
+int aao_batch_assemble_rhs(aao_batch* b, const double* f, const double* u0, double* rhs);
+
+/* aao_solve / aao_solve_adjoint for every problem; rhs and x (g and lam) are
+ * batch vectors; stats: NULL or count entries in problem order.  Returns
+ * AAO_OK when every problem converged, AAO_NOT_CONVERGED when some did not,
+ * else the first error (aao_batch_last_error names the problem). */
+int aao_batch_solve(aao_batch* b, const double* rhs, double* x, aao_stats* stats);
+int aao_batch_solve_adjoint(aao_batch* b, const double* g, double* lam, aao_stats* stats);
+
+/* aao_grad_logkappa for every problem: x, lam batch vectors; grad a batch
+ * node field. */
+int aao_batch_grad_logkappa(aao_batch* b, const double* x, const double* lam, double* grad);
+
+/* Message of the last failure on b (or of the last failed batch creation if
+ * b is NULL). */
+const char* aao_batch_last_error(const aao_batch* b);
+
+/* Free the batch and its problems (not the caller's workspace). */
+int aao_batch_destroy(aao_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,4 +7,4 @@ stage preconditioner, geometric-multigrid V-cycles on the shifted blocks),
 plus the transposed (adjoint) solve.  All arithmetic runs in hand-written HIP
 kernels for gfx950 behind the C ABI of include/aao_heat.h.
 """
-from .binding import AAOError, HeatProblem  # noqa: F401
+from .binding import AAOError, HeatBatch, HeatProblem  # noqa: F401

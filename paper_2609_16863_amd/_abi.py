@@ -53,6 +53,19 @@ SIGNATURES = {
     "aao_solve_adjoint": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(Stats)]),
     "aao_grad_logkappa": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "aao_last_error": (ctypes.c_char_p, [c_void_p]),
+    "aao_create_batch": (c_int, [ctypes.POINTER(Desc), c_int, ctypes.POINTER(Opts), c_int, ctypes.POINTER(c_void_p)]),
+    "aao_batch_count": (c_int, [c_void_p]),
+    "aao_batch_offsets": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "aao_batch_workspace_size": (c_int, [c_void_p, ctypes.POINTER(c_size_t)]),
+    "aao_batch_set_workspace": (c_int, [c_void_p, c_void_p, c_size_t]),
+    "aao_batch_set_stream": (c_int, [c_void_p, c_void_p]),
+    "aao_batch_problem": (c_int, [c_void_p, c_int, ctypes.POINTER(c_void_p)]),
+    "aao_batch_assemble_rhs": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "aao_batch_solve": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(Stats)]),
+    "aao_batch_solve_adjoint": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(Stats)]),
+    "aao_batch_grad_logkappa": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "aao_batch_last_error": (ctypes.c_char_p, [c_void_p]),
+    "aao_batch_destroy": (c_int, [c_void_p]),
 }
 
 _lib = None

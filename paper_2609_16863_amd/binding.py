@@ -22,6 +22,25 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _make_opts(lib, *, restart, maxit, tol, inner_k, cycles, nu1, nu2, omega, precision, use_graph,
+               mg_tail_max):
+    opts = _abi.Opts()
+    lib.aao_default_opts(ctypes.byref(opts))
+    opts.restart, opts.maxit, opts.tol = restart, maxit, tol
+    opts.inner_k, opts.cycles, opts.nu1, opts.nu2 = inner_k, cycles, nu1, nu2
+    opts.omega = omega
+    opts.precision = _abi.PRECISIONS[precision]
+    opts.use_graph = int(bool(use_graph))
+    opts.mg_tail_max = int(mg_tail_max)
+    return opts
+
+
+def _stats_dict(st, code):
+    return {"outer_iterations": st.outer_iterations, "restarts": st.restarts, "relres": st.relres,
+            "time_ms": st.time_ms, "precond_ms": st.precond_ms,
+            "history": list(st.history[: st.history_len]), "converged": code == 0}
+
+
 class HeatProblem:
     """All-at-once Radau IIA system for the heat equation on one GPU.
 
@@ -43,14 +62,9 @@ class HeatProblem:
         self._kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
         desc = _abi.Desc(dim, n, s, nt, float(T),
                          None if self._kappa is None else self._kappa.ctypes.data)
-        opts = _abi.Opts()
-        self._lib.aao_default_opts(ctypes.byref(opts))
-        opts.restart, opts.maxit, opts.tol = restart, maxit, tol
-        opts.inner_k, opts.cycles, opts.nu1, opts.nu2 = inner_k, cycles, nu1, nu2
-        opts.omega = omega
-        opts.precision = _abi.PRECISIONS[precision]
-        opts.use_graph = int(bool(use_graph))
-        opts.mg_tail_max = int(mg_tail_max)
+        opts = _make_opts(self._lib, restart=restart, maxit=maxit, tol=tol, inner_k=inner_k, cycles=cycles,
+                          nu1=nu1, nu2=nu2, omega=omega, precision=precision, use_graph=use_graph,
+                          mg_tail_max=mg_tail_max)
         self.precision = precision
         h = ctypes.c_void_p()
         code = self._lib.aao_create_problem(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h))
@@ -187,10 +201,7 @@ class HeatProblem:
         st = _abi.Stats()
         self._sync_stream()
         code = self._check(fn(self._h, _ptr(rhs), _ptr(x), ctypes.byref(st)))
-        stats = {"outer_iterations": st.outer_iterations, "restarts": st.restarts,
-                 "relres": st.relres, "time_ms": st.time_ms, "precond_ms": st.precond_ms,
-                 "history": list(st.history[: st.history_len]), "converged": code == 0}
-        return x, stats
+        return x, _stats_dict(st, code)
 
     def solve(self, rhs, x0=None):
         """FGMRES solve of A x = rhs; returns (x, stats)."""
@@ -207,4 +218,119 @@ class HeatProblem:
                else self._vec(out, self.N, "out"))
         self._sync_stream()
         self._check(self._lib.aao_grad_logkappa(self._h, _ptr(x), _ptr(lam), _ptr(out)))
+        return out
+
+
+class HeatBatch:
+    """Independent all-at-once problems solved together (same options).
+
+    ``problems`` is a list of dicts with keys dim, n, s, nt and optionally T
+    and kappa.  Batch vectors are single float64 CUDA tensors holding the
+    problems' vectors back to back; ``split``/``join`` convert to and from
+    per-problem views.  ``streams`` HIP streams run the problems concurrently.
+    Solver keyword options are those of HeatProblem.
+    """
+
+    def __init__(self, problems, *, streams=4, restart=30, maxit=100, tol=1e-8, inner_k=3, cycles=1,
+                 nu1=2, nu2=2, omega=0.0, precision="fp64", use_graph=True, mg_tail_max=0,
+                 device="cuda"):
+        self._lib = _abi.load()
+        self.count = len(problems)
+        self._kappas = []
+        descs = (_abi.Desc * self.count)()
+        for i, p in enumerate(problems):
+            k = p.get("kappa")
+            k = None if k is None else np.ascontiguousarray(k, dtype=np.float64)
+            self._kappas.append(k)
+            descs[i] = _abi.Desc(p["dim"], p["n"], p["s"], p["nt"], float(p.get("T", 1.0)),
+                                 None if k is None else k.ctypes.data)
+        self.problems = [dict(p) for p in problems]
+        self.tol = tol
+        opts = _make_opts(self._lib, restart=restart, maxit=maxit, tol=tol, inner_k=inner_k, cycles=cycles,
+                          nu1=nu1, nu2=nu2, omega=omega, precision=precision, use_graph=use_graph,
+                          mg_tail_max=mg_tail_max)
+        h = ctypes.c_void_p()
+        code = self._lib.aao_create_batch(descs, self.count, ctypes.byref(opts), int(streams), ctypes.byref(h))
+        if code != 0:
+            raise AAOError(code, self._lib.aao_batch_last_error(None).decode())
+        self._h = h
+        ou = np.zeros(self.count + 1, dtype=np.int64)
+        on = np.zeros(self.count + 1, dtype=np.int64)
+        of = np.zeros(self.count + 1, dtype=np.int64)
+        self._lib.aao_batch_offsets(h, ou.ctypes.data, on.ctypes.data, of.ctypes.data)
+        self.off_unknowns, self.off_nodes, self.off_forcing = ou, on, of
+        self.U, self.N, self.F = int(ou[-1]), int(on[-1]), int(of[-1])
+        self.device = torch.device(device)
+        nbytes = ctypes.c_size_t()
+        self._check(self._lib.aao_batch_workspace_size(h, ctypes.byref(nbytes)))
+        self._ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
+        self._sync_stream()
+        self._check(self._lib.aao_batch_set_workspace(h, _ptr(self._ws), nbytes.value))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            self._lib.aao_batch_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, code):
+        if code not in (0, 1):
+            raise AAOError(code, self._lib.aao_batch_last_error(self._h).decode())
+        return code
+
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self._lib.aao_batch_set_stream(self._h, ctypes.c_void_p(s))
+
+    def _vec(self, t, numel, name):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and t.is_contiguous() and t.numel() == numel):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor with {numel} values")
+        return t
+
+    def split(self, t, kind="unknowns"):
+        """Per-problem views of a batch tensor (kind: unknowns | nodes | forcing)."""
+        off = {"unknowns": self.off_unknowns, "nodes": self.off_nodes, "forcing": self.off_forcing}[kind]
+        return [t[int(off[i]): int(off[i + 1])] for i in range(self.count)]
+
+    def join(self, parts, kind="unknowns"):
+        return torch.cat([p.reshape(-1) for p in parts]).contiguous()
+
+    def assemble_rhs(self, f, u0, out=None):
+        f = self._vec(f, self.F, "f")
+        u0 = self._vec(u0, self.N, "u0")
+        out = torch.empty(self.U, dtype=torch.float64, device=self.device) if out is None else \
+            self._vec(out, self.U, "out")
+        self._sync_stream()
+        self._check(self._lib.aao_batch_assemble_rhs(self._h, _ptr(f), _ptr(u0), _ptr(out)))
+        return out
+
+    def _solve(self, fn, rhs, x0):
+        rhs = self._vec(rhs, self.U, "rhs")
+        x = torch.zeros_like(rhs) if x0 is None else self._vec(x0, self.U, "x0").clone()
+        st = (_abi.Stats * self.count)()
+        self._sync_stream()
+        code = self._check(fn(self._h, _ptr(rhs), _ptr(x), st))
+        return x, [_stats_dict(st[i], 0 if st[i].relres <= self.tol else 1) for i in range(self.count)]
+
+    def solve(self, rhs, x0=None):
+        """FGMRES solves of every problem; returns (x, [stats per problem])."""
+        return self._solve(self._lib.aao_batch_solve, rhs, x0)
+
+    def solve_adjoint(self, g, lam0=None):
+        return self._solve(self._lib.aao_batch_solve_adjoint, g, lam0)
+
+    def grad_logkappa(self, x, lam, out=None):
+        x = self._vec(x, self.U, "x")
+        lam = self._vec(lam, self.U, "lam")
+        out = torch.empty(self.N, dtype=torch.float64, device=self.device) if out is None else \
+            self._vec(out, self.N, "out")
+        self._sync_stream()
+        self._check(self._lib.aao_batch_grad_logkappa(self._h, _ptr(x), _ptr(lam), _ptr(out)))
         return out

@@ -187,6 +187,9 @@ int solve(aao_problem* h, const double* rhs, double* x, aao_stats* st, bool tran
 // `cycles` V-cycles on count blocks of (I + tau L_ii K), L = Crout factor of
 // A (or A^T); r, z in the preconditioner's working type.
 hipError_t apply_mg(aao_problem* h, bool transpose, int stage, int count, int cycles, const void* r, void* z);
+// Capture (without launching) the HIP graph of the handle's P-tilde (or its
+// transpose) so that later solves only replay it.
+hipError_t prepare_graph(aao_problem* h, bool transpose);
 // First multigrid level handled by the one-workgroup tail.
 int mg_tail_level(aao_problem* h);
 

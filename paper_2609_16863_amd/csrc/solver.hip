@@ -198,9 +198,7 @@ hipError_t apply_mg_typed(aao_problem* h, bool transpose, int stage, int count, 
 // call for this (transpose, k, cycles).  The graph reads its input from and
 // writes its output to fixed workspace buffers; the copies in and out run on
 // the handle's stream around the replay.
-hipError_t precond_apply(aao_problem* h, const double* r, void* z, int k, int cycles, bool transpose) {
-  if (!h->opts.use_graph) return apply_P_any(h, r, z, k, cycles, transpose);
-  const int64_t U = h->U;
+hipError_t precond_graph(aao_problem* h, int k, int cycles, bool transpose, aao_problem::GraphEntry** out) {
   double* gin = reinterpret_cast<double*>(h->ws + h->plan.gIn);
   void* gout = h->ws + h->plan.gOut;
   aao_problem::GraphEntry* ent = nullptr;
@@ -232,6 +230,17 @@ hipError_t precond_apply(aao_problem* h, const double* r, void* z, int k, int cy
     h->graphs.push_back(aao_problem::GraphEntry{transpose, k, cycles, graph, exec});
     ent = &h->graphs.back();
   }
+  *out = ent;
+  return hipSuccess;
+}
+
+hipError_t precond_apply(aao_problem* h, const double* r, void* z, int k, int cycles, bool transpose) {
+  if (!h->opts.use_graph) return apply_P_any(h, r, z, k, cycles, transpose);
+  const int64_t U = h->U;
+  double* gin = reinterpret_cast<double*>(h->ws + h->plan.gIn);
+  void* gout = h->ws + h->plan.gOut;
+  aao_problem::GraphEntry* ent = nullptr;
+  TRY(precond_graph(h, k, cycles, transpose, &ent));
   TRY(hipMemcpyAsync(gin, r, (size_t)U * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   TRY(hipGraphLaunch(ent->exec, h->stream));
   return hipMemcpyAsync(z, gout, (size_t)U * h->pi_bytes, hipMemcpyDeviceToDevice, h->stream);
@@ -503,6 +512,12 @@ hipError_t apply_mg(aao_problem* h, bool transpose, int stage, int count, int cy
     case AAO_PREC_FP16: return apply_mg_typed<float, __half>(h, transpose, stage, count, cycles, r, z);
     default: return apply_mg_typed<float, __hip_bfloat16>(h, transpose, stage, count, cycles, r, z);
   }
+}
+
+hipError_t prepare_graph(aao_problem* h, bool transpose) {
+  if (!h->opts.use_graph) return hipSuccess;
+  aao_problem::GraphEntry* ent = nullptr;
+  return precond_graph(h, h->opts.inner_k, h->opts.cycles, transpose, &ent);
 }
 
 int apply_P(aao_problem* h, const double* r, double* z, int inner_k, int cycles, bool transpose) {

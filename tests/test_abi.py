@@ -146,3 +146,38 @@ def test_mg_levels_match_oracle_hierarchy_sizes(dim, n):
         sizes.append(multigrid.coarse_size(sizes[-1]))
     assert list(nodes[: L.value]) == [m ** dim for m in sizes]
     lib.aao_destroy(h)
+
+
+def test_batch_creation_offsets_and_errors():
+    abi, lib = _lib()
+    specs = [(2, 8, 2, 3), (2, 5, 1, 2), (3, 4, 3, 2)]
+    descs = (abi.Desc * 3)(*[abi.Desc(d, n, s, nt, 1.0, None) for d, n, s, nt in specs])
+    h = ctypes.c_void_p()
+    assert lib.aao_create_batch(descs, 3, None, 4, ctypes.byref(h)) == 0
+    assert lib.aao_batch_count(h) == 3
+    ou, on, of = (np.zeros(4, dtype=np.int64) for _ in range(3))
+    assert lib.aao_batch_offsets(h, ou.ctypes.data, on.ctypes.data, of.ctypes.data) == 0
+    Ns = [n ** d for d, n, s, nt in specs]
+    Us = [N * (nt * (s + 1) + 1) for N, (d, n, s, nt) in zip(Ns, specs)]
+    Fs = [N * nt * s for N, (d, n, s, nt) in zip(Ns, specs)]
+    assert list(ou) == list(np.cumsum([0] + Us))
+    assert list(on) == list(np.cumsum([0] + Ns))
+    assert list(of) == list(np.cumsum([0] + Fs))
+    ws = ctypes.c_size_t()
+    assert lib.aao_batch_workspace_size(h, ctypes.byref(ws)) == 0 and ws.value > 0
+    sub = ctypes.c_void_p()
+    assert lib.aao_batch_problem(h, 1, ctypes.byref(sub)) == 0
+    Nv, Uv = ctypes.c_int64(), ctypes.c_int64()
+    lib.aao_sizes(sub, ctypes.byref(Nv), ctypes.byref(Uv))
+    assert (Nv.value, Uv.value) == (Ns[1], Us[1])
+    assert lib.aao_batch_problem(h, 3, ctypes.byref(sub)) == -1
+    assert lib.aao_batch_solve(h, ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20), None) == -5
+    assert lib.aao_batch_destroy(h) == 0
+    # a failing problem is named; bad counts and stream numbers are rejected
+    descs[1] = abi.Desc(2, 5, 4, 2, 1.0, None)
+    assert lib.aao_create_batch(descs, 3, None, 4, ctypes.byref(h)) == -1
+    assert b"problem 1" in lib.aao_batch_last_error(None)
+    assert lib.aao_create_batch(descs, 0, None, 4, ctypes.byref(h)) == -1
+    descs[1] = abi.Desc(2, 5, 1, 2, 1.0, None)
+    assert lib.aao_create_batch(descs, 3, None, 0, ctypes.byref(h)) == -1
+    assert lib.aao_create_batch(descs, 3, None, 17, ctypes.byref(h)) == -1

@@ -1,0 +1,155 @@
+"""GPU batches of independent problems (aao_create_batch / aao_batch_*).
+
+A batch runs its problems on several streams at once; each problem's result
+must be exactly that of the same problem solved alone (same kernels, same
+fixed-order reductions), and match the oracle's sequential stepping.  The
+gradient tests follow the tracking-loss workload: the loss, its gradients
+with respect to the forcing, the initial value and log kappa through the
+adjoint solve, checked against the oracle and against central differences
+of GPU forward solves.
+"""
+import numpy as np
+import pytest
+
+import heat_inputs
+from gpu_util import announce, rel_err, require_gpu, to_dev, to_host
+from oracle import adjoint, allatonce, stepping
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _problem_inputs(sp):
+    times = allatonce.Problem(sp["n"], 2, sp["s"], sp["nt"], 1.0).stage_times()
+    kappa, f, u0 = heat_inputs.spec_inputs(sp, times)
+    return kappa, f, u0
+
+
+def _small_uneven_specs():
+    """The uneven batch recipe (sizes, stages, steps drawn per problem) at
+    sizes the oracle handles quickly."""
+    base = heat_inputs.batch_problem_specs(count=6)
+    sizes = [16, 24, 33, 20, 40, 13]
+    return [dict(sp, n=sizes[i], nt=3 + sp["nt"] % 6) for i, sp in enumerate(base)]
+
+
+def test_batch_solve_equals_single_solves_and_oracle():
+    require_gpu()
+    from paper_2609_16863_amd import HeatBatch, HeatProblem
+    specs = _small_uneven_specs()
+    data = [_problem_inputs(sp) for sp in specs]
+    opts = dict(precision="fp32", tol=1e-11, restart=30, maxit=200)
+    announce("batch solve", [(sp["n"], sp["s"], sp["nt"]) for sp in specs])
+    hb = HeatBatch([dict(dim=2, n=sp["n"], s=sp["s"], nt=sp["nt"], kappa=k) for sp, (k, _, _) in zip(specs, data)],
+                   streams=3, **opts)
+    f = to_dev(np.concatenate([d[1].ravel() for d in data]))
+    u0 = to_dev(np.concatenate([d[2].ravel() for d in data]))
+    rhs = hb.assemble_rhs(f, u0)
+    x, stats = hb.solve(rhs)
+    xs = hb.split(x)
+    for i, (sp, (kappa, fi, u0i)) in enumerate(zip(specs, data)):
+        assert stats[i]["converged"], (i, stats[i])
+        hp = HeatProblem(2, sp["n"], sp["s"], sp["nt"], 1.0, kappa=kappa, **opts)
+        ri = hp.assemble_rhs(to_dev(fi.ravel()), to_dev(u0i))
+        assert torch.equal(ri, hb.split(rhs)[i])
+        xi, sti = hp.solve(ri)
+        assert sti["outer_iterations"] == stats[i]["outer_iterations"]
+        assert torch.equal(xi, xs[i]), i
+        p = allatonce.Problem(sp["n"], 2, sp["s"], sp["nt"], 1.0, kappa=kappa)
+        ref = stepping.solve(p, fi, u0i, method="lu")
+        assert rel_err(to_host(xs[i]), ref) <= 1e-8, (i, rel_err(to_host(xs[i]), ref))
+
+
+def _loss_and_grads_gpu(hb, specs, data, targets):
+    """Forward batch solve, tracking loss, adjoint batch solve, gradients."""
+    f = to_dev(np.concatenate([d[1].ravel() for d in data]))
+    u0 = to_dev(np.concatenate([d[2].ravel() for d in data]))
+    x, st = hb.solve(hb.assemble_rhs(f, u0))
+    assert all(s["converged"] for s in st)
+    xh = [to_host(v) for v in hb.split(x)]
+    losses, gx = [], []
+    for sp, xi, vt in zip(specs, xh, targets):
+        p = allatonce.Problem(sp["n"], 2, sp["s"], sp["nt"], 1.0)
+        v, _ = allatonce.split(p, xi)
+        d = v[1:] - vt[1:]
+        losses.append(0.5 * float(np.sum(d * d)))
+        gv = np.zeros_like(v)
+        gv[1:] = d
+        gx.append(allatonce.join(gv, np.zeros((p.nt, p.s, p.N))))
+    lam, st = hb.solve_adjoint(to_dev(np.concatenate(gx)))
+    assert all(s["converged"] for s in st)
+    gk = hb.grad_logkappa(x, lam)
+    out = []
+    for i, sp in enumerate(specs):
+        p = allatonce.Problem(sp["n"], 2, sp["s"], sp["nt"], 1.0)
+        lv, lV = allatonce.split(p, to_host(hb.split(lam)[i]))
+        out.append((losses[i], lV, lv[0], to_host(hb.split(gk, "nodes")[i])))
+    return out
+
+
+def _gradient_specs():
+    base = heat_inputs.gradient_problem_specs(count=3)
+    return [dict(sp, n=n, nt=6) for sp, n in zip(base, [16, 20, 24])]
+
+
+def _targets(specs, data):
+    out = []
+    for sp, (kappa, _, _) in zip(specs, data):
+        p = allatonce.Problem(sp["n"], 2, sp["s"], sp["nt"], 1.0, kappa=kappa)
+        ft, ut = heat_inputs.spec_target_inputs(sp, p.stage_times())
+        out.append(allatonce.split(p, stepping.solve(p, ft, ut, method="lu"))[0])
+    return out
+
+
+def test_batch_gradients_match_oracle():
+    require_gpu()
+    from paper_2609_16863_amd import HeatBatch
+    specs = _gradient_specs()
+    data = [_problem_inputs(sp) for sp in specs]
+    targets = _targets(specs, data)
+    announce("batch gradients", [sp["n"] for sp in specs])
+    hb = HeatBatch([dict(dim=2, n=sp["n"], s=sp["s"], nt=sp["nt"], kappa=k) for sp, (k, _, _) in zip(specs, data)],
+                   streams=2, precision="fp32", tol=1e-12, maxit=300)
+    got = _loss_and_grads_gpu(hb, specs, data, targets)
+    for sp, (kappa, f, u0), vt, (L, gf, gu0, gk) in zip(specs, data, targets, got):
+        p = allatonce.Problem(sp["n"], 2, sp["s"], sp["nt"], 1.0, kappa=kappa)
+        Lr, gfr, gu0r, gkr = adjoint.gradients(p, f, u0, vt)
+        assert abs(L - Lr) <= 1e-9 * abs(Lr)
+        assert rel_err(gf, gfr) <= 1e-7
+        assert rel_err(gu0, gu0r) <= 1e-7
+        assert rel_err(gk, gkr) <= 1e-7
+
+
+def test_gradient_central_differences_on_gpu():
+    """Directional derivatives of the loss from GPU forward solves at tol
+    1e-12 agree with the adjoint gradients (log kappa, f and u0 directions)."""
+    require_gpu()
+    from paper_2609_16863_amd import HeatBatch
+    sp = _gradient_specs()[0]
+    kappa, f, u0 = _problem_inputs(sp)
+    vt = _targets([sp], [(kappa, f, u0)])[0]
+    rng = np.random.default_rng(3004)
+    opts = dict(precision="fp32", tol=1e-12, maxit=300)
+
+    def loss(kap, ff, uu):
+        hb = HeatBatch([dict(dim=2, n=sp["n"], s=sp["s"], nt=sp["nt"], kappa=kap)], streams=1, **opts)
+        x, st = hb.solve(hb.assemble_rhs(to_dev(ff.ravel()), to_dev(uu)))
+        assert st[0]["converged"]
+        p = allatonce.Problem(sp["n"], 2, sp["s"], sp["nt"], 1.0)
+        v, _ = allatonce.split(p, to_host(x))
+        return 0.5 * float(np.sum((v[1:] - vt[1:]) ** 2))
+
+    hb = HeatBatch([dict(dim=2, n=sp["n"], s=sp["s"], nt=sp["nt"], kappa=kappa)], streams=1, **opts)
+    (L, gf, gu0, gk), = _loss_and_grads_gpu(hb, [sp], [(kappa, f, u0)], [vt])
+    theta = np.log(kappa)
+    announce("gradient central differences", sp["n"])
+    for _ in range(2):
+        d = rng.standard_normal(theta.shape)
+        eps = 1e-4 * np.linalg.norm(theta) / np.linalg.norm(d)
+        fd = (loss(np.exp(theta + eps * d), f, u0) - loss(np.exp(theta - eps * d), f, u0)) / (2 * eps)
+        assert abs(fd - gk @ d) <= 1e-5 * abs(gk @ d) + 1e-12
+    df, du = rng.standard_normal(f.shape), rng.standard_normal(u0.shape)
+    eps = 1e-3
+    fd = (loss(kappa, f + eps * df, u0 + eps * du) - loss(kappa, f - eps * df, u0 - eps * du)) / (2 * eps)
+    lin = float(np.sum(gf.reshape(f.shape) * df) + gu0 @ du)
+    assert abs(fd - lin) <= 1e-6 * abs(lin)
