@@ -4,15 +4,20 @@ One step = one full FGMRES solve to a true FP64 relative residual of 1e-8 of
 the all-at-once system (paper eq. (2.4)) with the block preconditioner
 (eqs. (3.2)-(3.3)) applied in FP32 (the mixed-precision arm, approach A2).
 The same solve with the FP64 preconditioner (approach A1) is timed beside
-it.  Workload: 2D heat on a 512 x 512 interior grid, Radau IIA s = 3, 64 time
-steps to T = 1, FGMRES(30); seeded Gaussian-bump source and smooth random
-initial condition (synthetic, generated on the host).
+it, with the same inner settings (4 inner GMRES iterations, one V-cycle with
+2 + 2 Jacobi sweeps per shifted block).  Workload: 2D heat on a 512 x 512
+interior grid, Radau IIA s = 3, 64 time steps to T = 1, FGMRES(30); seeded
+Gaussian-bump source and smooth random initial condition (synthetic,
+generated on the host).
 
-Prints one JSON line (rank 0).  `roofline` reports the dominant kernel's
-algorithmic HBM bytes / its average launch time, measured here with HIP
-events on the stream the kernel runs on; `cpu_baseline` times the FP64 CPU
-oracle (sequential stepping with an exact DST stage solve) on a bounded
-number of time steps, scaled to the full 64 steps.
+Prints one JSON line (rank 0).  `roofline` reports apply_A's algorithmic HBM
+bytes / its average launch time, and `roofline_vcycle` the same for one
+V-cycle on the 64 stage blocks of the batched Theta-tilde phase, both
+measured here with HIP events on the stream the kernels run on; `traffic` is
+the counter-measured HBM bytes per launch from profiles/ while the kernel
+source is unchanged.  `cpu_baseline` times the FP64 CPU oracle (sequential
+stepping with an exact DST stage solve) on a bounded number of time steps,
+scaled to the full 64 steps.
 """
 import argparse
 import json
@@ -154,9 +159,29 @@ def measure_roofline(hp, x, reps):
     sec = _event_time(lambda: hp.apply_A(x, y), reps)
     nbytes = 16.0 * hp.U
     gbs = nbytes / sec / 1e9
+    traffic = measured_traffic("k_apply_A_2d") if hp.n == 512 and hp.s == 3 and hp.nt == 64 else None
     return {"kernel": "k_apply_A_2d", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": nbytes,
-            "avg_launch_us": sec * 1e6}
+            "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "B per launch",
+            "bytes_per_launch": nbytes, "avg_launch_us": sec * 1e6}
+
+
+def measured_traffic(name):
+    """HBM bytes per launch of a roofline kernel from the committed counter
+    summary (rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by a plain copy of
+    known size), or None when the kernel's source changed since they were
+    taken (its sha256 no longer matches) or no summary exists."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "roofline_heat2d_n512_s3_nt64.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        m = re.match(r"traffic (\S+) source=(\S+) sha256=([0-9a-f]+) bytes_per_launch=(\d+)", line.strip())
+        if m and m.group(1) == name:
+            src = os.path.join(ROOT, m.group(2))
+            if os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == m.group(3):
+                return float(m.group(4))
+    return None
 
 
 def _event_time(fn, reps):
@@ -202,10 +227,12 @@ def measure_vcycle(hp, precision, reps):
     sec = _event_time(lambda: hp.apply_mg(r, 0, out=z, cycles=1), reps)
     nbytes = float(per_block * B)
     gbs = nbytes / sec / 1e9
+    traffic = (measured_traffic("vcycle") if hp.n == 512 and hp.s == 3 and hp.nt == 64 and precision == "fp32"
+               else None)
     return {"kernel": "V-cycle: k_down2d per level, k_tail, k_up2d per level", "bound": "hbm",
             "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "traffic": None, "bytes_per_launch": nbytes, "avg_launch_us": sec * 1e6,
-            "blocks": B, "levels": nodes, "tail_level": l0}
+            "traffic": traffic, "traffic_unit": "B per launch", "bytes_per_launch": nbytes,
+            "avg_launch_us": sec * 1e6, "blocks": B, "levels": nodes, "tail_level": l0}
 
 
 def measure_copy(nbytes, reps):
