@@ -108,6 +108,8 @@ struct aao_problem {
   std::vector<double> cinv_host;             // coarsest-level inverses: [transpose][stage] N_c^2 each
   int64_t cinv_N = 0;
   std::vector<double> faces_host;            // 2*dim*N when vark
+  std::vector<double> fd_host;               // coarsest level, constant kappa (2D): V (n_c^2) then lam (n_c)
+  int fd_n = 0;                              // n_c when fd_host is set
   std::vector<double> st9_host;              // Galerkin stencils of K, levels >= 1 (2D, vark)
   std::vector<size_t> st9_off;               // element offset per level (levels >= 1)
 
@@ -116,7 +118,7 @@ struct aao_problem {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   struct Plan {
-    size_t tri_d, tri_f, faces_d, faces_f, cinv_d, cinv_f, st9_d, st9_f;
+    size_t tri_d, tri_f, faces_d, faces_f, cinv_d, cinv_f, st9_d, st9_f, fd_d, fd_f;
     size_t outV, outZ, outW, outY;           // outer FGMRES
     size_t gIn, gOut;                        // fixed input/output of the captured P-tilde
     size_t inV, inZ, inW, inX;               // inner GMRES (nt instances)
@@ -152,6 +154,7 @@ namespace aao {
 bool radau_iia(int s, double* A, double* b, double* c);
 void crout_lower(int s, const double* A, double* L);
 void galerkin_1d(int n, int dim, double h, std::vector<int>& sizes, std::vector<std::vector<double>>& tri);
+bool tensor_eigen(int n, const std::vector<double>& tri, std::vector<double>& V, std::vector<double>& lam);
 void galerkin_stencils_2d(const std::vector<int>& sizes, const std::vector<double>& faces, double ih2,
                           std::vector<std::vector<double>>& st9);
 bool coarse_inverse(int dim, int n, const std::vector<double>& tri, double a, bool fine, double ih2,

@@ -33,6 +33,8 @@ void plan_workspace(aao_problem* h) {
   P.tri_f = take(h->tri_host.size() * sizeof(float));
   P.cinv_d = take(h->cinv_host.size() * sizeof(double));
   P.cinv_f = take(h->cinv_host.size() * sizeof(float));
+  P.fd_d = take(h->fd_host.size() * sizeof(double));
+  P.fd_f = take(h->fd_host.size() * sizeof(float));
   P.st9_d = take(h->st9_host.size() * sizeof(double));
   P.st9_f = take(h->st9_host.size() * sizeof(float));
   // faces (2*dim*N) followed by nodal kappa (N)
@@ -199,6 +201,16 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
       h->st9_host.insert(h->st9_host.end(), st9[l].begin(), st9[l].end());
     }
   }
+  // fast diagonalization of the coarsest level (2D, constant kappa)
+  if (d->dim == 2 && !h->vark) {
+    const int lc = (int)h->lev_n.size() - 1;
+    std::vector<double> V, lam;
+    if (aao::tensor_eigen(h->lev_n[lc], tri[lc], V, lam)) {
+      h->fd_n = h->lev_n[lc];
+      h->fd_host = V;
+      h->fd_host.insert(h->fd_host.end(), lam.begin(), lam.end());
+    }
+  }
   // exact inverses of the coarsest level, for the shifts tau L_ii (P-tilde)
   // and tau LT_ii (its transpose)
   {
@@ -259,6 +271,14 @@ int aao_set_workspace(aao_problem* h, void* dev_ptr, size_t bytes) {
       e = aao::launch_copy_cast<float, double>(reinterpret_cast<float*>(h->ws + h->plan.cinv_f),
                                                reinterpret_cast<const double*>(h->ws + h->plan.cinv_d),
                                                (int64_t)h->cinv_host.size(), h->stream);
+  }
+  if (e == hipSuccess && !h->fd_host.empty()) {
+    e = hipMemcpyAsync(h->ws + h->plan.fd_d, h->fd_host.data(), h->fd_host.size() * sizeof(double),
+                       hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = aao::launch_copy_cast<float, double>(reinterpret_cast<float*>(h->ws + h->plan.fd_f),
+                                               reinterpret_cast<const double*>(h->ws + h->plan.fd_d),
+                                               (int64_t)h->fd_host.size(), h->stream);
   }
   if (e == hipSuccess && !h->st9_host.empty()) {
     e = hipMemcpyAsync(h->ws + h->plan.st9_d, h->st9_host.data(), h->st9_host.size() * sizeof(double),

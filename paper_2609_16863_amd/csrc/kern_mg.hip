@@ -348,11 +348,14 @@ struct Tile {
   C cy[TEN ? 6 * H : (S9 ? 3 * H : 1)];  // per row:    M(j, j+d), a T(j, j+d) (S9: M only)
 };
 
-// Stencil coefficients (times a) of the nodes a thread sweeps, for
-// KIND_STENCIL9: element it of the thread is tile node threadIdx.x + 256 it.
+// The 9 operator coefficients of the nodes a thread sweeps, for the Galerkin
+// kinds (KIND_TENSOR, KIND_STENCIL9): element it of the thread is tile node
+// threadIdx.x + 256 it; entry (dj+1)*3 + (di+1) multiplies x at (di, dj).
+// Loaded (stencil part, before the tile barrier) and completed from the
+// staged factor rows (after it), then reused by every sweep.
 template <int KIND, int IT, class C>
 struct Coef9 {
-  C v[IT][KIND == KIND_STENCIL9 ? 9 : 1];
+  C v[IT][(KIND == KIND_STENCIL9 || KIND == KIND_TENSOR) ? 9 : 1];
 };
 
 template <int KIND, int R, class C>
@@ -431,19 +434,42 @@ __device__ __forceinline__ void tile_stage_op(Tile<KIND, R, C>& sm, const LevelO
   }
 }
 
+template <int KIND, int R, class C>
+__device__ __forceinline__ void tile_finish_coef(Coef9<KIND, Tile<KIND, R, C>::IT, C>& k9,
+                                                 const Tile<KIND, R, C>& sm) {
+  using T = Tile<KIND, R, C>;
+  if constexpr (T::S9 || T::TEN) {
+    constexpr int W = T::W, H = T::H;
+#pragma unroll
+    for (int it = 0; it < T::IT; ++it) {
+      const int t = threadIdx.x + it * 256;
+      const int tx = t < T::NE ? t % W : 0, ty = t < T::NE ? t / W : 0;
+#pragma unroll
+      for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+        for (int di = -1; di <= 1; ++di) {
+          C& k = k9.v[it][(dj + 1) * 3 + di + 1];
+          if constexpr (T::TEN)   // M_j (M + aT)_i + a T_j M_i
+            k = sm.cy[(dj + 1) * H + ty] * sm.cx[(di + 1) * W + tx] + sm.cy[(4 + dj) * H + ty] * sm.cx[(4 + di) * W + tx];
+          else                    // M_j M_i + a K (loaded)
+            k += sm.cy[(dj + 1) * H + ty] * sm.cx[(di + 1) * W + tx];
+        }
+    }
+  }
+}
+
 // Diagonal of the level operator at tile node (tx, ty) from the staged data.
 template <int KIND, int R, class C>
 __device__ __forceinline__ C tile_diag(const Tile<KIND, R, C>& sm, const LevelOp<C>& op, int t, int tx, int ty,
                                        const C* kc) {
   using T = Tile<KIND, R, C>;
   if constexpr (KIND == KIND_FINE) return C(1) + op.a * op.ih2 * C(4);
-  else if constexpr (T::S9)
-    return sm.cy[1 * T::H + ty] * sm.cx[1 * T::W + tx] + kc[4];
+  else if constexpr (T::S9 || T::TEN)
+    return kc[4];
   else if constexpr (T::VK)
     return C(1) + sm.f[t] + sm.f[T::NE + t] + sm.f[2 * T::NE + t] + sm.f[3 * T::NE + t];
   else
-    // M_j(0) (M + a T)_i(0) + a T_j(0) M_i(0)
-    return sm.cy[1 * T::H + ty] * sm.cx[1 * T::W + tx] + sm.cy[4 * T::H + ty] * sm.cx[4 * T::W + tx];
+    return C(0);
 }
 
 // (A x)_t for an interior tile node (all 8 neighbours inside the tile).
@@ -453,14 +479,12 @@ __device__ __forceinline__ C tile_Ax(const Tile<KIND, R, C>& sm, const C* __rest
   using T = Tile<KIND, R, C>;
   constexpr int W = T::W;
   const C c = x[t];
-  if constexpr (T::S9) {
+  if constexpr (T::S9 || T::TEN) {
     C acc = C(0);
 #pragma unroll
     for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
-      for (int di = -1; di <= 1; ++di)
-        acc += (sm.cy[(dj + 1) * T::H + ty] * sm.cx[(di + 1) * W + tx] + kc[(dj + 1) * 3 + di + 1]) *
-               x[t + dj * W + di];
+      for (int di = -1; di <= 1; ++di) acc += kc[(dj + 1) * 3 + di + 1] * x[t + dj * W + di];
     return acc;
   } else if constexpr (KIND == KIND_FINE) {
     return c + op.a * op.ih2 * (C(4) * c - x[t - 1] - x[t + 1] - x[t - W] - x[t + W]);
@@ -565,6 +589,7 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
     }
   }
   __syncthreads();
+  tile_finish_coef<KIND, R, C>(k9, sm);
   tile_inv_diag<KIND, R, C>(sm, op, ox, oy, omega, k9);
   C* cur = sm.x0;
   C* nxt = sm.x1;
@@ -678,6 +703,7 @@ __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_
     if (t < CNE) sec[t] = ev[it];
   }
   __syncthreads();
+  tile_finish_coef<KIND, R, C>(k9, sm);
   tile_inv_diag<KIND, R, C>(sm, op, ox, oy, omega, k9);
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
@@ -764,6 +790,8 @@ struct TailArgs {
   int off[TAIL_MAXL];   // LDS offsets: X at off, Y at off + N, B at off + 2N
   int toff[TAIL_MAXL];  // LDS offset of the level's 6*n factor copy
   const C* cinv;        // dense inverse of the last level, transposed
+  const C* fd;          // or its fast diagonalization (V, n^2 values, then lam, n values; null if absent)
+  int fdoff;            // LDS offset of the staged fast-diagonalization data
   int scratch;          // LDS offset of 2 * N_last values for the coarse solve
   LevelOp<C> op[TAIL_MAXL];
 };
@@ -846,6 +874,17 @@ __device__ __forceinline__ void tail_op(const TailArgs<C>& ta, const C* sm, int 
   }
 }
 
+// Diagonal of level t of the tail at node p = (i, j).
+template <bool VK, class C>
+__device__ __forceinline__ C tail_diag(const TailArgs<C>& ta, const C* sm, int t, int p, int i, int j) {
+  const LevelOp<C>& op = ta.op[t];
+  if (t == 0 && ta.first_fine) return level_diag<2, VK ? KIND_FINE_VK : KIND_FINE, C>(op, p, i, j, 0);
+  const C* tri = sm + ta.toff[t];
+  const int n = op.n;
+  if (op.st9) return tri[n + i] * tri[n + j] + op.a * op.st9[4 * op.N + p];
+  return tri[n + i] * tri[n + j] + op.a * (tri[4 * n + i] * tri[n + j] + tri[n + i] * tri[4 * n + j]);
+}
+
 template <bool VK, class TX, class TB, class C>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TX* __restrict__ xg, int64_t sx, const TB* __restrict__ bg,
                                                        int64_t sb, TailArgs<C> ta) {
@@ -858,6 +897,10 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TX* __restrict__ xg, int6
   for (int t = (ta.first_fine ? 1 : 0); t <= last; ++t) {
     const int n6 = 6 * ta.op[t].n;
     for (int q = tid; q < n6; q += nth) sm[ta.toff[t] + q] = ta.op[t].tri[q];
+  }
+  if (ta.fd) {
+    const int nl = ta.op[last].n, nfd = nl * nl + nl;
+    for (int q = tid; q < nfd; q += nth) sm[ta.fdoff + q] = ta.fd[q];
   }
   const int N0 = (int)ta.op[0].N;
   for (int p = tid; p < N0; p += nth) {
@@ -875,9 +918,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TX* __restrict__ xg, int6
       for (int p = tid; p < Nt; p += nth) {
         int i, j;
         tail_ij(p, n, inv_n, i, j);
-        C Ax, d;
-        tail_op<VK, C>(ta, sm, t, sm + X, p, i, j, Ax, d);   // only d is used
-        sm[X + p] = ta.omega * sm[Bt + p] / d;
+        sm[X + p] = ta.omega * sm[Bt + p] / tail_diag<VK, C>(ta, sm, t, p, i, j);
       }
       --rem;
       __syncthreads();
@@ -927,7 +968,44 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TX* __restrict__ xg, int6
     if (c != X) cur_y |= 1u << t;
     __syncthreads();
   }
-  {                                                   // coarsest level: exact
+  if (ta.fd) {                                        // coarsest level: exact, fast diagonalization
+    // A = M(x)M + a (T(x)M + M(x)T) on an n x n grid; with T V = M V diag(lam),
+    // V^T M V = I:  X = V ((V^T B V) ./ (1 + a (lam_l + lam_k))) V^T, where
+    // B[j][i] = b_{j n + i}.  Four n x n products through the free Y buffer.
+    const int n = ta.op[last].n, Nt = n * n;
+    const int X = ta.off[last], Y = X + Nt, Bl = X + 2 * Nt;
+    const C* V = sm + ta.fdoff;
+    const C* lam = V + Nt;
+    const C a = ta.op[last].a;
+    for (int q = tid; q < Nt; q += nth) {            // Y = B V
+      const int j = q / n, k = q - j * n;
+      C acc = C(0);
+      for (int i = 0; i < n; ++i) acc += sm[Bl + j * n + i] * V[i * n + k];
+      sm[Y + q] = acc;
+    }
+    __syncthreads();
+    for (int q = tid; q < Nt; q += nth) {            // X = (V^T Y) ./ D
+      const int l = q / n, k = q - l * n;
+      C acc = C(0);
+      for (int j = 0; j < n; ++j) acc += V[j * n + l] * sm[Y + j * n + k];
+      sm[X + q] = acc / (C(1) + a * (lam[l] + lam[k]));
+    }
+    __syncthreads();
+    for (int q = tid; q < Nt; q += nth) {            // Y = X V^T
+      const int l = q / n, i = q - l * n;
+      C acc = C(0);
+      for (int k = 0; k < n; ++k) acc += sm[X + l * n + k] * V[i * n + k];
+      sm[Y + q] = acc;
+    }
+    __syncthreads();
+    for (int q = tid; q < Nt; q += nth) {            // X = V Y
+      const int j = q / n, i = q - j * n;
+      C acc = C(0);
+      for (int l = 0; l < n; ++l) acc += V[j * n + l] * sm[Y + l * n + i];
+      sm[X + q] = acc;
+    }
+    __syncthreads();
+  } else {                                            // coarsest level: exact
     // x = A^{-1} b with the dense inverse: `parts` threads per row, each
     // summing a contiguous slice of columns; partial sums meet in the free
     // Y buffer of this level (Nt * parts <= 3 Nt values fit in X, Y, B? no:
@@ -1059,7 +1137,8 @@ Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L)
   const size_t budget = h->lds_budget;
   auto cost = [&](int l) { return sizeof(C) * (3 * (size_t)h->lev_N[l] + 6 * (size_t)h->lev_n[l]); };
   l0_ = levels_ - 1;
-  size_t bytes = cost(levels_ - 1) + sizeof(C) * 2 * (size_t)h->lev_N[levels_ - 1];
+  size_t bytes = cost(levels_ - 1) + sizeof(C) * 2 * (size_t)h->lev_N[levels_ - 1] +
+                 sizeof(C) * (size_t)(h->fd_n * h->fd_n + h->fd_n);
   // measured on MI355X (512^2, s=3): one workgroup is faster than grid
   // kernels up to a 32 x 32 level, slower above it
   const int64_t tail_max = h->opts.mg_tail_max > 0 ? h->opts.mg_tail_max : 1024;
@@ -1173,6 +1252,13 @@ hipError_t Multigrid<TI, TM>::tail(int stage, Vec x, Vec b, bool zero_init, int 
   for (int t = 0; t < ta.nl; ++t) {
     ta.toff[t] = off;
     off += 6 * ta.op[t].n;
+  }
+  ta.fd = nullptr;
+  ta.fdoff = off;
+  if (h_->fd_n > 0 && h_->fd_n == ta.op[ta.nl - 1].n) {
+    const bool dbl = sizeof(C) == 8;
+    ta.fd = reinterpret_cast<const C*>(h_->ws + (dbl ? h_->plan.fd_d : h_->plan.fd_f));
+    off += h_->fd_n * h_->fd_n + h_->fd_n;
   }
   ta.scratch = off;
   off += 2 * (int)ta.op[ta.nl - 1].N;

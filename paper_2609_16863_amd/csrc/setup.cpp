@@ -182,6 +182,108 @@ void galerkin_1d(int n, int dim, double h, std::vector<int>& sizes, std::vector<
   }
 }
 
+// Generalized eigenvectors of the pair (T, M) of 1D factors of one level
+// (both symmetric tridiagonal, M positive definite): T V = M V diag(lam) with
+// V^T M V = I.  Then M(x)M + a (T(x)M + M(x)T) = (V(x)V)^{-T} D (V(x)V)^{-1}
+// with D = I + a (lam(x)1 + 1(x)lam), so its inverse is applied by four
+// small matrix products and a diagonal scaling (fast diagonalization, Lynch,
+// Rice and Thomas 1964).  Computed as V = L^{-T} Q with M = L L^T and Q the
+// eigenvectors of L^{-1} T L^{-T} by cyclic Jacobi rotations.  V is returned
+// row-major (V[i n + k] = component i of vector k).
+bool tensor_eigen(int n, const std::vector<double>& tri, std::vector<double>& V, std::vector<double>& lam) {
+  std::vector<double> M((size_t)n * n, 0.0), T((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int d = -1; d <= 1; ++d) {
+      const int j = i + d;
+      if (j < 0 || j >= n) continue;
+      M[(size_t)i * n + j] = tri[(1 + d) * n + i];
+      T[(size_t)i * n + j] = tri[(4 + d) * n + i];
+    }
+  // Cholesky M = L L^T
+  std::vector<double> L((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = M[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(d > 0.0)) return false;
+    L[(size_t)j * n + j] = std::sqrt(d);
+    for (int i = j + 1; i < n; ++i) {
+      double v = M[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) v -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = v / L[(size_t)j * n + j];
+    }
+  }
+  // Linv = L^{-1} (lower triangular)
+  std::vector<double> Li((size_t)n * n, 0.0);
+  for (int c = 0; c < n; ++c)
+    for (int i = 0; i < n; ++i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) v -= L[(size_t)i * n + k] * Li[(size_t)k * n + c];
+      Li[(size_t)i * n + c] = v / L[(size_t)i * n + i];
+    }
+  // C = Linv T Linv^T
+  std::vector<double> W((size_t)n * n, 0.0), C((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double v = 0.0;
+      for (int k = 0; k < n; ++k) v += Li[(size_t)i * n + k] * T[(size_t)k * n + j];
+      W[(size_t)i * n + j] = v;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double v = 0.0;
+      for (int k = 0; k < n; ++k) v += W[(size_t)i * n + k] * Li[(size_t)j * n + k];
+      C[(size_t)i * n + j] = v;
+    }
+  // cyclic Jacobi: C = Q diag Q^T
+  std::vector<double> Q((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double c2 = C[(size_t)i * n + j] * C[(size_t)i * n + j];
+        tot += c2;
+        if (i != j) off += c2;
+      }
+    if (off <= 1e-32 * tot) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = C[(size_t)p * n + q];
+        if (apq == 0.0) continue;
+        const double app = C[(size_t)p * n + p], aqq = C[(size_t)q * n + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {   // C <- C J (columns p, q)
+          const double ckp = C[(size_t)k * n + p], ckq = C[(size_t)k * n + q];
+          C[(size_t)k * n + p] = c * ckp - sn * ckq;
+          C[(size_t)k * n + q] = sn * ckp + c * ckq;
+        }
+        for (int k = 0; k < n; ++k) {   // C <- J^T C (rows p, q)
+          const double cpk = C[(size_t)p * n + k], cqk = C[(size_t)q * n + k];
+          C[(size_t)p * n + k] = c * cpk - sn * cqk;
+          C[(size_t)q * n + k] = sn * cpk + c * cqk;
+        }
+        for (int k = 0; k < n; ++k) {   // Q <- Q J
+          const double qkp = Q[(size_t)k * n + p], qkq = Q[(size_t)k * n + q];
+          Q[(size_t)k * n + p] = c * qkp - sn * qkq;
+          Q[(size_t)k * n + q] = sn * qkp + c * qkq;
+        }
+      }
+  }
+  lam.assign(n, 0.0);
+  for (int k = 0; k < n; ++k) lam[k] = C[(size_t)k * n + k];
+  // V = L^{-T} Q
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      double v = 0.0;
+      for (int m = 0; m < n; ++m) v += Li[(size_t)m * n + i] * Q[(size_t)m * n + k];
+      V[(size_t)i * n + k] = v;
+    }
+  return true;
+}
+
 // Galerkin stencils of K on the coarse levels for variable diffusivity (2D).
 // K_0 is the 5-point operator with the face diffusivities (scaled by 1/h^2);
 // K_{l+1} = P^T K_l P / 4 with the tensor-linear interpolation P of
