@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--nu", type=int, default=2)
     ap.add_argument("--tail-max", type=int, default=0,
                     help="largest multigrid level (nodes) solved in one workgroup's LDS (0 = library default)")
+    ap.add_argument("--coarse-max", type=int, default=0,
+                    help="nodes of the exactly solved coarsest multigrid level (0 = library default)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-preconditioner arm")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=8, help="time steps in the CPU oracle sample")
@@ -70,7 +72,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     common = dict(restart=w.restart, tol=1e-8, inner_k=args.inner_k, cycles=args.cycles,
-                  nu1=args.nu, nu2=args.nu, mg_tail_max=args.tail_max)
+                  nu1=args.nu, nu2=args.nu, mg_tail_max=args.tail_max, coarse_max=args.coarse_max)
     t_setup = time.perf_counter()
     hp_mix = HeatProblem(w.dim, w.n, w.s, w.nt, w.T, precision=args.mixed, **common)
     f, u0 = heat_inputs.workload_inputs(w, hp_mix.stage_times())
@@ -141,7 +143,7 @@ def main():
         "config": {"workload": w.name, "dim": w.dim, "n": w.n, "s": w.s, "nt": w.nt,
                    "unknowns": hp_mix.U, "restart": w.restart, "tol": 1e-8,
                    "inner_k": args.inner_k, "cycles": args.cycles, "nu1": args.nu, "nu2": args.nu,
-                   "mg_tail_max": args.tail_max,
+                   "mg_tail_max": args.tail_max, "coarse_max": args.coarse_max,
                    "preconditioner": args.mixed, "parallelism": "single GPU"},
         "outer_iterations": st_mix["outer_iterations"], "relres": st_mix["relres"],
         "precond_ms_per_solve": st_mix["precond_ms"],

@@ -88,6 +88,10 @@ typedef struct aao_opts {
   int use_graph;           /* 1: replay P-tilde as a captured HIP graph        */
   int mg_tail_max;         /* largest multigrid level (nodes) solved inside one
                               workgroup's LDS (2D); 0 = 1024, capped by LDS    */
+  int coarse_max;          /* coarsening stops at a level of at most this many
+                              nodes, solved exactly; 0 = 256.  Up to 1024 for
+                              2D constant kappa (fast diagonalization), up to
+                              256 otherwise (dense inverse)                    */
 } aao_opts;
 
 /* Solve statistics (host struct filled by aao_solve*). */
@@ -104,7 +108,8 @@ typedef struct aao_stats {
 typedef struct aao_problem aao_problem;   /* opaque handle */
 
 /* Defaults: restart 30, maxit 100, tol 1e-8, inner_k 3, cycles 1,
- * nu1 = nu2 = 2, omega 0, precision FP64, use_graph 1, mg_tail_max 0.  With use_graph the
+ * nu1 = nu2 = 2, omega 0, precision FP64, use_graph 1, mg_tail_max 0,
+ * coarse_max 0.  With use_graph the
  * first application of P-tilde for a given (inner_k, cycles, transpose) is
  * captured into a HIP graph on a private stream and later applications
  * replay it on the handle's stream (inputs and outputs pass through fixed

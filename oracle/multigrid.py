@@ -10,7 +10,8 @@ iteration counts, never the solution of eq. (2.4).
 
 * Coarse nodes are every second fine node, 1-based fine indices 2, 4, ...,
   2 floor(n/2), so n_c = floor(n/2); coarsening stops once a level has at
-  most COARSE_MAX = 256 nodes, and that level is solved exactly.
+  most ``coarse_max`` nodes (default COARSE_MAX = 256), and that level is
+  solved exactly.
 * Prolongation P: (tensor-)linear interpolation, boundary values zero.
 * Restriction R = P^T / 2^d (full weighting); coarse operator R A P
   (Galerkin), so every level is symmetric positive definite.
@@ -63,12 +64,12 @@ def interpolation(n, dim):
 class Hierarchy:
     """Levels (A_l, P_l) for A_0 = I + a K."""
 
-    def __init__(self, K, n, dim, a):
+    def __init__(self, K, n, dim, a, coarse_max=COARSE_MAX):
         self.dim = dim
         self.sizes = [n]
         self.ops = [(sp.identity(K.shape[0], format="csr") + a * K).tocsr()]
         self.P = []
-        while self.sizes[-1] ** dim > COARSE_MAX and self.sizes[-1] > 1:
+        while self.sizes[-1] ** dim > coarse_max and self.sizes[-1] > 1:
             nf = self.sizes[-1]
             P = interpolation(nf, dim)
             R = P.T / (2.0 ** dim)

@@ -84,7 +84,7 @@ class StageOps:
     """Theta_hat, Rana's preconditioner and the shifted-block solvers of one problem."""
 
     def __init__(self, prob, inner_k=3, inner_tol=0.0, cycles=1, omega=None,
-                 nu1=1, nu2=1, exact_blocks=False):
+                 nu1=1, nu2=1, exact_blocks=False, coarse_max=multigrid.COARSE_MAX):
         self.prob = prob
         self.K = prob.K()
         self.Th = allatonce.theta_hat(prob, self.K)
@@ -96,7 +96,7 @@ class StageOps:
         self.nu1, self.nu2 = nu1, nu2
         self.exact_blocks = exact_blocks
         tau = prob.tau
-        self.hier = [multigrid.Hierarchy(self.K, prob.n, prob.dim, tau * self.L[i, i])
+        self.hier = [multigrid.Hierarchy(self.K, prob.n, prob.dim, tau * self.L[i, i], coarse_max)
                      for i in range(prob.s)]
         self._lu_blocks = None
         self._lu_theta = None

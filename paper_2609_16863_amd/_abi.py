@@ -23,7 +23,7 @@ class Desc(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("restart", c_int), ("maxit", c_int), ("tol", c_double), ("inner_k", c_int),
                 ("cycles", c_int), ("nu1", c_int), ("nu2", c_int), ("omega", c_double),
-                ("precision", c_int), ("use_graph", c_int), ("mg_tail_max", c_int)]
+                ("precision", c_int), ("use_graph", c_int), ("mg_tail_max", c_int), ("coarse_max", c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -23,7 +23,7 @@ def _ptr(t):
 
 
 def _make_opts(lib, *, restart, maxit, tol, inner_k, cycles, nu1, nu2, omega, precision, use_graph,
-               mg_tail_max):
+               mg_tail_max, coarse_max=0):
     opts = _abi.Opts()
     lib.aao_default_opts(ctypes.byref(opts))
     opts.restart, opts.maxit, opts.tol = restart, maxit, tol
@@ -32,6 +32,7 @@ def _make_opts(lib, *, restart, maxit, tol, inner_k, cycles, nu1, nu2, omega, pr
     opts.precision = _abi.PRECISIONS[precision]
     opts.use_graph = int(bool(use_graph))
     opts.mg_tail_max = int(mg_tail_max)
+    opts.coarse_max = int(coarse_max)
     return opts
 
 
@@ -51,12 +52,13 @@ class HeatProblem:
     GMRES iterations ``inner_k``, V-cycles ``cycles`` with ``nu1``/``nu2``
     Jacobi sweeps, and the preconditioner ``precision``
     ("fp64" | "fp32" | "bf16" | "fp16"); ``use_graph`` replays the
-    preconditioner as a captured HIP graph.
+    preconditioner as a captured HIP graph; ``coarse_max`` is the size of the
+    exactly solved coarsest multigrid level (0: 256 nodes).
     """
 
     def __init__(self, dim, n, s, nt, T=1.0, kappa=None, *, restart=30, maxit=100, tol=1e-8,
                  inner_k=3, cycles=1, nu1=2, nu2=2, omega=0.0, precision="fp64", use_graph=True,
-                 mg_tail_max=0, device="cuda"):
+                 mg_tail_max=0, coarse_max=0, device="cuda"):
         self._lib = _abi.load()
         self.dim, self.n, self.s, self.nt, self.T = dim, n, s, nt, float(T)
         self._kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
@@ -64,7 +66,7 @@ class HeatProblem:
                          None if self._kappa is None else self._kappa.ctypes.data)
         opts = _make_opts(self._lib, restart=restart, maxit=maxit, tol=tol, inner_k=inner_k, cycles=cycles,
                           nu1=nu1, nu2=nu2, omega=omega, precision=precision, use_graph=use_graph,
-                          mg_tail_max=mg_tail_max)
+                          mg_tail_max=mg_tail_max, coarse_max=coarse_max)
         self.precision = precision
         h = ctypes.c_void_p()
         code = self._lib.aao_create_problem(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h))
@@ -232,7 +234,7 @@ class HeatBatch:
     """
 
     def __init__(self, problems, *, streams=4, restart=30, maxit=100, tol=1e-8, inner_k=3, cycles=1,
-                 nu1=2, nu2=2, omega=0.0, precision="fp64", use_graph=True, mg_tail_max=0,
+                 nu1=2, nu2=2, omega=0.0, precision="fp64", use_graph=True, mg_tail_max=0, coarse_max=0,
                  device="cuda"):
         self._lib = _abi.load()
         self.count = len(problems)
@@ -248,7 +250,7 @@ class HeatBatch:
         self.tol = tol
         opts = _make_opts(self._lib, restart=restart, maxit=maxit, tol=tol, inner_k=inner_k, cycles=cycles,
                           nu1=nu1, nu2=nu2, omega=omega, precision=precision, use_graph=use_graph,
-                          mg_tail_max=mg_tail_max)
+                          mg_tail_max=mg_tail_max, coarse_max=coarse_max)
         h = ctypes.c_void_p()
         code = self._lib.aao_create_batch(descs, self.count, ctypes.byref(opts), int(streams), ctypes.byref(h))
         if code != 0:

@@ -20,7 +20,9 @@ constexpr int KMAX = 12;         // inner GMRES iterations per application
 constexpr int MMAX = 120;        // outer FGMRES restart length
 constexpr int DOTS_PER_PASS = 16;
 constexpr int RED_THREADS = 256;
-constexpr int COARSE_MAX = 256;  // the coarsest multigrid level (<= this many nodes) is solved exactly
+constexpr int COARSE_MAX = 256;        // default size of the exactly solved coarsest multigrid level
+constexpr int COARSE_DENSE_MAX = 256;  // largest coarsest level solved with a dense inverse
+constexpr int COARSE_FD_MAX = 1024;    // largest coarsest level solved by fast diagonalization (2D)
 
 // ---------------------------------------------------------------------------
 // Parameters passed to kernels by value
@@ -153,7 +155,8 @@ namespace aao {
 // setup.cpp (host only)
 bool radau_iia(int s, double* A, double* b, double* c);
 void crout_lower(int s, const double* A, double* L);
-void galerkin_1d(int n, int dim, double h, std::vector<int>& sizes, std::vector<std::vector<double>>& tri);
+void galerkin_1d(int n, int dim, double h, int coarse_max, std::vector<int>& sizes,
+                 std::vector<std::vector<double>>& tri);
 bool tensor_eigen(int n, const std::vector<double>& tri, std::vector<double>& V, std::vector<double>& lam);
 void galerkin_stencils_2d(const std::vector<int>& sizes, const std::vector<double>& faces, double ih2,
                           std::vector<std::vector<double>>& st9);

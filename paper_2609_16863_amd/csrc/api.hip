@@ -88,6 +88,7 @@ bool valid_opts(const aao_opts* o, std::string& why) {
   if (o->precision < AAO_PREC_FP64 || o->precision > AAO_PREC_FP16) { why = "unknown precision"; return false; }
   if (o->omega < 0.0 || o->omega >= 2.0) { why = "omega must be in [0, 2)"; return false; }
   if (o->mg_tail_max < 0) { why = "mg_tail_max must be >= 0"; return false; }
+  if (o->coarse_max < 0 || o->coarse_max > aao::COARSE_FD_MAX) { why = "coarse_max must be in [0, 1024]"; return false; }
   return true;
 }
 
@@ -115,6 +116,7 @@ void aao_default_opts(aao_opts* o) {
   o->precision = AAO_PREC_FP64;
   o->use_graph = 1;
   o->mg_tail_max = 0;
+  o->coarse_max = 0;
 }
 
 int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) {
@@ -183,8 +185,16 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
     }
   }
 
+  // 2D constant kappa solves the coarsest level by fast diagonalization (up
+  // to 1024 nodes); otherwise by a dense inverse (up to 256 nodes)
+  const int cmax = opts.coarse_max > 0 ? opts.coarse_max : aao::COARSE_MAX;
+  const bool fd_ok = d->dim == 2 && !d->kappa;
+  if (!fd_ok && cmax > aao::COARSE_DENSE_MAX) {
+    delete h;
+    return fail(nullptr, AAO_INVALID_ARG, "coarse_max above 256 needs 2D and constant kappa");
+  }
   std::vector<std::vector<double>> tri;
-  aao::galerkin_1d(d->n, d->dim, h->h, h->lev_n, tri);
+  aao::galerkin_1d(d->n, d->dim, h->h, cmax, h->lev_n, tri);
   h->lev_N.resize(h->lev_n.size());
   h->tri_off.assign(h->lev_n.size(), 0);
   for (size_t l = 0; l < h->lev_n.size(); ++l) {
@@ -202,18 +212,21 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
     }
   }
   // fast diagonalization of the coarsest level (2D, constant kappa)
-  if (d->dim == 2 && !h->vark) {
+  if (fd_ok) {
     const int lc = (int)h->lev_n.size() - 1;
     std::vector<double> V, lam;
     if (aao::tensor_eigen(h->lev_n[lc], tri[lc], V, lam)) {
       h->fd_n = h->lev_n[lc];
       h->fd_host = V;
       h->fd_host.insert(h->fd_host.end(), lam.begin(), lam.end());
+    } else if (h->lev_N.back() > aao::COARSE_DENSE_MAX) {
+      delete h;
+      return fail(nullptr, AAO_INVALID_ARG, "coarsest multigrid level not diagonalizable");
     }
   }
-  // exact inverses of the coarsest level, for the shifts tau L_ii (P-tilde)
-  // and tau LT_ii (its transpose)
-  {
+  // otherwise, exact inverses of the coarsest level, for the shifts tau L_ii
+  // (P-tilde) and tau LT_ii (its transpose)
+  if (h->fd_n == 0) {
     const int lc = (int)h->lev_n.size() - 1;
     h->cinv_N = h->lev_N[lc];
     for (int tr = 0; tr < 2; ++tr)

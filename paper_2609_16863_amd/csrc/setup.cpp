@@ -121,9 +121,10 @@ void crout_lower(int s, const double* A, double* L) {
 // boundary values), and M_{l+1} = P^T M_l P / 2, T_{l+1} = P^T T_l P / 2, so
 // that in d dimensions R = P^T / 2^d and the Galerkin operator R A_l P of
 // A_l = M(x)M + a (T(x)M + M(x)T) is again of that form.  Coarsening stops
-// once a level has at most COARSE_MAX nodes (that level is solved exactly).
+// once a level has at most coarse_max nodes (that level is solved exactly).
 // tri[l] = [Mlo, Md, Mup, Tlo, Td, Tup], each n_l long (level 0 included).
-void galerkin_1d(int n, int dim, double h, std::vector<int>& sizes, std::vector<std::vector<double>>& tri) {
+void galerkin_1d(int n, int dim, double h, int coarse_max, std::vector<int>& sizes,
+                 std::vector<std::vector<double>>& tri) {
   sizes.assign(1, n);
   int nf = n;
   std::vector<double> M(nf * nf, 0.0), T(nf * nf, 0.0);
@@ -147,7 +148,7 @@ void galerkin_1d(int n, int dim, double h, std::vector<int>& sizes, std::vector<
   };
   tri.assign(1, pack(M, T, nf));
   auto npow = [dim](int m) { double v = 1.0; for (int a = 0; a < dim; ++a) v *= m; return v; };
-  while (npow(nf) > COARSE_MAX && nf > 1) {
+  while (npow(nf) > coarse_max && nf > 1) {
     int nc = nf / 2;
     // P: nf x nc, coarse J at fine 2J+1 (0-based), neighbours 2J and 2J+2
     std::vector<double> P(nf * nc, 0.0);

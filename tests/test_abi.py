@@ -181,3 +181,20 @@ def test_batch_creation_offsets_and_errors():
     descs[1] = abi.Desc(2, 5, 1, 2, 1.0, None)
     assert lib.aao_create_batch(descs, 3, None, 0, ctypes.byref(h)) == -1
     assert lib.aao_create_batch(descs, 3, None, 17, ctypes.byref(h)) == -1
+
+
+def test_coarse_max_option():
+    """Coarsest level size: up to 1024 nodes for 2D constant kappa (fast
+    diagonalization), up to 256 for 3D or variable kappa (dense inverse)."""
+    abi, lib = _lib()
+    code, h = _create(abi, lib, dim=2, n=512, s=1, nt=1, coarse_max=1024)
+    assert code == 0
+    nodes = np.zeros(32, dtype=np.int64)
+    L, t = ctypes.c_int(), ctypes.c_int()
+    lib.aao_mg_levels(h, 32, nodes.ctypes.data, ctypes.byref(L), ctypes.byref(t))
+    assert list(nodes[: L.value]) == [512 ** 2, 256 ** 2, 128 ** 2, 64 ** 2, 32 ** 2]
+    lib.aao_destroy(h)
+    assert _create(abi, lib, dim=3, n=16, coarse_max=512)[0] == -1
+    assert _create(abi, lib, dim=2, n=16, kappa=np.ones(256), coarse_max=512)[0] == -1
+    assert _create(abi, lib, dim=2, n=16, coarse_max=2048)[0] == -1
+    assert _create(abi, lib, dim=3, n=16, coarse_max=256)[0] == 0

@@ -22,10 +22,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _oracle(p, transpose, stage, r_blocks, cycles, nu=2):
+def _oracle(p, transpose, stage, r_blocks, cycles, nu=2, coarse_max=multigrid.COARSE_MAX):
     A = p.A.T if transpose else p.A
     L, _ = tableau.crout(A)
-    H = multigrid.Hierarchy(p.K(), p.n, p.dim, p.tau * L[stage, stage])
+    H = multigrid.Hierarchy(p.K(), p.n, p.dim, p.tau * L[stage, stage], coarse_max)
     omega = 0.8 if p.dim == 2 else 6.0 / 7.0
     return np.stack([multigrid.solve(H, b, cycles, omega, nu, nu) for b in r_blocks])
 
@@ -133,3 +133,23 @@ def test_constant_kappa_array_matches_kappa_one():
     a = _run(hp1, r, 1, 2, False)
     b = _run(hpk, r, 1, 2, False)
     assert rel_err(b, a) <= 1e-13
+
+
+# A larger exactly solved coarsest level (fast diagonalization, 2D constant
+# kappa): 72 -> 36 -> 18 (exact), 130 -> 65 -> 32 (exact, 1024 nodes), and
+# 32 (the fine level itself); with the tail also holding the level above.
+@pytest.mark.parametrize("n,tail_max", [(72, 0), (130, 0), (130, 4096), (32, 0)])
+def test_apply_mg_coarse_max_1024(n, tail_max):
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    s, nt = 2, 2
+    p = allatonce.Problem(n, 2, s, nt, 1.0)
+    hp = HeatProblem(2, n, s, nt, 1.0, coarse_max=1024, mg_tail_max=tail_max)
+    rng = np.random.default_rng(41 + n)
+    for stage in range(s):
+        for transpose in (False, True):
+            r = rng.standard_normal((nt, p.N))
+            announce("apply_mg coarse_max 1024", n, "tail", tail_max, "stage", stage, "transpose", transpose)
+            z = _run(hp, r, stage, 2, transpose)
+            ref = _oracle(p, transpose, stage, r, 2, coarse_max=1024)
+            assert rel_err(z, ref) <= 1e-12, (stage, rel_err(z, ref))

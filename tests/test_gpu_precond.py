@@ -60,6 +60,19 @@ def test_apply_P_variable_kappa_fp64_matches_oracle(n, s, nt):
     assert rel_err(z, ref) <= 1e-10
 
 
+def test_apply_P_coarse_max_1024_matches_oracle():
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    n, s, nt = 72, 3, 3
+    p = allatonce.Problem(n, 2, s, nt, 1.0)
+    hp = HeatProblem(2, n, s, nt, 1.0, coarse_max=1024, nu1=2, nu2=2)
+    ops = precond.StageOps(p, inner_k=3, cycles=1, nu1=2, nu2=2, coarse_max=1024)
+    r = np.random.default_rng(23).standard_normal(p.U)
+    announce("apply_P coarse_max 1024", n, s, nt)
+    z = to_host(hp.apply_P(to_dev(r)))
+    assert rel_err(z, precond.apply_preconditioner(ops, r)) <= 1e-10
+
+
 @pytest.mark.parametrize("precision,tol", [("fp32", 2e-4), ("bf16", 5e-2), ("fp16", 2e-2)])
 def test_apply_P_low_precision_close_to_fp64_oracle(precision, tol):
     require_gpu()

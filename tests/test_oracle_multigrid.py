@@ -64,3 +64,19 @@ def test_contraction_factor(dim, n, a):
     e1 = np.linalg.norm(multigrid.solve(H, b, 4, omega) - xd)
     e2 = np.linalg.norm(multigrid.solve(H, b, 5, omega) - xd)
     assert e2 / e1 < 0.5
+
+
+@pytest.mark.parametrize("n,coarse_max", [(64, 1024), (70, 1024), (33, 64)])
+def test_coarse_max_sets_the_exact_level_and_cycles_still_converge(n, coarse_max):
+    K = grid.stiffness(n, 2)
+    H = multigrid.Hierarchy(K, n, 2, 0.05, coarse_max=coarse_max)
+    assert H.sizes[-1] ** 2 <= coarse_max < H.sizes[-2] ** 2
+    b = np.random.default_rng(9).standard_normal(n * n)
+    xd = spla.spsolve(H.ops[0].tocsc(), b)
+    x = multigrid.solve(H, b, cycles=40, omega=0.8)
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+    # one level only: the cycle is the exact solve
+    H1 = multigrid.Hierarchy(grid.stiffness(16, 2), 16, 2, 0.3, coarse_max=256)
+    b1 = np.random.default_rng(10).standard_normal(256)
+    assert H1.levels == 1
+    assert np.allclose(multigrid.vcycle(H1, b1), spla.spsolve(H1.ops[0].tocsc(), b1), rtol=1e-12, atol=1e-12)
