@@ -85,7 +85,7 @@ def main():
     if args.roofline_only:
         x = torch.randn(hp_mix.U, dtype=torch.float64, device=dev)
         out = {"roofline": measure_roofline(hp_mix, x, args.roofline_reps),
-               "roofline_vcycle": measure_vcycle(hp_mix, args.mixed, args.roofline_reps),
+               "roofline_vcycle": measure_vcycle(hp_mix, args.mixed, args.roofline_reps) if w.dim == 2 else None,
                "copy_reference": measure_copy(1 << 30, 5)}
         print(json.dumps(out))
         return
@@ -127,7 +127,7 @@ def main():
     # ---- roofline of the dominant kernel (live, HIP events) ------------------
     roofline = measure_roofline(hp_mix, x_mix, args.roofline_reps)
 
-    roofline_vcycle = measure_vcycle(hp_mix, args.mixed, args.roofline_reps)
+    roofline_vcycle = measure_vcycle(hp_mix, args.mixed, args.roofline_reps) if w.dim == 2 else None
 
     # ---- CPU oracle baseline on a bounded sample -----------------------------
     cpu = None
@@ -162,7 +162,8 @@ def measure_roofline(hp, x, reps):
     nbytes = 16.0 * hp.U
     gbs = nbytes / sec / 1e9
     traffic = measured_traffic("k_apply_A_2d") if hp.n == 512 and hp.s == 3 and hp.nt == 64 else None
-    return {"kernel": "k_apply_A_2d", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    return {"kernel": "k_apply_A_2d" if hp.dim == 2 else "k_apply_A", "bound": "hbm", "achieved": gbs,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "B per launch",
             "bytes_per_launch": nbytes, "avg_launch_us": sec * 1e6}
 

@@ -7,4 +7,5 @@ stage preconditioner, geometric-multigrid V-cycles on the shifted blocks),
 plus the transposed (adjoint) solve.  All arithmetic runs in hand-written HIP
 kernels for gfx950 behind the C ABI of include/aao_heat.h.
 """
+from .autograd import heat_solve  # noqa: F401
 from .binding import AAOError, HeatBatch, HeatProblem  # noqa: F401

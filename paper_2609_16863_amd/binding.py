@@ -64,6 +64,9 @@ class HeatProblem:
         self._kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
         desc = _abi.Desc(dim, n, s, nt, float(T),
                          None if self._kappa is None else self._kappa.ctypes.data)
+        self.options = dict(restart=restart, maxit=maxit, tol=tol, inner_k=inner_k, cycles=cycles, nu1=nu1,
+                            nu2=nu2, omega=omega, precision=precision, use_graph=use_graph,
+                            mg_tail_max=mg_tail_max, coarse_max=coarse_max, device=device)
         opts = _make_opts(self._lib, restart=restart, maxit=maxit, tol=tol, inner_k=inner_k, cycles=cycles,
                           nu1=nu1, nu2=nu2, omega=omega, precision=precision, use_graph=use_graph,
                           mg_tail_max=mg_tail_max, coarse_max=coarse_max)

@@ -153,3 +153,30 @@ def test_gradient_central_differences_on_gpu():
     fd = (loss(kappa, f + eps * df, u0 + eps * du) - loss(kappa, f - eps * df, u0 - eps * du)) / (2 * eps)
     lin = float(np.sum(gf.reshape(f.shape) * df) + gu0 @ du)
     assert abs(fd - lin) <= 1e-6 * abs(lin)
+
+
+def test_autograd_heat_solve_gradients_match_oracle():
+    """torch.autograd through the differentiable solve (forward FGMRES,
+    backward adjoint FGMRES + log-kappa gradient) equals the oracle's
+    gradients of the tracking loss."""
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem, heat_solve
+    sp = _gradient_specs()[1]
+    kappa, f, u0 = _problem_inputs(sp)
+    vt = _targets([sp], [(kappa, f, u0)])[0]
+    base = HeatProblem(2, sp["n"], sp["s"], sp["nt"], 1.0, precision="fp32", tol=1e-12, maxit=300)
+    ft = to_dev(f).requires_grad_(True)
+    ut = to_dev(u0).requires_grad_(True)
+    th = to_dev(np.log(kappa)).requires_grad_(True)
+    announce("autograd heat_solve", sp["n"])
+    x = heat_solve(ft, ut, base, theta=th)
+    N, nt = sp["n"] ** 2, sp["nt"]
+    v = x[: (nt + 1) * N].view(nt + 1, N)
+    loss = 0.5 * ((v[1:] - to_dev(vt[1:])) ** 2).sum()
+    loss.backward()
+    p = allatonce.Problem(sp["n"], 2, sp["s"], nt, 1.0, kappa=kappa)
+    Lr, gfr, gu0r, gkr = adjoint.gradients(p, f, u0, vt)
+    assert abs(loss.item() - Lr) <= 1e-9 * abs(Lr)
+    assert rel_err(to_host(ft.grad), gfr) <= 1e-7
+    assert rel_err(to_host(ut.grad), gu0r) <= 1e-7
+    assert rel_err(to_host(th.grad), gkr) <= 1e-7
