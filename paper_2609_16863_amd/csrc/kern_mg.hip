@@ -550,16 +550,33 @@ __device__ __forceinline__ void tile_inv_diag(Tile<KIND, R, C>& sm, const LevelO
   }
 }
 
+// Rana's coupling terms of a stage solve, formed on the fly in the level-0
+// down kernel: the right-hand side is b - sum_{l < NZ} c_l K z_l.
+template <class TF, class C>
+struct CplArgs {
+  const TF* z;        // z_0 of instance 0
+  int64_t sz, zs;     // instance stride, stride between z_l
+  C c[SMAX - 1];      // tau L_il
+  TF* out;            // the formed right-hand side (owned nodes written)
+  int64_t so;
+};
+
 // Down: x_NU (from zero, or from x0 when given) -> xout, and
 // b_c = R (b - A x_NU) -> bc, on the fine nodes of coarse tile (I0.., J0..).
-template <int KIND, int NU, class TF, class TC, class C>
+// NZ > 0 (level 0 only): b is first replaced by b - sum_l c_l K z_l, staged
+// with one more halo ring of each z_l, and written to cpl.out.
+template <int KIND, int NU, class TF, class TC, class C, int NZ>
 __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_t sb, const TF* __restrict__ x0,
                                                 int64_t sx0, TF* __restrict__ xout, int64_t sxo, TC* __restrict__ bc,
-                                                int64_t sbc, LevelOp<C> op, int nc, C omega, int gx, int gy) {
+                                                int64_t sbc, LevelOp<C> op, int nc, C omega, int gx, int gy,
+                                                CplArgs<TF, C> cpl) {
   constexpr int R = NU + 1;
   using T = Tile<KIND, R, C>;
   constexpr int W = T::W, H = T::H;
+  constexpr int ZW = W + 2, ZH = H + 2, ZNE = NZ > 0 ? ZW * ZH : 1, ZIT = (ZNE + 255) / 256;
+  static_assert(NZ == 0 || KIND == KIND_FINE || KIND == KIND_FINE_VK, "coupling terms live on level 0");
   __shared__ T sm;
+  __shared__ C szt[NZ > 0 ? NZ : 1][ZNE];
   const int tid = threadIdx.x;
   const int nf = op.n;
   const int L = xcd_tile((int)blockIdx.x, (int)gridDim.x);  // grid: gx * gy tiles per block
@@ -579,6 +596,24 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
     bv[it] = in ? ld<TF, C>(bi + g) : C(0);
     xv[it] = (in && xi) ? ld<TF, C>(xi + g) : C(0);
   }
+  if constexpr (NZ > 0) {
+    C zv[NZ][ZIT];
+#pragma unroll
+    for (int l = 0; l < NZ; ++l)
+#pragma unroll
+      for (int it = 0; it < ZIT; ++it) {
+        const int t = tid + it * 256, gi = ox - 1 + t % ZW, gj = oy - 1 + t / ZW;
+        const bool in = t < ZNE && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+        zv[l][it] = in ? ld<TF, C>(cpl.z + inst * cpl.sz + l * cpl.zs + (int64_t)gj * nf + gi) : C(0);
+      }
+#pragma unroll
+    for (int l = 0; l < NZ; ++l)
+#pragma unroll
+      for (int it = 0; it < ZIT; ++it) {
+        const int t = tid + it * 256;
+        if (t < ZNE) szt[l][t] = zv[l][it];
+      }
+  }
   tile_stage_op<KIND, R, C>(sm, op, ox, oy);
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
@@ -589,6 +624,39 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
     }
   }
   __syncthreads();
+  if constexpr (NZ > 0) {
+    // b <- b - sum_l c_l K z_l at every in-domain tile node (each thread
+    // updates only the nodes it reads later); owned nodes go to cpl.out
+    const int hx = (I0 + TCX >= nc) ? nf : 2 * (I0 + TCX), hy = (J0 + TCY >= nc) ? nf : 2 * (J0 + TCY);
+    const C inv_a = C(1) / op.a;
+#pragma unroll
+    for (int it = 0; it < T::IT; ++it) {
+      const int t = tid + it * 256;
+      if (t < T::NE) {
+        const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
+        if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
+          const int zt = (ty + 1) * ZW + tx + 1;
+          C acc = sm.b[t];
+#pragma unroll
+          for (int l = 0; l < NZ; ++l) {
+            const C* z = szt[l];
+            const C c0 = z[zt];
+            C kz;
+            if constexpr (KIND == KIND_FINE) {
+              kz = op.ih2 * (C(4) * c0 - z[zt - 1] - z[zt + 1] - z[zt - ZW] - z[zt + ZW]);
+            } else {   // staged face coefficients carry a / h^2
+              kz = inv_a * (sm.f[t] * (c0 - z[zt - 1]) + sm.f[T::NE + t] * (c0 - z[zt + 1]) +
+                            sm.f[2 * T::NE + t] * (c0 - z[zt - ZW]) + sm.f[3 * T::NE + t] * (c0 - z[zt + ZW]));
+            }
+            acc -= cpl.c[l] * kz;
+          }
+          sm.b[t] = acc;
+          if (gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy)
+            st<TF, C>(cpl.out + inst * cpl.so + (int64_t)gj * nf + gi, acc);
+        }
+      }
+    }
+  }
   tile_finish_coef<KIND, R, C>(k9, sm);
   tile_inv_diag<KIND, R, C>(sm, op, ox, oy, omega, k9);
   C* cur = sm.x0;
@@ -1278,20 +1346,34 @@ hipError_t Multigrid<TI, TM>::tail(int stage, Vec x, Vec b, bool zero_init, int 
 }
 
 template <class TI, class TM>
-hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, int64_t sx0, Vec xout, Vec bc, int B) {
+hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, int64_t sx0, Vec xout, Vec bc, int B,
+                                     const Coupling* cpl) {
   const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
   const int nc = h_->lev_n[l + 1];
   const C omega = (C)h_->omega;
   const int gx = (nc + TCX - 1) / TCX, gy = (nc + TCY - 1) / TCY;
   const dim3 g((unsigned)(gx * gy * B));
   const int nu = h_->opts.nu1;
-#define DN(K, NU, TF) hipLaunchKernelGGL((k_down2d<K, NU, TF, TM, C>), g, dim3(256), 0, st_, (const TF*)b.ptr, b.stride, (const TF*)x0, sx0, (TF*)xout.ptr, xout.stride, (TM*)bc.ptr, bc.stride, op, nc, omega, gx, gy)
-#define DN_NU(K, TF) do { if (nu == 1) DN(K, 1, TF); else if (nu == 2) DN(K, 2, TF); else DN(K, 3, TF); } while (0)
-  if (l == 0) {
-    if (h_->vark) DN_NU(KIND_FINE_VK, TI); else DN_NU(KIND_FINE, TI);
-  } else {
-    if (h_->vark) DN_NU(KIND_STENCIL9, TM); else DN_NU(KIND_TENSOR, TM);
+  const int nz = (l == 0 && cpl) ? cpl->nz : 0;
+  CplArgs<TI, C> ca{};
+  if (nz > 0) {
+    ca.z = cpl->z;
+    ca.sz = cpl->sz;
+    ca.zs = cpl->zstride;
+    for (int q = 0; q < nz; ++q) ca.c[q] = (C)(h_->tau * cpl->Lc[cpl->nz * h_->s + q]);
+    ca.out = cpl->out;
+    ca.so = cpl->so;
   }
+  CplArgs<TM, C> cm{};
+#define DN(K, NU, TF, NZ, CA) hipLaunchKernelGGL((k_down2d<K, NU, TF, TM, C, NZ>), g, dim3(256), 0, st_, (const TF*)b.ptr, b.stride, (const TF*)x0, sx0, (TF*)xout.ptr, xout.stride, (TM*)bc.ptr, bc.stride, op, nc, omega, gx, gy, CA)
+#define DN_NU(K, TF, NZ, CA) do { if (nu == 1) DN(K, 1, TF, NZ, CA); else if (nu == 2) DN(K, 2, TF, NZ, CA); else DN(K, 3, TF, NZ, CA); } while (0)
+#define DN_Z(K) do { if (nz == 0) DN_NU(K, TI, 0, ca); else if (nz == 1) DN_NU(K, TI, 1, ca); else DN_NU(K, TI, 2, ca); } while (0)
+  if (l == 0) {
+    if (h_->vark) DN_Z(KIND_FINE_VK); else DN_Z(KIND_FINE);
+  } else {
+    if (h_->vark) DN_NU(KIND_STENCIL9, TM, 0, cm); else DN_NU(KIND_TENSOR, TM, 0, cm);
+  }
+#undef DN_Z
 #undef DN_NU
 #undef DN
   return hipGetLastError();
@@ -1320,7 +1402,8 @@ hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec
 // One V-cycle on level l.  `pre` = the first (pointwise) sweep from zero was
 // already written into x by the restriction of the level above.
 template <class TI, class TM>
-hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_init, bool pre, int B, Vec* result) {
+hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_init, bool pre, int B, Vec* result,
+                                     const Coupling* cpl) {
   auto& P = h_->plan;
   if (l >= l0_) {
     MG_TRY(tail(stage, x, b, zero_init, B));
@@ -1348,7 +1431,8 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
     const int64_t Nc = h_->lev_N[l + 1];
     Vec bc{h_->ws + P.mgB[l + 1], Nc};
     Vec xc{h_->ws + P.mgX[l + 1], Nc};
-    MG_TRY(down2d(l, stage, b, zero_init ? nullptr : x.ptr, x.stride, tmp, bc, B));
+    MG_TRY(down2d(l, stage, b, zero_init ? nullptr : x.ptr, x.stride, tmp, bc, B, cpl));
+    if (cpl && cpl->nz > 0) b = Vec{cpl->out, cpl->so};   // the formed right-hand side
     Vec ec{};
     MG_TRY(vcycle(l + 1, stage, xc, bc, true, false, B, &ec));
     MG_TRY(up2d(l, stage, tmp, ec, b, x, B));
@@ -1409,13 +1493,21 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
 }
 
 template <class TI, class TM>
-hipError_t Multigrid<TI, TM>::solve(int stage, BVec<TI> x, BVec<const TI> rhs, int B, int cycles) {
+hipError_t Multigrid<TI, TM>::solve(int stage, BVec<TI> x, BVec<const TI> rhs, int B, int cycles,
+                                    const Coupling* cpl) {
   Vec xv{x.ptr, x.stride};
   Vec bv{const_cast<TI*>(rhs.ptr), rhs.stride};
+  const bool fused = cpl && cpl->nz > 0 && h_->dim == 2 && h_->opts.nu1 <= 3 && h_->opts.nu2 <= 3 && l0_ > 0;
+  if (cpl && cpl->nz > 0 && !fused) {
+    // the level-0 kernel that would form the coupling does not run: form it first
+    MG_TRY(rana_rhs<TI>(h_, cpl->Lc, cpl->nz, rhs.ptr, rhs.stride, cpl->z, cpl->sz, cpl->out, cpl->so, B, st_));
+    bv = Vec{cpl->out, cpl->so};
+  }
   for (int c = 0; c < cycles; ++c) {
     Vec res{};
-    MG_TRY(vcycle(0, stage, xv, bv, c == 0, false, B, &res));
+    MG_TRY(vcycle(0, stage, xv, bv, c == 0, false, B, &res, (fused && c == 0) ? cpl : nullptr));
     if (res.ptr != xv.ptr) return hipErrorUnknown;   // the driver always ends in x
+    if (fused && c == 0) bv = Vec{cpl->out, cpl->so};
   }
   return hipSuccess;
 }

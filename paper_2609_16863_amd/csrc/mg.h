@@ -17,10 +17,25 @@ class Multigrid {
   // L: lower Crout factor (s x s, row-major) whose diagonal gives the shifts.
   Multigrid(aao_problem* h, hipStream_t st, const double* L);
 
+  // Rana's coupling for stage i = nz > 0: the block right-hand side is
+  // rhs - tau sum_{l < i} Lc[i][l] K z_l (z_l at z + l * zstride, instance
+  // stride sz; Lc the s x s lower factor), formed inside the first level-0
+  // kernel where the tiled path runs (else by a separate kernel) and written
+  // to `out` (stride so).
+  struct Coupling {
+    const TI* z = nullptr;
+    int64_t sz = 0, zstride = 0;
+    int nz = 0;
+    const double* Lc = nullptr;
+    TI* out = nullptr;
+    int64_t so = 0;
+  };
+
   // x_b <- (`cycles` V-cycles from zero) ~ (I + tau L_ii K)^{-1} rhs_b for
   // b = 0..B-1.  x and rhs are level-0 vectors with their own instance
-  // strides; B <= nt.
-  hipError_t solve(int stage, BVec<TI> x, BVec<const TI> rhs, int B, int cycles);
+  // strides; B <= nt.  With `cpl`, the right-hand side is rhs minus the
+  // coupling terms (see Coupling).
+  hipError_t solve(int stage, BVec<TI> x, BVec<const TI> rhs, int B, int cycles, const Coupling* cpl = nullptr);
 
   // First level solved by the one-workgroup LDS tail (= levels when none).
   int tail_level() const { return l0_; }
@@ -30,13 +45,15 @@ class Multigrid {
     void* ptr;
     int64_t stride;
   };
-  hipError_t vcycle(int l, int stage, Vec x, Vec b, bool zero_init, bool pre, int B, Vec* result);
+  hipError_t vcycle(int l, int stage, Vec x, Vec b, bool zero_init, bool pre, int B, Vec* result,
+                    const Coupling* cpl = nullptr);
   hipError_t smooth(int l, int stage, Vec xin, Vec xout, Vec b, bool zero_init, int B);
   hipError_t resid_restrict(int l, int stage, Vec x, Vec b, Vec bc, Vec xc, bool zero_next, int B);
   hipError_t prolong(int l, Vec xin, Vec ec, Vec xout, int B);
   hipError_t prolong_smooth0(int stage, Vec xin, Vec ec, Vec b, Vec xout, int B);
   hipError_t tail(int stage, Vec x, Vec b, bool zero_init, int B);
-  hipError_t down2d(int l, int stage, Vec b, const void* x0, int64_t sx0, Vec xout, Vec bc, int B);
+  hipError_t down2d(int l, int stage, Vec b, const void* x0, int64_t sx0, Vec xout, Vec bc, int B,
+                    const Coupling* cpl = nullptr);
   hipError_t up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec xout, int B);
   const C* coarse_inv(int stage) const;
 

@@ -17,6 +17,7 @@
 // Rana's factor of A_RK^T).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <vector>
@@ -92,12 +93,16 @@ class Precond {
       TI* Zj = inZ_ + (int64_t)j * UV;
       // Rana: forward substitution over the stages
       for (int i = 0; i < h_->s; ++i) {
-        BVec<const TI> b{Vj, sN};
-        if (i > 0) {
-          TRY(rana_rhs<TI>(h_, Lc_, i, Vj + (int64_t)i * N, sN, Zj, sN, rana_, N, B, st_));
-          b = BVec<const TI>{rana_, N};
-        }
-        TRY(mg_.solve(i, BVec<TI>{Zj + (int64_t)i * N, sN}, b, B, cycles_));
+        typename Multigrid<TI, TM>::Coupling cpl;
+        cpl.z = Zj;
+        cpl.sz = sN;
+        cpl.zstride = N;
+        cpl.nz = i;
+        cpl.Lc = Lc_;
+        cpl.out = rana_;
+        cpl.so = N;
+        TRY(mg_.solve(i, BVec<TI>{Zj + (int64_t)i * N, sN}, BVec<const TI>{Vj + (int64_t)i * N, sN}, B, cycles_,
+                      i > 0 ? &cpl : nullptr));
       }
       TRY(theta_apply<TI>(h_, tab_, Zj, sN, inW_, sN, B, st_));
       // classical Gram-Schmidt, twice: h1 = V^T w; w -= V h1, h2 = V^T w,
