@@ -132,6 +132,7 @@ struct aao_problem {
   } plan{};
   int pi_bytes = 8;                           // inner (GMRES) storage bytes
   int pm_bytes = 8;                           // multigrid storage bytes
+  double mg_scale = 1.0;                      // coarse-level vectors are stored times this (FP16 storage)
 
   hipStream_t stream = nullptr;
   size_t lds_budget = 65536;                  // LDS bytes per workgroup for the multigrid tail

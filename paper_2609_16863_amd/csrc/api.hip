@@ -152,6 +152,13 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
   h->omega = opts.omega > 0.0 ? opts.omega : (d->dim == 2 ? 0.8 : 6.0 / 7.0);
   h->pi_bytes = opts.precision == AAO_PREC_FP64 ? 8 : 4;
   h->pm_bytes = opts.precision == AAO_PREC_FP64 ? 8 : (opts.precision == AAO_PREC_FP32 ? 4 : 2);
+  // FP16 multigrid storage: the V-cycle's right-hand sides are unit-norm
+  // Krylov vectors over s N entries, so their entries are near (s N)^{-1/2};
+  // the coarse levels store their vectors times the power of two nearest to
+  // (s N)^{1/2}, which keeps them near 1, well inside FP16's normal range
+  // (the cycle is linear below level 0, so only the level-0 transfers see it).
+  if (opts.precision == AAO_PREC_FP16)
+    h->mg_scale = std::ldexp(1.0, (int)std::lround(0.5 * std::log2((double)d->s * (double)h->N)));
 
   h->tab.s = d->s;
   h->tab.tau = h->tau;

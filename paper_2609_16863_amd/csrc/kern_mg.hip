@@ -243,7 +243,7 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict(const TF* __restrict__ x
                                                         const TF* __restrict__ b, int64_t sb,
                                                         TC* __restrict__ bc, int64_t sbc, TC* __restrict__ xc,
                                                         int64_t sxc, LevelOp<C> opf, LevelOp<C> opc, C omega,
-                                                        int zero_next) {
+                                                        int zero_next, C bscale) {
   const int pc = blockIdx.x * TPB + threadIdx.x;
   if (pc >= opc.N) return;
   const int64_t inst = blockIdx.y;
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict(const TF* __restrict__ x
       }
     }
   }
-  acc *= DIM == 3 ? C(0.125) : C(0.25);
+  acc *= (DIM == 3 ? C(0.125) : C(0.25)) * bscale;
   st<TC, C>(bc + inst * sbc + pc, acc);
   if (zero_next) st<TC, C>(xc + inst * sxc + pc, omega * acc / level_diag<DIM, KIND_TENSOR, C>(opc, pc, I, J, K));
 }
@@ -286,7 +286,7 @@ template <int DIM, bool VK, class TX, class TE, class C>
 __global__ __launch_bounds__(TPB) void k_prolong_smooth(const TX* __restrict__ xin, int64_t sxin,
                                                         const TE* __restrict__ ec, int64_t sec,
                                                         const TX* __restrict__ b, int64_t sb, TX* __restrict__ xout,
-                                                        int64_t sxout, LevelOp<C> op, int nc, C omega) {
+                                                        int64_t sxout, LevelOp<C> op, int nc, C omega, C escale) {
   const int p = blockIdx.x * TPB + threadIdx.x;
   if (p >= op.N) return;
   const int64_t inst = blockIdx.y;
@@ -295,7 +295,9 @@ __global__ __launch_bounds__(TPB) void k_prolong_smooth(const TX* __restrict__ x
   node_coords<DIM>(p, n, i, j, k);
   const TX* xi = xin + inst * sxin;
   const TE* e = ec + inst * sec;
-  auto y = [&](int q, int qi, int qj, int qk) { return ld<TX, C>(xi + q) + prolong_at<DIM, TE, C>(e, nc, qi, qj, qk); };
+  auto y = [&](int q, int qi, int qj, int qk) {
+    return ld<TX, C>(xi + q) + escale * prolong_at<DIM, TE, C>(e, nc, qi, qj, qk);
+  };
   const C yp = y(p, i, j, k);
   const C xm = i > 0 ? y(p - 1, i - 1, j, k) : C(0);
   const C xp = i + 1 < n ? y(p + 1, i + 1, j, k) : C(0);
@@ -569,7 +571,7 @@ template <int KIND, int NU, class TF, class TC, class C, int NZ>
 __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_t sb, const TF* __restrict__ x0,
                                                 int64_t sx0, TF* __restrict__ xout, int64_t sxo, TC* __restrict__ bc,
                                                 int64_t sbc, LevelOp<C> op, int nc, C omega, int gx, int gy,
-                                                CplArgs<TF, C> cpl) {
+                                                CplArgs<TF, C> cpl, C bscale) {
   constexpr int R = NU + 1;
   using T = Tile<KIND, R, C>;
   constexpr int W = T::W, H = T::H;
@@ -700,8 +702,9 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
     const int cx = c % TCX, cy = c / TCX, I = I0 + cx, J = J0 + cy;
     if (I >= nc || J >= nc) continue;
     const int tc = (2 * cy + 1 + R) * W + (2 * cx + 1 + R);
-    const C acc = C(0.25) * (nxt[tc] + C(0.5) * (nxt[tc - 1] + nxt[tc + 1] + nxt[tc - W] + nxt[tc + W]) +
-                             C(0.25) * (nxt[tc - W - 1] + nxt[tc - W + 1] + nxt[tc + W - 1] + nxt[tc + W + 1]));
+    const C acc = C(0.25) * bscale *
+                  (nxt[tc] + C(0.5) * (nxt[tc - 1] + nxt[tc + 1] + nxt[tc - W] + nxt[tc + W]) +
+                   C(0.25) * (nxt[tc - W - 1] + nxt[tc - W + 1] + nxt[tc + W - 1] + nxt[tc + W + 1]));
     st<TC, C>(bc + inst * sbc + J * nc + I, acc);
   }
   // owned fine nodes: [2 I0, 2 (I0 + TCX)) per axis, the last tile to the end
@@ -725,7 +728,8 @@ __device__ __forceinline__ int floor_half(int v) { return v >= 0 ? v / 2 : -((1 
 template <int KIND, int NU, class TF, class TE, class C>
 __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_t sxi, const TE* __restrict__ e,
                                               int64_t se, const TF* __restrict__ b, int64_t sb, TF* __restrict__ xout,
-                                              int64_t sxo, LevelOp<C> op, int nc, C omega, int gx, int gy) {
+                                              int64_t sxo, LevelOp<C> op, int nc, C omega, int gx, int gy,
+                                              C escale) {
   constexpr int R = NU;
   using T = Tile<KIND, R, C>;
   constexpr int W = T::W, H = T::H;
@@ -754,7 +758,7 @@ __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_
   for (int it = 0; it < CIT; ++it) {
     const int t = tid + it * 256, I = cx0 + t % CW, J = cy0 + t / CW;
     const bool in = t < CNE && I >= 0 && I < nc && J >= 0 && J < nc;
-    ev[it] = in ? ld<TE, C>(e + inst * se + (int64_t)J * nc + I) : C(0);
+    ev[it] = in ? escale * ld<TE, C>(e + inst * se + (int64_t)J * nc + I) : C(0);
   }
   tile_stage_op<KIND, R, C>(sm, op, ox, oy);
 #pragma unroll
@@ -1262,13 +1266,14 @@ hipError_t Multigrid<TI, TM>::resid_restrict(int l, int stage, Vec x, Vec b, Vec
   const dim3 g = grid2(opc.N, B);
   const int d3 = h_->dim == 3, z = (int)zero_next;
   if (l == 0) {
-#define RR0(D, K) hipLaunchKernelGGL((k_resid_restrict<D, K, TI, TM, C>), g, dim3(TPB), 0, st_, (const TI*)x.ptr, x.stride, (const TI*)b.ptr, b.stride, (TM*)bc.ptr, bc.stride, (TM*)xc.ptr, xc.stride, opf, opc, omega, z)
+    const C bs = (C)h_->mg_scale;
+#define RR0(D, K) hipLaunchKernelGGL((k_resid_restrict<D, K, TI, TM, C>), g, dim3(TPB), 0, st_, (const TI*)x.ptr, x.stride, (const TI*)b.ptr, b.stride, (TM*)bc.ptr, bc.stride, (TM*)xc.ptr, xc.stride, opf, opc, omega, z, bs)
     if (h_->vark) { if (d3) RR0(3, KIND_FINE_VK); else RR0(2, KIND_FINE_VK); }
     else { if (d3) RR0(3, KIND_FINE); else RR0(2, KIND_FINE); }
 #undef RR0
   } else {
-    if (d3) hipLaunchKernelGGL((k_resid_restrict<3, KIND_TENSOR, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)x.ptr, x.stride, (const TM*)b.ptr, b.stride, (TM*)bc.ptr, bc.stride, (TM*)xc.ptr, xc.stride, opf, opc, omega, z);
-    else hipLaunchKernelGGL((k_resid_restrict<2, KIND_TENSOR, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)x.ptr, x.stride, (const TM*)b.ptr, b.stride, (TM*)bc.ptr, bc.stride, (TM*)xc.ptr, xc.stride, opf, opc, omega, z);
+    if (d3) hipLaunchKernelGGL((k_resid_restrict<3, KIND_TENSOR, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)x.ptr, x.stride, (const TM*)b.ptr, b.stride, (TM*)bc.ptr, bc.stride, (TM*)xc.ptr, xc.stride, opf, opc, omega, z, C(1));
+    else hipLaunchKernelGGL((k_resid_restrict<2, KIND_TENSOR, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)x.ptr, x.stride, (const TM*)b.ptr, b.stride, (TM*)bc.ptr, bc.stride, (TM*)xc.ptr, xc.stride, opf, opc, omega, z, C(1));
   }
   return hipGetLastError();
 }
@@ -1294,7 +1299,8 @@ hipError_t Multigrid<TI, TM>::prolong_smooth0(int stage, Vec xin, Vec ec, Vec b,
   const int nc = h_->lev_n[1];
   const C omega = (C)h_->omega;
   const dim3 g = grid2(op.N, B);
-#define PS0(D, V) hipLaunchKernelGGL((k_prolong_smooth<D, V, TI, TM, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (const TM*)ec.ptr, ec.stride, (const TI*)b.ptr, b.stride, (TI*)xout.ptr, xout.stride, op, nc, omega)
+  const C es = (C)(1.0 / h_->mg_scale);
+#define PS0(D, V) hipLaunchKernelGGL((k_prolong_smooth<D, V, TI, TM, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (const TM*)ec.ptr, ec.stride, (const TI*)b.ptr, b.stride, (TI*)xout.ptr, xout.stride, op, nc, omega, es)
   if (h_->dim == 3) { if (h_->vark) PS0(3, true); else PS0(3, false); }
   else { if (h_->vark) PS0(2, true); else PS0(2, false); }
 #undef PS0
@@ -1365,7 +1371,8 @@ hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, in
     ca.so = cpl->so;
   }
   CplArgs<TM, C> cm{};
-#define DN(K, NU, TF, NZ, CA) hipLaunchKernelGGL((k_down2d<K, NU, TF, TM, C, NZ>), g, dim3(256), 0, st_, (const TF*)b.ptr, b.stride, (const TF*)x0, sx0, (TF*)xout.ptr, xout.stride, (TM*)bc.ptr, bc.stride, op, nc, omega, gx, gy, CA)
+  const C bs = l == 0 ? (C)h_->mg_scale : C(1);
+#define DN(K, NU, TF, NZ, CA) hipLaunchKernelGGL((k_down2d<K, NU, TF, TM, C, NZ>), g, dim3(256), 0, st_, (const TF*)b.ptr, b.stride, (const TF*)x0, sx0, (TF*)xout.ptr, xout.stride, (TM*)bc.ptr, bc.stride, op, nc, omega, gx, gy, CA, bs)
 #define DN_NU(K, TF, NZ, CA) do { if (nu == 1) DN(K, 1, TF, NZ, CA); else if (nu == 2) DN(K, 2, TF, NZ, CA); else DN(K, 3, TF, NZ, CA); } while (0)
 #define DN_Z(K) do { if (nz == 0) DN_NU(K, TI, 0, ca); else if (nz == 1) DN_NU(K, TI, 1, ca); else DN_NU(K, TI, 2, ca); } while (0)
   if (l == 0) {
@@ -1387,7 +1394,8 @@ hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec
   const int gx = (nc + TCX - 1) / TCX, gy = (nc + TCY - 1) / TCY;
   const dim3 g((unsigned)(gx * gy * B));
   const int nu = h_->opts.nu2;
-#define UP(K, NU, TF) hipLaunchKernelGGL((k_up2d<K, NU, TF, TM, C>), g, dim3(256), 0, st_, (const TF*)xin.ptr, xin.stride, (const TM*)ec.ptr, ec.stride, (const TF*)b.ptr, b.stride, (TF*)xout.ptr, xout.stride, op, nc, omega, gx, gy)
+  const C es = l == 0 ? (C)(1.0 / h_->mg_scale) : C(1);
+#define UP(K, NU, TF) hipLaunchKernelGGL((k_up2d<K, NU, TF, TM, C>), g, dim3(256), 0, st_, (const TF*)xin.ptr, xin.stride, (const TM*)ec.ptr, ec.stride, (const TF*)b.ptr, b.stride, (TF*)xout.ptr, xout.stride, op, nc, omega, gx, gy, es)
 #define UP_NU(K, TF) do { if (nu == 1) UP(K, 1, TF); else if (nu == 2) UP(K, 2, TF); else UP(K, 3, TF); } while (0)
   if (l == 0) {
     if (h_->vark) UP_NU(KIND_FINE_VK, TI); else UP_NU(KIND_FINE, TI);

@@ -8,8 +8,9 @@ algorithm, so FP64 agrees with the oracle to rounding (1e-12 relative: a few
 hundred roundings through a contraction).  FP32 is held to 2e-5 (unit
 roundoff 6e-8 times the same amplification); with BF16 / FP16 coarse-level
 storage the cycle's output differs from the exact-arithmetic cycle by about
-the 16-bit roundoff times the coarse-correction share, bounded here by
-3e-2 / 4e-3.
+the 16-bit roundoff (4e-3 / 5e-4) times the coarse-correction share, bounded
+here by 3e-2 / 1e-3 (FP16 levels store their vectors scaled by a power of
+two, so they stay in FP16's normal range).
 """
 import numpy as np
 import pytest
@@ -61,7 +62,7 @@ def test_apply_mg_fp64_matches_oracle(dim, n, s, nt, transpose):
         assert rel_err(z, ref) <= 1e-12, (stage, rel_err(z, ref))
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 2e-5), ("fp16", 4e-3), ("bf16", 3e-2)])
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-5), ("fp16", 1e-3), ("bf16", 3e-2)])
 def test_apply_mg_low_precision(precision, tol):
     require_gpu()
     from paper_2609_16863_amd import HeatProblem

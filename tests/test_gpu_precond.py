@@ -73,7 +73,7 @@ def test_apply_P_coarse_max_1024_matches_oracle():
     assert rel_err(z, precond.apply_preconditioner(ops, r)) <= 1e-10
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 2e-4), ("bf16", 5e-2), ("fp16", 2e-2)])
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-4), ("bf16", 5e-2), ("fp16", 1e-3)])
 def test_apply_P_low_precision_close_to_fp64_oracle(precision, tol):
     require_gpu()
     p, hp, ops, rng = _pair(2, 72, 3, 3, precision=precision, seed=5)
