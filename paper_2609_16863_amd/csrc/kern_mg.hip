@@ -338,23 +338,61 @@ constexpr int TCX = 16, TCY = 8;   // coarse nodes per down tile; fine tile is 2
 // coefficients times a/h^2 for variable kappa; the 1D Galerkin factor rows of
 // the tile's columns and rows for tensor levels).  Every global load of a
 // tile is issued up front, so a workgroup waits for memory once.
+//
+// Node t of the W x H tile (t = tx + W ty) lives at index G + t of each
+// per-node array, which is padded to a whole number of 256-node rows (NP)
+// plus a guard of G = W + 1 entries on both sides: every thread's nodes and
+// their stencil neighbours are in bounds, so the sweeps run without
+// branches, computing every node and selecting zero where a node is not
+// updated (the tile border, nodes outside the domain, the padding).
 template <int KIND, int R, class C>
 struct Tile {
   static constexpr int W = 2 * TCX + 1 + 2 * R, H = 2 * TCY + 1 + 2 * R, NE = W * H;
-  static constexpr int IT = (NE + 255) / 256;
+  static constexpr int IT = (NE + 255) / 256, NP = IT * 256, G = W + 1, NS = NP + 2 * G;
   static constexpr bool VK = KIND == KIND_FINE_VK, TEN = KIND == KIND_TENSOR, S9 = KIND == KIND_STENCIL9;
-  C b[NE], x0[NE], x1[NE];
-  C idg[KIND == KIND_FINE ? 1 : NE];
-  C f[VK ? 4 * NE : 1];
+  C b[NS], x0[NS], x1[NS];
+  C idg[KIND == KIND_FINE ? 1 : NS];
+  C f[VK ? 4 * NS : 1];
   C cx[TEN ? 6 * W : (S9 ? 3 * W : 1)];  // per column: (M + a T)(i, i+d), M(i, i+d), d = -1, 0, 1 (S9: M only)
   C cy[TEN ? 6 * H : (S9 ? 3 * H : 1)];  // per row:    M(j, j+d), a T(j, j+d) (S9: M only)
 };
 
+// The nodes of a tile one thread handles: element it is node
+// t = threadIdx.x + 256 it, at tile coordinates (tx, ty) (clamped into the
+// tile for padding nodes); bit it of `dom` is set for a node of the tile
+// inside the domain, of `inner` for one that is also off the tile border.
+template <int IT>
+struct Elems {
+  int tx[IT], ty[IT];
+  unsigned dom, inner;
+};
+
+template <int KIND, int R, class C>
+__device__ __forceinline__ Elems<Tile<KIND, R, C>::IT> tile_elems(int ox, int oy, int n) {
+  using T = Tile<KIND, R, C>;
+  Elems<T::IT> e;
+  e.dom = 0;
+  e.inner = 0;
+#pragma unroll
+  for (int it = 0; it < T::IT; ++it) {
+    const int t = threadIdx.x + it * 256;
+    const bool valid = t < T::NE;
+    const int tx = t % T::W, ty = valid ? t / T::W : T::H - 1;
+    e.tx[it] = tx;
+    e.ty[it] = ty;
+    const int gi = ox + tx, gj = oy + ty;
+    const bool d = valid && gi >= 0 && gi < n && gj >= 0 && gj < n;
+    const bool in = d && tx > 0 && tx < T::W - 1 && ty > 0 && ty < T::H - 1;
+    e.dom |= (unsigned)d << it;
+    e.inner |= (unsigned)in << it;
+  }
+  return e;
+}
+
 // The 9 operator coefficients of the nodes a thread sweeps, for the Galerkin
-// kinds (KIND_TENSOR, KIND_STENCIL9): element it of the thread is tile node
-// threadIdx.x + 256 it; entry (dj+1)*3 + (di+1) multiplies x at (di, dj).
-// Loaded (stencil part, before the tile barrier) and completed from the
-// staged factor rows (after it), then reused by every sweep.
+// kinds (KIND_TENSOR, KIND_STENCIL9): entry (dj+1)*3 + (di+1) multiplies x
+// at (di, dj).  Loaded (stencil part, before the tile barrier) and completed
+// from the staged factor rows (after it), then reused by every sweep.
 template <int KIND, int IT, class C>
 struct Coef9 {
   C v[IT][(KIND == KIND_STENCIL9 || KIND == KIND_TENSOR) ? 9 : 1];
@@ -362,15 +400,14 @@ struct Coef9 {
 
 template <int KIND, int R, class C>
 __device__ __forceinline__ void tile_load_coef(Coef9<KIND, Tile<KIND, R, C>::IT, C>& k9, const LevelOp<C>& op, int ox,
-                                               int oy) {
+                                               int oy, const Elems<Tile<KIND, R, C>::IT>& el) {
   using T = Tile<KIND, R, C>;
   if constexpr (T::S9) {
     const int n = op.n;
 #pragma unroll
     for (int it = 0; it < T::IT; ++it) {
-      const int t = threadIdx.x + it * 256, gi = ox + t % T::W, gj = oy + t / T::W;
-      const bool in = t < T::NE && gi >= 0 && gi < n && gj >= 0 && gj < n;
-      const int64_t g = in ? (int64_t)gj * n + gi : 0;
+      const bool in = (el.dom >> it) & 1u;
+      const int64_t g = in ? (int64_t)(oy + el.ty[it]) * n + ox + el.tx[it] : 0;
 #pragma unroll
       for (int d = 0; d < 9; ++d) k9.v[it][d] = in ? op.a * op.st9[d * op.N + g] : C(0);
     }
@@ -380,7 +417,8 @@ __device__ __forceinline__ void tile_load_coef(Coef9<KIND, Tile<KIND, R, C>::IT,
 // Stage the operator of the tile whose origin is (ox, oy) into LDS.  Loads
 // only; the caller synchronizes.
 template <int KIND, int R, class C>
-__device__ __forceinline__ void tile_stage_op(Tile<KIND, R, C>& sm, const LevelOp<C>& op, int ox, int oy) {
+__device__ __forceinline__ void tile_stage_op(Tile<KIND, R, C>& sm, const LevelOp<C>& op, int ox, int oy,
+                                              const Elems<Tile<KIND, R, C>::IT>& el) {
   using T = Tile<KIND, R, C>;
   constexpr int W = T::W, H = T::H;
   const int tid = threadIdx.x, n = op.n;
@@ -389,9 +427,8 @@ __device__ __forceinline__ void tile_stage_op(Tile<KIND, R, C>& sm, const LevelO
     C fv[4][T::IT];
 #pragma unroll
     for (int it = 0; it < T::IT; ++it) {
-      const int t = tid + it * 256, gi = ox + t % W, gj = oy + t / W;
-      const bool in = t < T::NE && gi >= 0 && gi < n && gj >= 0 && gj < n;
-      const int64_t g = in ? (int64_t)gj * n + gi : 0;
+      const bool in = (el.dom >> it) & 1u;
+      const int64_t g = in ? (int64_t)(oy + el.ty[it]) * n + ox + el.tx[it] : 0;
       fv[0][it] = in ? op.faces.m[0][g] : C(0);
       fv[1][it] = in ? op.faces.p[0][g] : C(0);
       fv[2][it] = in ? op.faces.m[1][g] : C(0);
@@ -400,10 +437,8 @@ __device__ __forceinline__ void tile_stage_op(Tile<KIND, R, C>& sm, const LevelO
 #pragma unroll
     for (int it = 0; it < T::IT; ++it) {
       const int t = tid + it * 256;
-      if (t < T::NE) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sm.f[q * T::NE + t] = s * fv[q][it];
-      }
+      for (int q = 0; q < 4; ++q) sm.f[q * T::NS + T::G + t] = s * fv[q][it];
     }
   }
   if constexpr (T::S9) {
@@ -438,14 +473,14 @@ __device__ __forceinline__ void tile_stage_op(Tile<KIND, R, C>& sm, const LevelO
 
 template <int KIND, int R, class C>
 __device__ __forceinline__ void tile_finish_coef(Coef9<KIND, Tile<KIND, R, C>::IT, C>& k9,
-                                                 const Tile<KIND, R, C>& sm) {
+                                                 const Tile<KIND, R, C>& sm,
+                                                 const Elems<Tile<KIND, R, C>::IT>& el) {
   using T = Tile<KIND, R, C>;
   if constexpr (T::S9 || T::TEN) {
     constexpr int W = T::W, H = T::H;
 #pragma unroll
     for (int it = 0; it < T::IT; ++it) {
-      const int t = threadIdx.x + it * 256;
-      const int tx = t < T::NE ? t % W : 0, ty = t < T::NE ? t / W : 0;
+      const int tx = el.tx[it], ty = el.ty[it];
 #pragma unroll
       for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
@@ -460,24 +495,26 @@ __device__ __forceinline__ void tile_finish_coef(Coef9<KIND, Tile<KIND, R, C>::I
   }
 }
 
-// Diagonal of the level operator at tile node (tx, ty) from the staged data.
+// Diagonal of the level operator at tile node t (per-node arrays offset by G).
 template <int KIND, int R, class C>
-__device__ __forceinline__ C tile_diag(const Tile<KIND, R, C>& sm, const LevelOp<C>& op, int t, int tx, int ty,
-                                       const C* kc) {
+__device__ __forceinline__ C tile_diag(const Tile<KIND, R, C>& sm, const LevelOp<C>& op, int t, const C* kc) {
   using T = Tile<KIND, R, C>;
   if constexpr (KIND == KIND_FINE) return C(1) + op.a * op.ih2 * C(4);
   else if constexpr (T::S9 || T::TEN)
     return kc[4];
-  else if constexpr (T::VK)
-    return C(1) + sm.f[t] + sm.f[T::NE + t] + sm.f[2 * T::NE + t] + sm.f[3 * T::NE + t];
-  else
+  else if constexpr (T::VK) {
+    const C* f = sm.f + T::G + t;
+    return C(1) + f[0] + f[T::NS] + f[2 * T::NS] + f[3 * T::NS];
+  } else
     return C(0);
 }
 
-// (A x)_t for an interior tile node (all 8 neighbours inside the tile).
+// (A x)_t for tile node t; x points at node 0 of a per-node array.  Every
+// neighbour index is inside the padded array; the value is only used for
+// nodes whose 8 neighbours are tile nodes.
 template <int KIND, int R, class C>
 __device__ __forceinline__ C tile_Ax(const Tile<KIND, R, C>& sm, const C* __restrict__ x, const LevelOp<C>& op, int t,
-                                     int tx, int ty, const C* kc) {
+                                     const C* kc) {
   using T = Tile<KIND, R, C>;
   constexpr int W = T::W;
   const C c = x[t];
@@ -490,64 +527,44 @@ __device__ __forceinline__ C tile_Ax(const Tile<KIND, R, C>& sm, const C* __rest
     return acc;
   } else if constexpr (KIND == KIND_FINE) {
     return c + op.a * op.ih2 * (C(4) * c - x[t - 1] - x[t + 1] - x[t - W] - x[t + W]);
-  } else if constexpr (T::VK) {
-    return c + sm.f[t] * (c - x[t - 1]) + sm.f[T::NE + t] * (c - x[t + 1]) + sm.f[2 * T::NE + t] * (c - x[t - W]) +
-           sm.f[3 * T::NE + t] * (c - x[t + W]);
   } else {
-    // sum_dj M_j(dj) sum_di (M + aT)_i(di) x + a T_j(dj) sum_di M_i(di) x
-    C acc = C(0);
-#pragma unroll
-    for (int dj = -1; dj <= 1; ++dj) {
-      C pv = C(0), qv = C(0);
-#pragma unroll
-      for (int di = -1; di <= 1; ++di) {
-        const C xv = x[t + dj * W + di];
-        pv += sm.cx[(di + 1) * W + tx] * xv;
-        qv += sm.cx[(4 + di) * W + tx] * xv;
-      }
-      acc += sm.cy[(dj + 1) * T::H + ty] * pv + sm.cy[(4 + dj) * T::H + ty] * qv;
-    }
-    return acc;
+    const C* f = sm.f + T::G + t;
+    return c + f[0] * (c - x[t - 1]) + f[T::NS] * (c - x[t + 1]) + f[2 * T::NS] * (c - x[t - W]) +
+           f[3 * T::NS] * (c - x[t + W]);
   }
 }
 
-// One weighted Jacobi sweep cur -> nxt over the tile (border and
-// out-of-domain nodes stay zero).
+// One weighted Jacobi sweep cur -> nxt over the tile (cur, nxt at node 0;
+// border, out-of-domain and padding nodes become zero).
 template <int KIND, int R, class C>
-__device__ __forceinline__ void tile_sweep(Tile<KIND, R, C>& sm, const C* cur, C* nxt, const LevelOp<C>& op, int ox,
-                                           int oy, C omega, const Coef9<KIND, Tile<KIND, R, C>::IT, C>& k9) {
+__device__ __forceinline__ void tile_sweep(Tile<KIND, R, C>& sm, const C* cur, C* nxt, const LevelOp<C>& op, C omega,
+                                           const Coef9<KIND, Tile<KIND, R, C>::IT, C>& k9,
+                                           const Elems<Tile<KIND, R, C>::IT>& el) {
   using T = Tile<KIND, R, C>;
-  constexpr int W = T::W, H = T::H;
-  const int n = op.n;
+  const C idc = omega / (C(1) + op.a * op.ih2 * C(4));
+  const C* b = sm.b + T::G;
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
     const int t = threadIdx.x + it * 256;
-    if (t < T::NE) {
-      const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
-      C v = C(0);
-      if (tx > 0 && tx < W - 1 && ty > 0 && ty < H - 1 && gi >= 0 && gi < n && gj >= 0 && gj < n) {
-        const C id = KIND == KIND_FINE ? omega / (C(1) + op.a * op.ih2 * C(4)) : sm.idg[KIND == KIND_FINE ? 0 : t];
-        v = cur[t] + id * (sm.b[t] - tile_Ax<KIND, R, C>(sm, cur, op, t, tx, ty, k9.v[it]));
-      }
-      nxt[t] = v;
-    }
+    const C id = KIND == KIND_FINE ? idc : sm.idg[KIND == KIND_FINE ? 0 : T::G + t];
+    const C v = cur[t] + id * (b[t] - tile_Ax<KIND, R, C>(sm, cur, op, t, k9.v[it]));
+    nxt[t] = ((el.inner >> it) & 1u) ? v : C(0);
   }
 }
 
-// omega / diagonal for every in-domain tile node (after the operator is staged).
+// omega / diagonal for every tile node (zero outside the domain); after the
+// operator is staged.
 template <int KIND, int R, class C>
-__device__ __forceinline__ void tile_inv_diag(Tile<KIND, R, C>& sm, const LevelOp<C>& op, int ox, int oy, C omega,
-                                              const Coef9<KIND, Tile<KIND, R, C>::IT, C>& k9) {
+__device__ __forceinline__ void tile_inv_diag(Tile<KIND, R, C>& sm, const LevelOp<C>& op, C omega,
+                                              const Coef9<KIND, Tile<KIND, R, C>::IT, C>& k9,
+                                              const Elems<Tile<KIND, R, C>::IT>& el) {
   using T = Tile<KIND, R, C>;
   if constexpr (KIND != KIND_FINE) {
 #pragma unroll
     for (int it = 0; it < T::IT; ++it) {
       const int t = threadIdx.x + it * 256;
-      if (t < T::NE) {
-        const int tx = t % T::W, ty = t / T::W, gi = ox + tx, gj = oy + ty;
-        const bool in = gi >= 0 && gi < op.n && gj >= 0 && gj < op.n;
-        sm.idg[t] = in ? omega / tile_diag<KIND, R, C>(sm, op, t, tx, ty, k9.v[it]) : C(0);
-      }
+      const C v = omega / tile_diag<KIND, R, C>(sm, op, t, k9.v[it]);
+      sm.idg[T::G + t] = ((el.dom >> it) & 1u) ? v : C(0);
     }
   }
 }
@@ -574,8 +591,8 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
                                                 CplArgs<TF, C> cpl, C bscale) {
   constexpr int R = NU + 1;
   using T = Tile<KIND, R, C>;
-  constexpr int W = T::W, H = T::H;
-  constexpr int ZW = W + 2, ZH = H + 2, ZNE = NZ > 0 ? ZW * ZH : 1, ZIT = (ZNE + 255) / 256;
+  constexpr int W = T::W, G = T::G;
+  constexpr int ZW = W + 2, ZH = T::H + 2, ZNE = NZ > 0 ? ZW * ZH : 1, ZIT = (ZNE + 255) / 256;
   static_assert(NZ == 0 || KIND == KIND_FINE || KIND == KIND_FINE_VK, "coupling terms live on level 0");
   __shared__ T sm;
   __shared__ C szt[NZ > 0 ? NZ : 1][ZNE];
@@ -587,14 +604,14 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
   const int ox = 2 * I0 - R, oy = 2 * J0 - R;
   const TF* bi = b + inst * sb;
   const TF* xi = x0 ? x0 + inst * sx0 : nullptr;
+  const Elems<T::IT> el = tile_elems<KIND, R, C>(ox, oy, nf);
   Coef9<KIND, T::IT, C> k9;
-  tile_load_coef<KIND, R, C>(k9, op, ox, oy);
+  tile_load_coef<KIND, R, C>(k9, op, ox, oy, el);
   C bv[T::IT], xv[T::IT];
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
-    const int t = tid + it * 256, gi = ox + t % W, gj = oy + t / W;
-    const bool in = t < T::NE && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
-    const int64_t g = in ? (int64_t)gj * nf + gi : 0;
+    const bool in = (el.dom >> it) & 1u;
+    const int64_t g = in ? (int64_t)(oy + el.ty[it]) * nf + ox + el.tx[it] : 0;
     bv[it] = in ? ld<TF, C>(bi + g) : C(0);
     xv[it] = (in && xi) ? ld<TF, C>(xi + g) : C(0);
   }
@@ -616,86 +633,75 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
         if (t < ZNE) szt[l][t] = zv[l][it];
       }
   }
-  tile_stage_op<KIND, R, C>(sm, op, ox, oy);
+  tile_stage_op<KIND, R, C>(sm, op, ox, oy, el);
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
     const int t = tid + it * 256;
-    if (t < T::NE) {
-      sm.b[t] = bv[it];
-      sm.x0[t] = xv[it];
-    }
+    sm.b[G + t] = bv[it];
+    sm.x0[G + t] = xv[it];
   }
   __syncthreads();
+  const int hx = (I0 + TCX >= nc) ? nf : 2 * (I0 + TCX), hy = (J0 + TCY >= nc) ? nf : 2 * (J0 + TCY);
   if constexpr (NZ > 0) {
     // b <- b - sum_l c_l K z_l at every in-domain tile node (each thread
     // updates only the nodes it reads later); owned nodes go to cpl.out
-    const int hx = (I0 + TCX >= nc) ? nf : 2 * (I0 + TCX), hy = (J0 + TCY >= nc) ? nf : 2 * (J0 + TCY);
     const C inv_a = C(1) / op.a;
 #pragma unroll
     for (int it = 0; it < T::IT; ++it) {
-      const int t = tid + it * 256;
-      if (t < T::NE) {
-        const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
-        if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
-          const int zt = (ty + 1) * ZW + tx + 1;
-          C acc = sm.b[t];
+      if ((el.dom >> it) & 1u) {
+        const int t = tid + it * 256, tx = el.tx[it], ty = el.ty[it], gi = ox + tx, gj = oy + ty;
+        const int zt = (ty + 1) * ZW + tx + 1;
+        C acc = sm.b[G + t];
 #pragma unroll
-          for (int l = 0; l < NZ; ++l) {
-            const C* z = szt[l];
-            const C c0 = z[zt];
-            C kz;
-            if constexpr (KIND == KIND_FINE) {
-              kz = op.ih2 * (C(4) * c0 - z[zt - 1] - z[zt + 1] - z[zt - ZW] - z[zt + ZW]);
-            } else {   // staged face coefficients carry a / h^2
-              kz = inv_a * (sm.f[t] * (c0 - z[zt - 1]) + sm.f[T::NE + t] * (c0 - z[zt + 1]) +
-                            sm.f[2 * T::NE + t] * (c0 - z[zt - ZW]) + sm.f[3 * T::NE + t] * (c0 - z[zt + ZW]));
-            }
-            acc -= cpl.c[l] * kz;
+        for (int l = 0; l < NZ; ++l) {
+          const C* z = szt[l];
+          const C c0 = z[zt];
+          C kz;
+          if constexpr (KIND == KIND_FINE) {
+            kz = op.ih2 * (C(4) * c0 - z[zt - 1] - z[zt + 1] - z[zt - ZW] - z[zt + ZW]);
+          } else {   // staged face coefficients carry a / h^2
+            const C* f = sm.f + G + t;
+            kz = inv_a * (f[0] * (c0 - z[zt - 1]) + f[T::NS] * (c0 - z[zt + 1]) + f[2 * T::NS] * (c0 - z[zt - ZW]) +
+                          f[3 * T::NS] * (c0 - z[zt + ZW]));
           }
-          sm.b[t] = acc;
-          if (gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy)
-            st<TF, C>(cpl.out + inst * cpl.so + (int64_t)gj * nf + gi, acc);
+          acc -= cpl.c[l] * kz;
         }
+        sm.b[G + t] = acc;
+        if (gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy)
+          st<TF, C>(cpl.out + inst * cpl.so + (int64_t)gj * nf + gi, acc);
       }
     }
   }
-  tile_finish_coef<KIND, R, C>(k9, sm);
-  tile_inv_diag<KIND, R, C>(sm, op, ox, oy, omega, k9);
-  C* cur = sm.x0;
-  C* nxt = sm.x1;
+  tile_finish_coef<KIND, R, C>(k9, sm, el);
+  tile_inv_diag<KIND, R, C>(sm, op, omega, k9, el);
+  C* cur = sm.x0 + G;
+  C* nxt = sm.x1 + G;
+  const C* bt = sm.b + G;
   int k = 0;
   if (!x0) {
     // first sweep from zero is pointwise: x = omega D^{-1} b
     __syncthreads();
+    const C idc = omega / (C(1) + op.a * op.ih2 * C(4));
 #pragma unroll
     for (int it = 0; it < T::IT; ++it) {
       const int t = tid + it * 256;
-      if (t < T::NE) {
-        const C id = KIND == KIND_FINE ? omega / (C(1) + op.a * op.ih2 * C(4)) : sm.idg[KIND == KIND_FINE ? 0 : t];
-        const int gi = ox + t % W, gj = oy + t / W;
-        const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
-        sm.x0[t] = in ? id * sm.b[t] : C(0);
-      }
+      const C id = KIND == KIND_FINE ? idc : sm.idg[KIND == KIND_FINE ? 0 : G + t];
+      cur[t] = ((el.dom >> it) & 1u) ? id * bt[t] : C(0);
     }
     k = 1;
   }
   __syncthreads();
   for (; k < NU; ++k) {
-    tile_sweep<KIND, R, C>(sm, cur, nxt, op, ox, oy, omega, k9);
+    tile_sweep<KIND, R, C>(sm, cur, nxt, op, omega, k9, el);
     __syncthreads();
     C* tmp = cur; cur = nxt; nxt = tmp;
   }
-  // residual on the interior of the tile (zero outside the domain)
+  // residual on the interior of the tile (zero elsewhere)
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
     const int t = tid + it * 256;
-    if (t < T::NE) {
-      const int tx = t % W, ty = t / W, gi = ox + tx, gj = oy + ty;
-      C v = C(0);
-      if (tx > 0 && tx < W - 1 && ty > 0 && ty < H - 1 && gi >= 0 && gi < nf && gj >= 0 && gj < nf)
-        v = sm.b[t] - tile_Ax<KIND, R, C>(sm, cur, op, t, tx, ty, k9.v[it]);
-      nxt[t] = v;
-    }
+    const C v = bt[t] - tile_Ax<KIND, R, C>(sm, cur, op, t, k9.v[it]);
+    nxt[t] = ((el.inner >> it) & 1u) ? v : C(0);
   }
   __syncthreads();
   for (int c = tid; c < TCX * TCY; c += 256) {
@@ -708,12 +714,11 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
     st<TC, C>(bc + inst * sbc + J * nc + I, acc);
   }
   // owned fine nodes: [2 I0, 2 (I0 + TCX)) per axis, the last tile to the end
-  const int hx = (I0 + TCX >= nc) ? nf : 2 * (I0 + TCX), hy = (J0 + TCY >= nc) ? nf : 2 * (J0 + TCY);
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
     const int t = tid + it * 256;
-    const int gi = ox + t % W, gj = oy + t / W;
-    if (t < T::NE && gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy)
+    const int gi = ox + el.tx[it], gj = oy + el.ty[it];
+    if (((el.dom >> it) & 1u) && gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy)
       st<TF, C>(xout + inst * sxo + (int64_t)gj * nf + gi, cur[t]);
   }
 }
@@ -732,7 +737,7 @@ __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_
                                               C escale) {
   constexpr int R = NU;
   using T = Tile<KIND, R, C>;
-  constexpr int W = T::W, H = T::H;
+  constexpr int G = T::G;
   constexpr int CW = TCX + R + 3, CH = TCY + R + 3, CNE = CW * CH, CIT = (CNE + 255) / 256;
   __shared__ T sm;
   __shared__ C sec[CNE];
@@ -743,14 +748,14 @@ __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_
   const int64_t inst = L / (gx * gy);
   const int ox = 2 * I0 - R, oy = 2 * J0 - R;
   const int cx0 = floor_half(ox - 1), cy0 = floor_half(oy - 1);
+  const Elems<T::IT> el = tile_elems<KIND, R, C>(ox, oy, nf);
   Coef9<KIND, T::IT, C> k9;
-  tile_load_coef<KIND, R, C>(k9, op, ox, oy);
+  tile_load_coef<KIND, R, C>(k9, op, ox, oy, el);
   C bv[T::IT], xv[T::IT], ev[CIT];
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
-    const int t = tid + it * 256, gi = ox + t % W, gj = oy + t / W;
-    const bool in = t < T::NE && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
-    const int64_t g = in ? (int64_t)gj * nf + gi : 0;
+    const bool in = (el.dom >> it) & 1u;
+    const int64_t g = in ? (int64_t)(oy + el.ty[it]) * nf + ox + el.tx[it] : 0;
     bv[it] = in ? ld<TF, C>(b + inst * sb + g) : C(0);
     xv[it] = in ? ld<TF, C>(xin + inst * sxi + g) : C(0);
   }
@@ -760,14 +765,12 @@ __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_
     const bool in = t < CNE && I >= 0 && I < nc && J >= 0 && J < nc;
     ev[it] = in ? escale * ld<TE, C>(e + inst * se + (int64_t)J * nc + I) : C(0);
   }
-  tile_stage_op<KIND, R, C>(sm, op, ox, oy);
+  tile_stage_op<KIND, R, C>(sm, op, ox, oy, el);
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
     const int t = tid + it * 256;
-    if (t < T::NE) {
-      sm.b[t] = bv[it];
-      sm.x1[t] = xv[it];
-    }
+    sm.b[G + t] = bv[it];
+    sm.x1[G + t] = xv[it];
   }
 #pragma unroll
   for (int it = 0; it < CIT; ++it) {
@@ -775,31 +778,24 @@ __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_
     if (t < CNE) sec[t] = ev[it];
   }
   __syncthreads();
-  tile_finish_coef<KIND, R, C>(k9, sm);
-  tile_inv_diag<KIND, R, C>(sm, op, ox, oy, omega, k9);
+  tile_finish_coef<KIND, R, C>(k9, sm, el);
+  tile_inv_diag<KIND, R, C>(sm, op, omega, k9, el);
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
     const int t = tid + it * 256;
-    if (t < T::NE) {
-      const int gi = ox + t % W, gj = oy + t / W;
-      const bool in = gi >= 0 && gi < nf && gj >= 0 && gj < nf;
-      C v = C(0);
-      if (in) {
-        const int li = floor_half(gi - 1), lj = floor_half(gj - 1);
-        const C wi0 = (gi & 1) ? C(1) : C(0.5), wi1 = (gi & 1) ? C(0) : C(0.5);
-        const C wj0 = (gj & 1) ? C(1) : C(0.5), wj1 = (gj & 1) ? C(0) : C(0.5);
-        const int c = (lj - cy0) * CW + (li - cx0);
-        const C pe = wj0 * (wi0 * sec[c] + wi1 * sec[c + 1]) + wj1 * (wi0 * sec[c + CW] + wi1 * sec[c + CW + 1]);
-        v = sm.x1[t] + pe;
-      }
-      sm.x0[t] = v;
-    }
+    const int gi = ox + el.tx[it], gj = oy + el.ty[it];
+    const int li = floor_half(gi - 1), lj = floor_half(gj - 1);
+    const C wi0 = (gi & 1) ? C(1) : C(0.5), wi1 = (gi & 1) ? C(0) : C(0.5);
+    const C wj0 = (gj & 1) ? C(1) : C(0.5), wj1 = (gj & 1) ? C(0) : C(0.5);
+    const int c = (lj - cy0) * CW + (li - cx0);
+    const C pe = wj0 * (wi0 * sec[c] + wi1 * sec[c + 1]) + wj1 * (wi0 * sec[c + CW] + wi1 * sec[c + CW + 1]);
+    sm.x0[G + t] = ((el.dom >> it) & 1u) ? sm.x1[G + t] + pe : C(0);
   }
   __syncthreads();
-  C* cur = sm.x0;
-  C* nxt = sm.x1;
+  C* cur = sm.x0 + G;
+  C* nxt = sm.x1 + G;
   for (int k = 0; k < NU; ++k) {
-    tile_sweep<KIND, R, C>(sm, cur, nxt, op, ox, oy, omega, k9);
+    tile_sweep<KIND, R, C>(sm, cur, nxt, op, omega, k9, el);
     __syncthreads();
     C* tmp = cur; cur = nxt; nxt = tmp;
   }
@@ -807,8 +803,8 @@ __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
     const int t = tid + it * 256;
-    const int gi = ox + t % W, gj = oy + t / W;
-    if (t < T::NE && gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy)
+    const int gi = ox + el.tx[it], gj = oy + el.ty[it];
+    if (((el.dom >> it) & 1u) && gi >= 2 * I0 && gi < hx && gj >= 2 * J0 && gj < hy)
       st<TF, C>(xout + inst * sxo + (int64_t)gj * nf + gi, cur[t]);
   }
 }
