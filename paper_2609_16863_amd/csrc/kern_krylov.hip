@@ -93,54 +93,58 @@ __device__ void gmres_givens(double* q, int j, const double* h2, double ww) {
 //                            h2 at H2, <w,w> at WW)
 // The block partials are summed in a fixed order, so results are bitwise
 // reproducible run to run.
-template <class TW, class TV>
+template <class TW, class TV, int ND>
 __global__ __launch_bounds__(TPB) void k_gs(TW* __restrict__ w, const TV* __restrict__ V, GSArgs a) {
+  // ND (a power of two >= nd) bounds the unrolled dot loops at compile time;
+  // slot d of the block partials keeps its place, <w,w> stays at DOTS_PER_PASS.
   using C = typename Acc<TW>::type;
   const int inst = blockIdx.y, blk = blockIdx.x, tid = threadIdx.x;
   TW* wi = w + (int64_t)inst * a.sw;
   const TV* Vi = V + (int64_t)inst * a.sv;
   double* q = a.slots + (int64_t)inst * a.sstride;
-  C cf[DOTS_PER_PASS];
+  C cf[ND];
 #pragma unroll
-  for (int d = 0; d < DOTS_PER_PASS; ++d) cf[d] = (a.axpy && d < a.nd) ? (C)q[a.ca + d] : C(0);
-  double acc[NSLOT];
+  for (int d = 0; d < ND; ++d) cf[d] = (a.axpy && d < a.nd) ? (C)q[a.ca + d] : C(0);
+  double acc[ND + 1];
 #pragma unroll
-  for (int d = 0; d < NSLOT; ++d) acc[d] = 0.0;
+  for (int d = 0; d <= ND; ++d) acc[d] = 0.0;
   for (int64_t idx = (int64_t)blk * TPB + tid; idx < a.L; idx += (int64_t)a.nblk * TPB) {
     C wv = ld<TW, C>(wi + idx);
-    C vv[DOTS_PER_PASS];
+    C vv[ND];
 #pragma unroll
-    for (int d = 0; d < DOTS_PER_PASS; ++d)
+    for (int d = 0; d < ND; ++d)
       vv[d] = (d < a.nd) ? ld<TV, C>(Vi + d * a.vstride + idx) : C(0);
     if (a.axpy) {
 #pragma unroll
-      for (int d = 0; d < DOTS_PER_PASS; ++d) wv -= cf[d] * vv[d];
+      for (int d = 0; d < ND; ++d) wv -= cf[d] * vv[d];
       st<TW, C>(wi + idx, wv);
     }
     const double wd = (double)wv;
+    if (a.dots) {
 #pragma unroll
-    for (int d = 0; d < DOTS_PER_PASS; ++d) acc[d] += (double)vv[d] * wd;
-    acc[DOTS_PER_PASS] += wd * wd;
+      for (int d = 0; d < ND; ++d) acc[d] += (double)vv[d] * wd;
+    }
+    acc[ND] += wd * wd;
   }
   if (!a.dots && !a.self) return;
-  __shared__ double red[TPB / 64][NSLOT];
+  __shared__ double red[TPB / 64][ND + 1];
   const int lane = tid & 63, wave = tid >> 6;
   const int nslots_used = a.dots ? a.nd : 0;
 #pragma unroll
-  for (int d = 0; d < NSLOT; ++d) {
-    if (d < nslots_used || (d == DOTS_PER_PASS && a.self)) {
+  for (int d = 0; d <= ND; ++d) {
+    if (d < nslots_used || (d == ND && a.self)) {
       const double v = wave_sum(acc[d]);
       if (lane == 0) red[wave][d] = v;
     }
   }
   __syncthreads();
   double* part = a.partial + ((int64_t)inst * a.nblk) * NSLOT;
-  if (tid < NSLOT) {
+  if (tid <= ND) {
     const int d = tid;
-    if (d < nslots_used || (d == DOTS_PER_PASS && a.self)) {
+    if (d < nslots_used || (d == ND && a.self)) {
       double sum = 0.0;
       for (int r = 0; r < TPB / 64; ++r) sum += red[r][d];
-      part[(int64_t)blk * NSLOT + d] = sum;
+      part[(int64_t)blk * NSLOT + (d == ND ? DOTS_PER_PASS : d)] = sum;
     }
   }
 }
@@ -182,7 +186,7 @@ __global__ __launch_bounds__(TPB) void k_gs_finish(GSArgs a) {
 }
 
 // out = (w - sum_{d<nd} slots[ca+d] V_d) * scale, scale = slots[cs] (cs >= 0) or `alpha`.
-template <class TW, class TV, class TO>
+template <class TW, class TV, class TO, int ND>
 __global__ __launch_bounds__(TPB) void k_basis(const TW* __restrict__ w, int64_t sw, const TV* __restrict__ V,
                                                int64_t vstride, int64_t sv, int nd, TO* __restrict__ out,
                                                int64_t so, const double* __restrict__ slots, int64_t sstride,
@@ -190,9 +194,9 @@ __global__ __launch_bounds__(TPB) void k_basis(const TW* __restrict__ w, int64_t
   using C = typename Acc<TO>::type;
   const int inst = blockIdx.y;
   const double* q = slots + (int64_t)inst * sstride;
-  C cf[DOTS_PER_PASS];
+  C cf[ND];
 #pragma unroll
-  for (int d = 0; d < DOTS_PER_PASS; ++d) cf[d] = d < nd ? (C)q[ca + d] : C(0);
+  for (int d = 0; d < ND; ++d) cf[d] = d < nd ? (C)q[ca + d] : C(0);
   const C sc = (C)(cs >= 0 ? q[cs] : alpha);
   const TW* wi = w + (int64_t)inst * sw;
   const TV* Vi = V + (int64_t)inst * sv;
@@ -200,7 +204,7 @@ __global__ __launch_bounds__(TPB) void k_basis(const TW* __restrict__ w, int64_t
   for (int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x; idx < L; idx += (int64_t)nblk * TPB) {
     C acc = ld<TW, C>(wi + idx);
 #pragma unroll
-    for (int d = 0; d < DOTS_PER_PASS; ++d)
+    for (int d = 0; d < ND; ++d)
       if (d < nd) acc -= cf[d] * ld<TV, C>(Vi + d * vstride + idx);
     st<TO, C>(oi + idx, acc * sc);
   }
@@ -209,7 +213,7 @@ __global__ __launch_bounds__(TPB) void k_basis(const TW* __restrict__ w, int64_t
 // out (+)= sum_{d<nd} y_d Z_d.  With `solve`, y is the GMRES least-squares
 // solution R y = g of the instance, recomputed by every workgroup from its
 // slots (at most KMAX unknowns); otherwise y = slots[cy + d].
-template <class TO, class TV>
+template <class TO, class TV, int ND>
 __global__ __launch_bounds__(TPB) void k_combine(TO* __restrict__ out, int64_t so, const TV* __restrict__ Z,
                                                  int64_t vstride, int64_t sv, int nd,
                                                  const double* __restrict__ slots, int64_t sstride, int cy,
@@ -232,15 +236,15 @@ __global__ __launch_bounds__(TPB) void k_combine(TO* __restrict__ out, int64_t s
     }
   }
   __syncthreads();
-  C cf[DOTS_PER_PASS];
+  C cf[ND];
 #pragma unroll
-  for (int d = 0; d < DOTS_PER_PASS; ++d) cf[d] = (C)ys[d];
+  for (int d = 0; d < ND; ++d) cf[d] = (C)ys[d];
   TO* oi = out + (int64_t)inst * so;
   const TV* Zi = Z + (int64_t)inst * sv;
   for (int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x; idx < L; idx += (int64_t)nblk * TPB) {
     C acc = accumulate ? ld<TO, C>(oi + idx) : C(0);
 #pragma unroll
-    for (int d = 0; d < DOTS_PER_PASS; ++d)
+    for (int d = 0; d < ND; ++d)
       if (d < nd) acc += cf[d] * ld<TV, C>(Zi + d * vstride + idx);
     st<TO, C>(oi + idx, acc);
   }
@@ -379,6 +383,17 @@ __global__ __launch_bounds__(TPB) void k_thetaT_rhs(const double* __restrict__ r
   for (int q = 0; q < ns; ++q) st<T, C>(o + q * NN + p, (C)(rV[q * NN + p] + tab.tau * tab.b[q] * zn));
 }
 
+// Dot-loop bound of a Krylov pass: the smallest of 1, 2, 4, 8, 16 that
+// covers nd basis vectors.
+#define DISPATCH_ND(nd, M)         \
+  do {                             \
+    if ((nd) <= 1) M(1);           \
+    else if ((nd) <= 2) M(2);      \
+    else if ((nd) <= 4) M(4);      \
+    else if ((nd) <= 8) M(8);      \
+    else M(DOTS_PER_PASS);         \
+  } while (0)
+
 inline dim3 seg_grid(int nblk, int B) { return dim3((unsigned)nblk, (unsigned)B); }
 inline dim3 pts_grid(int64_t N, int B) { return dim3((unsigned)((N + TPB - 1) / TPB), (unsigned)B); }
 
@@ -407,7 +422,9 @@ int seg_blocks(int64_t L, int B) {
 
 template <class TW, class TV>
 hipError_t gs_pass(TW* w, const TV* V, const GSArgs& a, int B, hipStream_t st) {
-  hipLaunchKernelGGL((k_gs<TW, TV>), seg_grid(a.nblk, B), dim3(TPB), 0, st, w, V, a);
+#define AAO_GS(ND) hipLaunchKernelGGL((k_gs<TW, TV, ND>), seg_grid(a.nblk, B), dim3(TPB), 0, st, w, V, a)
+  DISPATCH_ND(a.nd, AAO_GS);
+#undef AAO_GS
   if (a.dots || a.self) hipLaunchKernelGGL(k_gs_finish, dim3((unsigned)B), dim3(TPB), 0, st, a);
   return hipGetLastError();
 }
@@ -417,8 +434,11 @@ hipError_t basis_update(const TW* w, int64_t sw, const TV* V, int64_t vstride, i
                         int64_t so, const double* slots, int64_t sstride, int ca, int cs, double alpha, int64_t L,
                         int B, hipStream_t st) {
   const int nblk = seg_blocks(L, B);
-  hipLaunchKernelGGL((k_basis<TW, TV, TO>), seg_grid(nblk, B), dim3(TPB), 0, st, w, sw, V, vstride, sv, nd, out,
-                     so, slots, sstride, ca, cs, alpha, L, nblk);
+#define AAO_BASIS(ND)                                                                                     \
+  hipLaunchKernelGGL((k_basis<TW, TV, TO, ND>), seg_grid(nblk, B), dim3(TPB), 0, st, w, sw, V, vstride, sv, nd, \
+                     out, so, slots, sstride, ca, cs, alpha, L, nblk)
+  DISPATCH_ND(nd, AAO_BASIS);
+#undef AAO_BASIS
   return hipGetLastError();
 }
 
@@ -426,8 +446,11 @@ template <class TO, class TV>
 hipError_t combine(TO* out, int64_t so, const TV* Z, int64_t vstride, int64_t sv, int nd, const double* slots,
                    int64_t sstride, int cy, bool solve, bool accumulate, int64_t L, int B, hipStream_t st) {
   const int nblk = seg_blocks(L, B);
-  hipLaunchKernelGGL((k_combine<TO, TV>), seg_grid(nblk, B), dim3(TPB), 0, st, out, so, Z, vstride, sv, nd, slots,
-                     sstride, cy, (int)solve, (int)accumulate, L, nblk);
+#define AAO_COMB(ND)                                                                                         \
+  hipLaunchKernelGGL((k_combine<TO, TV, ND>), seg_grid(nblk, B), dim3(TPB), 0, st, out, so, Z, vstride, sv, nd, \
+                     slots, sstride, cy, (int)solve, (int)accumulate, L, nblk)
+  DISPATCH_ND(nd, AAO_COMB);
+#undef AAO_COMB
   return hipGetLastError();
 }
 

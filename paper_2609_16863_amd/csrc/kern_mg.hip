@@ -1150,6 +1150,229 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TX* __restrict__ xg, int6
   for (int p = tid; p < N0; p += nth) st<TX, C>(xg + inst * sx + p, sm[res + p]);
 }
 
+// ---------------------------------------------------------------------------
+// Coarse tail for the common case: NLS Galerkin smoothing levels of at most
+// TAIL_THREADS nodes, then the exact coarsest level (fast
+// diagonalization or the dense inverse), entered from x = 0.  One node per
+// thread and level: the node's nine coefficients, omega / diagonal and
+// right-hand side stay in registers for the whole cycle, so a sweep reads
+// only the eight neighbours from LDS.  Iterates live in LDS with a zero ring
+// (row pitch n + 2), so stencils, restriction and prolongation need no
+// boundary tests.  The restricted right-hand side of a coarse node is formed
+// by the thread that owns it, in a register.  Every global load is issued at
+// entry.  Same arithmetic as k_tail, up to summation order.
+// ---------------------------------------------------------------------------
+constexpr int TF_N0 = 32;                        // largest smoothing level: 32 x 32
+constexpr int TF_P0 = TF_N0 + 2, TF_Q0 = TF_P0 * TF_P0;
+constexpr int TF_NC = TF_N0 / 2;                 // largest coarsest level: 16 x 16
+constexpr int TF_PC = TF_NC + 2, TF_QC = TF_PC * TF_PC, TF_NCN = TF_NC * TF_NC;
+
+template <class C>
+struct TailFastArgs {
+  int n[3];            // level sizes (n x n); level NLS is the exact one
+  C a, omega;
+  int nu1, nu2;
+  const C* tri[2];     // 1D Galerkin factors of the smoothing levels (6 n each)
+  const C* st9[2];     // variable kappa: 9 N stencil of K per smoothing level
+  const C* fd;         // coarsest: V (n^2) then lam (n), or null
+  const C* cinv;       // coarsest: dense inverse, transposed (when fd is null)
+};
+
+template <int NLS, class C>
+struct TailFastLds {
+  C v[NLS][2][TF_Q0];        // iterates / residual of the smoothing levels (padded)
+  C cb[TF_NCN], cy[TF_NCN];  // coarsest: right-hand side, work
+  C cx[TF_QC];               // coarsest: solution (padded)
+  C cw[4 * TF_NCN];          // V and lam (fast diagonalization) or partial sums (dense)
+};
+
+// sum_{dj, di} k[(dj+1)*3 + di+1] x[pi + dj P + di]
+template <class C>
+__device__ __forceinline__ C tf_apply(const C* k, const C* __restrict__ x, int pi, int P) {
+  C acc = C(0);
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) acc += k[(dj + 1) * 3 + di + 1] * x[pi + dj * P + di];
+  return acc;
+}
+
+template <int KIND, int NLS, bool FD, class T, class C>
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail_fast(T* __restrict__ xg, int64_t sx, const T* __restrict__ bg,
+                                                            int64_t sb, TailFastArgs<C> ta) {
+  static_assert(KIND == KIND_TENSOR || KIND == KIND_STENCIL9, "Galerkin levels only");
+  __shared__ TailFastLds<NLS, C> sm;
+  const int tid = threadIdx.x;
+  const int64_t inst = blockIdx.x;
+  int n[NLS + 1], P[NLS + 1], pi[NLS + 1], ci[NLS + 1], cj[NLS + 1];
+  bool own[NLS + 1];
+#pragma unroll
+  for (int t = 0; t <= NLS; ++t) {
+    n[t] = ta.n[t];
+    P[t] = n[t] + 2;
+    own[t] = tid < n[t] * n[t];
+    cj[t] = own[t] ? tid / n[t] : 0;
+    ci[t] = own[t] ? tid - cj[t] * n[t] : 0;
+    pi[t] = (cj[t] + 1) * P[t] + ci[t] + 1;
+  }
+  const int nc = n[NLS], Nc = nc * nc;
+  // --- every global load up front
+  C b[NLS + 1];
+  b[0] = own[0] ? ld<T, C>(bg + inst * sb + tid) : C(0);
+  C fi[NLS][6], fj[NLS][6];   // factor columns at the node's i and j: M(d = -1, 0, 1), T(d = -1, 0, 1)
+  C k9[NLS][9];
+#pragma unroll
+  for (int t = 0; t < NLS; ++t) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      fi[t][q] = own[t] ? ta.tri[t][q * n[t] + ci[t]] : C(0);
+      fj[t][q] = own[t] ? ta.tri[t][q * n[t] + cj[t]] : C(0);
+    }
+    if constexpr (KIND == KIND_STENCIL9) {
+#pragma unroll
+      for (int d = 0; d < 9; ++d) k9[t][d] = own[t] ? ta.st9[t][d * n[t] * n[t] + tid] : C(0);
+    }
+  }
+  const int nfd = FD ? Nc + nc : 0;
+  const C fdv = (FD && tid < nfd) ? ta.fd[tid] : C(0);
+  // --- zero rings of the padded arrays (never written as interior nodes)
+#pragma unroll
+  for (int t = 0; t < NLS; ++t) {
+    for (int e = tid; e < P[t] * P[t]; e += TAIL_THREADS) {
+      const int y = e / P[t], x = e - y * P[t];
+      if (x == 0 || y == 0 || x == P[t] - 1 || y == P[t] - 1) {
+        sm.v[t][0][e] = C(0);
+        sm.v[t][1][e] = C(0);
+      }
+    }
+  }
+  {
+    const int Pc = P[NLS];
+    for (int e = tid; e < Pc * Pc; e += TAIL_THREADS) {
+      const int y = e / Pc, x = e - y * Pc;
+      if (x == 0 || y == 0 || x == Pc - 1 || y == Pc - 1) sm.cx[e] = C(0);
+    }
+  }
+  if (FD && tid < nfd) sm.cw[tid] = fdv;
+  // --- coefficients: (M + aT)_i M_j + a M_i T_j (+ a K stencil, variable kappa: M_i M_j + a K)
+  C idg[NLS];
+#pragma unroll
+  for (int t = 0; t < NLS; ++t) {
+#pragma unroll
+    for (int dj = 0; dj < 3; ++dj)
+#pragma unroll
+      for (int di = 0; di < 3; ++di) {
+        C& k = k9[t][dj * 3 + di];
+        if constexpr (KIND == KIND_TENSOR)
+          k = fj[t][dj] * (fi[t][di] + ta.a * fi[t][3 + di]) + ta.a * fj[t][3 + dj] * fi[t][di];
+        else
+          k = fj[t][dj] * fi[t][di] + ta.a * k;
+      }
+    idg[t] = own[t] ? ta.omega / k9[t][4] : C(0);
+  }
+  // --- down: sweeps from zero, residual, restriction (the coarse owner, in a register)
+  int cur[NLS];
+#pragma unroll
+  for (int t = 0; t < NLS; ++t) {
+    C x = idg[t] * b[t];
+    int c = 0;
+    if (own[t]) sm.v[t][0][pi[t]] = x;
+    __syncthreads();
+    for (int r = 1; r < ta.nu1; ++r) {
+      x += idg[t] * (b[t] - tf_apply<C>(k9[t], sm.v[t][c], pi[t], P[t]));
+      if (own[t]) sm.v[t][c ^ 1][pi[t]] = x;
+      __syncthreads();
+      c ^= 1;
+    }
+    const C res = b[t] - tf_apply<C>(k9[t], sm.v[t][c], pi[t], P[t]);
+    if (own[t]) sm.v[t][c ^ 1][pi[t]] = res;
+    __syncthreads();
+    cur[t] = c;
+    // full weighting at coarse node (I, J) = fine (2I + 1, 2J + 1)
+    const C* r = sm.v[t][c ^ 1];
+    const int f = (2 * cj[t + 1] + 2) * P[t] + 2 * ci[t + 1] + 2, Pf = P[t];
+    const C bc = C(0.25) * (r[f] + C(0.5) * (r[f - 1] + r[f + 1] + r[f - Pf] + r[f + Pf]) +
+                            C(0.25) * (r[f - Pf - 1] + r[f - Pf + 1] + r[f + Pf - 1] + r[f + Pf + 1]));
+    b[t + 1] = own[t + 1] ? bc : C(0);
+  }
+  // --- coarsest level, exact
+  if (own[NLS]) sm.cb[tid] = b[NLS];
+  __syncthreads();
+  if constexpr (FD) {
+    // A = M(x)M + a (T(x)M + M(x)T); with T V = M V diag(lam), V^T M V = I:
+    // X = V ((V^T B V) ./ (1 + a (lam_l + lam_k))) V^T, B[j][i] = b_{j n + i}
+    const C* V = sm.cw;
+    const C* lam = V + Nc;
+    const int j = cj[NLS], k = ci[NLS];
+    if (own[NLS]) {                                   // Y = B V
+      C acc = C(0);
+      for (int i = 0; i < nc; ++i) acc += sm.cb[j * nc + i] * V[i * nc + k];
+      sm.cy[tid] = acc;
+    }
+    __syncthreads();
+    if (own[NLS]) {                                   // B <- (V^T Y) ./ D
+      C acc = C(0);
+      for (int jj = 0; jj < nc; ++jj) acc += V[jj * nc + j] * sm.cy[jj * nc + k];
+      sm.cb[tid] = acc / (C(1) + ta.a * (lam[j] + lam[k]));
+    }
+    __syncthreads();
+    if (own[NLS]) {                                   // Y = B V^T
+      C acc = C(0);
+      for (int kk = 0; kk < nc; ++kk) acc += sm.cb[j * nc + kk] * V[k * nc + kk];
+      sm.cy[tid] = acc;
+    }
+    __syncthreads();
+    if (own[NLS]) {                                   // X = V Y
+      C acc = C(0);
+      for (int l = 0; l < nc; ++l) acc += V[j * nc + l] * sm.cy[l * nc + k];
+      sm.cx[pi[NLS]] = acc;
+    }
+    __syncthreads();
+  } else {
+    // x = A^{-1} b: four threads per row, each over a quarter of the columns
+    const int r = tid % Nc, part = tid / Nc, cols = (Nc + 3) / 4;
+    if (part < 4) {
+      const int c0 = part * cols, c1 = c0 + cols < Nc ? c0 + cols : Nc;
+      C acc = C(0);
+      for (int c = c0; c < c1; ++c) acc += ta.cinv[(int64_t)c * Nc + r] * sm.cb[c];
+      sm.cw[part * TF_NCN + r] = acc;
+    }
+    __syncthreads();
+    if (own[NLS])
+      sm.cx[pi[NLS]] = sm.cw[tid] + sm.cw[TF_NCN + tid] + sm.cw[2 * TF_NCN + tid] + sm.cw[3 * TF_NCN + tid];
+    __syncthreads();
+  }
+  // --- up: x += P e, post-smoothing; the finest tail level goes to global memory
+#pragma unroll
+  for (int t = NLS - 1; t >= 0; --t) {
+    const C* e = (t + 1 == NLS) ? sm.cx : sm.v[t + 1][cur[t + 1]];
+    const int Pc = P[t + 1];
+    // fine g takes coarse lo = floor((g - 1) / 2) and lo + 1 (padded: lo + 1, lo + 2)
+    // with weights (1, 0) for odd g, (1/2, 1/2) for even g
+    const int gi = ci[t], gj = cj[t];
+    const int li = ((gi - 1) >> 1) + 1, lj = ((gj - 1) >> 1) + 1;
+    const C wi0 = (gi & 1) ? C(1) : C(0.5), wi1 = (gi & 1) ? C(0) : C(0.5);
+    const C wj0 = (gj & 1) ? C(1) : C(0.5), wj1 = (gj & 1) ? C(0) : C(0.5);
+    const int q = lj * Pc + li;
+    const C pe = wj0 * (wi0 * e[q] + wi1 * e[q + 1]) + wj1 * (wi0 * e[q + Pc] + wi1 * e[q + Pc + 1]);
+    C x = sm.v[t][cur[t]][pi[t]] + pe;
+    int c = cur[t] ^ 1;
+    for (int r = 0; r < ta.nu2; ++r) {
+      if (own[t]) sm.v[t][c][pi[t]] = x;
+      __syncthreads();
+      x += idg[t] * (b[t] - tf_apply<C>(k9[t], sm.v[t][c], pi[t], P[t]));
+      c ^= 1;
+    }
+    if (t > 0) {
+      if (own[t]) sm.v[t][c][pi[t]] = x;
+      cur[t] = c;
+      __syncthreads();
+    } else if (own[0]) {
+      st<T, C>(xg + inst * sx + tid, x);
+    }
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1306,6 +1529,39 @@ hipError_t Multigrid<TI, TM>::prolong_smooth0(int stage, Vec xin, Vec ec, Vec b,
 template <class TI, class TM>
 hipError_t Multigrid<TI, TM>::tail(int stage, Vec x, Vec b, bool zero_init, int B) {
   if (h_->dim != 2) return hipErrorUnknown;   // the tail is 2D only
+  const int nls = levels_ - l0_ - 1;
+  const int nlast = h_->lev_n[levels_ - 1];
+  const bool use_fd = h_->fd_n > 0 && h_->fd_n == nlast;
+  // k_tail_fast: one smoothing level of at most 32 x 32 above the exact one
+  // (the usual tail: with the coarsest level at most 256 nodes, a level
+  // above it of at most 32 x 32 is the only smoothing level)
+  if (zero_init && l0_ > 0 && nls == 1 && h_->lev_n[l0_] <= TF_N0 && nlast * nlast <= TF_NCN &&
+      !(use_fd && h_->vark)) {
+    TailFastArgs<C> tf{};
+    for (int t = 0; t <= nls; ++t) tf.n[t] = h_->lev_n[l0_ + t];
+    tf.a = (C)a_[stage];
+    tf.omega = (C)h_->omega;
+    tf.nu1 = h_->opts.nu1;
+    tf.nu2 = h_->opts.nu2;
+    for (int t = 0; t < nls; ++t) {
+      const LevelOp<C> op = make_op<C>(h_, l0_ + t, a_[stage]);
+      tf.tri[t] = op.tri;
+      tf.st9[t] = op.st9;
+    }
+    const bool dbl = sizeof(C) == 8;
+    tf.fd = use_fd ? reinterpret_cast<const C*>(h_->ws + (dbl ? h_->plan.fd_d : h_->plan.fd_f)) : nullptr;
+    tf.cinv = use_fd ? nullptr : coarse_inv(stage);
+    const dim3 g((unsigned)B), blk((unsigned)TAIL_THREADS);
+    TM* xp = (TM*)x.ptr;
+    const TM* bp = (const TM*)b.ptr;
+#define TF_GO(K, NL, F) \
+  hipLaunchKernelGGL((k_tail_fast<K, NL, F, TM, C>), g, blk, 0, st_, xp, x.stride, bp, b.stride, tf)
+    if (h_->vark) TF_GO(KIND_STENCIL9, 1, false);
+    else if (use_fd) TF_GO(KIND_TENSOR, 1, true);
+    else TF_GO(KIND_TENSOR, 1, false);
+#undef TF_GO
+    return hipGetLastError();
+  }
   TailArgs<C> ta{};
   ta.nl = levels_ - l0_;
   ta.first_fine = l0_ == 0;
