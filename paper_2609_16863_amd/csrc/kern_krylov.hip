@@ -39,9 +39,10 @@ __device__ void gmres_start(double* q, double ww) {
 // Column j of the Hessenberg matrix from the two Gram-Schmidt passes:
 // h = h1 + h2, h_{j+1,j} = sqrt(<w,w> - |h2|^2); apply the previous
 // rotations, form the new one, update g, and the scale of the next basis
-// vector (0 once the instance has stopped).
-__device__ void gmres_givens(double* q, int j, const double* h2, double ww) {
-  if (q[S::ACTIVE] == 0.0) {
+// vector (0 once the instance has stopped).  qs: a copy of the slots below
+// InnerSlots::Y (in LDS) for the reads; results go to q.
+__device__ void gmres_givens(double* q, const double* qs, int j, const double* h2, double ww) {
+  if (qs[S::ACTIVE] == 0.0) {
     q[S::INV] = 0.0;
     return;
   }
@@ -49,14 +50,14 @@ __device__ void gmres_givens(double* q, int j, const double* h2, double ww) {
   double h2sq = 0.0;
   for (int i = 0; i <= j; ++i) {
     q[S::H2 + i] = h2[i];
-    col[i] = q[S::H1 + i] + h2[i];
+    col[i] = qs[S::H1 + i] + h2[i];
     h2sq += h2[i] * h2[i];
   }
   const double nrm2 = ww - h2sq;
   const double hn = nrm2 > 0.0 ? sqrt(nrm2) : 0.0;
   col[j + 1] = hn;
   for (int i = 0; i < j; ++i) {
-    const double c = q[S::CS + i], s = q[S::SN + i];
+    const double c = qs[S::CS + i], s = qs[S::SN + i];
     const double a = col[i], b = col[i + 1];
     col[i] = c * a + s * b;
     col[i + 1] = -s * a + c * b;
@@ -72,7 +73,7 @@ __device__ void gmres_givens(double* q, int j, const double* h2, double ww) {
   q[S::SN + j] = s;
   col[j] = rho;
   for (int i = 0; i <= j; ++i) q[S::R + j * (KMAX + 1) + i] = col[i];
-  const double gj = q[S::G + j];
+  const double gj = qs[S::G + j];
   q[S::G + j] = c * gj;
   q[S::G + j + 1] = -s * gj;
   q[S::M] = (double)(j + 1);
@@ -151,37 +152,57 @@ __global__ __launch_bounds__(TPB) void k_gs(TW* __restrict__ w, const TV* __rest
 
 // Second pass of a Gram-Schmidt reduction: one workgroup per instance sums
 // the block partials in a fixed order (thread t takes blocks t, t+TPB, ...,
-// then a tree), stores the results and runs the GMRES scalar update.
+// then a tree), stores the results and runs the GMRES scalar update.  All
+// partial loads of a thread are independent (slots unrolled inside the block
+// loop), and the slots the update reads are staged in LDS meanwhile.
+template <int ND>
 __global__ __launch_bounds__(TPB) void k_gs_finish(GSArgs a) {
   const int inst = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   double* q = a.slots + (int64_t)inst * a.sstride;
   const double* part = a.partial + ((int64_t)inst * a.nblk) * NSLOT;
-  const int nslots_used = a.dots ? a.nd : 0;
-  __shared__ double red[TPB / 64][NSLOT];
+  const int nsd = a.dots ? a.nd : 0;
+  __shared__ double red[TPB / 64][ND + 1];
   __shared__ double fin[NSLOT];
-  for (int d = 0; d < NSLOT; ++d) {
-    if (!(d < nslots_used || (d == DOTS_PER_PASS && a.self))) continue;
-    double sum = 0.0;
-    for (int b = tid; b < a.nblk; b += TPB) sum += part[(int64_t)b * NSLOT + d];
-    sum = wave_sum(sum);
-    if (lane == 0) red[wave][d] = sum;
+  __shared__ double qs[S::Y];
+  if (a.post == GS_POST_GIVENS)
+    for (int i = tid; i < S::Y; i += TPB) qs[i] = q[i];
+  double acc[ND + 1];
+#pragma unroll
+  for (int d = 0; d <= ND; ++d) acc[d] = 0.0;
+  for (int b = tid; b < a.nblk; b += TPB) {
+    const double* pb = part + (int64_t)b * NSLOT;
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+      if (d < nsd) acc[d] += pb[d];
+    if (a.self) acc[ND] += pb[DOTS_PER_PASS];
+  }
+#pragma unroll
+  for (int d = 0; d <= ND; ++d) {
+    if (d < nsd || (d == ND && a.self)) {
+      const double v = wave_sum(acc[d]);
+      if (lane == 0) red[wave][d] = v;
+    }
   }
   __syncthreads();
-  if (tid < NSLOT) {
+  if (tid <= ND) {
     const int d = tid;
-    if (d < nslots_used || (d == DOTS_PER_PASS && a.self)) {
+    if (d < nsd || (d == ND && a.self)) {
       double sum = 0.0;
       for (int r = 0; r < TPB / 64; ++r) sum += red[r][d];
-      fin[d] = sum;
-      if (d < nslots_used) q[a.od + d] = sum;
-      else q[a.os] = sum;
+      if (d < nsd) {
+        fin[d] = sum;
+        q[a.od + d] = sum;
+      } else {
+        fin[DOTS_PER_PASS] = sum;
+        q[a.os] = sum;
+      }
     }
   }
   __syncthreads();
   if (tid == 0) {
     if (a.post == GS_POST_INIT) gmres_start(q, fin[DOTS_PER_PASS]);
-    else if (a.post == GS_POST_GIVENS) gmres_givens(q, a.j, fin, fin[DOTS_PER_PASS]);
+    else if (a.post == GS_POST_GIVENS) gmres_givens(q, qs, a.j, fin, fin[DOTS_PER_PASS]);
   }
 }
 
@@ -425,7 +446,11 @@ hipError_t gs_pass(TW* w, const TV* V, const GSArgs& a, int B, hipStream_t st) {
 #define AAO_GS(ND) hipLaunchKernelGGL((k_gs<TW, TV, ND>), seg_grid(a.nblk, B), dim3(TPB), 0, st, w, V, a)
   DISPATCH_ND(a.nd, AAO_GS);
 #undef AAO_GS
-  if (a.dots || a.self) hipLaunchKernelGGL(k_gs_finish, dim3((unsigned)B), dim3(TPB), 0, st, a);
+  if (a.dots || a.self) {
+#define AAO_GSF(ND) hipLaunchKernelGGL((k_gs_finish<ND>), dim3((unsigned)B), dim3(TPB), 0, st, a)
+    DISPATCH_ND(a.dots ? a.nd : 0, AAO_GSF);
+#undef AAO_GSF
+  }
   return hipGetLastError();
 }
 

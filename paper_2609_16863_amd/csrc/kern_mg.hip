@@ -1151,21 +1151,20 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(TX* __restrict__ xg, int6
 }
 
 // ---------------------------------------------------------------------------
-// Coarse tail for the common case: NLS Galerkin smoothing levels of at most
-// TAIL_THREADS nodes, then the exact coarsest level (fast
-// diagonalization or the dense inverse), entered from x = 0.  One node per
-// thread and level: the node's nine coefficients, omega / diagonal and
-// right-hand side stay in registers for the whole cycle, so a sweep reads
-// only the eight neighbours from LDS.  Iterates live in LDS with a zero ring
+// Coarse tail for the common case: NLS (1 or 2) Galerkin smoothing levels,
+// the first of at most NPT * TAIL_THREADS nodes (n <= 64, NPT-node vertical
+// strips per thread), the second of at most TAIL_THREADS, then the exact coarsest level (fast diagonalization or
+// the dense inverse, at most 16 x 16), entered from x = 0.  Each thread owns
+// fixed nodes of every level and keeps their nine coefficients, omega /
+// diagonal and right-hand side in registers for the whole cycle, so a sweep
+// reads only the neighbours from LDS.  Iterates live in LDS with a zero ring
 // (row pitch n + 2), so stencils, restriction and prolongation need no
 // boundary tests.  The restricted right-hand side of a coarse node is formed
 // by the thread that owns it, in a register.  Every global load is issued at
 // entry.  Same arithmetic as k_tail, up to summation order.
 // ---------------------------------------------------------------------------
-constexpr int TF_N0 = 32;                        // largest smoothing level: 32 x 32
-constexpr int TF_P0 = TF_N0 + 2, TF_Q0 = TF_P0 * TF_P0;
-constexpr int TF_NC = TF_N0 / 2;                 // largest coarsest level: 16 x 16
-constexpr int TF_PC = TF_NC + 2, TF_QC = TF_PC * TF_PC, TF_NCN = TF_NC * TF_NC;
+constexpr int TF_NMAX = 64;                      // largest smoothing level: 64 x 64
+constexpr int TF_NC = 16, TF_NCN = TF_NC * TF_NC;   // largest coarsest level: 16 x 16
 
 template <class C>
 struct TailFastArgs {
@@ -1176,156 +1175,293 @@ struct TailFastArgs {
   const C* st9[2];     // variable kappa: 9 N stencil of K per smoothing level
   const C* fd;         // coarsest: V (n^2) then lam (n), or null
   const C* cinv;       // coarsest: dense inverse, transposed (when fd is null)
+  int ov[2][2];        // LDS offsets (elements) of the two padded iterate buffers per smoothing level
+  int ocb, ocy, ocx, ocw;   // coarsest: rhs, work, padded solution, V / partial sums
 };
 
-template <int NLS, class C>
-struct TailFastLds {
-  C v[NLS][2][TF_Q0];        // iterates / residual of the smoothing levels (padded)
-  C cb[TF_NCN], cy[TF_NCN];  // coarsest: right-hand side, work
-  C cx[TF_QC];               // coarsest: solution (padded)
-  C cw[4 * TF_NCN];          // V and lam (fast diagonalization) or partial sums (dense)
+// One smoothing level as seen by one thread: NP owned nodes.  With NP > 1
+// they are a vertical strip, nodes (i, NP q + m), so a sweep reads one
+// (NP + 2) x 3 window of the iterate for all of them.
+template <int KIND, int NP, class C>
+struct TfLev {
+  int n, P, o0, o1;              // size, padded pitch, buffer offsets
+  int pi[NP], ci[NP], cj[NP];
+  int woff[NP + 2];              // padded offsets of the window rows (column i - 1)
+  unsigned own;                  // bit m: node m exists
+  C k[NP][9], id[NP], b[NP];
+  C fi[6], fj[NP][6];            // factor columns at i and at each j (loaded at entry)
+  int cur;                       // buffer (0: o0, 1: o1) holding the smoothed iterate
+  __device__ int off(int c) const { return c ? o1 : o0; }
 };
 
-// sum_{dj, di} k[(dj+1)*3 + di+1] x[pi + dj P + di]
-template <class C>
-__device__ __forceinline__ C tf_apply(const C* k, const C* __restrict__ x, int pi, int P) {
-  C acc = C(0);
+template <int KIND, int NP, class C>
+__device__ __forceinline__ void tf_geom(TfLev<KIND, NP, C>& L, int n, int o0, int o1) {
+  L.n = n;
+  L.P = n + 2;
+  L.o0 = o0;
+  L.o1 = o1;
+  L.own = 0;
+  const int strips = (n + NP - 1) / NP;
+  const bool act = (int)threadIdx.x < n * strips;
+  const int q = act ? (int)threadIdx.x / n : 0;
+  const int i = act ? (int)threadIdx.x - q * n : 0;
 #pragma unroll
-  for (int dj = -1; dj <= 1; ++dj)
+  for (int m = 0; m < NP; ++m) {
+    const int j = NP * q + m;
+    const bool own = act && j < n;
+    L.own |= (unsigned)own << m;
+    L.ci[m] = own ? i : 0;
+    L.cj[m] = own ? j : 0;
+    L.pi[m] = (L.cj[m] + 1) * L.P + L.ci[m] + 1;
+  }
 #pragma unroll
-    for (int di = -1; di <= 1; ++di) acc += k[(dj + 1) * 3 + di + 1] * x[pi + dj * P + di];
-  return acc;
+  for (int r = 0; r < NP + 2; ++r) {
+    const int row = NP * q + r < L.P - 1 ? NP * q + r : L.P - 1;
+    L.woff[r] = row * L.P + i;
+  }
 }
 
-template <int KIND, int NLS, bool FD, class T, class C>
-__global__ __launch_bounds__(TAIL_THREADS) void k_tail_fast(T* __restrict__ xg, int64_t sx, const T* __restrict__ bg,
-                                                            int64_t sb, TailFastArgs<C> ta) {
-  static_assert(KIND == KIND_TENSOR || KIND == KIND_STENCIL9, "Galerkin levels only");
-  __shared__ TailFastLds<NLS, C> sm;
-  const int tid = threadIdx.x;
-  const int64_t inst = blockIdx.x;
-  int n[NLS + 1], P[NLS + 1], pi[NLS + 1], ci[NLS + 1], cj[NLS + 1];
-  bool own[NLS + 1];
+// Issue the coefficient loads of a level (factor columns; stencil of K).
+template <int KIND, int NP, class C>
+__device__ __forceinline__ void tf_load(TfLev<KIND, NP, C>& L, const C* __restrict__ tri, const C* __restrict__ st9) {
+  const bool any = L.own != 0;
 #pragma unroll
-  for (int t = 0; t <= NLS; ++t) {
-    n[t] = ta.n[t];
-    P[t] = n[t] + 2;
-    own[t] = tid < n[t] * n[t];
-    cj[t] = own[t] ? tid / n[t] : 0;
-    ci[t] = own[t] ? tid - cj[t] * n[t] : 0;
-    pi[t] = (cj[t] + 1) * P[t] + ci[t] + 1;
-  }
-  const int nc = n[NLS], Nc = nc * nc;
-  // --- every global load up front
-  C b[NLS + 1];
-  b[0] = own[0] ? ld<T, C>(bg + inst * sb + tid) : C(0);
-  C fi[NLS][6], fj[NLS][6];   // factor columns at the node's i and j: M(d = -1, 0, 1), T(d = -1, 0, 1)
-  C k9[NLS][9];
+  for (int q = 0; q < 6; ++q) L.fi[q] = any ? tri[q * L.n + L.ci[0]] : C(0);
 #pragma unroll
-  for (int t = 0; t < NLS; ++t) {
+  for (int m = 0; m < NP; ++m) {
+    const bool own = (L.own >> m) & 1u;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      fi[t][q] = own[t] ? ta.tri[t][q * n[t] + ci[t]] : C(0);
-      fj[t][q] = own[t] ? ta.tri[t][q * n[t] + cj[t]] : C(0);
-    }
+    for (int q = 0; q < 6; ++q) L.fj[m][q] = own ? tri[q * L.n + L.cj[m]] : C(0);
     if constexpr (KIND == KIND_STENCIL9) {
+      const int p = L.cj[m] * L.n + L.ci[m];
 #pragma unroll
-      for (int d = 0; d < 9; ++d) k9[t][d] = own[t] ? ta.st9[t][d * n[t] * n[t] + tid] : C(0);
+      for (int d = 0; d < 9; ++d) L.k[m][d] = own ? st9[d * L.n * L.n + p] : C(0);
     }
   }
-  const int nfd = FD ? Nc + nc : 0;
-  const C fdv = (FD && tid < nfd) ? ta.fd[tid] : C(0);
-  // --- zero rings of the padded arrays (never written as interior nodes)
+}
+
+// Coefficients (M + aT)_i M_j + a M_i T_j (variable kappa: M_i M_j + a K) and
+// omega / diagonal.
+template <int KIND, int NP, class C>
+__device__ __forceinline__ void tf_coef(TfLev<KIND, NP, C>& L, C a, C omega) {
 #pragma unroll
-  for (int t = 0; t < NLS; ++t) {
-    for (int e = tid; e < P[t] * P[t]; e += TAIL_THREADS) {
-      const int y = e / P[t], x = e - y * P[t];
-      if (x == 0 || y == 0 || x == P[t] - 1 || y == P[t] - 1) {
-        sm.v[t][0][e] = C(0);
-        sm.v[t][1][e] = C(0);
-      }
-    }
-  }
-  {
-    const int Pc = P[NLS];
-    for (int e = tid; e < Pc * Pc; e += TAIL_THREADS) {
-      const int y = e / Pc, x = e - y * Pc;
-      if (x == 0 || y == 0 || x == Pc - 1 || y == Pc - 1) sm.cx[e] = C(0);
-    }
-  }
-  if (FD && tid < nfd) sm.cw[tid] = fdv;
-  // --- coefficients: (M + aT)_i M_j + a M_i T_j (+ a K stencil, variable kappa: M_i M_j + a K)
-  C idg[NLS];
-#pragma unroll
-  for (int t = 0; t < NLS; ++t) {
+  for (int m = 0; m < NP; ++m) {
 #pragma unroll
     for (int dj = 0; dj < 3; ++dj)
 #pragma unroll
       for (int di = 0; di < 3; ++di) {
-        C& k = k9[t][dj * 3 + di];
+        C& k = L.k[m][dj * 3 + di];
         if constexpr (KIND == KIND_TENSOR)
-          k = fj[t][dj] * (fi[t][di] + ta.a * fi[t][3 + di]) + ta.a * fj[t][3 + dj] * fi[t][di];
+          k = L.fj[m][dj] * (L.fi[di] + a * L.fi[3 + di]) + a * L.fj[m][3 + dj] * L.fi[di];
         else
-          k = fj[t][dj] * fi[t][di] + ta.a * k;
+          k = L.fj[m][dj] * L.fi[di] + a * k;
       }
-    idg[t] = own[t] ? ta.omega / k9[t][4] : C(0);
+    L.id[m] = ((L.own >> m) & 1u) ? omega / L.k[m][4] : C(0);
   }
-  // --- down: sweeps from zero, residual, restriction (the coarse owner, in a register)
-  int cur[NLS];
+}
+
+// Zero the ring of a padded n x n array at LDS offset o.
+template <class C>
+__device__ __forceinline__ void tf_ring(C* sm, int o, int P) {
+  for (int e = threadIdx.x; e < 4 * (P - 1); e += TAIL_THREADS) {
+    const int side = e / (P - 1), r = e - side * (P - 1);
+    const int idx = side == 0 ? r : (side == 1 ? r * P + P - 1 : (side == 2 ? P * P - 1 - r : (P - 1 - r) * P));
+    sm[o + idx] = C(0);
+  }
+}
+
+// (A x) at every node of the thread, from the (NP + 2) x 3 window of x.
+template <int KIND, int NP, class C>
+__device__ __forceinline__ void tf_apply(const TfLev<KIND, NP, C>& L, const C* __restrict__ x, C (&ax)[NP]) {
+  C w[NP + 2][3];
 #pragma unroll
-  for (int t = 0; t < NLS; ++t) {
-    C x = idg[t] * b[t];
-    int c = 0;
-    if (own[t]) sm.v[t][0][pi[t]] = x;
-    __syncthreads();
-    for (int r = 1; r < ta.nu1; ++r) {
-      x += idg[t] * (b[t] - tf_apply<C>(k9[t], sm.v[t][c], pi[t], P[t]));
-      if (own[t]) sm.v[t][c ^ 1][pi[t]] = x;
-      __syncthreads();
-      c ^= 1;
+  for (int r = 0; r < NP + 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w[r][c] = x[L.woff[r] + c];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    C acc = C(0);
+#pragma unroll
+    for (int dj = 0; dj < 3; ++dj)
+#pragma unroll
+      for (int di = 0; di < 3; ++di) acc += L.k[m][dj * 3 + di] * w[m + dj][di];
+    ax[m] = acc;
+  }
+}
+
+// Pre-smoothing from zero (the first sweep pointwise), then the residual
+// into the other buffer.
+template <int KIND, int NP, class C>
+__device__ __forceinline__ void tf_down(TfLev<KIND, NP, C>& L, C* sm, int nu1) {
+  C x[NP], ax[NP];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    x[m] = L.id[m] * L.b[m];
+    if ((L.own >> m) & 1u) sm[L.o0 + L.pi[m]] = x[m];
+  }
+  __syncthreads();
+  int c = 0;
+  for (int r = 1; r < nu1; ++r) {
+    C* xo = sm + L.off(c ^ 1);
+    tf_apply(L, sm + L.off(c), ax);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      x[m] += L.id[m] * (L.b[m] - ax[m]);
+      if ((L.own >> m) & 1u) xo[L.pi[m]] = x[m];
     }
-    const C res = b[t] - tf_apply<C>(k9[t], sm.v[t][c], pi[t], P[t]);
-    if (own[t]) sm.v[t][c ^ 1][pi[t]] = res;
     __syncthreads();
-    cur[t] = c;
-    // full weighting at coarse node (I, J) = fine (2I + 1, 2J + 1)
-    const C* r = sm.v[t][c ^ 1];
-    const int f = (2 * cj[t + 1] + 2) * P[t] + 2 * ci[t + 1] + 2, Pf = P[t];
-    const C bc = C(0.25) * (r[f] + C(0.5) * (r[f - 1] + r[f + 1] + r[f - Pf] + r[f + Pf]) +
-                            C(0.25) * (r[f - Pf - 1] + r[f - Pf + 1] + r[f + Pf - 1] + r[f + Pf + 1]));
-    b[t + 1] = own[t + 1] ? bc : C(0);
+    c ^= 1;
+  }
+  C* ro = sm + L.off(c ^ 1);
+  tf_apply(L, sm + L.off(c), ax);
+#pragma unroll
+  for (int m = 0; m < NP; ++m)
+    if ((L.own >> m) & 1u) ro[L.pi[m]] = L.b[m] - ax[m];
+  __syncthreads();
+  L.cur = c;
+}
+
+// Full weighting of the fine residual into the coarse owners' right-hand
+// sides: coarse (I, J) sits at fine (2I + 1, 2J + 1).
+template <int KIND, int NPC, int NPF, class C>
+__device__ __forceinline__ void tf_restrict(TfLev<KIND, NPC, C>& Lc, const TfLev<KIND, NPF, C>& Lf, const C* sm) {
+  const C* r = sm + Lf.off(Lf.cur ^ 1);
+  const int Pf = Lf.P;
+#pragma unroll
+  for (int m = 0; m < NPC; ++m) {
+    const int f = (2 * Lc.cj[m] + 2) * Pf + 2 * Lc.ci[m] + 2;
+    const C v = C(0.25) * (r[f] + C(0.5) * (r[f - 1] + r[f + 1] + r[f - Pf] + r[f + Pf]) +
+                           C(0.25) * (r[f - Pf - 1] + r[f - Pf + 1] + r[f + Pf - 1] + r[f + Pf + 1]));
+    Lc.b[m] = ((Lc.own >> m) & 1u) ? v : C(0);
+  }
+}
+
+// x = x_smoothed + P e (e: padded coarse array at LDS offset oe, pitch Pc),
+// then nu2 sweeps.  Fine g takes coarse lo = floor((g - 1) / 2) and lo + 1
+// with weights (1, 0) for odd g, (1/2, 1/2) for even g.
+template <int KIND, int NP, class C>
+__device__ __forceinline__ void tf_up(TfLev<KIND, NP, C>& L, C* sm, int oe, int Pc, int nu2, C (&x)[NP]) {
+  const C* e = sm + oe;
+  const C* xs = sm + L.off(L.cur);
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    const int gi = L.ci[m], gj = L.cj[m];
+    const int q = (((gj - 1) >> 1) + 1) * Pc + ((gi - 1) >> 1) + 1;
+    const C wi0 = (gi & 1) ? C(1) : C(0.5), wi1 = (gi & 1) ? C(0) : C(0.5);
+    const C wj0 = (gj & 1) ? C(1) : C(0.5), wj1 = (gj & 1) ? C(0) : C(0.5);
+    x[m] = xs[L.pi[m]] + wj0 * (wi0 * e[q] + wi1 * e[q + 1]) + wj1 * (wi0 * e[q + Pc] + wi1 * e[q + Pc + 1]);
+  }
+  int c = L.cur ^ 1;
+  for (int r = 0; r < nu2; ++r) {
+    C* xo = sm + L.off(c);
+#pragma unroll
+    for (int m = 0; m < NP; ++m)
+      if ((L.own >> m) & 1u) xo[L.pi[m]] = x[m];
+    __syncthreads();
+    C ax[NP];
+    tf_apply(L, xo, ax);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) x[m] += L.id[m] * (L.b[m] - ax[m]);
+    c ^= 1;
+  }
+  L.cur = c;   // the buffer the final x would go to
+}
+
+template <int KIND, int NLS, int NPT, bool FD, class T, class C>
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail_fast(T* __restrict__ xg, int64_t sx, const T* __restrict__ bg,
+                                                            int64_t sb, TailFastArgs<C> ta) {
+  static_assert(KIND == KIND_TENSOR || KIND == KIND_STENCIL9, "Galerkin levels only");
+  static_assert(NLS == 1 || NLS == 2, "one or two smoothing levels");
+  extern __shared__ unsigned char tail_smem[];
+  C* sm = reinterpret_cast<C*>(tail_smem);
+  const int tid = threadIdx.x;
+  const int64_t inst = blockIdx.x;
+  TfLev<KIND, NPT, C> L0;
+  TfLev<KIND, 1, C> L1;
+  tf_geom(L0, ta.n[0], ta.ov[0][0], ta.ov[0][1]);
+  if constexpr (NLS == 2) tf_geom(L1, ta.n[1], ta.ov[1][0], ta.ov[1][1]);
+  const int nc = ta.n[NLS], Nc = nc * nc, Pc = nc + 2;
+  const bool ownc = tid < Nc;
+  const int cjc = ownc ? tid / nc : 0, cic = ownc ? tid - cjc * nc : 0;
+  // --- every global load up front
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) {
+    const int p = L0.cj[m] * L0.n + L0.ci[m];
+    L0.b[m] = ((L0.own >> m) & 1u) ? ld<T, C>(bg + inst * sb + p) : C(0);
+  }
+  tf_load(L0, ta.tri[0], ta.st9[0]);
+  if constexpr (NLS == 2) tf_load(L1, ta.tri[1], ta.st9[1]);
+  const int nfd = FD ? Nc + nc : 0;
+  const C fdv = (FD && tid < nfd) ? ta.fd[tid] : C(0);
+  // --- zero rings, staged fast-diagonalization data, coefficients
+  tf_ring(sm, L0.o0, L0.P);
+  tf_ring(sm, L0.o1, L0.P);
+  if constexpr (NLS == 2) {
+    tf_ring(sm, L1.o0, L1.P);
+    tf_ring(sm, L1.o1, L1.P);
+  }
+  tf_ring(sm, ta.ocx, Pc);
+  if (FD && tid < nfd) sm[ta.ocw + tid] = fdv;
+  tf_coef(L0, ta.a, ta.omega);
+  if constexpr (NLS == 2) tf_coef(L1, ta.a, ta.omega);
+  // --- down
+  tf_down(L0, sm, ta.nu1);
+  C bc;
+  if constexpr (NLS == 2) {
+    tf_restrict(L1, L0, sm);
+    tf_down(L1, sm, ta.nu1);
+    TfLev<KIND, 1, C> Lc;   // coarse owner geometry for the restriction
+    Lc.P = Pc;
+    Lc.own = ownc;
+    Lc.ci[0] = cic;
+    Lc.cj[0] = cjc;
+    tf_restrict(Lc, L1, sm);
+    bc = Lc.b[0];
+  } else {
+    TfLev<KIND, 1, C> Lc;
+    Lc.P = Pc;
+    Lc.own = ownc;
+    Lc.ci[0] = cic;
+    Lc.cj[0] = cjc;
+    tf_restrict(Lc, L0, sm);
+    bc = Lc.b[0];
   }
   // --- coarsest level, exact
-  if (own[NLS]) sm.cb[tid] = b[NLS];
+  C* cb = sm + ta.ocb;
+  C* cy = sm + ta.ocy;
+  C* cx = sm + ta.ocx;
+  C* cw = sm + ta.ocw;
+  const int pic = (cjc + 1) * Pc + cic + 1;
+  if (ownc) cb[tid] = bc;
   __syncthreads();
   if constexpr (FD) {
     // A = M(x)M + a (T(x)M + M(x)T); with T V = M V diag(lam), V^T M V = I:
     // X = V ((V^T B V) ./ (1 + a (lam_l + lam_k))) V^T, B[j][i] = b_{j n + i}
-    const C* V = sm.cw;
+    const C* V = cw;
     const C* lam = V + Nc;
-    const int j = cj[NLS], k = ci[NLS];
-    if (own[NLS]) {                                   // Y = B V
+    const int j = cjc, k = cic;
+    if (ownc) {                                       // Y = B V
       C acc = C(0);
-      for (int i = 0; i < nc; ++i) acc += sm.cb[j * nc + i] * V[i * nc + k];
-      sm.cy[tid] = acc;
+      for (int i = 0; i < nc; ++i) acc += cb[j * nc + i] * V[i * nc + k];
+      cy[tid] = acc;
     }
     __syncthreads();
-    if (own[NLS]) {                                   // B <- (V^T Y) ./ D
+    if (ownc) {                                       // B <- (V^T Y) ./ D
       C acc = C(0);
-      for (int jj = 0; jj < nc; ++jj) acc += V[jj * nc + j] * sm.cy[jj * nc + k];
-      sm.cb[tid] = acc / (C(1) + ta.a * (lam[j] + lam[k]));
+      for (int jj = 0; jj < nc; ++jj) acc += V[jj * nc + j] * cy[jj * nc + k];
+      cb[tid] = acc / (C(1) + ta.a * (lam[j] + lam[k]));
     }
     __syncthreads();
-    if (own[NLS]) {                                   // Y = B V^T
+    if (ownc) {                                       // Y = B V^T
       C acc = C(0);
-      for (int kk = 0; kk < nc; ++kk) acc += sm.cb[j * nc + kk] * V[k * nc + kk];
-      sm.cy[tid] = acc;
+      for (int kk = 0; kk < nc; ++kk) acc += cb[j * nc + kk] * V[k * nc + kk];
+      cy[tid] = acc;
     }
     __syncthreads();
-    if (own[NLS]) {                                   // X = V Y
+    if (ownc) {                                       // X = V Y
       C acc = C(0);
-      for (int l = 0; l < nc; ++l) acc += V[j * nc + l] * sm.cy[l * nc + k];
-      sm.cx[pi[NLS]] = acc;
+      for (int l = 0; l < nc; ++l) acc += V[j * nc + l] * cy[l * nc + k];
+      cx[pic] = acc;
     }
     __syncthreads();
   } else {
@@ -1334,43 +1470,46 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail_fast(T* __restrict__ xg, 
     if (part < 4) {
       const int c0 = part * cols, c1 = c0 + cols < Nc ? c0 + cols : Nc;
       C acc = C(0);
-      for (int c = c0; c < c1; ++c) acc += ta.cinv[(int64_t)c * Nc + r] * sm.cb[c];
-      sm.cw[part * TF_NCN + r] = acc;
+      for (int c = c0; c < c1; ++c) acc += ta.cinv[(int64_t)c * Nc + r] * cb[c];
+      cw[part * TF_NCN + r] = acc;
     }
     __syncthreads();
-    if (own[NLS])
-      sm.cx[pi[NLS]] = sm.cw[tid] + sm.cw[TF_NCN + tid] + sm.cw[2 * TF_NCN + tid] + sm.cw[3 * TF_NCN + tid];
+    if (ownc) cx[pic] = cw[tid] + cw[TF_NCN + tid] + cw[2 * TF_NCN + tid] + cw[3 * TF_NCN + tid];
     __syncthreads();
   }
-  // --- up: x += P e, post-smoothing; the finest tail level goes to global memory
+  // --- up; the finest tail level goes to global memory
+  int oe = ta.ocx, Pe = Pc;
+  if constexpr (NLS == 2) {
+    C x1[1];
+    tf_up(L1, sm, oe, Pe, ta.nu2, x1);
+    if (L1.own & 1u) sm[L1.off(L1.cur) + L1.pi[0]] = x1[0];
+    __syncthreads();
+    oe = L1.off(L1.cur);
+    Pe = L1.P;
+  }
+  C x0[NPT];
+  tf_up(L0, sm, oe, Pe, ta.nu2, x0);
 #pragma unroll
-  for (int t = NLS - 1; t >= 0; --t) {
-    const C* e = (t + 1 == NLS) ? sm.cx : sm.v[t + 1][cur[t + 1]];
-    const int Pc = P[t + 1];
-    // fine g takes coarse lo = floor((g - 1) / 2) and lo + 1 (padded: lo + 1, lo + 2)
-    // with weights (1, 0) for odd g, (1/2, 1/2) for even g
-    const int gi = ci[t], gj = cj[t];
-    const int li = ((gi - 1) >> 1) + 1, lj = ((gj - 1) >> 1) + 1;
-    const C wi0 = (gi & 1) ? C(1) : C(0.5), wi1 = (gi & 1) ? C(0) : C(0.5);
-    const C wj0 = (gj & 1) ? C(1) : C(0.5), wj1 = (gj & 1) ? C(0) : C(0.5);
-    const int q = lj * Pc + li;
-    const C pe = wj0 * (wi0 * e[q] + wi1 * e[q + 1]) + wj1 * (wi0 * e[q + Pc] + wi1 * e[q + Pc + 1]);
-    C x = sm.v[t][cur[t]][pi[t]] + pe;
-    int c = cur[t] ^ 1;
-    for (int r = 0; r < ta.nu2; ++r) {
-      if (own[t]) sm.v[t][c][pi[t]] = x;
-      __syncthreads();
-      x += idg[t] * (b[t] - tf_apply<C>(k9[t], sm.v[t][c], pi[t], P[t]));
-      c ^= 1;
-    }
-    if (t > 0) {
-      if (own[t]) sm.v[t][c][pi[t]] = x;
-      cur[t] = c;
-      __syncthreads();
-    } else if (own[0]) {
-      st<T, C>(xg + inst * sx + tid, x);
-    }
+  for (int m = 0; m < NPT; ++m)
+    if ((L0.own >> m) & 1u) st<T, C>(xg + inst * sx + L0.cj[m] * L0.n + L0.ci[m], x0[m]);
+}
+
+// LDS layout of k_tail_fast for levels n[0..nls] (elements of C); returns the total.
+template <class C>
+int tail_fast_layout(TailFastArgs<C>& ta, int nls) {
+  int off = 0;
+  for (int t = 0; t < nls; ++t) {
+    const int q = (ta.n[t] + 2) * (ta.n[t] + 2);
+    ta.ov[t][0] = off;
+    ta.ov[t][1] = off + q;
+    off += 2 * q;
   }
+  const int nc = ta.n[nls];
+  ta.ocb = off;
+  ta.ocy = off + nc * nc;
+  ta.ocx = off + 2 * nc * nc;
+  ta.ocw = ta.ocx + (nc + 2) * (nc + 2);
+  return ta.ocw + 4 * TF_NCN;
 }
 
 }  // namespace
@@ -1441,6 +1580,33 @@ Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L)
     --l0_;
   }
   tail_bytes_ = bytes;
+  // The register-resident tail (k_tail_fast): one or two Galerkin smoothing
+  // levels above an exact coarsest level of at most 16 x 16, the first at
+  // most 64 x 64.  Unless the caller bounds the tail, it takes a 64 x 64
+  // level too (measured on MI355X at 512^2, s = 3: faster than the tiled
+  // kernels for it).
+  fast_nls_ = 0;
+  fast_npt_ = 0;
+  fast_bytes_ = 0;
+  const int nlast = h->lev_n[levels_ - 1];
+  const bool fd = h->fd_n > 0 && h->fd_n == nlast;
+  auto fast_ok = [&](int l) {
+    const int nls = levels_ - 1 - l;
+    if (l < 1 || nls < 1 || nls > 2 || nlast > TF_NC || (fd && h->vark)) return false;
+    if (nls == 2 && sizeof(C) != 4) return false;   // FP64 coefficients of 4 nodes per thread do not fit registers
+    if (h->lev_n[l] > (nls == 1 ? 32 : TF_NMAX)) return false;
+    TailFastArgs<C> ta{};
+    for (int t = 0; t <= nls; ++t) ta.n[t] = h->lev_n[l + t];
+    return (size_t)tail_fast_layout<C>(ta, nls) * sizeof(C) <= budget;
+  };
+  if (h->opts.mg_tail_max <= 0 && l0_ > 1 && levels_ - l0_ == 2 && fast_ok(l0_ - 1)) --l0_;
+  if (fast_ok(l0_)) {
+    fast_nls_ = levels_ - 1 - l0_;
+    fast_npt_ = fast_nls_ == 2 ? 4 : 1;
+    TailFastArgs<C> ta{};
+    for (int t = 0; t <= fast_nls_; ++t) ta.n[t] = h->lev_n[l0_ + t];
+    fast_bytes_ = (size_t)tail_fast_layout<C>(ta, fast_nls_) * sizeof(C);
+  }
 }
 
 #define MG_TRY(...)                           \
@@ -1529,14 +1695,8 @@ hipError_t Multigrid<TI, TM>::prolong_smooth0(int stage, Vec xin, Vec ec, Vec b,
 template <class TI, class TM>
 hipError_t Multigrid<TI, TM>::tail(int stage, Vec x, Vec b, bool zero_init, int B) {
   if (h_->dim != 2) return hipErrorUnknown;   // the tail is 2D only
-  const int nls = levels_ - l0_ - 1;
-  const int nlast = h_->lev_n[levels_ - 1];
-  const bool use_fd = h_->fd_n > 0 && h_->fd_n == nlast;
-  // k_tail_fast: one smoothing level of at most 32 x 32 above the exact one
-  // (the usual tail: with the coarsest level at most 256 nodes, a level
-  // above it of at most 32 x 32 is the only smoothing level)
-  if (zero_init && l0_ > 0 && nls == 1 && h_->lev_n[l0_] <= TF_N0 && nlast * nlast <= TF_NCN &&
-      !(use_fd && h_->vark)) {
+  if (fast_nls_ > 0 && zero_init) {
+    const int nls = fast_nls_;
     TailFastArgs<C> tf{};
     for (int t = 0; t <= nls; ++t) tf.n[t] = h_->lev_n[l0_ + t];
     tf.a = (C)a_[stage];
@@ -1549,19 +1709,29 @@ hipError_t Multigrid<TI, TM>::tail(int stage, Vec x, Vec b, bool zero_init, int 
       tf.st9[t] = op.st9;
     }
     const bool dbl = sizeof(C) == 8;
+    const bool use_fd = h_->fd_n > 0 && h_->fd_n == h_->lev_n[levels_ - 1];
     tf.fd = use_fd ? reinterpret_cast<const C*>(h_->ws + (dbl ? h_->plan.fd_d : h_->plan.fd_f)) : nullptr;
     tf.cinv = use_fd ? nullptr : coarse_inv(stage);
+    tail_fast_layout<C>(tf, nls);
     const dim3 g((unsigned)B), blk((unsigned)TAIL_THREADS);
     TM* xp = (TM*)x.ptr;
     const TM* bp = (const TM*)b.ptr;
-#define TF_GO(K, NL, F) \
-  hipLaunchKernelGGL((k_tail_fast<K, NL, F, TM, C>), g, blk, 0, st_, xp, x.stride, bp, b.stride, tf)
-    if (h_->vark) TF_GO(KIND_STENCIL9, 1, false);
-    else if (use_fd) TF_GO(KIND_TENSOR, 1, true);
-    else TF_GO(KIND_TENSOR, 1, false);
+#define TF_GO(K, NL, NP, F) \
+  hipLaunchKernelGGL((k_tail_fast<K, NL, NP, F, TM, C>), g, blk, fast_bytes_, st_, xp, x.stride, bp, b.stride, tf)
+#define TF_KIND(NL, NP)                                 \
+  do {                                                  \
+    if (h_->vark) TF_GO(KIND_STENCIL9, NL, NP, false);  \
+    else if (use_fd) TF_GO(KIND_TENSOR, NL, NP, true);  \
+    else TF_GO(KIND_TENSOR, NL, NP, false);             \
+  } while (0)
+    if (nls == 1) TF_KIND(1, 1);
+    else if constexpr (sizeof(C) == 4) TF_KIND(2, 4);
+#undef TF_KIND
 #undef TF_GO
     return hipGetLastError();
   }
+  if (l0_ > 0 && !zero_init) return hipErrorInvalidValue;   // coarse tails always start from zero
+  if (tail_bytes_ > h_->lds_budget) return hipErrorInvalidValue;
   TailArgs<C> ta{};
   ta.nl = levels_ - l0_;
   ta.first_fine = l0_ == 0;
@@ -1787,6 +1957,22 @@ size_t mg_configure_lds() {
       (const void*)k_tail<false, float, float, float>, (const void*)k_tail<true, float, float, float>,
       (const void*)k_tail<false, __half, __half, float>, (const void*)k_tail<false, __hip_bfloat16, __hip_bfloat16, float>};
   for (const void* k : kernels)
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) != hipSuccess) {
+      (void)hipGetLastError();
+      return 65536;
+    }
+#define TF_PTR1(T, C)                                                                                     \
+  (const void*)k_tail_fast<KIND_STENCIL9, 1, 1, false, T, C>, (const void*)k_tail_fast<KIND_TENSOR, 1, 1, true, T, C>, \
+      (const void*)k_tail_fast<KIND_TENSOR, 1, 1, false, T, C>
+#define TF_PTR2(T, C)                                                                                     \
+  (const void*)k_tail_fast<KIND_STENCIL9, 2, 4, false, T, C>, (const void*)k_tail_fast<KIND_TENSOR, 2, 4, true, T, C>, \
+      (const void*)k_tail_fast<KIND_TENSOR, 2, 4, false, T, C>
+  const void* fast[] = {TF_PTR1(double, double), TF_PTR1(float, float), TF_PTR1(__half, float),
+                        TF_PTR1(__hip_bfloat16, float), TF_PTR2(float, float), TF_PTR2(__half, float),
+                        TF_PTR2(__hip_bfloat16, float)};
+#undef TF_PTR1
+#undef TF_PTR2
+  for (const void* k : fast)
     if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) != hipSuccess) {
       (void)hipGetLastError();
       return 65536;

@@ -63,6 +63,9 @@ class Multigrid {
   int levels_;
   int l0_;          // first level solved by the one-workgroup LDS tail
   size_t tail_bytes_;
+  int fast_nls_;    // > 0: the tail runs k_tail_fast with this many smoothing levels
+  int fast_npt_;    // its nodes per thread on the first tail level (1 or 4)
+  size_t fast_bytes_;
   int cinv_set_;    // 0: shifts of P-tilde, 1: of its transpose
 };
 
