@@ -87,7 +87,10 @@ typedef struct aao_opts {
   int precision;           /* aao_precision of P-tilde                         */
   int use_graph;           /* 1: replay P-tilde as a captured HIP graph        */
   int mg_tail_max;         /* largest multigrid level (nodes) solved inside one
-                              workgroup's LDS (2D); 0 = 1024, capped by LDS    */
+                              workgroup's LDS (2D); 0 = 1024, extended to one
+                              more level of at most 64 x 64 when the
+                              register-resident tail takes it (FP32, BF16,
+                              FP16 arithmetic); capped by LDS                  */
   int coarse_max;          /* coarsening stops at a level of at most this many
                               nodes, solved exactly; 0 = 256.  Up to 1024 for
                               2D constant kappa (fast diagonalization), up to
