@@ -332,6 +332,11 @@ __global__ __launch_bounds__(TPB) void k_prolong_smooth(const TX* __restrict__ x
 // halo work is redundant, the results are those of the separate sweeps).
 // ---------------------------------------------------------------------------
 constexpr int TCX = 16, TCY = 8;   // coarse nodes per down tile; fine tile is 2x
+// Level 0 with FP32 arithmetic uses TY0 coarse rows per tile: less halo and
+// padding work per owned node (1.5x instead of 2x) in the HBM-bound batched
+// sweeps; the LDS of an FP64 tile that tall would exceed 64 KiB.
+constexpr int TY0 = 16;
+constexpr int TALL_MIN_B = 8;   // blocks per launch from which level 0 uses TY0
 
 // Shared memory of one tile with halo R: right-hand side, two iterates, and
 // the operator staged for the sweeps (omega / diagonal per node; face
@@ -345,9 +350,9 @@ constexpr int TCX = 16, TCY = 8;   // coarse nodes per down tile; fine tile is 2
 // their stencil neighbours are in bounds, so the sweeps run without
 // branches, computing every node and selecting zero where a node is not
 // updated (the tile border, nodes outside the domain, the padding).
-template <int KIND, int R, class C>
+template <int KIND, int R, class C, int TY>
 struct Tile {
-  static constexpr int W = 2 * TCX + 1 + 2 * R, H = 2 * TCY + 1 + 2 * R, NE = W * H;
+  static constexpr int W = 2 * TCX + 1 + 2 * R, H = 2 * TY + 1 + 2 * R, NE = W * H;
   static constexpr int IT = (NE + 255) / 256, NP = IT * 256, G = W + 1, NS = NP + 2 * G;
   static constexpr bool VK = KIND == KIND_FINE_VK, TEN = KIND == KIND_TENSOR, S9 = KIND == KIND_STENCIL9;
   C b[NS], x0[NS], x1[NS];
@@ -367,9 +372,9 @@ struct Elems {
   unsigned dom, inner;
 };
 
-template <int KIND, int R, class C>
-__device__ __forceinline__ Elems<Tile<KIND, R, C>::IT> tile_elems(int ox, int oy, int n) {
-  using T = Tile<KIND, R, C>;
+template <int KIND, int R, class C, int TY>
+__device__ __forceinline__ Elems<Tile<KIND, R, C, TY>::IT> tile_elems(int ox, int oy, int n) {
+  using T = Tile<KIND, R, C, TY>;
   Elems<T::IT> e;
   e.dom = 0;
   e.inner = 0;
@@ -398,10 +403,10 @@ struct Coef9 {
   C v[IT][(KIND == KIND_STENCIL9 || KIND == KIND_TENSOR) ? 9 : 1];
 };
 
-template <int KIND, int R, class C>
-__device__ __forceinline__ void tile_load_coef(Coef9<KIND, Tile<KIND, R, C>::IT, C>& k9, const LevelOp<C>& op, int ox,
-                                               int oy, const Elems<Tile<KIND, R, C>::IT>& el) {
-  using T = Tile<KIND, R, C>;
+template <int KIND, int R, class C, int TY>
+__device__ __forceinline__ void tile_load_coef(Coef9<KIND, Tile<KIND, R, C, TY>::IT, C>& k9, const LevelOp<C>& op, int ox,
+                                               int oy, const Elems<Tile<KIND, R, C, TY>::IT>& el) {
+  using T = Tile<KIND, R, C, TY>;
   if constexpr (T::S9) {
     const int n = op.n;
 #pragma unroll
@@ -416,10 +421,10 @@ __device__ __forceinline__ void tile_load_coef(Coef9<KIND, Tile<KIND, R, C>::IT,
 
 // Stage the operator of the tile whose origin is (ox, oy) into LDS.  Loads
 // only; the caller synchronizes.
-template <int KIND, int R, class C>
-__device__ __forceinline__ void tile_stage_op(Tile<KIND, R, C>& sm, const LevelOp<C>& op, int ox, int oy,
-                                              const Elems<Tile<KIND, R, C>::IT>& el) {
-  using T = Tile<KIND, R, C>;
+template <int KIND, int R, class C, int TY>
+__device__ __forceinline__ void tile_stage_op(Tile<KIND, R, C, TY>& sm, const LevelOp<C>& op, int ox, int oy,
+                                              const Elems<Tile<KIND, R, C, TY>::IT>& el) {
+  using T = Tile<KIND, R, C, TY>;
   constexpr int W = T::W, H = T::H;
   const int tid = threadIdx.x, n = op.n;
   if constexpr (T::VK) {
@@ -471,11 +476,11 @@ __device__ __forceinline__ void tile_stage_op(Tile<KIND, R, C>& sm, const LevelO
   }
 }
 
-template <int KIND, int R, class C>
-__device__ __forceinline__ void tile_finish_coef(Coef9<KIND, Tile<KIND, R, C>::IT, C>& k9,
-                                                 const Tile<KIND, R, C>& sm,
-                                                 const Elems<Tile<KIND, R, C>::IT>& el) {
-  using T = Tile<KIND, R, C>;
+template <int KIND, int R, class C, int TY>
+__device__ __forceinline__ void tile_finish_coef(Coef9<KIND, Tile<KIND, R, C, TY>::IT, C>& k9,
+                                                 const Tile<KIND, R, C, TY>& sm,
+                                                 const Elems<Tile<KIND, R, C, TY>::IT>& el) {
+  using T = Tile<KIND, R, C, TY>;
   if constexpr (T::S9 || T::TEN) {
     constexpr int W = T::W, H = T::H;
 #pragma unroll
@@ -496,9 +501,9 @@ __device__ __forceinline__ void tile_finish_coef(Coef9<KIND, Tile<KIND, R, C>::I
 }
 
 // Diagonal of the level operator at tile node t (per-node arrays offset by G).
-template <int KIND, int R, class C>
-__device__ __forceinline__ C tile_diag(const Tile<KIND, R, C>& sm, const LevelOp<C>& op, int t, const C* kc) {
-  using T = Tile<KIND, R, C>;
+template <int KIND, int R, class C, int TY>
+__device__ __forceinline__ C tile_diag(const Tile<KIND, R, C, TY>& sm, const LevelOp<C>& op, int t, const C* kc) {
+  using T = Tile<KIND, R, C, TY>;
   if constexpr (KIND == KIND_FINE) return C(1) + op.a * op.ih2 * C(4);
   else if constexpr (T::S9 || T::TEN)
     return kc[4];
@@ -512,10 +517,10 @@ __device__ __forceinline__ C tile_diag(const Tile<KIND, R, C>& sm, const LevelOp
 // (A x)_t for tile node t; x points at node 0 of a per-node array.  Every
 // neighbour index is inside the padded array; the value is only used for
 // nodes whose 8 neighbours are tile nodes.
-template <int KIND, int R, class C>
-__device__ __forceinline__ C tile_Ax(const Tile<KIND, R, C>& sm, const C* __restrict__ x, const LevelOp<C>& op, int t,
+template <int KIND, int R, class C, int TY>
+__device__ __forceinline__ C tile_Ax(const Tile<KIND, R, C, TY>& sm, const C* __restrict__ x, const LevelOp<C>& op, int t,
                                      const C* kc) {
-  using T = Tile<KIND, R, C>;
+  using T = Tile<KIND, R, C, TY>;
   constexpr int W = T::W;
   const C c = x[t];
   if constexpr (T::S9 || T::TEN) {
@@ -536,34 +541,34 @@ __device__ __forceinline__ C tile_Ax(const Tile<KIND, R, C>& sm, const C* __rest
 
 // One weighted Jacobi sweep cur -> nxt over the tile (cur, nxt at node 0;
 // border, out-of-domain and padding nodes become zero).
-template <int KIND, int R, class C>
-__device__ __forceinline__ void tile_sweep(Tile<KIND, R, C>& sm, const C* cur, C* nxt, const LevelOp<C>& op, C omega,
-                                           const Coef9<KIND, Tile<KIND, R, C>::IT, C>& k9,
-                                           const Elems<Tile<KIND, R, C>::IT>& el) {
-  using T = Tile<KIND, R, C>;
+template <int KIND, int R, class C, int TY>
+__device__ __forceinline__ void tile_sweep(Tile<KIND, R, C, TY>& sm, const C* cur, C* nxt, const LevelOp<C>& op, C omega,
+                                           const Coef9<KIND, Tile<KIND, R, C, TY>::IT, C>& k9,
+                                           const Elems<Tile<KIND, R, C, TY>::IT>& el) {
+  using T = Tile<KIND, R, C, TY>;
   const C idc = omega / (C(1) + op.a * op.ih2 * C(4));
   const C* b = sm.b + T::G;
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
     const int t = threadIdx.x + it * 256;
     const C id = KIND == KIND_FINE ? idc : sm.idg[KIND == KIND_FINE ? 0 : T::G + t];
-    const C v = cur[t] + id * (b[t] - tile_Ax<KIND, R, C>(sm, cur, op, t, k9.v[it]));
+    const C v = cur[t] + id * (b[t] - tile_Ax<KIND, R, C, TY>(sm, cur, op, t, k9.v[it]));
     nxt[t] = ((el.inner >> it) & 1u) ? v : C(0);
   }
 }
 
 // omega / diagonal for every tile node (zero outside the domain); after the
 // operator is staged.
-template <int KIND, int R, class C>
-__device__ __forceinline__ void tile_inv_diag(Tile<KIND, R, C>& sm, const LevelOp<C>& op, C omega,
-                                              const Coef9<KIND, Tile<KIND, R, C>::IT, C>& k9,
-                                              const Elems<Tile<KIND, R, C>::IT>& el) {
-  using T = Tile<KIND, R, C>;
+template <int KIND, int R, class C, int TY>
+__device__ __forceinline__ void tile_inv_diag(Tile<KIND, R, C, TY>& sm, const LevelOp<C>& op, C omega,
+                                              const Coef9<KIND, Tile<KIND, R, C, TY>::IT, C>& k9,
+                                              const Elems<Tile<KIND, R, C, TY>::IT>& el) {
+  using T = Tile<KIND, R, C, TY>;
   if constexpr (KIND != KIND_FINE) {
 #pragma unroll
     for (int it = 0; it < T::IT; ++it) {
       const int t = threadIdx.x + it * 256;
-      const C v = omega / tile_diag<KIND, R, C>(sm, op, t, k9.v[it]);
+      const C v = omega / tile_diag<KIND, R, C, TY>(sm, op, t, k9.v[it]);
       sm.idg[T::G + t] = ((el.dom >> it) & 1u) ? v : C(0);
     }
   }
@@ -584,13 +589,13 @@ struct CplArgs {
 // b_c = R (b - A x_NU) -> bc, on the fine nodes of coarse tile (I0.., J0..).
 // NZ > 0 (level 0 only): b is first replaced by b - sum_l c_l K z_l, staged
 // with one more halo ring of each z_l, and written to cpl.out.
-template <int KIND, int NU, class TF, class TC, class C, int NZ>
+template <int KIND, int NU, class TF, class TC, class C, int NZ, int TY>
 __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_t sb, const TF* __restrict__ x0,
                                                 int64_t sx0, TF* __restrict__ xout, int64_t sxo, TC* __restrict__ bc,
                                                 int64_t sbc, LevelOp<C> op, int nc, C omega, int gx, int gy,
                                                 CplArgs<TF, C> cpl, C bscale) {
   constexpr int R = NU + 1;
-  using T = Tile<KIND, R, C>;
+  using T = Tile<KIND, R, C, TY>;
   constexpr int W = T::W, G = T::G;
   constexpr int ZW = W + 2, ZH = T::H + 2, ZNE = NZ > 0 ? ZW * ZH : 1, ZIT = (ZNE + 255) / 256;
   static_assert(NZ == 0 || KIND == KIND_FINE || KIND == KIND_FINE_VK, "coupling terms live on level 0");
@@ -599,14 +604,14 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
   const int tid = threadIdx.x;
   const int nf = op.n;
   const int L = xcd_tile((int)blockIdx.x, (int)gridDim.x);  // grid: gx * gy tiles per block
-  const int I0 = (L % gx) * TCX, J0 = ((L / gx) % gy) * TCY;
+  const int I0 = (L % gx) * TCX, J0 = ((L / gx) % gy) * TY;
   const int64_t inst = L / (gx * gy);
   const int ox = 2 * I0 - R, oy = 2 * J0 - R;
   const TF* bi = b + inst * sb;
   const TF* xi = x0 ? x0 + inst * sx0 : nullptr;
-  const Elems<T::IT> el = tile_elems<KIND, R, C>(ox, oy, nf);
+  const Elems<T::IT> el = tile_elems<KIND, R, C, TY>(ox, oy, nf);
   Coef9<KIND, T::IT, C> k9;
-  tile_load_coef<KIND, R, C>(k9, op, ox, oy, el);
+  tile_load_coef<KIND, R, C, TY>(k9, op, ox, oy, el);
   C bv[T::IT], xv[T::IT];
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
@@ -633,7 +638,7 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
         if (t < ZNE) szt[l][t] = zv[l][it];
       }
   }
-  tile_stage_op<KIND, R, C>(sm, op, ox, oy, el);
+  tile_stage_op<KIND, R, C, TY>(sm, op, ox, oy, el);
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
     const int t = tid + it * 256;
@@ -641,7 +646,7 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
     sm.x0[G + t] = xv[it];
   }
   __syncthreads();
-  const int hx = (I0 + TCX >= nc) ? nf : 2 * (I0 + TCX), hy = (J0 + TCY >= nc) ? nf : 2 * (J0 + TCY);
+  const int hx = (I0 + TCX >= nc) ? nf : 2 * (I0 + TCX), hy = (J0 + TY >= nc) ? nf : 2 * (J0 + TY);
   if constexpr (NZ > 0) {
     // b <- b - sum_l c_l K z_l at every in-domain tile node (each thread
     // updates only the nodes it reads later); owned nodes go to cpl.out
@@ -672,8 +677,8 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
       }
     }
   }
-  tile_finish_coef<KIND, R, C>(k9, sm, el);
-  tile_inv_diag<KIND, R, C>(sm, op, omega, k9, el);
+  tile_finish_coef<KIND, R, C, TY>(k9, sm, el);
+  tile_inv_diag<KIND, R, C, TY>(sm, op, omega, k9, el);
   C* cur = sm.x0 + G;
   C* nxt = sm.x1 + G;
   const C* bt = sm.b + G;
@@ -692,7 +697,7 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
   }
   __syncthreads();
   for (; k < NU; ++k) {
-    tile_sweep<KIND, R, C>(sm, cur, nxt, op, omega, k9, el);
+    tile_sweep<KIND, R, C, TY>(sm, cur, nxt, op, omega, k9, el);
     __syncthreads();
     C* tmp = cur; cur = nxt; nxt = tmp;
   }
@@ -700,11 +705,11 @@ __global__ __launch_bounds__(256) void k_down2d(const TF* __restrict__ b, int64_
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
     const int t = tid + it * 256;
-    const C v = bt[t] - tile_Ax<KIND, R, C>(sm, cur, op, t, k9.v[it]);
+    const C v = bt[t] - tile_Ax<KIND, R, C, TY>(sm, cur, op, t, k9.v[it]);
     nxt[t] = ((el.inner >> it) & 1u) ? v : C(0);
   }
   __syncthreads();
-  for (int c = tid; c < TCX * TCY; c += 256) {
+  for (int c = tid; c < TCX * TY; c += 256) {
     const int cx = c % TCX, cy = c / TCX, I = I0 + cx, J = J0 + cy;
     if (I >= nc || J >= nc) continue;
     const int tc = (2 * cy + 1 + R) * W + (2 * cx + 1 + R);
@@ -730,27 +735,27 @@ __device__ __forceinline__ int floor_half(int v) { return v >= 0 ? v / 2 : -((1 
 // owned fine nodes written to xout.  The coarse correction of the tile is
 // staged in LDS; fine node g takes lo = floor((g - 1) / 2) with weight 1
 // (odd g) or lo and lo + 1 with weights 1/2 (even g) along each axis.
-template <int KIND, int NU, class TF, class TE, class C>
+template <int KIND, int NU, class TF, class TE, class C, int TY>
 __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_t sxi, const TE* __restrict__ e,
                                               int64_t se, const TF* __restrict__ b, int64_t sb, TF* __restrict__ xout,
                                               int64_t sxo, LevelOp<C> op, int nc, C omega, int gx, int gy,
                                               C escale) {
   constexpr int R = NU;
-  using T = Tile<KIND, R, C>;
+  using T = Tile<KIND, R, C, TY>;
   constexpr int G = T::G;
-  constexpr int CW = TCX + R + 3, CH = TCY + R + 3, CNE = CW * CH, CIT = (CNE + 255) / 256;
+  constexpr int CW = TCX + R + 3, CH = TY + R + 3, CNE = CW * CH, CIT = (CNE + 255) / 256;
   __shared__ T sm;
   __shared__ C sec[CNE];
   const int tid = threadIdx.x;
   const int nf = op.n;
   const int L = xcd_tile((int)blockIdx.x, (int)gridDim.x);  // grid: gx * gy tiles per block
-  const int I0 = (L % gx) * TCX, J0 = ((L / gx) % gy) * TCY;
+  const int I0 = (L % gx) * TCX, J0 = ((L / gx) % gy) * TY;
   const int64_t inst = L / (gx * gy);
   const int ox = 2 * I0 - R, oy = 2 * J0 - R;
   const int cx0 = floor_half(ox - 1), cy0 = floor_half(oy - 1);
-  const Elems<T::IT> el = tile_elems<KIND, R, C>(ox, oy, nf);
+  const Elems<T::IT> el = tile_elems<KIND, R, C, TY>(ox, oy, nf);
   Coef9<KIND, T::IT, C> k9;
-  tile_load_coef<KIND, R, C>(k9, op, ox, oy, el);
+  tile_load_coef<KIND, R, C, TY>(k9, op, ox, oy, el);
   C bv[T::IT], xv[T::IT], ev[CIT];
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
@@ -765,7 +770,7 @@ __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_
     const bool in = t < CNE && I >= 0 && I < nc && J >= 0 && J < nc;
     ev[it] = in ? escale * ld<TE, C>(e + inst * se + (int64_t)J * nc + I) : C(0);
   }
-  tile_stage_op<KIND, R, C>(sm, op, ox, oy, el);
+  tile_stage_op<KIND, R, C, TY>(sm, op, ox, oy, el);
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
     const int t = tid + it * 256;
@@ -778,8 +783,8 @@ __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_
     if (t < CNE) sec[t] = ev[it];
   }
   __syncthreads();
-  tile_finish_coef<KIND, R, C>(k9, sm, el);
-  tile_inv_diag<KIND, R, C>(sm, op, omega, k9, el);
+  tile_finish_coef<KIND, R, C, TY>(k9, sm, el);
+  tile_inv_diag<KIND, R, C, TY>(sm, op, omega, k9, el);
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
     const int t = tid + it * 256;
@@ -795,11 +800,11 @@ __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_
   C* cur = sm.x0 + G;
   C* nxt = sm.x1 + G;
   for (int k = 0; k < NU; ++k) {
-    tile_sweep<KIND, R, C>(sm, cur, nxt, op, omega, k9, el);
+    tile_sweep<KIND, R, C, TY>(sm, cur, nxt, op, omega, k9, el);
     __syncthreads();
     C* tmp = cur; cur = nxt; nxt = tmp;
   }
-  const int hx = (I0 + TCX >= nc) ? nf : 2 * (I0 + TCX), hy = (J0 + TCY >= nc) ? nf : 2 * (J0 + TCY);
+  const int hx = (I0 + TCX >= nc) ? nf : 2 * (I0 + TCX), hy = (J0 + TY >= nc) ? nf : 2 * (J0 + TY);
 #pragma unroll
   for (int it = 0; it < T::IT; ++it) {
     const int t = tid + it * 256;
@@ -1779,7 +1784,12 @@ hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, in
   const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
   const int nc = h_->lev_n[l + 1];
   const C omega = (C)h_->omega;
-  const int gx = (nc + TCX - 1) / TCX, gy = (nc + TCY - 1) / TCY;
+  // tall level-0 tiles for batched launches (HBM-bound); latency-bound single
+  // blocks keep the short ones (more workgroups, shorter critical path)
+  const bool tall = l == 0 && sizeof(C) == 4 && B >= TALL_MIN_B;
+  constexpr int TY0L = sizeof(C) == 4 ? TY0 : TCY;
+  const int ty = tall ? TY0 : TCY;
+  const int gx = (nc + TCX - 1) / TCX, gy = (nc + ty - 1) / ty;
   const dim3 g((unsigned)(gx * gy * B));
   const int nu = h_->opts.nu1;
   const int nz = (l == 0 && cpl) ? cpl->nz : 0;
@@ -1794,7 +1804,8 @@ hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, in
   }
   CplArgs<TM, C> cm{};
   const C bs = l == 0 ? (C)h_->mg_scale : C(1);
-#define DN(K, NU, TF, NZ, CA) hipLaunchKernelGGL((k_down2d<K, NU, TF, TM, C, NZ>), g, dim3(256), 0, st_, (const TF*)b.ptr, b.stride, (const TF*)x0, sx0, (TF*)xout.ptr, xout.stride, (TM*)bc.ptr, bc.stride, op, nc, omega, gx, gy, CA, bs)
+#define DN_T(K, NU, TF, NZ, CA, TYV) hipLaunchKernelGGL((k_down2d<K, NU, TF, TM, C, NZ, TYV>), g, dim3(256), 0, st_, (const TF*)b.ptr, b.stride, (const TF*)x0, sx0, (TF*)xout.ptr, xout.stride, (TM*)bc.ptr, bc.stride, op, nc, omega, gx, gy, CA, bs)
+#define DN(K, NU, TF, NZ, CA) do { if ((K == KIND_FINE || K == KIND_FINE_VK) && tall) DN_T(K, NU, TF, NZ, CA, TY0L); else DN_T(K, NU, TF, NZ, CA, TCY); } while (0)
 #define DN_NU(K, TF, NZ, CA) do { if (nu == 1) DN(K, 1, TF, NZ, CA); else if (nu == 2) DN(K, 2, TF, NZ, CA); else DN(K, 3, TF, NZ, CA); } while (0)
 #define DN_Z(K) do { if (nz == 0) DN_NU(K, TI, 0, ca); else if (nz == 1) DN_NU(K, TI, 1, ca); else DN_NU(K, TI, 2, ca); } while (0)
   if (l == 0) {
@@ -1805,6 +1816,7 @@ hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, in
 #undef DN_Z
 #undef DN_NU
 #undef DN
+#undef DN_T
   return hipGetLastError();
 }
 
@@ -1813,11 +1825,15 @@ hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec
   const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
   const int nc = h_->lev_n[l + 1];
   const C omega = (C)h_->omega;
-  const int gx = (nc + TCX - 1) / TCX, gy = (nc + TCY - 1) / TCY;
+  const bool tall = l == 0 && sizeof(C) == 4 && B >= TALL_MIN_B;
+  constexpr int TY0L = sizeof(C) == 4 ? TY0 : TCY;
+  const int ty = tall ? TY0 : TCY;
+  const int gx = (nc + TCX - 1) / TCX, gy = (nc + ty - 1) / ty;
   const dim3 g((unsigned)(gx * gy * B));
   const int nu = h_->opts.nu2;
   const C es = l == 0 ? (C)(1.0 / h_->mg_scale) : C(1);
-#define UP(K, NU, TF) hipLaunchKernelGGL((k_up2d<K, NU, TF, TM, C>), g, dim3(256), 0, st_, (const TF*)xin.ptr, xin.stride, (const TM*)ec.ptr, ec.stride, (const TF*)b.ptr, b.stride, (TF*)xout.ptr, xout.stride, op, nc, omega, gx, gy, es)
+#define UP_T(K, NU, TF, TYV) hipLaunchKernelGGL((k_up2d<K, NU, TF, TM, C, TYV>), g, dim3(256), 0, st_, (const TF*)xin.ptr, xin.stride, (const TM*)ec.ptr, ec.stride, (const TF*)b.ptr, b.stride, (TF*)xout.ptr, xout.stride, op, nc, omega, gx, gy, es)
+#define UP(K, NU, TF) do { if ((K == KIND_FINE || K == KIND_FINE_VK) && tall) UP_T(K, NU, TF, TY0L); else UP_T(K, NU, TF, TCY); } while (0)
 #define UP_NU(K, TF) do { if (nu == 1) UP(K, 1, TF); else if (nu == 2) UP(K, 2, TF); else UP(K, 3, TF); } while (0)
   if (l == 0) {
     if (h_->vark) UP_NU(KIND_FINE_VK, TI); else UP_NU(KIND_FINE, TI);
@@ -1826,6 +1842,7 @@ hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec
   }
 #undef UP_NU
 #undef UP
+#undef UP_T
   return hipGetLastError();
 }
 

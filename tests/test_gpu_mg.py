@@ -99,6 +99,30 @@ def test_apply_mg_full_size_sampled_blocks():
     assert np.array_equal(zp, z[perm])
 
 
+@pytest.mark.parametrize("n,vark", [(150, False), (257, False), (75, True)])
+def test_apply_mg_fp32_batched_tiles_equal_single_blocks(n, vark):
+    """With FP32 arithmetic, level 0 runs taller tiles for launches of 8 or
+    more blocks and the short ones for single blocks.  Jacobi sweeps
+    recomputed in tile halos give every node the same value either way, so a
+    9-block call equals nine 1-block calls bit for bit; both match the oracle
+    (ragged last tiles at 150 and 257, face diffusivities at 75)."""
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    dim, s, nt = 2, 2, 9
+    rng = np.random.default_rng(5 * n)
+    kappa = np.exp(0.5 * rng.standard_normal(n * n)) if vark else None
+    p = allatonce.Problem(n, dim, s, nt, 1.0, kappa=kappa)
+    hp = HeatProblem(dim, n, s, nt, 1.0, precision="fp32", kappa=kappa)
+    r = rng.standard_normal((nt, p.N)).astype(np.float32).astype(np.float64)
+    for stage in range(s):
+        announce("apply_mg fp32 batched vs single", n, "vark", vark, "stage", stage)
+        z = _run(hp, r, stage, 1, False)
+        single = np.stack([_run(hp, r[b:b + 1], stage, 1, False)[0] for b in range(nt)])
+        assert np.array_equal(z, single), stage
+        ref = _oracle(p, False, stage, r[[0, nt - 1]], 1)
+        assert rel_err(z[[0, nt - 1]], ref) <= 2e-5, (stage, rel_err(z[[0, nt - 1]], ref))
+
+
 # Variable diffusivity: coarse levels are the Galerkin products R A P of the
 # face-coefficient operator (9-point stencils), as in the oracle hierarchy.
 # 72: tiled stencil level + tail stencil levels; 130: several tiled levels;
