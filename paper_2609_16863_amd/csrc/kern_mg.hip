@@ -332,11 +332,11 @@ __global__ __launch_bounds__(TPB) void k_prolong_smooth(const TX* __restrict__ x
 // halo work is redundant, the results are those of the separate sweeps).
 // ---------------------------------------------------------------------------
 constexpr int TCX = 16, TCY = 8;   // coarse nodes per down tile; fine tile is 2x
-// Level 0 with FP32 arithmetic uses TY0 coarse rows per tile: less halo and
-// padding work per owned node (1.5x instead of 2x) in the HBM-bound batched
-// sweeps; the LDS of an FP64 tile that tall would exceed 64 KiB.
+// Batched launches with FP32 arithmetic use TY0 coarse rows per tile: less
+// halo and padding work per owned node (1.5x instead of 2x) in the HBM-bound
+// batched sweeps; the LDS of an FP64 tile that tall would exceed 64 KiB.
 constexpr int TY0 = 16;
-constexpr int TALL_MIN_B = 8;   // blocks per launch from which level 0 uses TY0
+constexpr int TALL_MIN_B = 8;   // blocks per launch from which the tiles are TY0 tall
 
 // Shared memory of one tile with halo R: right-hand side, two iterates, and
 // the operator staged for the sweeps (omega / diagonal per node; face
@@ -1784,9 +1784,9 @@ hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, in
   const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
   const int nc = h_->lev_n[l + 1];
   const C omega = (C)h_->omega;
-  // tall level-0 tiles for batched launches (HBM-bound); latency-bound single
-  // blocks keep the short ones (more workgroups, shorter critical path)
-  const bool tall = l == 0 && sizeof(C) == 4 && B >= TALL_MIN_B;
+  // tall tiles for batched launches (HBM-bound); latency-bound single blocks
+  // keep the short ones (more workgroups, shorter critical path)
+  const bool tall = sizeof(C) == 4 && B >= TALL_MIN_B;
   constexpr int TY0L = sizeof(C) == 4 ? TY0 : TCY;
   const int ty = tall ? TY0 : TCY;
   const int gx = (nc + TCX - 1) / TCX, gy = (nc + ty - 1) / ty;
@@ -1805,7 +1805,7 @@ hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, in
   CplArgs<TM, C> cm{};
   const C bs = l == 0 ? (C)h_->mg_scale : C(1);
 #define DN_T(K, NU, TF, NZ, CA, TYV) hipLaunchKernelGGL((k_down2d<K, NU, TF, TM, C, NZ, TYV>), g, dim3(256), 0, st_, (const TF*)b.ptr, b.stride, (const TF*)x0, sx0, (TF*)xout.ptr, xout.stride, (TM*)bc.ptr, bc.stride, op, nc, omega, gx, gy, CA, bs)
-#define DN(K, NU, TF, NZ, CA) do { if ((K == KIND_FINE || K == KIND_FINE_VK) && tall) DN_T(K, NU, TF, NZ, CA, TY0L); else DN_T(K, NU, TF, NZ, CA, TCY); } while (0)
+#define DN(K, NU, TF, NZ, CA) do { if (tall) DN_T(K, NU, TF, NZ, CA, TY0L); else DN_T(K, NU, TF, NZ, CA, TCY); } while (0)
 #define DN_NU(K, TF, NZ, CA) do { if (nu == 1) DN(K, 1, TF, NZ, CA); else if (nu == 2) DN(K, 2, TF, NZ, CA); else DN(K, 3, TF, NZ, CA); } while (0)
 #define DN_Z(K) do { if (nz == 0) DN_NU(K, TI, 0, ca); else if (nz == 1) DN_NU(K, TI, 1, ca); else DN_NU(K, TI, 2, ca); } while (0)
   if (l == 0) {
@@ -1825,7 +1825,7 @@ hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec
   const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
   const int nc = h_->lev_n[l + 1];
   const C omega = (C)h_->omega;
-  const bool tall = l == 0 && sizeof(C) == 4 && B >= TALL_MIN_B;
+  const bool tall = sizeof(C) == 4 && B >= TALL_MIN_B;
   constexpr int TY0L = sizeof(C) == 4 ? TY0 : TCY;
   const int ty = tall ? TY0 : TCY;
   const int gx = (nc + TCX - 1) / TCX, gy = (nc + ty - 1) / ty;
@@ -1833,7 +1833,7 @@ hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec
   const int nu = h_->opts.nu2;
   const C es = l == 0 ? (C)(1.0 / h_->mg_scale) : C(1);
 #define UP_T(K, NU, TF, TYV) hipLaunchKernelGGL((k_up2d<K, NU, TF, TM, C, TYV>), g, dim3(256), 0, st_, (const TF*)xin.ptr, xin.stride, (const TM*)ec.ptr, ec.stride, (const TF*)b.ptr, b.stride, (TF*)xout.ptr, xout.stride, op, nc, omega, gx, gy, es)
-#define UP(K, NU, TF) do { if ((K == KIND_FINE || K == KIND_FINE_VK) && tall) UP_T(K, NU, TF, TY0L); else UP_T(K, NU, TF, TCY); } while (0)
+#define UP(K, NU, TF) do { if (tall) UP_T(K, NU, TF, TY0L); else UP_T(K, NU, TF, TCY); } while (0)
 #define UP_NU(K, TF) do { if (nu == 1) UP(K, 1, TF); else if (nu == 2) UP(K, 2, TF); else UP(K, 3, TF); } while (0)
   if (l == 0) {
     if (h_->vark) UP_NU(KIND_FINE_VK, TI); else UP_NU(KIND_FINE, TI);

@@ -101,8 +101,8 @@ def test_apply_mg_full_size_sampled_blocks():
 
 @pytest.mark.parametrize("n,vark", [(150, False), (257, False), (75, True)])
 def test_apply_mg_fp32_batched_tiles_equal_single_blocks(n, vark):
-    """With FP32 arithmetic, level 0 runs taller tiles for launches of 8 or
-    more blocks and the short ones for single blocks.  Jacobi sweeps
+    """With FP32 arithmetic, the tiled levels run taller tiles for launches
+    of 8 or more blocks and the short ones for single blocks.  Jacobi sweeps
     recomputed in tile halos give every node the same value either way, so a
     9-block call equals nine 1-block calls bit for bit; both match the oracle
     (ragged last tiles at 150 and 257, face diffusivities at 75)."""
