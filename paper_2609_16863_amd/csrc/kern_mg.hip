@@ -1574,9 +1574,8 @@ Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L)
   l0_ = levels_ - 1;
   size_t bytes = cost(levels_ - 1) + sizeof(C) * 2 * (size_t)h->lev_N[levels_ - 1] +
                  sizeof(C) * (size_t)(h->fd_n * h->fd_n + h->fd_n);
-  // measured on MI355X (512^2, s=3): the generic one-workgroup tail is
-  // faster than grid kernels up to a 32 x 32 level, slower above it (the
-  // register-resident tail below goes one level further)
+  // measured on MI355X (512^2, s=3): one workgroup is faster than grid
+  // kernels up to a 32 x 32 level, slower above it
   const int64_t tail_max = h->opts.mg_tail_max > 0 ? h->opts.mg_tail_max : 1024;
   while (l0_ > 0 && levels_ - l0_ < TAIL_MAXL) {
     const size_t more = bytes + cost(l0_ - 1);
