@@ -61,7 +61,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the all-at-once solve "
-                          "is measured at its single-GPU shape (see DESIGN.md for how it would shard)"}))
+                          "is measured at its single-GPU shape (time slabs per GPU would be the "
+                          "sharding, with the S-tilde sweep pipelined across slabs)"}))
         sys.exit(2)
     import torch
 
