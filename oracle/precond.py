@@ -95,6 +95,7 @@ class StageOps:
         self.omega = omega if omega is not None else (0.8 if prob.dim == 2 else 6.0 / 7.0)
         self.nu1, self.nu2 = nu1, nu2
         self.exact_blocks = exact_blocks
+        self.coarse_max = coarse_max
         tau = prob.tau
         self.hier = [multigrid.Hierarchy(self.K, prob.n, prob.dim, tau * self.L[i, i], coarse_max)
                      for i in range(prob.s)]
@@ -138,8 +139,35 @@ class StageOps:
         return self._lu_theta.solve(np.asarray(r, float).ravel()).reshape(self.prob.s, self.prob.N)
 
 
-def apply_preconditioner(ops, r, exact=False):
-    """z = P-tilde^{-1} r (or P^{-1} r when exact=True) by block back-substitution."""
+def schur_propagator(ops, exact=False):
+    """Phi(z) = z - X-tilde z, X-tilde = tau (b^T (x) I) Theta-tilde^{-1} (e (x) K)
+    (eq. (3.3)); with exact=True, Theta_hat^{-1} in place of Theta-tilde^{-1}."""
+    prob = ops.prob
+    solve_step = ops.theta_inv if exact else ops.theta_tilde_inv
+
+    def phi(z):
+        y = solve_step(np.tile(ops.K @ z, (prob.s, 1)))
+        return z - prob.tau * np.tensordot(prob.b, y, axes=(0, 0))
+    return phi
+
+
+def coarse_stage_ops(ops, cf):
+    """StageOps of the same problem with the time step cf * tau (the MGRIT
+    coarse propagator takes one S-tilde step of that size)."""
+    p = ops.prob
+    pc = allatonce.Problem(p.n, p.dim, p.s, 1, cf * p.tau, kappa=p.kappa)
+    return StageOps(pc, inner_k=ops.inner_k, inner_tol=ops.inner_tol, cycles=ops.cycles, omega=ops.omega,
+                    nu1=ops.nu1, nu2=ops.nu2, exact_blocks=ops.exact_blocks, coarse_max=ops.coarse_max)
+
+
+def apply_preconditioner(ops, r, exact=False, mgrit=None):
+    """z = P-tilde^{-1} r (or P^{-1} r when exact=True) by block back-substitution.
+
+    mgrit: None for the forward substitution in S-tilde, or a dict with keys
+    cf, iters and optionally relax ("F" / "FCF") to apply S-tilde^{-1} by
+    two-level MGRIT (``oracle.mgrit``) with the coarse step cf * tau.
+    """
+    from . import mgrit as _mgrit
     prob = ops.prob
     nt, s, N, tau = prob.nt, prob.s, prob.N, prob.tau
     rv, rV = allatonce.split(prob, np.asarray(r, float))
@@ -150,12 +178,13 @@ def apply_preconditioner(ops, r, exact=False):
     tv = rv.copy()
     for n in range(nt):
         tv[n + 1] = rv[n + 1] + tau * np.tensordot(prob.b, zV[n], axes=(0, 0))
-    zv = np.empty_like(tv)
-    zv[0] = tv[0]
-    for n in range(nt):
-        y = solve_step(np.tile(ops.K @ zv[n], (s, 1)))
-        Xz = tau * np.tensordot(prob.b, y, axes=(0, 0))
-        zv[n + 1] = tv[n + 1] + zv[n] - Xz
+    phi = schur_propagator(ops, exact)
+    if mgrit is None:
+        zv = np.array(_mgrit.sequential(list(tv), phi))
+    else:
+        cf = mgrit["cf"]
+        phi_c = schur_propagator(coarse_stage_ops(ops, cf), exact)
+        zv = np.array(_mgrit.solve(list(tv), phi, phi_c, cf, mgrit["iters"], mgrit.get("relax", "F")))
     return allatonce.join(zv, zV)
 
 
