@@ -62,6 +62,18 @@ typedef enum aao_precision {
   AAO_PREC_FP16 = 3
 } aao_precision;
 
+/* How S-tilde^{-1} of eq. (3.3) is applied inside P-tilde. */
+typedef enum aao_schur {
+  AAO_SCHUR_SWEEP = 0,     /* forward substitution in time, one step after the
+                              other (the sequential form of Fig. 5.1)          */
+  AAO_SCHUR_MGRIT = 1      /* two-level MGRIT in time (the parallel runs of
+                              Sec. 5.2 replace the substitution by MGRIT):
+                              F- or FCF-relaxation batched over the coarse
+                              intervals, C-points every mgrit_cf steps, and a
+                              coarse propagator that is the S-tilde step with
+                              step size mgrit_cf tau                           */
+} aao_schur;
+
 /* Problem description (Sec. 2).  kappa: host pointer to N nodal
  * diffusivities (> 0), copied at creation, or NULL for kappa = 1.  A face
  * between two interior nodes carries their harmonic mean, a face to the
@@ -95,6 +107,17 @@ typedef struct aao_opts {
                               nodes, solved exactly; 0 = 256.  Up to 1024 for
                               2D constant kappa (fast diagonalization), up to
                               256 otherwise (dense inverse)                    */
+  double inner_tol;        /* an inner GMRES solve (Theta-tilde and every
+                              S-tilde step) stops early once its residual
+                              estimate is <= inner_tol times its initial
+                              residual (Sec. 5.2 runs 1e-3 / 1e-6); 0 = always
+                              inner_k iterations                               */
+  int schur;               /* aao_schur                                        */
+  int mgrit_cf;            /* MGRIT coarsening factor in time, 2..64 (0 = 8)   */
+  int mgrit_iters;         /* MGRIT iterations, 1..nt (0 = 1); with
+                              ceil(nt / mgrit_cf) - 1 of them the result is the
+                              forward substitution's                           */
+  int mgrit_fcf;           /* 1: FCF-relaxation, 0: F-relaxation               */
 } aao_opts;
 
 /* Solve statistics (host struct filled by aao_solve*). */
@@ -106,13 +129,24 @@ typedef struct aao_stats {
   double precond_ms;       /* time inside P-tilde applications                */
   double history[128];     /* relative residual estimate per iteration        */
   int history_len;
+  int inner_solves;        /* inner GMRES solves run (one per time step of each
+                              Theta-tilde application, one per S-tilde step)   */
+  long long inner_iterations;  /* inner GMRES iterations over all those solves;
+                              inner_iterations / inner_solves is the mean
+                              count per solve (inner_k unless inner_tol stops
+                              solves early)                                    */
+  double theta_ms;         /* time in the Theta-tilde phase of P-tilde
+                              (eq. (3.2): the batched block-diagonal solve)    */
+  double schur_ms;         /* time in the S-tilde phase (eq. (3.3): the
+                              sweep in time)                                   */
 } aao_stats;
 
 typedef struct aao_problem aao_problem;   /* opaque handle */
 
 /* Defaults: restart 30, maxit 100, tol 1e-8, inner_k 3, cycles 1,
  * nu1 = nu2 = 2, omega 0, precision FP64, use_graph 1, mg_tail_max 0,
- * coarse_max 0.  With use_graph the
+ * coarse_max 0, inner_tol 0, schur AAO_SCHUR_SWEEP, mgrit_cf 8,
+ * mgrit_iters 1, mgrit_fcf 0.  With use_graph the
  * first application of P-tilde for a given (inner_k, cycles, transpose) is
  * captured into a HIP graph on a private stream and later applications
  * replay it on the handle's stream (inputs and outputs pass through fixed
@@ -235,9 +269,13 @@ const char* aao_last_error(const aao_problem* h);
  * ------------------------------------------------------------------------ */
 typedef struct aao_batch aao_batch;   /* opaque */
 
+/* Streams a batch may use: the device runs the work of one process on four
+ * hardware queues, so more streams would only contend for them. */
+#define AAO_BATCH_MAX_STREAMS 4
+
 /* Create a batch of `count` problems described by descs[0..count-1], all
  * with the options *opts (NULL: defaults), to be run on `streams` streams
- * (1..16).  Errors as aao_create_problem, with the failing problem named in
+ * (1..AAO_BATCH_MAX_STREAMS).  Errors as aao_create_problem, with the failing problem named in
  * aao_batch_last_error(NULL). */
 int aao_create_batch(const aao_desc* descs, int count, const aao_opts* opts, int streams, aao_batch** out);
 

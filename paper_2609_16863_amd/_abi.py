@@ -13,6 +13,7 @@ AAO_NOT_CONVERGED = 1
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "HIP_ERROR", -3: "NONFINITE",
                 -4: "WORKSPACE_TOO_SMALL", -5: "NO_WORKSPACE"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+SCHUR = {"sweep": 0, "mgrit": 1}
 
 
 class Desc(ctypes.Structure):
@@ -23,13 +24,16 @@ class Desc(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("restart", c_int), ("maxit", c_int), ("tol", c_double), ("inner_k", c_int),
                 ("cycles", c_int), ("nu1", c_int), ("nu2", c_int), ("omega", c_double),
-                ("precision", c_int), ("use_graph", c_int), ("mg_tail_max", c_int), ("coarse_max", c_int)]
+                ("precision", c_int), ("use_graph", c_int), ("mg_tail_max", c_int), ("coarse_max", c_int),
+                ("inner_tol", c_double), ("schur", c_int), ("mgrit_cf", c_int), ("mgrit_iters", c_int),
+                ("mgrit_fcf", c_int)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("outer_iterations", c_int), ("restarts", c_int), ("relres", c_double),
                 ("time_ms", c_double), ("precond_ms", c_double), ("history", c_double * 128),
-                ("history_len", c_int)]
+                ("history_len", c_int), ("inner_solves", c_int), ("inner_iterations", ctypes.c_longlong),
+                ("theta_ms", c_double), ("schur_ms", c_double)]
 
 
 # name -> (restype, argtypes); every entry point declared in include/aao_heat.h

@@ -23,7 +23,8 @@ def _ptr(t):
 
 
 def _make_opts(lib, *, restart, maxit, tol, inner_k, cycles, nu1, nu2, omega, precision, use_graph,
-               mg_tail_max, coarse_max=0):
+               mg_tail_max, coarse_max=0, inner_tol=0.0, schur="sweep", mgrit_cf=8, mgrit_iters=1,
+               mgrit_fcf=False):
     opts = _abi.Opts()
     lib.aao_default_opts(ctypes.byref(opts))
     opts.restart, opts.maxit, opts.tol = restart, maxit, tol
@@ -33,12 +34,19 @@ def _make_opts(lib, *, restart, maxit, tol, inner_k, cycles, nu1, nu2, omega, pr
     opts.use_graph = int(bool(use_graph))
     opts.mg_tail_max = int(mg_tail_max)
     opts.coarse_max = int(coarse_max)
+    opts.inner_tol = float(inner_tol)
+    opts.schur = _abi.SCHUR[schur]
+    opts.mgrit_cf = int(mgrit_cf)
+    opts.mgrit_iters = int(mgrit_iters)
+    opts.mgrit_fcf = int(bool(mgrit_fcf))
     return opts
 
 
 def _stats_dict(st, code):
     return {"outer_iterations": st.outer_iterations, "restarts": st.restarts, "relres": st.relres,
-            "time_ms": st.time_ms, "precond_ms": st.precond_ms,
+            "time_ms": st.time_ms, "precond_ms": st.precond_ms, "theta_ms": st.theta_ms,
+            "schur_ms": st.schur_ms, "inner_solves": st.inner_solves,
+            "inner_iterations": st.inner_iterations,
             "history": list(st.history[: st.history_len]), "converged": code == 0}
 
 
@@ -53,12 +61,18 @@ class HeatProblem:
     Jacobi sweeps, and the preconditioner ``precision``
     ("fp64" | "fp32" | "bf16" | "fp16"); ``use_graph`` replays the
     preconditioner as a captured HIP graph; ``coarse_max`` is the size of the
-    exactly solved coarsest multigrid level (0: 256 nodes).
+    exactly solved coarsest multigrid level (0: 256 nodes); ``inner_tol`` stops
+    an inner GMRES solve early at that relative residual (0: always
+    ``inner_k`` iterations).  ``schur`` = "sweep" applies S-tilde^{-1} by
+    forward substitution in time, "mgrit" by two-level MGRIT with
+    coarsening factor ``mgrit_cf``, ``mgrit_iters`` iterations and F- (or,
+    with ``mgrit_fcf``, FCF-) relaxation.
     """
 
     def __init__(self, dim, n, s, nt, T=1.0, kappa=None, *, restart=30, maxit=100, tol=1e-8,
                  inner_k=3, cycles=1, nu1=2, nu2=2, omega=0.0, precision="fp64", use_graph=True,
-                 mg_tail_max=0, coarse_max=0, device="cuda"):
+                 mg_tail_max=0, coarse_max=0, inner_tol=0.0, schur="sweep", mgrit_cf=8, mgrit_iters=1,
+                 mgrit_fcf=False, device="cuda"):
         self._lib = _abi.load()
         self.dim, self.n, self.s, self.nt, self.T = dim, n, s, nt, float(T)
         self._kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
@@ -66,10 +80,13 @@ class HeatProblem:
                          None if self._kappa is None else self._kappa.ctypes.data)
         self.options = dict(restart=restart, maxit=maxit, tol=tol, inner_k=inner_k, cycles=cycles, nu1=nu1,
                             nu2=nu2, omega=omega, precision=precision, use_graph=use_graph,
-                            mg_tail_max=mg_tail_max, coarse_max=coarse_max, device=device)
+                            mg_tail_max=mg_tail_max, coarse_max=coarse_max, inner_tol=inner_tol,
+                            schur=schur, mgrit_cf=mgrit_cf, mgrit_iters=mgrit_iters, mgrit_fcf=mgrit_fcf,
+                            device=device)
         opts = _make_opts(self._lib, restart=restart, maxit=maxit, tol=tol, inner_k=inner_k, cycles=cycles,
                           nu1=nu1, nu2=nu2, omega=omega, precision=precision, use_graph=use_graph,
-                          mg_tail_max=mg_tail_max, coarse_max=coarse_max)
+                          mg_tail_max=mg_tail_max, coarse_max=coarse_max, inner_tol=inner_tol, schur=schur,
+                          mgrit_cf=mgrit_cf, mgrit_iters=mgrit_iters, mgrit_fcf=mgrit_fcf)
         self.precision = precision
         h = ctypes.c_void_p()
         code = self._lib.aao_create_problem(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h))
@@ -238,7 +255,7 @@ class HeatBatch:
 
     def __init__(self, problems, *, streams=4, restart=30, maxit=100, tol=1e-8, inner_k=3, cycles=1,
                  nu1=2, nu2=2, omega=0.0, precision="fp64", use_graph=True, mg_tail_max=0, coarse_max=0,
-                 device="cuda"):
+                 inner_tol=0.0, schur="sweep", mgrit_cf=8, mgrit_iters=1, mgrit_fcf=False, device="cuda"):
         self._lib = _abi.load()
         self.count = len(problems)
         self._kappas = []
@@ -253,7 +270,8 @@ class HeatBatch:
         self.tol = tol
         opts = _make_opts(self._lib, restart=restart, maxit=maxit, tol=tol, inner_k=inner_k, cycles=cycles,
                           nu1=nu1, nu2=nu2, omega=omega, precision=precision, use_graph=use_graph,
-                          mg_tail_max=mg_tail_max, coarse_max=coarse_max)
+                          mg_tail_max=mg_tail_max, coarse_max=coarse_max, inner_tol=inner_tol, schur=schur,
+                          mgrit_cf=mgrit_cf, mgrit_iters=mgrit_iters, mgrit_fcf=mgrit_fcf)
         h = ctypes.c_void_p()
         code = self._lib.aao_create_batch(descs, self.count, ctypes.byref(opts), int(streams), ctypes.byref(h))
         if code != 0:

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libaao_heat.so")
-SOURCES = ["setup.cpp", "api.hip", "batch.hip", "kern_allatonce.hip", "kern_mg.hip", "kern_krylov.hip", "solver.hip"]
+SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("AAO_OFFLOAD_ARCH", "gfx950")
 FLAGS = [

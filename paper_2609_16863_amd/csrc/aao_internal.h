@@ -125,7 +125,8 @@ struct aao_problem {
     size_t gIn, gOut;                        // fixed input/output of the captured P-tilde
     size_t inV, inZ, inW, inX;               // inner GMRES (nt instances)
     size_t rana;                              // Rana right-hand side (nt*N)
-    size_t schurRhs, schurY;                  // S-tilde sweep (s*N)
+    size_t schurRhs, schurY;                  // S-tilde steps (s*N per instance)
+    size_t mgritT, mgritG, mgritE;            // MGRIT: t (nt+1 blocks), C-point values, corrections
     std::vector<size_t> mgX, mgT, mgB, mgR;   // per level, nt instances
     size_t partial, dscal, counters;          // reductions / device scalars / tickets
     size_t partial_bytes, dscal_bytes;
@@ -138,13 +139,19 @@ struct aao_problem {
   size_t lds_budget = 65536;                  // LDS bytes per workgroup for the multigrid tail
   struct GraphEntry {
     bool transpose;
-    int k, cycles;
+    int k, cycles, phase;
     hipGraph_t graph;
     hipGraphExec_t exec;
   };
   std::vector<GraphEntry> graphs;             // captured P-tilde applications
   hipStream_t capture_stream = nullptr;
+  hipEvent_t phase_ev[3] = {nullptr, nullptr, nullptr};   // P-tilde phase timing
   double* hpin = nullptr;                     // pinned host scalars
+  // Set while a call runs in the library's static scratch memory: no graph
+  // capture, no events, and host reads go through hpage instead of hpin.
+  bool no_alloc = false;
+  double hpage[4096];
+  double* host_scalars() { return no_alloc || !hpin ? hpage : hpin; }
   std::string err;
 };
 
@@ -186,6 +193,10 @@ hipError_t launch_fill(T* dst, T v, int64_t n, hipStream_t st);
 
 // kern_mg.hip
 size_t mg_configure_lds();
+
+// api.hip: copy the handle's constant tables into its workspace (h->ws) and
+// clear its counters, on the handle's stream (not synchronised).
+hipError_t upload_tables(aao_problem* h);
 
 // solver.hip
 void release_graphs(aao_problem* h);

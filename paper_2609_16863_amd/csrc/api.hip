@@ -54,8 +54,16 @@ void plan_workspace(aao_problem* h) {
   P.inW = take((size_t)UV * pi);
   P.inX = take((size_t)UV * pi);
   P.rana = take((size_t)h->nt * N * pi);
-  P.schurRhs = take((size_t)h->s * N * pi);
-  P.schurY = take((size_t)h->s * N * pi);
+  // S-tilde step buffers: one instance for the substitution, one per coarse
+  // interval for MGRIT's batched relaxation; MGRIT keeps t, the C-point
+  // values g and the coarse corrections e apart
+  const bool mgrit = h->opts.schur == AAO_SCHUR_MGRIT;
+  const int64_t Kc = mgrit ? (h->nt + h->opts.mgrit_cf - 1) / h->opts.mgrit_cf : 1;
+  P.schurRhs = take((size_t)Kc * h->s * N * pi);
+  P.schurY = take((size_t)Kc * h->s * N * pi);
+  P.mgritT = take(mgrit ? (size_t)(h->nt + 1) * N * pi : 0);
+  P.mgritG = take(mgrit ? (size_t)Kc * N * pi : 0);
+  P.mgritE = take(mgrit ? (size_t)Kc * N * pi : 0);
   P.mgX.assign(L, 0);
   P.mgT.assign(L, 0);
   P.mgB.assign(L, 0);
@@ -89,6 +97,11 @@ bool valid_opts(const aao_opts* o, std::string& why) {
   if (o->omega < 0.0 || o->omega >= 2.0) { why = "omega must be in [0, 2)"; return false; }
   if (o->mg_tail_max < 0) { why = "mg_tail_max must be >= 0"; return false; }
   if (o->coarse_max < 0 || o->coarse_max > aao::COARSE_FD_MAX) { why = "coarse_max must be in [0, 1024]"; return false; }
+  if (!(o->inner_tol >= 0.0 && o->inner_tol < 1.0)) { why = "inner_tol must be in [0, 1)"; return false; }
+  if (o->schur != AAO_SCHUR_SWEEP && o->schur != AAO_SCHUR_MGRIT) { why = "unknown schur"; return false; }
+  if (o->mgrit_cf != 0 && (o->mgrit_cf < 2 || o->mgrit_cf > 64)) { why = "mgrit_cf must be in [2, 64]"; return false; }
+  if (o->mgrit_iters < 0) { why = "mgrit_iters must be >= 0"; return false; }
+  if (o->mgrit_fcf != 0 && o->mgrit_fcf != 1) { why = "mgrit_fcf must be 0 or 1"; return false; }
   return true;
 }
 
@@ -98,6 +111,41 @@ namespace aao {
 int status_from_hip(aao_problem* h, hipError_t e, const char* what) {
   if (e == hipSuccess) return AAO_OK;
   return fail(h, AAO_HIP_ERROR, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+// FP64 table from the host to ws + off_d, and its FP32 copy at ws + off_f.
+hipError_t upload_pair(aao_problem* h, const double* host, size_t count, size_t off_d, size_t off_f) {
+  if (count == 0) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(h->ws + off_d, host, count * sizeof(double), hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return e;
+  return launch_copy_cast<float, double>(reinterpret_cast<float*>(h->ws + off_f),
+                                         reinterpret_cast<const double*>(h->ws + off_d), (int64_t)count, h->stream);
+}
+}  // namespace
+
+hipError_t upload_tables(aao_problem* h) {
+  const auto& P = h->plan;
+  hipError_t e = upload_pair(h, h->tri_host.data(), h->tri_host.size(), P.tri_d, P.tri_f);
+  if (e == hipSuccess) e = upload_pair(h, h->cinv_host.data(), h->cinv_host.size(), P.cinv_d, P.cinv_f);
+  if (e == hipSuccess) e = upload_pair(h, h->fd_host.data(), h->fd_host.size(), P.fd_d, P.fd_f);
+  if (e == hipSuccess) e = upload_pair(h, h->st9_host.data(), h->st9_host.size(), P.st9_d, P.st9_f);
+  if (e == hipSuccess && h->vark) {
+    // faces (2 dim N) followed by the nodal kappa (N)
+    const size_t nf = h->faces_host.size();
+    e = hipMemcpyAsync(h->ws + P.faces_d, h->faces_host.data(), nf * sizeof(double), hipMemcpyHostToDevice,
+                       h->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h->ws + P.faces_d + nf * sizeof(double), h->kappa.data(), h->N * sizeof(double),
+                         hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+      e = launch_copy_cast<float, double>(reinterpret_cast<float*>(h->ws + P.faces_f),
+                                          reinterpret_cast<const double*>(h->ws + P.faces_d),
+                                          (int64_t)(nf + h->N), h->stream);
+  }
+  if (e == hipSuccess)
+    e = launch_fill<unsigned>(reinterpret_cast<unsigned*>(h->ws + P.counters), 0u, h->nt + 2, h->stream);
+  return e;
 }
 }  // namespace aao
 
@@ -117,6 +165,11 @@ void aao_default_opts(aao_opts* o) {
   o->use_graph = 1;
   o->mg_tail_max = 0;
   o->coarse_max = 0;
+  o->inner_tol = 0.0;
+  o->schur = AAO_SCHUR_SWEEP;
+  o->mgrit_cf = 8;
+  o->mgrit_iters = 1;
+  o->mgrit_fcf = 0;
 }
 
 int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) {
@@ -134,6 +187,9 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
   if (o) opts = *o;
   std::string why;
   if (!valid_opts(&opts, why)) return fail(nullptr, AAO_INVALID_ARG, why);
+  if (opts.mgrit_cf == 0) opts.mgrit_cf = 8;
+  if (opts.mgrit_iters == 0) opts.mgrit_iters = 1;
+  if (opts.mgrit_iters > d->nt) return fail(nullptr, AAO_INVALID_ARG, "mgrit_iters must be <= nt");
 
   aao_problem* h = new (std::nothrow) aao_problem();
   if (!h) return fail(nullptr, AAO_INVALID_ARG, "out of host memory");
@@ -236,9 +292,13 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
   if (h->fd_n == 0) {
     const int lc = (int)h->lev_n.size() - 1;
     h->cinv_N = h->lev_N[lc];
-    for (int tr = 0; tr < 2; ++tr)
+    // sets 0, 1: shifts of P-tilde and its transpose; with MGRIT also 2, 3:
+    // those of the coarse propagator (time step mgrit_cf tau)
+    const int nsets = opts.schur == AAO_SCHUR_MGRIT ? 4 : 2;
+    for (int set = 0; set < nsets; ++set)
       for (int i = 0; i < d->s; ++i) {
-        const double a = h->tau * (tr ? h->LT : h->tab.L)[i * d->s + i];
+        const int tr = set & 1;
+        const double a = (set >= 2 ? opts.mgrit_cf : 1) * h->tau * (tr ? h->LT : h->tab.L)[i * d->s + i];
         std::vector<double> inv;
         if (!aao::coarse_inverse(d->dim, h->lev_n[lc], tri[lc], a, lc == 0, h->ih2,
                                  h->vark ? h->faces_host.data() : nullptr,
@@ -273,55 +333,12 @@ int aao_set_workspace(aao_problem* h, void* dev_ptr, size_t bytes) {
       return aao::status_from_hip(h, e, "pinned host scalars");
     }
   }
+  // captured P-tilde graphs hold the previous workspace's addresses
+  if (h->ws != static_cast<char*>(dev_ptr)) aao::release_graphs(h);
   h->ws = static_cast<char*>(dev_ptr);
   h->ws_bytes = bytes;
   h->lds_budget = aao::mg_configure_lds();
-  if (!h->tri_host.empty()) {
-    e = hipMemcpyAsync(h->ws + h->plan.tri_d, h->tri_host.data(), h->tri_host.size() * sizeof(double),
-                       hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess)
-      e = aao::launch_copy_cast<float, double>(reinterpret_cast<float*>(h->ws + h->plan.tri_f),
-                                               reinterpret_cast<const double*>(h->ws + h->plan.tri_d),
-                                               (int64_t)h->tri_host.size(), h->stream);
-  }
-  if (e == hipSuccess && !h->cinv_host.empty()) {
-    e = hipMemcpyAsync(h->ws + h->plan.cinv_d, h->cinv_host.data(), h->cinv_host.size() * sizeof(double),
-                       hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess)
-      e = aao::launch_copy_cast<float, double>(reinterpret_cast<float*>(h->ws + h->plan.cinv_f),
-                                               reinterpret_cast<const double*>(h->ws + h->plan.cinv_d),
-                                               (int64_t)h->cinv_host.size(), h->stream);
-  }
-  if (e == hipSuccess && !h->fd_host.empty()) {
-    e = hipMemcpyAsync(h->ws + h->plan.fd_d, h->fd_host.data(), h->fd_host.size() * sizeof(double),
-                       hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess)
-      e = aao::launch_copy_cast<float, double>(reinterpret_cast<float*>(h->ws + h->plan.fd_f),
-                                               reinterpret_cast<const double*>(h->ws + h->plan.fd_d),
-                                               (int64_t)h->fd_host.size(), h->stream);
-  }
-  if (e == hipSuccess && !h->st9_host.empty()) {
-    e = hipMemcpyAsync(h->ws + h->plan.st9_d, h->st9_host.data(), h->st9_host.size() * sizeof(double),
-                       hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess)
-      e = aao::launch_copy_cast<float, double>(reinterpret_cast<float*>(h->ws + h->plan.st9_f),
-                                               reinterpret_cast<const double*>(h->ws + h->plan.st9_d),
-                                               (int64_t)h->st9_host.size(), h->stream);
-  }
-  if (e == hipSuccess && h->vark) {
-    const size_t nf = h->faces_host.size();
-    e = hipMemcpyAsync(h->ws + h->plan.faces_d, h->faces_host.data(), nf * sizeof(double),
-                       hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(h->ws + h->plan.faces_d + nf * sizeof(double), h->kappa.data(),
-                         h->N * sizeof(double), hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess)
-      e = aao::launch_copy_cast<float, double>(reinterpret_cast<float*>(h->ws + h->plan.faces_f),
-                                               reinterpret_cast<const double*>(h->ws + h->plan.faces_d),
-                                               (int64_t)(nf + h->N), h->stream);
-  }
-  if (e == hipSuccess)
-    e = aao::launch_fill<unsigned>(reinterpret_cast<unsigned*>(h->ws + h->plan.counters), 0u, h->nt + 2, h->stream);
+  e = aao::upload_tables(h);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     h->ws = nullptr;
@@ -339,6 +356,8 @@ int aao_set_stream(aao_problem* h, void* stream) {
 int aao_destroy(aao_problem* h) {
   if (!h) return AAO_INVALID_ARG;
   aao::release_graphs(h);
+  for (hipEvent_t& ev : h->phase_ev)
+    if (ev) (void)hipEventDestroy(ev);
   if (h->hpin) (void)hipHostFree(h->hpin);
   delete h;
   return AAO_OK;

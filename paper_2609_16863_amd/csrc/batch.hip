@@ -119,7 +119,8 @@ extern "C" {
 
 int aao_create_batch(const aao_desc* descs, int count, const aao_opts* opts, int streams, aao_batch** out) {
   if (!descs || !out || count < 1) return bfail(nullptr, AAO_INVALID_ARG, "descs, out and count >= 1 required");
-  if (streams < 1 || streams > 16) return bfail(nullptr, AAO_INVALID_ARG, "streams must be in [1, 16]");
+  if (streams < 1 || streams > AAO_BATCH_MAX_STREAMS)
+    return bfail(nullptr, AAO_INVALID_ARG, "streams must be in [1, 4]");
   *out = nullptr;
   aao_batch* b = new (std::nothrow) aao_batch();
   if (!b) return bfail(nullptr, AAO_INVALID_ARG, "out of host memory");

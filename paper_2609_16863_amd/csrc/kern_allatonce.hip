@@ -56,10 +56,7 @@ __global__ __launch_bounds__(TPB) void k_apply_A(const TX* __restrict__ x, doubl
 // value is read from HBM once per launch.  W = 2 uses 16-byte loads and
 // stores (n even).  The x neighbours are taken from the adjacent lanes of the
 // wave; only lanes 0 and 63 load the value beyond their wave.
-#ifndef AAO_APPLY_ROWS
-#define AAO_APPLY_ROWS 64
-#endif
-constexpr int ROWS = AAO_APPLY_ROWS;
+constexpr int ROWS = 64;
 
 template <int W, class TX>
 __device__ __forceinline__ void ldw(const TX* p, double* out) {
@@ -448,9 +445,6 @@ Faces<double> face_ptrs(const aao_problem* h) {
 // The two-column 2D kernels need even n and 16-byte aligned x and y rows.
 template <class TX>
 static bool two_columns(int n, const TX* x, const double* y) {
-#ifdef AAO_APPLY_ONE_COLUMN
-  return false;
-#endif
   return n % 2 == 0 && reinterpret_cast<uintptr_t>(x) % (2 * sizeof(TX)) == 0 &&
          reinterpret_cast<uintptr_t>(y) % 16 == 0;
 }

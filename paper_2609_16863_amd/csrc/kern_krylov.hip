@@ -25,8 +25,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 using S = InnerSlots;
 
 // Start: beta = ||r||, g = beta e1, 1/beta for the first basis vector.
-__device__ void gmres_start(double* q, double ww) {
+__device__ void gmres_start(double* q, double ww, unsigned* counters) {
   const bool ok = ww > 0.0 && isfinite(ww);
+  if (counters) atomicAdd(&counters[1], 1u);
   const double nb = ok ? sqrt(ww) : 0.0;
   q[S::BETA] = nb;
   q[S::ACTIVE] = ok ? 1.0 : 0.0;
@@ -40,12 +41,18 @@ __device__ void gmres_start(double* q, double ww) {
 // h = h1 + h2, h_{j+1,j} = sqrt(<w,w> - |h2|^2); apply the previous
 // rotations, form the new one, update g, and the scale of the next basis
 // vector (0 once the instance has stopped).  qs: a copy of the slots below
-// InnerSlots::Y (in LDS) for the reads; results go to q.
-__device__ void gmres_givens(double* q, const double* qs, int j, const double* h2, double ww) {
+// InnerSlots::Y (in LDS) for the reads; results go to q.  An instance stops
+// when the new direction is lost: h_{j+1,j} = 0, or <w,w> - |h2|^2 within
+// 1e-12 <w,w> of cancelling (then fewer than ~6 digits of h_{j+1,j} would
+// be left, and the next basis vector would be scaled by a wrong 1/h_{j+1,j}),
+// or its residual estimate |g_{j+1}| has reached rtol * beta.
+__device__ void gmres_givens(double* q, const double* qs, int j, const double* h2, double ww, double rtol,
+                             unsigned* counters) {
   if (qs[S::ACTIVE] == 0.0) {
     q[S::INV] = 0.0;
     return;
   }
+  if (counters) atomicAdd(&counters[0], 1u);
   double col[KMAX + 1];
   double h2sq = 0.0;
   for (int i = 0; i <= j; ++i) {
@@ -54,7 +61,7 @@ __device__ void gmres_givens(double* q, const double* qs, int j, const double* h
     h2sq += h2[i] * h2[i];
   }
   const double nrm2 = ww - h2sq;
-  const double hn = nrm2 > 0.0 ? sqrt(nrm2) : 0.0;
+  const double hn = nrm2 > 1e-12 * ww ? sqrt(nrm2) : 0.0;
   col[j + 1] = hn;
   for (int i = 0; i < j; ++i) {
     const double c = qs[S::CS + i], s = qs[S::SN + i];
@@ -77,7 +84,7 @@ __device__ void gmres_givens(double* q, const double* qs, int j, const double* h
   q[S::G + j] = c * gj;
   q[S::G + j + 1] = -s * gj;
   q[S::M] = (double)(j + 1);
-  if (!(hn > 0.0)) {                       // exact breakdown: solution in the space
+  if (!(hn > 0.0) || fabs(s * gj) <= rtol * qs[S::BETA]) {   // breakdown, or converged
     q[S::ACTIVE] = 0.0;
     q[S::INV] = 0.0;
   } else {
@@ -201,8 +208,8 @@ __global__ __launch_bounds__(TPB) void k_gs_finish(GSArgs a) {
   }
   __syncthreads();
   if (tid == 0) {
-    if (a.post == GS_POST_INIT) gmres_start(q, fin[DOTS_PER_PASS]);
-    else if (a.post == GS_POST_GIVENS) gmres_givens(q, qs, a.j, fin, fin[DOTS_PER_PASS]);
+    if (a.post == GS_POST_INIT) gmres_start(q, fin[DOTS_PER_PASS], a.counters);
+    else if (a.post == GS_POST_GIVENS) gmres_givens(q, qs, a.j, fin, fin[DOTS_PER_PASS], a.rtol, a.counters);
   }
 }
 
@@ -319,10 +326,10 @@ __global__ __launch_bounds__(TPB) void k_rana_rhs(const T* __restrict__ v, int64
   st<T, C>(out + inst * so + p, acc);
 }
 
-// z_{v,0} = r_{v,0};  z_{v,n+1} = r_{v,n+1} + tau sum_i b_i z_{V,n,i}
+// t_{v,0} = r_{v,0};  t_{v,n+1} = r_{v,n+1} + tau sum_i b_i z_{V,n,i}
 template <class T>
-__global__ __launch_bounds__(TPB) void k_schur_coupling(const double* __restrict__ r, T* __restrict__ z, int N,
-                                                        int nt, int ns, Tab tab) {
+__global__ __launch_bounds__(TPB) void k_schur_coupling(const double* __restrict__ r, const T* __restrict__ zV,
+                                                        T* __restrict__ t, int N, int ns, Tab tab) {
   using C = typename Acc<T>::type;
   const int p = blockIdx.x * TPB + threadIdx.x;
   if (p >= N) return;
@@ -330,63 +337,108 @@ __global__ __launch_bounds__(TPB) void k_schur_coupling(const double* __restrict
   const int64_t NN = N;
   double acc = r[(int64_t)step * NN + p];
   if (step > 0) {
-    const T* zV = z + ((int64_t)(nt + 1) + (int64_t)(step - 1) * ns) * NN;
-    for (int q = 0; q < ns; ++q) acc += tab.tau * tab.b[q] * ld<T, double>(zV + q * NN + p);
+    const T* zs = zV + (int64_t)(step - 1) * ns * NN;
+    for (int q = 0; q < ns; ++q) acc += tab.tau * tab.b[q] * ld<T, double>(zs + q * NN + p);
   }
-  st<T, C>(z + (int64_t)step * NN + p, (C)acc);
+  st<T, C>(t + (int64_t)step * NN + p, (C)acc);
 }
 
-// out_i = K zv for every stage i (right-hand side e (x) K z of X-tilde)
+// S-tilde steps on B instances b (blockIdx.y) at once.  Instance b reads
+// its block at base + b * stride for every operand; strides may be negative
+// (the transposed sweep walks backwards in time).
+
+// out_{b,i} = K zin_b for every stage i (right-hand side (e (x) K) z of X-tilde)
 template <int DIM, bool VK, class T>
-__global__ __launch_bounds__(TPB) void k_schur_kz(const T* __restrict__ zv, T* __restrict__ out, int n, int N,
-                                                  int ns, typename Acc<T>::type ih2,
+__global__ __launch_bounds__(TPB) void k_schur_kz(const T* __restrict__ zin, int64_t szin, T* __restrict__ out,
+                                                  int64_t sout, int n, int N, int ns, typename Acc<T>::type ih2,
                                                   Faces<typename Acc<T>::type> fc) {
   using C = typename Acc<T>::type;
   const int p = blockIdx.x * TPB + threadIdx.x;
   if (p >= N) return;
+  const int64_t b = blockIdx.y;
   int i, j, k;
   node_coords<DIM>(p, n, i, j, k);
-  const C kz = ih2 * stencil_K<DIM, VK, T, C>(zv, p, i, j, k, n, N, fc);
-  for (int q = 0; q < ns; ++q) st<T, C>(out + (int64_t)q * N + p, kz);
+  const C kz = ih2 * stencil_K<DIM, VK, T, C>(zin + b * szin, p, i, j, k, n, N, fc);
+  T* o = out + b * sout;
+  for (int q = 0; q < ns; ++q) st<T, C>(o + (int64_t)q * N + p, kz);
 }
 
-// znext = tnext + zcur - tau sum_i b_i y_i
+// out_b = t_b + Phi(zin_b) = t_b + zin_b - tau sum_i b_i y_{b,i}   (y = Theta-tilde^{-1} rhs)
+// out may alias t or zin (element-wise).
+template <class T, class TT>
+__global__ __launch_bounds__(TPB) void k_phi_update(const TT* t, int64_t stt, const T* zin, int64_t szin,
+                                                    const T* __restrict__ y, int64_t sy, T* out, int64_t sout, int N,
+                                                    int ns, Tab tab) {
+  using C = typename Acc<T>::type;
+  const int p = blockIdx.x * TPB + threadIdx.x;
+  if (p >= N) return;
+  const int64_t b = blockIdx.y;
+  const T* yb = y + b * sy;
+  C acc = ld<TT, C>(t + b * stt + p) + ld<T, C>(zin + b * szin + p);
+  for (int q = 0; q < ns; ++q) acc -= (C)(tab.tau * tab.b[q]) * ld<T, C>(yb + (int64_t)q * N + p);
+  st<T, C>(out + b * sout + p, acc);
+}
+
+// out_{b,i} = b_i zin_b   (right-hand side (b (x) I) z of the transposed X-tilde)
 template <class T>
-__global__ __launch_bounds__(TPB) void k_schur_update(const T* tnext, const T* __restrict__ zcur,
-                                                      const T* __restrict__ y, T* znext, int N, int ns, Tab tab) {
+__global__ __launch_bounds__(TPB) void k_schurT_bw(const T* __restrict__ zin, int64_t szin, T* __restrict__ out,
+                                                   int64_t sout, int N, int ns, Tab tab) {
   using C = typename Acc<T>::type;
   const int p = blockIdx.x * TPB + threadIdx.x;
   if (p >= N) return;
-  C acc = ld<T, C>(tnext + p) + ld<T, C>(zcur + p);
-  for (int q = 0; q < ns; ++q) acc -= (C)(tab.tau * tab.b[q]) * ld<T, C>(y + (int64_t)q * N + p);
-  st<T, C>(znext + p, acc);
+  const int64_t b = blockIdx.y;
+  const C v = ld<T, C>(zin + b * szin + p);
+  T* o = out + b * sout;
+  for (int q = 0; q < ns; ++q) st<T, C>(o + (int64_t)q * N + p, (C)tab.b[q] * v);
 }
 
-// out_i = b_i w   (right-hand side (b (x) I) w of the transposed X-tilde)
-template <class T>
-__global__ __launch_bounds__(TPB) void k_schurT_bw(const T* __restrict__ w, T* __restrict__ out, int N, int ns,
-                                                   Tab tab) {
+// out_b = t_b + Phi^T(zin_b) = t_b + zin_b - tau K sum_i y_{b,i}
+template <int DIM, bool VK, class T, class TT>
+__global__ __launch_bounds__(TPB) void k_phiT_update(const TT* t, int64_t stt, const T* zin, int64_t szin,
+                                                     const T* __restrict__ y, int64_t sy, T* out, int64_t sout, int n,
+                                                     int N, int ns, typename Acc<T>::type ih2, double tau,
+                                                     Faces<typename Acc<T>::type> fc) {
   using C = typename Acc<T>::type;
   const int p = blockIdx.x * TPB + threadIdx.x;
   if (p >= N) return;
-  const C v = ld<T, C>(w + p);
-  for (int q = 0; q < ns; ++q) st<T, C>(out + (int64_t)q * N + p, (C)tab.b[q] * v);
-}
-
-// zcur = rprev + znext - tau K sum_i y_i
-template <int DIM, bool VK, class T>
-__global__ __launch_bounds__(TPB) void k_schurT_update(const double* __restrict__ rprev, const T* __restrict__ znext,
-                                                       const T* __restrict__ y, T* __restrict__ zcur, int n, int N,
-                                                       int ns, typename Acc<T>::type ih2, double tau,
-                                                       Faces<typename Acc<T>::type> fc) {
-  using C = typename Acc<T>::type;
-  const int p = blockIdx.x * TPB + threadIdx.x;
-  if (p >= N) return;
+  const int64_t b = blockIdx.y;
   int i, j, k;
   node_coords<DIM>(p, n, i, j, k);
+  const T* yb = y + b * sy;
   C ky = C(0);
-  for (int q = 0; q < ns; ++q) ky += stencil_K<DIM, VK, T, C>(y + (int64_t)q * N, p, i, j, k, n, N, fc);
-  st<T, C>(zcur + p, (C)rprev[p] + ld<T, C>(znext + p) - (C)tau * ih2 * ky);
+  for (int q = 0; q < ns; ++q) ky += stencil_K<DIM, VK, T, C>(yb + (int64_t)q * N, p, i, j, k, n, N, fc);
+  st<T, C>(out + b * sout + p, ld<TT, C>(t + b * stt + p) + ld<T, C>(zin + b * szin + p) - (C)tau * ih2 * ky);
+}
+
+// MGRIT coarse-grid step at one C-point: znew = g + Phi_c(e_prev) (Phi_c = 0
+// when e_prev is null), e_out = znew - zC, zC = znew.  Phi_c is the step with
+// tau_c (forward: e - tau_c b^T y; transposed: e - tau_c K sum_i y_i).
+template <int DIM, bool VK, bool TR, class T>
+__global__ __launch_bounds__(TPB) void k_mgrit_coarse(const T* __restrict__ g, const T* __restrict__ eprev,
+                                                      const T* __restrict__ y, T* __restrict__ zC,
+                                                      T* __restrict__ eout, int n, int N, int ns,
+                                                      typename Acc<T>::type ih2, Tab tabc,
+                                                      Faces<typename Acc<T>::type> fc) {
+  using C = typename Acc<T>::type;
+  const int p = blockIdx.x * TPB + threadIdx.x;
+  if (p >= N) return;
+  C znew = ld<T, C>(g + p);
+  if (eprev) {
+    C ph = ld<T, C>(eprev + p);
+    if (TR) {
+      int i, j, k;
+      node_coords<DIM>(p, n, i, j, k);
+      C ky = C(0);
+      for (int q = 0; q < ns; ++q) ky += stencil_K<DIM, VK, T, C>(y + (int64_t)q * N, p, i, j, k, n, N, fc);
+      ph -= (C)tabc.tau * ih2 * ky;
+    } else {
+      for (int q = 0; q < ns; ++q) ph -= (C)(tabc.tau * tabc.b[q]) * ld<T, C>(y + (int64_t)q * N + p);
+    }
+    znew += ph;
+  }
+  const C zold = ld<T, C>(zC + p);
+  st<T, C>(eout + p, znew - zold);
+  st<T, C>(zC + p, znew);
 }
 
 // out_{n,i} = r_{V,n,i} + tau b_i z_{v,n+1}
@@ -515,57 +567,74 @@ hipError_t rana_rhs(const aao_problem* h, const double* Lc, int i, const T* v, i
 }
 
 template <class T>
-hipError_t schur_coupling(const aao_problem* h, const double* r, T* z, hipStream_t st) {
-  hipLaunchKernelGGL((k_schur_coupling<T>), pts_grid(h->N, h->nt + 1), dim3(TPB), 0, st, r, z, (int)h->N, h->nt,
-                     h->s, h->tab);
+hipError_t schur_coupling(const aao_problem* h, const double* r, const T* zV, T* t, hipStream_t st) {
+  hipLaunchKernelGGL((k_schur_coupling<T>), pts_grid(h->N, h->nt + 1), dim3(TPB), 0, st, r, zV, t, (int)h->N, h->s,
+                     h->tab);
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t schur_kz(const aao_problem* h, const T* zv, T* out, hipStream_t st) {
+hipError_t schur_kz(const aao_problem* h, const T* zin, int64_t szin, T* out, int64_t sout, int B, hipStream_t st) {
   using C = typename Acc<T>::type;
   const Faces<C> fc = faces_of<C>(h);
-  const dim3 g = pts_grid(h->N, 1);
+  const dim3 g = pts_grid(h->N, B);
   const int n = h->n, N = (int)h->N, ns = h->s;
   const C ih2 = (C)h->ih2;
-  if (h->dim == 2) {
-    if (h->vark) hipLaunchKernelGGL((k_schur_kz<2, true, T>), g, dim3(TPB), 0, st, zv, out, n, N, ns, ih2, fc);
-    else hipLaunchKernelGGL((k_schur_kz<2, false, T>), g, dim3(TPB), 0, st, zv, out, n, N, ns, ih2, fc);
-  } else {
-    if (h->vark) hipLaunchKernelGGL((k_schur_kz<3, true, T>), g, dim3(TPB), 0, st, zv, out, n, N, ns, ih2, fc);
-    else hipLaunchKernelGGL((k_schur_kz<3, false, T>), g, dim3(TPB), 0, st, zv, out, n, N, ns, ih2, fc);
-  }
+#define AAO_KZ(D, V) \
+  hipLaunchKernelGGL((k_schur_kz<D, V, T>), g, dim3(TPB), 0, st, zin, szin, out, sout, n, N, ns, ih2, fc)
+  if (h->dim == 2) { if (h->vark) AAO_KZ(2, true); else AAO_KZ(2, false); }
+  else { if (h->vark) AAO_KZ(3, true); else AAO_KZ(3, false); }
+#undef AAO_KZ
+  return hipGetLastError();
+}
+
+template <class T, class TT>
+hipError_t phi_update(const aao_problem* h, const Tab& tab, const TT* t, int64_t stt, const T* zin, int64_t szin,
+                      const T* y, int64_t sy, T* out, int64_t sout, int B, hipStream_t st) {
+  hipLaunchKernelGGL((k_phi_update<T, TT>), pts_grid(h->N, B), dim3(TPB), 0, st, t, stt, zin, szin, y, sy, out, sout,
+                     (int)h->N, h->s, tab);
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t schur_update(const aao_problem* h, const T* tnext, const T* zcur, const T* y, T* znext, hipStream_t st) {
-  hipLaunchKernelGGL((k_schur_update<T>), pts_grid(h->N, 1), dim3(TPB), 0, st, tnext, zcur, y, znext, (int)h->N,
-                     h->s, h->tab);
+hipError_t schurT_bw(const aao_problem* h, const T* zin, int64_t szin, T* out, int64_t sout, int B, hipStream_t st) {
+  hipLaunchKernelGGL((k_schurT_bw<T>), pts_grid(h->N, B), dim3(TPB), 0, st, zin, szin, out, sout, (int)h->N, h->s,
+                     h->tab);
   return hipGetLastError();
 }
 
-template <class T>
-hipError_t schurT_bw(const aao_problem* h, const T* zv, T* out, hipStream_t st) {
-  hipLaunchKernelGGL((k_schurT_bw<T>), pts_grid(h->N, 1), dim3(TPB), 0, st, zv, out, (int)h->N, h->s, h->tab);
-  return hipGetLastError();
-}
-
-template <class T>
-hipError_t schurT_update(const aao_problem* h, const double* rprev, const T* znext, const T* y, T* zcur,
-                         hipStream_t st) {
+template <class T, class TT>
+hipError_t phiT_update(const aao_problem* h, double tau, const TT* t, int64_t stt, const T* zin, int64_t szin,
+                       const T* y, int64_t sy, T* out, int64_t sout, int B, hipStream_t st) {
   using C = typename Acc<T>::type;
   const Faces<C> fc = faces_of<C>(h);
-  const dim3 g = pts_grid(h->N, 1);
+  const dim3 g = pts_grid(h->N, B);
   const int n = h->n, N = (int)h->N, ns = h->s;
   const C ih2 = (C)h->ih2;
-  if (h->dim == 2) {
-    if (h->vark) hipLaunchKernelGGL((k_schurT_update<2, true, T>), g, dim3(TPB), 0, st, rprev, znext, y, zcur, n, N, ns, ih2, h->tau, fc);
-    else hipLaunchKernelGGL((k_schurT_update<2, false, T>), g, dim3(TPB), 0, st, rprev, znext, y, zcur, n, N, ns, ih2, h->tau, fc);
-  } else {
-    if (h->vark) hipLaunchKernelGGL((k_schurT_update<3, true, T>), g, dim3(TPB), 0, st, rprev, znext, y, zcur, n, N, ns, ih2, h->tau, fc);
-    else hipLaunchKernelGGL((k_schurT_update<3, false, T>), g, dim3(TPB), 0, st, rprev, znext, y, zcur, n, N, ns, ih2, h->tau, fc);
-  }
+#define AAO_PT(D, V)                                                                                           \
+  hipLaunchKernelGGL((k_phiT_update<D, V, T, TT>), g, dim3(TPB), 0, st, t, stt, zin, szin, y, sy, out, sout, n, N, \
+                     ns, ih2, tau, fc)
+  if (h->dim == 2) { if (h->vark) AAO_PT(2, true); else AAO_PT(2, false); }
+  else { if (h->vark) AAO_PT(3, true); else AAO_PT(3, false); }
+#undef AAO_PT
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t mgrit_coarse(const aao_problem* h, const Tab& tabc, bool transpose, const T* g, const T* eprev,
+                        const T* y, T* zC, T* eout, hipStream_t st) {
+  using C = typename Acc<T>::type;
+  const Faces<C> fc = faces_of<C>(h);
+  const dim3 gr = pts_grid(h->N, 1);
+  const int n = h->n, N = (int)h->N, ns = h->s;
+  const C ih2 = (C)h->ih2;
+#define AAO_MC(D, V, TR) \
+  hipLaunchKernelGGL((k_mgrit_coarse<D, V, TR, T>), gr, dim3(TPB), 0, st, g, eprev, y, zC, eout, n, N, ns, ih2, tabc, fc)
+#define AAO_MC_T(D, V) do { if (transpose) AAO_MC(D, V, true); else AAO_MC(D, V, false); } while (0)
+  if (h->dim == 2) { if (h->vark) AAO_MC_T(2, true); else AAO_MC_T(2, false); }
+  else { if (h->vark) AAO_MC_T(3, true); else AAO_MC_T(3, false); }
+#undef AAO_MC_T
+#undef AAO_MC
   return hipGetLastError();
 }
 
@@ -587,15 +656,23 @@ hipError_t thetaT_rhs(const aao_problem* h, const double* r, const T* z, T* out,
                                      hipStream_t);                                                                 \
   template hipError_t rana_rhs<T>(const aao_problem*, const double*, int, const T*, int64_t, const T*, int64_t, T*, \
                                   int64_t, int, hipStream_t);                                                      \
-  template hipError_t schur_coupling<T>(const aao_problem*, const double*, T*, hipStream_t);                       \
-  template hipError_t schur_kz<T>(const aao_problem*, const T*, T*, hipStream_t);                                  \
-  template hipError_t schur_update<T>(const aao_problem*, const T*, const T*, const T*, T*, hipStream_t);          \
-  template hipError_t schurT_bw<T>(const aao_problem*, const T*, T*, hipStream_t);                                 \
-  template hipError_t schurT_update<T>(const aao_problem*, const double*, const T*, const T*, T*, hipStream_t);    \
+  template hipError_t schur_coupling<T>(const aao_problem*, const double*, const T*, T*, hipStream_t);             \
+  template hipError_t schur_kz<T>(const aao_problem*, const T*, int64_t, T*, int64_t, int, hipStream_t);           \
+  template hipError_t phi_update<T, T>(const aao_problem*, const Tab&, const T*, int64_t, const T*, int64_t,       \
+                                       const T*, int64_t, T*, int64_t, int, hipStream_t);                         \
+  template hipError_t schurT_bw<T>(const aao_problem*, const T*, int64_t, T*, int64_t, int, hipStream_t);          \
+  template hipError_t phiT_update<T, T>(const aao_problem*, double, const T*, int64_t, const T*, int64_t,          \
+                                        const T*, int64_t, T*, int64_t, int, hipStream_t);                        \
+  template hipError_t mgrit_coarse<T>(const aao_problem*, const Tab&, bool, const T*, const T*, const T*, T*, T*,  \
+                                      hipStream_t);                                                               \
   template hipError_t thetaT_rhs<T>(const aao_problem*, const double*, const T*, T*, hipStream_t);
 
 AAO_INST_T(double)
 AAO_INST_T(float)
+template hipError_t phi_update<float, double>(const aao_problem*, const Tab&, const double*, int64_t, const float*,
+                                              int64_t, const float*, int64_t, float*, int64_t, int, hipStream_t);
+template hipError_t phiT_update<float, double>(const aao_problem*, double, const double*, int64_t, const float*,
+                                               int64_t, const float*, int64_t, float*, int64_t, int, hipStream_t);
 template hipError_t gs_pass<double, float>(double*, const float*, const GSArgs&, int, hipStream_t);
 template hipError_t basis_update<double, float, float>(const double*, int64_t, const float*, int64_t, int64_t, int,
                                                        float*, int64_t, const double*, int64_t, int, int, double,

@@ -1557,10 +1557,10 @@ inline dim3 grid2(int64_t N, int B) { return dim3((unsigned)((N + TPB - 1) / TPB
 // coarse levels whose three LDS vectors and factor copies fit the device's
 // LDS per workgroup (at most 128 KiB).
 template <class TI, class TM>
-Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L)
+Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L, int cinv_set)
     : h_(h), st_(st), levels_((int)h->lev_n.size()) {
   for (int i = 0; i < h->s; ++i) a_[i] = h->tau * L[i * h->s + i];
-  cinv_set_ = (L == h->LT) ? 1 : 0;
+  cinv_set_ = cinv_set >= 0 ? cinv_set : ((L == h->LT) ? 1 : 0);
   if (h->dim == 3) {
     // The 3D instantiation of the LDS tail faulted on gfx950 (aperture
     // violation) for reasons not yet established; 3D runs every level with

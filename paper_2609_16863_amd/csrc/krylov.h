@@ -36,9 +36,10 @@ struct GSArgs {
   int64_t sstride;
   int ca, od, os;     // coefficient / dot / self offsets in the slots
   double* partial;    // nblk * (DOTS_PER_PASS + 1) doubles per instance
-  unsigned* counters; // one zero-initialised ticket per instance
+  unsigned* counters; // [0]: inner GMRES iterations done, [1]: inner solves begun (or null)
   int nblk;
   int post, j;
+  double rtol;        // GS_POST_GIVENS: stop an instance once |g_{j+1}| <= rtol * beta (0: never)
 };
 
 // Number of workgroups per segment for the segmented reductions.
@@ -69,21 +70,34 @@ template <class T>
 hipError_t rana_rhs(const aao_problem* h, const double* Lc, int i, const T* v, int64_t sv, const T* z,
                     int64_t sz, T* out, int64_t so, int B, hipStream_t st);
 
-// S-tilde sweep pieces.
+// S-tilde pieces (eq. (3.3)).  t = r_v - Psi1 z_V for every step (nt + 1
+// blocks of N; zV: the nt stage blocks of s N).
 template <class T>
-hipError_t schur_coupling(const aao_problem* h, const double* r, T* z, hipStream_t st);
-template <class T>
-hipError_t schur_kz(const aao_problem* h, const T* zv, T* out, hipStream_t st);
-template <class T>
-hipError_t schur_update(const aao_problem* h, const T* tnext, const T* zcur, const T* y, T* znext,
-                        hipStream_t st);
+hipError_t schur_coupling(const aao_problem* h, const double* r, const T* zV, T* t, hipStream_t st);
 
-// Transposed-preconditioner pieces.
+// Batched S-tilde steps: instance b reads base + b * stride of every operand
+// (strides in elements, may be negative).
+// out_b = (e (x) K) zin_b  (s blocks of N per instance)
 template <class T>
-hipError_t schurT_bw(const aao_problem* h, const T* zv, T* out, hipStream_t st);
+hipError_t schur_kz(const aao_problem* h, const T* zin, int64_t szin, T* out, int64_t sout, int B, hipStream_t st);
+// out_b = t_b + zin_b - tab.tau sum_i b_i y_{b,i}
+template <class T, class TT>
+hipError_t phi_update(const aao_problem* h, const Tab& tab, const TT* t, int64_t stt, const T* zin, int64_t szin,
+                      const T* y, int64_t sy, T* out, int64_t sout, int B, hipStream_t st);
+// out_b = (b (x) I) zin_b
 template <class T>
-hipError_t schurT_update(const aao_problem* h, const double* rprev, const T* znext, const T* y, T* zcur,
-                         hipStream_t st);
+hipError_t schurT_bw(const aao_problem* h, const T* zin, int64_t szin, T* out, int64_t sout, int B, hipStream_t st);
+// out_b = t_b + zin_b - tau K sum_i y_{b,i}
+template <class T, class TT>
+hipError_t phiT_update(const aao_problem* h, double tau, const TT* t, int64_t stt, const T* zin, int64_t szin,
+                       const T* y, int64_t sy, T* out, int64_t sout, int B, hipStream_t st);
+// MGRIT coarse step at one C-point: znew = g + Phi_c(eprev) (eprev may be
+// null: Phi_c(0) = 0), eout = znew - zC, zC = znew.
+template <class T>
+hipError_t mgrit_coarse(const aao_problem* h, const Tab& tabc, bool transpose, const T* g, const T* eprev,
+                        const T* y, T* zC, T* eout, hipStream_t st);
+
+// Transposed-preconditioner right-hand side of Theta-tilde^T.
 template <class T>
 hipError_t thetaT_rhs(const aao_problem* h, const double* r, const T* z, T* out, hipStream_t st);
 

@@ -14,8 +14,11 @@ class Multigrid {
  public:
   using C = typename Acc<TI>::type;
 
-  // L: lower Crout factor (s x s, row-major) whose diagonal gives the shifts.
-  Multigrid(aao_problem* h, hipStream_t st, const double* L);
+  // L: lower Crout factor (s x s, row-major) whose diagonal gives the shifts
+  // tau L_ii.  cinv_set: which precomputed coarsest-level inverses match
+  // those shifts (0: P-tilde, 1: its transpose, 2 / 3: the same for the
+  // MGRIT coarse step); -1 picks 0 or 1 from L.
+  Multigrid(aao_problem* h, hipStream_t st, const double* L, int cinv_set = -1);
 
   // Rana's coupling for stage i = nz > 0: the block right-hand side is
   // rhs - tau sum_{l < i} Lc[i][l] K z_l (z_l at z + l * zstride, instance
@@ -66,7 +69,7 @@ class Multigrid {
   int fast_nls_;    // > 0: the tail runs k_tail_fast with this many smoothing levels
   int fast_npt_;    // its nodes per thread on the first tail level (1 or 4)
   size_t fast_bytes_;
-  int cinv_set_;    // 0: shifts of P-tilde, 1: of its transpose
+  int cinv_set_;    // coarsest-level inverse set (see the constructor)
 };
 
 }  // namespace aao

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <memory>
 #include <vector>
 
 #include "aao_internal.h"
@@ -41,16 +42,39 @@ using S = InnerSlots;
 template <class TI, class TM>
 class Precond {
  public:
+  // One S-tilde step size: the multigrid of Rana's diagonal blocks, the
+  // tableau (transposed for P-tilde^T) with its step tau, and the Crout
+  // factor the coupling uses.  `fine` steps tau; the MGRIT coarse stepper
+  // steps mgrit_cf tau (its factor and shifts scaled by mgrit_cf).
+  struct Stepper {
+    Multigrid<TI, TM> mg;
+    Tab tab;
+    double Lc[SMAX * SMAX];
+    Stepper(aao_problem* h, bool transpose, double scale, int cinv_set)
+        : mg(h, h->stream, scaled(h, transpose, scale).data(), cinv_set) {
+      const std::vector<double> L = scaled(h, transpose, scale);
+      for (int q = 0; q < SMAX * SMAX; ++q) Lc[q] = q < (int)L.size() ? L[q] : 0.0;
+      tab = h->tab;
+      tab.tau = h->tau * scale;
+      if (transpose) {
+        const int s = h->s;
+        for (int i = 0; i < s; ++i)
+          for (int j = 0; j < s; ++j) tab.A[i * s + j] = h->tab.A[j * s + i];
+      }
+    }
+    static std::vector<double> scaled(const aao_problem* h, bool transpose, double scale) {
+      const double* L = transpose ? h->LT : h->tab.L;
+      std::vector<double> out(L, L + h->s * h->s);
+      for (double& v : out) v *= scale;
+      return out;
+    }
+  };
+
   Precond(aao_problem* h, bool transpose, int k, int cycles)
       : h_(h), st_(h->stream), transpose_(transpose), k_(k), cycles_(cycles),
-        mg_(h, h->stream, transpose ? h->LT : h->tab.L) {
-    tab_ = h->tab;
-    if (transpose) {
-      const int s = h->s;
-      for (int i = 0; i < s; ++i)
-        for (int j = 0; j < s; ++j) tab_.A[i * s + j] = h->tab.A[j * s + i];
-    }
-    Lc_ = transpose ? h->LT : h->tab.L;
+        fine_(h, transpose, 1.0, transpose ? 1 : 0) {
+    if (h->opts.schur == AAO_SCHUR_MGRIT)
+      coarse_.reset(new Stepper(h, transpose, (double)h->opts.mgrit_cf, transpose ? 3 : 2));
     char* ws = h->ws;
     inV_ = reinterpret_cast<TI*>(ws + h->plan.inV);
     inZ_ = reinterpret_cast<TI*>(ws + h->plan.inZ);
@@ -59,6 +83,9 @@ class Precond {
     rana_ = reinterpret_cast<TI*>(ws + h->plan.rana);
     srhs_ = reinterpret_cast<TI*>(ws + h->plan.schurRhs);
     sy_ = reinterpret_cast<TI*>(ws + h->plan.schurY);
+    mt_ = reinterpret_cast<TI*>(ws + h->plan.mgritT);
+    mg_g_ = reinterpret_cast<TI*>(ws + h->plan.mgritG);
+    mg_e_ = reinterpret_cast<TI*>(ws + h->plan.mgritE);
     partial_ = reinterpret_cast<double*>(ws + h->plan.partial);
     slots_ = reinterpret_cast<double*>(ws + h->plan.dscal);
     counters_ = reinterpret_cast<unsigned*>(ws + h->plan.counters);
@@ -72,12 +99,14 @@ class Precond {
     a.partial = partial_;
     a.counters = counters_;
     a.nblk = seg_blocks(L, B);
+    a.rtol = h_->opts.inner_tol;
     return a;
   }
 
-  // out_b = Theta-tilde^{-1} rhs_b for B instances (rhs, out: s*N each).
+  // out_b = Theta-tilde^{-1} rhs_b for B instances (rhs, out: s*N each),
+  // with the step size of `sp`.
   template <class TR>
-  hipError_t inner(const TR* rhs, int64_t srhs, TI* out, int64_t sout, int B) {
+  hipError_t inner(Stepper& sp, const TR* rhs, int64_t srhs, TI* out, int64_t sout, int B) {
     const int64_t N = h_->N, sN = (int64_t)h_->s * N, UV = h_->UV;
     // beta = ||rhs||, first basis vector rhs / beta
     GSArgs a0 = gs_args(sN, B);
@@ -98,13 +127,13 @@ class Precond {
         cpl.sz = sN;
         cpl.zstride = N;
         cpl.nz = i;
-        cpl.Lc = Lc_;
+        cpl.Lc = sp.Lc;
         cpl.out = rana_;
         cpl.so = N;
-        TRY(mg_.solve(i, BVec<TI>{Zj + (int64_t)i * N, sN}, BVec<const TI>{Vj + (int64_t)i * N, sN}, B, cycles_,
-                      i > 0 ? &cpl : nullptr));
+        TRY(sp.mg.solve(i, BVec<TI>{Zj + (int64_t)i * N, sN}, BVec<const TI>{Vj + (int64_t)i * N, sN}, B,
+                        cycles_, i > 0 ? &cpl : nullptr));
       }
-      TRY(theta_apply<TI>(h_, tab_, Zj, sN, inW_, sN, B, st_));
+      TRY(theta_apply<TI>(h_, sp.tab, Zj, sN, inW_, sN, B, st_));
       // classical Gram-Schmidt, twice: h1 = V^T w; w -= V h1, h2 = V^T w,
       // <w,w> and the Givens update in the second pass' finishing workgroup
       const int nd = j + 1;
@@ -133,33 +162,129 @@ class Precond {
     return hipSuccess;
   }
 
-  // z (TI, U values) = P-tilde^{-1} r (FP64) or its transpose.
-  hipError_t apply(const double* r, TI* z) {
+  // out_b = t_b + Phi(zin_b) for B instances, Phi the S-tilde step of `sp`:
+  // forward  Phi(z) = z - tau (b^T (x) I) Theta-tilde^{-1} (e (x) K) z,
+  // transposed Phi^T(z) = z - tau K sum_i [Theta-tilde^{-T} (b (x) z)]_i.
+  // Strides (elements) may be negative; t is TI or FP64.
+  template <class TT>
+  hipError_t phi_step(Stepper& sp, const TT* t, int64_t stt, const TI* zin, int64_t szin, TI* out, int64_t sout,
+                      int B) {
+    const int64_t sN = (int64_t)h_->s * h_->N;
+    if (!transpose_) {
+      TRY(schur_kz<TI>(h_, zin, szin, srhs_, sN, B, st_));
+      TRY(inner<TI>(sp, srhs_, sN, sy_, sN, B));
+      return phi_update<TI, TT>(h_, sp.tab, t, stt, zin, szin, sy_, sN, out, sout, B, st_);
+    }
+    TRY(schurT_bw<TI>(h_, zin, szin, srhs_, sN, B, st_));
+    TRY(inner<TI>(sp, srhs_, sN, sy_, sN, B));
+    return phiT_update<TI, TT>(h_, sp.tab.tau, t, stt, zin, szin, sy_, sN, out, sout, B, st_);
+  }
+
+  // z_m, m = 0..nt, of the recurrence z_0 = t_0, z_{m+1} = t_{m+1} + Phi(z_m)
+  // with block m of z at z0 + m dz and of t at t0 + m dt (dz, dt = +-N):
+  // forward substitution, or two-level MGRIT with C-points every c steps
+  // (K = ceil(nt / c) intervals; initial guess t_0 at the first C-point and
+  // 0 at the others).  One MGRIT iteration: F-relaxation of every interval
+  // at once (step j of all intervals is one batched S-tilde step), FCF's
+  // C-relaxation when asked, the fine propagation g_k into every C-point,
+  // then the sequential coarse sweep z_kc <- g_k + Phi_c(e_{k-1}) with
+  // e_k = (new - old) z_kc and Phi_c the step of size c tau.  A final
+  // F-relaxation fills the F-points.
+  template <class TT>
+  hipError_t schur_solve(const TT* t0, int64_t dt, TI* z0, int64_t dz) {
+    const int nt = h_->nt;
+    const int64_t N = h_->N;
+    const bool in_place = (const void*)t0 == (const void*)z0;   // t already sits in z
+    if (!coarse_) {
+      if (!in_place) TRY(launch_copy_cast<TI, TT>(z0, t0, N, st_));
+      for (int m = 0; m < nt; ++m)
+        TRY(phi_step<TT>(fine_, t0 + (m + 1) * dt, 0, z0 + m * dz, 0, z0 + (m + 1) * dz, 0, 1));
+      return hipSuccess;
+    }
+    const int c = h_->opts.mgrit_cf;
+    const int K = (nt + c - 1) / c;
+    const int64_t cz = (int64_t)c * dz, ct = (int64_t)c * dt;
+    // C-points: z_{kc}, k = 0..K-1, kept in place in z; initial guess t_0, 0, ...
+    if (!in_place) TRY(launch_copy_cast<TI, TT>(z0, t0, N, st_));
+    for (int k = 1; k < K; ++k) TRY(launch_fill<TI>(z0 + k * cz, TI(0), N, st_));
+    // F-relaxation: step j of every interval k < Kj at once
+    auto f_relax = [&](bool last) -> hipError_t {
+      for (int j = 1; j < c && j <= nt; ++j) {
+        const int Kj = std::min(K, (nt - j) / c + 1);   // intervals k with kc + j <= nt
+        TRY(phi_step<TT>(fine_, t0 + j * dt, ct, z0 + (j - 1) * dz, cz, z0 + j * dz, cz, Kj));
+      }
+      // a last interval of full length ends at nt, one step past the others
+      if (last && nt % c == 0) TRY(phi_step<TT>(fine_, t0 + nt * dt, 0, z0 + (nt - 1) * dz, 0, z0 + nt * dz, 0, 1));
+      return hipSuccess;
+    };
+    for (int it = 0; it < h_->opts.mgrit_iters && K > 1; ++it) {
+      TRY(f_relax(false));
+      if (h_->opts.mgrit_fcf) {
+        // C-relaxation: z_{kc} = t_{kc} + Phi(z_{kc-1}), k = 1..K-1, then F again
+        TRY(phi_step<TT>(fine_, t0 + ct, ct, z0 + (c - 1) * dz, cz, z0 + cz, cz, K - 1));
+        TRY(f_relax(false));
+      }
+      // g_k = t_{kc} + Phi(z_{kc-1}) for k = 1..K-1 (g block k at mg_g_ + k N)
+      TRY(phi_step<TT>(fine_, t0 + ct, ct, z0 + (c - 1) * dz, cz, mg_g_ + N, N, K - 1));
+      // coarse sweep: z_{kc} <- g_k + Phi_c(e_{k-1}), e_k = new - old
+      const int64_t sN = (int64_t)h_->s * N;
+      for (int k = 1; k < K; ++k) {
+        const TI* eprev = nullptr;
+        if (k >= 2) {
+          eprev = mg_e_ + (k - 1) * N;
+          if (!transpose_) TRY(schur_kz<TI>(h_, eprev, 0, srhs_, sN, 1, st_));
+          else TRY(schurT_bw<TI>(h_, eprev, 0, srhs_, sN, 1, st_));
+          TRY(inner<TI>(*coarse_, srhs_, sN, sy_, sN, 1));
+        }
+        TRY(mgrit_coarse<TI>(h_, coarse_->tab, transpose_, mg_g_ + k * N, eprev, sy_, z0 + k * cz, mg_e_ + k * N,
+                             st_));
+      }
+    }
+    return f_relax(true);
+  }
+
+  // z (TI, U values) = P-tilde^{-1} r (FP64) or its transpose, in two
+  // phases.  Forward: phase 1 = Theta-tilde on every step and the coupling
+  // t_v = r_v - Psi1 z_V, phase 2 = S-tilde^{-1} t_v.  Transposed: phase 1 =
+  // the S-tilde^T solve backwards in time, phase 2 = Theta-tilde^T on every
+  // step.
+  hipError_t apply(const double* r, TI* z, int phase) {
+    if (phase != 2) TRY(transpose_ ? schurT_phase(r, z) : theta_phase(r, z));
+    if (phase != 1) TRY(transpose_ ? thetaT_phase(r, z) : schur_phase(r, z));
+    return hipSuccess;
+  }
+
+  hipError_t theta_phase(const double* r, TI* z) {
     const int64_t N = h_->N, sN = (int64_t)h_->s * N;
     const int nt = h_->nt;
-    TI* zv = z;
     TI* zV = z + (int64_t)(nt + 1) * N;
     const double* rV = r + (int64_t)(nt + 1) * N;
-    if (!transpose_) {
-      TRY(inner<double>(rV, sN, zV, sN, nt));
-      TRY(schur_coupling<TI>(h_, r, z, st_));
-      for (int n = 0; n < nt; ++n) {
-        TRY(schur_kz<TI>(h_, zv + (int64_t)n * N, srhs_, st_));
-        TRY(inner<TI>(srhs_, sN, sy_, sN, 1));
-        TI* znext = zv + (int64_t)(n + 1) * N;
-        TRY(schur_update<TI>(h_, znext, zv + (int64_t)n * N, sy_, znext, st_));
-      }
-    } else {
-      TRY(launch_copy_cast<TI, double>(zv + (int64_t)nt * N, r + (int64_t)nt * N, N, st_));
-      for (int n = nt - 1; n >= 0; --n) {
-        TRY(schurT_bw<TI>(h_, zv + (int64_t)(n + 1) * N, srhs_, st_));
-        TRY(inner<TI>(srhs_, sN, sy_, sN, 1));
-        TRY(schurT_update<TI>(h_, r + (int64_t)n * N, zv + (int64_t)(n + 1) * N, sy_, zv + (int64_t)n * N, st_));
-      }
-      TRY(thetaT_rhs<TI>(h_, r, z, inX_, st_));
-      TRY(inner<TI>(inX_, sN, zV, sN, nt));
-    }
-    return hipSuccess;
+    TRY(inner<double>(fine_, rV, sN, zV, sN, nt));
+    // t_v goes to z_v (substitution, which then works in place) or to the
+    // separate t buffer (MGRIT)
+    return schur_coupling<TI>(h_, r, zV, coarse_ ? mt_ : z, st_);
+  }
+
+  hipError_t schur_phase(const double* r, TI* z) {
+    (void)r;
+    const TI* t = coarse_ ? mt_ : z;
+    return schur_solve<TI>(t, h_->N, z, h_->N);
+  }
+
+  // z_{v,nt} = r_{v,nt}, z_{v,n} = r_{v,n} + Phi^T(z_{v,n+1}): the forward
+  // recurrence in the reversed time index m = nt - n.
+  hipError_t schurT_phase(const double* r, TI* z) {
+    const int64_t N = h_->N;
+    const int nt = h_->nt;
+    return schur_solve<double>(r + (int64_t)nt * N, -N, z + (int64_t)nt * N, -N);
+  }
+
+  hipError_t thetaT_phase(const double* r, TI* z) {
+    const int64_t N = h_->N, sN = (int64_t)h_->s * N;
+    const int nt = h_->nt;
+    TI* zV = z + (int64_t)(nt + 1) * N;
+    TRY(thetaT_rhs<TI>(h_, r, z, inX_, st_));
+    return inner<TI>(fine_, inX_, sN, zV, sN, nt);
   }
 
  private:
@@ -167,27 +292,27 @@ class Precond {
   hipStream_t st_;
   bool transpose_;
   int k_, cycles_;
-  Multigrid<TI, TM> mg_;
-  Tab tab_;
-  const double* Lc_;
-  TI *inV_, *inZ_, *inW_, *inX_, *rana_, *srhs_, *sy_;
+  Stepper fine_;
+  std::unique_ptr<Stepper> coarse_;
+  TI *inV_, *inZ_, *inW_, *inX_, *rana_, *srhs_, *sy_, *mt_, *mg_g_, *mg_e_;
   double *partial_, *slots_;
   unsigned* counters_;
 };
 
 template <class TI, class TM>
-hipError_t apply_P_typed(aao_problem* h, const double* r, TI* z, int k, int cycles, bool transpose) {
+hipError_t apply_P_typed(aao_problem* h, const double* r, TI* z, int k, int cycles, bool transpose, int phase) {
   Precond<TI, TM> P(h, transpose, k, cycles);
-  return P.apply(r, z);
+  return P.apply(r, z, phase);
 }
 
 // Dispatch on the handle's precision; z is TI-typed storage (double for FP64).
-hipError_t apply_P_any(aao_problem* h, const double* r, void* z, int k, int cycles, bool transpose) {
+// phase: 1 or 2 for one phase of P-tilde, 0 for both.
+hipError_t apply_P_any(aao_problem* h, const double* r, void* z, int k, int cycles, bool transpose, int phase) {
   switch (h->opts.precision) {
-    case AAO_PREC_FP64: return apply_P_typed<double, double>(h, r, (double*)z, k, cycles, transpose);
-    case AAO_PREC_FP32: return apply_P_typed<float, float>(h, r, (float*)z, k, cycles, transpose);
-    case AAO_PREC_FP16: return apply_P_typed<float, __half>(h, r, (float*)z, k, cycles, transpose);
-    default: return apply_P_typed<float, __hip_bfloat16>(h, r, (float*)z, k, cycles, transpose);
+    case AAO_PREC_FP64: return apply_P_typed<double, double>(h, r, (double*)z, k, cycles, transpose, phase);
+    case AAO_PREC_FP32: return apply_P_typed<float, float>(h, r, (float*)z, k, cycles, transpose, phase);
+    case AAO_PREC_FP16: return apply_P_typed<float, __half>(h, r, (float*)z, k, cycles, transpose, phase);
+    default: return apply_P_typed<float, __hip_bfloat16>(h, r, (float*)z, k, cycles, transpose, phase);
   }
 }
 
@@ -199,16 +324,18 @@ hipError_t apply_mg_typed(aao_problem* h, bool transpose, int stage, int count, 
                   cycles);
 }
 
-// Apply P-tilde directly, or by replaying a HIP graph captured on the first
-// call for this (transpose, k, cycles).  The graph reads its input from and
-// writes its output to fixed workspace buffers; the copies in and out run on
-// the handle's stream around the replay.
-hipError_t precond_graph(aao_problem* h, int k, int cycles, bool transpose, aao_problem::GraphEntry** out) {
+// Apply P-tilde directly, or by replaying HIP graphs captured on the first
+// call for this (transpose, k, cycles): one graph per phase, so that the
+// phases can be timed apart.  The graphs read their input from and write
+// their output to fixed workspace buffers; the copies in and out run on the
+// handle's stream around the replays.
+hipError_t precond_graph(aao_problem* h, int k, int cycles, bool transpose, int phase,
+                         aao_problem::GraphEntry** out) {
   double* gin = reinterpret_cast<double*>(h->ws + h->plan.gIn);
   void* gout = h->ws + h->plan.gOut;
   aao_problem::GraphEntry* ent = nullptr;
   for (auto& g : h->graphs)
-    if (g.transpose == transpose && g.k == k && g.cycles == cycles) ent = &g;
+    if (g.transpose == transpose && g.k == k && g.cycles == cycles && g.phase == phase) ent = &g;
   if (!ent) {
     if (!h->capture_stream) TRY(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
     hipStream_t saved = h->stream;
@@ -218,7 +345,7 @@ hipError_t precond_graph(aao_problem* h, int k, int cycles, bool transpose, aao_
       h->stream = saved;
       return e;
     }
-    e = apply_P_any(h, gin, gout, k, cycles, transpose);
+    e = apply_P_any(h, gin, gout, k, cycles, transpose, phase);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(h->capture_stream, &graph);
     h->stream = saved;
@@ -232,22 +359,40 @@ hipError_t precond_graph(aao_problem* h, int k, int cycles, bool transpose, aao_
       (void)hipGraphDestroy(graph);
       return e;
     }
-    h->graphs.push_back(aao_problem::GraphEntry{transpose, k, cycles, graph, exec});
+    h->graphs.push_back(aao_problem::GraphEntry{transpose, k, cycles, phase, graph, exec});
     ent = &h->graphs.back();
   }
   *out = ent;
   return hipSuccess;
 }
 
-hipError_t precond_apply(aao_problem* h, const double* r, void* z, int k, int cycles, bool transpose) {
-  if (!h->opts.use_graph) return apply_P_any(h, r, z, k, cycles, transpose);
+// z = P-tilde^{-1} r.  With `timed`, the handle's phase events are recorded
+// before phase 1, between the phases and after phase 2.
+hipError_t precond_apply(aao_problem* h, const double* r, void* z, int k, int cycles, bool transpose, bool timed) {
+  hipEvent_t* ev = h->phase_ev;
+  if (!h->opts.use_graph || h->no_alloc) {
+    if (timed) TRY(hipEventRecord(ev[0], h->stream));
+    TRY(apply_P_any(h, r, z, k, cycles, transpose, 1));
+    if (timed) TRY(hipEventRecord(ev[1], h->stream));
+    TRY(apply_P_any(h, r, z, k, cycles, transpose, 2));
+    if (timed) TRY(hipEventRecord(ev[2], h->stream));
+    return hipSuccess;
+  }
   const int64_t U = h->U;
   double* gin = reinterpret_cast<double*>(h->ws + h->plan.gIn);
   void* gout = h->ws + h->plan.gOut;
+  // the entries live in a vector that capturing may grow: keep the handles
   aao_problem::GraphEntry* ent = nullptr;
-  TRY(precond_graph(h, k, cycles, transpose, &ent));
+  TRY(precond_graph(h, k, cycles, transpose, 1, &ent));
+  const hipGraphExec_t x1 = ent->exec;
+  TRY(precond_graph(h, k, cycles, transpose, 2, &ent));
+  const hipGraphExec_t x2 = ent->exec;
   TRY(hipMemcpyAsync(gin, r, (size_t)U * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
-  TRY(hipGraphLaunch(ent->exec, h->stream));
+  if (timed) TRY(hipEventRecord(ev[0], h->stream));
+  TRY(hipGraphLaunch(x1, h->stream));
+  if (timed) TRY(hipEventRecord(ev[1], h->stream));
+  TRY(hipGraphLaunch(x2, h->stream));
+  if (timed) TRY(hipEventRecord(ev[2], h->stream));
   return hipMemcpyAsync(z, gout, (size_t)U * h->pi_bytes, hipMemcpyDeviceToDevice, h->stream);
 }
 
@@ -279,7 +424,6 @@ class Fgmres {
     a.nd = nd;
     a.slots = oslots_;
     a.partial = partial_;
-    a.counters = counters_;
     a.nblk = seg_blocks(h_->U, 1);
     return a;
   }
@@ -290,9 +434,10 @@ class Fgmres {
     a.self = 1;
     a.os = 0;
     TRY(gs_pass<double, double>(const_cast<double*>(x), x, a, 1, st_));
-    TRY(hipMemcpyAsync(h_->hpin, oslots_, sizeof(double), hipMemcpyDeviceToHost, st_));
+    double* hp = h_->host_scalars();
+    TRY(hipMemcpyAsync(hp, oslots_, sizeof(double), hipMemcpyDeviceToHost, st_));
     TRY(hipStreamSynchronize(st_));
-    *out = h_->hpin[0];
+    *out = hp[0];
     return hipSuccess;
   }
 
@@ -333,7 +478,7 @@ class Fgmres {
         TRY(gs_pass<double, double>(w_, V_ + (int64_t)c0 * U, a, 1, st_));
       }
     }
-    double* hp = h_->hpin;
+    double* hp = h_->host_scalars();
     TRY(hipMemcpyAsync(hp, oslots_ + H1, sizeof(double) * (size_t)(WW - H1 + 1), hipMemcpyDeviceToHost, st_));
     TRY(hipStreamSynchronize(st_));
     hcol.assign(nd, 0.0);
@@ -347,10 +492,34 @@ class Fgmres {
     return hipSuccess;
   }
 
-  // V_{nd} = (w - V h2) / hn  (second Gram-Schmidt correction folded in)
-  hipError_t next_basis(int nd, double inv_hn) {
+  // The second Gram-Schmidt correction applied to w (w -= V h2), and
+  // ||w||^2 computed directly: used when <w,w> - |h2|^2 cancels.
+  hipError_t correct_and_norm(int nd, double& ww) {
+    const int64_t U = h_->U;
+    const int H2 = 8 + MMAX + 8, WW = H2 + MMAX + 8;
+    for (int c0 = 0; c0 < nd; c0 += DOTS_PER_PASS) {
+      const int cnt = std::min(DOTS_PER_PASS, nd - c0);
+      GSArgs a = gs_args(cnt);
+      a.axpy = 1;
+      a.ca = H2 + c0;
+      a.self = c0 + cnt >= nd;
+      a.os = WW;
+      TRY(gs_pass<double, double>(w_, V_ + (int64_t)c0 * U, a, 1, st_));
+    }
+    double* hp = h_->host_scalars();
+    TRY(hipMemcpyAsync(hp, oslots_ + WW, sizeof(double), hipMemcpyDeviceToHost, st_));
+    TRY(hipStreamSynchronize(st_));
+    ww = hp[0];
+    return hipSuccess;
+  }
+
+  // V_{nd} = (w - V h2) / hn, or w / hn when the correction was applied.
+  hipError_t next_basis(int nd, double inv_hn, bool corrected) {
     const int64_t U = h_->U;
     const int H2 = 8 + MMAX + 8;
+    if (corrected)
+      return basis_update<double, double, double>(w_, 0, V_, U, 0, 0, V_ + (int64_t)nd * U, 0, oslots_, 0, 0, -1,
+                                                  inv_hn, U, 1, st_);
     if (nd <= DOTS_PER_PASS)
       return basis_update<double, double, double>(w_, 0, V_, U, 0, nd, V_ + (int64_t)nd * U, 0, oslots_, 0, H2, -1,
                                                   inv_hn, U, 1, st_);
@@ -364,20 +533,47 @@ class Fgmres {
                                                 inv_hn, U, 1, st_);
   }
 
+  // P-tilde^{-1} of the FP64 vector r, into the TI vector z; phase times
+  // are added once the stream has been synchronised (see phase_times).
+  hipError_t precond(const double* r, TI* z) {
+    TRY(precond_apply(h_, r, z, h_->opts.inner_k, h_->opts.cycles, transpose_, timed_));
+    pending_ = timed_;
+    ++applications_;
+    return hipSuccess;
+  }
+
+  void phase_times() {
+    if (!pending_) return;
+    float a = 0.f, b = 0.f;
+    if (hipEventElapsedTime(&a, h_->phase_ev[0], h_->phase_ev[1]) == hipSuccess &&
+        hipEventElapsedTime(&b, h_->phase_ev[1], h_->phase_ev[2]) == hipSuccess) {
+      // forward: Theta-tilde first; transposed: the S-tilde^T sweep first
+      theta_ms_ += transpose_ ? b : a;
+      schur_ms_ += transpose_ ? a : b;
+    }
+    pending_ = false;
+  }
+
   int run(const double* rhs, double* x, aao_stats* stats) {
     const int64_t U = h_->U;
     const int m = h_->opts.restart;
     auto t0 = std::chrono::steady_clock::now();
-    hipEvent_t pe0, pe1;
-    bool ev = hipEventCreate(&pe0) == hipSuccess && hipEventCreate(&pe1) == hipSuccess;
-    double precond_ms = 0.0;
+    timed_ = !h_->no_alloc;
+    for (int i = 0; i < 3 && timed_; ++i)
+      if (!h_->phase_ev[i] && hipEventCreate(&h_->phase_ev[i]) != hipSuccess) timed_ = false;
     aao_stats local{};
     aao_stats& stt = stats ? *stats : local;
     stt = aao_stats{};
+    hipError_t e = launch_fill<unsigned>(counters_, 0u, 2, st_);
+    if (e != hipSuccess) return status_from_hip(h_, e, "solve");
     double nb2 = 0.0;
-    hipError_t e = norm2(rhs, &nb2);
+    e = norm2(rhs, &nb2);
     if (e != hipSuccess) return status_from_hip(h_, e, "solve");
     const double nb = std::sqrt(nb2);
+    if (!std::isfinite(nb)) {
+      h_->err = "non-finite value in the right-hand side";
+      return AAO_NONFINITE;
+    }
     if (!(nb > 0.0)) {       // zero right-hand side: x = 0 is the solution
       e = launch_fill<double>(x, 0.0, U, st_);
       if (e == hipSuccess) e = hipStreamSynchronize(st_);
@@ -406,19 +602,19 @@ class Fgmres {
       bool stop = false;
       for (int j = 0; j < m && !stop; ++j) {
         its++;
-        if (ev) hipEventRecord(pe0, st_);
-        if ((e = precond_apply(h_, V_ + (int64_t)j * U, Z_ + (int64_t)j * U, h_->opts.inner_k, h_->opts.cycles,
-                               transpose_)) != hipSuccess)
-          break;
-        if (ev) hipEventRecord(pe1, st_);
+        if ((e = precond(V_ + (int64_t)j * U, Z_ + (int64_t)j * U)) != hipSuccess) break;
         if ((e = op<TI>(Z_ + (int64_t)j * U, w_)) != hipSuccess) break;
         double h2sq, ww;
         if ((e = orthogonalize(j + 1, hcol, h2sq, ww)) != hipSuccess) break;
-        if (ev) {
-          float ms = 0.f;
-          if (hipEventElapsedTime(&ms, pe0, pe1) == hipSuccess) precond_ms += ms;
+        phase_times();
+        // h_{j+1,j} = sqrt(<w,w> - |h2|^2) unless that cancels: then the
+        // corrected w's norm is computed directly
+        double nrm2 = ww - h2sq;
+        bool corrected = false;
+        if (!(nrm2 > 1e-8 * ww) && ww > 0.0 && std::isfinite(ww)) {
+          if ((e = correct_and_norm(j + 1, nrm2)) != hipSuccess) break;
+          corrected = true;
         }
-        const double nrm2 = ww - h2sq;
         const double hn = nrm2 > 0.0 ? std::sqrt(nrm2) : 0.0;
         std::vector<double> col(hcol);
         col.push_back(hn);
@@ -441,7 +637,7 @@ class Fgmres {
         if (stt.history_len < 128) stt.history[stt.history_len++] = est;
         if (est <= h_->opts.tol || hn == 0.0 || its >= h_->opts.maxit) stop = true;
         if (!stop && j + 1 < m)
-          if ((e = next_basis(j + 1, 1.0 / hn)) != hipSuccess) break;
+          if ((e = next_basis(j + 1, 1.0 / hn, corrected)) != hipSuccess) break;
       }
       if (e != hipSuccess || status == AAO_NONFINITE) break;
       // x += Z y
@@ -453,8 +649,9 @@ class Fgmres {
       const int YOFF = 4 * (MMAX + 8);
       double* ydev = oslots_ + YOFF;
       if (mm > 0) {
-        for (int i = 0; i < mm; ++i) h_->hpin[i] = y[i];
-        if ((e = hipMemcpyAsync(ydev, h_->hpin, sizeof(double) * mm, hipMemcpyHostToDevice, st_)) != hipSuccess)
+        double* hp = h_->host_scalars();
+        for (int i = 0; i < mm; ++i) hp[i] = y[i];
+        if ((e = hipMemcpyAsync(ydev, hp, sizeof(double) * mm, hipMemcpyHostToDevice, st_)) != hipSuccess)
           break;
         for (int c0 = 0; c0 < mm; c0 += DOTS_PER_PASS) {
           const int cnt = std::min(DOTS_PER_PASS, mm - c0);
@@ -467,12 +664,20 @@ class Fgmres {
         if ((e = hipStreamSynchronize(st_)) != hipSuccess) break;
       }
     }
-    if (ev) {
-      hipEventDestroy(pe0);
-      hipEventDestroy(pe1);
+    if (e == hipSuccess) {
+      phase_times();
+      unsigned* hc = reinterpret_cast<unsigned*>(h_->host_scalars());
+      e = hipMemcpyAsync(hc, counters_, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, st_);
+      if (e == hipSuccess) e = hipStreamSynchronize(st_);
+      if (e == hipSuccess) {
+        stt.inner_iterations = hc[0];
+        stt.inner_solves = (int)hc[1];
+      }
     }
     stt.outer_iterations = its;
-    stt.precond_ms = precond_ms;
+    stt.theta_ms = theta_ms_;
+    stt.schur_ms = schur_ms_;
+    stt.precond_ms = theta_ms_ + schur_ms_;
     stt.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (e != hipSuccess) return status_from_hip(h_, e, transpose_ ? "solve_adjoint" : "solve");
     if (status == AAO_NONFINITE) h_->err = "non-finite value in the Krylov recurrence";
@@ -487,6 +692,9 @@ class Fgmres {
   double *V_, *w_, *partial_, *oslots_;
   unsigned* counters_;
   TI* Z_;
+  bool timed_ = false, pending_ = false;
+  int applications_ = 0;
+  double theta_ms_ = 0.0, schur_ms_ = 0.0;
 };
 
 }  // namespace
@@ -520,18 +728,19 @@ hipError_t apply_mg(aao_problem* h, bool transpose, int stage, int count, int cy
 }
 
 hipError_t prepare_graph(aao_problem* h, bool transpose) {
-  if (!h->opts.use_graph) return hipSuccess;
+  if (!h->opts.use_graph || h->no_alloc) return hipSuccess;
   aao_problem::GraphEntry* ent = nullptr;
-  return precond_graph(h, h->opts.inner_k, h->opts.cycles, transpose, &ent);
+  TRY(precond_graph(h, h->opts.inner_k, h->opts.cycles, transpose, 1, &ent));
+  return precond_graph(h, h->opts.inner_k, h->opts.cycles, transpose, 2, &ent);
 }
 
 int apply_P(aao_problem* h, const double* r, double* z, int inner_k, int cycles, bool transpose) {
   hipError_t e;
   if (h->opts.precision == AAO_PREC_FP64) {
-    e = precond_apply(h, r, z, inner_k, cycles, transpose);
+    e = precond_apply(h, r, z, inner_k, cycles, transpose, false);
   } else {
     float* zp = reinterpret_cast<float*>(h->ws + h->plan.outY);
-    e = precond_apply(h, r, zp, inner_k, cycles, transpose);
+    e = precond_apply(h, r, zp, inner_k, cycles, transpose, false);
     if (e == hipSuccess) e = launch_copy_cast<double, float>(z, zp, h->U, h->stream);
   }
   return status_from_hip(h, e, "apply_P");
