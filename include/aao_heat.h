@@ -238,6 +238,21 @@ int aao_assemble_rhs(aao_problem* h, const double* f, const double* u0, double* 
  * last iterate, st filled) or an error. */
 int aao_solve(aao_problem* h, const double* rhs, double* x, aao_stats* st);
 
+/* aao_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * The handle's workspace is placed in a static device array of
+ * AAO_NO_ALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends; problems whose aao_workspace_size exceeds it
+ * are rejected with AAO_WORKSPACE_TOO_SMALL.  No device memory is allocated
+ * or freed, no graph is captured and no event is created (theta_ms and
+ * schur_ms stay 0).  The handle needs no aao_set_workspace; if it has one,
+ * that workspace is left untouched.  The array is shared by all calls on a
+ * device and is re-initialised by each call: calls that overlap in time on
+ * one device race and must be serialised by the caller.  Synchronous on the
+ * handle's stream.  Results equal aao_solve's. */
+#define AAO_NO_ALLOC_SCRATCH_BYTES (64u << 20)
+int aao_solve_no_alloc(aao_problem* h, const double* rhs, double* x, aao_stats* st);
+
 /* Solve A^T lam = g the same way with the transposed preconditioner.
  * g, lam: device, U values; lam holds the initial guess on entry. */
 int aao_solve_adjoint(aao_problem* h, const double* g, double* lam, aao_stats* st);

@@ -55,6 +55,7 @@ SIGNATURES = {
     "aao_assemble_rhs": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "aao_solve": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(Stats)]),
     "aao_solve_adjoint": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(Stats)]),
+    "aao_solve_no_alloc": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(Stats)]),
     "aao_grad_logkappa": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "aao_last_error": (ctypes.c_char_p, [c_void_p]),
     "aao_create_batch": (c_int, [ctypes.POINTER(Desc), c_int, ctypes.POINTER(Opts), c_int, ctypes.POINTER(c_void_p)]),
