@@ -167,6 +167,16 @@ int aao_workspace_size(const aao_problem* h, size_t* bytes);
  * handle's stream.  The workspace stays caller-owned. */
 int aao_set_workspace(aao_problem* h, void* dev_ptr, size_t bytes);
 
+/* Replace the diffusivity of a handle created with variable kappa (Sec. 2,
+ * eq. (2.1)): values is a DEVICE pointer to N nodal values, kappa itself
+ * (is_log = 0) or theta = log kappa (is_log = 1; the library takes exp).
+ * Rebuilds the face coefficients, the coarse Galerkin stencils and the
+ * coarsest-level inverses on the host and copies them into the workspace in
+ * place, so the captured P-tilde graphs stay valid (synchronises the
+ * handle's stream).  AAO_INVALID_ARG for a constant-kappa handle or values
+ * that are not finite and > 0; the handle is unchanged on error. */
+int aao_set_kappa(aao_problem* h, const double* values, int is_log);
+
 /* Stream for all later work (a hipStream_t; NULL = default stream). */
 int aao_set_stream(aao_problem* h, void* stream);
 

@@ -43,6 +43,7 @@ SIGNATURES = {
     "aao_workspace_size": (c_int, [c_void_p, ctypes.POINTER(c_size_t)]),
     "aao_set_workspace": (c_int, [c_void_p, c_void_p, c_size_t]),
     "aao_set_stream": (c_int, [c_void_p, c_void_p]),
+    "aao_set_kappa": (c_int, [c_void_p, c_void_p, c_int]),
     "aao_destroy": (c_int, [c_void_p]),
     "aao_get_tableau": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "aao_sizes": (c_int, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int64)]),

@@ -141,6 +141,15 @@ class HeatProblem:
             raise ValueError(f"{name} must be a contiguous float64 CUDA tensor with {numel} values")
         return t
 
+    def set_kappa(self, values, log=False):
+        """Replace the nodal diffusivity (N float64 CUDA values; theta =
+        log kappa with ``log=True``) of a problem created with a kappa array.
+        The library rebuilds its diffusivity tables in place."""
+        values = self._vec(values.detach().contiguous() if isinstance(values, torch.Tensor) else values,
+                           self.N, "kappa")
+        self._sync_stream()
+        self._check(self._lib.aao_set_kappa(self._h, _ptr(values), int(bool(log))))
+
     def tableau(self):
         A = np.zeros(self.s * self.s)
         b = np.zeros(self.s)
@@ -316,6 +325,18 @@ class HeatBatch:
                 and t.is_contiguous() and t.numel() == numel):
             raise ValueError(f"{name} must be a contiguous float64 CUDA tensor with {numel} values")
         return t
+
+    def set_kappa(self, i, values, log=False):
+        """Replace problem i's nodal diffusivity (N_i float64 CUDA values, or
+        log kappa with ``log=True``); see HeatProblem.set_kappa."""
+        h = ctypes.c_void_p()
+        self._check(self._lib.aao_batch_problem(self._h, int(i), ctypes.byref(h)))
+        n = int(self.off_nodes[i + 1] - self.off_nodes[i])
+        values = self._vec(values.detach().contiguous(), n, "kappa")
+        torch.cuda.current_stream(self.device).synchronize()
+        code = self._lib.aao_set_kappa(h, _ptr(values), int(bool(log)))
+        if code != 0:
+            raise AAOError(code, self._lib.aao_last_error(h).decode())
 
     def split(self, t, kind="unknowns"):
         """Per-problem views of a batch tensor (kind: unknowns | nodes | forcing)."""

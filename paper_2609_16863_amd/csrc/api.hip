@@ -86,6 +86,59 @@ void plan_workspace(aao_problem* h) {
   h->ws_need = align256(off);
 }
 
+// The tables that depend on the diffusivity, for nodal values `kappa`
+// (empty for kappa = 1): face coefficients and the Galerkin stencils of the
+// coarse levels (variable kappa), and the exact inverses of the coarsest
+// level when it is not solved by fast diagonalization -- for the shifts
+// tau L_ii of P-tilde and tau LT_ii of its transpose (sets 0, 1) and, with
+// MGRIT, those of its coarse step of mgrit_cf tau (sets 2, 3).  Written into
+// the handle only when all of them could be built.
+bool kappa_tables(aao_problem* h, const std::vector<double>& kappa, std::string& why) {
+  std::vector<double> faces, st9_all, cinv;
+  std::vector<size_t> st9_off;
+  std::vector<std::vector<double>> st9;
+  const int L = (int)h->lev_n.size();
+  if (!kappa.empty()) {
+    for (double kv : kappa)
+      if (!(kv > 0.0) || !std::isfinite(kv)) {
+        why = "kappa must be finite and > 0";
+        return false;
+      }
+    aao::face_coefficients(h->dim, h->n, kappa.data(), faces);
+    aao::galerkin_stencils_2d(h->lev_n, faces, h->ih2, st9);
+    st9_off.assign(L, 0);
+    for (int l = 1; l < L; ++l) {
+      st9_off[l] = st9_all.size();
+      st9_all.insert(st9_all.end(), st9[l].begin(), st9[l].end());
+    }
+  }
+  if (h->fd_n == 0) {
+    const int lc = L - 1;
+    const std::vector<double> tri(h->tri_host.begin() + h->tri_off[lc],
+                                  h->tri_host.begin() + h->tri_off[lc] + 6 * h->lev_n[lc]);
+    const int nsets = h->opts.schur == AAO_SCHUR_MGRIT ? 4 : 2;
+    for (int set = 0; set < nsets; ++set)
+      for (int i = 0; i < h->s; ++i) {
+        const double* Lf = (set & 1) ? h->LT : h->tab.L;
+        const double a = (set >= 2 ? h->opts.mgrit_cf : 1) * h->tau * Lf[i * h->s + i];
+        std::vector<double> inv;
+        if (!aao::coarse_inverse(h->dim, h->lev_n[lc], tri, a, lc == 0, h->ih2,
+                                 kappa.empty() ? nullptr : faces.data(),
+                                 (!kappa.empty() && lc > 0) ? st9[lc].data() : nullptr, inv)) {
+          why = "singular coarsest multigrid level";
+          return false;
+        }
+        cinv.insert(cinv.end(), inv.begin(), inv.end());
+      }
+  }
+  h->faces_host.swap(faces);
+  h->st9_host.swap(st9_all);
+  h->st9_off.swap(st9_off);
+  h->cinv_host.swap(cinv);
+  if (h->fd_n == 0) h->cinv_N = h->lev_N[L - 1];
+  return true;
+}
+
 bool valid_opts(const aao_opts* o, std::string& why) {
   if (o->restart < 1 || o->restart > aao::MMAX) { why = "restart must be in [1, 120]"; return false; }
   if (o->maxit < 1) { why = "maxit must be >= 1"; return false; }
@@ -241,7 +294,6 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
         delete h;
         return fail(nullptr, AAO_INVALID_ARG, "kappa must be finite and > 0");
       }
-    aao::face_coefficients(d->dim, d->n, d->kappa, h->faces_host);
     if (d->dim == 3) {
       delete h;
       return fail(nullptr, AAO_INVALID_ARG, "variable kappa is supported in 2D only");
@@ -265,15 +317,6 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
     h->tri_off[l] = h->tri_host.size();
     h->tri_host.insert(h->tri_host.end(), tri[l].begin(), tri[l].end());
   }
-  std::vector<std::vector<double>> st9;
-  if (h->vark) {
-    aao::galerkin_stencils_2d(h->lev_n, h->faces_host, h->ih2, st9);
-    h->st9_off.assign(h->lev_n.size(), 0);
-    for (size_t l = 1; l < h->lev_n.size(); ++l) {
-      h->st9_off[l] = h->st9_host.size();
-      h->st9_host.insert(h->st9_host.end(), st9[l].begin(), st9[l].end());
-    }
-  }
   // fast diagonalization of the coarsest level (2D, constant kappa)
   if (fd_ok) {
     const int lc = (int)h->lev_n.size() - 1;
@@ -287,27 +330,9 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
       return fail(nullptr, AAO_INVALID_ARG, "coarsest multigrid level not diagonalizable");
     }
   }
-  // otherwise, exact inverses of the coarsest level, for the shifts tau L_ii
-  // (P-tilde) and tau LT_ii (its transpose)
-  if (h->fd_n == 0) {
-    const int lc = (int)h->lev_n.size() - 1;
-    h->cinv_N = h->lev_N[lc];
-    // sets 0, 1: shifts of P-tilde and its transpose; with MGRIT also 2, 3:
-    // those of the coarse propagator (time step mgrit_cf tau)
-    const int nsets = opts.schur == AAO_SCHUR_MGRIT ? 4 : 2;
-    for (int set = 0; set < nsets; ++set)
-      for (int i = 0; i < d->s; ++i) {
-        const int tr = set & 1;
-        const double a = (set >= 2 ? opts.mgrit_cf : 1) * h->tau * (tr ? h->LT : h->tab.L)[i * d->s + i];
-        std::vector<double> inv;
-        if (!aao::coarse_inverse(d->dim, h->lev_n[lc], tri[lc], a, lc == 0, h->ih2,
-                                 h->vark ? h->faces_host.data() : nullptr,
-                                 (h->vark && lc > 0) ? st9[lc].data() : nullptr, inv)) {
-          delete h;
-          return fail(nullptr, AAO_INVALID_ARG, "singular coarsest multigrid level");
-        }
-        h->cinv_host.insert(h->cinv_host.end(), inv.begin(), inv.end());
-      }
+  if (!kappa_tables(h, h->kappa, why)) {
+    delete h;
+    return fail(nullptr, AAO_INVALID_ARG, why);
   }
   plan_workspace(h);
   *out = h;
@@ -345,6 +370,30 @@ int aao_set_workspace(aao_problem* h, void* dev_ptr, size_t bytes) {
     return aao::status_from_hip(h, e, "workspace upload");
   }
   return AAO_OK;
+}
+
+int aao_set_kappa(aao_problem* h, const double* values, int is_log) {
+  if (!h) return AAO_INVALID_ARG;
+  if (!values) return fail(h, AAO_INVALID_ARG, "null kappa");
+  if (!h->vark) return fail(h, AAO_INVALID_ARG, "the handle was created with constant kappa");
+  if (is_log != 0 && is_log != 1) return fail(h, AAO_INVALID_ARG, "is_log must be 0 or 1");
+  std::vector<double> kap((size_t)h->N);
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = hipMemcpy(kap.data(), values, kap.size() * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return aao::status_from_hip(h, e, "set_kappa");
+  if (is_log)
+    for (double& v : kap) v = std::exp(v);
+  const size_t nf = h->faces_host.size(), ns = h->st9_host.size(), nc = h->cinv_host.size();
+  std::string why;
+  if (!kappa_tables(h, kap, why)) return fail(h, AAO_INVALID_ARG, why);
+  if (h->faces_host.size() != nf || h->st9_host.size() != ns || h->cinv_host.size() != nc)
+    return fail(h, AAO_INVALID_ARG, "internal: diffusivity tables changed size");
+  h->kappa.swap(kap);
+  if (!h->ws) return AAO_OK;
+  // same sizes and places in the workspace: the captured graphs stay valid
+  e = aao::upload_tables(h);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  return aao::status_from_hip(h, e, "set_kappa upload");
 }
 
 int aao_set_stream(aao_problem* h, void* stream) {

@@ -164,11 +164,15 @@ def test_autograd_heat_solve_gradients_match_oracle():
     sp = _gradient_specs()[1]
     kappa, f, u0 = _problem_inputs(sp)
     vt = _targets([sp], [(kappa, f, u0)])[0]
-    base = HeatProblem(2, sp["n"], sp["s"], sp["nt"], 1.0, precision="fp32", tol=1e-12, maxit=300)
+    # one handle for every call: the library takes theta = log kappa itself
+    base = HeatProblem(2, sp["n"], sp["s"], sp["nt"], 1.0, kappa=np.ones(sp["n"] ** 2), precision="fp32",
+                       tol=1e-12, maxit=300)
     ft = to_dev(f).requires_grad_(True)
     ut = to_dev(u0).requires_grad_(True)
     th = to_dev(np.log(kappa)).requires_grad_(True)
     announce("autograd heat_solve", sp["n"])
+    # a first call at another diffusivity, so the handle has to move to theta
+    heat_solve(ft.detach(), ut.detach(), base, theta=th.detach() + 0.3)
     x = heat_solve(ft, ut, base, theta=th)
     N, nt = sp["n"] ** 2, sp["nt"]
     v = x[: (nt + 1) * N].view(nt + 1, N)
@@ -180,3 +184,30 @@ def test_autograd_heat_solve_gradients_match_oracle():
     assert rel_err(to_host(ft.grad), gfr) <= 1e-7
     assert rel_err(to_host(ut.grad), gu0r) <= 1e-7
     assert rel_err(to_host(th.grad), gkr) <= 1e-7
+
+
+def test_set_kappa_equals_a_fresh_handle():
+    """aao_set_kappa (device values) on an existing handle gives the solve of
+    a handle created with that diffusivity: bit for bit from kappa, to
+    rounding from log kappa."""
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    sp = _gradient_specs()[0]
+    kappa, f, u0 = _problem_inputs(sp)
+    opts = dict(precision="fp32", tol=1e-10, schur="mgrit", mgrit_cf=2)
+    fresh = HeatProblem(2, sp["n"], sp["s"], sp["nt"], 1.0, kappa=kappa, **opts)
+    moved = HeatProblem(2, sp["n"], sp["s"], sp["nt"], 1.0, kappa=2.0 * kappa, **opts)
+    rhs = fresh.assemble_rhs(to_dev(f.ravel()), to_dev(u0))
+    announce("set_kappa")
+    x0, _ = moved.solve(rhs)            # graphs captured at the old diffusivity
+    moved.set_kappa(to_dev(kappa))
+    x1, st1 = fresh.solve(rhs)
+    x2, st2 = moved.solve(rhs)
+    assert st1["outer_iterations"] == st2["outer_iterations"]
+    assert torch.equal(x1, x2)
+    assert not torch.equal(x0, x2)
+    # through theta = log kappa: exp(log kappa) differs from kappa by rounding
+    moved.set_kappa(to_dev(2.0 * kappa))
+    moved.set_kappa(to_dev(np.log(kappa)), log=True)
+    x3, _ = moved.solve(rhs)
+    assert rel_err(to_host(x3), to_host(x1)) <= 1e-12

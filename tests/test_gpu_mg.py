@@ -62,17 +62,26 @@ def test_apply_mg_fp64_matches_oracle(dim, n, s, nt, transpose):
         assert rel_err(z, ref) <= 1e-12, (stage, rel_err(z, ref))
 
 
+# 130: one-level tail (its 65^2 level is above 64^2); 150, 257 and 75 with
+# variable kappa: the two-level register tail (a <= 64^2 smoothing level, one
+# more, then the exact level), which the benchmark-size cycles use
+@pytest.mark.parametrize("n,vark,tail_levels", [(130, False, 1), (150, False, 2), (257, False, 2),
+                                                (75, True, 2)])
 @pytest.mark.parametrize("precision,tol", [("fp32", 2e-5), ("fp16", 1e-3), ("bf16", 3e-2)])
-def test_apply_mg_low_precision(precision, tol):
+def test_apply_mg_low_precision(precision, tol, n, vark, tail_levels):
     require_gpu()
     from paper_2609_16863_amd import HeatProblem
-    dim, n, s, nt = 2, 130, 3, 3
-    p = allatonce.Problem(n, dim, s, nt, 1.0)
-    hp = HeatProblem(dim, n, s, nt, 1.0, precision=precision)
-    rng = np.random.default_rng(11)
+    dim, s, nt = 2, 3, 3
+    rng = np.random.default_rng(11 + n)
+    kappa = np.exp(0.5 * rng.standard_normal(n * n)) if vark else None
+    p = allatonce.Problem(n, dim, s, nt, 1.0, kappa=kappa)
+    hp = HeatProblem(dim, n, s, nt, 1.0, precision=precision, kappa=kappa)
+    nodes, tail = hp.mg_levels()
+    if precision != "fp64":
+        assert len(nodes) - 1 - tail == tail_levels, (nodes, tail)
     r = rng.standard_normal((nt, p.N))
     for stage in range(s):
-        announce("apply_mg", precision, dim, n, s, nt, "stage", stage)
+        announce("apply_mg", precision, dim, n, s, nt, "vark", vark, "stage", stage)
         z = _run(hp, r.astype(np.float32).astype(np.float64), stage, 2, False)
         ref = _oracle(p, False, stage, r.astype(np.float32).astype(np.float64), 2)
         assert rel_err(z, ref) <= tol, (stage, rel_err(z, ref))

@@ -91,30 +91,3 @@ def test_adjoint_solve_matches_oracle(precision):
     lam, st = hp.solve_adjoint(to_dev(g))
     assert st["converged"]
     assert rel_err(to_host(lam), adjoint.solve(p, g)) <= 1e-8
-
-
-@pytest.mark.parametrize("name,precision,k,steps", [("heat2d_n512_s3_nt64", "fp32", 4, 8),
-                                                    ("heat3d_n128_s3_nt32", "fp32", 3, 2)])
-def test_full_size_workload_sampled_steps(name, precision, k, steps):
-    """The benchmark-size 2D problem (67.4M unknowns) and the 3D problem
-    (270.5M unknowns, FGMRES(20)), solved on the GPU; stepping is sequential,
-    so the first `steps` steps of x* are what the oracle computes on them."""
-    require_gpu()
-    from paper_2609_16863_amd import HeatProblem
-    w = heat_inputs.WORKLOADS[name]
-    hp = HeatProblem(w.dim, w.n, w.s, w.nt, w.T, restart=w.restart, tol=1e-10, maxit=200, inner_k=k,
-                     precision=precision)
-    f, u0 = heat_inputs.workload_inputs(w, hp.stage_times())
-    announce("full-size solve", name, precision)
-    rhs = hp.assemble_rhs(to_dev(np.ravel(f)), to_dev(u0))
-    x, st = hp.solve(rhs)
-    assert st["converged"], st
-    p = allatonce.Problem(w.n, w.dim, w.s, w.nt, w.T)
-    sub = allatonce.Problem(w.n, w.dim, w.s, steps, p.tau * steps)
-    xs = stepping.solve_steps(p, f, u0, steps)
-    vs, Vs = allatonce.split(sub, xs)
-    xg = to_host(x)
-    del x, rhs
-    vg, Vg = allatonce.split(p, xg)
-    assert rel_err(vg[: steps + 1], vs) <= 1e-8
-    assert rel_err(Vg[:steps], Vs) <= 1e-8
