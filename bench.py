@@ -2,22 +2,26 @@
 
 One step = one full FGMRES solve to a true FP64 relative residual of 1e-8 of
 the all-at-once system (paper eq. (2.4)) with the block preconditioner
-(eqs. (3.2)-(3.3)) applied in FP32 (the mixed-precision arm, approach A2).
-The same solve with the FP64 preconditioner (approach A1) is timed beside
-it, with the same inner settings (4 inner GMRES iterations, one V-cycle with
-2 + 2 Jacobi sweeps per shifted block).  Workload: 2D heat on a 512 x 512
-interior grid, Radau IIA s = 3, 64 time steps to T = 1, FGMRES(30); seeded
-Gaussian-bump source and smooth random initial condition (synthetic,
-generated on the host).
+(eqs. (3.2)-(3.3)) applied in FP32 (the mixed-precision arm, approach A2),
+its S-tilde solve done by one two-level MGRIT iteration (coarsening factor 8;
+the parallel route of Sec. 5.2).  The same solve with the FP64
+preconditioner (approach A1) is timed beside it with equal inner settings
+(4 inner GMRES iterations, one V-cycle with 2 + 2 Jacobi sweeps per shifted
+block), and both again with S-tilde by forward substitution.  Workload: 2D
+heat on a 512 x 512 interior grid, Radau IIA s = 3, 64 time steps to T = 1,
+FGMRES(30); seeded Gaussian-bump source and smooth random initial condition
+(synthetic, generated on the host).  The multigrid launch shapes come from
+the library's autotuner (aao_autotune) before timing.
 
-Prints one JSON line (rank 0).  `roofline` reports apply_A's algorithmic HBM
-bytes / its average launch time, and `roofline_vcycle` the same for one
-V-cycle on the 64 stage blocks of the batched Theta-tilde phase, both
-measured here with HIP events on the stream the kernels run on; `traffic` is
-the counter-measured HBM bytes per launch from profiles/ while the kernel
-source is unchanged.  `cpu_baseline` times the FP64 CPU oracle (sequential
-stepping with an exact DST stage solve) on a bounded number of time steps,
-scaled to the full 64 steps.
+Prints one JSON line.  Besides the contract keys it reports the Theta-tilde /
+S-tilde time split and inner-iteration counts, the forward error against the
+oracle on all time steps, per-kernel launch times of the V-cycle at the block
+counts P-tilde uses, `roofline` for the dominant kernel (live, HIP events on
+the launch stream; traffic from the committed counter summary while its
+source is unchanged), apply_A and the 64-block V-cycle as secondary
+rooflines, `cpu_baseline` (the oracle's DST stepping on all 64 steps with
+every host core), and `extra` timings of the 3D 128^3 workload in four
+preconditioner precisions and of the 64-problem uneven batch.
 """
 import argparse
 import json
@@ -32,28 +36,38 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "solve time to relres 1e-8, mixed vs FP64 precond; stencil/V-cycle HBM GB/s"
+PBYTES = {"fp64": (8, 8), "fp32": (4, 4), "bf16": (4, 2), "fp16": (4, 2)}   # (level 0, coarse levels)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="heat2d_n512_s3_nt64")
     ap.add_argument("--mixed", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--inner-k", type=int, default=4)
     ap.add_argument("--cycles", type=int, default=1)
     ap.add_argument("--nu", type=int, default=2)
-    ap.add_argument("--tail-max", type=int, default=0,
-                    help="largest multigrid level (nodes) solved in one workgroup's LDS (0 = library default)")
-    ap.add_argument("--coarse-max", type=int, default=0,
-                    help="nodes of the exactly solved coarsest multigrid level (0 = library default)")
+    ap.add_argument("--schur", default="mgrit", choices=["mgrit", "sweep"],
+                    help="S-tilde by two-level MGRIT or by forward substitution")
+    ap.add_argument("--mgrit-cf", type=int, default=8)
+    ap.add_argument("--mgrit-iters", type=int, default=1)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch shapes")
+    ap.add_argument("--launch-shapes", default=None,
+                    help="TALL_MIN_B,TAIL_EXTEND: set the multigrid launch shapes instead of autotuning "
+                         "(for runs under a profiler, which distorts the tuner's timings)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-preconditioner arm")
+    ap.add_argument("--no-variants", action="store_true", help="skip the S-tilde substitution arms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=8, help="time steps in the CPU oracle sample")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 3D and batch timings")
     ap.add_argument("--roofline-reps", type=int, default=20)
     ap.add_argument("--roofline-only", action="store_true",
-                    help="only the roofline launches (apply_A, V-cycle, a 1 GiB device copy); for counter runs")
+                    help="only the roofline launches (V-cycle kernels, apply_A, a 1 GiB copy); for counter runs")
     return ap.parse_args()
 
 
@@ -62,7 +76,7 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the all-at-once solve "
                           "is measured at its single-GPU shape (time slabs per GPU would be the "
-                          "sharding, with the S-tilde sweep pipelined across slabs)"}))
+                          "sharding, with S-tilde by MGRIT across slabs)"}))
         sys.exit(2)
     import torch
 
@@ -72,21 +86,34 @@ def main():
     w = heat_inputs.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    common = dict(restart=w.restart, tol=1e-8, inner_k=args.inner_k, cycles=args.cycles,
-                  nu1=args.nu, nu2=args.nu, mg_tail_max=args.tail_max, coarse_max=args.coarse_max)
+    common = dict(restart=w.restart, tol=1e-8, inner_k=args.inner_k, cycles=args.cycles, nu1=args.nu,
+                  nu2=args.nu, schur=args.schur, mgrit_cf=args.mgrit_cf, mgrit_iters=args.mgrit_iters)
     t_setup = time.perf_counter()
     hp_mix = HeatProblem(w.dim, w.n, w.s, w.nt, w.T, precision=args.mixed, **common)
     f, u0 = heat_inputs.workload_inputs(w, hp_mix.stage_times())
     f_d = torch.from_numpy(np.ascontiguousarray(f.ravel())).to(dev)
     u0_d = torch.from_numpy(u0).to(dev)
     rhs = hp_mix.assemble_rhs(f_d, u0_d)
+    del f_d
+    if args.launch_shapes:
+        tall, ext = (int(v) for v in args.launch_shapes.split(","))
+        hp_mix.set_launch_shapes(tall, ext)
+        tune = dict(hp_mix.tune_state, source="given")
+    elif args.no_autotune:
+        tune = None
+    else:
+        tune = dict(hp_mix.autotune(reps=5), source="autotune")
+
+    def shapes(hp):
+        if tune is not None:
+            hp.set_launch_shapes(tune["tall_min_b"], tune["tail_extend"])
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
-    print(f"[bench] {w.name}: U = {hp_mix.U:,} unknowns, setup {setup_s:.1f} s", file=sys.stderr, flush=True)
+    log(f"{w.name}: U = {hp_mix.U:,} unknowns, setup {setup_s:.1f} s, launch shapes {tune and (tune['tall_min_b'], tune['tail_extend'])}")
     if args.roofline_only:
+        prof = vcycle_kernels(hp_mix, args.mixed, args.roofline_reps)
         x = torch.randn(hp_mix.U, dtype=torch.float64, device=dev)
-        out = {"roofline": measure_roofline(hp_mix, x, args.roofline_reps),
-               "roofline_vcycle": measure_vcycle(hp_mix, args.mixed, args.roofline_reps) if w.dim == 2 else None,
+        out = {"vcycle_kernels": prof, "apply_A": measure_apply_A(hp_mix, x, args.roofline_reps),
                "copy_reference": measure_copy(1 << 30, 5)}
         print(json.dumps(out))
         return
@@ -104,37 +131,61 @@ def main():
             if it >= W:
                 times.append(dt)
             stats = st
-            print(f"[bench] {label} solve {it - W if it >= W else 'warmup'}: {dt * 1e3:.1f} ms, "
-                  f"{st['outer_iterations']} its, relres {st['relres']:.2e}", file=sys.stderr, flush=True)
+            log(f"{label} solve {it - W if it >= W else 'warmup'}: {dt * 1e3:.1f} ms, "
+                f"{st['outer_iterations']} its, relres {st['relres']:.2e}, "
+                f"theta {st['theta_ms']:.1f} ms, S-tilde {st['schur_ms']:.1f} ms")
         return times, stats, x
+
+    def summary(times, st):
+        return {"solve_s": float(np.mean(times)), "outer_iterations": st["outer_iterations"],
+                "relres": st["relres"], "theta_ms": st["theta_ms"], "schur_ms": st["schur_ms"],
+                "inner_solves": st["inner_solves"], "inner_iterations": st["inner_iterations"]}
 
     # ---- timed region: K mixed-precision solves -----------------------------
     torch.cuda.synchronize()
-    times_mix, st_mix, x_mix = run(hp_mix, args.mixed, args.steps, args.warmup)
+    times_mix, st_mix, x_mix = run(hp_mix, f"{args.mixed}/{args.schur}", args.steps, args.warmup)
     total_s = sum(times_mix)
     ms_per_step = 1e3 * total_s / args.steps
+    x_host = x_mix.cpu().numpy()
 
-    # ---- FP64-preconditioner arm --------------------------------------------
+    # ---- FP64-preconditioner arm and the substitution variants ---------------
     fp64 = None
     if not args.no_fp64:
         hp64 = HeatProblem(w.dim, w.n, w.s, w.nt, w.T, precision="fp64", **common)
-        times64, st64, x64 = run(hp64, "fp64", args.steps, args.warmup)
-        fp64 = {"solve_s": float(np.mean(times64)), "outer_iterations": st64["outer_iterations"],
-                "relres": st64["relres"],
-                "mixed_vs_fp64_speedup": float(np.mean(times64) / np.mean(times_mix))}
-        del hp64, x64
+        shapes(hp64)
+        times64, st64, _ = run(hp64, f"fp64/{args.schur}", args.steps, args.warmup)
+        fp64 = summary(times64, st64)
+        fp64["mixed_vs_fp64_speedup"] = float(np.mean(times64) / np.mean(times_mix))
+        del hp64
         torch.cuda.empty_cache()
+    variants = {}
+    if not args.no_variants:
+        other = "sweep" if args.schur == "mgrit" else "mgrit"
+        for prec in ([args.mixed] + ([] if args.no_fp64 else ["fp64"])):
+            hv = HeatProblem(w.dim, w.n, w.s, w.nt, w.T, precision=prec, **dict(common, schur=other))
+            shapes(hv)
+            tv, sv, _ = run(hv, f"{prec}/{other}", 2, 1)
+            variants[f"{prec}_{other}"] = summary(tv, sv)
+            del hv
+            torch.cuda.empty_cache()
 
-    # ---- roofline of the dominant kernel (live, HIP events) ------------------
-    roofline = measure_roofline(hp_mix, x_mix, args.roofline_reps)
+    # ---- rooflines (live, HIP events on the launch stream) -------------------
+    prof = vcycle_kernels(hp_mix, args.mixed, args.roofline_reps)
+    dom = prof["dominant"]
+    roofline = {k: v for k, v in prof["by_kernel"][dom].items() if k != "launches"}
+    roofline["kernel"] = dom
+    roofline["traffic"] = measured_traffic(dom.split("<")[0], w, args.mixed)
+    apply_a = measure_apply_A(hp_mix, x_mix, args.roofline_reps)
+    vc64 = prof["kernels"]["vcycle"][str(w.nt)]
 
-    roofline_vcycle = measure_vcycle(hp_mix, args.mixed, args.roofline_reps) if w.dim == 2 else None
-
-    # ---- CPU oracle baseline on a bounded sample -----------------------------
-    cpu = None
-    fwd_err = None
+    # ---- CPU oracle baseline and the forward error ---------------------------
+    cpu = fwd_err = None
     if not args.no_cpu:
-        cpu, fwd_err = cpu_baseline(w, f, u0, x_mix, args.cpu_steps)
+        cpu, fwd_err = cpu_baseline(w, f, u0, x_host)
+    del x_mix
+
+    # ---- the other workloads (3D in four precisions, the uneven batch) --------
+    extra = None if args.no_extras else extras(args, tune is not None)
 
     out = {
         "metric": METRIC, "value": total_s / args.steps, "unit": "s", "n_gpus": 1,
@@ -144,44 +195,164 @@ def main():
         "config": {"workload": w.name, "dim": w.dim, "n": w.n, "s": w.s, "nt": w.nt,
                    "unknowns": hp_mix.U, "restart": w.restart, "tol": 1e-8,
                    "inner_k": args.inner_k, "cycles": args.cycles, "nu1": args.nu, "nu2": args.nu,
-                   "mg_tail_max": args.tail_max, "coarse_max": args.coarse_max,
-                   "preconditioner": args.mixed, "parallelism": "single GPU"},
+                   "schur": args.schur, "mgrit_cf": args.mgrit_cf, "mgrit_iters": args.mgrit_iters,
+                   "preconditioner": args.mixed, "launch_shapes": tune and {k: tune[k] for k in
+                                                                            ("tall_min_b", "tail_extend", "source")},
+                   "parallelism": "single GPU"},
         "outer_iterations": st_mix["outer_iterations"], "relres": st_mix["relres"],
-        "precond_ms_per_solve": st_mix["precond_ms"],
-        "fp64_preconditioner": fp64,
-        "forward_error_vs_oracle_sampled_steps": fwd_err,
-        "roofline": roofline, "roofline_vcycle": roofline_vcycle, "cpu_baseline": cpu,
+        "phases_ms_per_solve": {"theta": st_mix["theta_ms"], "schur": st_mix["schur_ms"]},
+        "inner": {"solves": st_mix["inner_solves"], "iterations": st_mix["inner_iterations"]},
+        "fp64_preconditioner": fp64, "schur_variants": variants,
+        "forward_error_vs_oracle": fwd_err,
+        "roofline": roofline, "roofline_apply_A": apply_a,
+        "roofline_vcycle_64_blocks": vc64, "vcycle_kernels": prof,
+        "cpu_baseline": cpu, "extra": extra,
     }
     print(json.dumps(out))
 
 
-def measure_roofline(hp, x, reps):
+def vcycle_kernels(hp, precision, reps):
+    """Per-launch times of one V-cycle at the block counts P-tilde uses (one
+    S-tilde step; an MGRIT relaxation batch; all nt Theta-tilde blocks), with
+    each kernel's algorithmic bytes: per block, a tiled down kernel at level l
+    reads b_l and writes the smoothed x_l and b_{l+1}  [p(2 N_l) + p' N_{l+1}];
+    an up kernel reads x_l, the correction and b_l and writes x_l
+    [p(3 N_l) + p' N_{l+1}]; the register tail reads b and writes x at its
+    first level [2 p N_tail]; p / p' the storage bytes of the two levels.
+    The dominant kernel is the one with the most time per application of
+    P-tilde: sum over block counts of (V-cycles per application) x (mean
+    launch time), with the V-cycle counts of the autotuner's report."""
+    nodes, tail = hp.mg_levels()
+    p0, pc = PBYTES[precision]
+    pl = [p0] + [pc] * (len(nodes) - 1)
+    nt, s, k = hp.nt, hp.s, hp.options["inner_k"]
+    cf = hp.options["mgrit_cf"]
+    K = -(-nt // cf)
+    per_solve = k * s * hp.options["cycles"]   # V-cycles per inner GMRES solve
+    weight = {}
+
+    def add(B, n):
+        if B >= 1 and n > 0:
+            weight[B] = weight.get(B, 0) + n
+
+    if hp.options["schur"] == "mgrit":
+        # per iteration: F-relaxation steps j = 1..cf-1 over the intervals
+        # that reach kc + j, the step into the K-1 C-points, and K-2 coarse
+        # steps (the first correction needs none); then the last F-relaxation
+        it = hp.options["mgrit_iters"]
+        for j in range(1, cf):
+            add(min(K, (nt - j) // cf + 1) if j <= nt else 0, per_solve * (it + 1))
+        add(K - 1, per_solve * it)
+        add(1, per_solve * it * max(K - 2, 0))
+        if nt % cf == 0:
+            add(1, per_solve)
+    else:
+        add(1, per_solve * nt)
+    add(nt, per_solve)
+    counts = sorted(weight)
+
+    def kbytes(label):
+        name, lev = label.split("@")
+        lev = int(lev)
+        if name == "k_down2d":
+            return pl[lev] * 2 * nodes[lev] + pl[lev + 1] * nodes[lev + 1]
+        if name == "k_up2d":
+            return pl[lev] * 3 * nodes[lev] + pl[lev + 1] * nodes[lev + 1]
+        if name in ("k_tail_fast", "k_tail"):
+            return 2 * pl[lev] * nodes[lev]
+        return None
+
+    kernels, totals = {"vcycle": {}}, {}
+    for B in counts:
+        launches, total_us = hp.profile_vcycle(count=B, stage=0, reps=reps)
+        vc_bytes = 0
+        for label, us, us_alone in launches:
+            nb = kbytes(label)
+            entry = {"avg_launch_us": us, "alone_us": us_alone, "bound": "hbm", "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s"}
+            if nb is not None:
+                entry["bytes_per_launch"] = float(nb * B)
+                entry["achieved"] = nb * B / (us * 1e-6) / 1e9
+                entry["frac"] = entry["achieved"] / HBM_PEAK_GBS
+                vc_bytes += nb * B
+            kernels.setdefault(label, {})[str(B)] = entry
+            totals[label] = totals.get(label, 0.0) + weight.get(B, 0) * us
+        gbs = vc_bytes / (total_us * 1e-6) / 1e9
+        kernels["vcycle"][str(B)] = {"avg_launch_us": total_us, "bytes_per_launch": float(vc_bytes),
+                                     "achieved": gbs, "frac": gbs / HBM_PEAK_GBS, "bound": "hbm",
+                                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "blocks": B, "levels": nodes,
+                                     "tail_level": tail}
+    # group the launches by compiled kernel (what a kernel trace reports):
+    # level 0 and the coarse levels are different instantiations, and so are
+    # the short and tall tiles of the tiled kernels
+    tall_min = hp.tune_state["tall_min_b"] if hp.tune_state else 8
+
+    def symbol(label, B):
+        name, lev = label.split("@")
+        sym = name + ("<level 0" if lev == "0" else "<coarse levels")
+        if name in ("k_down2d", "k_up2d") and precision != "fp64":
+            sym += ", tall tiles" if B >= tall_min else ", short tiles"
+        return sym + ">"
+
+    groups = {}
+    for label, per_b in kernels.items():
+        if label == "vcycle":
+            continue
+        for b, e in per_b.items():
+            B = int(b)
+            g = groups.setdefault(symbol(label, B), {"launches": 0.0, "us": 0.0, "alone": 0.0, "bytes": 0.0,
+                                                     "labels": set()})
+            g["launches"] += weight.get(B, 0)
+            g["us"] += weight.get(B, 0) * e["avg_launch_us"]
+            g["alone"] += weight.get(B, 0) * e["alone_us"]
+            g["bytes"] += weight.get(B, 0) * e.get("bytes_per_launch", 0.0)
+            g["labels"].add(f"{label} x{B}")
+    # launch durations: each launch replayed alone from a graph (its kernel
+    # time plus the short gap between graph nodes, which is what a kernel
+    # trace's average tracks); the in-situ times add the dispatch gap after
+    # an event to every launch
+    all_us = sum(g["alone"] for g in groups.values())
+    table = {}
+    for sym, g in groups.items():
+        if g["launches"] == 0:
+            continue
+        avg = g["alone"] / g["launches"]
+        gbs = g["bytes"] / (g["alone"] * 1e-6) / 1e9
+        table[sym] = {"launches_per_application": g["launches"], "avg_launch_us": avg,
+                      "in_situ_us": g["us"] / g["launches"],
+                      "bytes_per_launch": g["bytes"] / g["launches"], "achieved": gbs,
+                      "frac": gbs / HBM_PEAK_GBS, "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "share_of_vcycle_time": g["alone"] / all_us, "launches": sorted(g["labels"])}
+    dom = max(table, key=lambda k: table[k]["share_of_vcycle_time"])
+    return {"kernels": kernels, "weights": {str(b): weight.get(b, 0) for b in counts},
+            "by_kernel": table, "dominant": dom}
+
+
+def measure_apply_A(hp, x, reps):
     """apply_A: 16 B per unknown (read x once, write y once) per launch."""
     import torch
     y = torch.empty_like(x)
     sec = _event_time(lambda: hp.apply_A(x, y), reps)
     nbytes = 16.0 * hp.U
     gbs = nbytes / sec / 1e9
-    traffic = measured_traffic("k_apply_A_2d") if hp.n == 512 and hp.s == 3 and hp.nt == 64 else None
     return {"kernel": "k_apply_A_2d" if hp.dim == 2 else "k_apply_A", "bound": "hbm", "achieved": gbs,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "B per launch",
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
             "bytes_per_launch": nbytes, "avg_launch_us": sec * 1e6}
 
 
-def measured_traffic(name):
-    """HBM bytes per launch of a roofline kernel from the committed counter
+def measured_traffic(kernel, w, precision):
+    """HBM bytes per launch of the roofline kernel from the committed counter
     summary (rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by a plain copy of
     known size), or None when the kernel's source changed since they were
     taken (its sha256 no longer matches) or no summary exists."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "roofline_heat2d_n512_s3_nt64.md")
+    path = os.path.join(ROOT, "profiles", f"traffic_{w.name}_{precision}.md")
     if not os.path.exists(path):
         return None
     for line in open(path):
         m = re.match(r"traffic (\S+) source=(\S+) sha256=([0-9a-f]+) bytes_per_launch=(\d+)", line.strip())
-        if m and m.group(1) == name:
+        if m and m.group(1) == kernel:
             src = os.path.join(ROOT, m.group(2))
             if os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == m.group(3):
                 return float(m.group(4))
@@ -205,40 +376,6 @@ def _event_time(fn, reps):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
-def measure_vcycle(hp, precision, reps):
-    """One V-cycle (from zero) on all nt stage blocks of stage 0, the batched
-    shifted-block solve of Theta-tilde.  Algorithmic bytes of the fused 2D
-    level kernels, per block: level l above the LDS tail moves
-    5 N_l p_l + 2 N_{l+1} p_{l+1} (pre-smooth + restriction read b_l and write
-    the smoothed x_l and b_{l+1}; prolongation + post-smoothing read x_l, the
-    correction and b_l and write x_l); the tail reads b and writes x at its
-    first level.  p_l: 8 (FP64), 4 (FP32, and level 0 of BF16/FP16), 2 (BF16/FP16
-    coarse levels)."""
-    import torch
-    nodes, l0 = hp.mg_levels()
-    L = len(nodes)
-    pw = 8 if precision == "fp64" else 4
-    pc = {"fp64": 8, "fp32": 4}.get(precision, 2)
-    p = [pw] + [pc] * (L - 1)
-    per_block = 0
-    for l in range(min(l0, L - 1)):
-        per_block += 5 * nodes[l] * p[l] + 2 * nodes[l + 1] * p[l + 1]
-    if l0 < L:
-        per_block += 2 * nodes[l0] * p[l0]
-    B = hp.nt
-    r = torch.randn(B * hp.N, dtype=hp.working_dtype(), device="cuda")
-    z = torch.empty_like(r)
-    sec = _event_time(lambda: hp.apply_mg(r, 0, out=z, cycles=1), reps)
-    nbytes = float(per_block * B)
-    gbs = nbytes / sec / 1e9
-    traffic = (measured_traffic("vcycle") if hp.n == 512 and hp.s == 3 and hp.nt == 64 and precision == "fp32"
-               else None)
-    return {"kernel": "V-cycle: k_down2d per level, k_tail, k_up2d per level", "bound": "hbm",
-            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "traffic": traffic, "traffic_unit": "B per launch", "bytes_per_launch": nbytes,
-            "avg_launch_us": sec * 1e6, "blocks": B, "levels": nodes, "tail_level": l0}
-
-
 def measure_copy(nbytes, reps):
     """Reference: a plain device-to-device copy of nbytes (read + write)."""
     import torch
@@ -248,28 +385,89 @@ def measure_copy(nbytes, reps):
     return {"bytes": nbytes, "avg_launch_us": sec * 1e6, "GBs": 2 * nbytes / sec / 1e9}
 
 
-def cpu_baseline(w, f, u0, x_gpu, nsteps):
+def cpu_baseline(w, f, u0, x_gpu):
+    """The oracle (sequential Radau IIA stepping with exact DST stage solves,
+    FFTs on every host core) on the whole workload, and the GPU solution's
+    forward error against it on all steps."""
     from oracle import allatonce, stepping
-    import torch
+    cores = len(os.sched_getaffinity(0))
     p = allatonce.Problem(w.n, w.dim, w.s, w.nt, w.T)
     tm = {}
     t0 = time.perf_counter()
-    xs = stepping.solve_steps(p, f, u0, nsteps, timings=tm)
+    xs = stepping.solve(p, f, u0, method="dst", workers=cores, timings=tm)
     dt = time.perf_counter() - t0
-    full = tm["factor_s"] + tm["step_s"] * (w.nt / nsteps)
-    # forward error of the GPU solution on the sampled steps (stepping is
-    # sequential, so the first nsteps steps of x* are exactly these)
-    sub = allatonce.Problem(w.n, w.dim, w.s, nsteps, p.tau * nsteps)
-    vs, Vs = allatonce.split(sub, xs)
-    xg = x_gpu.cpu().numpy()
-    vg, Vg = allatonce.split(p, xg)
-    ev = np.linalg.norm(vg[: nsteps + 1] - vs) / np.linalg.norm(vs)
-    eV = np.linalg.norm(Vg[:nsteps] - Vs) / np.linalg.norm(Vs)
-    cpu = {"value": full, "unit": "s", "cores": 1, "kind": "oracle",
-           "sample": f"{nsteps} of {w.nt} time steps of sequential Radau IIA stepping with exact DST "
-                     f"stage solves ({tm['method']}), {dt:.1f} s measured, scaled to {w.nt} steps",
-           "host_cores_available": len(os.sched_getaffinity(0))}
-    return cpu, {"v": float(ev), "V": float(eV), "steps": nsteps}
+    vs, Vs = allatonce.split(p, xs)
+    vg, Vg = allatonce.split(p, x_gpu)
+    ev = np.linalg.norm(vg - vs) / np.linalg.norm(vs)
+    eV = np.linalg.norm(Vg - Vs) / np.linalg.norm(Vs)
+    cpu = {"value": dt, "unit": "s", "cores": cores, "kind": "oracle",
+           "sample": f"the whole workload: {w.nt} steps of sequential Radau IIA stepping with exact DST "
+                     f"stage solves (scipy.fft on {cores} workers), setup {tm['factor_s']:.2f} s + "
+                     f"stepping {tm['step_s']:.2f} s"}
+    return cpu, {"v": float(ev), "V": float(eV), "steps": w.nt}
+
+
+def extras(args, autotune):
+    """3D 128^3 (s = 3, nt = 32, FGMRES(20)) with the preconditioner in FP64,
+    FP32, BF16 and FP16, and the 64-problem uneven batch (FP32), each timed
+    over a few solves after a warm-up."""
+    import torch
+
+    import heat_inputs
+    from oracle import allatonce
+    from paper_2609_16863_amd import HeatBatch, HeatProblem
+    out = {}
+    w3 = heat_inputs.WORKLOADS["heat3d_n128_s3_nt32"]
+    res3 = {}
+    for prec in ["fp64", "fp32", "bf16", "fp16"]:
+        hp = HeatProblem(w3.dim, w3.n, w3.s, w3.nt, w3.T, restart=w3.restart, tol=1e-8, inner_k=3,
+                         precision=prec, schur=args.schur, mgrit_cf=args.mgrit_cf)
+        f, u0 = heat_inputs.workload_inputs(w3, hp.stage_times())
+        rhs = hp.assemble_rhs(torch.from_numpy(np.ascontiguousarray(f.ravel())).cuda(), torch.from_numpy(u0).cuda())
+        del f
+        times, st = [], None
+        for it in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st = hp.solve(rhs)
+            torch.cuda.synchronize()
+            if it > 0:
+                times.append(time.perf_counter() - t0)
+            del x
+        log(f"3D {prec}: {np.mean(times) * 1e3:.0f} ms, {st['outer_iterations']} its")
+        res3[prec] = {"solve_s": float(np.mean(times)), "outer_iterations": st["outer_iterations"],
+                      "relres": st["relres"], "theta_ms": st["theta_ms"], "schur_ms": st["schur_ms"]}
+        del hp, rhs
+        torch.cuda.empty_cache()
+    out[w3.name] = {"unknowns": w3.n ** 3 * (w3.nt * (w3.s + 1) + 1), "restart": w3.restart, "inner_k": 3,
+                    "schur": args.schur, "solves": res3}
+    specs = heat_inputs.batch_problem_specs()
+    data = []
+    for sp in specs:
+        times = allatonce.Problem(sp["n"], 2, sp["s"], sp["nt"], 1.0).stage_times()
+        data.append(heat_inputs.spec_inputs(sp, times))
+    hb = HeatBatch([dict(dim=2, n=sp["n"], s=sp["s"], nt=sp["nt"], kappa=kap) for sp, (kap, _, _) in zip(specs, data)],
+                   streams=4, precision="fp32", tol=1e-8, inner_k=3, schur=args.schur, mgrit_cf=args.mgrit_cf)
+    rhs = hb.assemble_rhs(torch.from_numpy(np.concatenate([d[1].ravel() for d in data])).cuda(),
+                          torch.from_numpy(np.concatenate([d[2].ravel() for d in data])).cuda())
+    times = []
+    for it in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st = hb.solve(rhs)
+        torch.cuda.synchronize()
+        if it > 0:
+            times.append(time.perf_counter() - t0)
+        del x
+    its = [s["outer_iterations"] for s in st]
+    log(f"uneven batch: {np.mean(times) * 1e3:.0f} ms, outer its {min(its)}..{max(its)}")
+    out["batch64_uneven_kappa"] = {"problems": len(specs), "unknowns": hb.U, "solve_s": float(np.mean(times)),
+                                   "outer_iterations_min_max": [min(its), max(its)],
+                                   "converged": all(s["converged"] for s in st), "preconditioner": "fp32",
+                                   "schur": args.schur, "streams": 4}
+    hb.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

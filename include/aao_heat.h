@@ -274,6 +274,54 @@ int aao_solve_adjoint(aao_problem* h, const double* g, double* lam, aao_stats* s
  * g: device, N values (overwritten). */
 int aao_grad_logkappa(aao_problem* h, const double* x, const double* lam, double* g);
 
+/* Launch timing of the shifted-block solve: one V-cycle from zero on
+ * `count` blocks (1..nt) of stage `stage`, timed two ways over `reps`
+ * (1..1000) repetitions on the handle's stream.  In situ: the cycle runs with
+ * a HIP event after every kernel launch, so a launch's time is the interval
+ * since the previous event -- the kernel as it runs inside a solve (inputs
+ * just written by the launch before it, cold caches) plus the dispatch gap
+ * after an event.  Alone: the cycle is captured as a graph and every launch
+ * is replayed by itself, `reps` copies back to back, so its time is the warm
+ * kernel plus the short gap between graph nodes.  Writes the number of
+ * launches per cycle to *nlaunch, their mean in-situ / alone microseconds to
+ * us / us_alone [0..min(cap, *nlaunch)-1] (either may be NULL), their labels
+ * ("kernel@level", one per line, NUL-terminated, truncated to labels_cap) to
+ * labels (may be NULL), and the mean time of the whole cycle replayed as a
+ * graph to *total_us.  Uses the handle's inner-GMRES buffers as scratch
+ * (their contents are overwritten).  Synchronous. */
+int aao_profile_vcycle(aao_problem* h, int stage, int count, int reps, char* labels, size_t labels_cap, double* us,
+                       double* us_alone, int cap, int* nlaunch, double* total_us);
+
+/* Launch shapes of the multigrid kernels, chosen by aao_autotune.  The
+ * tiled level kernels run short tiles or tall ones from tall_min_b blocks
+ * per launch on; the register tail takes a 64 x 64 level too when
+ * tail_extend.  Neither changes the cycle's arithmetic. */
+typedef struct aao_tune {
+  int tall_min_b;          /* chosen threshold (1, 8 or 2^30 = never)         */
+  int tail_extend;         /* chosen: 1 or 0                                   */
+  int from_cache;          /* 1: read from the cache file, nothing timed       */
+  int blocks[3];           /* block counts timed: one S-tilde step, one MGRIT
+                              relaxation batch, the Theta-tilde batch          */
+  double weight[3];        /* V-cycles per P-tilde application at each         */
+  double us[6][3];         /* mean V-cycle microseconds of candidate c
+                              (tall_min_b = {1, 8, 2^30}[c % 3], tail_extend =
+                              c < 3) at each block count (0: not timed)        */
+} aao_tune;
+
+/* Time the candidate launch shapes (`reps` V-cycles each, on stage 0) at
+ * the block counts P-tilde uses and keep the one with the least V-cycle time
+ * per application (weighted by the counts above).  With cache_path (host
+ * string, may be NULL), a line for this device architecture and problem
+ * shape is read from that text file if present -- then nothing is timed --
+ * or appended after timing.  Drops captured graphs when the shapes change.
+ * out: host, may be NULL.  Needs the workspace; synchronous. */
+int aao_autotune(aao_problem* h, int reps, const char* cache_path, aao_tune* out);
+
+/* Set the launch shapes directly (a choice made earlier by aao_autotune):
+ * tall_min_b >= 1, tail_extend 0 or 1.  Drops captured graphs when they
+ * change. */
+int aao_set_launch_shapes(aao_problem* h, int tall_min_b, int tail_extend);
+
 /* Message of the last failure on h (or of the last failed creation if h is
  * NULL).  Valid until the next call on h. */
 const char* aao_last_error(const aao_problem* h);

@@ -36,6 +36,11 @@ class Stats(ctypes.Structure):
                 ("theta_ms", c_double), ("schur_ms", c_double)]
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("tall_min_b", c_int), ("tail_extend", c_int), ("from_cache", c_int), ("blocks", c_int * 3),
+                ("weight", c_double * 3), ("us", (c_double * 3) * 6)]
+
+
 # name -> (restype, argtypes); every entry point declared in include/aao_heat.h
 SIGNATURES = {
     "aao_default_opts": (None, [ctypes.POINTER(Opts)]),
@@ -59,6 +64,10 @@ SIGNATURES = {
     "aao_solve_no_alloc": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(Stats)]),
     "aao_grad_logkappa": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "aao_last_error": (ctypes.c_char_p, [c_void_p]),
+    "aao_profile_vcycle": (c_int, [c_void_p, c_int, c_int, c_int, ctypes.c_char_p, c_size_t, c_void_p, c_void_p,
+                                   c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double)]),
+    "aao_autotune": (c_int, [c_void_p, c_int, ctypes.c_char_p, ctypes.POINTER(Tune)]),
+    "aao_set_launch_shapes": (c_int, [c_void_p, c_int, c_int]),
     "aao_create_batch": (c_int, [ctypes.POINTER(Desc), c_int, ctypes.POINTER(Opts), c_int, ctypes.POINTER(c_void_p)]),
     "aao_batch_count": (c_int, [c_void_p]),
     "aao_batch_offsets": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -98,6 +98,7 @@ class HeatProblem:
         self.N, self.U = Nv.value, Uv.value
         self.device = torch.device(device)
         self._ws = None
+        self.tune_state = None
         if self.device.type == "cuda":
             self._attach_workspace()
 
@@ -217,6 +218,39 @@ class HeatProblem:
         self._check(self._lib.aao_apply_mg(self._h, int(bool(transpose)), int(stage), count, int(cycles),
                                            _ptr(r), _ptr(out)))
         return out
+
+    def profile_vcycle(self, count=1, stage=0, reps=10):
+        """Mean microseconds of every kernel launch of one V-cycle on `count`
+        blocks, in situ and alone (see aao_profile_vcycle):
+        ([(label, us_in_situ, us_alone), ...], cycle_us)."""
+        cap = 512
+        us = np.zeros(cap)
+        ua = np.zeros(cap)
+        labels = ctypes.create_string_buffer(cap * 48)
+        nl, tot = ctypes.c_int(), ctypes.c_double()
+        self._sync_stream()
+        self._check(self._lib.aao_profile_vcycle(self._h, int(stage), int(count), int(reps), labels, len(labels),
+                                                 us.ctypes.data, ua.ctypes.data, cap, ctypes.byref(nl),
+                                                 ctypes.byref(tot)))
+        names = labels.value.decode().splitlines()
+        n = nl.value
+        return list(zip(names, us[:n].tolist(), ua[:n].tolist())), tot.value
+
+    def autotune(self, reps=5, cache=None):
+        """Choose the multigrid launch shapes by timing (see aao_autotune);
+        returns the tuner's report as a dict."""
+        t = _abi.Tune()
+        self._sync_stream()
+        self._check(self._lib.aao_autotune(self._h, int(reps), None if cache is None else str(cache).encode(),
+                                           ctypes.byref(t)))
+        self.tune_state = {"tall_min_b": t.tall_min_b, "tail_extend": t.tail_extend, "from_cache": t.from_cache,
+                           "blocks": list(t.blocks), "weight": list(t.weight), "us": [list(row) for row in t.us]}
+        return self.tune_state
+
+    def set_launch_shapes(self, tall_min_b, tail_extend):
+        """Apply a launch-shape choice (see aao_set_launch_shapes)."""
+        self._check(self._lib.aao_set_launch_shapes(self._h, int(tall_min_b), int(bool(tail_extend))))
+        self.tune_state = dict(self.tune_state or {}, tall_min_b=int(tall_min_b), tail_extend=int(bool(tail_extend)))
 
     def assemble_rhs(self, f, u0, out=None):
         f = self._vec(f, self.N * self.nt * self.s, "f")

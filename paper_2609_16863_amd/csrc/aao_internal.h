@@ -131,6 +131,13 @@ struct aao_problem {
     size_t partial, dscal, counters;          // reductions / device scalars / tickets
     size_t partial_bytes, dscal_bytes;
   } plan{};
+  // Multigrid launch shapes (aao_autotune): blocks per launch from which the
+  // FP32 tiled level kernels use their tall tiles, and whether the register
+  // tail also takes a 64 x 64 level.  Neither changes the algorithm.
+  struct Tune {
+    int tall_min_b = 8;
+    bool tail_extend = true;
+  } tune;
   int pi_bytes = 8;                           // inner (GMRES) storage bytes
   int pm_bytes = 8;                           // multigrid storage bytes
   double mg_scale = 1.0;                      // coarse-level vectors are stored times this (FP16 storage)
@@ -205,6 +212,12 @@ int solve(aao_problem* h, const double* rhs, double* x, aao_stats* st, bool tran
 // `cycles` V-cycles on count blocks of (I + tau L_ii K), L = Crout factor of
 // A (or A^T); r, z in the preconditioner's working type.
 hipError_t apply_mg(aao_problem* h, bool transpose, int stage, int count, int cycles, const void* r, void* z);
+// One V-cycle from zero on `count` blocks of stage `stage`: labels of its
+// launches and their mean microseconds in situ (event after every launch)
+// and alone (each launch replayed by itself from a graph), and the mean
+// microseconds of the whole cycle replayed as a graph.
+hipError_t profile_vcycle(aao_problem* h, int stage, int count, int reps, std::vector<std::string>& labels,
+                          std::vector<double>& us_situ, std::vector<double>& us_alone, double& total_us);
 // Capture (without launching) the HIP graph of the handle's P-tilde (or its
 // transpose) so that later solves only replay it.
 hipError_t prepare_graph(aao_problem* h, bool transpose);

@@ -336,7 +336,6 @@ constexpr int TCX = 16, TCY = 8;   // coarse nodes per down tile; fine tile is 2
 // halo and padding work per owned node (1.5x instead of 2x) in the HBM-bound
 // batched sweeps; the LDS of an FP64 tile that tall would exceed 64 KiB.
 constexpr int TY0 = 16;
-constexpr int TALL_MIN_B = 8;   // blocks per launch from which the tiles are TY0 tall
 
 // Shared memory of one tile with halo R: right-hand side, two iterates, and
 // the operator staged for the sweeps (omega / diagonal per node; face
@@ -1604,7 +1603,7 @@ Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L, in
     for (int t = 0; t <= nls; ++t) ta.n[t] = h->lev_n[l + t];
     return (size_t)tail_fast_layout<C>(ta, nls) * sizeof(C) <= budget;
   };
-  if (h->opts.mg_tail_max <= 0 && l0_ > 1 && levels_ - l0_ == 2 && fast_ok(l0_ - 1)) --l0_;
+  if (h->opts.mg_tail_max <= 0 && h->tune.tail_extend && l0_ > 1 && levels_ - l0_ == 2 && fast_ok(l0_ - 1)) --l0_;
   if (fast_ok(l0_)) {
     fast_nls_ = levels_ - 1 - l0_;
     fast_npt_ = fast_nls_ == 2 ? 4 : 1;
@@ -1786,7 +1785,7 @@ hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, in
   const C omega = (C)h_->omega;
   // tall tiles for batched launches (HBM-bound); latency-bound single blocks
   // keep the short ones (more workgroups, shorter critical path)
-  const bool tall = sizeof(C) == 4 && B >= TALL_MIN_B;
+  const bool tall = sizeof(C) == 4 && B >= h_->tune.tall_min_b;
   constexpr int TY0L = sizeof(C) == 4 ? TY0 : TCY;
   const int ty = tall ? TY0 : TCY;
   const int gx = (nc + TCX - 1) / TCX, gy = (nc + ty - 1) / ty;
@@ -1825,7 +1824,7 @@ hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec
   const LevelOp<C> op = make_op<C>(h_, l, a_[stage]);
   const int nc = h_->lev_n[l + 1];
   const C omega = (C)h_->omega;
-  const bool tall = sizeof(C) == 4 && B >= TALL_MIN_B;
+  const bool tall = sizeof(C) == 4 && B >= h_->tune.tall_min_b;
   constexpr int TY0L = sizeof(C) == 4 ? TY0 : TCY;
   const int ty = tall ? TY0 : TCY;
   const int gx = (nc + TCX - 1) / TCX, gy = (nc + ty - 1) / ty;
@@ -1849,11 +1848,25 @@ hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec
 // One V-cycle on level l.  `pre` = the first (pointwise) sweep from zero was
 // already written into x by the restriction of the level above.
 template <class TI, class TM>
+hipError_t Multigrid<TI, TM>::mark(const char* kernel, int l) {
+  if (!marks_) return hipSuccess;
+  const std::string label = std::string(kernel) + "@" + std::to_string(l);
+  if (marks_->ev.empty()) {   // labels only (a captured cycle)
+    marks_->label.push_back(label);
+    return hipSuccess;
+  }
+  if (marks_->next >= marks_->ev.size()) return hipSuccess;
+  marks_->label[marks_->next] = label;
+  return hipEventRecord(marks_->ev[marks_->next++], st_);
+}
+
+template <class TI, class TM>
 hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_init, bool pre, int B, Vec* result,
                                      const Coupling* cpl) {
   auto& P = h_->plan;
   if (l >= l0_) {
     MG_TRY(tail(stage, x, b, zero_init, B));
+    MG_TRY(mark(fast_nls_ > 0 && zero_init ? "k_tail_fast" : "k_tail", l));
     *result = x;
     return hipSuccess;
   }
@@ -1867,6 +1880,7 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
       hipLaunchKernelGGL((k_coarse_solve<TM, C>), g, blk, 0, st_, (const TM*)b.ptr, b.stride, (TM*)x.ptr, x.stride,
                          coarse_inv(stage), Nc);
     MG_TRY(hipGetLastError());
+    MG_TRY(mark("k_coarse_solve", l));
     *result = x;
     return hipSuccess;
   }
@@ -1879,10 +1893,12 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
     Vec bc{h_->ws + P.mgB[l + 1], Nc};
     Vec xc{h_->ws + P.mgX[l + 1], Nc};
     MG_TRY(down2d(l, stage, b, zero_init ? nullptr : x.ptr, x.stride, tmp, bc, B, cpl));
+    MG_TRY(mark("k_down2d", l));
     if (cpl && cpl->nz > 0) b = Vec{cpl->out, cpl->so};   // the formed right-hand side
     Vec ec{};
     MG_TRY(vcycle(l + 1, stage, xc, bc, true, false, B, &ec));
     MG_TRY(up2d(l, stage, tmp, ec, b, x, B));
+    MG_TRY(mark("k_up2d", l));
     *result = x;
     return hipSuccess;
   }
@@ -1897,6 +1913,7 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
       const int alternations = (nu1 - 1) + nu2;
       Vec first = (l == 0 && (alternations % 2 == 1)) ? tmp : x;
       MG_TRY(smooth(l, stage, first, first, b, true, B));
+      MG_TRY(mark("k_smooth", l));
       cur = first;
     }
     --rem;
@@ -1904,6 +1921,7 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
   for (; rem > 0; --rem) {
     Vec nxt = partner(cur);
     MG_TRY(smooth(l, stage, cur, nxt, b, false, B));
+    MG_TRY(mark("k_smooth", l));
     cur = nxt;
   }
   const int64_t Nc = h_->lev_N[l + 1];
@@ -1911,28 +1929,33 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
   Vec xc{h_->ws + P.mgX[l + 1], Nc};
   const bool next_grid = (l + 1) < l0_;
   MG_TRY(resid_restrict(l, stage, cur, b, bc, xc, next_grid, B));
+  MG_TRY(mark("k_resid_restrict", l));
   Vec ec{};
   MG_TRY(vcycle(l + 1, stage, xc, bc, true, next_grid, B, &ec));
   int post = nu2;
   if (fused_post) {
     Vec nxt = partner(cur);
     MG_TRY(prolong_smooth0(stage, cur, ec, b, nxt, B));
+    MG_TRY(mark("k_prolong_smooth", l));
     cur = nxt;
     --post;
   } else {
     // pointwise prolongation: pick its target so the sweeps end in x
     Vec tgt = (post % 2 == 0) ? x : tmp;
     MG_TRY(prolong(l, cur, ec, tgt, B));
+    MG_TRY(mark("k_prolong", l));
     cur = tgt;
   }
   for (; post > 0; --post) {
     Vec nxt = partner(cur);
     MG_TRY(smooth(l, stage, cur, nxt, b, false, B));
+    MG_TRY(mark("k_smooth", l));
     cur = nxt;
   }
   if (l == 0 && cur.ptr != x.ptr) {   // odd sweep counts from a nonzero start: copy back
     MG_TRY(basis_update<TI, TI, TI>((const TI*)cur.ptr, cur.stride, (const TI*)cur.ptr, 0, 0, 0, (TI*)x.ptr,
                                     x.stride, nullptr, 0, 0, -1, 1.0, Nl, B, st_));
+    MG_TRY(mark("k_basis", l));
     cur = x;
   }
   *result = cur;

@@ -3,6 +3,9 @@
 // level operation.
 #pragma once
 
+#include <string>
+#include <vector>
+
 #include "aao_internal.h"
 
 namespace aao {
@@ -43,6 +46,15 @@ class Multigrid {
   // First level solved by the one-workgroup LDS tail (= levels when none).
   int tail_level() const { return l0_; }
 
+  // Launch labels ("kernel name@level") of vcycle(), in launch order, while
+  // set; with events in `ev`, one is also recorded after every launch.
+  struct Marks {
+    std::vector<hipEvent_t> ev;
+    std::vector<std::string> label;
+    size_t next = 0;
+  };
+  void set_marks(Marks* m) { marks_ = m; }
+
  private:
   struct Vec {
     void* ptr;
@@ -60,8 +72,11 @@ class Multigrid {
   hipError_t up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec xout, int B);
   const C* coarse_inv(int stage) const;
 
+  hipError_t mark(const char* kernel, int l);
+
   aao_problem* h_;
   hipStream_t st_;
+  Marks* marks_ = nullptr;
   double a_[SMAX];
   int levels_;
   int l0_;          // first level solved by the one-workgroup LDS tail

@@ -21,6 +21,7 @@
 #include <chrono>
 #include <cmath>
 #include <memory>
+#include <string>
 #include <vector>
 
 #include "aao_internal.h"
@@ -698,6 +699,176 @@ class Fgmres {
 };
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Launch timing of the V-cycle and the tile autotuner
+// ---------------------------------------------------------------------------
+// The kernel nodes of a graph captured from one stream, in launch order
+// (a chain: each node depends on the one before).
+std::vector<hipGraphNode_t> chain_order(hipGraph_t g, hipError_t& e) {
+  std::vector<hipGraphNode_t> out;
+  size_t n = 0;
+  e = hipGraphGetNodes(g, nullptr, &n);
+  if (e != hipSuccess || n == 0) return out;
+  std::vector<hipGraphNode_t> nodes(n);
+  if ((e = hipGraphGetNodes(g, nodes.data(), &n)) != hipSuccess) return out;
+  hipGraphNode_t cur = nullptr;
+  for (auto nd : nodes) {
+    size_t deps = 0;
+    if ((e = hipGraphNodeGetDependencies(nd, nullptr, &deps)) != hipSuccess) return out;
+    if (deps == 0) cur = nd;
+  }
+  while (cur && out.size() < n) {
+    out.push_back(cur);
+    size_t nd = 0;
+    if ((e = hipGraphNodeGetDependentNodes(cur, nullptr, &nd)) != hipSuccess) return out;
+    if (nd != 1) break;
+    hipGraphNode_t next = nullptr;
+    if ((e = hipGraphNodeGetDependentNodes(cur, &next, &nd)) != hipSuccess) return out;
+    cur = next;
+  }
+  if (out.size() != n) e = hipErrorInvalidValue;   // not a chain
+  return out;
+}
+
+// Mean microseconds per replay of an instantiated graph (events around
+// `reps` back-to-back replays).
+hipError_t time_graph(hipGraphExec_t x, hipStream_t st, int reps, double& us) {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) e = hipGraphLaunch(x, st);   // warm-up
+  if (e == hipSuccess) e = hipEventRecord(a, st);
+  for (int k = 0; k < reps && e == hipSuccess; ++k) e = hipGraphLaunch(x, st);
+  if (e == hipSuccess) e = hipEventRecord(b, st);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  us = 1e3 * ms / reps;
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  return e;
+}
+
+// Per-launch times of one V-cycle from zero on `count` blocks, two ways:
+// in situ -- the cycle run `reps` times with an event recorded after every
+// launch, so a launch's time is the interval since the previous event (the
+// kernel with cold caches as in a solve, plus the dispatch gap after an
+// event) -- and alone -- the cycle captured as a graph and each launch
+// replayed by itself, `reps` copies back to back (every V-cycle kernel writes
+// buffers it does not read, so repeating it alone is well defined).  The
+// cycle time is the mean of `reps` replays of the cycle's graph.
+template <class TI, class TM>
+hipError_t profile_vcycle_typed(aao_problem* h, int stage, int count, int reps, std::vector<std::string>& labels,
+                                std::vector<double>& us_situ, std::vector<double>& us_alone, double& total_us) {
+  const int64_t N = h->N;
+  TI* r = reinterpret_cast<TI*>(h->ws + h->plan.inV);
+  TI* z = reinterpret_cast<TI*>(h->ws + h->plan.inZ);
+  const BVec<TI> zv{z, N};
+  const BVec<const TI> rv{r, N};
+  TRY(launch_fill<TI>(r, TI(1), (int64_t)count * N, h->stream));
+  TRY(hipStreamSynchronize(h->stream));
+  // in situ
+  {
+    Multigrid<TI, TM> mg(h, h->stream, h->tab.L);
+    TRY(mg.solve(stage, zv, rv, count, 1));   // warm-up
+    constexpr int MAXM = 256;                 // launches per V-cycle, at most
+    typename Multigrid<TI, TM>::Marks m;
+    m.ev.assign((size_t)reps * MAXM, nullptr);
+    m.label.assign(m.ev.size(), std::string());
+    std::vector<hipEvent_t> start(reps, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto& ev : m.ev)
+      if (e == hipSuccess) e = hipEventCreate(&ev);
+    for (auto& ev : start)
+      if (e == hipSuccess) e = hipEventCreate(&ev);
+    size_t per = 0;
+    if (e == hipSuccess) {
+      mg.set_marks(&m);
+      for (int k = 0; k < reps && e == hipSuccess; ++k) {
+        m.next = (size_t)k * MAXM;
+        e = hipEventRecord(start[k], h->stream);
+        if (e == hipSuccess) e = mg.solve(stage, zv, rv, count, 1);
+        if (k == 0) per = m.next;
+      }
+      mg.set_marks(nullptr);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) {
+      labels.assign(m.label.begin(), m.label.begin() + per);
+      us_situ.assign(per, 0.0);
+      for (int k = 0; k < reps; ++k) {
+        hipEvent_t prev = start[k];
+        for (size_t i = 0; i < per; ++i) {
+          float ms = 0.f;
+          hipEvent_t cur = m.ev[(size_t)k * MAXM + i];
+          if (hipEventElapsedTime(&ms, prev, cur) == hipSuccess) us_situ[i] += 1e3 * ms / reps;
+          prev = cur;
+        }
+      }
+    }
+    for (auto& ev : m.ev)
+      if (ev) (void)hipEventDestroy(ev);
+    for (auto& ev : start)
+      if (ev) (void)hipEventDestroy(ev);
+    TRY(e);
+  }
+  // alone, and the whole cycle, from a captured graph
+  hipStream_t cap = nullptr;
+  TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  Multigrid<TI, TM> mg(h, cap, h->tab.L);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    const hipError_t e1 = mg.solve(stage, zv, rv, count, 1);
+    const hipError_t e2 = hipStreamEndCapture(cap, &g);
+    e = e1 != hipSuccess ? e1 : e2;
+  }
+  hipGraphExec_t x = nullptr;
+  std::vector<hipGraphNode_t> chain;
+  if (e == hipSuccess) chain = chain_order(g, e);
+  if (e == hipSuccess && chain.size() != labels.size()) e = hipErrorInvalidValue;
+  if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e == hipSuccess) e = time_graph(x, h->stream, reps, total_us);
+  if (x) (void)hipGraphExecDestroy(x);
+  us_alone.assign(chain.size(), 0.0);
+  for (size_t i = 0; i < chain.size() && e == hipSuccess; ++i) {
+    hipKernelNodeParams kp{};
+    e = hipGraphKernelNodeGetParams(chain[i], &kp);
+    hipGraph_t gi = nullptr;
+    if (e == hipSuccess) e = hipGraphCreate(&gi, 0);
+    hipGraphNode_t prev = nullptr;
+    for (int k = 0; k < reps && e == hipSuccess; ++k) {
+      hipGraphNode_t nd = nullptr;
+      e = hipGraphAddKernelNode(&nd, gi, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+      prev = nd;
+    }
+    hipGraphExec_t xi = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&xi, gi, nullptr, nullptr, 0);
+    double t = 0.0;
+    if (e == hipSuccess) e = time_graph(xi, h->stream, 1, t);
+    us_alone[i] = t / reps;
+    if (xi) (void)hipGraphExecDestroy(xi);
+    if (gi) (void)hipGraphDestroy(gi);
+  }
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cap);
+  return e;
+}
+
+hipError_t profile_vcycle(aao_problem* h, int stage, int count, int reps, std::vector<std::string>& labels,
+                          std::vector<double>& us_situ, std::vector<double>& us_alone, double& total_us) {
+  switch (h->opts.precision) {
+    case AAO_PREC_FP64:
+      return profile_vcycle_typed<double, double>(h, stage, count, reps, labels, us_situ, us_alone, total_us);
+    case AAO_PREC_FP32:
+      return profile_vcycle_typed<float, float>(h, stage, count, reps, labels, us_situ, us_alone, total_us);
+    case AAO_PREC_FP16:
+      return profile_vcycle_typed<float, __half>(h, stage, count, reps, labels, us_situ, us_alone, total_us);
+    default:
+      return profile_vcycle_typed<float, __hip_bfloat16>(h, stage, count, reps, labels, us_situ, us_alone, total_us);
+  }
+}
 
 void release_graphs(aao_problem* h) {
   for (auto& g : h->graphs) {

@@ -65,8 +65,10 @@ def test_heat2d_n512_all_steps(precision, schur):
     w = heat_inputs.WORKLOADS["heat2d_n512_s3_nt64"]
     hp = HeatProblem(w.dim, w.n, w.s, w.nt, w.T, restart=w.restart, tol=1e-10, maxit=200, inner_k=4,
                      precision=precision, schur=schur, mgrit_cf=8)
+    # the benchmark's launch configuration: shapes from the autotuner
+    tune = hp.autotune(reps=3)
     f, u0, ref = _reference(w.name, hp.stage_times())
-    announce("512^2 all steps", precision, schur)
+    announce("512^2 all steps", precision, schur, "shapes", tune["tall_min_b"], tune["tail_extend"])
     x, st = hp.solve(hp.assemble_rhs(to_dev(np.ravel(f)), to_dev(u0)))
     assert st["converged"], st
     ev, eV, worst = _check_all_steps(w, x, ref)
