@@ -1,4 +1,4 @@
-"""Block preconditioners of Sec. 3 and FGMRES (Algorithm 1, right preconditioning).
+"""Block preconditioners of Sec. 3 and FGMRES (Algorithm 1).
 
 Test infrastructure only (see ``oracle/__init__.py``).
 
@@ -239,3 +239,82 @@ def fgmres(apply_A, apply_P, rhs, restart=30, tol=1e-8, maxit=100, x0=None):
             Vb.append(w / H[j + 1, j])
         for i in range(m):
             x = x + y[i] * Z[i]
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1: split-preconditioned FGMRES in four precisions
+# ----------------------------------------------------------------------------
+def fgmres_split(apply_A, apply_PL, apply_PR, b, restart=30, tol=1e-8, maxit=100, x0=None,
+                 rnd=None, rnd_A=None, rnd_PL=None, rnd_PR=None):
+    """Algorithm 1 of Sec. 4, restarted, in FP64 arithmetic with optional
+    rounding of each step's result to a lower precision.
+
+    apply_PL / apply_PR: z = P_L^{-1} v / P_R^{-1} v (None = identity);
+    rnd, rnd_A, rnd_PL, rnd_PR: functions rounding the results of the
+    working-precision steps, of the products with A and of the two
+    preconditioner applications (None = FP64).  Within one cycle:
+        t = A x0, t~ = P_L^{-1} t, b~ = P_L^{-1} b, r0 = b~ - t~,
+        beta = ||r0||, v1 = r0 / beta;  for k = 1, 2, ...:
+        z_k = P_R^{-1} v_k, s = A z_k, w = P_L^{-1} s, modified Gram-Schmidt,
+        y_k = argmin ||beta e1 - H_k y||, and the cycle stops once that
+        least-squares residual is <= tol times the first cycle's beta; then
+        x = x0 + Z_k y_k.  A new cycle starts from x (restart).
+    Returns (x, iterations, true relative residuals ||b - A x|| / ||b||
+    after each cycle).
+    """
+    ident = lambda v: v
+    PL = apply_PL or ident
+    PR = apply_PR or ident
+    r_u = rnd or ident
+    r_A = rnd_A or ident
+    r_L = rnd_PL or ident
+    r_R = rnd_PR or ident
+    x = np.zeros_like(b) if x0 is None else np.array(x0, float)
+    nb = np.linalg.norm(b)
+    b_t = r_L(PL(b))
+    beta0 = None
+    its = 0
+    hist = []
+    while True:
+        t = r_A(apply_A(x))
+        t_t = r_L(PL(t)) if np.any(t) else np.zeros_like(t)
+        r0 = r_u(b_t - t_t)
+        beta = np.linalg.norm(r0)
+        beta0 = beta if beta0 is None else beta0
+        hist.append(np.linalg.norm(b - apply_A(x)) / nb)
+        if beta <= tol * beta0 or its >= maxit or beta == 0.0:
+            return x, its, hist
+        Vb = [r_u(r0 / beta)]
+        Z = []
+        H = np.zeros((restart + 1, restart))
+        m = 0
+        done = False
+        for j in range(restart):
+            its += 1
+            z = r_R(PR(Vb[j]))
+            Z.append(z)
+            w = r_L(PL(r_A(apply_A(z))))
+            for i in range(j + 1):
+                H[i, j] = Vb[i] @ w
+                w = r_u(w - H[i, j] * Vb[i])
+            H[j + 1, j] = np.linalg.norm(w)
+            m = j + 1
+            e1 = np.zeros(m + 1)
+            e1[0] = beta
+            y, *_ = np.linalg.lstsq(H[: m + 1, :m], e1, rcond=None)
+            est = np.linalg.norm(e1 - H[: m + 1, :m] @ y)
+            if est <= tol * beta0 or H[j + 1, j] == 0.0 or its >= maxit:
+                done = True
+                break
+            Vb.append(r_u(w / H[j + 1, j]))
+        for i in range(m):
+            x = r_u(x + y[i] * Z[i])
+        if done:
+            hist.append(np.linalg.norm(b - apply_A(x)) / nb)
+            return x, its, hist
+
+
+def round_fp32(v):
+    """Round to IEEE single precision (round to nearest even) and back."""
+    return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+

@@ -95,3 +95,102 @@ def test_fgmres_practical_preconditioner_converges_to_stepping(s):
     assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
     # Sec. 5.1: at most 10 outer iterations to 1e-8 with 3 multigrid cycles (here 1e-10)
     assert its <= 14
+
+
+# ---- Algorithm 1 (split preconditioning, four precisions) ------------------
+def test_algorithm1_without_preconditioners_is_gmres_minimiser():
+    """P_L = P_R = I, one cycle of k steps: x_k minimises ||b - A x|| over the
+    Krylov space K_k(A, b) (brute-force least squares over its power basis)."""
+    rng = np.random.default_rng(12)
+    m, k = 25, 5
+    A = np.eye(m) * 2 + rng.standard_normal((m, m)) * 0.3
+    b = rng.standard_normal(m)
+    x, its, _ = precond.fgmres_split(lambda v: A @ v, None, None, b, restart=k, tol=0.0, maxit=k)
+    assert its == k
+    Kr = np.column_stack([np.linalg.matrix_power(A, j) @ b for j in range(k)])
+    y, *_ = np.linalg.lstsq(A @ Kr, b, rcond=None)
+    assert np.linalg.norm(x - Kr @ y) <= 1e-9 * np.linalg.norm(x)
+
+
+def test_algorithm1_left_ideal_preconditioner_two_steps():
+    """P_L = the ideal P of eq. (3.1): (P^{-1} A - I)^2 = 0, so the
+    left-preconditioned iteration ends in at most two steps (Sec. 3)."""
+    p, f, u0, _ = _prob(2, 4, 3, 4)
+    ops = precond.StageOps(p)
+    K = p.K()
+    rhs = allatonce.rhs(p, f, u0)
+    x, its, _ = precond.fgmres_split(lambda y: allatonce.apply_blockwise(p, y, K),
+                                     lambda r: precond.apply_preconditioner(ops, r, exact=True), None,
+                                     rhs, restart=10, tol=1e-12)
+    assert its <= 2
+    xs = stepping.solve(p, f, u0, method="lu")
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_algorithm1_right_equals_fgmres():
+    """Algorithm 1 with P_L = I is the right-preconditioned FGMRES."""
+    p, f, u0, _ = _prob(2, 6, 3, 4)
+    ops = precond.StageOps(p, inner_k=3, nu1=2, nu2=2)
+    K = p.K()
+    A = lambda y: allatonce.apply_blockwise(p, y, K)
+    P = lambda r: precond.apply_preconditioner(ops, r)
+    rhs = allatonce.rhs(p, f, u0)
+    x1, its1, _ = precond.fgmres_split(A, None, P, rhs, restart=30, tol=1e-10)
+    x2, its2, _ = precond.fgmres(A, P, rhs, restart=30, tol=1e-10)
+    assert its1 == its2
+    assert np.linalg.norm(x1 - x2) <= 1e-10 * np.linalg.norm(x2)
+
+
+@pytest.mark.parametrize("side,k", [("right", 3), ("split", 3), ("left", 10)])
+def test_algorithm1_sides_reach_the_solution(side, k):
+    """With P-tilde on either side (or both), tightly converged Algorithm 1
+    reaches x* = sequential stepping; on the left the inner solves must be
+    tight, since the test is then on P-tilde^{-1}(A x) - P-tilde^{-1} b for
+    a nonlinear P-tilde (next test)."""
+    p, f, u0, _ = _prob(2, 6, 2, 4)
+    ops = precond.StageOps(p, inner_k=k, nu1=2, nu2=2)
+    K = p.K()
+    P = lambda r: precond.apply_preconditioner(ops, r)
+    PL = P if side in ("left", "split") else None
+    PR = P if side in ("right", "split") else None
+    rhs = allatonce.rhs(p, f, u0)
+    x, its, hist = precond.fgmres_split(lambda y: allatonce.apply_blockwise(p, y, K), PL, PR, rhs,
+                                        restart=30, tol=1e-12, maxit=200)
+    xs = stepping.solve(p, f, u0, method="lu")
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs), (its, hist[-1])
+
+
+def test_algorithm1_left_accuracy_follows_inner_accuracy():
+    """Left preconditioning with the nonlinear P-tilde (inner GMRES from zero,
+    Sec. 3): once the preconditioned residual is tiny, the true residual is
+    bounded by how far P-tilde is from a fixed linear map, which shrinks as
+    the inner iterations grow."""
+    p, f, u0, _ = _prob(2, 6, 2, 4)
+    K = p.K()
+    A = lambda y: allatonce.apply_blockwise(p, y, K)
+    rhs = allatonce.rhs(p, f, u0)
+    true = []
+    for k in (3, 6, 10):
+        ops = precond.StageOps(p, inner_k=k, nu1=2, nu2=2)
+        _, _, hist = precond.fgmres_split(A, lambda r: precond.apply_preconditioner(ops, r), None, rhs,
+                                          restart=30, tol=1e-12, maxit=100)
+        true.append(hist[-1])
+    assert true[0] > 1e-6 and true[2] < 1e-10 and true[0] > true[1] > true[2]
+
+
+def test_algorithm1_single_precision_system_stagnates():
+    """Approach A3 (Sec. 5): the system solved in single precision
+    (u = u_A = u_PR = FP32).  The true FP64 residual cannot go far below the
+    FP32 unit roundoff times the condition of the problem, unlike FP64."""
+    p, f, u0, _ = _prob(2, 12, 2, 6)
+    ops = precond.StageOps(p, inner_k=3, nu1=2, nu2=2)
+    K = p.K()
+    A = lambda y: allatonce.apply_blockwise(p, y, K)
+    P = lambda r: precond.apply_preconditioner(ops, r)
+    rhs = allatonce.rhs(p, f, u0)
+    r32 = precond.round_fp32
+    _, _, h32 = precond.fgmres_split(A, None, P, rhs, restart=30, tol=1e-12, maxit=60, rnd=r32, rnd_A=r32,
+                                     rnd_PR=r32)
+    _, _, h64 = precond.fgmres_split(A, None, P, rhs, restart=30, tol=1e-12, maxit=60)
+    assert min(h64) <= 1e-11
+    assert min(h32) >= 1e-9
