@@ -74,6 +74,14 @@ typedef enum aao_schur {
                               step size mgrit_cf tau                           */
 } aao_schur;
 
+/* Where P-tilde enters the outer FGMRES (Algorithm 1 of Sec. 4: P_L on the
+ * left, P_R on the right). */
+typedef enum aao_side {
+  AAO_SIDE_RIGHT = 0,      /* P_L = I, P_R = P-tilde (the sequential runs)      */
+  AAO_SIDE_LEFT = 1,       /* P_L = P-tilde, P_R = I (the parallel runs)        */
+  AAO_SIDE_SPLIT = 2       /* P_L = P_R = P-tilde                              */
+} aao_side;
+
 /* Problem description (Sec. 2).  kappa: host pointer to N nodal
  * diffusivities (> 0), copied at creation, or NULL for kappa = 1.  A face
  * between two interior nodes carries their harmonic mean, a face to the
@@ -118,6 +126,16 @@ typedef struct aao_opts {
                               ceil(nt / mgrit_cf) - 1 of them the result is the
                               forward substitution's                           */
   int mgrit_fcf;           /* 1: FCF-relaxation, 0: F-relaxation               */
+  int side;                /* aao_side.  RIGHT stops on the true residual
+                              ||rhs - A x|| <= tol ||rhs||.  LEFT and SPLIT
+                              follow Algorithm 1: the solve ends when the
+                              least-squares residual of the preconditioned
+                              system is <= tol times the first cycle's
+                              ||P_L^{-1} rhs - P_L^{-1} A x0|| (or, at a
+                              restart, when the preconditioned residual of x
+                              is); stats.relres reports the true residual,
+                              which P-tilde's nonlinearity (inner GMRES) can
+                              leave larger                                     */
 } aao_opts;
 
 /* Solve statistics (host struct filled by aao_solve*). */
@@ -241,8 +259,9 @@ int aao_mg_levels(const aao_problem* h, int cap, int64_t* nodes, int* levels, in
  * at t_n + c_i tau; u0: device, N values; rhs: device, U values. */
 int aao_assemble_rhs(aao_problem* h, const double* f, const double* u0, double* rhs);
 
-/* Solve A x = rhs by right-preconditioned restarted FGMRES (Algorithm 1 with
- * P_L = I) in FP64 with P-tilde applied in the handle's precision.
+/* Solve A x = rhs by restarted FGMRES (Algorithm 1; P-tilde on the side
+ * opts.side, right by default) in FP64 with P-tilde applied in the handle's
+ * precision.
  * x: device, U values, initial guess on entry, solution on exit.
  * st: host, may be NULL.  Returns AAO_OK or AAO_NOT_CONVERGED (x holds the
  * last iterate, st filled) or an error. */

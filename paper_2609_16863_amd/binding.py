@@ -24,7 +24,7 @@ def _ptr(t):
 
 def _make_opts(lib, *, restart, maxit, tol, inner_k, cycles, nu1, nu2, omega, precision, use_graph,
                mg_tail_max, coarse_max=0, inner_tol=0.0, schur="sweep", mgrit_cf=8, mgrit_iters=1,
-               mgrit_fcf=False):
+               mgrit_fcf=False, side="right"):
     opts = _abi.Opts()
     lib.aao_default_opts(ctypes.byref(opts))
     opts.restart, opts.maxit, opts.tol = restart, maxit, tol
@@ -39,6 +39,7 @@ def _make_opts(lib, *, restart, maxit, tol, inner_k, cycles, nu1, nu2, omega, pr
     opts.mgrit_cf = int(mgrit_cf)
     opts.mgrit_iters = int(mgrit_iters)
     opts.mgrit_fcf = int(bool(mgrit_fcf))
+    opts.side = _abi.SIDES[side]
     return opts
 
 
@@ -72,7 +73,7 @@ class HeatProblem:
     def __init__(self, dim, n, s, nt, T=1.0, kappa=None, *, restart=30, maxit=100, tol=1e-8,
                  inner_k=3, cycles=1, nu1=2, nu2=2, omega=0.0, precision="fp64", use_graph=True,
                  mg_tail_max=0, coarse_max=0, inner_tol=0.0, schur="sweep", mgrit_cf=8, mgrit_iters=1,
-                 mgrit_fcf=False, device="cuda"):
+                 mgrit_fcf=False, side="right", device="cuda"):
         self._lib = _abi.load()
         self.dim, self.n, self.s, self.nt, self.T = dim, n, s, nt, float(T)
         self._kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
@@ -82,11 +83,11 @@ class HeatProblem:
                             nu2=nu2, omega=omega, precision=precision, use_graph=use_graph,
                             mg_tail_max=mg_tail_max, coarse_max=coarse_max, inner_tol=inner_tol,
                             schur=schur, mgrit_cf=mgrit_cf, mgrit_iters=mgrit_iters, mgrit_fcf=mgrit_fcf,
-                            device=device)
+                            side=side, device=device)
         opts = _make_opts(self._lib, restart=restart, maxit=maxit, tol=tol, inner_k=inner_k, cycles=cycles,
                           nu1=nu1, nu2=nu2, omega=omega, precision=precision, use_graph=use_graph,
                           mg_tail_max=mg_tail_max, coarse_max=coarse_max, inner_tol=inner_tol, schur=schur,
-                          mgrit_cf=mgrit_cf, mgrit_iters=mgrit_iters, mgrit_fcf=mgrit_fcf)
+                          mgrit_cf=mgrit_cf, mgrit_iters=mgrit_iters, mgrit_fcf=mgrit_fcf, side=side)
         self.precision = precision
         h = ctypes.c_void_p()
         code = self._lib.aao_create_problem(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h))

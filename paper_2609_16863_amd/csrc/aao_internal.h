@@ -122,6 +122,7 @@ struct aao_problem {
   struct Plan {
     size_t tri_d, tri_f, faces_d, faces_f, cinv_d, cinv_f, st9_d, st9_f, fd_d, fd_f;
     size_t outV, outZ, outW, outY;           // outer FGMRES
+    size_t outPb;                            // P-tilde^{-1} b (left / split preconditioning)
     size_t gIn, gOut;                        // fixed input/output of the captured P-tilde
     size_t inV, inZ, inW, inX;               // inner GMRES (nt instances)
     size_t rana;                              // Rana right-hand side (nt*N)
@@ -195,6 +196,9 @@ hipError_t launch_grad_logkappa(const aao_problem* h, const double* x, const dou
                                 hipStream_t st);
 template <class TD, class TS>
 hipError_t launch_copy_cast(TD* dst, const TS* src, int64_t n, hipStream_t st);
+// out = a - b (b may be null), converted to TO
+template <class TO, class TA>
+hipError_t launch_diff(TO* out, const TA* a, const TA* b, int64_t n, hipStream_t st);
 template <class T>
 hipError_t launch_fill(T* dst, T v, int64_t n, hipStream_t st);
 

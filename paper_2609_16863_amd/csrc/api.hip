@@ -47,6 +47,7 @@ void plan_workspace(aao_problem* h) {
   P.outZ = take((size_t)m * U * pi);
   P.outW = take((size_t)U * sizeof(double));
   P.outY = take((size_t)U * pi);
+  P.outPb = take(h->opts.side != AAO_SIDE_RIGHT ? (size_t)U * pi : 0);
   P.gIn = take(h->opts.use_graph ? (size_t)U * sizeof(double) : 0);
   P.gOut = take(h->opts.use_graph ? (size_t)U * pi : 0);
   P.inV = take((size_t)(k + 1) * UV * pi);
@@ -155,6 +156,7 @@ bool valid_opts(const aao_opts* o, std::string& why) {
   if (o->mgrit_cf != 0 && (o->mgrit_cf < 2 || o->mgrit_cf > 64)) { why = "mgrit_cf must be in [2, 64]"; return false; }
   if (o->mgrit_iters < 0) { why = "mgrit_iters must be >= 0"; return false; }
   if (o->mgrit_fcf != 0 && o->mgrit_fcf != 1) { why = "mgrit_fcf must be 0 or 1"; return false; }
+  if (o->side < AAO_SIDE_RIGHT || o->side > AAO_SIDE_SPLIT) { why = "unknown side"; return false; }
   return true;
 }
 
@@ -223,6 +225,7 @@ void aao_default_opts(aao_opts* o) {
   o->mgrit_cf = 8;
   o->mgrit_iters = 1;
   o->mgrit_fcf = 0;
+  o->side = AAO_SIDE_RIGHT;
 }
 
 int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) {

@@ -528,6 +528,23 @@ hipError_t launch_assemble_rhs(const aao_problem* h, const double* f, const doub
                         hipMemcpyDeviceToDevice, st);
 }
 
+// out = a - b (b may be null: out = a), converted to TO
+template <class TO, class TA>
+__global__ void k_diff(TO* __restrict__ out, const TA* __restrict__ a, const TA* __restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    const double v = ld<TA, double>(a + i) - (b ? ld<TA, double>(b + i) : 0.0);
+    out[i] = (TO)v;
+  }
+}
+
+template <class TO, class TA>
+hipError_t launch_diff(TO* out, const TA* a, const TA* b, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_diff<TO, TA>), dim3(grid1d(n)), dim3(TPB), 0, st, out, a, b, n);
+  return hipGetLastError();
+}
+template hipError_t launch_diff<double, double>(double*, const double*, const double*, int64_t, hipStream_t);
+template hipError_t launch_diff<double, float>(double*, const float*, const float*, int64_t, hipStream_t);
+
 template <class TD, class TS>
 hipError_t launch_copy_cast(TD* dst, const TS* src, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL((k_copy_cast<TD, TS>), dim3(grid1d(n)), dim3(TPB), 0, st, dst, src, n);

@@ -537,6 +537,10 @@ class Fgmres {
   // P-tilde^{-1} of the FP64 vector r, into the TI vector z; phase times
   // are added once the stream has been synchronised (see phase_times).
   hipError_t precond(const double* r, TI* z) {
+    if (pending_) {   // a previous application's times are still unread
+      TRY(hipEventSynchronize(h_->phase_ev[2]));
+      phase_times();
+    }
     TRY(precond_apply(h_, r, z, h_->opts.inner_k, h_->opts.cycles, transpose_, timed_));
     pending_ = timed_;
     ++applications_;
@@ -555,9 +559,17 @@ class Fgmres {
     pending_ = false;
   }
 
+  // Algorithm 1, restarted.  side RIGHT: z_j = P^{-1} v_j, w = A z_j, and
+  // a cycle starts from r = rhs - A x; LEFT: w = P^{-1} (A v_j), r0 =
+  // P^{-1} rhs - P^{-1} (A x); SPLIT: both.  P = P-tilde (or its transpose).
   int run(const double* rhs, double* x, aao_stats* stats) {
     const int64_t U = h_->U;
     const int m = h_->opts.restart;
+    const int side = h_->opts.side;
+    const bool left = side != AAO_SIDE_RIGHT, right = side != AAO_SIDE_LEFT;
+    TI* tY = reinterpret_cast<TI*>(h_->ws + h_->plan.outY);     // P^{-1} of a product with A
+    TI* pb = reinterpret_cast<TI*>(h_->ws + h_->plan.outPb);    // P^{-1} rhs
+    double* tr = V_ + (int64_t)m * U;   // true residual, in the basis slot no cycle start uses
     auto t0 = std::chrono::steady_clock::now();
     timed_ = !h_->no_alloc;
     for (int i = 0; i < 3 && timed_; ++i)
@@ -581,30 +593,62 @@ class Fgmres {
       stt.relres = 0.0;
       return e == hipSuccess ? AAO_OK : status_from_hip(h_, e, "solve");
     }
+    if (left && (e = precond(rhs, pb)) != hipSuccess) return status_from_hip(h_, e, "solve");
     int its = 0;
     int status = AAO_NOT_CONVERGED;
+    double beta0 = -1.0;   // the first cycle's residual norm (LEFT / SPLIT stopping reference)
     std::vector<double> R((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m), hcol;
     while (true) {
-      // r = rhs - A x
-      if ((e = op<double>(x, w_)) != hipSuccess) break;
-      if ((e = launch_sub_from(rhs, w_, U, st_)) != hipSuccess) break;
-      double b2;
-      if ((e = norm2(w_, &b2)) != hipSuccess) break;
-      const double beta = std::sqrt(b2);
-      stt.relres = beta / nb;
-      if (!std::isfinite(beta)) { status = AAO_NONFINITE; break; }
-      if (stt.relres <= h_->opts.tol) { status = AAO_OK; break; }
+      // true residual rhs - A x, and the cycle's starting residual
+      if ((e = op<double>(x, tr)) != hipSuccess) break;
+      double ax2 = 0.0;
+      if (left && (e = norm2(tr, &ax2)) != hipSuccess) break;
+      if ((e = launch_sub_from(rhs, tr, U, st_)) != hipSuccess) break;
+      double t2;
+      if ((e = norm2(tr, &t2)) != hipSuccess) break;
+      stt.relres = std::sqrt(t2) / nb;
+      if (!std::isfinite(stt.relres)) { status = AAO_NONFINITE; break; }
+      double beta;
+      if (!left) {
+        if ((e = launch_copy_cast<double, double>(w_, tr, U, st_)) != hipSuccess) break;
+        beta = std::sqrt(t2);
+      } else {
+        // r0 = P^{-1} rhs - P^{-1} (A x); A x = rhs - tr (zero for x = 0)
+        if (ax2 > 0.0) {
+          if ((e = launch_diff<double, double>(w_, rhs, tr, U, st_)) != hipSuccess) break;
+          if ((e = precond(w_, tY)) != hipSuccess) break;
+          if ((e = launch_diff<double, TI>(w_, pb, tY, U, st_)) != hipSuccess) break;
+        } else {
+          if ((e = launch_diff<double, TI>(w_, pb, nullptr, U, st_)) != hipSuccess) break;
+        }
+        double b2;
+        if ((e = norm2(w_, &b2)) != hipSuccess) break;
+        beta = std::sqrt(b2);
+        if (!std::isfinite(beta)) { status = AAO_NONFINITE; break; }
+      }
+      if (beta0 < 0.0) beta0 = left ? beta : nb;
+      if (left ? beta <= h_->opts.tol * beta0 : stt.relres <= h_->opts.tol) { status = AAO_OK; break; }
+      if (!(beta > 0.0)) { status = AAO_OK; break; }
       if (its >= h_->opts.maxit) { status = AAO_NOT_CONVERGED; break; }
       stt.restarts++;
       if ((e = launch_scale<double, double>(V_, w_, 1.0 / beta, U, st_)) != hipSuccess) break;
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = beta;
       int mm = 0;
-      bool stop = false;
+      bool stop = false, ls_met = false;
       for (int j = 0; j < m && !stop; ++j) {
         its++;
-        if ((e = precond(V_ + (int64_t)j * U, Z_ + (int64_t)j * U)) != hipSuccess) break;
-        if ((e = op<TI>(Z_ + (int64_t)j * U, w_)) != hipSuccess) break;
+        double* vj = V_ + (int64_t)j * U;
+        if (right) {
+          if ((e = precond(vj, Z_ + (int64_t)j * U)) != hipSuccess) break;
+          if ((e = op<TI>(Z_ + (int64_t)j * U, w_)) != hipSuccess) break;
+        } else {
+          if ((e = op<double>(vj, w_)) != hipSuccess) break;
+        }
+        if (left) {
+          if ((e = precond(w_, tY)) != hipSuccess) break;
+          if ((e = launch_copy_cast<double, TI>(w_, tY, U, st_)) != hipSuccess) break;
+        }
         double h2sq, ww;
         if ((e = orthogonalize(j + 1, hcol, h2sq, ww)) != hipSuccess) break;
         phase_times();
@@ -634,14 +678,15 @@ class Fgmres {
         g[j + 1] = -sn[j] * g[j];
         g[j] = cs[j] * g[j];
         mm = j + 1;
-        const double est = std::fabs(g[j + 1]) / nb;
+        const double est = std::fabs(g[j + 1]) / beta0;
         if (stt.history_len < 128) stt.history[stt.history_len++] = est;
-        if (est <= h_->opts.tol || hn == 0.0 || its >= h_->opts.maxit) stop = true;
+        if (est <= h_->opts.tol) ls_met = true;
+        if (ls_met || hn == 0.0 || its >= h_->opts.maxit) stop = true;
         if (!stop && j + 1 < m)
           if ((e = next_basis(j + 1, 1.0 / hn, corrected)) != hipSuccess) break;
       }
       if (e != hipSuccess || status == AAO_NONFINITE) break;
-      // x += Z y
+      // x += Z y (right, split) or V y (left)
       for (int i = mm - 1; i >= 0; --i) {
         double acc = g[i];
         for (int jj = i + 1; jj < mm; ++jj) acc -= R[(size_t)jj * (m + 1) + i] * y[jj];
@@ -654,15 +699,29 @@ class Fgmres {
         for (int i = 0; i < mm; ++i) hp[i] = y[i];
         if ((e = hipMemcpyAsync(ydev, hp, sizeof(double) * mm, hipMemcpyHostToDevice, st_)) != hipSuccess)
           break;
-        for (int c0 = 0; c0 < mm; c0 += DOTS_PER_PASS) {
+        for (int c0 = 0; c0 < mm && e == hipSuccess; c0 += DOTS_PER_PASS) {
           const int cnt = std::min(DOTS_PER_PASS, mm - c0);
-          if ((e = combine<double, TI>(x, 0, Z_ + (int64_t)c0 * U, U, 0, cnt, oslots_, 0, YOFF + c0, false, true, U, 1,
-                                       st_)) != hipSuccess)
-            break;
+          if (right)
+            e = combine<double, TI>(x, 0, Z_ + (int64_t)c0 * U, U, 0, cnt, oslots_, 0, YOFF + c0, false, true, U, 1,
+                                    st_);
+          else
+            e = combine<double, double>(x, 0, V_ + (int64_t)c0 * U, U, 0, cnt, oslots_, 0, YOFF + c0, false, true,
+                                        U, 1, st_);
         }
         if (e != hipSuccess) break;
         // the host buffer is reused by the next iteration: wait for the copy
         if ((e = hipStreamSynchronize(st_)) != hipSuccess) break;
+      }
+      if (left && ls_met) {
+        // Algorithm 1 ends here: the least-squares residual of the
+        // preconditioned system met the target; report the true residual
+        if ((e = op<double>(x, tr)) != hipSuccess) break;
+        if ((e = launch_sub_from(rhs, tr, U, st_)) != hipSuccess) break;
+        double t2;
+        if ((e = norm2(tr, &t2)) != hipSuccess) break;
+        stt.relres = std::sqrt(t2) / nb;
+        status = AAO_OK;
+        break;
       }
     }
     if (e == hipSuccess) {
