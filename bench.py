@@ -68,11 +68,17 @@ def parse():
     ap.add_argument("--roofline-reps", type=int, default=20)
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the roofline launches (V-cycle kernels, apply_A, a 1 GiB copy); for counter runs")
+    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "ROOFLINE_JSON"),
+                    help="print the counter summary of the dominant kernel from two --roofline-only counter runs "
+                         "(FETCH_SIZE, WRITE_SIZE counter_collection CSVs) and that run's JSON; needs no GPU")
     return ap.parse_args()
 
 
 def main():
     args = parse()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the all-at-once solve "
                           "is measured at its single-GPU shape (time slabs per GPU would be the "
@@ -172,10 +178,11 @@ def main():
     # ---- rooflines (live, HIP events on the launch stream) -------------------
     prof = vcycle_kernels(hp_mix, args.mixed, args.roofline_reps)
     dom = prof["dominant"]
-    roofline = {k: v for k, v in prof["by_kernel"][dom].items() if k != "launches"}
+    roofline = {k: v for k, v in prof["by_kernel"][dom].items() if k not in ("launches", "members")}
     roofline["kernel"] = dom
-    roofline["traffic"] = measured_traffic(dom.split("<")[0], w, args.mixed)
+    roofline["traffic"] = measured_traffic(traffic_key(dom), w, args.mixed)
     apply_a = measure_apply_A(hp_mix, x_mix, args.roofline_reps)
+    apply_a["traffic"] = measured_traffic(apply_a["kernel"], w, args.mixed)
     vc64 = prof["kernels"]["vcycle"][str(w.nt)]
 
     # ---- CPU oracle baseline and the forward error ---------------------------
@@ -262,6 +269,25 @@ def vcycle_kernels(hp, precision, reps):
             return 2 * pl[lev] * nodes[lev]
         return None
 
+    tall_min = hp.tune_state["tall_min_b"] if hp.tune_state else 8
+    side = [int(round(v ** (1.0 / hp.dim))) for v in nodes]
+
+    def grid_workgroups(label, B):
+        """Workgroups of one launch (what a counter run reports per dispatch):
+        the 2D tiled level kernels cover the coarse level in tiles of 16 x 8
+        (short) or 16 x 16 (tall) coarse nodes, 256 threads each, per block;
+        the tail runs one workgroup per block."""
+        name, lev = label.split("@")
+        if hp.dim != 2:
+            return None
+        if name in ("k_down2d", "k_up2d"):
+            nc = side[int(lev) + 1]
+            ty = 16 if (precision != "fp64" and B >= tall_min) else 8
+            return -(-nc // 16) * -(-nc // ty) * B
+        if name in ("k_tail_fast", "k_tail"):
+            return B
+        return None
+
     kernels, totals = {"vcycle": {}}, {}
     for B in counts:
         launches, total_us = hp.profile_vcycle(count=B, stage=0, reps=reps)
@@ -285,8 +311,6 @@ def vcycle_kernels(hp, precision, reps):
     # group the launches by compiled kernel (what a kernel trace reports):
     # level 0 and the coarse levels are different instantiations, and so are
     # the short and tall tiles of the tiled kernels
-    tall_min = hp.tune_state["tall_min_b"] if hp.tune_state else 8
-
     def symbol(label, B):
         name, lev = label.split("@")
         sym = name + ("<level 0" if lev == "0" else "<coarse levels")
@@ -301,7 +325,11 @@ def vcycle_kernels(hp, precision, reps):
         for b, e in per_b.items():
             B = int(b)
             g = groups.setdefault(symbol(label, B), {"launches": 0.0, "us": 0.0, "alone": 0.0, "bytes": 0.0,
-                                                     "labels": set()})
+                                                     "labels": set(), "members": []})
+            if weight.get(B, 0):
+                g["members"].append({"label": label, "blocks": B, "weight": weight[B],
+                                     "workgroups": grid_workgroups(label, B),
+                                     "bytes_per_launch": e.get("bytes_per_launch")})
             g["launches"] += weight.get(B, 0)
             g["us"] += weight.get(B, 0) * e["avg_launch_us"]
             g["alone"] += weight.get(B, 0) * e["alone_us"]
@@ -322,7 +350,8 @@ def vcycle_kernels(hp, precision, reps):
                       "in_situ_us": g["us"] / g["launches"],
                       "bytes_per_launch": g["bytes"] / g["launches"], "achieved": gbs,
                       "frac": gbs / HBM_PEAK_GBS, "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "share_of_vcycle_time": g["alone"] / all_us, "launches": sorted(g["labels"])}
+                      "share_of_vcycle_time": g["alone"] / all_us, "launches": sorted(g["labels"]),
+                      "members": g["members"]}
     dom = max(table, key=lambda k: table[k]["share_of_vcycle_time"])
     return {"kernels": kernels, "weights": {str(b): weight.get(b, 0) for b in counts},
             "by_kernel": table, "dominant": dom}
@@ -338,6 +367,104 @@ def measure_apply_A(hp, x, reps):
     return {"kernel": "k_apply_A_2d" if hp.dim == 2 else "k_apply_A", "bound": "hbm", "achieved": gbs,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
             "bytes_per_launch": nbytes, "avg_launch_us": sec * 1e6}
+
+
+def traffic_key(symbol):
+    """The kernel group's name in the counter summary (no spaces)."""
+    return symbol.replace(" ", "")
+
+
+def _counter_rows(path, counter):
+    """(kernel name, workgroups, value in KiB) per dispatch of a rocprofv3
+    counter_collection CSV."""
+    import csv
+    out = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") != counter:
+                continue
+            wg = int(r.get("Workgroup_Size") or 1) or 1
+            out.append((r["Kernel_Name"], int(r["Grid_Size"]) // wg, float(r["Counter_Value"])))
+    return out
+
+
+def _kernel_matches(name, base, level0):
+    """name is an instantiation of the multigrid kernel `base` for level 0
+    (first template argument 0 or 1: the fine-grid kinds) or for the coarse
+    levels (2 or 3: tensor or stored-stencil Galerkin operators)."""
+    i = name.find(base + "<")
+    if i < 0:
+        return False
+    kind = int(name[i + len(base) + 1:].split(",")[0])
+    return (kind <= 1) == level0
+
+
+def traffic_summary(fetch_csv, write_csv, roof_json):
+    """Markdown summary of the HBM traffic of the dominant kernel group from
+    two counter runs of `bench.py --roofline-only` (FETCH_SIZE, WRITE_SIZE),
+    scaled by what the counters read for the 1 GiB copy in the same runs."""
+    import statistics
+    roof = json.loads([ln for ln in open(roof_json) if ln.startswith("{")][-1])
+    prof = roof["vcycle_kernels"]
+    dom = prof["dominant"]
+    grp = prof["by_kernel"][dom]
+    fetch, write = _counter_rows(fetch_csv, "FETCH_SIZE"), _counter_rows(write_csv, "WRITE_SIZE")
+    nbytes = roof["copy_reference"]["bytes"]
+
+    def copy_kib(rows):
+        vals = [v for name, wg, v in rows if "copyBuffer" in name]
+        if not vals:
+            raise SystemExit("no copy dispatch in the counter run")
+        return max(vals)
+
+    f_scale = nbytes / 1024 / copy_kib(fetch)
+    w_scale = nbytes / 1024 / copy_kib(write)
+    lines = [f"copy reference: {nbytes:,} B read and written; FETCH_SIZE reads {copy_kib(fetch):,.0f} KiB "
+             f"(scale {f_scale:.3f}), WRITE_SIZE {copy_kib(write):,.0f} KiB (scale {w_scale:.3f})", "",
+             "| launch | blocks | workgroups | launches per P-tilde | FETCH_SIZE KiB | WRITE_SIZE KiB "
+             "| scaled bytes | algorithmic bytes | ratio |", "|---|---|---|---|---|---|---|---|---|"]
+    base = dom.split("<")[0]
+    level0 = "<level 0" in dom
+    tot_w = tot_meas = tot_alg = 0.0
+    for m in grp["members"]:
+        if m["workgroups"] is None:
+            raise SystemExit(f"no grid size known for {m['label']}")
+        fv = [v for name, wg, v in fetch if wg == m["workgroups"] and _kernel_matches(name, base, level0)]
+        wv = [v for name, wg, v in write if wg == m["workgroups"] and _kernel_matches(name, base, level0)]
+        if not fv or not wv:
+            raise SystemExit(f"no dispatch of {base} with {m['workgroups']} workgroups")
+        fk, wk = statistics.median(fv), statistics.median(wv)
+        meas = fk * 1024 * f_scale + wk * 1024 * w_scale
+        alg = m["bytes_per_launch"]
+        lines.append(f"| `{m['label']}` | {m['blocks']} | {m['workgroups']} | {m['weight']:g} | {fk:,.0f} | "
+                     f"{wk:,.0f} | {meas:,.0f} | {alg:,.0f} | {meas / alg:.3f} |")
+        tot_w += m["weight"]
+        tot_meas += m["weight"] * meas
+        tot_alg += m["weight"] * alg
+    per_launch = tot_meas / tot_w
+    lines += ["", f"{dom}: {per_launch:,.0f} B per launch measured, {tot_alg / tot_w:,.0f} B algorithmic "
+              f"(launches weighted by their count per P-tilde application; ratio {tot_meas / tot_alg:.3f})", ""]
+    # apply_A, the secondary roofline, from the same runs
+    ka = roof["apply_A"]["kernel"]
+    fa = [v for name, wg, v in fetch if f"{ka}<" in name]
+    wa = [v for name, wg, v in write if f"{ka}<" in name]
+    if not fa or not wa:
+        raise SystemExit(f"no dispatch of {ka}")
+    fk, wk = statistics.median(fa), statistics.median(wa)
+    meas_a = fk * 1024 * f_scale + wk * 1024 * w_scale
+    alg_a = roof["apply_A"]["bytes_per_launch"]
+    lines += [f"{ka}: FETCH_SIZE {fk:,.0f} KiB, WRITE_SIZE {wk:,.0f} KiB per launch (median of {len(fa)}); "
+              f"{meas_a:,.0f} B measured, {alg_a:,.0f} B algorithmic (ratio {meas_a / alg_a:.3f})", ""]
+    import hashlib
+
+    def sha(src):
+        return hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+
+    src = "paper_2609_16863_amd/csrc/kern_mg.hip"
+    lines.append(f"traffic {traffic_key(dom)} source={src} sha256={sha(src)} bytes_per_launch={per_launch:.0f}")
+    src = "paper_2609_16863_amd/csrc/kern_allatonce.hip"
+    lines.append(f"traffic {ka} source={src} sha256={sha(src)} bytes_per_launch={meas_a:.0f}")
+    print("\n".join(lines))
 
 
 def measured_traffic(kernel, w, precision):
