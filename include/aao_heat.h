@@ -76,6 +76,19 @@ typedef enum aao_schur {
 
 /* Where P-tilde enters the outer FGMRES (Algorithm 1 of Sec. 4: P_L on the
  * left, P_R on the right). */
+/* Precision of the outer solve (Algorithm 1's u and u_A). */
+typedef enum aao_outer {
+  AAO_OUTER_FP64 = 0,      /* the system solved in FP64 (approaches A1/A2/A5)  */
+  AAO_OUTER_FP32 = 1       /* approach A3 of Sec. 5: the system solved in single
+                              precision, simulated as the paper simulates its
+                              lower precisions: the result of every outer step
+                              (products with A, residuals, basis vectors, the
+                              iterate) is rounded to FP32; stats.relres stays
+                              the FP64 true residual.  A negative control: the
+                              true residual stalls near FP32's unit roundoff
+                              times the problem's conditioning               */
+} aao_outer;
+
 typedef enum aao_side {
   AAO_SIDE_RIGHT = 0,      /* P_L = I, P_R = P-tilde (the sequential runs)      */
   AAO_SIDE_LEFT = 1,       /* P_L = P-tilde, P_R = I (the parallel runs)        */
@@ -136,6 +149,7 @@ typedef struct aao_opts {
                               is); stats.relres reports the true residual,
                               which P-tilde's nonlinearity (inner GMRES) can
                               leave larger                                     */
+  int outer_precision;     /* aao_outer                                        */
 } aao_opts;
 
 /* Solve statistics (host struct filled by aao_solve*). */
@@ -164,7 +178,7 @@ typedef struct aao_problem aao_problem;   /* opaque handle */
 /* Defaults: restart 30, maxit 100, tol 1e-8, inner_k 3, cycles 1,
  * nu1 = nu2 = 2, omega 0, precision FP64, use_graph 1, mg_tail_max 0,
  * coarse_max 0, inner_tol 0, schur AAO_SCHUR_SWEEP, mgrit_cf 8,
- * mgrit_iters 1, mgrit_fcf 0.  With use_graph the
+ * mgrit_iters 1, mgrit_fcf 0, side RIGHT, outer_precision FP64.  With use_graph the
  * first application of P-tilde for a given (inner_k, cycles, transpose) is
  * captured into a HIP graph on a private stream and later applications
  * replay it on the handle's stream (inputs and outputs pass through fixed

@@ -15,6 +15,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "HIP_ERROR",
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
 SCHUR = {"sweep": 0, "mgrit": 1}
 SIDES = {"right": 0, "left": 1, "split": 2}
+OUTER = {"fp64": 0, "fp32": 1}
 
 
 class Desc(ctypes.Structure):
@@ -27,7 +28,8 @@ class Opts(ctypes.Structure):
                 ("cycles", c_int), ("nu1", c_int), ("nu2", c_int), ("omega", c_double),
                 ("precision", c_int), ("use_graph", c_int), ("mg_tail_max", c_int), ("coarse_max", c_int),
                 ("inner_tol", c_double), ("schur", c_int), ("mgrit_cf", c_int), ("mgrit_iters", c_int),
-                ("mgrit_fcf", c_int), ("side", c_int)]
+                ("mgrit_fcf", c_int), ("side", c_int),
+                ("outer_precision", c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -22,24 +22,38 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _make_opts(lib, *, restart, maxit, tol, inner_k, cycles, nu1, nu2, omega, precision, use_graph,
-               mg_tail_max, coarse_max=0, inner_tol=0.0, schur="sweep", mgrit_cf=8, mgrit_iters=1,
-               mgrit_fcf=False, side="right"):
+# Solver options of aao_opts (include/aao_heat.h) with the library's defaults
+# where the binding does not choose its own.
+SOLVER_DEFAULTS = dict(restart=30, maxit=100, tol=1e-8, inner_k=3, cycles=1, nu1=2, nu2=2, omega=0.0,
+                       precision="fp64", use_graph=True, mg_tail_max=0, coarse_max=0, inner_tol=0.0,
+                       schur="sweep", mgrit_cf=8, mgrit_iters=1, mgrit_fcf=False, side="right",
+                       outer_precision="fp64")
+
+
+def _solver_options(kw):
+    unknown = sorted(set(kw) - set(SOLVER_DEFAULTS))
+    if unknown:
+        raise TypeError(f"unknown solver option(s): {', '.join(unknown)}")
+    return dict(SOLVER_DEFAULTS, **kw)
+
+
+def _make_opts(lib, o):
     opts = _abi.Opts()
     lib.aao_default_opts(ctypes.byref(opts))
-    opts.restart, opts.maxit, opts.tol = restart, maxit, tol
-    opts.inner_k, opts.cycles, opts.nu1, opts.nu2 = inner_k, cycles, nu1, nu2
-    opts.omega = omega
-    opts.precision = _abi.PRECISIONS[precision]
-    opts.use_graph = int(bool(use_graph))
-    opts.mg_tail_max = int(mg_tail_max)
-    opts.coarse_max = int(coarse_max)
-    opts.inner_tol = float(inner_tol)
-    opts.schur = _abi.SCHUR[schur]
-    opts.mgrit_cf = int(mgrit_cf)
-    opts.mgrit_iters = int(mgrit_iters)
-    opts.mgrit_fcf = int(bool(mgrit_fcf))
-    opts.side = _abi.SIDES[side]
+    opts.restart, opts.maxit, opts.tol = o["restart"], o["maxit"], o["tol"]
+    opts.inner_k, opts.cycles, opts.nu1, opts.nu2 = o["inner_k"], o["cycles"], o["nu1"], o["nu2"]
+    opts.omega = o["omega"]
+    opts.precision = _abi.PRECISIONS[o["precision"]]
+    opts.use_graph = int(bool(o["use_graph"]))
+    opts.mg_tail_max = int(o["mg_tail_max"])
+    opts.coarse_max = int(o["coarse_max"])
+    opts.inner_tol = float(o["inner_tol"])
+    opts.schur = _abi.SCHUR[o["schur"]]
+    opts.mgrit_cf = int(o["mgrit_cf"])
+    opts.mgrit_iters = int(o["mgrit_iters"])
+    opts.mgrit_fcf = int(bool(o["mgrit_fcf"]))
+    opts.side = _abi.SIDES[o["side"]]
+    opts.outer_precision = _abi.OUTER[o["outer_precision"]]
     return opts
 
 
@@ -67,27 +81,23 @@ class HeatProblem:
     ``inner_k`` iterations).  ``schur`` = "sweep" applies S-tilde^{-1} by
     forward substitution in time, "mgrit" by two-level MGRIT with
     coarsening factor ``mgrit_cf``, ``mgrit_iters`` iterations and F- (or,
-    with ``mgrit_fcf``, FCF-) relaxation.
+    with ``mgrit_fcf``, FCF-) relaxation.  ``side`` places P-tilde on the
+    "right", "left" or both ("split") sides of Algorithm 1;
+    ``outer_precision`` = "fp32" runs the outer solve in simulated single
+    precision (approach A3).  All solver options and their defaults are in
+    SOLVER_DEFAULTS.
     """
 
-    def __init__(self, dim, n, s, nt, T=1.0, kappa=None, *, restart=30, maxit=100, tol=1e-8,
-                 inner_k=3, cycles=1, nu1=2, nu2=2, omega=0.0, precision="fp64", use_graph=True,
-                 mg_tail_max=0, coarse_max=0, inner_tol=0.0, schur="sweep", mgrit_cf=8, mgrit_iters=1,
-                 mgrit_fcf=False, side="right", device="cuda"):
+    def __init__(self, dim, n, s, nt, T=1.0, kappa=None, *, device="cuda", **solver):
         self._lib = _abi.load()
         self.dim, self.n, self.s, self.nt, self.T = dim, n, s, nt, float(T)
         self._kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
         desc = _abi.Desc(dim, n, s, nt, float(T),
                          None if self._kappa is None else self._kappa.ctypes.data)
-        self.options = dict(restart=restart, maxit=maxit, tol=tol, inner_k=inner_k, cycles=cycles, nu1=nu1,
-                            nu2=nu2, omega=omega, precision=precision, use_graph=use_graph,
-                            mg_tail_max=mg_tail_max, coarse_max=coarse_max, inner_tol=inner_tol,
-                            schur=schur, mgrit_cf=mgrit_cf, mgrit_iters=mgrit_iters, mgrit_fcf=mgrit_fcf,
-                            side=side, device=device)
-        opts = _make_opts(self._lib, restart=restart, maxit=maxit, tol=tol, inner_k=inner_k, cycles=cycles,
-                          nu1=nu1, nu2=nu2, omega=omega, precision=precision, use_graph=use_graph,
-                          mg_tail_max=mg_tail_max, coarse_max=coarse_max, inner_tol=inner_tol, schur=schur,
-                          mgrit_cf=mgrit_cf, mgrit_iters=mgrit_iters, mgrit_fcf=mgrit_fcf, side=side)
+        o = _solver_options(solver)
+        self.options = dict(o, device=device)
+        opts = _make_opts(self._lib, o)
+        precision = o["precision"]
         self.precision = precision
         h = ctypes.c_void_p()
         code = self._lib.aao_create_problem(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h))
@@ -297,9 +307,7 @@ class HeatBatch:
     Solver keyword options are those of HeatProblem.
     """
 
-    def __init__(self, problems, *, streams=4, restart=30, maxit=100, tol=1e-8, inner_k=3, cycles=1,
-                 nu1=2, nu2=2, omega=0.0, precision="fp64", use_graph=True, mg_tail_max=0, coarse_max=0,
-                 inner_tol=0.0, schur="sweep", mgrit_cf=8, mgrit_iters=1, mgrit_fcf=False, device="cuda"):
+    def __init__(self, problems, *, streams=4, device="cuda", **solver):
         self._lib = _abi.load()
         self.count = len(problems)
         self._kappas = []
@@ -311,11 +319,10 @@ class HeatBatch:
             descs[i] = _abi.Desc(p["dim"], p["n"], p["s"], p["nt"], float(p.get("T", 1.0)),
                                  None if k is None else k.ctypes.data)
         self.problems = [dict(p) for p in problems]
-        self.tol = tol
-        opts = _make_opts(self._lib, restart=restart, maxit=maxit, tol=tol, inner_k=inner_k, cycles=cycles,
-                          nu1=nu1, nu2=nu2, omega=omega, precision=precision, use_graph=use_graph,
-                          mg_tail_max=mg_tail_max, coarse_max=coarse_max, inner_tol=inner_tol, schur=schur,
-                          mgrit_cf=mgrit_cf, mgrit_iters=mgrit_iters, mgrit_fcf=mgrit_fcf)
+        o = _solver_options(solver)
+        self.options = dict(o, device=device)
+        self.tol = o["tol"]
+        opts = _make_opts(self._lib, o)
         h = ctypes.c_void_p()
         code = self._lib.aao_create_batch(descs, self.count, ctypes.byref(opts), int(streams), ctypes.byref(h))
         if code != 0:

@@ -157,6 +157,10 @@ bool valid_opts(const aao_opts* o, std::string& why) {
   if (o->mgrit_iters < 0) { why = "mgrit_iters must be >= 0"; return false; }
   if (o->mgrit_fcf != 0 && o->mgrit_fcf != 1) { why = "mgrit_fcf must be 0 or 1"; return false; }
   if (o->side < AAO_SIDE_RIGHT || o->side > AAO_SIDE_SPLIT) { why = "unknown side"; return false; }
+  if (o->outer_precision != AAO_OUTER_FP64 && o->outer_precision != AAO_OUTER_FP32) {
+    why = "unknown outer_precision";
+    return false;
+  }
   return true;
 }
 
@@ -226,6 +230,7 @@ void aao_default_opts(aao_opts* o) {
   o->mgrit_iters = 1;
   o->mgrit_fcf = 0;
   o->side = AAO_SIDE_RIGHT;
+  o->outer_precision = AAO_OUTER_FP64;
 }
 
 int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) {

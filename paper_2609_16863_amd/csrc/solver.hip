@@ -567,6 +567,10 @@ class Fgmres {
     const int m = h_->opts.restart;
     const int side = h_->opts.side;
     const bool left = side != AAO_SIDE_RIGHT, right = side != AAO_SIDE_LEFT;
+    // approach A3: u = u_A = FP32, simulated by rounding every outer step's
+    // result (a no-op in FP64)
+    const bool chop = h_->opts.outer_precision == AAO_OUTER_FP32;
+    auto rnd = [&](double* v) { return chop ? launch_round_f32(v, U, st_) : hipSuccess; };
     TI* tY = reinterpret_cast<TI*>(h_->ws + h_->plan.outY);     // P^{-1} of a product with A
     TI* pb = reinterpret_cast<TI*>(h_->ws + h_->plan.outPb);    // P^{-1} rhs
     double* tr = V_ + (int64_t)m * U;   // true residual, in the basis slot no cycle start uses
@@ -610,17 +614,30 @@ class Fgmres {
       if (!std::isfinite(stt.relres)) { status = AAO_NONFINITE; break; }
       double beta;
       if (!left) {
-        if ((e = launch_copy_cast<double, double>(w_, tr, U, st_)) != hipSuccess) break;
-        beta = std::sqrt(t2);
+        if (!chop) {
+          if ((e = launch_copy_cast<double, double>(w_, tr, U, st_)) != hipSuccess) break;
+          beta = std::sqrt(t2);
+        } else {
+          // r0 = fl(rhs - fl(A x)) with fl the rounding to FP32
+          if ((e = op<double>(x, w_)) != hipSuccess || (e = rnd(w_)) != hipSuccess) break;
+          if ((e = launch_sub_from(rhs, w_, U, st_)) != hipSuccess) break;
+          if ((e = rnd(w_)) != hipSuccess) break;
+          double b2;
+          if ((e = norm2(w_, &b2)) != hipSuccess) break;
+          beta = std::sqrt(b2);
+          if (!std::isfinite(beta)) { status = AAO_NONFINITE; break; }
+        }
       } else {
         // r0 = P^{-1} rhs - P^{-1} (A x); A x = rhs - tr (zero for x = 0)
         if (ax2 > 0.0) {
           if ((e = launch_diff<double, double>(w_, rhs, tr, U, st_)) != hipSuccess) break;
+          if ((e = rnd(w_)) != hipSuccess) break;
           if ((e = precond(w_, tY)) != hipSuccess) break;
           if ((e = launch_diff<double, TI>(w_, pb, tY, U, st_)) != hipSuccess) break;
         } else {
           if ((e = launch_diff<double, TI>(w_, pb, nullptr, U, st_)) != hipSuccess) break;
         }
+        if ((e = rnd(w_)) != hipSuccess) break;
         double b2;
         if ((e = norm2(w_, &b2)) != hipSuccess) break;
         beta = std::sqrt(b2);
@@ -632,6 +649,7 @@ class Fgmres {
       if (its >= h_->opts.maxit) { status = AAO_NOT_CONVERGED; break; }
       stt.restarts++;
       if ((e = launch_scale<double, double>(V_, w_, 1.0 / beta, U, st_)) != hipSuccess) break;
+      if ((e = rnd(V_)) != hipSuccess) break;
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = beta;
       int mm = 0;
@@ -645,6 +663,7 @@ class Fgmres {
         } else {
           if ((e = op<double>(vj, w_)) != hipSuccess) break;
         }
+        if ((e = rnd(w_)) != hipSuccess) break;
         if (left) {
           if ((e = precond(w_, tY)) != hipSuccess) break;
           if ((e = launch_copy_cast<double, TI>(w_, tY, U, st_)) != hipSuccess) break;
@@ -682,8 +701,10 @@ class Fgmres {
         if (stt.history_len < 128) stt.history[stt.history_len++] = est;
         if (est <= h_->opts.tol) ls_met = true;
         if (ls_met || hn == 0.0 || its >= h_->opts.maxit) stop = true;
-        if (!stop && j + 1 < m)
+        if (!stop && j + 1 < m) {
           if ((e = next_basis(j + 1, 1.0 / hn, corrected)) != hipSuccess) break;
+          if ((e = rnd(V_ + (int64_t)(j + 1) * U)) != hipSuccess) break;
+        }
       }
       if (e != hipSuccess || status == AAO_NONFINITE) break;
       // x += Z y (right, split) or V y (left)
@@ -708,7 +729,7 @@ class Fgmres {
             e = combine<double, double>(x, 0, V_ + (int64_t)c0 * U, U, 0, cnt, oslots_, 0, YOFF + c0, false, true,
                                         U, 1, st_);
         }
-        if (e != hipSuccess) break;
+        if (e != hipSuccess || (e = rnd(x)) != hipSuccess) break;
         // the host buffer is reused by the next iteration: wait for the copy
         if ((e = hipStreamSynchronize(st_)) != hipSuccess) break;
       }

@@ -80,7 +80,8 @@ def test_sizes_and_workspace():
 
 
 @pytest.mark.parametrize("bad", [dict(dim=4), dict(n=1), dict(s=4), dict(nt=0), dict(T=-1.0),
-                                 dict(restart=0), dict(inner_k=13), dict(precision=7), dict(nu1=0)])
+                                 dict(restart=0), dict(inner_k=13), dict(precision=7), dict(nu1=0),
+                                 dict(side=3), dict(schur=2), dict(outer_precision=2)])
 def test_invalid_arguments_are_rejected(bad):
     abi, lib = _lib()
     desc_keys = {"dim", "n", "s", "nt", "T"}
@@ -198,3 +199,14 @@ def test_coarse_max_option():
     assert _create(abi, lib, dim=2, n=16, kappa=np.ones(256), coarse_max=512)[0] == -1
     assert _create(abi, lib, dim=2, n=16, coarse_max=2048)[0] == -1
     assert _create(abi, lib, dim=3, n=16, coarse_max=256)[0] == 0
+
+
+def test_binding_rejects_unknown_solver_options():
+    from paper_2609_16863_amd import binding
+    with pytest.raises(TypeError):
+        binding._solver_options({"outer_precison": "fp32"})
+    o = binding._solver_options({"outer_precision": "fp32"})
+    assert o["outer_precision"] == "fp32" and o["side"] == "right"
+    abi, lib = _lib()
+    opts = binding._make_opts(lib, o)
+    assert opts.outer_precision == 1 and opts.restart == 30
