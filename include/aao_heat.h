@@ -50,16 +50,22 @@ typedef enum aao_status {
   AAO_NO_WORKSPACE = -5        /* a device call before aao_set_workspace      */
 } aao_status;
 
-/* Precision in which the preconditioner P-tilde is applied (Sec. 4,
- * approaches A1/A2/A5).  The system itself, the outer FGMRES and its
- * residuals are always FP64.  BF16/FP16 store the multigrid vectors of the
- * shifted-block solves in 16 bits with FP32 arithmetic; the inner GMRES,
- * Rana coupling and the S-tilde sweep then run in FP32. */
+/* Precision in which the preconditioner P-tilde is applied (Sec. 4;
+ * approaches A1/A2/A4/A5 of Sec. 5).  The outer FGMRES is FP64 unless
+ * opts.outer_precision says otherwise.  BF16/FP16 store the coarse
+ * multigrid levels of the shifted-block solves in 16 bits with FP32
+ * arithmetic; level 0, the inner GMRES, Rana coupling and S-tilde then run
+ * in FP32 (approach A5: P-tilde single, P-tilde_int half).  FP16_ALL is
+ * approach A4 (P-tilde and P-tilde_int in half precision): every vector
+ * P-tilde stores is FP16 -- inner GMRES bases and results, Theta-tilde and
+ * S-tilde results, all multigrid levels, the outer Z basis -- with FP32
+ * arithmetic and no scaling.  A negative control. */
 typedef enum aao_precision {
   AAO_PREC_FP64 = 0,
   AAO_PREC_FP32 = 1,
   AAO_PREC_BF16 = 2,
-  AAO_PREC_FP16 = 3
+  AAO_PREC_FP16 = 3,
+  AAO_PREC_FP16_ALL = 4
 } aao_precision;
 
 /* How S-tilde^{-1} of eq. (3.3) is applied inside P-tilde. */
@@ -253,7 +259,8 @@ int aao_apply_P_with(aao_problem* h, const double* r, double* z, int inner_k, in
  * nu2, omega; coarsening to at most 256 nodes, solved exactly).
  * r, z: device, count * N values each, block b at offset b * N, in the
  * preconditioner's working type: double for AAO_PREC_FP64, float for
- * FP32, BF16 and FP16 (the 16-bit formats are the coarse levels' storage).
+ * FP32, BF16 and FP16 (the 16-bit formats are the coarse levels' storage),
+ * FP16 (IEEE binary16) for FP16_ALL.
  * 1 <= count <= nt, 0 <= stage < s, 1 <= cycles <= 64; r and z must not
  * overlap.  Asynchronous on the handle's stream. */
 int aao_apply_mg(aao_problem* h, int transpose, int stage, int count, int cycles, const void* r, void* z);

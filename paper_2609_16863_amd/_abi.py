@@ -12,7 +12,7 @@ AAO_OK = 0
 AAO_NOT_CONVERGED = 1
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "HIP_ERROR", -3: "NONFINITE",
                 -4: "WORKSPACE_TOO_SMALL", -5: "NO_WORKSPACE"}
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "fp16_all": 4}
 SCHUR = {"sweep": 0, "mgrit": 1}
 SIDES = {"right": 0, "left": 1, "split": 2}
 OUTER = {"fp64": 0, "fp32": 1}

@@ -74,7 +74,8 @@ class HeatProblem:
     2D only).  Solver options: FGMRES ``restart``/``maxit``/``tol``, inner
     GMRES iterations ``inner_k``, V-cycles ``cycles`` with ``nu1``/``nu2``
     Jacobi sweeps, and the preconditioner ``precision``
-    ("fp64" | "fp32" | "bf16" | "fp16"); ``use_graph`` replays the
+    ("fp64" | "fp32" | "bf16" | "fp16" | "fp16_all", the last approach A4);
+    ``use_graph`` replays the
     preconditioner as a captured HIP graph; ``coarse_max`` is the size of the
     exactly solved coarsest multigrid level (0: 256 nodes); ``inner_tol`` stops
     an inner GMRES solve early at that relative residual (0: always
@@ -205,7 +206,7 @@ class HeatProblem:
 
     def working_dtype(self):
         """Element type of the preconditioner's vectors (apply_mg operands)."""
-        return torch.float64 if self.precision == "fp64" else torch.float32
+        return {"fp64": torch.float64, "fp16_all": torch.float16}.get(self.precision, torch.float32)
 
     def mg_levels(self):
         """(nodes per level, first level solved in one workgroup's LDS)."""

@@ -147,7 +147,7 @@ bool valid_opts(const aao_opts* o, std::string& why) {
   if (o->inner_k < 1 || o->inner_k > aao::KMAX) { why = "inner_k must be in [1, 12]"; return false; }
   if (o->cycles < 1 || o->cycles > 64) { why = "cycles must be in [1, 64]"; return false; }
   if (o->nu1 < 1 || o->nu2 < 1 || o->nu1 > 16 || o->nu2 > 16) { why = "nu1, nu2 must be in [1, 16]"; return false; }
-  if (o->precision < AAO_PREC_FP64 || o->precision > AAO_PREC_FP16) { why = "unknown precision"; return false; }
+  if (o->precision < AAO_PREC_FP64 || o->precision > AAO_PREC_FP16_ALL) { why = "unknown precision"; return false; }
   if (o->omega < 0.0 || o->omega >= 2.0) { why = "omega must be in [0, 2)"; return false; }
   if (o->mg_tail_max < 0) { why = "mg_tail_max must be >= 0"; return false; }
   if (o->coarse_max < 0 || o->coarse_max > aao::COARSE_FD_MAX) { why = "coarse_max must be in [0, 1024]"; return false; }
@@ -267,7 +267,7 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
   h->UV = h->N * (int64_t)d->nt * d->s;
   h->opts = opts;
   h->omega = opts.omega > 0.0 ? opts.omega : (d->dim == 2 ? 0.8 : 6.0 / 7.0);
-  h->pi_bytes = opts.precision == AAO_PREC_FP64 ? 8 : 4;
+  h->pi_bytes = opts.precision == AAO_PREC_FP64 ? 8 : (opts.precision == AAO_PREC_FP16_ALL ? 2 : 4);
   h->pm_bytes = opts.precision == AAO_PREC_FP64 ? 8 : (opts.precision == AAO_PREC_FP32 ? 4 : 2);
   // FP16 multigrid storage: the V-cycle's right-hand sides are unit-norm
   // Krylov vectors over s N entries, so their entries are near (s N)^{-1/2};

@@ -585,6 +585,15 @@ template hipError_t launch_apply_AT<double>(const aao_problem*, const double*, d
 template hipError_t launch_apply_AT<float>(const aao_problem*, const float*, double*, hipStream_t);
 template hipError_t launch_apply_A<double>(const aao_problem*, const double*, double*, hipStream_t);
 template hipError_t launch_apply_A<float>(const aao_problem*, const float*, double*, hipStream_t);
+template hipError_t launch_apply_A<__half>(const aao_problem*, const __half*, double*, hipStream_t);
+template hipError_t launch_apply_AT<__half>(const aao_problem*, const __half*, double*, hipStream_t);
+template hipError_t launch_copy_cast<double, __half>(double*, const __half*, int64_t, hipStream_t);
+template hipError_t launch_copy_cast<__half, double>(__half*, const double*, int64_t, hipStream_t);
+template hipError_t launch_copy_cast<__half, __half>(__half*, const __half*, int64_t, hipStream_t);
+template hipError_t launch_scale<__half, __half>(__half*, const __half*, double, int64_t, hipStream_t);
+template hipError_t launch_scale<__half, double>(__half*, const double*, double, int64_t, hipStream_t);
+template hipError_t launch_fill<__half>(__half*, __half, int64_t, hipStream_t);
+template hipError_t launch_diff<double, __half>(double*, const __half*, const __half*, int64_t, hipStream_t);
 template hipError_t launch_copy_cast<double, float>(double*, const float*, int64_t, hipStream_t);
 template hipError_t launch_copy_cast<float, double>(float*, const double*, int64_t, hipStream_t);
 template hipError_t launch_copy_cast<double, double>(double*, const double*, int64_t, hipStream_t);

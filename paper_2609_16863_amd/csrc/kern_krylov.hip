@@ -669,6 +669,17 @@ hipError_t thetaT_rhs(const aao_problem* h, const double* r, const T* z, T* out,
 
 AAO_INST_T(double)
 AAO_INST_T(float)
+AAO_INST_T(__half)
+template hipError_t phi_update<__half, double>(const aao_problem*, const Tab&, const double*, int64_t, const __half*,
+                                               int64_t, const __half*, int64_t, __half*, int64_t, int, hipStream_t);
+template hipError_t phiT_update<__half, double>(const aao_problem*, double, const double*, int64_t, const __half*,
+                                                int64_t, const __half*, int64_t, __half*, int64_t, int, hipStream_t);
+template hipError_t gs_pass<double, __half>(double*, const __half*, const GSArgs&, int, hipStream_t);
+template hipError_t basis_update<double, __half, __half>(const double*, int64_t, const __half*, int64_t, int64_t,
+                                                         int, __half*, int64_t, const double*, int64_t, int, int,
+                                                         double, int64_t, int, hipStream_t);
+template hipError_t combine<double, __half>(double*, int64_t, const __half*, int64_t, int64_t, int, const double*,
+                                            int64_t, int, bool, bool, int64_t, int, hipStream_t);
 template hipError_t phi_update<float, double>(const aao_problem*, const Tab&, const double*, int64_t, const float*,
                                               int64_t, const float*, int64_t, float*, int64_t, int, hipStream_t);
 template hipError_t phiT_update<float, double>(const aao_problem*, double, const double*, int64_t, const float*,

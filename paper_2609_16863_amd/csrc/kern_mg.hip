@@ -2024,5 +2024,6 @@ template class Multigrid<double, double>;
 template class Multigrid<float, float>;
 template class Multigrid<float, __half>;
 template class Multigrid<float, __hip_bfloat16>;
+template class Multigrid<__half, __half>;
 
 }  // namespace aao

@@ -313,6 +313,7 @@ hipError_t apply_P_any(aao_problem* h, const double* r, void* z, int k, int cycl
     case AAO_PREC_FP64: return apply_P_typed<double, double>(h, r, (double*)z, k, cycles, transpose, phase);
     case AAO_PREC_FP32: return apply_P_typed<float, float>(h, r, (float*)z, k, cycles, transpose, phase);
     case AAO_PREC_FP16: return apply_P_typed<float, __half>(h, r, (float*)z, k, cycles, transpose, phase);
+    case AAO_PREC_FP16_ALL: return apply_P_typed<__half, __half>(h, r, (__half*)z, k, cycles, transpose, phase);
     default: return apply_P_typed<float, __hip_bfloat16>(h, r, (float*)z, k, cycles, transpose, phase);
   }
 }
@@ -945,6 +946,8 @@ hipError_t profile_vcycle(aao_problem* h, int stage, int count, int reps, std::v
       return profile_vcycle_typed<float, float>(h, stage, count, reps, labels, us_situ, us_alone, total_us);
     case AAO_PREC_FP16:
       return profile_vcycle_typed<float, __half>(h, stage, count, reps, labels, us_situ, us_alone, total_us);
+    case AAO_PREC_FP16_ALL:
+      return profile_vcycle_typed<__half, __half>(h, stage, count, reps, labels, us_situ, us_alone, total_us);
     default:
       return profile_vcycle_typed<float, __hip_bfloat16>(h, stage, count, reps, labels, us_situ, us_alone, total_us);
   }
@@ -965,6 +968,7 @@ int mg_tail_level(aao_problem* h) {
     case AAO_PREC_FP64: return Multigrid<double, double>(h, h->stream, h->tab.L).tail_level();
     case AAO_PREC_FP32: return Multigrid<float, float>(h, h->stream, h->tab.L).tail_level();
     case AAO_PREC_FP16: return Multigrid<float, __half>(h, h->stream, h->tab.L).tail_level();
+    case AAO_PREC_FP16_ALL: return Multigrid<__half, __half>(h, h->stream, h->tab.L).tail_level();
     default: return Multigrid<float, __hip_bfloat16>(h, h->stream, h->tab.L).tail_level();
   }
 }
@@ -974,6 +978,7 @@ hipError_t apply_mg(aao_problem* h, bool transpose, int stage, int count, int cy
     case AAO_PREC_FP64: return apply_mg_typed<double, double>(h, transpose, stage, count, cycles, r, z);
     case AAO_PREC_FP32: return apply_mg_typed<float, float>(h, transpose, stage, count, cycles, r, z);
     case AAO_PREC_FP16: return apply_mg_typed<float, __half>(h, transpose, stage, count, cycles, r, z);
+    case AAO_PREC_FP16_ALL: return apply_mg_typed<__half, __half>(h, transpose, stage, count, cycles, r, z);
     default: return apply_mg_typed<float, __hip_bfloat16>(h, transpose, stage, count, cycles, r, z);
   }
 }
@@ -989,6 +994,10 @@ int apply_P(aao_problem* h, const double* r, double* z, int inner_k, int cycles,
   hipError_t e;
   if (h->opts.precision == AAO_PREC_FP64) {
     e = precond_apply(h, r, z, inner_k, cycles, transpose, false);
+  } else if (h->opts.precision == AAO_PREC_FP16_ALL) {
+    __half* zp = reinterpret_cast<__half*>(h->ws + h->plan.outY);
+    e = precond_apply(h, r, zp, inner_k, cycles, transpose, false);
+    if (e == hipSuccess) e = launch_copy_cast<double, __half>(z, zp, h->U, h->stream);
   } else {
     float* zp = reinterpret_cast<float*>(h->ws + h->plan.outY);
     e = precond_apply(h, r, zp, inner_k, cycles, transpose, false);
@@ -1000,6 +1009,10 @@ int apply_P(aao_problem* h, const double* r, double* z, int inner_k, int cycles,
 int solve(aao_problem* h, const double* rhs, double* x, aao_stats* st, bool transpose) {
   if (h->opts.precision == AAO_PREC_FP64) {
     Fgmres<double> F(h, transpose);
+    return F.run(rhs, x, st);
+  }
+  if (h->opts.precision == AAO_PREC_FP16_ALL) {
+    Fgmres<__half> F(h, transpose);
     return F.run(rhs, x, st);
   }
   Fgmres<float> F(h, transpose);
