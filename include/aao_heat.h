@@ -156,6 +156,17 @@ typedef struct aao_opts {
                               which P-tilde's nonlinearity (inner GMRES) can
                               leave larger                                     */
   int outer_precision;     /* aao_outer                                        */
+  int mg_low_from;         /* BF16/FP16 preconditioners: the first multigrid
+                              level stored in 16 bits; the levels above it stay
+                              FP32 (per-level decreasing precision, Sec. 4).
+                              0 = 1, every coarse level; a value beyond the last
+                              level keeps them all in FP32                     */
+  int mg_coarse_fp32;      /* 1: the coarse solve (2D: the one-workgroup tail
+                              and its exact coarsest solve; 3D: the exactly
+                              solved coarsest level) stays FP32 where
+                              mg_low_from puts the levels above it in 16 bits
+                              -- a coarse-solve precision apart from the
+                              smoother's (Sec. 4); 0 = no                      */
 } aao_opts;
 
 /* Solve statistics (host struct filled by aao_solve*). */
@@ -184,7 +195,8 @@ typedef struct aao_problem aao_problem;   /* opaque handle */
 /* Defaults: restart 30, maxit 100, tol 1e-8, inner_k 3, cycles 1,
  * nu1 = nu2 = 2, omega 0, precision FP64, use_graph 1, mg_tail_max 0,
  * coarse_max 0, inner_tol 0, schur AAO_SCHUR_SWEEP, mgrit_cf 8,
- * mgrit_iters 1, mgrit_fcf 0, side RIGHT, outer_precision FP64.  With use_graph the
+ * mgrit_iters 1, mgrit_fcf 0, side RIGHT, outer_precision FP64,
+ * mg_low_from 0, mg_coarse_fp32 0.  With use_graph the
  * first application of P-tilde for a given (inner_k, cycles, transpose) is
  * captured into a HIP graph on a private stream and later applications
  * replay it on the handle's stream (inputs and outputs pass through fixed

@@ -29,7 +29,7 @@ class Opts(ctypes.Structure):
                 ("precision", c_int), ("use_graph", c_int), ("mg_tail_max", c_int), ("coarse_max", c_int),
                 ("inner_tol", c_double), ("schur", c_int), ("mgrit_cf", c_int), ("mgrit_iters", c_int),
                 ("mgrit_fcf", c_int), ("side", c_int),
-                ("outer_precision", c_int)]
+                ("outer_precision", c_int), ("mg_low_from", c_int), ("mg_coarse_fp32", c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -27,7 +27,7 @@ def _ptr(t):
 SOLVER_DEFAULTS = dict(restart=30, maxit=100, tol=1e-8, inner_k=3, cycles=1, nu1=2, nu2=2, omega=0.0,
                        precision="fp64", use_graph=True, mg_tail_max=0, coarse_max=0, inner_tol=0.0,
                        schur="sweep", mgrit_cf=8, mgrit_iters=1, mgrit_fcf=False, side="right",
-                       outer_precision="fp64")
+                       outer_precision="fp64", mg_low_from=0, mg_coarse_fp32=False)
 
 
 def _solver_options(kw):
@@ -54,6 +54,8 @@ def _make_opts(lib, o):
     opts.mgrit_fcf = int(bool(o["mgrit_fcf"]))
     opts.side = _abi.SIDES[o["side"]]
     opts.outer_precision = _abi.OUTER[o["outer_precision"]]
+    opts.mg_low_from = int(o["mg_low_from"])
+    opts.mg_coarse_fp32 = int(bool(o["mg_coarse_fp32"]))
     return opts
 
 
@@ -85,8 +87,10 @@ class HeatProblem:
     with ``mgrit_fcf``, FCF-) relaxation.  ``side`` places P-tilde on the
     "right", "left" or both ("split") sides of Algorithm 1;
     ``outer_precision`` = "fp32" runs the outer solve in simulated single
-    precision (approach A3).  All solver options and their defaults are in
-    SOLVER_DEFAULTS.
+    precision (approach A3).  ``mg_low_from`` (first multigrid level in 16
+    bits) and ``mg_coarse_fp32`` (coarse solve kept FP32) set the V-cycle's
+    precision schedule for "bf16"/"fp16".  All solver options and their
+    defaults are in SOLVER_DEFAULTS.
     """
 
     def __init__(self, dim, n, s, nt, T=1.0, kappa=None, *, device="cuda", **solver):

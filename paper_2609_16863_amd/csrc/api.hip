@@ -69,8 +69,10 @@ void plan_workspace(aao_problem* h) {
   P.mgT.assign(L, 0);
   P.mgB.assign(L, 0);
   P.mgR.assign(L, 0);
+  // coarse levels the precision schedule may keep in the level-0 format
+  const bool sched = h->opts.mg_low_from > 1 || h->opts.mg_coarse_fp32;
   for (int l = 0; l < L; ++l) {
-    const size_t bytes = (size_t)h->nt * h->lev_N[l] * (l == 0 ? pi : pm);
+    const size_t bytes = (size_t)h->nt * h->lev_N[l] * (l == 0 || sched ? pi : pm);
     if (l > 0) {
       P.mgX[l] = take(bytes);
       P.mgB[l] = take(bytes);
@@ -161,6 +163,8 @@ bool valid_opts(const aao_opts* o, std::string& why) {
     why = "unknown outer_precision";
     return false;
   }
+  if (o->mg_low_from < 0) { why = "mg_low_from must be >= 0"; return false; }
+  if (o->mg_coarse_fp32 != 0 && o->mg_coarse_fp32 != 1) { why = "mg_coarse_fp32 must be 0 or 1"; return false; }
   return true;
 }
 
@@ -231,6 +235,8 @@ void aao_default_opts(aao_opts* o) {
   o->mgrit_fcf = 0;
   o->side = AAO_SIDE_RIGHT;
   o->outer_precision = AAO_OUTER_FP64;
+  o->mg_low_from = 0;
+  o->mg_coarse_fp32 = 0;
 }
 
 int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) {

@@ -8,6 +8,8 @@
 // l >= 1 is  M(x)M + a (T(x)M + M(x)T)  (3D: three-fold products) with 1D
 // tridiagonal factors M_l, T_l, so its 9/27 coefficients are formed in
 // registers from six short arrays instead of being streamed from HBM.
+#include <type_traits>
+
 #include "aao_internal.h"
 #include "krylov.h"
 #include "mg.h"
@@ -1566,6 +1568,7 @@ Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L, in
     // grid kernels and a pointwise exact solve on the one-node level.
     l0_ = levels_;
     tail_bytes_ = 0;
+    set_level_storage();
     return;
   }
   const size_t budget = h->lds_budget;
@@ -1611,6 +1614,46 @@ Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L, in
     for (int t = 0; t <= fast_nls_; ++t) ta.n[t] = h->lev_n[l0_ + t];
     fast_bytes_ = (size_t)tail_fast_layout<C>(ta, fast_nls_) * sizeof(C);
   }
+  set_level_storage();
+}
+
+// The precision schedule of the V-cycle (Sec. 4 cites per-level decreasing
+// precision and a coarse-solve precision apart from the smoother's): levels
+// from opts.mg_low_from on (default 1) are stored in TM, the ones above in
+// TI; with opts.mg_coarse_fp32 the coarse solve -- the one-workgroup tail
+// and its exact coarsest solve in 2D, the exactly solved coarsest level in
+// 3D -- keeps TI as well.  Level 0 is always TI.
+template <class TI, class TM>
+void Multigrid<TI, TM>::set_level_storage() {
+  low_.assign(levels_ + 1, 0);
+  if (std::is_same<TI, TM>::value) return;
+  const int from = h_->opts.mg_low_from > 0 ? h_->opts.mg_low_from : 1;
+  for (int l = 1; l < levels_; ++l) {
+    const bool coarse_solve = h_->dim == 2 ? l >= l0_ : l == levels_ - 1;
+    low_[l] = l >= from && !(h_->opts.mg_coarse_fp32 && coarse_solve);
+  }
+}
+
+template <class TI, class TM>
+template <class F>
+hipError_t Multigrid<TI, TM>::typed1(int l, F&& f) const {
+  if constexpr (std::is_same<TI, TM>::value) {
+    return f(TI{});
+  } else {
+    if (low(l)) return f(TM{});
+    return f(TI{});
+  }
+}
+
+template <class TI, class TM>
+template <class F>
+hipError_t Multigrid<TI, TM>::typed2(int l, F&& f) const {
+  if constexpr (std::is_same<TI, TM>::value) {
+    return f(TI{}, TI{});
+  } else {
+    if (low(l)) return low(l + 1) ? f(TM{}, TM{}) : f(TM{}, TI{});
+    return low(l + 1) ? f(TI{}, TM{}) : f(TI{}, TI{});
+  }
 }
 
 #define MG_TRY(...)                           \
@@ -1641,8 +1684,12 @@ hipError_t Multigrid<TI, TM>::smooth(int l, int stage, Vec xin, Vec xout, Vec b,
       else hipLaunchKernelGGL((k_smooth<2, KIND_FINE, TI, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (TI*)xout.ptr, xout.stride, (const TI*)b.ptr, b.stride, op, omega, (int)zero_init);
     }
   } else {
-    if (d3) hipLaunchKernelGGL((k_smooth<3, KIND_TENSOR, TM, C>), g, dim3(TPB), 0, st_, (const TM*)xin.ptr, xin.stride, (TM*)xout.ptr, xout.stride, (const TM*)b.ptr, b.stride, op, omega, (int)zero_init);
-    else hipLaunchKernelGGL((k_smooth<2, KIND_TENSOR, TM, C>), g, dim3(TPB), 0, st_, (const TM*)xin.ptr, xin.stride, (TM*)xout.ptr, xout.stride, (const TM*)b.ptr, b.stride, op, omega, (int)zero_init);
+    return typed1(l, [&](auto t) {
+      using TL = decltype(t);
+      if (d3) hipLaunchKernelGGL((k_smooth<3, KIND_TENSOR, TL, C>), g, dim3(TPB), 0, st_, (const TL*)xin.ptr, xin.stride, (TL*)xout.ptr, xout.stride, (const TL*)b.ptr, b.stride, op, omega, (int)zero_init);
+      else hipLaunchKernelGGL((k_smooth<2, KIND_TENSOR, TL, C>), g, dim3(TPB), 0, st_, (const TL*)xin.ptr, xin.stride, (TL*)xout.ptr, xout.stride, (const TL*)b.ptr, b.stride, op, omega, (int)zero_init);
+      return hipGetLastError();
+    });
   }
   return hipGetLastError();
 }
@@ -1656,15 +1703,22 @@ hipError_t Multigrid<TI, TM>::resid_restrict(int l, int stage, Vec x, Vec b, Vec
   const int d3 = h_->dim == 3, z = (int)zero_next;
   if (l == 0) {
     const C bs = (C)h_->mg_scale;
-#define RR0(D, K) hipLaunchKernelGGL((k_resid_restrict<D, K, TI, TM, C>), g, dim3(TPB), 0, st_, (const TI*)x.ptr, x.stride, (const TI*)b.ptr, b.stride, (TM*)bc.ptr, bc.stride, (TM*)xc.ptr, xc.stride, opf, opc, omega, z, bs)
-    if (h_->vark) { if (d3) RR0(3, KIND_FINE_VK); else RR0(2, KIND_FINE_VK); }
-    else { if (d3) RR0(3, KIND_FINE); else RR0(2, KIND_FINE); }
+    return typed1(1, [&](auto tc) {
+      using TC = decltype(tc);
+#define RR0(D, K) hipLaunchKernelGGL((k_resid_restrict<D, K, TI, TC, C>), g, dim3(TPB), 0, st_, (const TI*)x.ptr, x.stride, (const TI*)b.ptr, b.stride, (TC*)bc.ptr, bc.stride, (TC*)xc.ptr, xc.stride, opf, opc, omega, z, bs)
+      if (h_->vark) { if (d3) RR0(3, KIND_FINE_VK); else RR0(2, KIND_FINE_VK); }
+      else { if (d3) RR0(3, KIND_FINE); else RR0(2, KIND_FINE); }
 #undef RR0
-  } else {
-    if (d3) hipLaunchKernelGGL((k_resid_restrict<3, KIND_TENSOR, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)x.ptr, x.stride, (const TM*)b.ptr, b.stride, (TM*)bc.ptr, bc.stride, (TM*)xc.ptr, xc.stride, opf, opc, omega, z, C(1));
-    else hipLaunchKernelGGL((k_resid_restrict<2, KIND_TENSOR, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)x.ptr, x.stride, (const TM*)b.ptr, b.stride, (TM*)bc.ptr, bc.stride, (TM*)xc.ptr, xc.stride, opf, opc, omega, z, C(1));
+      return hipGetLastError();
+    });
   }
-  return hipGetLastError();
+  return typed2(l, [&](auto tf, auto tc) {
+    using TF = decltype(tf);
+    using TC = decltype(tc);
+    if (d3) hipLaunchKernelGGL((k_resid_restrict<3, KIND_TENSOR, TF, TC, C>), g, dim3(TPB), 0, st_, (const TF*)x.ptr, x.stride, (const TF*)b.ptr, b.stride, (TC*)bc.ptr, bc.stride, (TC*)xc.ptr, xc.stride, opf, opc, omega, z, C(1));
+    else hipLaunchKernelGGL((k_resid_restrict<2, KIND_TENSOR, TF, TC, C>), g, dim3(TPB), 0, st_, (const TF*)x.ptr, x.stride, (const TF*)b.ptr, b.stride, (TC*)bc.ptr, bc.stride, (TC*)xc.ptr, xc.stride, opf, opc, omega, z, C(1));
+    return hipGetLastError();
+  });
 }
 
 template <class TI, class TM>
@@ -1673,13 +1727,17 @@ hipError_t Multigrid<TI, TM>::prolong(int l, Vec xin, Vec ec, Vec xout, int B) {
   const int Nf = (int)h_->lev_N[l];
   const dim3 g = grid2(Nf, B);
   // only coarse grid levels use the separate prolongation (level 0 fuses it)
-  if (h_->dim == 2)
-    hipLaunchKernelGGL((k_prolong<2, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)xin.ptr, xin.stride,
-                       (const TM*)ec.ptr, ec.stride, (TM*)xout.ptr, xout.stride, nf, Nf, nc);
-  else
-    hipLaunchKernelGGL((k_prolong<3, TM, TM, C>), g, dim3(TPB), 0, st_, (const TM*)xin.ptr, xin.stride,
-                       (const TM*)ec.ptr, ec.stride, (TM*)xout.ptr, xout.stride, nf, Nf, nc);
-  return hipGetLastError();
+  return typed2(l, [&](auto tf, auto tc) {
+    using TF = decltype(tf);
+    using TC = decltype(tc);
+    if (h_->dim == 2)
+      hipLaunchKernelGGL((k_prolong<2, TF, TC, C>), g, dim3(TPB), 0, st_, (const TF*)xin.ptr, xin.stride,
+                         (const TC*)ec.ptr, ec.stride, (TF*)xout.ptr, xout.stride, nf, Nf, nc);
+    else
+      hipLaunchKernelGGL((k_prolong<3, TF, TC, C>), g, dim3(TPB), 0, st_, (const TF*)xin.ptr, xin.stride,
+                         (const TC*)ec.ptr, ec.stride, (TF*)xout.ptr, xout.stride, nf, Nf, nc);
+    return hipGetLastError();
+  });
 }
 
 template <class TI, class TM>
@@ -1689,11 +1747,14 @@ hipError_t Multigrid<TI, TM>::prolong_smooth0(int stage, Vec xin, Vec ec, Vec b,
   const C omega = (C)h_->omega;
   const dim3 g = grid2(op.N, B);
   const C es = (C)(1.0 / h_->mg_scale);
-#define PS0(D, V) hipLaunchKernelGGL((k_prolong_smooth<D, V, TI, TM, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (const TM*)ec.ptr, ec.stride, (const TI*)b.ptr, b.stride, (TI*)xout.ptr, xout.stride, op, nc, omega, es)
-  if (h_->dim == 3) { if (h_->vark) PS0(3, true); else PS0(3, false); }
-  else { if (h_->vark) PS0(2, true); else PS0(2, false); }
+  return typed1(1, [&](auto tc) {
+    using TC = decltype(tc);
+#define PS0(D, V) hipLaunchKernelGGL((k_prolong_smooth<D, V, TI, TC, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (const TC*)ec.ptr, ec.stride, (const TI*)b.ptr, b.stride, (TI*)xout.ptr, xout.stride, op, nc, omega, es)
+    if (h_->dim == 3) { if (h_->vark) PS0(3, true); else PS0(3, false); }
+    else { if (h_->vark) PS0(2, true); else PS0(2, false); }
 #undef PS0
-  return hipGetLastError();
+    return hipGetLastError();
+  });
 }
 
 template <class TI, class TM>
@@ -1718,21 +1779,24 @@ hipError_t Multigrid<TI, TM>::tail(int stage, Vec x, Vec b, bool zero_init, int 
     tf.cinv = use_fd ? nullptr : coarse_inv(stage);
     tail_fast_layout<C>(tf, nls);
     const dim3 g((unsigned)B), blk((unsigned)TAIL_THREADS);
-    TM* xp = (TM*)x.ptr;
-    const TM* bp = (const TM*)b.ptr;
+    return typed1(l0_, [&](auto t) {
+      using TS = decltype(t);
+      TS* xp = (TS*)x.ptr;
+      const TS* bp = (const TS*)b.ptr;
 #define TF_GO(K, NL, NP, F) \
-  hipLaunchKernelGGL((k_tail_fast<K, NL, NP, F, TM, C>), g, blk, fast_bytes_, st_, xp, x.stride, bp, b.stride, tf)
+  hipLaunchKernelGGL((k_tail_fast<K, NL, NP, F, TS, C>), g, blk, fast_bytes_, st_, xp, x.stride, bp, b.stride, tf)
 #define TF_KIND(NL, NP)                                 \
   do {                                                  \
     if (h_->vark) TF_GO(KIND_STENCIL9, NL, NP, false);  \
     else if (use_fd) TF_GO(KIND_TENSOR, NL, NP, true);  \
     else TF_GO(KIND_TENSOR, NL, NP, false);             \
   } while (0)
-    if (nls == 1) TF_KIND(1, 1);
-    else if constexpr (sizeof(C) == 4) TF_KIND(2, 4);
+      if (nls == 1) TF_KIND(1, 1);
+      else if constexpr (sizeof(C) == 4) TF_KIND(2, 4);
 #undef TF_KIND
 #undef TF_GO
-    return hipGetLastError();
+      return hipGetLastError();
+    });
   }
   if (l0_ > 0 && !zero_init) return hipErrorInvalidValue;   // coarse tails always start from zero
   if (tail_bytes_ > h_->lds_budget) return hipErrorInvalidValue;
@@ -1772,7 +1836,11 @@ hipError_t Multigrid<TI, TM>::tail(int stage, Vec x, Vec b, bool zero_init, int 
     else
       hipLaunchKernelGGL((k_tail<false, TI, TI, C>), g, blk, shm, st_, (TI*)x.ptr, x.stride, (const TI*)b.ptr, b.stride, ta);
   } else {
-    hipLaunchKernelGGL((k_tail<false, TM, TM, C>), g, blk, shm, st_, (TM*)x.ptr, x.stride, (const TM*)b.ptr, b.stride, ta);
+    return typed1(l0_, [&](auto t) {
+      using TS = decltype(t);
+      hipLaunchKernelGGL((k_tail<false, TS, TS, C>), g, blk, shm, st_, (TS*)x.ptr, x.stride, (const TS*)b.ptr, b.stride, ta);
+      return hipGetLastError();
+    });
   }
   return hipGetLastError();
 }
@@ -1801,22 +1869,29 @@ hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, in
     ca.out = cpl->out;
     ca.so = cpl->so;
   }
-  CplArgs<TM, C> cm{};
   const C bs = l == 0 ? (C)h_->mg_scale : C(1);
-#define DN_T(K, NU, TF, NZ, CA, TYV) hipLaunchKernelGGL((k_down2d<K, NU, TF, TM, C, NZ, TYV>), g, dim3(256), 0, st_, (const TF*)b.ptr, b.stride, (const TF*)x0, sx0, (TF*)xout.ptr, xout.stride, (TM*)bc.ptr, bc.stride, op, nc, omega, gx, gy, CA, bs)
+  // TF / TC: storage of this level and of the next (the precision schedule)
+#define DN_T(K, NU, TF, NZ, CA, TYV) hipLaunchKernelGGL((k_down2d<K, NU, TF, TC, C, NZ, TYV>), g, dim3(256), 0, st_, (const TF*)b.ptr, b.stride, (const TF*)x0, sx0, (TF*)xout.ptr, xout.stride, (TC*)bc.ptr, bc.stride, op, nc, omega, gx, gy, CA, bs)
 #define DN(K, NU, TF, NZ, CA) do { if (tall) DN_T(K, NU, TF, NZ, CA, TY0L); else DN_T(K, NU, TF, NZ, CA, TCY); } while (0)
 #define DN_NU(K, TF, NZ, CA) do { if (nu == 1) DN(K, 1, TF, NZ, CA); else if (nu == 2) DN(K, 2, TF, NZ, CA); else DN(K, 3, TF, NZ, CA); } while (0)
 #define DN_Z(K) do { if (nz == 0) DN_NU(K, TI, 0, ca); else if (nz == 1) DN_NU(K, TI, 1, ca); else DN_NU(K, TI, 2, ca); } while (0)
-  if (l == 0) {
-    if (h_->vark) DN_Z(KIND_FINE_VK); else DN_Z(KIND_FINE);
-  } else {
-    if (h_->vark) DN_NU(KIND_STENCIL9, TM, 0, cm); else DN_NU(KIND_TENSOR, TM, 0, cm);
-  }
+  if (l == 0)
+    return typed1(1, [&](auto tc) {
+      using TC = decltype(tc);
+      if (h_->vark) DN_Z(KIND_FINE_VK); else DN_Z(KIND_FINE);
+      return hipGetLastError();
+    });
+  return typed2(l, [&](auto tf, auto tc) {
+    using TF = decltype(tf);
+    using TC = decltype(tc);
+    CplArgs<TF, C> cm{};
+    if (h_->vark) DN_NU(KIND_STENCIL9, TF, 0, cm); else DN_NU(KIND_TENSOR, TF, 0, cm);
+    return hipGetLastError();
+  });
 #undef DN_Z
 #undef DN_NU
 #undef DN
 #undef DN_T
-  return hipGetLastError();
 }
 
 template <class TI, class TM>
@@ -1831,18 +1906,24 @@ hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec
   const dim3 g((unsigned)(gx * gy * B));
   const int nu = h_->opts.nu2;
   const C es = l == 0 ? (C)(1.0 / h_->mg_scale) : C(1);
-#define UP_T(K, NU, TF, TYV) hipLaunchKernelGGL((k_up2d<K, NU, TF, TM, C, TYV>), g, dim3(256), 0, st_, (const TF*)xin.ptr, xin.stride, (const TM*)ec.ptr, ec.stride, (const TF*)b.ptr, b.stride, (TF*)xout.ptr, xout.stride, op, nc, omega, gx, gy, es)
+#define UP_T(K, NU, TF, TYV) hipLaunchKernelGGL((k_up2d<K, NU, TF, TC, C, TYV>), g, dim3(256), 0, st_, (const TF*)xin.ptr, xin.stride, (const TC*)ec.ptr, ec.stride, (const TF*)b.ptr, b.stride, (TF*)xout.ptr, xout.stride, op, nc, omega, gx, gy, es)
 #define UP(K, NU, TF) do { if (tall) UP_T(K, NU, TF, TY0L); else UP_T(K, NU, TF, TCY); } while (0)
 #define UP_NU(K, TF) do { if (nu == 1) UP(K, 1, TF); else if (nu == 2) UP(K, 2, TF); else UP(K, 3, TF); } while (0)
-  if (l == 0) {
-    if (h_->vark) UP_NU(KIND_FINE_VK, TI); else UP_NU(KIND_FINE, TI);
-  } else {
-    if (h_->vark) UP_NU(KIND_STENCIL9, TM); else UP_NU(KIND_TENSOR, TM);
-  }
+  if (l == 0)
+    return typed1(1, [&](auto tc) {
+      using TC = decltype(tc);
+      if (h_->vark) UP_NU(KIND_FINE_VK, TI); else UP_NU(KIND_FINE, TI);
+      return hipGetLastError();
+    });
+  return typed2(l, [&](auto tf, auto tc) {
+    using TF = decltype(tf);
+    using TC = decltype(tc);
+    if (h_->vark) UP_NU(KIND_STENCIL9, TF); else UP_NU(KIND_TENSOR, TF);
+    return hipGetLastError();
+  });
 #undef UP_NU
 #undef UP
 #undef UP_T
-  return hipGetLastError();
 }
 
 // One V-cycle on level l.  `pre` = the first (pointwise) sweep from zero was
@@ -1877,8 +1958,12 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
       hipLaunchKernelGGL((k_coarse_solve<TI, C>), g, blk, 0, st_, (const TI*)b.ptr, b.stride, (TI*)x.ptr, x.stride,
                          coarse_inv(stage), Nc);
     else
-      hipLaunchKernelGGL((k_coarse_solve<TM, C>), g, blk, 0, st_, (const TM*)b.ptr, b.stride, (TM*)x.ptr, x.stride,
-                         coarse_inv(stage), Nc);
+      MG_TRY(typed1(l, [&](auto t) {
+        using TS = decltype(t);
+        hipLaunchKernelGGL((k_coarse_solve<TS, C>), g, blk, 0, st_, (const TS*)b.ptr, b.stride, (TS*)x.ptr, x.stride,
+                           coarse_inv(stage), Nc);
+        return hipGetLastError();
+      }));
     MG_TRY(hipGetLastError());
     MG_TRY(mark("k_coarse_solve", l));
     *result = x;
@@ -1995,7 +2080,8 @@ size_t mg_configure_lds() {
   const void* kernels[] = {
       (const void*)k_tail<false, double, double, double>, (const void*)k_tail<true, double, double, double>,
       (const void*)k_tail<false, float, float, float>, (const void*)k_tail<true, float, float, float>,
-      (const void*)k_tail<false, __half, __half, float>, (const void*)k_tail<false, __hip_bfloat16, __hip_bfloat16, float>};
+      (const void*)k_tail<false, __half, __half, float>, (const void*)k_tail<true, __half, __half, float>,
+      (const void*)k_tail<false, __hip_bfloat16, __hip_bfloat16, float>};
   for (const void* k : kernels)
     if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) != hipSuccess) {
       (void)hipGetLastError();

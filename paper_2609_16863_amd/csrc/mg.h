@@ -11,7 +11,9 @@
 namespace aao {
 
 // TI: storage of the finest level (the inner-GMRES vectors); TM: storage of
-// the coarse levels.  Arithmetic is in Acc<TI>::type.
+// the coarse levels where the precision schedule puts them in the low
+// format (opts.mg_low_from, opts.mg_coarse_fp32), TI elsewhere.  Arithmetic
+// is in Acc<TI>::type.
 template <class TI, class TM>
 class Multigrid {
  public:
@@ -74,6 +76,16 @@ class Multigrid {
 
   hipError_t mark(const char* kernel, int l);
 
+  // Storage precision of every level (see the class comment).
+  void set_level_storage();
+  bool low(int l) const { return l > 0 && l < levels_ && low_[l] != 0; }
+  // f(T{}) with the storage type T of level l; f(TF{}, TC{}) with those of
+  // levels l and l + 1.
+  template <class F>
+  hipError_t typed1(int l, F&& f) const;
+  template <class F>
+  hipError_t typed2(int l, F&& f) const;
+
   aao_problem* h_;
   hipStream_t st_;
   Marks* marks_ = nullptr;
@@ -85,6 +97,7 @@ class Multigrid {
   int fast_npt_;    // its nodes per thread on the first tail level (1 or 4)
   size_t fast_bytes_;
   int cinv_set_;    // coarsest-level inverse set (see the constructor)
+  std::vector<char> low_;   // low_[l]: level l stored in TM (else TI)
 };
 
 }  // namespace aao

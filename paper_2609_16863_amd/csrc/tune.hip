@@ -43,7 +43,8 @@ std::string tune_key(const aao_problem* h) {
   k << arch << " dim=" << h->dim << " n=" << h->n << " s=" << h->s << " nt=" << h->nt << " prec=" << h->opts.precision
     << " vark=" << (h->vark ? 1 : 0) << " nu=" << h->opts.nu1 << "," << h->opts.nu2 << " k=" << h->opts.inner_k
     << " schur=" << h->opts.schur << " cf=" << h->opts.mgrit_cf << " it=" << h->opts.mgrit_iters
-    << " fcf=" << h->opts.mgrit_fcf << " coarse=" << h->opts.coarse_max << " tail=" << h->opts.mg_tail_max;
+    << " fcf=" << h->opts.mgrit_fcf << " coarse=" << h->opts.coarse_max << " tail=" << h->opts.mg_tail_max
+    << " low=" << h->opts.mg_low_from << "," << h->opts.mg_coarse_fp32;
   return k.str();
 }
 
