@@ -167,6 +167,18 @@ typedef struct aao_opts {
                               mg_low_from puts the levels above it in 16 bits
                               -- a coarse-solve precision apart from the
                               smoother's (Sec. 4); 0 = no                      */
+  int relax_matvec;        /* 1: iteration-dependent precision of the products
+                              with A inside an FGMRES cycle (Sec. 4 names this
+                              relaxation, after Simoncini and Szyld, as future
+                              work): the product of iteration k may carry a
+                              relative error up to eta = tol beta0 / rho, rho
+                              the least-squares residual after iteration k-1
+                              (beta at a cycle's first) and beta0 the first
+                              cycle's; it is rounded to BF16 when eta >= 10 *
+                              2^-8, else to FP32 when eta >= 10 * 2^-24
+                              (simulated, as the paper simulates its lower
+                              precisions); products that start a cycle stay
+                              FP64.  stats.relaxed_* count them.  0 = off      */
 } aao_opts;
 
 /* Solve statistics (host struct filled by aao_solve*). */
@@ -188,6 +200,8 @@ typedef struct aao_stats {
                               (eq. (3.2): the batched block-diagonal solve)    */
   double schur_ms;         /* time in the S-tilde phase (eq. (3.3): the
                               sweep in time)                                   */
+  int relaxed_fp32;        /* products with A rounded to FP32 (relax_matvec)  */
+  int relaxed_bf16;        /* products with A rounded to BF16 (relax_matvec)  */
 } aao_stats;
 
 typedef struct aao_problem aao_problem;   /* opaque handle */
@@ -196,7 +210,7 @@ typedef struct aao_problem aao_problem;   /* opaque handle */
  * nu1 = nu2 = 2, omega 0, precision FP64, use_graph 1, mg_tail_max 0,
  * coarse_max 0, inner_tol 0, schur AAO_SCHUR_SWEEP, mgrit_cf 8,
  * mgrit_iters 1, mgrit_fcf 0, side RIGHT, outer_precision FP64,
- * mg_low_from 0, mg_coarse_fp32 0.  With use_graph the
+ * mg_low_from 0, relax_matvec 0, mg_coarse_fp32 0.  With use_graph the
  * first application of P-tilde for a given (inner_k, cycles, transpose) is
  * captured into a HIP graph on a private stream and later applications
  * replay it on the handle's stream (inputs and outputs pass through fixed

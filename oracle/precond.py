@@ -234,6 +234,7 @@ def fgmres(apply_A, apply_P, rhs, restart=30, tol=1e-8, maxit=100, x0=None):
             e1[0] = beta
             y, *_ = np.linalg.lstsq(H[: m + 1, :m], e1, rcond=None)
             est = np.linalg.norm(e1 - H[: m + 1, :m] @ y)
+            rho = est
             if est <= tol * nb or H[j + 1, j] == 0.0 or its >= maxit:
                 break
             Vb.append(w / H[j + 1, j])
@@ -245,9 +246,18 @@ def fgmres(apply_A, apply_P, rhs, restart=30, tol=1e-8, maxit=100, x0=None):
 # Algorithm 1: split-preconditioned FGMRES in four precisions
 # ----------------------------------------------------------------------------
 def fgmres_split(apply_A, apply_PL, apply_PR, b, restart=30, tol=1e-8, maxit=100, x0=None,
-                 rnd=None, rnd_A=None, rnd_PL=None, rnd_PR=None):
+                 rnd=None, rnd_A=None, rnd_PL=None, rnd_PR=None, relax=False, stats=None):
     """Algorithm 1 of Sec. 4, restarted, in FP64 arithmetic with optional
     rounding of each step's result to a lower precision.
+
+    relax: the iteration-dependent matrix-vector tolerance that Sec. 4 names
+    (after Simoncini and Szyld) and leaves to future work.  The product
+    s = A z_k of iteration k may carry a relative error up to
+    eta_k = tol beta_0 / rho_{k-1}, rho_{k-1} the least-squares residual
+    after the previous iteration (beta at a cycle's first): it is rounded to
+    BF16 when eta_k >= 10 u_bf16, else to FP32 when eta_k >= 10 u_fp32
+    (RELAX_TIERS), else kept.  The products that start a cycle stay exact.
+    stats (a dict) receives the number of products rounded per tier.
 
     apply_PL / apply_PR: z = P_L^{-1} v / P_R^{-1} v (None = identity);
     rnd, rnd_A, rnd_PL, rnd_PR: functions rounding the results of the
@@ -289,11 +299,21 @@ def fgmres_split(apply_A, apply_PL, apply_PR, b, restart=30, tol=1e-8, maxit=100
         H = np.zeros((restart + 1, restart))
         m = 0
         done = False
+        rho = beta
         for j in range(restart):
             its += 1
             z = r_R(PR(Vb[j]))
             Z.append(z)
-            w = r_L(PL(r_A(apply_A(z))))
+            s_ = r_A(apply_A(z))
+            if relax:
+                eta = tol * beta0 / rho
+                for name, u, rounder in RELAX_TIERS:
+                    if eta >= 10.0 * u:
+                        s_ = rounder(s_)
+                        if stats is not None:
+                            stats[name] = stats.get(name, 0) + 1
+                        break
+            w = r_L(PL(s_))
             for i in range(j + 1):
                 H[i, j] = Vb[i] @ w
                 w = r_u(w - H[i, j] * Vb[i])
@@ -303,6 +323,7 @@ def fgmres_split(apply_A, apply_PL, apply_PR, b, restart=30, tol=1e-8, maxit=100
             e1[0] = beta
             y, *_ = np.linalg.lstsq(H[: m + 1, :m], e1, rcond=None)
             est = np.linalg.norm(e1 - H[: m + 1, :m] @ y)
+            rho = est
             if est <= tol * beta0 or H[j + 1, j] == 0.0 or its >= maxit:
                 done = True
                 break
@@ -317,4 +338,17 @@ def fgmres_split(apply_A, apply_PL, apply_PR, b, restart=30, tol=1e-8, maxit=100
 def round_fp32(v):
     """Round to IEEE single precision (round to nearest even) and back."""
     return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def round_bf16(v):
+    """Round to FP32, then to bfloat16 (8 significand bits, nearest even on
+    the 16 dropped bits), and back."""
+    f = np.asarray(v, dtype=np.float64).astype(np.float32)
+    bits = f.view(np.uint32).astype(np.uint64)
+    bits = (bits + 0x7FFF + ((bits >> 16) & 1)) & 0xFFFF0000
+    return bits.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+# (name, unit roundoff, rounding) from the lowest precision up
+RELAX_TIERS = (("bf16", 2.0 ** -8, round_bf16), ("fp32", 2.0 ** -24, round_fp32))
 

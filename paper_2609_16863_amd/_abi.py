@@ -29,14 +29,16 @@ class Opts(ctypes.Structure):
                 ("precision", c_int), ("use_graph", c_int), ("mg_tail_max", c_int), ("coarse_max", c_int),
                 ("inner_tol", c_double), ("schur", c_int), ("mgrit_cf", c_int), ("mgrit_iters", c_int),
                 ("mgrit_fcf", c_int), ("side", c_int),
-                ("outer_precision", c_int), ("mg_low_from", c_int), ("mg_coarse_fp32", c_int)]
+                ("outer_precision", c_int), ("mg_low_from", c_int), ("mg_coarse_fp32", c_int),
+                ("relax_matvec", c_int)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("outer_iterations", c_int), ("restarts", c_int), ("relres", c_double),
                 ("time_ms", c_double), ("precond_ms", c_double), ("history", c_double * 128),
                 ("history_len", c_int), ("inner_solves", c_int), ("inner_iterations", ctypes.c_longlong),
-                ("theta_ms", c_double), ("schur_ms", c_double)]
+                ("theta_ms", c_double), ("schur_ms", c_double), ("relaxed_fp32", c_int),
+                ("relaxed_bf16", c_int)]
 
 
 class Tune(ctypes.Structure):

@@ -27,7 +27,7 @@ def _ptr(t):
 SOLVER_DEFAULTS = dict(restart=30, maxit=100, tol=1e-8, inner_k=3, cycles=1, nu1=2, nu2=2, omega=0.0,
                        precision="fp64", use_graph=True, mg_tail_max=0, coarse_max=0, inner_tol=0.0,
                        schur="sweep", mgrit_cf=8, mgrit_iters=1, mgrit_fcf=False, side="right",
-                       outer_precision="fp64", mg_low_from=0, mg_coarse_fp32=False)
+                       outer_precision="fp64", mg_low_from=0, mg_coarse_fp32=False, relax_matvec=False)
 
 
 def _solver_options(kw):
@@ -56,6 +56,7 @@ def _make_opts(lib, o):
     opts.outer_precision = _abi.OUTER[o["outer_precision"]]
     opts.mg_low_from = int(o["mg_low_from"])
     opts.mg_coarse_fp32 = int(bool(o["mg_coarse_fp32"]))
+    opts.relax_matvec = int(bool(o["relax_matvec"]))
     return opts
 
 
@@ -63,7 +64,8 @@ def _stats_dict(st, code):
     return {"outer_iterations": st.outer_iterations, "restarts": st.restarts, "relres": st.relres,
             "time_ms": st.time_ms, "precond_ms": st.precond_ms, "theta_ms": st.theta_ms,
             "schur_ms": st.schur_ms, "inner_solves": st.inner_solves,
-            "inner_iterations": st.inner_iterations,
+            "inner_iterations": st.inner_iterations, "relaxed_fp32": st.relaxed_fp32,
+            "relaxed_bf16": st.relaxed_bf16,
             "history": list(st.history[: st.history_len]), "converged": code == 0}
 
 
@@ -89,7 +91,9 @@ class HeatProblem:
     ``outer_precision`` = "fp32" runs the outer solve in simulated single
     precision (approach A3).  ``mg_low_from`` (first multigrid level in 16
     bits) and ``mg_coarse_fp32`` (coarse solve kept FP32) set the V-cycle's
-    precision schedule for "bf16"/"fp16".  All solver options and their
+    precision schedule for "bf16"/"fp16"; ``relax_matvec`` lowers the
+    precision of the products with A as the residual falls.  All solver
+    options and their
     defaults are in SOLVER_DEFAULTS.
     """
 

@@ -203,6 +203,8 @@ template <class T>
 hipError_t launch_fill(T* dst, T v, int64_t n, hipStream_t st);
 // x <- x rounded to FP32 (nearest even) and back: simulated single precision
 hipError_t launch_round_f32(double* x, int64_t n, hipStream_t st);
+// x <- x rounded to FP32, then to BF16 (nearest even), and back
+hipError_t launch_round_bf16(double* x, int64_t n, hipStream_t st);
 
 // kern_mg.hip
 size_t mg_configure_lds();

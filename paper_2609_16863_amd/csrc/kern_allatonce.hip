@@ -567,6 +567,16 @@ hipError_t launch_round_f32(double* x, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void k_round_bf16(double* __restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB)
+    x[i] = (double)__bfloat162float(__float2bfloat16((float)x[i]));
+}
+
+hipError_t launch_round_bf16(double* x, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_round_bf16, dim3(grid1d(n)), dim3(TPB), 0, st, x, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_sub_from(const double* a, double* y, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_sub_from, dim3(grid1d(n)), dim3(TPB), 0, st, a, y, n);
   return hipGetLastError();

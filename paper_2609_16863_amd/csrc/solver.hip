@@ -655,6 +655,7 @@ class Fgmres {
       g[0] = beta;
       int mm = 0;
       bool stop = false, ls_met = false;
+      double lsres = beta;   // least-squares residual after the previous iteration
       for (int j = 0; j < m && !stop; ++j) {
         its++;
         double* vj = V_ + (int64_t)j * U;
@@ -665,6 +666,17 @@ class Fgmres {
           if ((e = op<double>(vj, w_)) != hipSuccess) break;
         }
         if ((e = rnd(w_)) != hipSuccess) break;
+        if (h_->opts.relax_matvec && lsres > 0.0) {
+          // the relative error this product may carry (Simoncini-Szyld)
+          const double eta = h_->opts.tol * beta0 / lsres;
+          if (eta >= 10.0 * 0x1p-8) {
+            if ((e = launch_round_bf16(w_, U, st_)) != hipSuccess) break;
+            stt.relaxed_bf16++;
+          } else if (eta >= 10.0 * 0x1p-24) {
+            if ((e = launch_round_f32(w_, U, st_)) != hipSuccess) break;
+            stt.relaxed_fp32++;
+          }
+        }
         if (left) {
           if ((e = precond(w_, tY)) != hipSuccess) break;
           if ((e = launch_copy_cast<double, TI>(w_, tY, U, st_)) != hipSuccess) break;
@@ -698,7 +710,8 @@ class Fgmres {
         g[j + 1] = -sn[j] * g[j];
         g[j] = cs[j] * g[j];
         mm = j + 1;
-        const double est = std::fabs(g[j + 1]) / beta0;
+        lsres = std::fabs(g[j + 1]);
+        const double est = lsres / beta0;
         if (stt.history_len < 128) stt.history[stt.history_len++] = est;
         if (est <= h_->opts.tol) ls_met = true;
         if (ls_met || hn == 0.0 || its >= h_->opts.maxit) stop = true;

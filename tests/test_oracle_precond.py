@@ -194,3 +194,57 @@ def test_algorithm1_single_precision_system_stagnates():
     _, _, h64 = precond.fgmres_split(A, None, P, rhs, restart=30, tol=1e-12, maxit=60)
     assert min(h64) <= 1e-11
     assert min(h32) >= 1e-9
+
+
+def test_round_bf16_is_nearest_even_bfloat16():
+    """Against a brute-force choice between the two neighbouring bfloat16
+    values of the FP32 input (ties to the even significand)."""
+    rng = np.random.default_rng(8)
+    x = np.concatenate([rng.standard_normal(2000) * 10.0 ** rng.integers(-30, 30, 2000),
+                        [1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(1.0 + 2.0 ** -8), 0.0, 1.0, 2.0 ** -126]])
+    f = x.astype(np.float32)
+    bits = f.view(np.uint32).astype(np.int64)
+    lo = (bits & ~0xFFFF) & 0xFFFFFFFF
+    hi = lo + 0x10000
+    vlo = lo.astype(np.uint32).view(np.float32).astype(np.float64)
+    vhi = hi.astype(np.uint32).view(np.float32).astype(np.float64)
+    fv = f.astype(np.float64)
+    dlo, dhi = np.abs(fv - vlo), np.abs(vhi - fv)
+    even_lo = ((lo >> 16) & 1) == 0
+    want = np.where(dlo < dhi, vlo, np.where(dhi < dlo, vhi, np.where(even_lo, vlo, vhi)))
+    got = precond.round_bf16(x)
+    assert np.array_equal(got, want)
+    nz = x != 0
+    assert np.max(np.abs(got[nz] - fv[nz]) / np.abs(fv[nz])) <= 2.0 ** -8
+
+
+def _relax_problem():
+    p, f, u0, _ = _prob(2, 12, 2, 6)
+    ops = precond.StageOps(p, inner_k=3, nu1=2, nu2=2)
+    K = p.K()
+    return (lambda y: allatonce.apply_blockwise(p, y, K)), (lambda r: precond.apply_preconditioner(ops, r)), \
+        allatonce.rhs(p, f, u0)
+
+
+def test_relaxed_matvec_keeps_the_target():
+    """The iteration-dependent matvec tolerance (Sec. 4, after Simoncini and
+    Szyld): products taken in BF16 / FP32 once the residual has fallen far
+    enough still reach the target, in the same number of iterations."""
+    A, P, rhs = _relax_problem()
+    for tol in (1e-8, 1e-11):
+        st = {}
+        _, its_r, hist_r = precond.fgmres_split(A, None, P, rhs, restart=30, tol=tol, maxit=60, relax=True,
+                                                stats=st)
+        _, its, _ = precond.fgmres_split(A, None, P, rhs, restart=30, tol=tol, maxit=60)
+        assert hist_r[-1] <= tol
+        assert abs(its_r - its) <= 1
+        assert st.get("fp32", 0) >= 1 and st.get("bf16", 0) >= 1 and sum(st.values()) < its_r
+
+
+def test_relaxing_every_product_loses_the_target():
+    """Without the criterion (every product in BF16) the true residual stalls
+    far above 1e-8: the relaxation has to follow the residual."""
+    A, P, rhs = _relax_problem()
+    _, _, hist = precond.fgmres_split(A, None, P, rhs, restart=30, tol=1e-8, maxit=60,
+                                      rnd_A=precond.round_bf16)
+    assert min(hist) > 1e-6
