@@ -13,9 +13,13 @@ V = [V_0, ..., V_{nt-1}], V_n = [V_{n,1}, ..., V_{n,s}], the system is
     Psi2  : (e (x) K) in block (n, n), zero last block column
     Theta : I_nt (x) (I_s (x) M + tau A (x) K)
 
-with M = I here (finite differences).  b holds the initial condition:
-b_0 = u0 and b_{n>=1} = 0 for homogeneous Dirichlet data.  The stage right
-hand side is f_{n,i} = f(x, t_n + c_i tau), t_n = n tau.
+with M = I for finite differences (disc "fd", the unit square or cube) and
+the Q1 mass matrix for bilinear finite elements (disc "q1", the square
+[0, length]^2, ``oracle.fe``).  b holds the initial condition: b_0 = M u0 and
+b_{n>=1} = 0 for homogeneous Dirichlet data.  The stage right-hand side is
+M f_{n,i} with f_{n,i} = f(x, t_n + c_i tau) at the nodes, t_n = n tau (for
+finite elements, the load vector of the nodal interpolant of f; a reading:
+the paper calls f_n the discretisation of the right-hand side).
 
 The vector of unknowns is x = [v; V]: (nt+1) blocks of v, then nt*s blocks of
 V in (step, stage) order; U = N (nt (s+1) + 1) values in total.
@@ -30,7 +34,7 @@ from typing import Optional
 import numpy as np
 import scipy.sparse as sp
 
-from . import grid, tableau
+from . import fe, grid, tableau
 
 
 @dataclass
@@ -41,6 +45,8 @@ class Problem:
     nt: int                # time steps
     T: float = 1.0         # final time
     kappa: Optional[np.ndarray] = None   # nodal diffusivity (N,), None = 1
+    disc: str = "fd"       # "fd" (finite differences) or "q1" (bilinear elements, 2D)
+    length: float = 1.0    # side of the square (q1)
 
     A: np.ndarray = field(init=False, repr=False)
     b: np.ndarray = field(init=False, repr=False)
@@ -48,6 +54,11 @@ class Problem:
 
     def __post_init__(self):
         self.A, self.b, self.c = tableau.radau_iia(self.s)
+        if self.disc not in ("fd", "q1"):
+            raise ValueError(self.disc)
+        if self.disc == "q1" and (self.dim != 2 or self.kappa is not None):
+            raise ValueError("q1 elements: 2D, constant diffusivity")
+        self._mk = None
 
     @property
     def N(self):
@@ -59,7 +70,7 @@ class Problem:
 
     @property
     def h(self):
-        return grid.spacing(self.n)
+        return fe.spacing(self.n, self.length) if self.disc == "q1" else grid.spacing(self.n)
 
     @property
     def U(self):
@@ -74,7 +85,20 @@ class Problem:
         return (np.arange(self.nt)[:, None] + self.c[None, :]) * self.tau
 
     def K(self):
+        if self.disc == "q1":
+            return self._q1()[1]
         return grid.stiffness(self.n, self.dim, self.kappa)
+
+    def M(self):
+        """Mass matrix: the identity for finite differences."""
+        if self.disc == "q1":
+            return self._q1()[0]
+        return sp.identity(self.N, format="csr")
+
+    def _q1(self):
+        if self._mk is None:
+            self._mk = fe.q1_matrices(self.n, self.length)
+        return self._mk
 
 
 def unknowns(N, nt, s):
@@ -95,10 +119,16 @@ def join(v, V):
 
 
 def rhs(prob, f, u0):
-    """Right-hand side [b; f]: b_0 = u0, b_{n>=1} = 0, f in (nt, s, N) order."""
+    """Right-hand side [b; f]: b_0 = M u0, b_{n>=1} = 0, the stage blocks M f
+    in (nt, s, N) order (M = I for finite differences)."""
     v = np.zeros((prob.nt + 1, prob.N))
+    fs = np.asarray(f, float).reshape(prob.nt, prob.s, prob.N)
+    if prob.disc == "q1":
+        M = prob.M()
+        v[0] = M @ u0
+        return join(v, (M @ fs.reshape(-1, prob.N).T).T.reshape(fs.shape))
     v[0] = u0
-    return join(v, np.asarray(f, float).reshape(prob.nt, prob.s, prob.N))
+    return join(v, fs)
 
 
 def blocks(prob, sparse=True):
@@ -107,16 +137,16 @@ def blocks(prob, sparse=True):
     eye = (lambda m: sp.identity(m, format="csr")) if sparse else np.eye
     N, nt, s, tau = prob.N, prob.nt, prob.s, prob.tau
     K = prob.K() if sparse else prob.K().toarray()
-    IN = eye(N)
+    MN = prob.M() if sparse else prob.M().toarray()
     sub = np.eye(nt + 1, k=-1)                    # ones at (n+1, n)
-    Phi = kr(np.eye(nt + 1) - sub, IN)
+    Phi = kr(np.eye(nt + 1) - sub, MN)
     Esub = np.zeros((nt + 1, nt))
     Esub[np.arange(1, nt + 1), np.arange(nt)] = 1.0
-    Psi1 = -kr(Esub, kr(tau * prob.b[None, :], IN))
+    Psi1 = -kr(Esub, kr(tau * prob.b[None, :], MN))
     Ediag = np.zeros((nt, nt + 1))
     Ediag[np.arange(nt), np.arange(nt)] = 1.0
     Psi2 = kr(Ediag, kr(np.ones((s, 1)), K))
-    Theta_hat = kr(np.eye(s), IN) + tau * kr(prob.A, K)
+    Theta_hat = kr(np.eye(s), MN) + tau * kr(prob.A, K)
     Theta = kr(np.eye(nt), Theta_hat)
     return Phi, Psi1, Psi2, Theta
 
@@ -130,9 +160,9 @@ def operator(prob, sparse=True):
 
 
 def theta_hat(prob, K=None):
-    """The stage matrix I_s (x) I + tau A (x) K of eq. (2.3), sparse."""
+    """The stage matrix I_s (x) M + tau A (x) K of eq. (2.3), sparse."""
     K = prob.K() if K is None else K
-    return (sp.kron(sp.identity(prob.s), sp.identity(prob.N))
+    return (sp.kron(sp.identity(prob.s), prob.M())
             + prob.tau * sp.kron(prob.A, K)).tocsc()
 
 
@@ -143,6 +173,8 @@ def apply_rows(prob, x, rows, K=None):
     the v part (block n, node p) or of a stage block (n, i, node p) uses only
     the K-row of p.  ``rows`` are global indices into the layout of x.
     """
+    if prob.disc != "fd":
+        raise ValueError("apply_rows: finite differences only")
     K = prob.K() if K is None else K
     N, nt, s, tau = prob.N, prob.nt, prob.s, prob.tau
     x = np.asarray(x)
@@ -174,32 +206,33 @@ def apply_rows(prob, x, rows, K=None):
 def apply_blockwise(prob, x, K=None, transpose=False):
     """y = A x (or A^T x) one block row at a time, never forming A.
 
-    Forward rows:  y_{v,0} = v_0;
-                   y_{v,n+1} = v_{n+1} - v_n - tau sum_i b_i V_{n,i};
-                   y_{V,n,i} = V_{n,i} + K (v_n + tau sum_j a_ij V_{n,j}).
-    Transposed rows follow from the transposed blocks:
-                   y_{v,n} = x_{v,n} - x_{v,n+1} + K sum_i x_{V,n,i}  (n < nt),
-                   y_{v,nt} = x_{v,nt};
-                   y_{V,n,j} = x_{V,n,j} + tau K sum_i a_ij x_{V,n,i}
-                               - tau b_j x_{v,n+1}.
+    Forward rows:  y_{v,0} = M v_0;
+                   y_{v,n+1} = M (v_{n+1} - v_n - tau sum_i b_i V_{n,i});
+                   y_{V,n,i} = M V_{n,i} + K (v_n + tau sum_j a_ij V_{n,j}).
+    Transposed rows follow from the transposed blocks (M, K symmetric):
+                   y_{v,n} = M (x_{v,n} - x_{v,n+1}) + K sum_i x_{V,n,i}  (n < nt),
+                   y_{v,nt} = M x_{v,nt};
+                   y_{V,n,j} = M x_{V,n,j} + tau K sum_i a_ij x_{V,n,i}
+                               - tau b_j M x_{v,n+1}.
     """
     K = prob.K() if K is None else K
+    Mm = prob.M()
     tau, A, b = prob.tau, prob.A, prob.b
     v, V = split(prob, np.asarray(x, float))
     yv = np.empty_like(v)
     yV = np.empty_like(V)
     if not transpose:
-        yv[0] = v[0]
+        yv[0] = Mm @ v[0]
         for n in range(prob.nt):
-            yv[n + 1] = v[n + 1] - v[n] - tau * np.tensordot(b, V[n], axes=(0, 0))
+            yv[n + 1] = Mm @ (v[n + 1] - v[n] - tau * np.tensordot(b, V[n], axes=(0, 0)))
             for i in range(prob.s):
                 w = v[n] + tau * np.tensordot(A[i], V[n], axes=(0, 0))
-                yV[n, i] = V[n, i] + K @ w
+                yV[n, i] = Mm @ V[n, i] + K @ w
     else:
-        yv[prob.nt] = v[prob.nt]
+        yv[prob.nt] = Mm @ v[prob.nt]
         for n in range(prob.nt):
-            yv[n] = v[n] - v[n + 1] + K @ V[n].sum(axis=0)
+            yv[n] = Mm @ (v[n] - v[n + 1]) + K @ V[n].sum(axis=0)
             for j in range(prob.s):
                 mix = tau * np.tensordot(A[:, j], V[n], axes=(0, 0))
-                yV[n, j] = V[n, j] + K @ mix - tau * b[j] * v[n + 1]
+                yV[n, j] = Mm @ V[n, j] + K @ mix - tau * b[j] * (Mm @ v[n + 1])
     return join(yv, yV)

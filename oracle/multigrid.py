@@ -1,4 +1,5 @@
-"""Geometric multigrid V-cycle for the shifted blocks I + a K.
+"""Geometric multigrid V-cycle for the shifted blocks M + a K (M = I for
+finite differences, the Q1 mass matrix for bilinear elements).
 
 Test infrastructure only (see ``oracle/__init__.py``).
 
@@ -62,12 +63,13 @@ def interpolation(n, dim):
 
 
 class Hierarchy:
-    """Levels (A_l, P_l) for A_0 = I + a K."""
+    """Levels (A_l, P_l) for A_0 = M + a K (M = I unless given)."""
 
-    def __init__(self, K, n, dim, a, coarse_max=COARSE_MAX):
+    def __init__(self, K, n, dim, a, coarse_max=COARSE_MAX, M=None):
         self.dim = dim
         self.sizes = [n]
-        self.ops = [(sp.identity(K.shape[0], format="csr") + a * K).tocsr()]
+        M0 = sp.identity(K.shape[0], format="csr") if M is None else M
+        self.ops = [(M0 + a * K).tocsr()]
         self.P = []
         while self.sizes[-1] ** dim > coarse_max and self.sizes[-1] > 1:
             nf = self.sizes[-1]

@@ -18,7 +18,11 @@ Applying z = P^{-1} r is block back-substitution:
     z_V = Theta^{-1} r_V                          (independent per step)
     t_{v,0} = r_{v,0},  t_{v,n+1} = r_{v,n+1} + tau sum_i b_i z_{V,n,i}
     z_{v,0} = t_{v,0},  z_{v,n+1} = t_{v,n+1} + z_{v,n} - X z_{v,n}
-(the M^{-1} step of S-tilde is the identity since M = I).
+(the M^{-1} step of S-tilde is the identity when M = I; with Q1 elements
+t_v carries M in its coupling term, t_{v,n+1} = r_{v,n+1} + tau M sum_i b_i
+z_{V,n,i}, and S-tilde^{-1} first applies M^{-1} to every block of t_v by 20
+steps of Chebyshev semi-iteration, as the paper does, before the
+substitution).
 
 Rana's stage preconditioner (cited, not defined, in the paper; reading): the
 Crout factor A_RK = L U (U unit upper) gives P_int = I_s (x) M + tau L (x) K,
@@ -33,7 +37,7 @@ with s = 1 being exact (tests/test_oracle_precond.py).
 import numpy as np
 import scipy.sparse.linalg as spla
 
-from . import allatonce, multigrid, tableau
+from . import allatonce, fe, multigrid, tableau
 
 
 # ----------------------------------------------------------------------------
@@ -97,13 +101,15 @@ class StageOps:
         self.exact_blocks = exact_blocks
         self.coarse_max = coarse_max
         tau = prob.tau
-        self.hier = [multigrid.Hierarchy(self.K, prob.n, prob.dim, tau * self.L[i, i], coarse_max)
+        self.M = prob.M()
+        Mh = self.M if prob.disc == "q1" else None
+        self.hier = [multigrid.Hierarchy(self.K, prob.n, prob.dim, tau * self.L[i, i], coarse_max, M=Mh)
                      for i in range(prob.s)]
         self._lu_blocks = None
         self._lu_theta = None
 
     def block_solve(self, i, rhs):
-        """Inexact (or exact) inverse of I + tau L_ii K."""
+        """Inexact (or exact) inverse of M + tau L_ii K."""
         if self.exact_blocks:
             if self._lu_blocks is None:
                 self._lu_blocks = [spla.splu(h.ops[0].tocsc()) for h in self.hier]
@@ -111,7 +117,7 @@ class StageOps:
         return multigrid.solve(self.hier[i], rhs, self.cycles, self.omega, self.nu1, self.nu2)
 
     def rana(self, r):
-        """Forward substitution with I_s (x) I + tau L (x) K; r, z shape (s, N)."""
+        """Forward substitution with I_s (x) M + tau L (x) K; r, z shape (s, N)."""
         s, tau = self.prob.s, self.prob.tau
         z = np.zeros_like(r)
         for i in range(s):
@@ -155,7 +161,7 @@ def coarse_stage_ops(ops, cf):
     """StageOps of the same problem with the time step cf * tau (the MGRIT
     coarse propagator takes one S-tilde step of that size)."""
     p = ops.prob
-    pc = allatonce.Problem(p.n, p.dim, p.s, 1, cf * p.tau, kappa=p.kappa)
+    pc = allatonce.Problem(p.n, p.dim, p.s, 1, cf * p.tau, kappa=p.kappa, disc=p.disc, length=p.length)
     return StageOps(pc, inner_k=ops.inner_k, inner_tol=ops.inner_tol, cycles=ops.cycles, omega=ops.omega,
                     nu1=ops.nu1, nu2=ops.nu2, exact_blocks=ops.exact_blocks, coarse_max=ops.coarse_max)
 
@@ -177,7 +183,15 @@ def apply_preconditioner(ops, r, exact=False, mgrit=None):
         zV[n] = solve_step(rV[n])
     tv = rv.copy()
     for n in range(nt):
-        tv[n + 1] = rv[n + 1] + tau * np.tensordot(prob.b, zV[n], axes=(0, 0))
+        tv[n + 1] = rv[n + 1] + tau * (ops.M @ np.tensordot(prob.b, zV[n], axes=(0, 0)))
+    if prob.disc == "q1":
+        # S-tilde = blockdiag(M) (bidiagonal part): its block-diagonal mass
+        # solve first, by Chebyshev semi-iteration (or exactly)
+        if exact:
+            lu = spla.splu(ops.M.tocsc())
+            tv = np.array([lu.solve(t) for t in tv])
+        else:
+            tv = fe.chebyshev_mass(ops.M, tv)
     phi = schur_propagator(ops, exact)
     if mgrit is None:
         zv = np.array(_mgrit.sequential(list(tv), phi))

@@ -10,6 +10,10 @@ so this stepping yields its unique solution x* (the result every FGMRES solve
 of eq. (2.4) converges to).  The stage right-hand side is f_n - (e (x) K) v_n:
 the paper prints "f_n - K v_n"; the Psi2 = e (x) K block fixes the reading.
 
+With Q1 elements (prob.disc "q1") the stage right-hand side is the load
+vector M f_n (f_n at the nodes) and v_0 = u0 (b_0 = M u0); the update needs
+no mass solve since every term of eq. (2.2) carries M.
+
 Two exact stage solvers:
 * ``"lu"``  -- sparse LU (SuperLU) of the stage matrix, factored once.
 * ``"dst"`` -- constant diffusivity only: K is diagonalised by the
@@ -40,7 +44,7 @@ def solve(prob, f, u0, method="auto", workers=None, timings=None):
     ``timings`` (dict, optional) receives 'factor_s' and 'step_s'.
     """
     if method == "auto":
-        method = "dst" if prob.kappa is None else "lu"
+        method = "dst" if prob.kappa is None and prob.disc == "fd" else "lu"
     nt, s, N, tau = prob.nt, prob.s, prob.N, prob.tau
     f = np.asarray(f, float).reshape(nt, s, N)
     v = np.empty((nt + 1, N))
@@ -50,6 +54,9 @@ def solve(prob, f, u0, method="auto", workers=None, timings=None):
     if method == "lu":
         K = prob.K()
         lu = spla.splu(allatonce.theta_hat(prob, K))
+        if prob.disc == "q1":
+            Mm = prob.M()
+            f = (Mm @ f.reshape(-1, N).T).T.reshape(nt, s, N)
         t1 = time.perf_counter()
         for n in range(nt):
             Kv = K @ v[n]
@@ -57,8 +64,8 @@ def solve(prob, f, u0, method="auto", workers=None, timings=None):
             V[n] = lu.solve(r).reshape(s, N)
             v[n + 1] = v[n] + tau * np.tensordot(prob.b, V[n], axes=(0, 0))
     elif method == "dst":
-        if prob.kappa is not None:
-            raise ValueError("DST stepping needs constant diffusivity")
+        if prob.kappa is not None or prob.disc != "fd":
+            raise ValueError("DST stepping needs finite differences with constant diffusivity")
         shape = grid.field_shape(prob.n, prob.dim)
         lam = grid.dst_eigenvalues(prob.n, prob.dim).ravel()
         # per-mode inverse of I + tau lam A  (N, s, s)
@@ -85,6 +92,7 @@ def solve(prob, f, u0, method="auto", workers=None, timings=None):
 
 def solve_steps(prob, f, u0, nsteps, method="auto", workers=None, timings=None):
     """Run only the first ``nsteps`` steps (a bounded sample for timing)."""
-    sub = allatonce.Problem(prob.n, prob.dim, prob.s, nsteps, prob.tau * nsteps, prob.kappa)
+    sub = allatonce.Problem(prob.n, prob.dim, prob.s, nsteps, prob.tau * nsteps, prob.kappa, prob.disc,
+                            prob.length)
     f = np.asarray(f, float).reshape(prob.nt, prob.s, prob.N)[:nsteps]
     return solve(sub, f, u0, method=method, workers=workers, timings=timings)
