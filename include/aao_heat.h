@@ -101,6 +101,21 @@ typedef enum aao_side {
   AAO_SIDE_SPLIT = 2       /* P_L = P_R = P-tilde                              */
 } aao_side;
 
+/* Spatial discretisation. */
+typedef enum aao_disc {
+  AAO_DISC_FD = 0,         /* 5/7-point finite differences on the unit square
+                              or cube, M = I                                   */
+  AAO_DISC_Q1 = 1          /* bilinear finite elements (Sec. 2 and Sec. 5 use
+                              Q1/Q2) on the square [0, length]^2, uniform grid,
+                              with their mass matrix M: Phi and Psi1 carry M,
+                              Theta_hat = I_s (x) M + tau A (x) K, the
+                              multigrid solves M + a K, and S-tilde applies
+                              M^{-1} by 20 steps of Chebyshev semi-iteration
+                              with the Jacobi splitting (Sec. 5).  2D,
+                              kappa = NULL, nu1, nu2 <= 3; the transposed
+                              solve and the kappa gradient are not available */
+} aao_disc;
+
 /* Problem description (Sec. 2).  kappa: host pointer to N nodal
  * diffusivities (> 0), copied at creation, or NULL for kappa = 1.  A face
  * between two interior nodes carries their harmonic mean, a face to the
@@ -112,6 +127,10 @@ typedef struct aao_desc {
   int nt;                  /* time steps, >= 1                                */
   double T;                /* final time, > 0                                 */
   const double* kappa;     /* host, N values, or NULL                          */
+  int disc;                /* aao_disc                                         */
+  double length;           /* side of the square for AAO_DISC_Q1 (0 = 1); the
+                              finite-difference domain is the unit square or
+                              cube (0 or 1 only)                               */
 } aao_desc;
 
 /* Solver options.  Fill with aao_default_opts, then override. */

@@ -20,7 +20,10 @@ OUTER = {"fp64": 0, "fp32": 1}
 
 class Desc(ctypes.Structure):
     _fields_ = [("dim", c_int), ("n", c_int), ("s", c_int), ("nt", c_int), ("T", c_double),
-                ("kappa", c_void_p)]
+                ("kappa", c_void_p), ("disc", c_int), ("length", c_double)]
+
+
+DISCS = {"fd": 0, "q1": 1}
 
 
 class Opts(ctypes.Structure):

@@ -75,7 +75,9 @@ class HeatProblem:
     Parameters follow the paper's problem statement (Sec. 2): ``dim``-D unit
     domain with ``n`` interior nodes per axis, ``s``-stage Radau IIA, ``nt``
     steps to final time ``T``; ``kappa`` optional nodal diffusivity (N values,
-    2D only).  Solver options: FGMRES ``restart``/``maxit``/``tol``, inner
+    2D only).  ``disc`` = "q1" selects bilinear finite elements with their
+    mass matrix on the square [0, length]^2 (2D, kappa = 1) in place of
+    finite differences.  Solver options: FGMRES ``restart``/``maxit``/``tol``, inner
     GMRES iterations ``inner_k``, V-cycles ``cycles`` with ``nu1``/``nu2``
     Jacobi sweeps, and the preconditioner ``precision``
     ("fp64" | "fp32" | "bf16" | "fp16" | "fp16_all", the last approach A4);
@@ -97,12 +99,14 @@ class HeatProblem:
     defaults are in SOLVER_DEFAULTS.
     """
 
-    def __init__(self, dim, n, s, nt, T=1.0, kappa=None, *, device="cuda", **solver):
+    def __init__(self, dim, n, s, nt, T=1.0, kappa=None, *, disc="fd", length=1.0, device="cuda", **solver):
         self._lib = _abi.load()
         self.dim, self.n, self.s, self.nt, self.T = dim, n, s, nt, float(T)
+        self.disc, self.length = disc, float(length)
         self._kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
         desc = _abi.Desc(dim, n, s, nt, float(T),
-                         None if self._kappa is None else self._kappa.ctypes.data)
+                         None if self._kappa is None else self._kappa.ctypes.data, _abi.DISCS[disc],
+                         float(length))
         o = _solver_options(solver)
         self.options = dict(o, device=device)
         opts = _make_opts(self._lib, o)
@@ -326,7 +330,8 @@ class HeatBatch:
             k = None if k is None else np.ascontiguousarray(k, dtype=np.float64)
             self._kappas.append(k)
             descs[i] = _abi.Desc(p["dim"], p["n"], p["s"], p["nt"], float(p.get("T", 1.0)),
-                                 None if k is None else k.ctypes.data)
+                                 None if k is None else k.ctypes.data, _abi.DISCS[p.get("disc", "fd")],
+                                 float(p.get("length", 1.0)))
         self.problems = [dict(p) for p in problems]
         o = _solver_options(solver)
         self.options = dict(o, device=device)

@@ -65,6 +65,8 @@ void plan_workspace(aao_problem* h) {
   P.mgritT = take(mgrit ? (size_t)(h->nt + 1) * N * pi : 0);
   P.mgritG = take(mgrit ? (size_t)Kc * N * pi : 0);
   P.mgritE = take(mgrit ? (size_t)Kc * N * pi : 0);
+  P.feA = take(h->fe ? (size_t)(h->nt + 1) * N * pi : 0);
+  P.feB = take(h->fe ? (size_t)(h->nt + 1) * N * pi : 0);
   P.mgX.assign(L, 0);
   P.mgT.assign(L, 0);
   P.mgB.assign(L, 0);
@@ -125,7 +127,7 @@ bool kappa_tables(aao_problem* h, const std::vector<double>& kappa, std::string&
         const double* Lf = (set & 1) ? h->LT : h->tab.L;
         const double a = (set >= 2 ? h->opts.mgrit_cf : 1) * h->tau * Lf[i * h->s + i];
         std::vector<double> inv;
-        if (!aao::coarse_inverse(h->dim, h->lev_n[lc], tri, a, lc == 0, h->ih2,
+        if (!aao::coarse_inverse(h->dim, h->lev_n[lc], tri, a, lc == 0 && !h->fe, h->ih2,
                                  kappa.empty() ? nullptr : faces.data(),
                                  (!kappa.empty() && lc > 0) ? st9[lc].data() : nullptr, inv)) {
           why = "singular coarsest multigrid level";
@@ -249,6 +251,15 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
   if (d->s < 1 || d->s > aao::SMAX) return fail(nullptr, AAO_INVALID_ARG, "s must be 1, 2 or 3");
   if (d->nt < 1 || d->nt > 65535) return fail(nullptr, AAO_INVALID_ARG, "nt must be in [1, 65535]");
   if (!(d->T > 0.0) || !std::isfinite(d->T)) return fail(nullptr, AAO_INVALID_ARG, "T must be > 0");
+  if (d->disc != AAO_DISC_FD && d->disc != AAO_DISC_Q1) return fail(nullptr, AAO_INVALID_ARG, "unknown disc");
+  if (d->disc == AAO_DISC_FD && d->length != 0.0 && d->length != 1.0)
+    return fail(nullptr, AAO_INVALID_ARG, "finite differences live on the unit domain (length 0 or 1)");
+  if (d->disc == AAO_DISC_Q1) {
+    if (d->dim != 2 || d->kappa) return fail(nullptr, AAO_INVALID_ARG, "Q1 elements: 2D and constant kappa");
+    if ((int64_t)(d->nt + 1) + (int64_t)d->nt * d->s > 65535)
+      return fail(nullptr, AAO_INVALID_ARG, "Q1 elements: (nt + 1) + nt s must be <= 65535");
+    if (d->length < 0.0 || !std::isfinite(d->length)) return fail(nullptr, AAO_INVALID_ARG, "length must be > 0");
+  }
   const double Nd = std::pow((double)d->n, d->dim);
   if (Nd > 1.5e9) return fail(nullptr, AAO_INVALID_ARG, "grid too large (N must fit in int32)");
   aao_opts opts;
@@ -259,6 +270,8 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
   if (opts.mgrit_cf == 0) opts.mgrit_cf = 8;
   if (opts.mgrit_iters == 0) opts.mgrit_iters = 1;
   if (opts.mgrit_iters > d->nt) return fail(nullptr, AAO_INVALID_ARG, "mgrit_iters must be <= nt");
+  if (d->disc == AAO_DISC_Q1 && (opts.nu1 > 3 || opts.nu2 > 3))
+    return fail(nullptr, AAO_INVALID_ARG, "Q1 elements: nu1, nu2 <= 3");
 
   aao_problem* h = new (std::nothrow) aao_problem();
   if (!h) return fail(nullptr, AAO_INVALID_ARG, "out of host memory");
@@ -268,7 +281,8 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
   h->nt = d->nt;
   h->T = d->T;
   h->tau = d->T / d->nt;
-  h->h = 1.0 / (d->n + 1);
+  h->fe = d->disc == AAO_DISC_Q1;
+  h->h = (h->fe && d->length > 0.0 ? d->length : 1.0) / (d->n + 1);
   h->ih2 = 1.0 / (h->h * h->h);
   h->N = (int64_t)std::llround(Nd);
   h->U = h->N * ((int64_t)d->nt * (d->s + 1) + 1);
@@ -325,7 +339,7 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
     return fail(nullptr, AAO_INVALID_ARG, "coarse_max above 256 needs 2D and constant kappa");
   }
   std::vector<std::vector<double>> tri;
-  aao::galerkin_1d(d->n, d->dim, h->h, cmax, h->lev_n, tri);
+  aao::galerkin_1d(d->n, d->dim, h->h, cmax, h->fe, h->lev_n, tri);
   h->lev_N.resize(h->lev_n.size());
   h->tri_off.assign(h->lev_n.size(), 0);
   for (size_t l = 0; l < h->lev_n.size(); ++l) {
@@ -524,6 +538,7 @@ int aao_solve_adjoint(aao_problem* h, const double* g, double* lam, aao_stats* s
 int aao_grad_logkappa(aao_problem* h, const double* x, const double* lam, double* g) {
   if (!h) return AAO_INVALID_ARG;
   if (!x || !lam || !g) return fail(h, AAO_INVALID_ARG, "null pointer");
+  if (h->fe) return fail(h, AAO_INVALID_ARG, "Q1 elements: the kappa gradient is not available");
   if (h->vark && !h->ws) return fail(h, AAO_NO_WORKSPACE, "aao_set_workspace first");
   return aao::status_from_hip(h, aao::launch_grad_logkappa(h, x, lam, g, h->stream), "grad_logkappa");
 }

@@ -8,6 +8,7 @@
 // consecutive x, and a workgroup covers whole rows, so each value is fetched
 // from HBM about once per launch.
 #include "aao_internal.h"
+#include "fe.h"
 #include "stencil.h"
 
 namespace aao {
@@ -457,6 +458,7 @@ static bool two_columns(int n, const TX* x, const double* y) {
 
 template <class TX>
 hipError_t launch_apply_A(const aao_problem* h, const TX* x, double* y, hipStream_t st) {
+  if (h->fe) return fe_apply_A<TX>(h, x, y, false, st);
   const int n = h->n, N = (int)h->N, nt = h->nt;
   Faces<double> fc = face_ptrs(h);
   if (h->dim == 2) {
@@ -481,6 +483,7 @@ hipError_t launch_apply_A(const aao_problem* h, const TX* x, double* y, hipStrea
 
 template <class TX>
 hipError_t launch_apply_AT(const aao_problem* h, const TX* x, double* y, hipStream_t st) {
+  if (h->fe) return fe_apply_A<TX>(h, x, y, true, st);
   const int n = h->n, N = (int)h->N, nt = h->nt;
   Faces<double> fc = face_ptrs(h);
   if (h->dim == 2) {
@@ -519,6 +522,7 @@ hipError_t launch_grad_logkappa(const aao_problem* h, const double* x, const dou
 
 hipError_t launch_assemble_rhs(const aao_problem* h, const double* f, const double* u0, double* rhs,
                                hipStream_t st) {
+  if (h->fe) return fe_assemble_rhs(h, f, u0, rhs, st);
   const int64_t N = h->N;
   hipError_t e = hipMemcpyAsync(rhs, u0, N * sizeof(double), hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) return e;

@@ -3,6 +3,7 @@
 // the Givens update of GMRES on device, and the stage-level operators used by
 // the preconditioner (Theta_hat, Rana coupling, S-tilde sweep pieces).
 #include "aao_internal.h"
+#include "fe.h"
 #include "krylov.h"
 #include "stencil.h"
 
@@ -534,6 +535,7 @@ hipError_t combine(TO* out, int64_t so, const TV* Z, int64_t vstride, int64_t sv
 template <class T>
 hipError_t theta_apply(const aao_problem* h, const Tab& tab, const T* z, int64_t sz, T* w, int64_t sw, int B,
                        hipStream_t st) {
+  if (h->fe) return fe_theta_apply<T>(h, tab, z, sz, w, sw, B, st);
   using C = typename Acc<T>::type;
   const dim3 g = pts_grid(h->N, B);
   const Faces<C> fc = faces_of<C>(h);
@@ -552,6 +554,7 @@ hipError_t rana_rhs(const aao_problem* h, const double* Lc, int i, const T* v, i
   using C = typename Acc<T>::type;
   Tab tab = h->tab;
   for (int q = 0; q < h->s * h->s; ++q) tab.L[q] = Lc[q];
+  if (h->fe) return fe_rana_rhs<T>(h, tab, i, v, sv, z, sz, out, so, B, st);
   const dim3 g = pts_grid(h->N, B);
   const Faces<C> fc = faces_of<C>(h);
   const int n = h->n, N = (int)h->N, ns = h->s;
@@ -568,6 +571,7 @@ hipError_t rana_rhs(const aao_problem* h, const double* Lc, int i, const T* v, i
 
 template <class T>
 hipError_t schur_coupling(const aao_problem* h, const double* r, const T* zV, T* t, hipStream_t st) {
+  if (h->fe) return fe_schur_coupling<T>(h, r, zV, t, st);
   hipLaunchKernelGGL((k_schur_coupling<T>), pts_grid(h->N, h->nt + 1), dim3(TPB), 0, st, r, zV, t, (int)h->N, h->s,
                      h->tab);
   return hipGetLastError();
@@ -575,6 +579,7 @@ hipError_t schur_coupling(const aao_problem* h, const double* r, const T* zV, T*
 
 template <class T>
 hipError_t schur_kz(const aao_problem* h, const T* zin, int64_t szin, T* out, int64_t sout, int B, hipStream_t st) {
+  if (h->fe) return fe_schur_kz<T>(h, zin, szin, out, sout, B, st);
   using C = typename Acc<T>::type;
   const Faces<C> fc = faces_of<C>(h);
   const dim3 g = pts_grid(h->N, B);

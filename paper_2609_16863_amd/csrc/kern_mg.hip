@@ -1802,7 +1802,7 @@ hipError_t Multigrid<TI, TM>::tail(int stage, Vec x, Vec b, bool zero_init, int 
   if (tail_bytes_ > h_->lds_budget) return hipErrorInvalidValue;
   TailArgs<C> ta{};
   ta.nl = levels_ - l0_;
-  ta.first_fine = l0_ == 0;
+  ta.first_fine = l0_ == 0 && !h_->fe;   // Q1: level 0 is a tensor level too
   ta.zero_init = zero_init;
   ta.nu1 = h_->opts.nu1;
   ta.nu2 = h_->opts.nu2;
@@ -1878,7 +1878,11 @@ hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, in
   if (l == 0)
     return typed1(1, [&](auto tc) {
       using TC = decltype(tc);
-      if (h_->vark) DN_Z(KIND_FINE_VK); else DN_Z(KIND_FINE);
+      // Q1 elements: level 0 is the tensor form M1(x)M1 + a (T(x)M1 + M1(x)T)
+      // of the 1D element matrices (Rana's coupling formed separately)
+      if (h_->fe) DN_NU(KIND_TENSOR, TI, 0, ca);
+      else if (h_->vark) DN_Z(KIND_FINE_VK);
+      else DN_Z(KIND_FINE);
       return hipGetLastError();
     });
   return typed2(l, [&](auto tf, auto tc) {
@@ -1912,7 +1916,9 @@ hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec
   if (l == 0)
     return typed1(1, [&](auto tc) {
       using TC = decltype(tc);
-      if (h_->vark) UP_NU(KIND_FINE_VK, TI); else UP_NU(KIND_FINE, TI);
+      if (h_->fe) UP_NU(KIND_TENSOR, TI);
+      else if (h_->vark) UP_NU(KIND_FINE_VK, TI);
+      else UP_NU(KIND_FINE, TI);
       return hipGetLastError();
     });
   return typed2(l, [&](auto tf, auto tc) {
@@ -2052,7 +2058,8 @@ hipError_t Multigrid<TI, TM>::solve(int stage, BVec<TI> x, BVec<const TI> rhs, i
                                     const Coupling* cpl) {
   Vec xv{x.ptr, x.stride};
   Vec bv{const_cast<TI*>(rhs.ptr), rhs.stride};
-  const bool fused = cpl && cpl->nz > 0 && h_->dim == 2 && h_->opts.nu1 <= 3 && h_->opts.nu2 <= 3 && l0_ > 0;
+  const bool fused = cpl && cpl->nz > 0 && h_->dim == 2 && h_->opts.nu1 <= 3 && h_->opts.nu2 <= 3 && l0_ > 0 &&
+                     !h_->fe;
   if (cpl && cpl->nz > 0 && !fused) {
     // the level-0 kernel that would form the coupling does not run: form it first
     MG_TRY(rana_rhs<TI>(h_, cpl->Lc, cpl->nz, rhs.ptr, rhs.stride, cpl->z, cpl->sz, cpl->out, cpl->so, B, st_));

@@ -116,23 +116,29 @@ void crout_lower(int s, const double* A, double* L) {
 }
 
 // 1D Galerkin factors of the hierarchy.  Level 0: M_0 = I,
-// T_0 = tridiag(-1, 2, -1)/h^2 on n nodes.  Coarse nodes are the fine nodes
+// T_0 = tridiag(-1, 2, -1)/h^2 on n nodes for finite differences; for
+// bilinear elements (fe) the 1D mass and stiffness matrices
+// M_0 = h tridiag(1/6, 2/3, 1/6), T_0 = tridiag(-1, 2, -1)/h, whose tensor
+// form M(x)M + a (T(x)M + M(x)T) is the Q1 matrix M + a K.  Coarse nodes are the fine nodes
 // 2, 4, ..., 2 floor(n/2) (1-based), P is linear interpolation (zero
 // boundary values), and M_{l+1} = P^T M_l P / 2, T_{l+1} = P^T T_l P / 2, so
 // that in d dimensions R = P^T / 2^d and the Galerkin operator R A_l P of
 // A_l = M(x)M + a (T(x)M + M(x)T) is again of that form.  Coarsening stops
 // once a level has at most coarse_max nodes (that level is solved exactly).
 // tri[l] = [Mlo, Md, Mup, Tlo, Td, Tup], each n_l long (level 0 included).
-void galerkin_1d(int n, int dim, double h, int coarse_max, std::vector<int>& sizes,
+void galerkin_1d(int n, int dim, double h, int coarse_max, bool fe, std::vector<int>& sizes,
                  std::vector<std::vector<double>>& tri) {
   sizes.assign(1, n);
   int nf = n;
   std::vector<double> M(nf * nf, 0.0), T(nf * nf, 0.0);
+  const double ts = fe ? 1.0 / h : 1.0 / (h * h);
   for (int i = 0; i < nf; ++i) {
-    M[i * nf + i] = 1.0;
-    T[i * nf + i] = 2.0 / (h * h);
-    if (i > 0) T[i * nf + i - 1] = -1.0 / (h * h);
-    if (i + 1 < nf) T[i * nf + i + 1] = -1.0 / (h * h);
+    M[i * nf + i] = fe ? 2.0 * h / 3.0 : 1.0;
+    if (fe && i > 0) M[i * nf + i - 1] = h / 6.0;
+    if (fe && i + 1 < nf) M[i * nf + i + 1] = h / 6.0;
+    T[i * nf + i] = 2.0 * ts;
+    if (i > 0) T[i * nf + i - 1] = -ts;
+    if (i + 1 < nf) T[i * nf + i + 1] = -ts;
   }
   auto pack = [](const std::vector<double>& Mx, const std::vector<double>& Tx, int m) {
     std::vector<double> t(6 * m, 0.0);

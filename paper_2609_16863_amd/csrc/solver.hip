@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "aao_internal.h"
+#include "fe.h"
 #include "krylov.h"
 #include "mg.h"
 
@@ -87,6 +88,8 @@ class Precond {
     mt_ = reinterpret_cast<TI*>(ws + h->plan.mgritT);
     mg_g_ = reinterpret_cast<TI*>(ws + h->plan.mgritG);
     mg_e_ = reinterpret_cast<TI*>(ws + h->plan.mgritE);
+    fea_ = reinterpret_cast<TI*>(ws + h->plan.feA);
+    feb_ = reinterpret_cast<TI*>(ws + h->plan.feB);
     partial_ = reinterpret_cast<double*>(ws + h->plan.partial);
     slots_ = reinterpret_cast<double*>(ws + h->plan.dscal);
     counters_ = reinterpret_cast<unsigned*>(ws + h->plan.counters);
@@ -268,7 +271,10 @@ class Precond {
 
   hipError_t schur_phase(const double* r, TI* z) {
     (void)r;
-    const TI* t = coarse_ ? mt_ : z;
+    TI* t = coarse_ ? mt_ : z;
+    // Q1 elements: S-tilde = blockdiag(M) times the bidiagonal recurrence;
+    // its block-diagonal mass solve first (Chebyshev, Sec. 5), in place
+    if (h_->fe) TRY(fe_mass_solve<TI>(h_, t, fea_, feb_, h_->nt + 1, st_));
     return schur_solve<TI>(t, h_->N, z, h_->N);
   }
 
@@ -295,7 +301,7 @@ class Precond {
   int k_, cycles_;
   Stepper fine_;
   std::unique_ptr<Stepper> coarse_;
-  TI *inV_, *inZ_, *inW_, *inX_, *rana_, *srhs_, *sy_, *mt_, *mg_g_, *mg_e_;
+  TI *inV_, *inZ_, *inW_, *inX_, *rana_, *srhs_, *sy_, *mt_, *mg_g_, *mg_e_, *fea_, *feb_;
   double *partial_, *slots_;
   unsigned* counters_;
 };
@@ -1020,6 +1026,10 @@ int apply_P(aao_problem* h, const double* r, double* z, int inner_k, int cycles,
 }
 
 int solve(aao_problem* h, const double* rhs, double* x, aao_stats* st, bool transpose) {
+  if (transpose && h->fe) {
+    h->err = "Q1 elements: the transposed solve is not available";
+    return AAO_INVALID_ARG;
+  }
   if (h->opts.precision == AAO_PREC_FP64) {
     Fgmres<double> F(h, transpose);
     return F.run(rhs, x, st);

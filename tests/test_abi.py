@@ -211,3 +211,34 @@ def test_binding_rejects_unknown_solver_options():
     abi, lib = _lib()
     opts = binding._make_opts(lib, o)
     assert opts.outer_precision == 1 and opts.restart == 30
+
+
+@pytest.mark.parametrize("bad", [dict(disc=2), dict(disc=1, dim=3), dict(disc=1, kappa=True), dict(length=2.0),
+                                 dict(disc=1, nu1=4), dict(disc=1, length=-1.0)])
+def test_q1_descriptions_are_checked(bad):
+    abi, lib = _lib()
+    opts = abi.Opts()
+    lib.aao_default_opts(ctypes.byref(opts))
+    if "nu1" in bad:
+        opts.nu1 = bad["nu1"]
+    dim = bad.get("dim", 2)
+    n = 6
+    kap = np.ones(n ** dim) if bad.get("kappa") else None
+    desc = abi.Desc(dim, n, 2, 3, 1.0, None if kap is None else kap.ctypes.data, bad.get("disc", 0),
+                    bad.get("length", 0.0))
+    h = ctypes.c_void_p()
+    assert lib.aao_create_problem(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h)) == -1
+    assert not h.value
+
+
+def test_q1_handle_sizes_and_levels():
+    abi, lib = _lib()
+    opts = abi.Opts()
+    lib.aao_default_opts(ctypes.byref(opts))
+    desc = abi.Desc(2, 31, 2, 13, 2.0, None, 1, 2.0)
+    h = ctypes.c_void_p()
+    assert lib.aao_create_problem(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h)) == 0
+    N, U = ctypes.c_int64(), ctypes.c_int64()
+    lib.aao_sizes(h, ctypes.byref(N), ctypes.byref(U))
+    assert U.value == 38440          # Table 1, Q1, s = 2, l = 5
+    lib.aao_destroy(h)
