@@ -364,7 +364,7 @@ def measure_apply_A(hp, x, reps):
     sec = _event_time(lambda: hp.apply_A(x, y), reps)
     nbytes = 16.0 * hp.U
     gbs = nbytes / sec / 1e9
-    return {"kernel": "k_apply_A_2d" if hp.dim == 2 else "k_apply_A", "bound": "hbm", "achieved": gbs,
+    return {"kernel": "k_apply_A_2d" if hp.dim == 2 else "k_apply_A_3d", "bound": "hbm", "achieved": gbs,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
             "bytes_per_launch": nbytes, "avg_launch_us": sec * 1e6}
 
@@ -564,10 +564,12 @@ def extras(args, autotune):
         log(f"3D {prec}: {np.mean(times) * 1e3:.0f} ms, {st['outer_iterations']} its")
         res3[prec] = {"solve_s": float(np.mean(times)), "outer_iterations": st["outer_iterations"],
                       "relres": st["relres"], "theta_ms": st["theta_ms"], "schur_ms": st["schur_ms"]}
+        if prec == "fp64":
+            apply3 = measure_apply_A(hp, rhs, args.roofline_reps)
         del hp, rhs
         torch.cuda.empty_cache()
     out[w3.name] = {"unknowns": w3.n ** 3 * (w3.nt * (w3.s + 1) + 1), "restart": w3.restart, "inner_k": 3,
-                    "schur": args.schur, "solves": res3}
+                    "schur": args.schur, "solves": res3, "roofline_apply_A": apply3}
     specs = heat_inputs.batch_problem_specs()
     data = []
     for sp in specs:

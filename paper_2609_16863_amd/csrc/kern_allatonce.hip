@@ -219,6 +219,155 @@ __global__ __launch_bounds__(TPB) void k_apply_A_2d(const TX* __restrict__ x, do
   }
 }
 
+// 3D variant (constant kappa): the 64 lanes of a wave own W * 64 adjacent x
+// positions of one row (j, plane k) of one step, the four waves of a
+// workgroup four consecutive rows j, and each thread marches along z over
+// ZR planes with a register window of planes k-1 .. k+2 of every input
+// field (plane k+2 is fetched while plane k is computed).  x neighbours
+// come from the adjacent lanes; the y neighbours (rows j +- 1 of plane k)
+// are loaded directly: the sibling waves fetch those rows for themselves at
+// the same time, so they come from L2.  Per value and field: one streamed
+// load and two cached ones, against seven for one thread per node.
+constexpr int ZR = 32;
+constexpr int TPB3 = 512;
+constexpr int RWG = TPB3 / 64;   // rows (waves) per workgroup
+
+// Workgroup b of the 1D grid takes logical tile xcd_tile(b, B), ordered x
+// block fastest, then row group, z chunk and step: each XCD walks a
+// contiguous range, so the rows j +- 1 a workgroup reads from its
+// neighbours' row groups sit in the same L2.
+template <int W>
+struct March3D {
+  int n, i, j, lane, step, k0, k1, eoff, xb;
+  bool live, edge;
+  __device__ March3D(int n_, int xblocks, int jgroups, int zchunks) : n(n_) {
+    int t = xcd_tile(blockIdx.x, gridDim.x);
+    xb = t % xblocks;
+    t /= xblocks;
+    const int jg = t % jgroups;
+    t /= jgroups;
+    const int zc = t % zchunks;
+    step = t / zchunks;
+    lane = threadIdx.x & 63;
+    i = (xb * 64 + lane) * W;
+    j = jg * RWG + (threadIdx.x >> 6);
+    k0 = zc * ZR;
+    k1 = k0 + ZR < n ? k0 + ZR : n;
+    live = i < n && j < n;
+    eoff = lane == 0 ? -1 : W;
+    edge = live && ((lane == 0 && i > 0) || (lane == 63 && i + W < n));
+  }
+  // the whole wave has no node (wave-uniform: j and the x range per wave)
+  __device__ bool idle() const { return j >= n || xb * 64 * W >= n; }
+  // row (jr, plane kr) of field f at this thread's columns; zero outside
+  // the grid and for planes past kmax
+  template <class TX>
+  __device__ void row(const TX* f, int jr, int kr, int kmax, double* out) const {
+    if (live && jr >= 0 && jr < n && kr >= 0 && kr <= kmax && kr < n) {
+      ldw<W>(f + ((int64_t)kr * n + jr) * n + i, out);
+    } else {
+#pragma unroll
+      for (int c = 0; c < W; ++c) out[c] = 0.0;
+    }
+  }
+  template <class TX>
+  __device__ double edge_val(const TX* f, int kr, int kmax) const {
+    return (edge && kr <= kmax) ? ld<TX, double>(f + ((int64_t)kr * n + j) * n + i + eoff) : 0.0;
+  }
+  __device__ double left(const double* r, double e, int c) const {
+    if (c > 0) return r[c - 1];
+    const double s = __shfl_up(r[W - 1], 1);
+    return lane == 0 ? e : s;
+  }
+  __device__ double right(const double* r, double e, int c) const {
+    if (c < W - 1) return r[c + 1];
+    const double s = __shfl_down(r[0], 1);
+    return lane == 63 ? e : s;
+  }
+};
+
+template <int S, int W, class TX>
+__global__ __launch_bounds__(TPB3) void k_apply_A_3d(const TX* __restrict__ x, double* __restrict__ y, int n, int nt,
+                                                     int xblocks, int jgroups, int zchunks, double ih2, Tab tab) {
+  const March3D<W> m(n, xblocks, jgroups, zchunks);
+  if (m.idle()) return;
+  const int step = m.step;
+  const int64_t N = (int64_t)n * n * n;
+  constexpr int F = S + 1;  // v_n and the S stage fields
+  const TX* fld[F];
+  fld[0] = x + (int64_t)step * N;
+#pragma unroll
+  for (int q = 0; q < S; ++q) fld[q + 1] = x + ((int64_t)(nt + 1) + (int64_t)step * S + q) * N;
+  const TX* vn = x + (int64_t)(step + 1) * N;
+  double* yV = y + ((int64_t)(nt + 1) + (int64_t)step * S) * N;
+  double* yv = y + (int64_t)(step + 1) * N;
+  const int kl = m.k1;  // last plane any window needs
+  double r0[F][W], r1[F][W], r2[F][W], r3[F][W], e0[F], e1[F], w0[W], w1[W];
+#pragma unroll
+  for (int q = 0; q < F; ++q) {
+    m.row(fld[q], m.j, m.k0 - 1, kl, r0[q]);
+    m.row(fld[q], m.j, m.k0, kl, r1[q]);
+    m.row(fld[q], m.j, m.k0 + 1, kl, r2[q]);
+    e0[q] = m.edge_val(fld[q], m.k0, kl);
+  }
+  m.row(vn, m.j, m.k0, kl, w0);
+  for (int kp = m.k0; kp < m.k1; ++kp) {
+    double ym[F][W], yp[F][W];
+#pragma unroll
+    for (int q = 0; q < F; ++q) {
+      m.row(fld[q], m.j, kp + 2, kl, r3[q]);
+      e1[q] = m.edge_val(fld[q], kp + 1, m.k1 - 1);
+      m.row(fld[q], m.j - 1, kp, kl, ym[q]);
+      m.row(fld[q], m.j + 1, kp, kl, yp[q]);
+    }
+    m.row(vn, m.j, kp + 1, m.k1 - 1, w1);
+    const int64_t p = ((int64_t)kp * n + m.j) * n + m.i;
+    double KF[F][W];
+#pragma unroll
+    for (int q = 0; q < F; ++q)
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+        KF[q][c] = ih2 * (6.0 * r1[q][c] - m.left(r1[q], e0[q], c) - m.right(r1[q], e0[q], c) - ym[q][c] -
+                          yp[q][c] - r0[q][c] - r2[q][c]);
+    if (m.live) {
+      double yvv[W];
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        double upd = 0.0;
+#pragma unroll
+        for (int r = 0; r < S; ++r) upd += tab.b[r] * r1[r + 1][c];
+        yvv[c] = w0[c] - r1[0][c] - tab.tau * upd;
+      }
+#pragma unroll
+      for (int r = 0; r < S; ++r) {
+        double out[W];
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+          double mix = 0.0;
+#pragma unroll
+          for (int q = 0; q < S; ++q) mix += tab.A[r * S + q] * KF[q + 1][c];
+          out[c] = r1[r + 1][c] + KF[0][c] + tab.tau * mix;
+        }
+        stw<W>(yV + (int64_t)r * N + p, out);
+      }
+      stw<W>(yv + p, yvv);
+      if (step == 0) stw<W>(y + p, r1[0]);
+    }
+#pragma unroll
+    for (int q = 0; q < F; ++q) {
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        r0[q][c] = r1[q][c];
+        r1[q][c] = r2[q][c];
+        r2[q][c] = r3[q][c];
+      }
+      e0[q] = e1[q];
+    }
+#pragma unroll
+    for (int c = 0; c < W; ++c) w0[c] = w1[c];
+  }
+}
+
 // Transposed, 2D marching form (see k_apply_A_2d).
 template <int S, bool VK, int W, class TX>
 __global__ __launch_bounds__(TPB) void k_apply_AT_2d(const TX* __restrict__ x, double* __restrict__ y, int n, int nt,
@@ -471,6 +620,23 @@ hipError_t launch_apply_A(const aao_problem* h, const TX* x, double* y, hipStrea
   } while (0)
     DISPATCH_SV(h->s, h->vark, AAO_A2);
 #undef AAO_A2
+    return hipGetLastError();
+  }
+  if (h->dim == 3 && !h->vark) {
+    const int W = two_columns(n, x, y) ? 2 : 1;
+    const int xblocks = (n + 64 * W - 1) / (64 * W), jgroups = (n + RWG - 1) / RWG, zchunks = (n + ZR - 1) / ZR;
+    const dim3 g3((unsigned)((int64_t)xblocks * jgroups * zchunks * nt));
+#define AAO_A3(S, V)                                                                                          \
+  do {                                                                                                       \
+    if (W == 2)                                                                                              \
+      hipLaunchKernelGGL((k_apply_A_3d<S, 2, TX>), g3, dim3(TPB3), 0, st, x, y, n, nt, xblocks, jgroups, zchunks, \
+                         h->ih2, h->tab);                                                                    \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_apply_A_3d<S, 1, TX>), g3, dim3(TPB3), 0, st, x, y, n, nt, xblocks, jgroups, zchunks, \
+                         h->ih2, h->tab);                                                                    \
+  } while (0)
+    DISPATCH_SV(h->s, false, AAO_A3);
+#undef AAO_A3
     return hipGetLastError();
   }
   dim3 grid((unsigned)((h->N + TPB - 1) / TPB), (unsigned)h->nt);

@@ -12,7 +12,10 @@ pytestmark = pytest.mark.gpu
 CASES = [(2, 3, 1, 3, False), (2, 4, 2, 4, True), (2, 5, 3, 2, False), (3, 3, 2, 3, False),
          (3, 3, 3, 2, True), (2, 37, 3, 5, False), (2, 37, 2, 5, True), (3, 11, 3, 3, False),
          # 2D row-marching tiles (64 rows; 512 columns for even n, 256 for odd n), ragged in x and y
-         (2, 300, 3, 2, False), (2, 270, 2, 2, True), (2, 530, 1, 1, False), (2, 301, 1, 2, True)]
+         (2, 300, 3, 2, False), (2, 270, 2, 2, True), (2, 530, 1, 1, False), (2, 301, 1, 2, True),
+         # 3D z-marching (32 planes per thread, 64 x 2 columns per wave for even n, 64 for odd n):
+         # ragged x, y and z; several x blocks
+         (3, 40, 3, 2, False), (3, 33, 2, 2, False), (3, 130, 1, 1, False), (3, 67, 2, 1, False)]
 
 
 def _setup(dim, n, s, nt, vk, seed):
