@@ -166,7 +166,7 @@ __global__ __launch_bounds__(TPB) void k_smooth(const T* __restrict__ xin, int64
 template <int DIM, class TX, class TE, class C>
 __global__ __launch_bounds__(TPB) void k_prolong(const TX* xin, int64_t sxin, const TE* __restrict__ ec,
                                                  int64_t sec, TX* xout, int64_t sxout, int nf, int Nf,
-                                                 int nc) {
+                                                 int nc, C escale) {
   const int p = blockIdx.x * TPB + threadIdx.x;
   if (p >= Nf) return;
   const int64_t inst = blockIdx.y;
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(TPB) void k_prolong(const TX* xin, int64_t sxin, co
           acc += wt[0][a] * wt[1][b] * wt[2][q] *
                  ld<TE, C>(e + ((int64_t)idx[2][q] * nc + idx[1][b]) * nc + idx[0][a]);
   }
-  st<TX, C>(xout + inst * sxout + p, ld<TX, C>(xin + inst * sxin + p) + acc);
+  st<TX, C>(xout + inst * sxout + p, ld<TX, C>(xin + inst * sxin + p) + escale * acc);
 }
 
 // (P e)(i, j[, k]): linear interpolation of the coarse correction at a fine
@@ -273,6 +273,61 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict(const TF* __restrict__ x
         level_apply<DIM, KIND, TF, C>(xi, opf, pf, ii, jj, DIM == 3 ? kk : 0, Ax, d);
         const C wt = DIM == 3 ? w[di + 1] * w[dj + 1] * w[dk + 1] : w[di + 1] * w[dj + 1];
         acc += wt * (ld<TF, C>(bi + pf) - Ax);
+      }
+    }
+  }
+  acc *= (DIM == 3 ? C(0.125) : C(0.25)) * bscale;
+  st<TC, C>(bc + inst * sbc + pc, acc);
+  if (zero_next) st<TC, C>(xc + inst * sxc + pc, omega * acc / level_diag<DIM, KIND_TENSOR, C>(opc, pc, I, J, K));
+}
+
+// r = b - A x at every node of a level (3D: the residual is formed once per
+// node, then restricted by k_restrict; forming it at the 27 fine nodes
+// around each coarse node would apply the 27-point operator 27 times).
+template <int DIM, int KIND, class TF, class C>
+__global__ __launch_bounds__(TPB) void k_residual(const TF* __restrict__ x, int64_t sx, const TF* __restrict__ b,
+                                                  int64_t sb, TF* __restrict__ r, int64_t sr, LevelOp<C> op) {
+  const int p = blockIdx.x * TPB + threadIdx.x;
+  if (p >= op.N) return;
+  const int64_t inst = blockIdx.y;
+  int i, j, k;
+  node_coords<DIM>(p, op.n, i, j, k);
+  C Ax, d;
+  level_apply<DIM, KIND, TF, C>(x + inst * sx, op, p, i, j, k, Ax, d);
+  st<TF, C>(r + inst * sr + p, ld<TF, C>(b + inst * sb + p) - Ax);
+}
+
+// Full weighting of a residual: b_c = 2^{-d} sum w(d) r(2I+1+d), scaled by
+// bscale; with `zero_next` also the coarse level's first Jacobi sweep from
+// zero, x_c = omega b_c / D_c.
+template <int DIM, class TF, class TC, class C>
+__global__ __launch_bounds__(TPB) void k_restrict(const TF* __restrict__ r, int64_t sr, TC* __restrict__ bc,
+                                                  int64_t sbc, TC* __restrict__ xc, int64_t sxc, int nf,
+                                                  LevelOp<C> opc, C omega, int zero_next, C bscale) {
+  const int pc = blockIdx.x * TPB + threadIdx.x;
+  if (pc >= opc.N) return;
+  const int64_t inst = blockIdx.y;
+  int I, J, K;
+  node_coords<DIM>(pc, opc.n, I, J, K);
+  const TF* ri = r + inst * sr;
+  const C w[3] = {C(0.5), C(1), C(0.5)};
+  const int fi = 2 * I + 1, fj = 2 * J + 1, fk = 2 * K + 1;
+  const int dk0 = DIM == 3 ? -1 : 0, dk1 = DIM == 3 ? 1 : 0;
+  C acc = C(0);
+  for (int dk = dk0; dk <= dk1; ++dk) {
+    const int kk = fk + dk;
+    if (DIM == 3 && kk >= nf) continue;
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int jj = fj + dj;
+      if (jj >= nf) continue;
+#pragma unroll
+      for (int di = -1; di <= 1; ++di) {
+        const int ii = fi + di;
+        if (ii >= nf) continue;
+        const int pf = DIM == 3 ? (kk * nf + jj) * nf + ii : jj * nf + ii;
+        const C wt = DIM == 3 ? w[di + 1] * w[dj + 1] * w[dk + 1] : w[di + 1] * w[dj + 1];
+        acc += wt * ld<TF, C>(ri + pf);
       }
     }
   }
@@ -1701,6 +1756,28 @@ hipError_t Multigrid<TI, TM>::resid_restrict(int l, int stage, Vec x, Vec b, Vec
   const C omega = (C)h_->omega;
   const dim3 g = grid2(opc.N, B);
   const int d3 = h_->dim == 3, z = (int)zero_next;
+  if (d3) {
+    // residual once per fine node into the level's residual buffer, then
+    // the full weighting (3D has constant kappa: tensor or fine operator)
+    Vec r{h_->ws + h_->plan.mgR[l], (int64_t)opf.N};
+    const C bs = l == 0 ? (C)h_->mg_scale : C(1);
+    const dim3 gf = grid2(opf.N, B);
+    return typed2(l, [&](auto tf, auto tc) {
+      using TF = decltype(tf);
+      using TC = decltype(tc);
+      if (l == 0)
+        hipLaunchKernelGGL((k_residual<3, KIND_FINE, TF, C>), gf, dim3(TPB), 0, st_, (const TF*)x.ptr, x.stride,
+                           (const TF*)b.ptr, b.stride, (TF*)r.ptr, r.stride, opf);
+      else
+        hipLaunchKernelGGL((k_residual<3, KIND_TENSOR, TF, C>), gf, dim3(TPB), 0, st_, (const TF*)x.ptr, x.stride,
+                           (const TF*)b.ptr, b.stride, (TF*)r.ptr, r.stride, opf);
+      MG_TRY(hipGetLastError());
+      MG_TRY(mark("k_residual", l));
+      hipLaunchKernelGGL((k_restrict<3, TF, TC, C>), g, dim3(TPB), 0, st_, (const TF*)r.ptr, r.stride, (TC*)bc.ptr,
+                         bc.stride, (TC*)xc.ptr, xc.stride, opf.n, opc, omega, z, bs);
+      return hipGetLastError();
+    });
+  }
   if (l == 0) {
     const C bs = (C)h_->mg_scale;
     return typed1(1, [&](auto tc) {
@@ -1726,16 +1803,18 @@ hipError_t Multigrid<TI, TM>::prolong(int l, Vec xin, Vec ec, Vec xout, int B) {
   const int nf = h_->lev_n[l], nc = h_->lev_n[l + 1];
   const int Nf = (int)h_->lev_N[l];
   const dim3 g = grid2(Nf, B);
-  // only coarse grid levels use the separate prolongation (level 0 fuses it)
+  // the coarse grid levels, and level 0 in 3D (2D fuses it into the first
+  // post-smoothing sweep); at level 0 the FP16 levels' scale is removed
+  const C es = l == 0 ? (C)(1.0 / h_->mg_scale) : C(1);
   return typed2(l, [&](auto tf, auto tc) {
     using TF = decltype(tf);
     using TC = decltype(tc);
     if (h_->dim == 2)
       hipLaunchKernelGGL((k_prolong<2, TF, TC, C>), g, dim3(TPB), 0, st_, (const TF*)xin.ptr, xin.stride,
-                         (const TC*)ec.ptr, ec.stride, (TF*)xout.ptr, xout.stride, nf, Nf, nc);
+                         (const TC*)ec.ptr, ec.stride, (TF*)xout.ptr, xout.stride, nf, Nf, nc, es);
     else
       hipLaunchKernelGGL((k_prolong<3, TF, TC, C>), g, dim3(TPB), 0, st_, (const TF*)xin.ptr, xin.stride,
-                         (const TC*)ec.ptr, ec.stride, (TF*)xout.ptr, xout.stride, nf, Nf, nc);
+                         (const TC*)ec.ptr, ec.stride, (TF*)xout.ptr, xout.stride, nf, Nf, nc, es);
     return hipGetLastError();
   });
 }
@@ -1996,7 +2075,7 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
   auto partner = [&](const Vec& v) { return v.ptr == x.ptr ? tmp : x; };
   // writes after the first sweep alternate buffers; at level 0 the result
   // must end in x, so the first sweep's target is chosen by parity
-  const bool fused_post = (l == 0);
+  const bool fused_post = (l == 0) && h_->dim == 2;
   Vec cur = x;
   int rem = nu1;
   if (zero_init) {
@@ -2020,7 +2099,7 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
   Vec xc{h_->ws + P.mgX[l + 1], Nc};
   const bool next_grid = (l + 1) < l0_;
   MG_TRY(resid_restrict(l, stage, cur, b, bc, xc, next_grid, B));
-  MG_TRY(mark("k_resid_restrict", l));
+  MG_TRY(mark(h_->dim == 3 ? "k_restrict" : "k_resid_restrict", l));
   Vec ec{};
   MG_TRY(vcycle(l + 1, stage, xc, bc, true, next_grid, B, &ec));
   int post = nu2;
