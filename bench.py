@@ -400,14 +400,14 @@ def _kernel_matches(name, base, level0):
 
 
 def traffic_summary(fetch_csv, write_csv, roof_json):
-    """Markdown summary of the HBM traffic of the dominant kernel group from
-    two counter runs of `bench.py --roofline-only` (FETCH_SIZE, WRITE_SIZE),
+    """Markdown summary of the HBM traffic of every V-cycle kernel group (the
+    benchmark's dominant kernel is one of them) and of apply_A from two
+    counter runs of `bench.py --roofline-only` (FETCH_SIZE, WRITE_SIZE),
     scaled by what the counters read for the 1 GiB copy in the same runs."""
+    import hashlib
     import statistics
     roof = json.loads([ln for ln in open(roof_json) if ln.startswith("{")][-1])
     prof = roof["vcycle_kernels"]
-    dom = prof["dominant"]
-    grp = prof["by_kernel"][dom]
     fetch, write = _counter_rows(fetch_csv, "FETCH_SIZE"), _counter_rows(write_csv, "WRITE_SIZE")
     nbytes = roof["copy_reference"]["bytes"]
 
@@ -421,29 +421,34 @@ def traffic_summary(fetch_csv, write_csv, roof_json):
     w_scale = nbytes / 1024 / copy_kib(write)
     lines = [f"copy reference: {nbytes:,} B read and written; FETCH_SIZE reads {copy_kib(fetch):,.0f} KiB "
              f"(scale {f_scale:.3f}), WRITE_SIZE {copy_kib(write):,.0f} KiB (scale {w_scale:.3f})", "",
-             "| launch | blocks | workgroups | launches per P-tilde | FETCH_SIZE KiB | WRITE_SIZE KiB "
-             "| scaled bytes | algorithmic bytes | ratio |", "|---|---|---|---|---|---|---|---|---|"]
-    base = dom.split("<")[0]
-    level0 = "<level 0" in dom
-    tot_w = tot_meas = tot_alg = 0.0
-    for m in grp["members"]:
-        if m["workgroups"] is None:
-            raise SystemExit(f"no grid size known for {m['label']}")
-        fv = [v for name, wg, v in fetch if wg == m["workgroups"] and _kernel_matches(name, base, level0)]
-        wv = [v for name, wg, v in write if wg == m["workgroups"] and _kernel_matches(name, base, level0)]
-        if not fv or not wv:
-            raise SystemExit(f"no dispatch of {base} with {m['workgroups']} workgroups")
-        fk, wk = statistics.median(fv), statistics.median(wv)
-        meas = fk * 1024 * f_scale + wk * 1024 * w_scale
-        alg = m["bytes_per_launch"]
-        lines.append(f"| `{m['label']}` | {m['blocks']} | {m['workgroups']} | {m['weight']:g} | {fk:,.0f} | "
-                     f"{wk:,.0f} | {meas:,.0f} | {alg:,.0f} | {meas / alg:.3f} |")
-        tot_w += m["weight"]
-        tot_meas += m["weight"] * meas
-        tot_alg += m["weight"] * alg
-    per_launch = tot_meas / tot_w
-    lines += ["", f"{dom}: {per_launch:,.0f} B per launch measured, {tot_alg / tot_w:,.0f} B algorithmic "
-              f"(launches weighted by their count per P-tilde application; ratio {tot_meas / tot_alg:.3f})", ""]
+             f"dominant kernel group in this run: {prof['dominant']}", "",
+             "| group | launch | blocks | workgroups | launches per P-tilde | FETCH_SIZE KiB | WRITE_SIZE KiB "
+             "| scaled bytes | algorithmic bytes | ratio |", "|---|---|---|---|---|---|---|---|---|---|"]
+    per_group = {}
+    for sym, grp in sorted(prof["by_kernel"].items()):
+        base = sym.split("<")[0]
+        level0 = "<level 0" in sym
+        tot_w = tot_meas = tot_alg = 0.0
+        for m in grp["members"]:
+            if m["workgroups"] is None:
+                raise SystemExit(f"no grid size known for {m['label']}")
+            fv = [v for name, wg, v in fetch if wg == m["workgroups"] and _kernel_matches(name, base, level0)]
+            wv = [v for name, wg, v in write if wg == m["workgroups"] and _kernel_matches(name, base, level0)]
+            if not fv or not wv:
+                raise SystemExit(f"no dispatch of {base} with {m['workgroups']} workgroups")
+            fk, wk = statistics.median(fv), statistics.median(wv)
+            meas = fk * 1024 * f_scale + wk * 1024 * w_scale
+            alg = m["bytes_per_launch"]
+            lines.append(f"| {sym} | `{m['label']}` | {m['blocks']} | {m['workgroups']} | {m['weight']:g} | {fk:,.0f} | "
+                         f"{wk:,.0f} | {meas:,.0f} | {alg:,.0f} | {meas / alg:.3f} |")
+            tot_w += m["weight"]
+            tot_meas += m["weight"] * meas
+            tot_alg += m["weight"] * alg
+        per_group[sym] = (tot_meas / tot_w, tot_alg / tot_w)
+    lines += ["", "| group | measured bytes per launch | algorithmic bytes per launch | ratio |", "|---|---|---|---|"]
+    for sym, (meas, alg) in per_group.items():
+        lines.append(f"| {sym} | {meas:,.0f} | {alg:,.0f} | {meas / alg:.3f} |")
+    lines.append("")
     # apply_A, the secondary roofline, from the same runs
     ka = roof["apply_A"]["kernel"]
     fa = [v for name, wg, v in fetch if f"{ka}<" in name]
@@ -455,13 +460,13 @@ def traffic_summary(fetch_csv, write_csv, roof_json):
     alg_a = roof["apply_A"]["bytes_per_launch"]
     lines += [f"{ka}: FETCH_SIZE {fk:,.0f} KiB, WRITE_SIZE {wk:,.0f} KiB per launch (median of {len(fa)}); "
               f"{meas_a:,.0f} B measured, {alg_a:,.0f} B algorithmic (ratio {meas_a / alg_a:.3f})", ""]
-    import hashlib
 
     def sha(src):
         return hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
 
     src = "paper_2609_16863_amd/csrc/kern_mg.hip"
-    lines.append(f"traffic {traffic_key(dom)} source={src} sha256={sha(src)} bytes_per_launch={per_launch:.0f}")
+    for sym, (meas, _) in per_group.items():
+        lines.append(f"traffic {traffic_key(sym)} source={src} sha256={sha(src)} bytes_per_launch={meas:.0f}")
     src = "paper_2609_16863_amd/csrc/kern_allatonce.hip"
     lines.append(f"traffic {ka} source={src} sha256={sha(src)} bytes_per_launch={meas_a:.0f}")
     print("\n".join(lines))

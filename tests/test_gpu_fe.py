@@ -150,3 +150,25 @@ def test_paper_problem_iterations(precision):
         ours = [its[s, l][0] for l in LEVELS]
         assert max(ours) - min(ours) <= 2, its        # mesh-independent, as in the paper
         assert all(abs(its[s, l][0] - its[s, l][1]) <= 2 for l in LEVELS), its
+
+
+def test_batch_mixes_elements_and_finite_differences():
+    """A batch holding a Q1 problem and a finite-difference one equals the
+    two single solves bit for bit."""
+    require_gpu()
+    from paper_2609_16863_amd import HeatBatch, HeatProblem
+    specs = [dict(dim=2, n=31, s=2, nt=6, disc="q1", length=L2), dict(dim=2, n=24, s=3, nt=4)]
+    opts = dict(tol=1e-10, inner_k=3, precision="fp32")
+    hb = HeatBatch(specs, streams=2, **opts)
+    rng = np.random.default_rng(12)
+    fs = [rng.standard_normal((sp["nt"], sp["s"], sp["n"] ** 2)) for sp in specs]
+    us = [rng.standard_normal(sp["n"] ** 2) for sp in specs]
+    announce("fe batch")
+    x, st = hb.solve(hb.assemble_rhs(to_dev(np.concatenate([f.ravel() for f in fs])), to_dev(np.concatenate(us))))
+    assert all(s["converged"] for s in st)
+    for sp, f, u, xb in zip(specs, fs, us, hb.split(x)):
+        hp = HeatProblem(sp["dim"], sp["n"], sp["s"], sp["nt"], 1.0, disc=sp.get("disc", "fd"),
+                         length=sp.get("length", 1.0), **opts)
+        xs, _ = hp.solve(hp.assemble_rhs(to_dev(f.ravel()), to_dev(u)))
+        assert np.array_equal(to_host(xb), to_host(xs))
+    hb.close()

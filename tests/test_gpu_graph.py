@@ -12,16 +12,20 @@ from gpu_util import announce, require_gpu, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("precision,dim,n,s,nt", [("fp64", 2, 40, 3, 4), ("fp32", 2, 72, 2, 3),
-                                                  ("bf16", 2, 33, 2, 2), ("fp32", 3, 12, 2, 2)])
-def test_graph_replay_is_bitwise_equal_to_direct(precision, dim, n, s, nt):
+# the MGRIT cases fork its last F-relaxation into concurrent chains: graph
+# branches when captured, side streams when launched directly
+@pytest.mark.parametrize("precision,dim,n,s,nt,mgrit", [("fp64", 2, 40, 3, 4, 0), ("fp32", 2, 72, 2, 3, 0),
+                                                        ("bf16", 2, 33, 2, 2, 0), ("fp32", 3, 12, 2, 2, 0),
+                                                        ("fp32", 2, 40, 3, 16, 4), ("fp64", 2, 33, 2, 13, 3)])
+def test_graph_replay_is_bitwise_equal_to_direct(precision, dim, n, s, nt, mgrit):
     require_gpu()
     from paper_2609_16863_amd import HeatProblem
-    hg = HeatProblem(dim, n, s, nt, 1.0, precision=precision, use_graph=True)
-    hd = HeatProblem(dim, n, s, nt, 1.0, precision=precision, use_graph=False)
+    kw = dict(schur="mgrit", mgrit_cf=mgrit) if mgrit else {}
+    hg = HeatProblem(dim, n, s, nt, 1.0, precision=precision, use_graph=True, **kw)
+    hd = HeatProblem(dim, n, s, nt, 1.0, precision=precision, use_graph=False, **kw)
     rng = np.random.default_rng(9)
     r1, r2 = to_dev(rng.standard_normal(hg.U)), to_dev(rng.standard_normal(hg.U))
-    announce("graph replay", precision, dim, n, s, nt)
+    announce("graph replay", precision, dim, n, s, nt, mgrit)
     z1, z2 = to_host(hd.apply_P(r1)), to_host(hd.apply_P(r2))
     for rep in range(3):
         g1 = to_host(hg.apply_P(r1))
