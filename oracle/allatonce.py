@@ -14,8 +14,8 @@ V = [V_0, ..., V_{nt-1}], V_n = [V_{n,1}, ..., V_{n,s}], the system is
     Theta : I_nt (x) (I_s (x) M + tau A (x) K)
 
 with M = I for finite differences (disc "fd", the unit square or cube) and
-the Q1 mass matrix for bilinear finite elements (disc "q1", the square
-[0, length]^2, ``oracle.fe``).  b holds the initial condition: b_0 = M u0 and
+the mass matrix of bilinear (disc "q1") or biquadratic (disc "q2") finite
+elements on the square [0, length]^2 (``oracle.fe``).  b holds the initial condition: b_0 = M u0 and
 b_{n>=1} = 0 for homogeneous Dirichlet data.  The stage right-hand side is
 M f_{n,i} with f_{n,i} = f(x, t_n + c_i tau) at the nodes, t_n = n tau (for
 finite elements, the load vector of the nodal interpolant of f; a reading:
@@ -45,8 +45,8 @@ class Problem:
     nt: int                # time steps
     T: float = 1.0         # final time
     kappa: Optional[np.ndarray] = None   # nodal diffusivity (N,), None = 1
-    disc: str = "fd"       # "fd" (finite differences) or "q1" (bilinear elements, 2D)
-    length: float = 1.0    # side of the square (q1)
+    disc: str = "fd"       # "fd" (finite differences), "q1" / "q2" (bilinear / biquadratic elements, 2D)
+    length: float = 1.0    # side of the square (q1, q2)
 
     A: np.ndarray = field(init=False, repr=False)
     b: np.ndarray = field(init=False, repr=False)
@@ -54,11 +54,17 @@ class Problem:
 
     def __post_init__(self):
         self.A, self.b, self.c = tableau.radau_iia(self.s)
-        if self.disc not in ("fd", "q1"):
+        if self.disc not in ("fd",) + fe.DISCS:
             raise ValueError(self.disc)
-        if self.disc == "q1" and (self.dim != 2 or self.kappa is not None):
-            raise ValueError("q1 elements: 2D, constant diffusivity")
+        if self.fe and (self.dim != 2 or self.kappa is not None):
+            raise ValueError("finite elements: 2D, constant diffusivity")
+        if self.disc == "q2" and self.n % 2 != 1:
+            raise ValueError("q2 elements: odd n")
         self._mk = None
+
+    @property
+    def fe(self):
+        return self.disc in fe.DISCS
 
     @property
     def N(self):
@@ -70,7 +76,7 @@ class Problem:
 
     @property
     def h(self):
-        return fe.spacing(self.n, self.length) if self.disc == "q1" else grid.spacing(self.n)
+        return fe.spacing(self.n, self.length) if self.fe else grid.spacing(self.n)
 
     @property
     def U(self):
@@ -85,19 +91,19 @@ class Problem:
         return (np.arange(self.nt)[:, None] + self.c[None, :]) * self.tau
 
     def K(self):
-        if self.disc == "q1":
-            return self._q1()[1]
+        if self.fe:
+            return self._fe()[1]
         return grid.stiffness(self.n, self.dim, self.kappa)
 
     def M(self):
         """Mass matrix: the identity for finite differences."""
-        if self.disc == "q1":
-            return self._q1()[0]
+        if self.fe:
+            return self._fe()[0]
         return sp.identity(self.N, format="csr")
 
-    def _q1(self):
+    def _fe(self):
         if self._mk is None:
-            self._mk = fe.q1_matrices(self.n, self.length)
+            self._mk = fe.matrices(self.disc, self.n, self.length)
         return self._mk
 
 
@@ -123,7 +129,7 @@ def rhs(prob, f, u0):
     in (nt, s, N) order (M = I for finite differences)."""
     v = np.zeros((prob.nt + 1, prob.N))
     fs = np.asarray(f, float).reshape(prob.nt, prob.s, prob.N)
-    if prob.disc == "q1":
+    if prob.fe:
         M = prob.M()
         v[0] = M @ u0
         return join(v, (M @ fs.reshape(-1, prob.N).T).T.reshape(fs.shape))

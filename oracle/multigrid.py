@@ -1,5 +1,6 @@
 """Geometric multigrid V-cycle for the shifted blocks M + a K (M = I for
-finite differences, the Q1 mass matrix for bilinear elements).
+finite differences, the Q1 or Q2 mass matrix for finite elements).  For Q2
+elements the coarse nodes (every second node) are the element vertices.
 
 Test infrastructure only (see ``oracle/__init__.py``).
 

@@ -102,7 +102,7 @@ class StageOps:
         self.coarse_max = coarse_max
         tau = prob.tau
         self.M = prob.M()
-        Mh = self.M if prob.disc == "q1" else None
+        Mh = self.M if prob.fe else None
         self.hier = [multigrid.Hierarchy(self.K, prob.n, prob.dim, tau * self.L[i, i], coarse_max, M=Mh)
                      for i in range(prob.s)]
         self._lu_blocks = None
@@ -184,14 +184,14 @@ def apply_preconditioner(ops, r, exact=False, mgrit=None):
     tv = rv.copy()
     for n in range(nt):
         tv[n + 1] = rv[n + 1] + tau * (ops.M @ np.tensordot(prob.b, zV[n], axes=(0, 0)))
-    if prob.disc == "q1":
+    if prob.fe:
         # S-tilde = blockdiag(M) (bidiagonal part): its block-diagonal mass
         # solve first, by Chebyshev semi-iteration (or exactly)
         if exact:
             lu = spla.splu(ops.M.tocsc())
             tv = np.array([lu.solve(t) for t in tv])
         else:
-            tv = fe.chebyshev_mass(ops.M, tv)
+            tv = fe.chebyshev_mass(ops.M, tv, bounds=fe.jacobi_bounds(prob.disc))
     phi = schur_propagator(ops, exact)
     if mgrit is None:
         zv = np.array(_mgrit.sequential(list(tv), phi))

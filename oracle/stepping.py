@@ -10,7 +10,7 @@ so this stepping yields its unique solution x* (the result every FGMRES solve
 of eq. (2.4) converges to).  The stage right-hand side is f_n - (e (x) K) v_n:
 the paper prints "f_n - K v_n"; the Psi2 = e (x) K block fixes the reading.
 
-With Q1 elements (prob.disc "q1") the stage right-hand side is the load
+With finite elements (prob.disc "q1" or "q2") the stage right-hand side is the load
 vector M f_n (f_n at the nodes) and v_0 = u0 (b_0 = M u0); the update needs
 no mass solve since every term of eq. (2.2) carries M.
 
@@ -54,7 +54,7 @@ def solve(prob, f, u0, method="auto", workers=None, timings=None):
     if method == "lu":
         K = prob.K()
         lu = spla.splu(allatonce.theta_hat(prob, K))
-        if prob.disc == "q1":
+        if prob.fe:
             Mm = prob.M()
             f = (Mm @ f.reshape(-1, N).T).T.reshape(nt, s, N)
         t1 = time.perf_counter()
