@@ -105,15 +105,24 @@ typedef enum aao_side {
 typedef enum aao_disc {
   AAO_DISC_FD = 0,         /* 5/7-point finite differences on the unit square
                               or cube, M = I                                   */
-  AAO_DISC_Q1 = 1          /* bilinear finite elements (Sec. 2 and Sec. 5 use
+  AAO_DISC_Q1 = 1,         /* bilinear finite elements (Sec. 2 and Sec. 5 use
                               Q1/Q2) on the square [0, length]^2, uniform grid,
                               with their mass matrix M: Phi and Psi1 carry M,
                               Theta_hat = I_s (x) M + tau A (x) K, the
                               multigrid solves M + a K, and S-tilde applies
                               M^{-1} by 20 steps of Chebyshev semi-iteration
-                              with the Jacobi splitting (Sec. 5).  2D,
-                              kappa = NULL, nu1, nu2 <= 3; the transposed
-                              solve and the kappa gradient are not available */
+                              with the Jacobi splitting (Sec. 5; D^{-1} M has
+                              its spectrum in [1/4, 9/4]).  2D, kappa = NULL,
+                              nu1, nu2 <= 3; the transposed solve and the
+                              kappa gradient are not available                */
+  AAO_DISC_Q2 = 2          /* biquadratic finite elements (Sec. 5, Tables 1-4)
+                              under the same conditions as AAO_DISC_Q1: n odd
+                              and >= 3 (n interior nodes per axis, (n + 1) / 2
+                              elements of side 2 length / (n + 1)), nodes
+                              ordered x fastest like every grid here; the
+                              Chebyshev mass solve uses the Q2 interval
+                              [1/4, 25/16]; the multigrid's first coarse level
+                              holds the element vertices                       */
 } aao_disc;
 
 /* Problem description (Sec. 2).  kappa: host pointer to N nodal
@@ -128,7 +137,7 @@ typedef struct aao_desc {
   double T;                /* final time, > 0                                 */
   const double* kappa;     /* host, N values, or NULL                          */
   int disc;                /* aao_disc                                         */
-  double length;           /* side of the square for AAO_DISC_Q1 (0 = 1); the
+  double length;           /* side of the square for AAO_DISC_Q1/Q2 (0 = 1); the
                               finite-difference domain is the unit square or
                               cube (0 or 1 only)                               */
 } aao_desc;

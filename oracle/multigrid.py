@@ -12,8 +12,9 @@ iteration counts, never the solution of eq. (2.4).
 
 * Coarse nodes are every second fine node, 1-based fine indices 2, 4, ...,
   2 floor(n/2), so n_c = floor(n/2); coarsening stops once a level has at
-  most ``coarse_max`` nodes (default COARSE_MAX = 256), and that level is
-  solved exactly.
+  most ``coarse_max`` nodes (default COARSE_MAX = 256) and there are at
+  least ``min_levels`` levels, and that level is solved exactly (Q2 elements
+  take min_levels = 2: their fine level is always smoothed).
 * Prolongation P: (tensor-)linear interpolation, boundary values zero.
 * Restriction R = P^T / 2^d (full weighting); coarse operator R A P
   (Galerkin), so every level is symmetric positive definite.
@@ -66,13 +67,13 @@ def interpolation(n, dim):
 class Hierarchy:
     """Levels (A_l, P_l) for A_0 = M + a K (M = I unless given)."""
 
-    def __init__(self, K, n, dim, a, coarse_max=COARSE_MAX, M=None):
+    def __init__(self, K, n, dim, a, coarse_max=COARSE_MAX, M=None, min_levels=1):
         self.dim = dim
         self.sizes = [n]
         M0 = sp.identity(K.shape[0], format="csr") if M is None else M
         self.ops = [(M0 + a * K).tocsr()]
         self.P = []
-        while self.sizes[-1] ** dim > coarse_max and self.sizes[-1] > 1:
+        while (self.sizes[-1] ** dim > coarse_max or len(self.ops) < min_levels) and self.sizes[-1] > 1:
             nf = self.sizes[-1]
             P = interpolation(nf, dim)
             R = P.T / (2.0 ** dim)

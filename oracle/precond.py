@@ -103,7 +103,9 @@ class StageOps:
         tau = prob.tau
         self.M = prob.M()
         Mh = self.M if prob.fe else None
-        self.hier = [multigrid.Hierarchy(self.K, prob.n, prob.dim, tau * self.L[i, i], coarse_max, M=Mh)
+        ml = 2 if prob.disc == "q2" else 1
+        self.hier = [multigrid.Hierarchy(self.K, prob.n, prob.dim, tau * self.L[i, i], coarse_max, M=Mh,
+                                         min_levels=ml)
                      for i in range(prob.s)]
         self._lu_blocks = None
         self._lu_theta = None

@@ -23,7 +23,7 @@ class Desc(ctypes.Structure):
                 ("kappa", c_void_p), ("disc", c_int), ("length", c_double)]
 
 
-DISCS = {"fd": 0, "q1": 1}
+DISCS = {"fd": 0, "q1": 1, "q2": 2}
 
 
 class Opts(ctypes.Structure):

@@ -100,7 +100,8 @@ struct aao_problem {
   aao_opts opts{};
   double omega = 0.8;
   bool vark = false;
-  bool fe = false;                           // bilinear finite elements (AAO_DISC_Q1)
+  bool fe = false;                           // finite elements (AAO_DISC_Q1 or AAO_DISC_Q2)
+  int fe_order = 0;                          // 1: bilinear (Q1), 2: biquadratic (Q2)
   std::vector<double> kappa;                 // host copy (N) when vark
 
   // multigrid levels (sizes per axis), shared by all stages
@@ -129,7 +130,7 @@ struct aao_problem {
     size_t rana;                              // Rana right-hand side (nt*N)
     size_t schurRhs, schurY;                  // S-tilde steps (s*N per instance)
     size_t mgritT, mgritG, mgritE;            // MGRIT: t (nt+1 blocks), C-point values, corrections
-    size_t feA, feB;                          // Q1: Chebyshev mass-solve iterates (nt+1 blocks each)
+    size_t feA, feB;                          // finite elements: Chebyshev mass-solve iterates (nt+1 blocks each)
     std::vector<size_t> mgX, mgT, mgB, mgR;   // per level, nt instances
     size_t partial, dscal, counters;          // reductions / device scalars / tickets
     size_t partial_bytes, dscal_bytes;
@@ -173,7 +174,7 @@ namespace aao {
 // setup.cpp (host only)
 bool radau_iia(int s, double* A, double* b, double* c);
 void crout_lower(int s, const double* A, double* L);
-void galerkin_1d(int n, int dim, double h, int coarse_max, bool fe, std::vector<int>& sizes,
+void galerkin_1d(int n, int dim, double h, int coarse_max, int fe, std::vector<int>& sizes,
                  std::vector<std::vector<double>>& tri);
 bool tensor_eigen(int n, const std::vector<double>& tri, std::vector<double>& V, std::vector<double>& lam);
 void galerkin_stencils_2d(const std::vector<int>& sizes, const std::vector<double>& faces, double ih2,

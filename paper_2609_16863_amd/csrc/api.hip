@@ -251,14 +251,18 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
   if (d->s < 1 || d->s > aao::SMAX) return fail(nullptr, AAO_INVALID_ARG, "s must be 1, 2 or 3");
   if (d->nt < 1 || d->nt > 65535) return fail(nullptr, AAO_INVALID_ARG, "nt must be in [1, 65535]");
   if (!(d->T > 0.0) || !std::isfinite(d->T)) return fail(nullptr, AAO_INVALID_ARG, "T must be > 0");
-  if (d->disc != AAO_DISC_FD && d->disc != AAO_DISC_Q1) return fail(nullptr, AAO_INVALID_ARG, "unknown disc");
+  if (d->disc != AAO_DISC_FD && d->disc != AAO_DISC_Q1 && d->disc != AAO_DISC_Q2)
+    return fail(nullptr, AAO_INVALID_ARG, "unknown disc");
+  const bool fe = d->disc != AAO_DISC_FD;
   if (d->disc == AAO_DISC_FD && d->length != 0.0 && d->length != 1.0)
     return fail(nullptr, AAO_INVALID_ARG, "finite differences live on the unit domain (length 0 or 1)");
-  if (d->disc == AAO_DISC_Q1) {
-    if (d->dim != 2 || d->kappa) return fail(nullptr, AAO_INVALID_ARG, "Q1 elements: 2D and constant kappa");
+  if (fe) {
+    if (d->dim != 2 || d->kappa) return fail(nullptr, AAO_INVALID_ARG, "finite elements: 2D and constant kappa");
     if ((int64_t)(d->nt + 1) + (int64_t)d->nt * d->s > 65535)
-      return fail(nullptr, AAO_INVALID_ARG, "Q1 elements: (nt + 1) + nt s must be <= 65535");
+      return fail(nullptr, AAO_INVALID_ARG, "finite elements: (nt + 1) + nt s must be <= 65535");
     if (d->length < 0.0 || !std::isfinite(d->length)) return fail(nullptr, AAO_INVALID_ARG, "length must be > 0");
+    if (d->disc == AAO_DISC_Q2 && (d->n < 3 || d->n % 2 == 0))
+      return fail(nullptr, AAO_INVALID_ARG, "Q2 elements: n must be odd and >= 3");
   }
   const double Nd = std::pow((double)d->n, d->dim);
   if (Nd > 1.5e9) return fail(nullptr, AAO_INVALID_ARG, "grid too large (N must fit in int32)");
@@ -270,8 +274,8 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
   if (opts.mgrit_cf == 0) opts.mgrit_cf = 8;
   if (opts.mgrit_iters == 0) opts.mgrit_iters = 1;
   if (opts.mgrit_iters > d->nt) return fail(nullptr, AAO_INVALID_ARG, "mgrit_iters must be <= nt");
-  if (d->disc == AAO_DISC_Q1 && (opts.nu1 > 3 || opts.nu2 > 3))
-    return fail(nullptr, AAO_INVALID_ARG, "Q1 elements: nu1, nu2 <= 3");
+  if (fe && (opts.nu1 > 3 || opts.nu2 > 3))
+    return fail(nullptr, AAO_INVALID_ARG, "finite elements: nu1, nu2 <= 3");
 
   aao_problem* h = new (std::nothrow) aao_problem();
   if (!h) return fail(nullptr, AAO_INVALID_ARG, "out of host memory");
@@ -281,7 +285,8 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
   h->nt = d->nt;
   h->T = d->T;
   h->tau = d->T / d->nt;
-  h->fe = d->disc == AAO_DISC_Q1;
+  h->fe = fe;
+  h->fe_order = d->disc == AAO_DISC_Q2 ? 2 : (fe ? 1 : 0);
   h->h = (h->fe && d->length > 0.0 ? d->length : 1.0) / (d->n + 1);
   h->ih2 = 1.0 / (h->h * h->h);
   h->N = (int64_t)std::llround(Nd);
@@ -339,7 +344,7 @@ int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) 
     return fail(nullptr, AAO_INVALID_ARG, "coarse_max above 256 needs 2D and constant kappa");
   }
   std::vector<std::vector<double>> tri;
-  aao::galerkin_1d(d->n, d->dim, h->h, cmax, h->fe, h->lev_n, tri);
+  aao::galerkin_1d(d->n, d->dim, h->h, cmax, h->fe_order, h->lev_n, tri);
   h->lev_N.resize(h->lev_n.size());
   h->tri_off.assign(h->lev_n.size(), 0);
   for (size_t l = 0; l < h->lev_n.size(); ++l) {
@@ -538,7 +543,7 @@ int aao_solve_adjoint(aao_problem* h, const double* g, double* lam, aao_stats* s
 int aao_grad_logkappa(aao_problem* h, const double* x, const double* lam, double* g) {
   if (!h) return AAO_INVALID_ARG;
   if (!x || !lam || !g) return fail(h, AAO_INVALID_ARG, "null pointer");
-  if (h->fe) return fail(h, AAO_INVALID_ARG, "Q1 elements: the kappa gradient is not available");
+  if (h->fe) return fail(h, AAO_INVALID_ARG, "finite elements: the kappa gradient is not available");
   if (h->vark && !h->ws) return fail(h, AAO_NO_WORKSPACE, "aao_set_workspace first");
   return aao::status_from_hip(h, aao::launch_grad_logkappa(h, x, lam, g, h->stream), "grad_logkappa");
 }

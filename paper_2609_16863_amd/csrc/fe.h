@@ -1,7 +1,7 @@
-// Launchers of the bilinear finite-element (Q1) operators (kern_fe.hip).
-// Each applies to the handle's uniform square grid (2D, kappa = 1); the
-// finite-difference launchers call them when the handle was created with
-// AAO_DISC_Q1.
+// Launchers of the bilinear (Q1) and biquadratic (Q2) finite-element
+// operators (kern_fe.hip).  Each applies to the handle's uniform square mesh
+// (2D, kappa = 1); the finite-difference launchers call them when the handle
+// was created with AAO_DISC_Q1 or AAO_DISC_Q2.
 #pragma once
 
 #include "aao_internal.h"
@@ -11,7 +11,7 @@ namespace aao {
 // Chebyshev steps of the mass solve inside S-tilde (Sec. 5 uses 20)
 constexpr int FE_CHEB_STEPS = 20;
 
-// y = A x (or A^T x), the all-at-once operator of eq. (2.4) with M and K of Q1
+// y = A x (or A^T x), the all-at-once operator of eq. (2.4) with M and K of the elements
 template <class TX>
 hipError_t fe_apply_A(const aao_problem* h, const TX* x, double* y, bool transpose, hipStream_t st);
 // w = (I_s (x) M + tau A (x) K) z on B instances (strides sz, sw)

@@ -24,7 +24,10 @@ constexpr int TPB = 256;
 // the stored 9-point stencil op.st9 when that is set (2D, variable kappa).
 // KIND_STENCIL9: the same level in the LDS-tiled kernels, which keep the
 // stencil coefficients of their nodes in registers.
-enum { KIND_FINE = 0, KIND_FINE_VK = 1, KIND_TENSOR = 2, KIND_STENCIL9 = 3 };
+// KIND_Q2: level 0 of biquadratic elements (2D), the tensor form of 1D
+// factors with five diagonals (op.tri holds M(i, i + d) and T(i, i + d),
+// d = -2..2, ten arrays of n); it runs in the grid kernels only.
+enum { KIND_FINE = 0, KIND_FINE_VK = 1, KIND_TENSOR = 2, KIND_STENCIL9 = 3, KIND_Q2 = 4 };
 
 template <class C>
 struct Tri3 {
@@ -47,6 +50,11 @@ template <int DIM, int KIND, class C>
 __device__ __forceinline__ C level_diag(const LevelOp<C>& op, int p, int i, int j, int k) {
   if (KIND == KIND_FINE) return C(1) + op.a * op.ih2 * C(2 * DIM);
   if (KIND == KIND_FINE_VK) return C(1) + op.a * op.ih2 * stencil_K_diag<DIM, true, C>(p, op.faces);
+  if (KIND == KIND_Q2) {
+    const int n = op.n;
+    const C mi = op.tri[2 * n + i], ti = op.tri[7 * n + i], mj = op.tri[2 * n + j], tj = op.tri[7 * n + j];
+    return mi * mj + op.a * (ti * mj + mi * tj);
+  }
   const Tri3<C> ri = tri_row(op.tri, op.n, i), rj = tri_row(op.tri, op.n, j);
   if (DIM == 2 && op.st9) return ri.m[1] * rj.m[1] + op.a * op.st9[4 * op.N + p];
   if (DIM == 2) return ri.m[1] * rj.m[1] + op.a * (ri.t[1] * rj.m[1] + ri.m[1] * rj.t[1]);
@@ -63,6 +71,34 @@ __device__ __forceinline__ void level_apply(const T* __restrict__ x, const Level
   if (KIND == KIND_FINE || KIND == KIND_FINE_VK) {
     const C kx = stencil_K<DIM, KIND == KIND_FINE_VK, T, C>(x, p, i, j, k, n, (int)op.N, op.faces);
     Ax = ld<T, C>(x + p) + op.a * op.ih2 * kx;
+    diag = level_diag<DIM, KIND, C>(op, p, i, j, k);
+    return;
+  }
+  if (KIND == KIND_Q2) {
+    // (M_y (x) (M_x + a T_x) + a T_y (x) M_x) x over the 5 x 5 neighbourhood
+    C mx[5], px[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      mx[d] = op.tri[d * n + i];
+      px[d] = mx[d] + op.a * op.tri[(5 + d) * n + i];
+    }
+    C acc = C(0);
+#pragma unroll
+    for (int dj = -2; dj <= 2; ++dj) {
+      const int jj = j + dj;
+      if (jj < 0 || jj >= n) continue;
+      C pv = C(0), qv = C(0);
+#pragma unroll
+      for (int di = -2; di <= 2; ++di) {
+        const int ii = i + di;
+        if (ii < 0 || ii >= n) continue;
+        const C xv = ld<T, C>(x + p + dj * n + di);
+        pv += px[di + 2] * xv;
+        qv += mx[di + 2] * xv;
+      }
+      acc += op.tri[(dj + 2) * n + j] * pv + op.a * op.tri[(dj + 7) * n + j] * qv;
+    }
+    Ax = acc;
     diag = level_diag<DIM, KIND, C>(op, p, i, j, k);
     return;
   }
@@ -1634,7 +1670,9 @@ Multigrid<TI, TM>::Multigrid(aao_problem* h, hipStream_t st, const double* L, in
   // measured on MI355X (512^2, s=3): one workgroup is faster than grid
   // kernels up to a 32 x 32 level, slower above it
   const int64_t tail_max = h->opts.mg_tail_max > 0 ? h->opts.mg_tail_max : 1024;
-  while (l0_ > 0 && levels_ - l0_ < TAIL_MAXL) {
+  // Q2: level 0 (five-diagonal factors) runs in the grid kernels only
+  const int l0_min = h->fe_order == 2 ? 1 : 0;
+  while (l0_ > l0_min && levels_ - l0_ < TAIL_MAXL) {
     const size_t more = bytes + cost(l0_ - 1);
     if (more > budget) break;
     if (tail_max > 0 && h->lev_N[l0_ - 1] > tail_max) break;
@@ -1731,7 +1769,9 @@ hipError_t Multigrid<TI, TM>::smooth(int l, int stage, Vec xin, Vec xout, Vec b,
   const dim3 g = grid2(op.N, B);
   const int d3 = h_->dim == 3;
   if (l == 0) {
-    if (h_->vark) {
+    if (h_->fe_order == 2) {
+      hipLaunchKernelGGL((k_smooth<2, KIND_Q2, TI, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (TI*)xout.ptr, xout.stride, (const TI*)b.ptr, b.stride, op, omega, (int)zero_init);
+    } else if (h_->vark) {
       if (d3) hipLaunchKernelGGL((k_smooth<3, KIND_FINE_VK, TI, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (TI*)xout.ptr, xout.stride, (const TI*)b.ptr, b.stride, op, omega, (int)zero_init);
       else hipLaunchKernelGGL((k_smooth<2, KIND_FINE_VK, TI, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (TI*)xout.ptr, xout.stride, (const TI*)b.ptr, b.stride, op, omega, (int)zero_init);
     } else {
@@ -1756,25 +1796,29 @@ hipError_t Multigrid<TI, TM>::resid_restrict(int l, int stage, Vec x, Vec b, Vec
   const C omega = (C)h_->omega;
   const dim3 g = grid2(opc.N, B);
   const int d3 = h_->dim == 3, z = (int)zero_next;
-  if (d3) {
+  if (split_restrict(l)) {
     // residual once per fine node into the level's residual buffer, then
-    // the full weighting (3D has constant kappa: tensor or fine operator)
+    // the full weighting (3D has constant kappa: tensor or fine operator;
+    // Q2 level 0: its 25-point operator)
     Vec r{h_->ws + h_->plan.mgR[l], (int64_t)opf.N};
     const C bs = l == 0 ? (C)h_->mg_scale : C(1);
     const dim3 gf = grid2(opf.N, B);
     return typed2(l, [&](auto tf, auto tc) {
       using TF = decltype(tf);
       using TC = decltype(tc);
-      if (l == 0)
-        hipLaunchKernelGGL((k_residual<3, KIND_FINE, TF, C>), gf, dim3(TPB), 0, st_, (const TF*)x.ptr, x.stride,
-                           (const TF*)b.ptr, b.stride, (TF*)r.ptr, r.stride, opf);
-      else
-        hipLaunchKernelGGL((k_residual<3, KIND_TENSOR, TF, C>), gf, dim3(TPB), 0, st_, (const TF*)x.ptr, x.stride,
-                           (const TF*)b.ptr, b.stride, (TF*)r.ptr, r.stride, opf);
+#define RES(D, K) hipLaunchKernelGGL((k_residual<D, K, TF, C>), gf, dim3(TPB), 0, st_, (const TF*)x.ptr, x.stride, (const TF*)b.ptr, b.stride, (TF*)r.ptr, r.stride, opf)
+      if (!d3) RES(2, KIND_Q2);
+      else if (l == 0) RES(3, KIND_FINE);
+      else RES(3, KIND_TENSOR);
+#undef RES
       MG_TRY(hipGetLastError());
       MG_TRY(mark("k_residual", l));
-      hipLaunchKernelGGL((k_restrict<3, TF, TC, C>), g, dim3(TPB), 0, st_, (const TF*)r.ptr, r.stride, (TC*)bc.ptr,
-                         bc.stride, (TC*)xc.ptr, xc.stride, opf.n, opc, omega, z, bs);
+      if (d3)
+        hipLaunchKernelGGL((k_restrict<3, TF, TC, C>), g, dim3(TPB), 0, st_, (const TF*)r.ptr, r.stride, (TC*)bc.ptr,
+                           bc.stride, (TC*)xc.ptr, xc.stride, opf.n, opc, omega, z, bs);
+      else
+        hipLaunchKernelGGL((k_restrict<2, TF, TC, C>), g, dim3(TPB), 0, st_, (const TF*)r.ptr, r.stride, (TC*)bc.ptr,
+                           bc.stride, (TC*)xc.ptr, xc.stride, opf.n, opc, omega, z, bs);
       return hipGetLastError();
     });
   }
@@ -1881,7 +1925,7 @@ hipError_t Multigrid<TI, TM>::tail(int stage, Vec x, Vec b, bool zero_init, int 
   if (tail_bytes_ > h_->lds_budget) return hipErrorInvalidValue;
   TailArgs<C> ta{};
   ta.nl = levels_ - l0_;
-  ta.first_fine = l0_ == 0 && !h_->fe;   // Q1: level 0 is a tensor level too
+  ta.first_fine = l0_ == 0 && !h_->fe;   // Q1: level 0 is a tensor level too (Q2 keeps it out of the tail)
   ta.zero_init = zero_init;
   ta.nu1 = h_->opts.nu1;
   ta.nu2 = h_->opts.nu2;
@@ -2057,7 +2101,7 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
   const int nu1 = h_->opts.nu1, nu2 = h_->opts.nu2;
   const int64_t Nl = h_->lev_N[l];
   Vec tmp{h_->ws + P.mgT[l], Nl};
-  if (h_->dim == 2 && nu1 <= 3 && nu2 <= 3 && !pre) {
+  if (h_->dim == 2 && nu1 <= 3 && nu2 <= 3 && !pre && !(l == 0 && h_->fe_order == 2)) {
     // tiled: down (sweeps, residual, restriction) -> coarse cycle -> up
     const int64_t Nc = h_->lev_N[l + 1];
     Vec bc{h_->ws + P.mgB[l + 1], Nc};
@@ -2075,7 +2119,7 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
   auto partner = [&](const Vec& v) { return v.ptr == x.ptr ? tmp : x; };
   // writes after the first sweep alternate buffers; at level 0 the result
   // must end in x, so the first sweep's target is chosen by parity
-  const bool fused_post = (l == 0) && h_->dim == 2;
+  const bool fused_post = (l == 0) && h_->dim == 2 && h_->fe_order != 2;
   Vec cur = x;
   int rem = nu1;
   if (zero_init) {
@@ -2097,9 +2141,13 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
   const int64_t Nc = h_->lev_N[l + 1];
   Vec bc{h_->ws + P.mgB[l + 1], Nc};
   Vec xc{h_->ws + P.mgX[l + 1], Nc};
-  const bool next_grid = (l + 1) < l0_;
+  // the coarse level's first sweep fused into the restriction, unless that
+  // level runs the tiled kernels (2D, nu1, nu2 <= 3: reached here only from
+  // level 0 of Q2 elements), which start from zero themselves
+  const bool next_tiled = h_->dim == 2 && nu1 <= 3 && nu2 <= 3;
+  const bool next_grid = (l + 1) < l0_ && !next_tiled;
   MG_TRY(resid_restrict(l, stage, cur, b, bc, xc, next_grid, B));
-  MG_TRY(mark(h_->dim == 3 ? "k_restrict" : "k_resid_restrict", l));
+  MG_TRY(mark(split_restrict(l) ? "k_restrict" : "k_resid_restrict", l));
   Vec ec{};
   MG_TRY(vcycle(l + 1, stage, xc, bc, true, next_grid, B, &ec));
   int post = nu2;

@@ -79,6 +79,10 @@ class Multigrid {
   // Storage precision of every level (see the class comment).
   void set_level_storage();
   bool low(int l) const { return l > 0 && l < levels_ && low_[l] != 0; }
+  // the residual of level l is formed once per node, then restricted (3D;
+  // level 0 of Q2 elements, whose 25-point operator the fused kernel would
+  // apply at all nine fine nodes around each coarse node)
+  bool split_restrict(int l) const { return h_->dim == 3 || (l == 0 && h_->fe_order == 2); }
   // f(T{}) with the storage type T of level l; f(TF{}, TC{}) with those of
   // levels l and l + 1.
   template <class F>

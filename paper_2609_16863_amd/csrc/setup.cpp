@@ -116,29 +116,55 @@ void crout_lower(int s, const double* A, double* L) {
 }
 
 // 1D Galerkin factors of the hierarchy.  Level 0: M_0 = I,
-// T_0 = tridiag(-1, 2, -1)/h^2 on n nodes for finite differences; for
-// bilinear elements (fe) the 1D mass and stiffness matrices
-// M_0 = h tridiag(1/6, 2/3, 1/6), T_0 = tridiag(-1, 2, -1)/h, whose tensor
-// form M(x)M + a (T(x)M + M(x)T) is the Q1 matrix M + a K.  Coarse nodes are the fine nodes
-// 2, 4, ..., 2 floor(n/2) (1-based), P is linear interpolation (zero
+// T_0 = tridiag(-1, 2, -1)/h^2 on n nodes for finite differences (fe = 0);
+// for bilinear elements (fe = 1) the 1D mass and stiffness matrices
+// M_0 = h tridiag(1/6, 2/3, 1/6), T_0 = tridiag(-1, 2, -1)/h; for
+// biquadratic elements (fe = 2, n odd, element side H = 2h) the quadratic
+// ones, whose rows at element vertices (odd 0-based index) couple five
+// nodes, M: H/30 (-1, 2, 8, 2, -1), T: (1, -8, 14, -8, 1)/(3H), and whose
+// rows at edge midpoints couple three, M: H/30 (2, 16, 2), T: (-8, 16, -8)/(3H).
+// The tensor form M(x)M + a (T(x)M + M(x)T) of these is the finite-element
+// matrix M + a K.  Coarse nodes are the fine nodes 2, 4, ..., 2 floor(n/2)
+// (1-based; for Q2 the element vertices), P is linear interpolation (zero
 // boundary values), and M_{l+1} = P^T M_l P / 2, T_{l+1} = P^T T_l P / 2, so
 // that in d dimensions R = P^T / 2^d and the Galerkin operator R A_l P of
-// A_l = M(x)M + a (T(x)M + M(x)T) is again of that form.  Coarsening stops
-// once a level has at most coarse_max nodes (that level is solved exactly).
-// tri[l] = [Mlo, Md, Mup, Tlo, Td, Tup], each n_l long (level 0 included).
-void galerkin_1d(int n, int dim, double h, int coarse_max, bool fe, std::vector<int>& sizes,
+// A_l = M(x)M + a (T(x)M + M(x)T) is again of that form; from level 1 on the
+// factors are tridiagonal (for Q2 a midpoint row, the only one reaching a
+// vertex two nodes away, never lies under two coarse nodes' supports).
+// Coarsening stops once a level has at most coarse_max nodes (that level is
+// solved exactly); Q2 coarsens at least once, so that level 0 is never the
+// exactly solved one.
+// tri[l] = [Mlo, Md, Mup, Tlo, Td, Tup], each n_l long; for Q2, tri[0] =
+// [M(i,i-2), .., M(i,i+2), T(i,i-2), .., T(i,i+2)], ten arrays of n.
+void galerkin_1d(int n, int dim, double h, int coarse_max, int fe, std::vector<int>& sizes,
                  std::vector<std::vector<double>>& tri) {
   sizes.assign(1, n);
   int nf = n;
   std::vector<double> M(nf * nf, 0.0), T(nf * nf, 0.0);
-  const double ts = fe ? 1.0 / h : 1.0 / (h * h);
-  for (int i = 0; i < nf; ++i) {
-    M[i * nf + i] = fe ? 2.0 * h / 3.0 : 1.0;
-    if (fe && i > 0) M[i * nf + i - 1] = h / 6.0;
-    if (fe && i + 1 < nf) M[i * nf + i + 1] = h / 6.0;
-    T[i * nf + i] = 2.0 * ts;
-    if (i > 0) T[i * nf + i - 1] = -ts;
-    if (i + 1 < nf) T[i * nf + i + 1] = -ts;
+  int band = 1;
+  if (fe == 2) {
+    band = 2;
+    const double H = 2.0 * h;
+    static const double mv[5] = {-1, 2, 8, 2, -1}, tv[5] = {1, -8, 14, -8, 1};
+    static const double mm[5] = {0, 2, 16, 2, 0}, tm[5] = {0, -8, 16, -8, 0};
+    for (int i = 0; i < nf; ++i) {
+      const bool vertex = i & 1;
+      for (int d = -2; d <= 2; ++d) {
+        if (i + d < 0 || i + d >= nf) continue;
+        M[i * nf + i + d] = H / 30.0 * (vertex ? mv : mm)[d + 2];
+        T[i * nf + i + d] = (vertex ? tv : tm)[d + 2] / (3.0 * H);
+      }
+    }
+  } else {
+    const double ts = fe ? 1.0 / h : 1.0 / (h * h);
+    for (int i = 0; i < nf; ++i) {
+      M[i * nf + i] = fe ? 2.0 * h / 3.0 : 1.0;
+      if (fe && i > 0) M[i * nf + i - 1] = h / 6.0;
+      if (fe && i + 1 < nf) M[i * nf + i + 1] = h / 6.0;
+      T[i * nf + i] = 2.0 * ts;
+      if (i > 0) T[i * nf + i - 1] = -ts;
+      if (i + 1 < nf) T[i * nf + i + 1] = -ts;
+    }
   }
   auto pack = [](const std::vector<double>& Mx, const std::vector<double>& Tx, int m) {
     std::vector<double> t(6 * m, 0.0);
@@ -152,9 +178,19 @@ void galerkin_1d(int n, int dim, double h, int coarse_max, bool fe, std::vector<
     }
     return t;
   };
-  tri.assign(1, pack(M, T, nf));
+  auto pack5 = [](const std::vector<double>& Mx, const std::vector<double>& Tx, int m) {
+    std::vector<double> t(10 * m, 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int d = -2; d <= 2; ++d) {
+        if (i + d < 0 || i + d >= m) continue;
+        t[(d + 2) * m + i] = Mx[i * m + i + d];
+        t[(d + 7) * m + i] = Tx[i * m + i + d];
+      }
+    return t;
+  };
+  tri.assign(1, band == 2 ? pack5(M, T, nf) : pack(M, T, nf));
   auto npow = [dim](int m) { double v = 1.0; for (int a = 0; a < dim; ++a) v *= m; return v; };
-  while (npow(nf) > coarse_max && nf > 1) {
+  while ((npow(nf) > coarse_max || (fe == 2 && sizes.size() == 1)) && nf > 1) {
     int nc = nf / 2;
     // P: nf x nc, coarse J at fine 2J+1 (0-based), neighbours 2J and 2J+2
     std::vector<double> P(nf * nc, 0.0);
@@ -167,7 +203,7 @@ void galerkin_1d(int n, int dim, double h, int coarse_max, bool fe, std::vector<
     auto rap = [&](const std::vector<double>& X) {
       std::vector<double> XP(nf * nc, 0.0), out(nc * nc, 0.0);
       for (int i = 0; i < nf; ++i)
-        for (int k = std::max(0, i - 1); k <= std::min(nf - 1, i + 1); ++k) {
+        for (int k = std::max(0, i - band); k <= std::min(nf - 1, i + band); ++k) {
           double x = X[i * nf + k];
           if (x == 0.0) continue;
           for (int J = 0; J < nc; ++J) XP[i * nc + J] += x * P[k * nc + J];
@@ -186,6 +222,7 @@ void galerkin_1d(int n, int dim, double h, int coarse_max, bool fe, std::vector<
     M.swap(Mc);
     T.swap(Tc);
     nf = nc;
+    band = 1;
   }
 }
 

@@ -272,7 +272,7 @@ class Precond {
   hipError_t schur_phase(const double* r, TI* z) {
     (void)r;
     TI* t = coarse_ ? mt_ : z;
-    // Q1 elements: S-tilde = blockdiag(M) times the bidiagonal recurrence;
+    // finite elements: S-tilde = blockdiag(M) times the bidiagonal recurrence;
     // its block-diagonal mass solve first (Chebyshev, Sec. 5), in place
     if (h_->fe) TRY(fe_mass_solve<TI>(h_, t, fea_, feb_, h_->nt + 1, st_));
     return schur_solve<TI>(t, h_->N, z, h_->N);
@@ -1027,7 +1027,7 @@ int apply_P(aao_problem* h, const double* r, double* z, int inner_k, int cycles,
 
 int solve(aao_problem* h, const double* rhs, double* x, aao_stats* st, bool transpose) {
   if (transpose && h->fe) {
-    h->err = "Q1 elements: the transposed solve is not available";
+    h->err = "finite elements: the transposed solve is not available";
     return AAO_INVALID_ARG;
   }
   if (h->opts.precision == AAO_PREC_FP64) {

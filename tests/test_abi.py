@@ -213,16 +213,19 @@ def test_binding_rejects_unknown_solver_options():
     assert opts.outer_precision == 1 and opts.restart == 30
 
 
-@pytest.mark.parametrize("bad", [dict(disc=2), dict(disc=1, dim=3), dict(disc=1, kappa=True), dict(length=2.0),
-                                 dict(disc=1, nu1=4), dict(disc=1, length=-1.0)])
-def test_q1_descriptions_are_checked(bad):
+@pytest.mark.parametrize("bad", [dict(disc=3), dict(disc=1, dim=3), dict(disc=1, kappa=True), dict(length=2.0),
+                                 dict(disc=1, nu1=4), dict(disc=1, length=-1.0), dict(disc=2),
+                                 dict(disc=2, n=7, dim=3), dict(disc=2, n=7, kappa=True), dict(disc=2, n=7, nu2=4)])
+def test_element_descriptions_are_checked(bad):
     abi, lib = _lib()
     opts = abi.Opts()
     lib.aao_default_opts(ctypes.byref(opts))
     if "nu1" in bad:
         opts.nu1 = bad["nu1"]
+    if "nu2" in bad:
+        opts.nu2 = bad["nu2"]
     dim = bad.get("dim", 2)
-    n = 6
+    n = bad.get("n", 6)         # even: refused for Q2 elements
     kap = np.ones(n ** dim) if bad.get("kappa") else None
     desc = abi.Desc(dim, n, 2, 3, 1.0, None if kap is None else kap.ctypes.data, bad.get("disc", 0),
                     bad.get("length", 0.0))
@@ -241,4 +244,22 @@ def test_q1_handle_sizes_and_levels():
     N, U = ctypes.c_int64(), ctypes.c_int64()
     lib.aao_sizes(h, ctypes.byref(N), ctypes.byref(U))
     assert U.value == 38440          # Table 1, Q1, s = 2, l = 5
+    lib.aao_destroy(h)
+
+
+def test_q2_handle_sizes_and_levels():
+    abi, lib = _lib()
+    opts = abi.Opts()
+    lib.aao_default_opts(ctypes.byref(opts))
+    for n, nt, dof in [(15, 8, 5625), (31, 16, 47089)]:     # Table 1, Q2, s = 2, l = 3, 4
+        desc = abi.Desc(2, n, 2, nt, 2.0, None, 2, 2.0)
+        h = ctypes.c_void_p()
+        assert lib.aao_create_problem(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h)) == 0
+        N, U = ctypes.c_int64(), ctypes.c_int64()
+        lib.aao_sizes(h, ctypes.byref(N), ctypes.byref(U))
+        assert U.value == dof and N.value == n * n
+        lib.aao_destroy(h)
+    desc = abi.Desc(2, 3, 1, 2, 1.0, None, 2, 1.0)          # smallest Q2 mesh: two elements per axis
+    h = ctypes.c_void_p()
+    assert lib.aao_create_problem(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h)) == 0
     lib.aao_destroy(h)
