@@ -21,7 +21,9 @@ the launch stream; traffic from the committed counter summary while its
 source is unchanged), apply_A and the 64-block V-cycle as secondary
 rooflines, `cpu_baseline` (the oracle's DST stepping on all 64 steps with
 every host core), and `extra` timings of the 3D 128^3 workload in four
-preconditioner precisions and of the 64-problem uneven batch.
+preconditioner precisions, of the 64-problem uneven batch, and of the
+paper's parallel test case #1 (Q2 elements, 255^2 nodes, s = 3, 256 steps)
+with its own solver settings (test case #2, 535M unknowns, on request).
 """
 import argparse
 import json
@@ -64,7 +66,9 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-preconditioner arm")
     ap.add_argument("--no-variants", action="store_true", help="skip the S-tilde substitution arms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extras", action="store_true", help="skip the 3D and batch timings")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 3D, batch and paper-case timings")
+    ap.add_argument("--paper-case2", action="store_true",
+                    help="also time the paper's test case #2 (Q2, 511^2 nodes, 512 steps: 535M unknowns)")
     ap.add_argument("--roofline-reps", type=int, default=20)
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the roofline launches (V-cycle kernels, apply_A, a 1 GiB copy); for counter runs")
@@ -541,14 +545,21 @@ def cpu_baseline(w, f, u0, x_gpu):
 
 def extras(args, autotune):
     """3D 128^3 (s = 3, nt = 32, FGMRES(20)) with the preconditioner in FP64,
-    FP32, BF16 and FP16, and the 64-problem uneven batch (FP32), each timed
-    over a few solves after a warm-up."""
+    FP32, BF16 and FP16, the 64-problem uneven batch (FP32) and the paper's
+    Q2 test cases, each timed over a few solves after a warm-up."""
     import torch
 
     import heat_inputs
-    from oracle import allatonce
     from paper_2609_16863_amd import HeatBatch, HeatProblem
     out = {}
+    tableaux = {}
+
+    def stage_times(s, nt, T):
+        # the library's Radau IIA nodes c (from a tiny handle per s)
+        if s not in tableaux:
+            tableaux[s] = HeatProblem(2, 2, s, 1, 1.0).tableau()[2]
+        return (np.arange(nt)[:, None] + tableaux[s][None, :]) * (T / nt)
+
     w3 = heat_inputs.WORKLOADS["heat3d_n128_s3_nt32"]
     res3 = {}
     for prec in ["fp64", "fp32", "bf16", "fp16"]:
@@ -578,7 +589,7 @@ def extras(args, autotune):
     specs = heat_inputs.batch_problem_specs()
     data = []
     for sp in specs:
-        times = allatonce.Problem(sp["n"], 2, sp["s"], sp["nt"], 1.0).stage_times()
+        times = stage_times(sp["s"], sp["nt"], 1.0)
         data.append(heat_inputs.spec_inputs(sp, times))
     hb = HeatBatch([dict(dim=2, n=sp["n"], s=sp["s"], nt=sp["nt"], kappa=kap) for sp, (kap, _, _) in zip(specs, data)],
                    streams=4, precision="fp32", tol=1e-8, inner_k=3, schur=args.schur, mgrit_cf=args.mgrit_cf)
@@ -601,7 +612,78 @@ def extras(args, autotune):
                                    "schur": args.schur, "streams": 4}
     hb.close()
     torch.cuda.empty_cache()
+    cases = ["paper_case1_q2_n255_s3_nt256"] + (["paper_case2_q2_n511_s3_nt512"] if args.paper_case2 else [])
+    for name in cases:
+        out[name] = paper_case(heat_inputs.PAPER_CASES[name], args.mgrit_cf)
     return out
+
+
+# The paper's CPU figures for its parallel test cases (Sec. 5.2, Tables 5 and
+# 6; MPI-Fortran on Xeon Platinum 8358 cores): outer (inner) iterations and
+# total seconds T_p on p = 1, 8, 64 processes.  Context only: another machine.
+PAPER_TABLE = {
+    "paper_case1_q2_n255_s3_nt256": {
+        "single": {"its": "9 (24)", "T_s": {"1": 2469.4, "8": 464.9, "64": 135.0}},
+        "double": {"its": "7 (23)", "T_s": {"1": 3316.0, "8": 585.3, "64": 149.9}}},
+    "paper_case2_q2_n511_s3_nt512": {
+        "single": {"its": "11 (33)", "T_s": {"1": 36272.4, "8": 6683.2, "64": 1677.8}},
+        "double": {"its": "8 (30)", "T_s": {"1": 77926.6, "8": 11745.0, "64": 2592.2}}},
+}
+
+
+def paper_case(case, mgrit_cf, reps=2):
+    """One of the paper's parallel test cases (Q2 elements, Sec. 5.2) with the
+    paper's solver settings: left-preconditioned FGMRES(15), tol 1e-8, the
+    inner GMRES on Theta-tilde stopped after 3 iterations or at 1e-3 (P-tilde
+    in FP32) and after 5 or at 1e-6 (FP64), S-tilde by MGRIT; plus the FP32
+    P-tilde on the right.  Reports the solve time (mean of ``reps`` after a
+    warm-up), the iterations, the true relative residual, and the largest
+    nodal error against the manufactured solution relative to max |v|."""
+    import torch
+
+    import heat_inputs
+    from paper_2609_16863_amd import HeatProblem
+    settings = {"left_fp32": dict(side="left", precision="fp32", inner_k=3, inner_tol=1e-3),
+                "left_fp64": dict(side="left", precision="fp64", inner_k=5, inner_tol=1e-6),
+                "right_fp32": dict(side="right", precision="fp32", inner_k=3, inner_tol=1e-3)}
+    res = {}
+    for label, kw in settings.items():
+        hp = HeatProblem(2, case.n, case.s, case.nt, case.tf, disc="q2", length=case.length, restart=case.restart,
+                         tol=1e-8, maxit=100, schur="mgrit", mgrit_cf=mgrit_cf, **kw)
+        times_st = hp.stage_times()
+        f, u0, exact = heat_inputs.paper_case_inputs(case, times_st)
+        rhs = hp.assemble_rhs(torch.from_numpy(np.ascontiguousarray(f.ravel())).cuda(), torch.from_numpy(u0).cuda())
+        del f
+        times = []
+        for it in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st = hp.solve(rhs)
+            torch.cuda.synchronize()
+            if it > 0:
+                times.append(time.perf_counter() - t0)
+            if it < reps:
+                del x
+        v = x[: (case.nt + 1) * case.N].view(case.nt + 1, case.N).cpu().numpy()
+        del x
+        tau = case.tf / case.nt
+        err, vmax = 0.0, 0.0
+        for m in range(case.nt + 1):
+            ex = exact(m * tau)
+            err = max(err, float(np.max(np.abs(v[m] - ex))))
+            vmax = max(vmax, float(np.max(np.abs(ex + 1.0))))
+        log(f"{case.name} {label}: {np.mean(times) * 1e3:.0f} ms, {st['outer_iterations']} its "
+            f"({st['inner_iterations']} inner), relres {st['relres']:.1e}, error {err / vmax:.1e}")
+        res[label] = {"solve_s": float(np.mean(times)), "outer_iterations": st["outer_iterations"],
+                      "inner_iterations": st["inner_iterations"], "converged": st["converged"],
+                      "true_relres": st["relres"], "max_error_vs_manufactured": err / vmax,
+                      "theta_ms": st["theta_ms"], "schur_ms": st["schur_ms"]}
+        del hp, rhs, v
+        torch.cuda.empty_cache()
+    res["left_fp32_vs_fp64_speedup"] = res["left_fp64"]["solve_s"] / res["left_fp32"]["solve_s"]
+    return {"elements": "Q2", "nodes": case.N, "s": case.s, "nt": case.nt, "tf": case.tf,
+            "unknowns": case.N * (case.nt * (case.s + 1) + 1), "restart": case.restart, "schur": "mgrit",
+            "mgrit_cf": mgrit_cf, "solves": res, "paper_cpu_for_context": PAPER_TABLE[case.name]}
 
 
 if __name__ == "__main__":

@@ -14,6 +14,8 @@ no public dataset is involved.  These synthetic inputs stand in for them:
                   om_k ~ U[0.5, 3], ph_k ~ U[0, 2 pi].
 * ``smooth``   -- u0 = sum over modes k_a <= 8 of c_k prod_a sin(k_a pi x_a)
                   / |k|^2, c_k ~ N(0, 1).
+* ``paper_case_inputs`` -- the manufactured solution of the paper's
+                  parallel test cases (Sec. 5.2, Table 4) at the nodes.
 * ``kappa``    -- log kappa ~ N(0, 1) per cell of an 8^d patch partition of
                   the unit domain, kappa = clip(exp(.), 0.1, 10), sampled at
                   the interior nodes (the value of the patch holding the node).
@@ -24,5 +26,5 @@ coordinates ((i+1) h, ...), h = 1/(n+1).
 from .generators import (  # noqa: F401
     WORKLOADS, Workload, nodes, sin_product, mms_source, bump_source,
     smooth_initial, lognormal_kappa, workload_inputs, batch_problem_specs,
-    gradient_problem_specs, spec_inputs, spec_target_inputs,
+    gradient_problem_specs, spec_inputs, spec_target_inputs, PaperCase, PAPER_CASES, paper_case_inputs,
 )

@@ -54,6 +54,47 @@ def mms_source(n, dim, times):
     return (dim * np.pi ** 2 - 1.0) * np.exp(-t)[..., None] * phi
 
 
+@dataclass(frozen=True)
+class PaperCase:
+    """A parallel test case of Sec. 5.2 (Table 4): Q2 elements on [-1, 1]^2
+    (here [0, 2]^2), n interior nodes per axis, Radau IIA with s stages over
+    nt steps up to tf, outer FGMRES restarted every 15 iterations."""
+    name: str
+    n: int
+    s: int
+    nt: int
+    tf: float
+    restart: int = 15
+    length: float = 2.0
+
+    @property
+    def N(self):
+        return self.n * self.n
+
+
+PAPER_CASES = {
+    # test case #1: h = 1.563e-2 (element side), 65025 nodes, 256 steps of 8.236e-2
+    "paper_case1_q2_n255_s3_nt256": PaperCase("paper_case1_q2_n255_s3_nt256", 255, 3, 256, 21.084),
+    # test case #2: h = 7.813e-3, 261121 nodes, 512 steps of 5.437e-2
+    "paper_case2_q2_n511_s3_nt512": PaperCase("paper_case2_q2_n511_s3_nt512", 511, 3, 512, 27.838),
+}
+
+
+def paper_case_inputs(case, times):
+    """Nodal source, initial value and exact solution of the test cases'
+    manufactured solution v = exp((tf - t) / 10) phi + 1, phi the cosine
+    bump of [-1, 1]^2 (on [0, 2]^2: sin(pi x / 2) sin(pi y / 2), at the nodes
+    the unit square's sin(pi x) sin(pi y)).  The constant 1 is the boundary
+    value; the interior unknowns carry v - 1, whose source is
+    f = (pi^2 / 2 - 1/10) exp((tf - t) / 10) phi.  Returns f (times' shape
+    plus N), u0 (N,) and exact(t) -> (N,) for v - 1."""
+    phi = sin_product(case.n, 2)
+    t = np.asarray(times, float)
+    f = (np.pi ** 2 / 2.0 - 0.1) * np.exp((case.tf - t) / 10.0)[..., None] * phi
+    u0 = np.exp(case.tf / 10.0) * phi
+    return f, u0, (lambda tt: np.exp((case.tf - tt) / 10.0) * phi)
+
+
 def _bump_params(rng, dim, nbumps=8):
     a = rng.standard_normal(nbumps)
     centers = rng.uniform(0.15, 0.85, (nbumps, dim))

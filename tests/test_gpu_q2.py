@@ -170,6 +170,32 @@ def test_paper_problem_iterations_and_error(precision):
         assert all(its[s, l][3] / 1.2 <= its[s, l][2] <= its[s, l][3] * 1.2 for l in LEVELS), its
 
 
+def test_paper_case1_shape_first_steps_match_stepping():
+    """At the shape of the paper's test case #1 (Sec. 5.2: Q2, 255^2 nodes,
+    s = 3, 256 steps, 66.7M unknowns) the solve with the FP32 P-tilde (right,
+    S-tilde by MGRIT) reaches the oracle's stepping on the first 8 steps, v
+    and V separately: the system is block lower triangular in time, so its
+    first steps depend on the first steps' data only."""
+    require_gpu()
+    import heat_inputs
+    case = heat_inputs.PAPER_CASES["paper_case1_q2_n255_s3_nt256"]
+    n, s, nt, N = case.n, case.s, case.nt, case.N
+    hp = _hp(n, s, nt, case.tf, restart=case.restart, tol=1e-10, inner_k=3, precision="fp32", schur="mgrit")
+    rng = np.random.default_rng(1005)
+    f = rng.standard_normal((nt, s, N))
+    u0 = rng.standard_normal(N)
+    announce("q2 paper case 1 shape")
+    x, st = hp.solve(hp.assemble_rhs(to_dev(f.ravel()), to_dev(u0)))
+    assert st["converged"] and st["relres"] <= 1e-10, st
+    steps = 8
+    v = to_host(x[: (steps + 1) * N]).reshape(steps + 1, N)
+    V = to_host(x[(nt + 1) * N: (nt + 1 + steps * s) * N]).reshape(steps, s, N)
+    del x
+    p8 = _prob(n, s, steps, steps * case.tf / nt)
+    vo, Vo = allatonce.split(p8, stepping.solve(p8, f[:steps], u0))
+    assert rel_err(v, vo) <= 1e-8 and rel_err(V, Vo) <= 1e-8
+
+
 def test_batch_mixes_q2_q1_and_finite_differences():
     """A batch holding Q2, Q1 and finite-difference problems equals the
     single solves bit for bit."""
