@@ -207,6 +207,12 @@ typedef struct aao_opts {
                               (simulated, as the paper simulates its lower
                               precisions); products that start a cycle stay
                               FP64.  stats.relaxed_* count them.  0 = off      */
+  int mgrit_coarse_k;      /* inner GMRES iterations of MGRIT's coarse
+                              propagator (the S-tilde step of mgrit_cf tau);
+                              the fine propagator keeps inner_k.  A cheaper
+                              coarse propagator shortens the sequential
+                              coarse sweep; with one MGRIT iteration S-tilde
+                              stays an approximation either way.  0 = inner_k */
 } aao_opts;
 
 /* Solve statistics (host struct filled by aao_solve*). */
@@ -238,7 +244,7 @@ typedef struct aao_problem aao_problem;   /* opaque handle */
  * nu1 = nu2 = 2, omega 0, precision FP64, use_graph 1, mg_tail_max 0,
  * coarse_max 0, inner_tol 0, schur AAO_SCHUR_SWEEP, mgrit_cf 8,
  * mgrit_iters 1, mgrit_fcf 0, side RIGHT, outer_precision FP64,
- * mg_low_from 0, relax_matvec 0, mg_coarse_fp32 0.  With use_graph the
+ * mg_low_from 0, relax_matvec 0, mg_coarse_fp32 0, mgrit_coarse_k 0.  With use_graph the
  * first application of P-tilde for a given (inner_k, cycles, transpose) is
  * captured into a HIP graph on a private stream and later applications
  * replay it on the handle's stream (inputs and outputs pass through fixed

@@ -159,12 +159,13 @@ def schur_propagator(ops, exact=False):
     return phi
 
 
-def coarse_stage_ops(ops, cf):
+def coarse_stage_ops(ops, cf, coarse_k=None):
     """StageOps of the same problem with the time step cf * tau (the MGRIT
-    coarse propagator takes one S-tilde step of that size)."""
+    coarse propagator takes one S-tilde step of that size), with coarse_k
+    inner GMRES iterations (None: the fine propagator's)."""
     p = ops.prob
     pc = allatonce.Problem(p.n, p.dim, p.s, 1, cf * p.tau, kappa=p.kappa, disc=p.disc, length=p.length)
-    return StageOps(pc, inner_k=ops.inner_k, inner_tol=ops.inner_tol, cycles=ops.cycles, omega=ops.omega,
+    return StageOps(pc, inner_k=coarse_k or ops.inner_k, inner_tol=ops.inner_tol, cycles=ops.cycles, omega=ops.omega,
                     nu1=ops.nu1, nu2=ops.nu2, exact_blocks=ops.exact_blocks, coarse_max=ops.coarse_max)
 
 
@@ -172,8 +173,9 @@ def apply_preconditioner(ops, r, exact=False, mgrit=None):
     """z = P-tilde^{-1} r (or P^{-1} r when exact=True) by block back-substitution.
 
     mgrit: None for the forward substitution in S-tilde, or a dict with keys
-    cf, iters and optionally relax ("F" / "FCF") to apply S-tilde^{-1} by
-    two-level MGRIT (``oracle.mgrit``) with the coarse step cf * tau.
+    cf, iters and optionally relax ("F" / "FCF") and coarse_k (the coarse
+    propagator's inner GMRES iterations) to apply S-tilde^{-1} by two-level
+    MGRIT (``oracle.mgrit``) with the coarse step cf * tau.
     """
     from . import mgrit as _mgrit
     prob = ops.prob
@@ -199,7 +201,7 @@ def apply_preconditioner(ops, r, exact=False, mgrit=None):
         zv = np.array(_mgrit.sequential(list(tv), phi))
     else:
         cf = mgrit["cf"]
-        phi_c = schur_propagator(coarse_stage_ops(ops, cf), exact)
+        phi_c = schur_propagator(coarse_stage_ops(ops, cf, mgrit.get("coarse_k")), exact)
         zv = np.array(_mgrit.solve(list(tv), phi, phi_c, cf, mgrit["iters"], mgrit.get("relax", "F")))
     return allatonce.join(zv, zV)
 

@@ -27,7 +27,8 @@ def _ptr(t):
 SOLVER_DEFAULTS = dict(restart=30, maxit=100, tol=1e-8, inner_k=3, cycles=1, nu1=2, nu2=2, omega=0.0,
                        precision="fp64", use_graph=True, mg_tail_max=0, coarse_max=0, inner_tol=0.0,
                        schur="sweep", mgrit_cf=8, mgrit_iters=1, mgrit_fcf=False, side="right",
-                       outer_precision="fp64", mg_low_from=0, mg_coarse_fp32=False, relax_matvec=False)
+                       outer_precision="fp64", mg_low_from=0, mg_coarse_fp32=False, relax_matvec=False,
+                       mgrit_coarse_k=0)
 
 
 def _solver_options(kw):
@@ -57,6 +58,7 @@ def _make_opts(lib, o):
     opts.mg_low_from = int(o["mg_low_from"])
     opts.mg_coarse_fp32 = int(bool(o["mg_coarse_fp32"]))
     opts.relax_matvec = int(bool(o["relax_matvec"]))
+    opts.mgrit_coarse_k = int(o["mgrit_coarse_k"])
     return opts
 
 

@@ -52,8 +52,9 @@ class Precond {
     Multigrid<TI, TM> mg;
     Tab tab;
     double Lc[SMAX * SMAX];
-    Stepper(aao_problem* h, bool transpose, double scale, int cinv_set)
-        : mg(h, h->stream, scaled(h, transpose, scale).data(), cinv_set) {
+    int k;   // inner GMRES iterations of this step size
+    Stepper(aao_problem* h, bool transpose, double scale, int cinv_set, int kin)
+        : mg(h, h->stream, scaled(h, transpose, scale).data(), cinv_set), k(kin) {
       const std::vector<double> L = scaled(h, transpose, scale);
       for (int q = 0; q < SMAX * SMAX; ++q) Lc[q] = q < (int)L.size() ? L[q] : 0.0;
       tab = h->tab;
@@ -74,9 +75,10 @@ class Precond {
 
   Precond(aao_problem* h, bool transpose, int k, int cycles)
       : h_(h), st_(h->stream), transpose_(transpose), k_(k), cycles_(cycles),
-        fine_(h, transpose, 1.0, transpose ? 1 : 0) {
+        fine_(h, transpose, 1.0, transpose ? 1 : 0, k) {
     if (h->opts.schur == AAO_SCHUR_MGRIT)
-      coarse_.reset(new Stepper(h, transpose, (double)h->opts.mgrit_cf, transpose ? 3 : 2));
+      coarse_.reset(new Stepper(h, transpose, (double)h->opts.mgrit_cf, transpose ? 3 : 2,
+                                h->opts.mgrit_coarse_k > 0 ? h->opts.mgrit_coarse_k : k));
     char* ws = h->ws;
     inV_ = reinterpret_cast<TI*>(ws + h->plan.inV);
     inZ_ = reinterpret_cast<TI*>(ws + h->plan.inZ);
@@ -121,7 +123,8 @@ class Precond {
     TRY(gs_pass<TR, TI>(const_cast<TR*>(rhs), inV_, a0, B, st_));
     TRY(basis_update<TR, TI, TI>(rhs, srhs, inV_, UV, sN, 0, inV_, sN, slots_, S::STRIDE, 0, S::INV, 0.0, sN, B,
                                  st_));
-    for (int j = 0; j < k_; ++j) {
+    const int kk = sp.k;
+    for (int j = 0; j < kk; ++j) {
       TI* Vj = inV_ + (int64_t)j * UV;
       TI* Zj = inZ_ + (int64_t)j * UV;
       // Rana: forward substitution over the stages
@@ -158,11 +161,11 @@ class Precond {
       a2.post = GS_POST_GIVENS;
       a2.j = j;
       TRY(gs_pass<TI, TI>(inW_, inV_, a2, B, st_));
-      if (j + 1 < k_)
+      if (j + 1 < kk)
         TRY(basis_update<TI, TI, TI>(inW_, sN, inV_, UV, sN, nd, inV_ + (int64_t)(j + 1) * UV, sN, slots_,
                                      S::STRIDE, S::H2, S::INV, 0.0, sN, B, st_));
     }
-    TRY(combine<TI, TI>(out, sout, inZ_, UV, sN, k_, slots_, S::STRIDE, 0, true, false, sN, B, st_));
+    TRY(combine<TI, TI>(out, sout, inZ_, UV, sN, kk, slots_, S::STRIDE, 0, true, false, sN, B, st_));
     return hipSuccess;
   }
 

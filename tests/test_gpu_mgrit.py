@@ -9,6 +9,8 @@ oracle.precond.apply_preconditioner).
   and variable diffusivity (dense coarsest inverses for the coarse step);
 * K - 1 iterations reproduce the forward substitution: GPU MGRIT equals the
   GPU sweep;
+* a coarse propagator with fewer inner GMRES iterations (mgrit_coarse_k)
+  equals the oracle's MGRIT with the same coarse propagator;
 * a solve with the MGRIT preconditioner (one iteration) reaches the unique
   solution x* = A^{-1} [b; f] (sequential stepping), forward and adjoint.
 Tolerance 1e-10 as for the substitution preconditioner (FP64 rounding
@@ -46,6 +48,49 @@ def test_apply_P_mgrit_fp64_matches_oracle(n, s, nt, cf, iters, fcf):
     exact_after = -(-(K - 1) // 2) if fcf else K - 1
     if iters < exact_after:
         assert rel_err(ref, sub) > 1e-9
+
+
+@pytest.mark.parametrize("n,s,nt,cf,iters,fcf,ck", [(24, 2, 12, 4, 1, False, 1), (20, 3, 10, 3, 1, False, 2),
+                                                     (20, 2, 7, 2, 2, False, 1)])
+def test_apply_P_mgrit_coarse_k_matches_oracle(n, s, nt, cf, iters, fcf, ck):
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    p = allatonce.Problem(n, 2, s, nt, 1.0)
+    hp = HeatProblem(2, n, s, nt, 1.0, inner_k=3, nu1=2, nu2=2, schur="mgrit", mgrit_cf=cf,
+                     mgrit_iters=iters, mgrit_fcf=fcf, mgrit_coarse_k=ck)
+    ops = precond.StageOps(p, inner_k=3, cycles=1, nu1=2, nu2=2)
+    r = np.random.default_rng(n + nt + ck).standard_normal(p.U)
+    announce("apply_P mgrit coarse k", n, s, nt, cf, iters, fcf, ck)
+    z = to_host(hp.apply_P(to_dev(r)))
+    relax = "FCF" if fcf else "F"
+    ref = precond.apply_preconditioner(ops, r, mgrit=dict(cf=cf, iters=iters, relax=relax, coarse_k=ck))
+    assert rel_err(z, ref) <= 1e-10
+    # the coarse propagator's inner count changes P-tilde
+    full = precond.apply_preconditioner(ops, r, mgrit=dict(cf=cf, iters=iters, relax=relax))
+    assert rel_err(ref, full) > 1e-9
+
+
+@pytest.mark.parametrize("adjoint_solve", [False, True])
+def test_solve_with_cheap_coarse_propagator_reaches_oracle(adjoint_solve):
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    n, s, nt = 28, 3, 12
+    rng = np.random.default_rng(44)
+    p = allatonce.Problem(n, 2, s, nt, 1.0)
+    hp = HeatProblem(2, n, s, nt, 1.0, tol=1e-11, precision="fp32", inner_k=4, schur="mgrit", mgrit_cf=4,
+                     mgrit_coarse_k=1)
+    announce("solve mgrit coarse k", adjoint_solve)
+    if adjoint_solve:
+        g = rng.standard_normal(p.U)
+        lam, st = hp.solve_adjoint(to_dev(g))
+        assert st["converged"], st
+        assert rel_err(to_host(lam), adjoint.solve(p, g)) <= 1e-8
+    else:
+        f = rng.standard_normal((nt, s, p.N))
+        u0 = rng.standard_normal(p.N)
+        x, st = hp.solve(hp.assemble_rhs(to_dev(f.ravel()), to_dev(u0)))
+        assert st["converged"], st
+        assert rel_err(to_host(x), stepping.solve(p, f, u0)) <= 1e-8
 
 
 def test_apply_P_mgrit_variable_kappa_matches_oracle():

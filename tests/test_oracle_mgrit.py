@@ -96,16 +96,20 @@ def test_scalar_error_recursion(a, a_c, cf):
     assert np.allclose(eps1, want, rtol=1e-10, atol=1e-13)
 
 
-def test_preconditioner_with_converged_mgrit_equals_substitution():
+@pytest.mark.parametrize("coarse_k", [None, 1])
+def test_preconditioner_with_converged_mgrit_equals_substitution(coarse_k):
+    """K - 1 F-iterations make every C-point exact whatever the coarse
+    propagator is, so a cheaper coarse propagator (fewer inner GMRES
+    iterations) still reproduces the substitution."""
     n, s, nt, cf = 10, 2, 7, 3
     p = allatonce.Problem(n, 2, s, nt, 1.0)
     ops = precond.StageOps(p, inner_k=2, cycles=1, nu1=2, nu2=2)
     r = np.random.default_rng(6).standard_normal(p.U)
     z_sub = precond.apply_preconditioner(ops, r)
     K = -(-nt // cf)
-    z_mg = precond.apply_preconditioner(ops, r, mgrit=dict(cf=cf, iters=K - 1))
+    z_mg = precond.apply_preconditioner(ops, r, mgrit=dict(cf=cf, iters=K - 1, coarse_k=coarse_k))
     assert np.allclose(z_mg, z_sub, rtol=0, atol=1e-12 * np.abs(z_sub).max())
     # a single iteration is an approximation, close but not equal
-    z_1 = precond.apply_preconditioner(ops, r, mgrit=dict(cf=cf, iters=1))
+    z_1 = precond.apply_preconditioner(ops, r, mgrit=dict(cf=cf, iters=1, coarse_k=coarse_k))
     d = np.linalg.norm(z_1 - z_sub) / np.linalg.norm(z_sub)
     assert 1e-12 < d < 0.5
