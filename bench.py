@@ -3,9 +3,9 @@
 One step = one full FGMRES solve to a true FP64 relative residual of 1e-8 of
 the all-at-once system (paper eq. (2.4)) with the block preconditioner
 (eqs. (3.2)-(3.3)) applied in FP32 (the mixed-precision arm, approach A2),
-its S-tilde solve done by one two-level MGRIT iteration (coarsening factor 4,
-the coarse propagator with one inner GMRES iteration; the parallel route of
-Sec. 5.2).  The same solve with the FP64
+its S-tilde solve done by one two-level MGRIT iteration (coarsening factor 4;
+the parallel route of Sec. 5.2), whose steps solve Theta-tilde with one inner
+GMRES iteration where the block-diagonal Theta-tilde solve takes four.  The same solve with the FP64
 preconditioner (approach A1) is timed beside it with equal inner settings
 (4 inner GMRES iterations, one V-cycle with 2 + 2 Jacobi sweeps per shifted
 block), and both again with S-tilde by forward substitution.  Workload: 2D
@@ -60,6 +60,8 @@ def parse():
                     help="S-tilde by two-level MGRIT or by forward substitution")
     ap.add_argument("--mgrit-cf", type=int, default=4)
     ap.add_argument("--mgrit-iters", type=int, default=1)
+    ap.add_argument("--schur-k", type=int, default=1,
+                    help="inner GMRES iterations inside S-tilde's steps (0 = inner k)")
     ap.add_argument("--mgrit-coarse-k", type=int, default=1,
                     help="inner GMRES iterations of MGRIT's coarse propagator (0 = inner k)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch shapes")
@@ -101,7 +103,7 @@ def main():
     torch.cuda.set_device(dev)
     common = dict(restart=w.restart, tol=1e-8, inner_k=args.inner_k, cycles=args.cycles, nu1=args.nu,
                   nu2=args.nu, schur=args.schur, mgrit_cf=args.mgrit_cf, mgrit_iters=args.mgrit_iters,
-                  mgrit_coarse_k=args.mgrit_coarse_k)
+                  mgrit_coarse_k=args.mgrit_coarse_k, schur_k=args.schur_k)
     t_setup = time.perf_counter()
     hp_mix = HeatProblem(w.dim, w.n, w.s, w.nt, w.T, precision=args.mixed, **common)
     f, u0 = heat_inputs.workload_inputs(w, hp_mix.stage_times())
@@ -211,7 +213,7 @@ def main():
                    "unknowns": hp_mix.U, "restart": w.restart, "tol": 1e-8,
                    "inner_k": args.inner_k, "cycles": args.cycles, "nu1": args.nu, "nu2": args.nu,
                    "schur": args.schur, "mgrit_cf": args.mgrit_cf, "mgrit_iters": args.mgrit_iters,
-                   "mgrit_coarse_k": args.mgrit_coarse_k or args.inner_k,
+                   "mgrit_coarse_k": args.mgrit_coarse_k or args.inner_k, "schur_k": args.schur_k or args.inner_k,
                    "preconditioner": args.mixed, "launch_shapes": tune and {k: tune[k] for k in
                                                                             ("tall_min_b", "tail_extend", "source")},
                    "parallelism": "single GPU"},
@@ -244,7 +246,8 @@ def vcycle_kernels(hp, precision, reps):
     nt, s, k = hp.nt, hp.s, hp.options["inner_k"]
     cf = hp.options["mgrit_cf"]
     K = -(-nt // cf)
-    per_solve = k * s * hp.options["cycles"]   # V-cycles per inner GMRES solve
+    ks = hp.options["schur_k"] or k
+    per_solve = ks * s * hp.options["cycles"]   # V-cycles per inner GMRES solve of an S-tilde step
     weight = {}
 
     def add(B, n):
@@ -265,7 +268,7 @@ def vcycle_kernels(hp, precision, reps):
             add(1, per_solve)
     else:
         add(1, per_solve * nt)
-    add(nt, per_solve)
+    add(nt, k * s * hp.options["cycles"])   # Theta-tilde: every step at once, inner_k iterations
     counts = sorted(weight)
 
     def kbytes(label):
@@ -571,7 +574,7 @@ def extras(args, autotune):
     for prec in ["fp64", "fp32", "bf16", "fp16"]:
         hp = HeatProblem(w3.dim, w3.n, w3.s, w3.nt, w3.T, restart=w3.restart, tol=1e-8, inner_k=3,
                          precision=prec, schur=args.schur, mgrit_cf=args.mgrit_cf,
-                         mgrit_coarse_k=args.mgrit_coarse_k)
+                         mgrit_coarse_k=args.mgrit_coarse_k, schur_k=args.schur_k)
         f, u0 = heat_inputs.workload_inputs(w3, hp.stage_times())
         rhs = hp.assemble_rhs(torch.from_numpy(np.ascontiguousarray(f.ravel())).cuda(), torch.from_numpy(u0).cuda())
         del f
@@ -593,6 +596,7 @@ def extras(args, autotune):
         torch.cuda.empty_cache()
     out[w3.name] = {"unknowns": w3.n ** 3 * (w3.nt * (w3.s + 1) + 1), "restart": w3.restart, "inner_k": 3,
                     "schur": args.schur, "mgrit_cf": args.mgrit_cf, "mgrit_coarse_k": args.mgrit_coarse_k,
+                    "schur_k": args.schur_k,
                     "solves": res3, "roofline_apply_A": apply3}
     specs = heat_inputs.batch_problem_specs()
     data = []
@@ -601,7 +605,7 @@ def extras(args, autotune):
         data.append(heat_inputs.spec_inputs(sp, times))
     hb = HeatBatch([dict(dim=2, n=sp["n"], s=sp["s"], nt=sp["nt"], kappa=kap) for sp, (kap, _, _) in zip(specs, data)],
                    streams=4, precision="fp32", tol=1e-8, inner_k=3, schur=args.schur, mgrit_cf=args.mgrit_cf,
-                   mgrit_coarse_k=args.mgrit_coarse_k)
+                   mgrit_coarse_k=args.mgrit_coarse_k, schur_k=args.schur_k)
     rhs = hb.assemble_rhs(torch.from_numpy(np.concatenate([d[1].ravel() for d in data])).cuda(),
                           torch.from_numpy(np.concatenate([d[2].ravel() for d in data])).cuda())
     times = []
@@ -623,7 +627,7 @@ def extras(args, autotune):
     torch.cuda.empty_cache()
     cases = ["paper_case1_q2_n255_s3_nt256"] + (["paper_case2_q2_n511_s3_nt512"] if args.paper_case2 else [])
     for name in cases:
-        out[name] = paper_case(heat_inputs.PAPER_CASES[name], args.mgrit_cf, args.mgrit_coarse_k)
+        out[name] = paper_case(heat_inputs.PAPER_CASES[name], args.mgrit_cf, args.mgrit_coarse_k, args.schur_k)
     return out
 
 
@@ -640,14 +644,15 @@ PAPER_TABLE = {
 }
 
 
-def paper_case(case, mgrit_cf, mgrit_coarse_k, reps=2):
+def paper_case(case, mgrit_cf, mgrit_coarse_k, schur_k, reps=2):
     """One of the paper's parallel test cases (Q2 elements, Sec. 5.2) with the
     paper's solver settings: left-preconditioned FGMRES(15), tol 1e-8, the
     inner GMRES on Theta-tilde stopped after 3 iterations or at 1e-3 (P-tilde
     in FP32) and after 5 or at 1e-6 (FP64), S-tilde by MGRIT with the fine
     propagator on the coarse level too (coarsening factor 8); plus the FP32
     P-tilde on the right with the benchmark's MGRIT (mgrit_cf, with
-    mgrit_coarse_k inner iterations on the coarse level).  Left
+    mgrit_coarse_k inner iterations on the coarse level and schur_k in the
+    S-tilde steps).  Left
     preconditioning stops on the preconditioned residual, so it wants P-tilde
     close to linear: the cheaper coarse propagator is kept to the right.
     Reports the solve time (mean of ``reps`` after a warm-up), the
@@ -661,7 +666,7 @@ def paper_case(case, mgrit_cf, mgrit_coarse_k, reps=2):
     settings = {"left_fp32": dict(side="left", precision="fp32", inner_k=3, inner_tol=1e-3, **paper_mgrit),
                 "left_fp64": dict(side="left", precision="fp64", inner_k=5, inner_tol=1e-6, **paper_mgrit),
                 "right_fp32": dict(side="right", precision="fp32", inner_k=3, inner_tol=1e-3, mgrit_cf=mgrit_cf,
-                                   mgrit_coarse_k=mgrit_coarse_k)}
+                                   mgrit_coarse_k=mgrit_coarse_k, schur_k=schur_k)}
     res = {}
     for label, kw in settings.items():
         hp = HeatProblem(2, case.n, case.s, case.nt, case.tf, disc="q2", length=case.length, restart=case.restart,
@@ -694,7 +699,8 @@ def paper_case(case, mgrit_cf, mgrit_coarse_k, reps=2):
                       "inner_iterations": st["inner_iterations"], "converged": st["converged"],
                       "true_relres": st["relres"], "max_error_vs_manufactured": err / vmax,
                       "theta_ms": st["theta_ms"], "schur_ms": st["schur_ms"], "mgrit_cf": kw["mgrit_cf"],
-                      "mgrit_coarse_k": kw["mgrit_coarse_k"] or kw["inner_k"]}
+                      "mgrit_coarse_k": kw["mgrit_coarse_k"] or kw["inner_k"],
+                      "schur_k": kw.get("schur_k", 0) or kw["inner_k"]}
         del hp, rhs, v
         torch.cuda.empty_cache()
     res["left_fp32_vs_fp64_speedup"] = res["left_fp64"]["solve_s"] / res["left_fp32"]["solve_s"]

@@ -213,6 +213,10 @@ typedef struct aao_opts {
                               coarse propagator shortens the sequential
                               coarse sweep; with one MGRIT iteration S-tilde
                               stays an approximation either way.  0 = inner_k */
+  int schur_k;             /* inner GMRES iterations of the Theta-tilde solves
+                              inside S-tilde's steps (the substitution's, and
+                              MGRIT's fine propagator); Theta-tilde's own
+                              block solve keeps inner_k.  0 = inner_k          */
 } aao_opts;
 
 /* Solve statistics (host struct filled by aao_solve*). */
@@ -244,7 +248,7 @@ typedef struct aao_problem aao_problem;   /* opaque handle */
  * nu1 = nu2 = 2, omega 0, precision FP64, use_graph 1, mg_tail_max 0,
  * coarse_max 0, inner_tol 0, schur AAO_SCHUR_SWEEP, mgrit_cf 8,
  * mgrit_iters 1, mgrit_fcf 0, side RIGHT, outer_precision FP64,
- * mg_low_from 0, relax_matvec 0, mg_coarse_fp32 0, mgrit_coarse_k 0.  With use_graph the
+ * mg_low_from 0, relax_matvec 0, mg_coarse_fp32 0, mgrit_coarse_k 0, schur_k 0.  With use_graph the
  * first application of P-tilde for a given (inner_k, cycles, transpose) is
  * captured into a HIP graph on a private stream and later applications
  * replay it on the handle's stream (inputs and outputs pass through fixed

@@ -88,8 +88,11 @@ class StageOps:
     """Theta_hat, Rana's preconditioner and the shifted-block solvers of one problem."""
 
     def __init__(self, prob, inner_k=3, inner_tol=0.0, cycles=1, omega=None,
-                 nu1=1, nu2=1, exact_blocks=False, coarse_max=multigrid.COARSE_MAX):
+                 nu1=1, nu2=1, exact_blocks=False, coarse_max=multigrid.COARSE_MAX, schur_k=None):
         self.prob = prob
+        # inner GMRES iterations of the Theta-tilde solves inside S-tilde's
+        # steps (None: inner_k, the paper's single inner solver)
+        self.schur_k = schur_k or inner_k
         self.K = prob.K()
         self.Th = allatonce.theta_hat(prob, self.K)
         self.L, _ = tableau.crout(prob.A)
@@ -132,12 +135,13 @@ class StageOps:
     def theta_apply(self, x):
         return self.Th @ x
 
-    def theta_tilde_inv(self, r):
-        """Theta-tilde^{-1} r for one step: inner GMRES(k) with Rana."""
+    def theta_tilde_inv(self, r, k=None):
+        """Theta-tilde^{-1} r for one step: inner GMRES(k) with Rana (k
+        defaults to inner_k)."""
         s, N = self.prob.s, self.prob.N
         x, _ = gmres(self.theta_apply,
                      lambda v: self.rana(v.reshape(s, N)).ravel(),
-                     np.asarray(r, float).ravel(), self.inner_k, self.inner_tol)
+                     np.asarray(r, float).ravel(), k or self.inner_k, self.inner_tol)
         return x.reshape(s, N)
 
     def theta_inv(self, r):
@@ -151,7 +155,7 @@ def schur_propagator(ops, exact=False):
     """Phi(z) = z - X-tilde z, X-tilde = tau (b^T (x) I) Theta-tilde^{-1} (e (x) K)
     (eq. (3.3)); with exact=True, Theta_hat^{-1} in place of Theta-tilde^{-1}."""
     prob = ops.prob
-    solve_step = ops.theta_inv if exact else ops.theta_tilde_inv
+    solve_step = ops.theta_inv if exact else (lambda r: ops.theta_tilde_inv(r, ops.schur_k))
 
     def phi(z):
         y = solve_step(np.tile(ops.K @ z, (prob.s, 1)))

@@ -33,7 +33,7 @@ class Opts(ctypes.Structure):
                 ("inner_tol", c_double), ("schur", c_int), ("mgrit_cf", c_int), ("mgrit_iters", c_int),
                 ("mgrit_fcf", c_int), ("side", c_int),
                 ("outer_precision", c_int), ("mg_low_from", c_int), ("mg_coarse_fp32", c_int),
-                ("relax_matvec", c_int), ("mgrit_coarse_k", c_int)]
+                ("relax_matvec", c_int), ("mgrit_coarse_k", c_int), ("schur_k", c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -28,7 +28,7 @@ SOLVER_DEFAULTS = dict(restart=30, maxit=100, tol=1e-8, inner_k=3, cycles=1, nu1
                        precision="fp64", use_graph=True, mg_tail_max=0, coarse_max=0, inner_tol=0.0,
                        schur="sweep", mgrit_cf=8, mgrit_iters=1, mgrit_fcf=False, side="right",
                        outer_precision="fp64", mg_low_from=0, mg_coarse_fp32=False, relax_matvec=False,
-                       mgrit_coarse_k=0)
+                       mgrit_coarse_k=0, schur_k=0)
 
 
 def _solver_options(kw):
@@ -59,6 +59,7 @@ def _make_opts(lib, o):
     opts.mg_coarse_fp32 = int(bool(o["mg_coarse_fp32"]))
     opts.relax_matvec = int(bool(o["relax_matvec"]))
     opts.mgrit_coarse_k = int(o["mgrit_coarse_k"])
+    opts.schur_k = int(o["schur_k"])
     return opts
 
 

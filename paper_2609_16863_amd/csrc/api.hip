@@ -169,6 +169,7 @@ bool valid_opts(const aao_opts* o, std::string& why) {
   if (o->mg_coarse_fp32 != 0 && o->mg_coarse_fp32 != 1) { why = "mg_coarse_fp32 must be 0 or 1"; return false; }
   if (o->relax_matvec != 0 && o->relax_matvec != 1) { why = "relax_matvec must be 0 or 1"; return false; }
   if (o->mgrit_coarse_k < 0 || o->mgrit_coarse_k > aao::KMAX) { why = "mgrit_coarse_k must be in [0, 12]"; return false; }
+  if (o->schur_k < 0 || o->schur_k > aao::KMAX) { why = "schur_k must be in [0, 12]"; return false; }
   return true;
 }
 
@@ -243,6 +244,7 @@ void aao_default_opts(aao_opts* o) {
   o->mg_coarse_fp32 = 0;
   o->relax_matvec = 0;
   o->mgrit_coarse_k = 0;
+  o->schur_k = 0;
 }
 
 int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) {

@@ -112,7 +112,7 @@ class Precond {
   // out_b = Theta-tilde^{-1} rhs_b for B instances (rhs, out: s*N each),
   // with the step size of `sp`.
   template <class TR>
-  hipError_t inner(Stepper& sp, const TR* rhs, int64_t srhs, TI* out, int64_t sout, int B) {
+  hipError_t inner(Stepper& sp, const TR* rhs, int64_t srhs, TI* out, int64_t sout, int B, int kin = 0) {
     const int64_t N = h_->N, sN = (int64_t)h_->s * N, UV = h_->UV;
     // beta = ||rhs||, first basis vector rhs / beta
     GSArgs a0 = gs_args(sN, B);
@@ -123,7 +123,7 @@ class Precond {
     TRY(gs_pass<TR, TI>(const_cast<TR*>(rhs), inV_, a0, B, st_));
     TRY(basis_update<TR, TI, TI>(rhs, srhs, inV_, UV, sN, 0, inV_, sN, slots_, S::STRIDE, 0, S::INV, 0.0, sN, B,
                                  st_));
-    const int kk = sp.k;
+    const int kk = kin > 0 ? kin : sp.k;
     for (int j = 0; j < kk; ++j) {
       TI* Vj = inV_ + (int64_t)j * UV;
       TI* Zj = inZ_ + (int64_t)j * UV;
@@ -177,13 +177,14 @@ class Precond {
   hipError_t phi_step(Stepper& sp, const TT* t, int64_t stt, const TI* zin, int64_t szin, TI* out, int64_t sout,
                       int B) {
     const int64_t sN = (int64_t)h_->s * h_->N;
+    const int ks = h_->opts.schur_k;   // S-tilde's own inner count (0: the stepper's)
     if (!transpose_) {
       TRY(schur_kz<TI>(h_, zin, szin, srhs_, sN, B, st_));
-      TRY(inner<TI>(sp, srhs_, sN, sy_, sN, B));
+      TRY(inner<TI>(sp, srhs_, sN, sy_, sN, B, ks));
       return phi_update<TI, TT>(h_, sp.tab, t, stt, zin, szin, sy_, sN, out, sout, B, st_);
     }
     TRY(schurT_bw<TI>(h_, zin, szin, srhs_, sN, B, st_));
-    TRY(inner<TI>(sp, srhs_, sN, sy_, sN, B));
+    TRY(inner<TI>(sp, srhs_, sN, sy_, sN, B, ks));
     return phiT_update<TI, TT>(h_, sp.tab.tau, t, stt, zin, szin, sy_, sN, out, sout, B, st_);
   }
 

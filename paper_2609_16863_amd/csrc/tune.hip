@@ -44,7 +44,8 @@ std::string tune_key(const aao_problem* h) {
     << " vark=" << (h->vark ? 1 : 0) << " nu=" << h->opts.nu1 << "," << h->opts.nu2 << " k=" << h->opts.inner_k
     << " schur=" << h->opts.schur << " cf=" << h->opts.mgrit_cf << " it=" << h->opts.mgrit_iters
     << " fcf=" << h->opts.mgrit_fcf << " coarse=" << h->opts.coarse_max << " tail=" << h->opts.mg_tail_max
-    << " low=" << h->opts.mg_low_from << "," << h->opts.mg_coarse_fp32;
+    << " low=" << h->opts.mg_low_from << "," << h->opts.mg_coarse_fp32 << " sk=" << h->opts.schur_k
+    << " ck=" << h->opts.mgrit_coarse_k;
   return k.str();
 }
 
@@ -107,8 +108,11 @@ int aao_autotune(aao_problem* h, int reps, const char* cache_path, aao_tune* out
   aao_tune& r = out ? *out : local;
   r = aao_tune{};
   // block counts per launch and V-cycles per P-tilde application at each
-  // (k inner iterations x s stages x cycles per shifted-block solve)
-  const double per_solve = (double)h->opts.inner_k * h->s * h->opts.cycles;
+  // (k inner iterations x s stages x cycles per shifted-block solve; the
+  // S-tilde steps take schur_k iterations, MGRIT's coarse ones mgrit_coarse_k)
+  const double per_v = (double)h->s * h->opts.cycles;
+  const double per_solve = per_v * (h->opts.schur_k > 0 ? h->opts.schur_k : h->opts.inner_k);
+  const double per_coarse = per_v * (h->opts.mgrit_coarse_k > 0 ? h->opts.mgrit_coarse_k : h->opts.inner_k);
   const int nt = h->nt;
   int K = 1;
   if (h->opts.schur == AAO_SCHUR_MGRIT) K = (nt + h->opts.mgrit_cf - 1) / h->opts.mgrit_cf;
@@ -117,12 +121,12 @@ int aao_autotune(aao_problem* h, int reps, const char* cache_path, aao_tune* out
   r.blocks[2] = nt;
   if (h->opts.schur == AAO_SCHUR_MGRIT) {
     const int c = h->opts.mgrit_cf, it = h->opts.mgrit_iters;
-    r.weight[0] = per_solve * it * std::max(K - 2, 0);
+    r.weight[0] = per_coarse * it * std::max(K - 2, 0);
     r.weight[1] = per_solve * ((double)it * c * (h->opts.mgrit_fcf ? 2 : 1) + (c - 1));
   } else {
     r.weight[0] = per_solve * nt;
   }
-  r.weight[2] += per_solve;
+  r.weight[2] += per_v * h->opts.inner_k;
   const std::string key = tune_key(h);
   const aao_problem::Tune saved = h->tune;
   int tall = 0, ext = 0;

@@ -10,7 +10,9 @@ oracle.precond.apply_preconditioner).
 * K - 1 iterations reproduce the forward substitution: GPU MGRIT equals the
   GPU sweep;
 * a coarse propagator with fewer inner GMRES iterations (mgrit_coarse_k)
-  equals the oracle's MGRIT with the same coarse propagator;
+  equals the oracle's MGRIT with the same coarse propagator, and S-tilde's
+  steps with their own inner count (schur_k) equal the oracle's, with the
+  substitution and with MGRIT;
 * a solve with the MGRIT preconditioner (one iteration) reaches the unique
   solution x* = A^{-1} [b; f] (sequential stepping), forward and adjoint.
 Tolerance 1e-10 as for the substitution preconditioner (FP64 rounding
@@ -70,6 +72,25 @@ def test_apply_P_mgrit_coarse_k_matches_oracle(n, s, nt, cf, iters, fcf, ck):
     assert rel_err(ref, full) > 1e-9
 
 
+@pytest.mark.parametrize("schur,sk,ck", [("sweep", 1, 0), ("mgrit", 1, 1), ("mgrit", 2, 0)])
+def test_apply_P_schur_k_matches_oracle(schur, sk, ck):
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    n, s, nt, cf = 24, 3, 10, 4
+    p = allatonce.Problem(n, 2, s, nt, 1.0)
+    hp = HeatProblem(2, n, s, nt, 1.0, inner_k=4, nu1=2, nu2=2, schur=schur, mgrit_cf=cf, schur_k=sk,
+                     mgrit_coarse_k=ck)
+    ops = precond.StageOps(p, inner_k=4, cycles=1, nu1=2, nu2=2, schur_k=sk)
+    r = np.random.default_rng(17 + sk).standard_normal(p.U)
+    announce("apply_P schur k", schur, sk, ck)
+    z = to_host(hp.apply_P(to_dev(r)))
+    mg = None if schur == "sweep" else dict(cf=cf, iters=1, coarse_k=ck or None)
+    ref = precond.apply_preconditioner(ops, r, mgrit=mg)
+    assert rel_err(z, ref) <= 1e-10
+    full = precond.apply_preconditioner(precond.StageOps(p, inner_k=4, cycles=1, nu1=2, nu2=2), r, mgrit=mg)
+    assert rel_err(ref, full) > 1e-9
+
+
 @pytest.mark.parametrize("adjoint_solve", [False, True])
 def test_solve_with_cheap_coarse_propagator_reaches_oracle(adjoint_solve):
     require_gpu()
@@ -78,7 +99,7 @@ def test_solve_with_cheap_coarse_propagator_reaches_oracle(adjoint_solve):
     rng = np.random.default_rng(44)
     p = allatonce.Problem(n, 2, s, nt, 1.0)
     hp = HeatProblem(2, n, s, nt, 1.0, tol=1e-11, precision="fp32", inner_k=4, schur="mgrit", mgrit_cf=4,
-                     mgrit_coarse_k=1)
+                     mgrit_coarse_k=1, schur_k=1)
     announce("solve mgrit coarse k", adjoint_solve)
     if adjoint_solve:
         g = rng.standard_normal(p.U)

@@ -69,6 +69,30 @@ def test_rana_exact_for_one_stage():
     assert np.allclose(ops.theta_tilde_inv(r), ops.theta_inv(r), rtol=1e-12, atol=1e-12)
 
 
+def test_schur_steps_take_their_own_inner_count():
+    """S-tilde's steps use schur_k inner iterations: one iteration from zero
+    is the minimal-residual multiple of Rana's step, x = alpha z with
+    z = Rana(r), w = Theta_hat z, alpha = <r, w> / <w, w>; the propagator of
+    a schur_k = 1 problem applies exactly that."""
+    p, _, _, rng = _prob(2, 6, 3, 3)
+    ops = precond.StageOps(p, inner_k=3, nu1=2, nu2=2, schur_k=1)
+    assert ops.schur_k == 1 and ops.inner_k == 3
+    r = rng.standard_normal((3, p.N))
+    z = ops.rana(r).ravel()
+    w = ops.Th @ z
+    alpha = (r.ravel() @ w) / (w @ w)
+    assert np.allclose(ops.theta_tilde_inv(r, 1).ravel(), alpha * z, rtol=1e-12, atol=1e-13)
+    v = rng.standard_normal(p.N)
+    phi = precond.schur_propagator(ops)
+    rhs = np.tile(ops.K @ v, (3, 1))
+    zr = ops.rana(rhs).ravel()
+    wr = ops.Th @ zr
+    y = ((rhs.ravel() @ wr) / (wr @ wr) * zr).reshape(3, p.N)
+    assert np.allclose(phi(v), v - p.tau * np.tensordot(p.b, y, axes=(0, 0)), rtol=1e-12, atol=1e-12)
+    # the default takes inner_k, which differs
+    assert not np.allclose(precond.schur_propagator(precond.StageOps(p, inner_k=3, nu1=2, nu2=2))(v), phi(v))
+
+
 def test_rana_is_block_lower_triangular_solve():
     p, _, _, rng = _prob(2, 4, 3, 2)
     ops = precond.StageOps(p, exact_blocks=True)
