@@ -32,6 +32,15 @@ hipError_t fe_schur_kz(const aao_problem* h, const T* zin, int64_t szin, T* out,
 // t <- Chebyshev approximation of M^{-1} t on B blocks, in place (ya, yb: scratch, B N values each)
 template <class T>
 hipError_t fe_mass_solve(const aao_problem* h, T* t, T* ya, T* yb, int B, hipStream_t st);
+// Level 0 of the multigrid for Q2 elements (M + a K, the shift a = tau L_ii
+// scaled as the V-cycle asks): a weighted Jacobi sweep xin -> xout (from
+// zero: omega D^{-1} b), and the residual r = b - (M + a K) x; B instances
+template <class T>
+hipError_t fe_q2_smooth(const aao_problem* h, double a, const T* xin, int64_t sxin, T* xout, int64_t sxout,
+                        const T* b, int64_t sb, double omega, bool zero_init, int B, hipStream_t st);
+template <class T>
+hipError_t fe_q2_residual(const aao_problem* h, double a, const T* x, int64_t sx, const T* b, int64_t sb, T* r,
+                          int64_t sr, int B, hipStream_t st);
 // rhs = [M u0; 0; M f]
 hipError_t fe_assemble_rhs(const aao_problem* h, const double* f, const double* u0, double* rhs, hipStream_t st);
 

@@ -11,6 +11,7 @@
 #include <type_traits>
 
 #include "aao_internal.h"
+#include "fe.h"
 #include "krylov.h"
 #include "mg.h"
 #include "stencil.h"
@@ -24,10 +25,9 @@ constexpr int TPB = 256;
 // the stored 9-point stencil op.st9 when that is set (2D, variable kappa).
 // KIND_STENCIL9: the same level in the LDS-tiled kernels, which keep the
 // stencil coefficients of their nodes in registers.
-// KIND_Q2: level 0 of biquadratic elements (2D), the tensor form of 1D
-// factors with five diagonals (op.tri holds M(i, i + d) and T(i, i + d),
-// d = -2..2, ten arrays of n); it runs in the grid kernels only.
-enum { KIND_FINE = 0, KIND_FINE_VK = 1, KIND_TENSOR = 2, KIND_STENCIL9 = 3, KIND_Q2 = 4 };
+// (Level 0 of biquadratic elements has its own kernels, fe_q2_smooth and
+// fe_q2_residual in kern_fe.hip.)
+enum { KIND_FINE = 0, KIND_FINE_VK = 1, KIND_TENSOR = 2, KIND_STENCIL9 = 3 };
 
 template <class C>
 struct Tri3 {
@@ -50,11 +50,6 @@ template <int DIM, int KIND, class C>
 __device__ __forceinline__ C level_diag(const LevelOp<C>& op, int p, int i, int j, int k) {
   if (KIND == KIND_FINE) return C(1) + op.a * op.ih2 * C(2 * DIM);
   if (KIND == KIND_FINE_VK) return C(1) + op.a * op.ih2 * stencil_K_diag<DIM, true, C>(p, op.faces);
-  if (KIND == KIND_Q2) {
-    const int n = op.n;
-    const C mi = op.tri[2 * n + i], ti = op.tri[7 * n + i], mj = op.tri[2 * n + j], tj = op.tri[7 * n + j];
-    return mi * mj + op.a * (ti * mj + mi * tj);
-  }
   const Tri3<C> ri = tri_row(op.tri, op.n, i), rj = tri_row(op.tri, op.n, j);
   if (DIM == 2 && op.st9) return ri.m[1] * rj.m[1] + op.a * op.st9[4 * op.N + p];
   if (DIM == 2) return ri.m[1] * rj.m[1] + op.a * (ri.t[1] * rj.m[1] + ri.m[1] * rj.t[1]);
@@ -71,34 +66,6 @@ __device__ __forceinline__ void level_apply(const T* __restrict__ x, const Level
   if (KIND == KIND_FINE || KIND == KIND_FINE_VK) {
     const C kx = stencil_K<DIM, KIND == KIND_FINE_VK, T, C>(x, p, i, j, k, n, (int)op.N, op.faces);
     Ax = ld<T, C>(x + p) + op.a * op.ih2 * kx;
-    diag = level_diag<DIM, KIND, C>(op, p, i, j, k);
-    return;
-  }
-  if (KIND == KIND_Q2) {
-    // (M_y (x) (M_x + a T_x) + a T_y (x) M_x) x over the 5 x 5 neighbourhood
-    C mx[5], px[5];
-#pragma unroll
-    for (int d = 0; d < 5; ++d) {
-      mx[d] = op.tri[d * n + i];
-      px[d] = mx[d] + op.a * op.tri[(5 + d) * n + i];
-    }
-    C acc = C(0);
-#pragma unroll
-    for (int dj = -2; dj <= 2; ++dj) {
-      const int jj = j + dj;
-      if (jj < 0 || jj >= n) continue;
-      C pv = C(0), qv = C(0);
-#pragma unroll
-      for (int di = -2; di <= 2; ++di) {
-        const int ii = i + di;
-        if (ii < 0 || ii >= n) continue;
-        const C xv = ld<T, C>(x + p + dj * n + di);
-        pv += px[di + 2] * xv;
-        qv += mx[di + 2] * xv;
-      }
-      acc += op.tri[(dj + 2) * n + j] * pv + op.a * op.tri[(dj + 7) * n + j] * qv;
-    }
-    Ax = acc;
     diag = level_diag<DIM, KIND, C>(op, p, i, j, k);
     return;
   }
@@ -1770,7 +1737,8 @@ hipError_t Multigrid<TI, TM>::smooth(int l, int stage, Vec xin, Vec xout, Vec b,
   const int d3 = h_->dim == 3;
   if (l == 0) {
     if (h_->fe_order == 2) {
-      hipLaunchKernelGGL((k_smooth<2, KIND_Q2, TI, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (TI*)xout.ptr, xout.stride, (const TI*)b.ptr, b.stride, op, omega, (int)zero_init);
+      return fe_q2_smooth<TI>(h_, a_[stage], (const TI*)xin.ptr, xin.stride, (TI*)xout.ptr, xout.stride,
+                              (const TI*)b.ptr, b.stride, h_->omega, zero_init, B, st_);
     } else if (h_->vark) {
       if (d3) hipLaunchKernelGGL((k_smooth<3, KIND_FINE_VK, TI, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (TI*)xout.ptr, xout.stride, (const TI*)b.ptr, b.stride, op, omega, (int)zero_init);
       else hipLaunchKernelGGL((k_smooth<2, KIND_FINE_VK, TI, C>), g, dim3(TPB), 0, st_, (const TI*)xin.ptr, xin.stride, (TI*)xout.ptr, xout.stride, (const TI*)b.ptr, b.stride, op, omega, (int)zero_init);
@@ -1807,9 +1775,18 @@ hipError_t Multigrid<TI, TM>::resid_restrict(int l, int stage, Vec x, Vec b, Vec
       using TF = decltype(tf);
       using TC = decltype(tc);
 #define RES(D, K) hipLaunchKernelGGL((k_residual<D, K, TF, C>), gf, dim3(TPB), 0, st_, (const TF*)x.ptr, x.stride, (const TF*)b.ptr, b.stride, (TF*)r.ptr, r.stride, opf)
-      if (!d3) RES(2, KIND_Q2);
-      else if (l == 0) RES(3, KIND_FINE);
-      else RES(3, KIND_TENSOR);
+      if (!d3) {
+        // level 0 of Q2 elements, always stored as TI
+        if constexpr (std::is_same<TF, TI>::value)
+          MG_TRY(fe_q2_residual<TI>(h_, a_[stage], (const TI*)x.ptr, x.stride, (const TI*)b.ptr, b.stride,
+                                    (TI*)r.ptr, r.stride, B, st_));
+        else
+          return hipErrorInvalidValue;
+      } else if (l == 0) {
+        RES(3, KIND_FINE);
+      } else {
+        RES(3, KIND_TENSOR);
+      }
 #undef RES
       MG_TRY(hipGetLastError());
       MG_TRY(mark("k_residual", l));
