@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the 3D, batch and paper-case timings")
     ap.add_argument("--paper-case2", action="store_true",
                     help="also time the paper's test case #2 (Q2, 511^2 nodes, 512 steps: 535M unknowns)")
+    ap.add_argument("--paper-case-only", action="store_true",
+                    help="only the paper's test case #1 (Q2) with its solver settings; for kernel traces")
     ap.add_argument("--roofline-reps", type=int, default=20)
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the roofline launches (V-cycle kernels, apply_A, a 1 GiB copy); for counter runs")
@@ -98,6 +100,11 @@ def main():
     import heat_inputs
     from paper_2609_16863_amd import HeatProblem
 
+    if args.paper_case_only:
+        name = "paper_case1_q2_n255_s3_nt256"
+        res = paper_case(heat_inputs.PAPER_CASES[name], args.mgrit_cf, args.mgrit_coarse_k, args.schur_k)
+        print(json.dumps({name: res}))
+        return
     w = heat_inputs.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
