@@ -33,10 +33,11 @@ def test_profile_vcycle_labels_and_times():
         situ = [u for _, u, _ in launches]
         alone = [u for _, _, u in launches]
         assert all(u > 0 for u in situ) and all(u > 0 for u in alone)
-        # the graph-replayed cycle costs at most the in-situ launches
-        # (which add an event between every two of them), and at least the
-        # launches alone (which run warm)
-        assert 0.8 * sum(alone) <= total <= 1.2 * sum(situ), (sum(alone), total, sum(situ))
+        # the graph-replayed cycle costs at most the in-situ launches (which
+        # add an event between every two of them) and at least its longest
+        # launch; the sum of the launches alone is no bound (replayed alone,
+        # each pays the dispatch latency that back-to-back launches hide)
+        assert max(alone) <= 1.2 * total and total <= 1.2 * sum(situ), (alone, total, sum(situ))
 
 
 def test_autotune_choice_cache_and_parity(tmp_path):
