@@ -579,7 +579,7 @@ def extras(args, autotune):
     w3 = heat_inputs.WORKLOADS["heat3d_n128_s3_nt32"]
     res3 = {}
     for prec in ["fp64", "fp32", "bf16", "fp16"]:
-        hp = HeatProblem(w3.dim, w3.n, w3.s, w3.nt, w3.T, restart=w3.restart, tol=1e-8, inner_k=3,
+        hp = HeatProblem(w3.dim, w3.n, w3.s, w3.nt, w3.T, restart=w3.restart, tol=1e-8, inner_k=args.inner_k,
                          precision=prec, schur=args.schur, mgrit_cf=args.mgrit_cf,
                          mgrit_coarse_k=args.mgrit_coarse_k, schur_k=args.schur_k)
         f, u0 = heat_inputs.workload_inputs(w3, hp.stage_times())
@@ -601,7 +601,7 @@ def extras(args, autotune):
             apply3 = measure_apply_A(hp, rhs, args.roofline_reps)
         del hp, rhs
         torch.cuda.empty_cache()
-    out[w3.name] = {"unknowns": w3.n ** 3 * (w3.nt * (w3.s + 1) + 1), "restart": w3.restart, "inner_k": 3,
+    out[w3.name] = {"unknowns": w3.n ** 3 * (w3.nt * (w3.s + 1) + 1), "restart": w3.restart, "inner_k": args.inner_k,
                     "schur": args.schur, "mgrit_cf": args.mgrit_cf, "mgrit_coarse_k": args.mgrit_coarse_k,
                     "schur_k": args.schur_k,
                     "solves": res3, "roofline_apply_A": apply3}
@@ -611,7 +611,7 @@ def extras(args, autotune):
         times = stage_times(sp["s"], sp["nt"], 1.0)
         data.append(heat_inputs.spec_inputs(sp, times))
     hb = HeatBatch([dict(dim=2, n=sp["n"], s=sp["s"], nt=sp["nt"], kappa=kap) for sp, (kap, _, _) in zip(specs, data)],
-                   streams=4, precision="fp32", tol=1e-8, inner_k=3, schur=args.schur, mgrit_cf=args.mgrit_cf,
+                   streams=4, precision="fp32", tol=1e-8, inner_k=args.inner_k, schur=args.schur, mgrit_cf=args.mgrit_cf,
                    mgrit_coarse_k=args.mgrit_coarse_k, schur_k=args.schur_k)
     rhs = hb.assemble_rhs(torch.from_numpy(np.concatenate([d[1].ravel() for d in data])).cuda(),
                           torch.from_numpy(np.concatenate([d[2].ravel() for d in data])).cuda())
@@ -629,7 +629,7 @@ def extras(args, autotune):
     out["batch64_uneven_kappa"] = {"problems": len(specs), "unknowns": hb.U, "solve_s": float(np.mean(times)),
                                    "outer_iterations_min_max": [min(its), max(its)],
                                    "converged": all(s["converged"] for s in st), "preconditioner": "fp32",
-                                   "schur": args.schur, "streams": 4}
+                                   "schur": args.schur, "streams": 4, "inner_k": args.inner_k}
     hb.close()
     torch.cuda.empty_cache()
     cases = ["paper_case1_q2_n255_s3_nt256"] + (["paper_case2_q2_n511_s3_nt512"] if args.paper_case2 else [])
