@@ -78,9 +78,9 @@ class HeatProblem:
     Parameters follow the paper's problem statement (Sec. 2): ``dim``-D unit
     domain with ``n`` interior nodes per axis, ``s``-stage Radau IIA, ``nt``
     steps to final time ``T``; ``kappa`` optional nodal diffusivity (N values,
-    2D only).  ``disc`` = "q1" selects bilinear finite elements with their
-    mass matrix on the square [0, length]^2 (2D, kappa = 1) in place of
-    finite differences.  Solver options: FGMRES ``restart``/``maxit``/``tol``, inner
+    2D only).  ``disc`` = "q1" or "q2" selects bilinear or biquadratic
+    finite elements with their mass matrix on the square [0, length]^2 (2D,
+    kappa = 1; "q2" needs odd ``n``) in place of finite differences.  Solver options: FGMRES ``restart``/``maxit``/``tol``, inner
     GMRES iterations ``inner_k``, V-cycles ``cycles`` with ``nu1``/``nu2``
     Jacobi sweeps, and the preconditioner ``precision``
     ("fp64" | "fp32" | "bf16" | "fp16" | "fp16_all", the last approach A4);
@@ -91,7 +91,9 @@ class HeatProblem:
     ``inner_k`` iterations).  ``schur`` = "sweep" applies S-tilde^{-1} by
     forward substitution in time, "mgrit" by two-level MGRIT with
     coarsening factor ``mgrit_cf``, ``mgrit_iters`` iterations and F- (or,
-    with ``mgrit_fcf``, FCF-) relaxation.  ``side`` places P-tilde on the
+    with ``mgrit_fcf``, FCF-) relaxation; ``schur_k`` and ``mgrit_coarse_k``
+    are the inner GMRES iterations of S-tilde's steps and of MGRIT's coarse
+    propagator (0: ``inner_k``).  ``side`` places P-tilde on the
     "right", "left" or both ("split") sides of Algorithm 1;
     ``outer_precision`` = "fp32" runs the outer solve in simulated single
     precision (approach A3).  ``mg_low_from`` (first multigrid level in 16
