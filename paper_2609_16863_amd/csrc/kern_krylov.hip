@@ -93,6 +93,19 @@ __device__ void gmres_givens(double* q, const double* qs, int j, const double* h
   }
 }
 
+// One inner GMRES iteration from zero is a minimal-residual step: with
+// z = P_R^{-1} r and w = Theta_hat z, x = alpha z, alpha = <w, r> / <w, w>
+// (the least-squares solution of GMRES(1), without forming the normalized
+// basis vector).  alpha goes to slots[Y].
+__device__ void mr_step(double* q, double wr, double ww, unsigned* counters) {
+  const bool ok = ww > 0.0 && isfinite(ww);
+  if (counters) {
+    atomicAdd(&counters[1], 1u);
+    if (ok) atomicAdd(&counters[0], 1u);
+  }
+  q[S::Y] = ok ? wr / ww : 0.0;
+}
+
 // One pass of Gram-Schmidt on every instance; block partials of the dot
 // products go to `partial` and k_gs_finish completes them.  Optionally:
 //   axpy:  w <- w - sum_{d<nd} slots[ca+d] V_d   (stored back to w)
@@ -100,6 +113,7 @@ __device__ void gmres_givens(double* q, const double* qs, int j, const double* h
 //   post:  GS_POST_INIT   -> GMRES start  (beta, g, 1/beta) from slots[os]
 //          GS_POST_GIVENS -> Givens update of column j (slots hold h1 at H1,
 //                            h2 at H2, <w,w> at WW)
+//          GS_POST_MR     -> minimal-residual step: slots[Y] = <w,V_0> / <w,w>
 // The block partials are summed in a fixed order, so results are bitwise
 // reproducible run to run.
 template <class TW, class TV, int ND>
@@ -211,6 +225,7 @@ __global__ __launch_bounds__(TPB) void k_gs_finish(GSArgs a) {
   if (tid == 0) {
     if (a.post == GS_POST_INIT) gmres_start(q, fin[DOTS_PER_PASS], a.counters);
     else if (a.post == GS_POST_GIVENS) gmres_givens(q, qs, a.j, fin, fin[DOTS_PER_PASS], a.rtol, a.counters);
+    else if (a.post == GS_POST_MR) mr_step(q, fin[0], fin[DOTS_PER_PASS], a.counters);
   }
 }
 

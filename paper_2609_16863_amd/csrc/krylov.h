@@ -22,7 +22,7 @@ struct InnerSlots {
   static constexpr int R = Y + 16;               // R[(KMAX+1) * KMAX], column j at R + j*(KMAX+1)
 };
 
-enum { GS_POST_NONE = 0, GS_POST_INIT = 1, GS_POST_GIVENS = 2 };
+enum { GS_POST_NONE = 0, GS_POST_INIT = 1, GS_POST_GIVENS = 2, GS_POST_MR = 3 };
 
 // One fused Gram-Schmidt pass over B instances of length L (see k_gs).
 struct GSArgs {

@@ -22,6 +22,7 @@
 #include <cmath>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "aao_internal.h"
@@ -124,6 +125,9 @@ class Precond {
     TRY(basis_update<TR, TI, TI>(rhs, srhs, inV_, UV, sN, 0, inV_, sN, slots_, S::STRIDE, 0, S::INV, 0.0, sN, B,
                                  st_));
     const int kk = kin > 0 ? kin : sp.k;
+    if constexpr (std::is_same<TR, TI>::value) {
+      if (kk == 1) return mr_inner(sp, rhs, srhs, out, sout, B);
+    }
     for (int j = 0; j < kk; ++j) {
       TI* Vj = inV_ + (int64_t)j * UV;
       TI* Zj = inZ_ + (int64_t)j * UV;
@@ -167,6 +171,40 @@ class Precond {
     }
     TRY(combine<TI, TI>(out, sout, inZ_, UV, sN, kk, slots_, S::STRIDE, 0, true, false, sN, B, st_));
     return hipSuccess;
+  }
+
+  // GMRES(1) from zero as the minimal-residual step it is: z = Rana(rhs),
+  // w = Theta_hat z, out = (<w, rhs> / <w, w>) z -- the result of the
+  // general loop above for one iteration, with one reduction instead of the
+  // normalization, two Gram-Schmidt passes and the Givens update.
+  hipError_t mr_inner(Stepper& sp, const TI* rhs, int64_t srhs, TI* out, int64_t sout, int B) {
+    const int64_t N = h_->N, sN = (int64_t)h_->s * N, UV = h_->UV;
+    TI* Z0 = inZ_;
+    for (int i = 0; i < h_->s; ++i) {
+      typename Multigrid<TI, TM>::Coupling cpl;
+      cpl.z = Z0;
+      cpl.sz = sN;
+      cpl.zstride = N;
+      cpl.nz = i;
+      cpl.Lc = sp.Lc;
+      cpl.out = rana_;
+      cpl.so = N;
+      TRY(sp.mg.solve(i, BVec<TI>{Z0 + (int64_t)i * N, sN}, BVec<const TI>{rhs + (int64_t)i * N, srhs}, B, cycles_,
+                      i > 0 ? &cpl : nullptr));
+    }
+    TRY(theta_apply<TI>(h_, sp.tab, Z0, sN, inW_, sN, B, st_));
+    GSArgs a = gs_args(sN, B);
+    a.sw = sN;
+    a.vstride = UV;
+    a.sv = srhs;
+    a.nd = 1;
+    a.dots = 1;
+    a.od = S::H1;
+    a.self = 1;
+    a.os = S::WW;
+    a.post = GS_POST_MR;
+    TRY(gs_pass<TI, TI>(inW_, rhs, a, B, st_));
+    return combine<TI, TI>(out, sout, Z0, UV, sN, 1, slots_, S::STRIDE, S::Y, false, false, sN, B, st_);
   }
 
   // out_b = t_b + Phi(zin_b) for B instances, Phi the S-tilde step of `sp`:
