@@ -48,7 +48,7 @@ __device__ void gmres_start(double* q, double ww, unsigned* counters) {
 // be left, and the next basis vector would be scaled by a wrong 1/h_{j+1,j}),
 // or its residual estimate |g_{j+1}| has reached rtol * beta.
 __device__ void gmres_givens(double* q, const double* qs, int j, const double* h2, double ww, double rtol,
-                             unsigned* counters) {
+                             unsigned* counters, bool one_pass) {
   if (qs[S::ACTIVE] == 0.0) {
     q[S::INV] = 0.0;
     return;
@@ -58,7 +58,7 @@ __device__ void gmres_givens(double* q, const double* qs, int j, const double* h
   double h2sq = 0.0;
   for (int i = 0; i <= j; ++i) {
     q[S::H2 + i] = h2[i];
-    col[i] = qs[S::H1 + i] + h2[i];
+    col[i] = (one_pass ? 0.0 : qs[S::H1 + i]) + h2[i];
     h2sq += h2[i] * h2[i];
   }
   const double nrm2 = ww - h2sq;
@@ -224,7 +224,8 @@ __global__ __launch_bounds__(TPB) void k_gs_finish(GSArgs a) {
   __syncthreads();
   if (tid == 0) {
     if (a.post == GS_POST_INIT) gmres_start(q, fin[DOTS_PER_PASS], a.counters);
-    else if (a.post == GS_POST_GIVENS) gmres_givens(q, qs, a.j, fin, fin[DOTS_PER_PASS], a.rtol, a.counters);
+    else if (a.post == GS_POST_GIVENS)
+      gmres_givens(q, qs, a.j, fin, fin[DOTS_PER_PASS], a.rtol, a.counters, a.one_pass != 0);
     else if (a.post == GS_POST_MR) mr_step(q, fin[0], fin[DOTS_PER_PASS], a.counters);
   }
 }

@@ -40,6 +40,8 @@ struct GSArgs {
   int nblk;
   int post, j;
   double rtol;        // GS_POST_GIVENS: stop an instance once |g_{j+1}| <= rtol * beta (0: never)
+  int one_pass;       // GS_POST_GIVENS after a single classical pass: the column is this pass' dots
+                      // alone (no first-pass h1 to add)
 };
 
 // Number of workgroups per segment for the segmented reductions.

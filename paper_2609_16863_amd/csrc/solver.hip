@@ -155,6 +155,21 @@ class Precond {
       a1.nd = nd;
       a1.dots = 1;
       a1.od = S::H1;
+      if (h_->opts.inner_orth == AAO_ORTH_CGS1) {
+        // one classical pass: h = V^T w and <w,w> together, h_{j+1,j} from
+        // their difference, then v_{j+1} = (w - V h) / h_{j+1,j}
+        a1.od = S::H2;
+        a1.self = 1;
+        a1.os = S::WW;
+        a1.post = GS_POST_GIVENS;
+        a1.j = j;
+        a1.one_pass = 1;
+        TRY(gs_pass<TI, TI>(inW_, inV_, a1, B, st_));
+        if (j + 1 < kk)
+          TRY(basis_update<TI, TI, TI>(inW_, sN, inV_, UV, sN, nd, inV_ + (int64_t)(j + 1) * UV, sN, slots_,
+                                       S::STRIDE, S::H2, S::INV, 0.0, sN, B, st_));
+        continue;
+      }
       TRY(gs_pass<TI, TI>(inW_, inV_, a1, B, st_));
       GSArgs a2 = a1;
       a2.axpy = 1;

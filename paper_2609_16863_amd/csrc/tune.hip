@@ -45,7 +45,7 @@ std::string tune_key(const aao_problem* h) {
     << " schur=" << h->opts.schur << " cf=" << h->opts.mgrit_cf << " it=" << h->opts.mgrit_iters
     << " fcf=" << h->opts.mgrit_fcf << " coarse=" << h->opts.coarse_max << " tail=" << h->opts.mg_tail_max
     << " low=" << h->opts.mg_low_from << "," << h->opts.mg_coarse_fp32 << " sk=" << h->opts.schur_k
-    << " ck=" << h->opts.mgrit_coarse_k;
+    << " ck=" << h->opts.mgrit_coarse_k << " orth=" << h->opts.inner_orth;
   return k.str();
 }
 

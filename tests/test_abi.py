@@ -83,7 +83,8 @@ def test_sizes_and_workspace():
                                  dict(restart=0), dict(inner_k=13), dict(precision=7), dict(nu1=0),
                                  dict(side=3), dict(schur=2), dict(outer_precision=2), dict(precision=5),
                                  dict(mg_low_from=-1), dict(mg_coarse_fp32=2), dict(mgrit_coarse_k=-1),
-                                 dict(mgrit_coarse_k=13), dict(schur_k=-1), dict(schur_k=13)])
+                                 dict(mgrit_coarse_k=13), dict(schur_k=-1), dict(schur_k=13),
+                                 dict(inner_orth=2)])
 def test_invalid_arguments_are_rejected(bad):
     abi, lib = _lib()
     desc_keys = {"dim", "n", "s", "nt", "T"}

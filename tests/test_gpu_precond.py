@@ -18,10 +18,11 @@ from oracle import allatonce, precond
 pytestmark = pytest.mark.gpu
 
 
-def _pair(dim, n, s, nt, precision="fp64", k=3, cycles=1, nu=2, seed=0, transpose=False):
+def _pair(dim, n, s, nt, precision="fp64", k=3, cycles=1, nu=2, seed=0, transpose=False, orth="cgs2"):
     from paper_2609_16863_amd import HeatProblem
     p = allatonce.Problem(n, dim, s, nt, 1.0)
-    hp = HeatProblem(dim, n, s, nt, 1.0, inner_k=k, cycles=cycles, nu1=nu, nu2=nu, precision=precision)
+    hp = HeatProblem(dim, n, s, nt, 1.0, inner_k=k, cycles=cycles, nu1=nu, nu2=nu, precision=precision,
+                     inner_orth=orth)
     ops = precond.StageOps(p, inner_k=k, cycles=cycles, nu1=nu, nu2=nu)
     return p, hp, ops, np.random.default_rng(seed)
 
@@ -39,6 +40,41 @@ def test_apply_P_fp64_matches_oracle(dim, n, s, nt):
     ref = precond.apply_preconditioner(ops, r)
     assert rel_err(z, ref) <= 1e-10
     assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-4)])
+@pytest.mark.parametrize("dim,n,s,nt", [(2, 72, 2, 3), (2, 130, 3, 2), (3, 12, 2, 2)])
+def test_apply_P_one_pass_gram_schmidt_matches_oracle(dim, n, s, nt, precision, tol):
+    """The inner GMRES with one classical Gram-Schmidt pass (h_{j+1,j} from
+    <w,w> - |h|^2) is the oracle's modified Gram-Schmidt GMRES up to
+    rounding."""
+    require_gpu()
+    p, hp, ops, rng = _pair(dim, n, s, nt, precision=precision, k=4, seed=n + 1, orth="cgs1")
+    ops = precond.StageOps(p, inner_k=4, cycles=1, nu1=2, nu2=2)
+    r = rng.standard_normal(p.U)
+    announce("apply_P cgs1", precision, dim, n, s, nt)
+    z = to_host(hp.apply_P(to_dev(r)))
+    assert rel_err(z, precond.apply_preconditioner(ops, r)) <= tol
+
+
+@pytest.mark.parametrize("dim,n,nt", [(2, 40, 12), (3, 14, 8)])
+def test_solve_with_the_benchmark_settings_reaches_stepping(dim, n, nt):
+    """One-pass Gram-Schmidt, one inner iteration in S-tilde and on MGRIT's
+    coarse level, FP32 P-tilde: the solve reaches x* (stepping)."""
+    require_gpu()
+    from oracle import stepping
+    from paper_2609_16863_amd import HeatProblem
+    s = 3
+    p = allatonce.Problem(n, dim, s, nt, 1.0)
+    hp = HeatProblem(dim, n, s, nt, 1.0, tol=1e-11, maxit=200, precision="fp32", inner_k=4, schur="mgrit",
+                     mgrit_cf=4, mgrit_coarse_k=1, schur_k=1, inner_orth="cgs1")
+    rng = np.random.default_rng(dim * 100 + n)
+    f = rng.standard_normal((nt, s, p.N))
+    u0 = rng.standard_normal(p.N)
+    announce("solve benchmark settings", dim, n, nt)
+    x, st = hp.solve(hp.assemble_rhs(to_dev(f.ravel()), to_dev(u0)))
+    assert st["converged"], st
+    assert rel_err(to_host(x), stepping.solve(p, f, u0)) <= 1e-8
 
 
 @pytest.mark.parametrize("n,s,nt", [(40, 2, 3), (72, 3, 2)])
