@@ -4,12 +4,12 @@ One step = one full FGMRES solve to a true FP64 relative residual of 1e-8 of
 the all-at-once system (paper eq. (2.4)) with the block preconditioner
 (eqs. (3.2)-(3.3)) applied in FP32 (the mixed-precision arm, approach A2),
 its S-tilde solve done by one two-level MGRIT iteration (coarsening factor 4;
-the parallel route of Sec. 5.2), whose steps solve Theta-tilde with one inner
-GMRES iteration where the block-diagonal Theta-tilde solve takes four, with
-one classical Gram-Schmidt pass per inner iteration.  The same solve with the FP64
-preconditioner (approach A1) is timed beside it with equal inner settings
-(4 inner GMRES iterations, one V-cycle with 2 + 2 Jacobi sweeps per shifted
-block), and both again with S-tilde by forward substitution.  Workload: 2D
+the parallel route of Sec. 5.2).  The block-diagonal Theta-tilde solve runs
+4 inner GMRES iterations, S-tilde's steps and MGRIT's coarse level one, each
+with one classical Gram-Schmidt pass and one V-cycle of 2 + 2 Jacobi sweeps
+per shifted block.  The same solve with the FP64 preconditioner (approach
+A1) is timed beside it with equal inner settings, and both again with
+S-tilde by forward substitution.  Workload: 2D
 heat on a 512 x 512 interior grid, Radau IIA s = 3, 64 time steps to T = 1,
 FGMRES(30); seeded Gaussian-bump source and smooth random initial condition
 (synthetic, generated on the host).  The multigrid launch shapes come from
