@@ -7,7 +7,8 @@ its S-tilde solve done by one two-level MGRIT iteration (coarsening factor 4;
 the parallel route of Sec. 5.2).  The block-diagonal Theta-tilde solve runs
 4 inner GMRES iterations, S-tilde's steps and MGRIT's coarse level one, each
 with one classical Gram-Schmidt pass and one V-cycle of 2 + 2 Jacobi sweeps
-per shifted block.  The same solve with the FP64 preconditioner (approach
+per shifted block; the outer FGMRES takes its second Gram-Schmidt pass from
+the basis' Gram matrix.  The same solve with the FP64 preconditioner (approach
 A1) is timed beside it with equal inner settings, and both again with
 S-tilde by forward substitution.  Workload: 2D
 heat on a 512 x 512 interior grid, Radau IIA s = 3, 64 time steps to T = 1,
@@ -63,6 +64,8 @@ def parse():
     ap.add_argument("--mgrit-iters", type=int, default=1)
     ap.add_argument("--inner-orth", default="cgs1", choices=["cgs2", "cgs1"],
                     help="Gram-Schmidt passes of the inner GMRES")
+    ap.add_argument("--outer-orth", default="gram", choices=["cgs2", "gram"],
+                    help="Gram-Schmidt of the outer FGMRES")
     ap.add_argument("--schur-k", type=int, default=1,
                     help="inner GMRES iterations inside S-tilde's steps (0 = inner k)")
     ap.add_argument("--mgrit-coarse-k", type=int, default=1,
@@ -106,7 +109,7 @@ def main():
     if args.paper_case_only:
         name = "paper_case1_q2_n255_s3_nt256"
         res = paper_case(heat_inputs.PAPER_CASES[name], args.mgrit_cf, args.mgrit_coarse_k, args.schur_k,
-                         args.inner_orth)
+                         args.inner_orth, args.outer_orth)
         print(json.dumps({name: res}))
         return
     w = heat_inputs.WORKLOADS[args.workload]
@@ -114,7 +117,8 @@ def main():
     torch.cuda.set_device(dev)
     common = dict(restart=w.restart, tol=1e-8, inner_k=args.inner_k, cycles=args.cycles, nu1=args.nu,
                   nu2=args.nu, schur=args.schur, mgrit_cf=args.mgrit_cf, mgrit_iters=args.mgrit_iters,
-                  mgrit_coarse_k=args.mgrit_coarse_k, schur_k=args.schur_k, inner_orth=args.inner_orth)
+                  mgrit_coarse_k=args.mgrit_coarse_k, schur_k=args.schur_k, inner_orth=args.inner_orth,
+                  outer_orth=args.outer_orth)
     t_setup = time.perf_counter()
     hp_mix = HeatProblem(w.dim, w.n, w.s, w.nt, w.T, precision=args.mixed, **common)
     f, u0 = heat_inputs.workload_inputs(w, hp_mix.stage_times())
@@ -225,7 +229,7 @@ def main():
                    "inner_k": args.inner_k, "cycles": args.cycles, "nu1": args.nu, "nu2": args.nu,
                    "schur": args.schur, "mgrit_cf": args.mgrit_cf, "mgrit_iters": args.mgrit_iters,
                    "mgrit_coarse_k": args.mgrit_coarse_k or args.inner_k, "schur_k": args.schur_k or args.inner_k,
-                   "inner_orth": args.inner_orth,
+                   "inner_orth": args.inner_orth, "outer_orth": args.outer_orth,
                    "preconditioner": args.mixed, "launch_shapes": tune and {k: tune[k] for k in
                                                                             ("tall_min_b", "tail_extend", "source")},
                    "parallelism": "single GPU"},
@@ -586,7 +590,8 @@ def extras(args, autotune):
     for prec in ["fp64", "fp32", "bf16", "fp16"]:
         hp = HeatProblem(w3.dim, w3.n, w3.s, w3.nt, w3.T, restart=w3.restart, tol=1e-8, inner_k=args.inner_k,
                          precision=prec, schur=args.schur, mgrit_cf=args.mgrit_cf,
-                         mgrit_coarse_k=args.mgrit_coarse_k, schur_k=args.schur_k, inner_orth=args.inner_orth)
+                         mgrit_coarse_k=args.mgrit_coarse_k, schur_k=args.schur_k, inner_orth=args.inner_orth,
+                         outer_orth=args.outer_orth)
         f, u0 = heat_inputs.workload_inputs(w3, hp.stage_times())
         rhs = hp.assemble_rhs(torch.from_numpy(np.ascontiguousarray(f.ravel())).cuda(), torch.from_numpy(u0).cuda())
         del f
@@ -608,7 +613,7 @@ def extras(args, autotune):
         torch.cuda.empty_cache()
     out[w3.name] = {"unknowns": w3.n ** 3 * (w3.nt * (w3.s + 1) + 1), "restart": w3.restart, "inner_k": args.inner_k,
                     "schur": args.schur, "mgrit_cf": args.mgrit_cf, "mgrit_coarse_k": args.mgrit_coarse_k,
-                    "schur_k": args.schur_k, "inner_orth": args.inner_orth,
+                    "schur_k": args.schur_k, "inner_orth": args.inner_orth, "outer_orth": args.outer_orth,
                     "solves": res3, "roofline_apply_A": apply3}
     specs = heat_inputs.batch_problem_specs()
     data = []
@@ -617,7 +622,8 @@ def extras(args, autotune):
         data.append(heat_inputs.spec_inputs(sp, times))
     hb = HeatBatch([dict(dim=2, n=sp["n"], s=sp["s"], nt=sp["nt"], kappa=kap) for sp, (kap, _, _) in zip(specs, data)],
                    streams=4, precision="fp32", tol=1e-8, inner_k=args.inner_k, schur=args.schur, mgrit_cf=args.mgrit_cf,
-                   mgrit_coarse_k=args.mgrit_coarse_k, schur_k=args.schur_k, inner_orth=args.inner_orth)
+                   mgrit_coarse_k=args.mgrit_coarse_k, schur_k=args.schur_k, inner_orth=args.inner_orth,
+                   outer_orth=args.outer_orth)
     rhs = hb.assemble_rhs(torch.from_numpy(np.concatenate([d[1].ravel() for d in data])).cuda(),
                           torch.from_numpy(np.concatenate([d[2].ravel() for d in data])).cuda())
     times = []
@@ -635,13 +641,13 @@ def extras(args, autotune):
                                    "outer_iterations_min_max": [min(its), max(its)],
                                    "converged": all(s["converged"] for s in st), "preconditioner": "fp32",
                                    "schur": args.schur, "streams": 4, "inner_k": args.inner_k,
-                                   "inner_orth": args.inner_orth}
+                                   "inner_orth": args.inner_orth, "outer_orth": args.outer_orth}
     hb.close()
     torch.cuda.empty_cache()
     cases = ["paper_case1_q2_n255_s3_nt256"] + (["paper_case2_q2_n511_s3_nt512"] if args.paper_case2 else [])
     for name in cases:
         out[name] = paper_case(heat_inputs.PAPER_CASES[name], args.mgrit_cf, args.mgrit_coarse_k, args.schur_k,
-                               args.inner_orth)
+                               args.inner_orth, args.outer_orth)
     return out
 
 
@@ -658,7 +664,7 @@ PAPER_TABLE = {
 }
 
 
-def paper_case(case, mgrit_cf, mgrit_coarse_k, schur_k, inner_orth, reps=2):
+def paper_case(case, mgrit_cf, mgrit_coarse_k, schur_k, inner_orth, outer_orth, reps=2):
     """One of the paper's parallel test cases (Q2 elements, Sec. 5.2) with the
     paper's solver settings: left-preconditioned FGMRES(15), tol 1e-8, the
     inner GMRES on Theta-tilde stopped after 3 iterations or at 1e-3 (P-tilde
@@ -680,7 +686,8 @@ def paper_case(case, mgrit_cf, mgrit_coarse_k, schur_k, inner_orth, reps=2):
     settings = {"left_fp32": dict(side="left", precision="fp32", inner_k=3, inner_tol=1e-3, **paper_mgrit),
                 "left_fp64": dict(side="left", precision="fp64", inner_k=5, inner_tol=1e-6, **paper_mgrit),
                 "right_fp32": dict(side="right", precision="fp32", inner_k=3, inner_tol=1e-3, mgrit_cf=mgrit_cf,
-                                   mgrit_coarse_k=mgrit_coarse_k, schur_k=schur_k, inner_orth=inner_orth)}
+                                   mgrit_coarse_k=mgrit_coarse_k, schur_k=schur_k, inner_orth=inner_orth,
+                                   outer_orth=outer_orth)}
     res = {}
     for label, kw in settings.items():
         hp = HeatProblem(2, case.n, case.s, case.nt, case.tf, disc="q2", length=case.length, restart=case.restart,
@@ -715,7 +722,7 @@ def paper_case(case, mgrit_cf, mgrit_coarse_k, schur_k, inner_orth, reps=2):
                       "theta_ms": st["theta_ms"], "schur_ms": st["schur_ms"], "mgrit_cf": kw["mgrit_cf"],
                       "mgrit_coarse_k": kw["mgrit_coarse_k"] or kw["inner_k"],
                       "schur_k": kw.get("schur_k", 0) or kw["inner_k"],
-                      "inner_orth": kw.get("inner_orth", "cgs2")}
+                      "inner_orth": kw.get("inner_orth", "cgs2"), "outer_orth": kw.get("outer_orth", "cgs2")}
         del hp, rhs, v
         torch.cuda.empty_cache()
     res["left_fp32_vs_fp64_speedup"] = res["left_fp64"]["solve_s"] / res["left_fp32"]["solve_s"]

@@ -99,10 +99,14 @@ typedef enum aao_outer {
  * Gram-Schmidt; both forms here are classical, batched over all instances). */
 typedef enum aao_orth {
   AAO_ORTH_CGS2 = 0,       /* two classical passes (reorthogonalized)          */
-  AAO_ORTH_CGS1 = 1        /* one classical pass: the dots with the basis and
+  AAO_ORTH_CGS1 = 1,       /* one classical pass: the dots with the basis and
                               <w,w> together, h_{j+1,j} = sqrt(<w,w> - |h|^2);
                               a pass less per iteration, orthogonality as
-                              classical Gram-Schmidt keeps it                  */
+                              classical Gram-Schmidt keeps it (inner only)     */
+  AAO_ORTH_GRAM = 2        /* two classical passes with the second taken from
+                              the Gram matrix of the basis: h = (2I - G) V^T w,
+                              ||w - V h||^2 from <w,w>, h and G; one sweep
+                              over the basis per iteration (outer only)        */
 } aao_orth;
 
 typedef enum aao_side {
@@ -227,7 +231,10 @@ typedef struct aao_opts {
                               inside S-tilde's steps (the substitution's, and
                               MGRIT's fine propagator); Theta-tilde's own
                               block solve keeps inner_k.  0 = inner_k          */
-  int inner_orth;          /* aao_orth: orthogonalization of the inner GMRES  */
+  int inner_orth;          /* aao_orth: orthogonalization of the inner GMRES
+                              (CGS2 or CGS1)                                   */
+  int outer_orth;          /* aao_orth: orthogonalization of the outer FGMRES
+                              (CGS2 or GRAM)                                   */
 } aao_opts;
 
 /* Solve statistics (host struct filled by aao_solve*). */
@@ -259,7 +266,8 @@ typedef struct aao_problem aao_problem;   /* opaque handle */
  * nu1 = nu2 = 2, omega 0, precision FP64, use_graph 1, mg_tail_max 0,
  * coarse_max 0, inner_tol 0, schur AAO_SCHUR_SWEEP, mgrit_cf 8,
  * mgrit_iters 1, mgrit_fcf 0, side RIGHT, outer_precision FP64,
- * mg_low_from 0, relax_matvec 0, mg_coarse_fp32 0, mgrit_coarse_k 0, schur_k 0, inner_orth CGS2.  With use_graph the
+ * mg_low_from 0, relax_matvec 0, mg_coarse_fp32 0, mgrit_coarse_k 0, schur_k 0, inner_orth and
+ * outer_orth CGS2.  With use_graph the
  * first application of P-tilde for a given (inner_k, cycles, transpose) is
  * captured into a HIP graph on a private stream and later applications
  * replay it on the handle's stream (inputs and outputs pass through fixed

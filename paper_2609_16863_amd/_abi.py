@@ -16,7 +16,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "fp16_all": 4}
 SCHUR = {"sweep": 0, "mgrit": 1}
 SIDES = {"right": 0, "left": 1, "split": 2}
 OUTER = {"fp64": 0, "fp32": 1}
-ORTH = {"cgs2": 0, "cgs1": 1}
+ORTH = {"cgs2": 0, "cgs1": 1, "gram": 2}
 
 
 class Desc(ctypes.Structure):
@@ -35,7 +35,7 @@ class Opts(ctypes.Structure):
                 ("mgrit_fcf", c_int), ("side", c_int),
                 ("outer_precision", c_int), ("mg_low_from", c_int), ("mg_coarse_fp32", c_int),
                 ("relax_matvec", c_int), ("mgrit_coarse_k", c_int), ("schur_k", c_int),
-                ("inner_orth", c_int)]
+                ("inner_orth", c_int), ("outer_orth", c_int)]
 
 
 class Stats(ctypes.Structure):

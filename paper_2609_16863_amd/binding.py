@@ -28,7 +28,7 @@ SOLVER_DEFAULTS = dict(restart=30, maxit=100, tol=1e-8, inner_k=3, cycles=1, nu1
                        precision="fp64", use_graph=True, mg_tail_max=0, coarse_max=0, inner_tol=0.0,
                        schur="sweep", mgrit_cf=8, mgrit_iters=1, mgrit_fcf=False, side="right",
                        outer_precision="fp64", mg_low_from=0, mg_coarse_fp32=False, relax_matvec=False,
-                       mgrit_coarse_k=0, schur_k=0, inner_orth="cgs2")
+                       mgrit_coarse_k=0, schur_k=0, inner_orth="cgs2", outer_orth="cgs2")
 
 
 def _solver_options(kw):
@@ -61,6 +61,7 @@ def _make_opts(lib, o):
     opts.mgrit_coarse_k = int(o["mgrit_coarse_k"])
     opts.schur_k = int(o["schur_k"])
     opts.inner_orth = _abi.ORTH[o["inner_orth"]]
+    opts.outer_orth = _abi.ORTH[o["outer_orth"]]
     return opts
 
 
@@ -95,7 +96,9 @@ class HeatProblem:
     with ``mgrit_fcf``, FCF-) relaxation; ``schur_k`` and ``mgrit_coarse_k``
     are the inner GMRES iterations of S-tilde's steps and of MGRIT's coarse
     propagator (0: ``inner_k``); ``inner_orth`` = "cgs2" (two classical
-    Gram-Schmidt passes) or "cgs1" (one) in the inner GMRES.  ``side`` places P-tilde on the
+    Gram-Schmidt passes) or "cgs1" (one) in the inner GMRES; ``outer_orth``
+    = "cgs2" or "gram" (the second pass from the basis' Gram matrix: one
+    sweep over the basis per iteration) in the outer FGMRES.  ``side`` places P-tilde on the
     "right", "left" or both ("split") sides of Algorithm 1;
     ``outer_precision`` = "fp32" runs the outer solve in simulated single
     precision (approach A3).  ``mg_low_from`` (first multigrid level in 16

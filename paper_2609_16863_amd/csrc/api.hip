@@ -170,7 +170,8 @@ bool valid_opts(const aao_opts* o, std::string& why) {
   if (o->relax_matvec != 0 && o->relax_matvec != 1) { why = "relax_matvec must be 0 or 1"; return false; }
   if (o->mgrit_coarse_k < 0 || o->mgrit_coarse_k > aao::KMAX) { why = "mgrit_coarse_k must be in [0, 12]"; return false; }
   if (o->schur_k < 0 || o->schur_k > aao::KMAX) { why = "schur_k must be in [0, 12]"; return false; }
-  if (o->inner_orth != AAO_ORTH_CGS2 && o->inner_orth != AAO_ORTH_CGS1) { why = "unknown inner_orth"; return false; }
+  if (o->inner_orth != AAO_ORTH_CGS2 && o->inner_orth != AAO_ORTH_CGS1) { why = "inner_orth must be CGS2 or CGS1"; return false; }
+  if (o->outer_orth != AAO_ORTH_CGS2 && o->outer_orth != AAO_ORTH_GRAM) { why = "outer_orth must be CGS2 or GRAM"; return false; }
   return true;
 }
 
@@ -247,6 +248,7 @@ void aao_default_opts(aao_opts* o) {
   o->mgrit_coarse_k = 0;
   o->schur_k = 0;
   o->inner_orth = AAO_ORTH_CGS2;
+  o->outer_orth = AAO_ORTH_CGS2;
 }
 
 int aao_create_problem(const aao_desc* d, const aao_opts* o, aao_problem** out) {

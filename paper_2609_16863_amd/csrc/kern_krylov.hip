@@ -172,6 +172,55 @@ __global__ __launch_bounds__(TPB) void k_gs(TW* __restrict__ w, const TV* __rest
   }
 }
 
+// One pass over a chunk of the basis for the Gram-matrix form of classical
+// Gram-Schmidt: block partials of <w, V_d> (slot d), <vlast, V_d> (slot
+// nd + d, the newest basis vector's Gram column) and <w, w>; k_gs_finish with
+// 2 nd dots completes them into slots[od ..].  nd <= DOTS_PER_PASS / 2.
+template <class TW, class TV, int ND>
+__global__ __launch_bounds__(TPB) void k_gs_gram(const TW* __restrict__ w, const TV* __restrict__ V,
+                                                 const TV* __restrict__ vlast, GSArgs a) {
+  const int blk = blockIdx.x, tid = threadIdx.x;
+  double acc[ND], accg[ND], self = 0.0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) acc[d] = accg[d] = 0.0;
+  for (int64_t idx = (int64_t)blk * TPB + tid; idx < a.L; idx += (int64_t)a.nblk * TPB) {
+    const double wv = (double)w[idx], lv = (double)vlast[idx];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const double vv = d < a.nd ? (double)V[d * a.vstride + idx] : 0.0;
+      acc[d] += vv * wv;
+      accg[d] += vv * lv;
+    }
+    self += wv * wv;
+  }
+  __shared__ double red[TPB / 64][2 * ND + 1];
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    if (d < a.nd) {
+      const double v1 = wave_sum(acc[d]), v2 = wave_sum(accg[d]);
+      if (lane == 0) {
+        red[wave][d] = v1;
+        red[wave][ND + d] = v2;
+      }
+    }
+  }
+  const double vs = wave_sum(self);
+  if (lane == 0) red[wave][2 * ND] = vs;
+  __syncthreads();
+  double* part = a.partial + (int64_t)blk * NSLOT;
+  if (tid < 2 * ND + 1) {
+    const int e = tid;
+    const bool used = e == 2 * ND ? a.self != 0 : (e % ND) < a.nd;
+    if (used) {
+      double sum = 0.0;
+      for (int r = 0; r < TPB / 64; ++r) sum += red[r][e];
+      const int slot = e == 2 * ND ? DOTS_PER_PASS : (e < ND ? e : a.nd + (e - ND));
+      part[slot] = sum;
+    }
+  }
+}
+
 // Second pass of a Gram-Schmidt reduction: one workgroup per instance sums
 // the block partials in a fixed order (thread t takes blocks t, t+TPB, ...,
 // then a tree), stores the results and runs the GMRES scalar update.  All
@@ -520,6 +569,23 @@ hipError_t gs_pass(TW* w, const TV* V, const GSArgs& a, int B, hipStream_t st) {
     DISPATCH_ND(a.dots ? a.nd : 0, AAO_GSF);
 #undef AAO_GSF
   }
+  return hipGetLastError();
+}
+
+hipError_t gs_gram(const double* w, const double* V, const double* vlast, const GSArgs& a, hipStream_t st) {
+  if (a.nd < 1 || 2 * a.nd > DOTS_PER_PASS) return hipErrorInvalidValue;
+#define AAO_GG(ND) hipLaunchKernelGGL((k_gs_gram<double, double, ND>), seg_grid(a.nblk, 1), dim3(TPB), 0, st, w, V, vlast, a)
+  if (a.nd <= 1) AAO_GG(1);
+  else if (a.nd <= 2) AAO_GG(2);
+  else if (a.nd <= 4) AAO_GG(4);
+  else AAO_GG(8);
+#undef AAO_GG
+  GSArgs f = a;
+  f.dots = 1;
+  f.nd = 2 * a.nd;
+#define AAO_GSF(ND) hipLaunchKernelGGL((k_gs_finish<ND>), dim3(1u), dim3(TPB), 0, st, f)
+  DISPATCH_ND(f.nd, AAO_GSF);
+#undef AAO_GSF
   return hipGetLastError();
 }
 

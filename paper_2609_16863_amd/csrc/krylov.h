@@ -50,6 +50,11 @@ int seg_blocks(int64_t L, int B);
 template <class TW, class TV>
 hipError_t gs_pass(TW* w, const TV* V, const GSArgs& a, int B, hipStream_t st);
 
+// One instance (the outer solve): slots[od + d] = <w, V_d> and
+// slots[od + nd + d] = <vlast, V_d> for d < nd (nd <= DOTS_PER_PASS / 2),
+// slots[os] = <w, w> when a.self.
+hipError_t gs_gram(const double* w, const double* V, const double* vlast, const GSArgs& a, hipStream_t st);
+
 // out = (w - sum_{d<nd} slots[ca+d] V_d) * (cs >= 0 ? slots[cs] : alpha)
 template <class TW, class TV, class TO>
 hipError_t basis_update(const TW* w, int64_t sw, const TV* V, int64_t vstride, int64_t sv, int nd, TO* out,

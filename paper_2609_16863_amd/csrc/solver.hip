@@ -509,6 +509,7 @@ class Fgmres {
   // Classical Gram-Schmidt of w against V_0..V_{nd-1}, twice.  Leaves
   // w - V h1 in w, and on the host h1 + h2 (hcol), |h2|^2 and <w, w>.
   hipError_t orthogonalize(int nd, std::vector<double>& hcol, double& h2sq, double& ww) {
+    if (h_->opts.outer_orth == AAO_ORTH_GRAM) return orthogonalize_gram(nd, hcol, h2sq, ww);
     const int64_t U = h_->U;
     const int H1 = 8, H2 = H1 + MMAX + 8, WW = H2 + MMAX + 8;
     for (int c0 = 0; c0 < nd; c0 += DOTS_PER_PASS) {
@@ -555,6 +556,64 @@ class Fgmres {
     }
     ww = hp[WW - H1];
     return hipSuccess;
+  }
+
+  // Classical Gram-Schmidt twice, with the second pass taken from the Gram
+  // matrix G = V^T V of the basis instead of a second sweep over it:
+  // h1 = V^T w, h = h1 + V^T (w - V h1) = (2 I - G) h1 and
+  // ||w - V h||^2 = <w,w> - 2 h^T h1 + h^T G h, in exact arithmetic the
+  // two-pass result.  One sweep per iteration forms h1, <w,w> and the
+  // newest basis vector's Gram column <V_d, v_{nd-1}> together; w itself is
+  // left as it is, and h goes to the device slots (H2), where next_basis
+  // and correct_and_norm take their coefficients from.  Returns h in hcol
+  // and h2sq = <w,w> - ||w - V h||^2.
+  hipError_t orthogonalize_gram(int nd, std::vector<double>& hcol, double& h2sq, double& ww) {
+    const int64_t U = h_->U;
+    const int H2 = 8 + MMAX + 8, WW = H2 + MMAX + 8, SCR = WW + 8;
+    constexpr int CH = DOTS_PER_PASS / 2;
+    const double* vlast = V_ + (int64_t)(nd - 1) * U;
+    for (int c0 = 0; c0 < nd; c0 += CH) {
+      const int cnt = std::min(CH, nd - c0);
+      GSArgs a = gs_args(cnt);
+      a.dots = 1;
+      a.od = SCR + 2 * c0;
+      a.self = c0 + cnt >= nd;
+      a.os = WW;
+      TRY(gs_gram(w_, V_ + (int64_t)c0 * U, vlast, a, st_));
+    }
+    double* hp = h_->host_scalars();
+    TRY(hipMemcpyAsync(hp, oslots_ + WW, sizeof(double) * (size_t)(SCR - WW + 2 * nd), hipMemcpyDeviceToHost, st_));
+    TRY(hipStreamSynchronize(st_));
+    ww = hp[0];
+    const double* sc = hp + (SCR - WW);
+    const int ld = MMAX + 1;
+    gram_.resize((size_t)ld * ld);
+    std::vector<double> h1(nd);
+    for (int c0 = 0; c0 < nd; c0 += CH) {
+      const int cnt = std::min(CH, nd - c0);
+      for (int d = 0; d < cnt; ++d) {
+        h1[c0 + d] = sc[2 * c0 + d];
+        const double gv = sc[2 * c0 + cnt + d];
+        gram_[(size_t)(c0 + d) * ld + nd - 1] = gv;
+        gram_[(size_t)(nd - 1) * ld + c0 + d] = gv;
+      }
+    }
+    hcol.assign(nd, 0.0);
+    for (int i = 0; i < nd; ++i) {
+      double gh = 0.0;
+      for (int k = 0; k < nd; ++k) gh += gram_[(size_t)i * ld + k] * h1[k];
+      hcol[i] = 2.0 * h1[i] - gh;
+    }
+    double hh1 = 0.0, hgh = 0.0;
+    for (int i = 0; i < nd; ++i) {
+      hh1 += hcol[i] * h1[i];
+      double gh = 0.0;
+      for (int k = 0; k < nd; ++k) gh += gram_[(size_t)i * ld + k] * hcol[k];
+      hgh += hcol[i] * gh;
+    }
+    h2sq = 2.0 * hh1 - hgh;
+    hup_ = hcol;
+    return hipMemcpyAsync(oslots_ + H2, hup_.data(), sizeof(double) * (size_t)nd, hipMemcpyHostToDevice, st_);
   }
 
   // The second Gram-Schmidt correction applied to w (w -= V h2), and
@@ -850,6 +909,8 @@ class Fgmres {
   double *V_, *w_, *partial_, *oslots_;
   unsigned* counters_;
   TI* Z_;
+  std::vector<double> gram_;   // Gram matrix of the outer basis (outer_orth GRAM), (MMAX + 1)^2
+  std::vector<double> hup_;    // its projection coefficients, uploaded to the slots
   bool timed_ = false, pending_ = false;
   int applications_ = 0;
   double theta_ms_ = 0.0, schur_ms_ = 0.0;

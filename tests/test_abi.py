@@ -84,7 +84,7 @@ def test_sizes_and_workspace():
                                  dict(side=3), dict(schur=2), dict(outer_precision=2), dict(precision=5),
                                  dict(mg_low_from=-1), dict(mg_coarse_fp32=2), dict(mgrit_coarse_k=-1),
                                  dict(mgrit_coarse_k=13), dict(schur_k=-1), dict(schur_k=13),
-                                 dict(inner_orth=2)])
+                                 dict(inner_orth=2), dict(outer_orth=1), dict(outer_orth=3)])
 def test_invalid_arguments_are_rejected(bad):
     abi, lib = _lib()
     desc_keys = {"dim", "n", "s", "nt", "T"}

@@ -56,13 +56,16 @@ def test_solve_matches_stepping(dim, n, s, nt, precision):
     assert rel_err(x, xs) <= 1e-8, st
 
 
-def test_iteration_counts_track_oracle_fgmres():
-    """Same preconditioner settings: GPU FP64 FGMRES iterations within +-1 of the oracle's."""
+@pytest.mark.parametrize("outer_orth", ["cgs2", "gram"])
+def test_iteration_counts_track_oracle_fgmres(outer_orth):
+    """Same preconditioner settings: GPU FP64 FGMRES iterations within +-1 of
+    the oracle's (modified Gram-Schmidt), with two classical passes or the
+    Gram-matrix form."""
     require_gpu()
     from paper_2609_16863_amd import HeatProblem
     n, s, nt = 24, 3, 6
     p = allatonce.Problem(n, 2, s, nt, 1.0)
-    hp = HeatProblem(2, n, s, nt, 1.0, tol=1e-8)
+    hp = HeatProblem(2, n, s, nt, 1.0, tol=1e-8, outer_orth=outer_orth)
     rng = np.random.default_rng(77)
     f = heat_inputs.bump_source(rng, n, 2, hp.stage_times())
     u0 = heat_inputs.smooth_initial(rng, n, 2)
