@@ -300,6 +300,21 @@ def vcycle_kernels(hp, precision, reps):
 
     tall_min = hp.tune_state["tall_min_b"] if hp.tune_state else 8
     side = [int(round(v ** (1.0 / hp.dim))) for v in nodes]
+    nu2 = hp.options["nu2"]
+
+    def marches(label, B):
+        """Level 0 of the constant-coefficient 2D operator from tall_min
+        blocks runs the row-marching up kernel."""
+        return (label == "k_up2d@0" and hp.dim == 2 and hp.disc == "fd" and hp._kappa is None
+                and B >= tall_min)
+
+    def march_grid(B):
+        """Workgroups of k_up2d_march: four waves, one wave per strip of
+        64 - 2 nu2 columns and 16 or 32 rows of one block."""
+        nf, ow = side[0], 64 - 2 * nu2
+        strips = -(-nf // ow)
+        seg = 32 if strips * -(-nf // 16) * B > 8 * 4 * 256 else 16
+        return -(-(strips * -(-nf // seg) * B) // 4)
 
     def grid_workgroups(label, B):
         """Workgroups of one launch (what a counter run reports per dispatch):
@@ -309,6 +324,8 @@ def vcycle_kernels(hp, precision, reps):
         name, lev = label.split("@")
         if hp.dim != 2:
             return None
+        if marches(label, B):
+            return march_grid(B)
         if name in ("k_down2d", "k_up2d"):
             nc = side[int(lev) + 1]
             ty = 16 if (precision != "fp64" and B >= tall_min) else 8
@@ -342,6 +359,8 @@ def vcycle_kernels(hp, precision, reps):
     # the short and tall tiles of the tiled kernels
     def symbol(label, B):
         name, lev = label.split("@")
+        if marches(label, B):
+            return "k_up2d_march<level 0>"
         sym = name + ("<level 0" if lev == "0" else "<coarse levels")
         if name in ("k_down2d", "k_up2d") and precision != "fp64":
             sym += ", tall tiles" if B >= tall_min else ", short tiles"
@@ -424,6 +443,8 @@ def _kernel_matches(name, base, level0):
     i = name.find(base + "<")
     if i < 0:
         return False
+    if base == "k_up2d_march":   # level 0 only
+        return level0
     kind = int(name[i + len(base) + 1:].split(",")[0])
     return (kind <= 1) == level0
 

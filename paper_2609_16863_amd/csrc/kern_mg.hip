@@ -873,6 +873,128 @@ __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_
   }
 }
 
+// Up on level 0 of the constant-coefficient finite-difference operator,
+// row-marching.  One wave owns OW = 64 - 2 NU adjacent columns (lane =
+// column) and SEG rows of one instance, and computes NU more columns on
+// each side and NU more rows below and above: the halo its sweeps consume
+// (values there are wrong by the missing outer neighbours, which reach no
+// owned node within NU sweeps).  The wave walks up the rows: row j takes
+// x_in + P e, sweep k updates row j - k from a window of three rows of
+// sweep k - 1 kept in registers, x neighbours come from the adjacent lanes,
+// and the loads of rows j + 1 .. j + MPD are in flight meanwhile.  Each
+// node takes the same arithmetic as in k_up2d, with no LDS staging and no
+// barrier.  Coarse rows of the bilinear prolongation: fine rows 2m - 1 and
+// 2m use coarse rows m - 1 (weight 1, resp. 1/2) and m (0, resp. 1/2).
+constexpr int MPD = 4;    // rows fetched ahead
+
+template <int NU, class TF, class TE, class C, int SEG>
+__global__ __launch_bounds__(256) void k_up2d_march(const TF* __restrict__ xin, int64_t sxi, const TE* __restrict__ e,
+                                                    int64_t se, const TF* __restrict__ b, int64_t sb,
+                                                    TF* __restrict__ xout, int64_t sxo, LevelOp<C> op, int nc,
+                                                    C omega, int nstrips, int nsegs, int64_t units, C escale) {
+  constexpr int OW = 64 - 2 * NU;
+  const int64_t u = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (u >= units) return;   // whole wave
+  const int lane = threadIdx.x & 63;
+  const int strip = (int)(u % nstrips);
+  const int64_t rest = u / nstrips;
+  const int seg = (int)(rest % nsegs);
+  const int64_t inst = rest / nsegs;
+  const int n = op.n;
+  const int g = strip * OW - NU + lane;
+  const bool colin = g >= 0 && g < n;
+  const bool own = colin && lane >= NU && lane < 64 - NU;
+  const int j0 = seg * SEG, j1 = j0 + SEG < n ? j0 + SEG : n;
+  const int jlo = j0 - NU, jlast = j1 - 1 + NU;
+  const int li = floor_half(g - 1);
+  const bool cin0 = colin && li >= 0 && li < nc, cin1 = colin && li + 1 >= 0 && li + 1 < nc;
+  const C wi0 = (g & 1) ? C(1) : C(0.5), wi1 = (g & 1) ? C(0) : C(0.5);
+  const TF* xi = xin + inst * sxi;
+  const TF* bi = b + inst * sb;
+  const TE* ei = e + inst * se;
+  TF* xo = xout + inst * sxo;
+  const C idc = omega / (C(1) + op.a * op.ih2 * C(4));
+  // Loads are unconditional from a clamped in-bounds address and masked
+  // afterwards, so that no branch (and no wait) separates a fetch from the
+  // rows computed meanwhile.  Coarse values stay unscaled until used.
+  const int lic0 = cin0 ? li : 0, lic1 = cin1 ? li + 1 : 0;
+  auto hrow = [&](int J) -> C {
+    const bool jin = J >= 0 && J < nc;
+    const int64_t o = jin ? (int64_t)J * nc : 0;
+    const C e0 = ld<TE, C>(ei + o + lic0), e1 = ld<TE, C>(ei + o + lic1);
+    return wi0 * ((jin && cin0) ? escale * e0 : C(0)) + wi1 * ((jin && cin1) ? escale * e1 : C(0));
+  };
+  C qx[MPD], qb[MPD], qe0[MPD], qe1[MPD];
+  bool qin[MPD], qjin[MPD];
+  auto fetch = [&](int r, int q) {
+    const bool rin = colin && r >= 0 && r < n && r <= jlast;
+    const int64_t o = rin ? (int64_t)r * n + g : 0;
+    qx[q] = ld<TF, C>(xi + o);
+    qb[q] = ld<TF, C>(bi + o);
+    qin[q] = rin;
+    const int J = floor_half(r - 1) + 1;
+    const bool jin = r <= jlast && J >= 0 && J < nc;
+    const int64_t oc = jin ? (int64_t)J * nc : 0;
+    qe0[q] = ld<TE, C>(ei + oc + lic0);
+    qe1[q] = ld<TE, C>(ei + oc + lic1);
+    qjin[q] = jin;
+  };
+#pragma unroll
+  for (int q = 0; q < MPD; ++q) fetch(jlo + q, q);
+  C hlo = hrow(floor_half(jlo - 1)), hhi = hlo;
+  C X[NU > 1 ? NU : 1][3];   // X[k]: sweep k at rows j - k - 2, j - k - 1, j - k
+  C Bw[NU + 1];              // b at rows j, j - 1, .., j - NU
+#pragma unroll
+  for (int k = 0; k < NU; ++k) X[k][0] = X[k][1] = X[k][2] = C(0);
+#pragma unroll
+  for (int k = 0; k <= NU; ++k) Bw[k] = C(0);
+  // the march is unrolled completely (a fixed SEG + 2 NU rows; those past
+  // jlast load nothing and store nothing), so the fetch queue needs no
+  // register moves between rows
+  constexpr int ROWS = SEG + 2 * NU;
+#pragma unroll
+  for (int t = 0; t < ROWS; ++t) {
+    const int q = t % MPD;
+    const int j = jlo + t;
+    // prolongation and x_in on row j
+    const C e0 = (qjin[q] && cin0) ? escale * qe0[q] : C(0), e1 = (qjin[q] && cin1) ? escale * qe1[q] : C(0);
+    const C hnew = wi0 * e0 + wi1 * e1;
+    const bool odd = j & 1;
+    hlo = odd ? hhi : hlo;
+    hhi = hnew;
+    const C wj0 = odd ? C(1) : C(0.5), wj1 = odd ? C(0) : C(0.5);
+    const C pe = wj0 * hlo + wj1 * hhi;
+    const bool rin0 = colin && j >= 0 && j < n;
+    const C x0 = rin0 ? qx[q] + pe : C(0);
+#pragma unroll
+    for (int k = NU; k > 0; --k) Bw[k] = Bw[k - 1];
+    Bw[0] = qin[q] ? qb[q] : C(0);
+    if (t + MPD < ROWS) fetch(j + MPD, q);
+    X[0][0] = X[0][1];
+    X[0][1] = X[0][2];
+    X[0][2] = x0;
+    // sweeps: sweep k on row j - k from the window of sweep k - 1
+#pragma unroll
+    for (int k = 1; k <= NU; ++k) {
+      const C* w = X[k - 1];
+      const C c = w[1];
+      const C xl = __shfl_up(c, 1), xr = __shfl_down(c, 1);
+      const C Ax = c + op.a * op.ih2 * (C(4) * c - xl - xr - w[0] - w[2]);
+      const C v = c + idc * (Bw[k] - Ax);
+      const int jr = j - k;
+      const bool rin = colin && jr >= 0 && jr < n;
+      const C vk = rin ? v : C(0);
+      if (k < NU) {
+        X[k][0] = X[k][1];
+        X[k][1] = X[k][2];
+        X[k][2] = vk;
+      } else if (own && jr >= j0 && jr < j1) {
+        st<TF, C>(xo + (int64_t)jr * n + g, vk);
+      }
+    }
+  }
+}
+
 // Exact solve on the coarsest level (at most COARSE_MAX nodes) with its
 // precomputed dense inverse, stored transposed: x_r = sum_c invT[c Nc + r] b_c.
 template <class T, class C>
@@ -2013,6 +2135,29 @@ hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec
 #define UP_T(K, NU, TF, TYV) hipLaunchKernelGGL((k_up2d<K, NU, TF, TC, C, TYV>), g, dim3(256), 0, st_, (const TF*)xin.ptr, xin.stride, (const TC*)ec.ptr, ec.stride, (const TF*)b.ptr, b.stride, (TF*)xout.ptr, xout.stride, op, nc, omega, gx, gy, es)
 #define UP(K, NU, TF) do { if (tall) UP_T(K, NU, TF, TY0L); else UP_T(K, NU, TF, TCY); } while (0)
 #define UP_NU(K, TF) do { if (nu == 1) UP(K, 1, TF); else if (nu == 2) UP(K, 2, TF); else UP(K, 3, TF); } while (0)
+  if (l == 0 && !h_->fe && !h_->vark && B >= h_->tune.tall_min_b) {
+    // level 0 of the constant-coefficient operator, batched: the row march
+    // (the values of the tiles, without their LDS round trips and barriers);
+    // 16-row segments while one round of waves does not fill the chip
+    // (8 per SIMD), 32-row ones (less halo) beyond
+    const int nf = h_->lev_n[0];
+    const int ow = 64 - 2 * nu;
+    const int nstrips = (nf + ow - 1) / ow;
+    const bool seg32 = (int64_t)nstrips * ((nf + 15) / 16) * B > 8 * 4 * 256;
+    const int seg = seg32 ? 32 : 16;
+    const int nsegs = (nf + seg - 1) / seg;
+    const int64_t units = (int64_t)nstrips * nsegs * B;
+    const dim3 gm((unsigned)((units + 3) / 4));
+#define UPM(NU, SEG) hipLaunchKernelGGL((k_up2d_march<NU, TI, TC, C, SEG>), gm, dim3(256), 0, st_, (const TI*)xin.ptr, xin.stride, (const TC*)ec.ptr, ec.stride, (const TI*)b.ptr, b.stride, (TI*)xout.ptr, xout.stride, op, nc, omega, nstrips, nsegs, units, es)
+#define UPM_NU(SEG) do { if (nu == 1) UPM(1, SEG); else if (nu == 2) UPM(2, SEG); else UPM(3, SEG); } while (0)
+    return typed1(1, [&](auto tc) {
+      using TC = decltype(tc);
+      if (seg32) UPM_NU(32); else UPM_NU(16);
+      return hipGetLastError();
+    });
+#undef UPM_NU
+#undef UPM
+  }
   if (l == 0)
     return typed1(1, [&](auto tc) {
       using TC = decltype(tc);

@@ -111,10 +111,12 @@ def test_apply_mg_full_size_sampled_blocks():
 @pytest.mark.parametrize("n,vark", [(150, False), (257, False), (75, True)])
 def test_apply_mg_fp32_batched_tiles_equal_single_blocks(n, vark):
     """With FP32 arithmetic, the tiled levels run taller tiles for launches
-    of 8 or more blocks and the short ones for single blocks.  Jacobi sweeps
-    recomputed in tile halos give every node the same value either way, so a
-    9-block call equals nine 1-block calls bit for bit; both match the oracle
-    (ragged last tiles at 150 and 257, face diffusivities at 75)."""
+    of 8 or more blocks and the short ones for single blocks (level 0 of the
+    constant-coefficient operator runs the row-marching up kernel instead of
+    tall tiles).  Jacobi sweeps recomputed in halos give every node the same
+    value either way, so a 9-block call equals nine 1-block calls bit for
+    bit; both match the oracle (ragged last tiles at 150 and 257, face
+    diffusivities at 75)."""
     require_gpu()
     from paper_2609_16863_amd import HeatProblem
     dim, s, nt = 2, 2, 9
@@ -130,6 +132,36 @@ def test_apply_mg_fp32_batched_tiles_equal_single_blocks(n, vark):
         assert np.array_equal(z, single), stage
         ref = _oracle(p, False, stage, r[[0, nt - 1]], 1)
         assert rel_err(z[[0, nt - 1]], ref) <= 2e-5, (stage, rel_err(z[[0, nt - 1]], ref))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+@pytest.mark.parametrize("n,nu,nt", [(40, 1, 4), (61, 3, 4), (150, 2, 9), (515, 2, 4), (512, 2, 64)])
+def test_apply_mg_level0_row_march_equals_tiles(precision, tol, n, nu, nt):
+    """From tall_min_b blocks on, the up kernel of level 0 of the
+    constant-coefficient 2D operator is the row march (one wave per strip of
+    64 - 2 nu columns and 16 or 32 rows, register windows instead of LDS
+    tiles); tall_min_b = 2^30 sends every launch to the tiles.  Both apply
+    the same arithmetic to every node, so the cycles agree bit for bit:
+    one strip (40), the ragged last strip and segment (61, 150, 515), nu = 1
+    and 3, and 32-row segments (512 with 64 blocks).  Block 0 is checked
+    against the oracle."""
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    dim, s = 2, 2
+    p = allatonce.Problem(n, dim, s, nt, 1.0)
+    hp = HeatProblem(dim, n, s, nt, 1.0, precision=precision, nu1=nu, nu2=nu)
+    rng = np.random.default_rng(3 * n + nu)
+    r = rng.standard_normal((nt, p.N))
+    if precision == "fp32":
+        r = r.astype(np.float32).astype(np.float64)
+    announce("apply_mg row march vs tiles", precision, n, "nu", nu, "blocks", nt)
+    hp.set_launch_shapes(1, 0)
+    z_march = _run(hp, r, 1, 2, False)
+    hp.set_launch_shapes(1 << 30, 0)
+    z_tiles = _run(hp, r, 1, 2, False)
+    assert np.array_equal(z_march, z_tiles)
+    ref = _oracle(p, False, 1, r[:1], 2, nu=nu)
+    assert rel_err(z_march[:1], ref) <= tol, rel_err(z_march[:1], ref)
 
 
 # Variable diffusivity: coarse levels are the Galerkin products R A P of the
