@@ -302,16 +302,21 @@ def vcycle_kernels(hp, precision, reps):
     side = [int(round(v ** (1.0 / hp.dim))) for v in nodes]
     nu2 = hp.options["nu2"]
 
+    nu1 = hp.options["nu1"]
+
     def marches(label, B):
         """Level 0 of the constant-coefficient 2D operator from tall_min
-        blocks runs the row-marching up kernel."""
-        return (label == "k_up2d@0" and hp.dim == 2 and hp.disc == "fd" and hp._kappa is None
-                and B >= tall_min)
+        blocks runs the row-marching kernels (the profiled cycle starts
+        from zero and forms no coupling terms)."""
+        return (label in ("k_up2d@0", "k_down2d@0") and hp.dim == 2 and hp.disc == "fd"
+                and hp._kappa is None and B >= tall_min)
 
-    def march_grid(B):
-        """Workgroups of k_up2d_march: four waves, one wave per strip of
-        64 - 2 nu2 columns and 16 or 32 rows of one block."""
-        nf, ow = side[0], 64 - 2 * nu2
+    def march_grid(label, B):
+        """Workgroups of k_up2d_march / k_down2d_march: four waves, one wave
+        per strip of 64 - 2 nu2 (up) or 62 - 2 nu1 (down) columns and 16 or
+        32 rows of one block."""
+        nf = side[0]
+        ow = 64 - 2 * nu2 if label.startswith("k_up2d") else 62 - 2 * nu1
         strips = -(-nf // ow)
         seg = 32 if strips * -(-nf // 16) * B > 8 * 4 * 256 else 16
         return -(-(strips * -(-nf // seg) * B) // 4)
@@ -325,7 +330,7 @@ def vcycle_kernels(hp, precision, reps):
         if hp.dim != 2:
             return None
         if marches(label, B):
-            return march_grid(B)
+            return march_grid(label, B)
         if name in ("k_down2d", "k_up2d"):
             nc = side[int(lev) + 1]
             ty = 16 if (precision != "fp64" and B >= tall_min) else 8
@@ -360,7 +365,7 @@ def vcycle_kernels(hp, precision, reps):
     def symbol(label, B):
         name, lev = label.split("@")
         if marches(label, B):
-            return "k_up2d_march<level 0>"
+            return name + "_march<level 0>"
         sym = name + ("<level 0" if lev == "0" else "<coarse levels")
         if name in ("k_down2d", "k_up2d") and precision != "fp64":
             sym += ", tall tiles" if B >= tall_min else ", short tiles"
@@ -443,7 +448,7 @@ def _kernel_matches(name, base, level0):
     i = name.find(base + "<")
     if i < 0:
         return False
-    if base == "k_up2d_march":   # level 0 only
+    if base.endswith("_march"):   # level 0 only
         return level0
     kind = int(name[i + len(base) + 1:].split(",")[0])
     return (kind <= 1) == level0

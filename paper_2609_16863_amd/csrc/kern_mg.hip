@@ -995,6 +995,140 @@ __global__ __launch_bounds__(256) void k_up2d_march(const TF* __restrict__ xin, 
   }
 }
 
+// Down on level 0 of the constant-coefficient finite-difference operator
+// from a zero initial guess, row-marching (the counterpart of
+// k_up2d_march).  Row r of the march forms b - sum_l c_l K z_l (z rows
+// r - 1 .. r + 1 in registers), the pointwise first sweep on row r, sweep k
+// on row r - k, the residual on row r - NU and, when that row is even, the
+// full-weighting restriction onto the coarse row centred one row below.  The
+// residual must be exact one node beyond the owned columns and rows on the
+// upper side (the stencil of the last coarse node) and on the owned nodes
+// themselves, so a wave owns OW = 62 - 2 HC columns starting at lane HC =
+// NU (+ 1 with coupling terms, whose K z needs one more lane) and marches
+// NU rows below and NU + 1 above its SEG rows.  OW and SEG are even: strips
+// and segments start at even fine indices, so every coarse node 2I + 1 has
+// its whole stencil in the strip and segment that own it.
+template <int NU, class TF, class TC, class C, int NZ, int SEG>
+__global__ __launch_bounds__(256) void k_down2d_march(const TF* __restrict__ b, int64_t sb, TF* __restrict__ xout,
+                                                      int64_t sxo, TC* __restrict__ bc, int64_t sbc, LevelOp<C> op,
+                                                      int nc, C omega, int nstrips, int nsegs, int64_t units,
+                                                      CplArgs<TF, C> cpl, C bscale) {
+  constexpr int S = NU - 1;   // window sweeps after the pointwise one
+  constexpr int HC = NU + (NZ > 0 ? 1 : 0), OW = 62 - 2 * HC;
+  constexpr int ROWS = SEG + 2 * NU + 1;
+  constexpr int PD = NZ == 0 ? 2 * MPD : MPD;   // rows fetched ahead (one load per row without coupling)
+  const int64_t u = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (u >= units) return;   // whole wave
+  const int lane = threadIdx.x & 63;
+  const int strip = (int)(u % nstrips);
+  const int64_t rest = u / nstrips;
+  const int seg = (int)(rest % nsegs);
+  const int64_t inst = rest / nsegs;
+  const int n = op.n;
+  const int g = strip * OW - HC + lane;
+  const bool colin = g >= 0 && g < n;
+  const bool own = colin && lane >= HC && lane < HC + OW;
+  const bool cown = own && (g & 1) && (g - 1) / 2 < nc;   // owns coarse column (g - 1) / 2
+  const int j0 = seg * SEG, j1 = j0 + SEG < n ? j0 + SEG : n;
+  const int jlo = j0 - NU, jlast = j1 + NU;
+  const TF* bi = b + inst * sb;
+  TF* xo = xout + inst * sxo;
+  TC* bco = bc + inst * sbc + (cown ? (g - 1) / 2 : 0);
+  const C idc = omega / (C(1) + op.a * op.ih2 * C(4));
+  const TF* zi[NZ > 0 ? NZ : 1];
+#pragma unroll
+  for (int l = 0; l < NZ; ++l) zi[l] = cpl.z + inst * cpl.sz + l * cpl.zs;
+  // unconditional loads from clamped addresses, masked afterwards
+  auto off = [&](int r) -> int64_t { return (colin && r >= 0 && r < n) ? (int64_t)r * n + g : 0; };
+  auto inr = [&](int r) -> bool { return colin && r >= 0 && r < n; };
+  C qb[PD], qz[NZ > 0 ? NZ : 1][PD];
+  auto fetch = [&](int r, int q) {
+    qb[q] = ld<TF, C>(bi + off(r));
+#pragma unroll
+    for (int l = 0; l < NZ; ++l) qz[l][q] = ld<TF, C>(zi[l] + off(r + 1));
+  };
+#pragma unroll
+  for (int q = 0; q < PD; ++q) fetch(jlo + q, q);
+  C Zw[NZ > 0 ? NZ : 1][3];   // z_l at rows r - 1, r, r + 1
+#pragma unroll
+  for (int l = 0; l < NZ; ++l) {
+    Zw[l][0] = C(0);
+    Zw[l][1] = inr(jlo - 1) ? ld<TF, C>(zi[l] + off(jlo - 1)) : C(0);
+    Zw[l][2] = inr(jlo) ? ld<TF, C>(zi[l] + off(jlo)) : C(0);
+  }
+  C X[S + 1][3];   // X[k]: sweep k (0: the pointwise one) at rows r - k - 2 .. r - k
+  C Bw[S + 2];     // right-hand side at rows r, r - 1, .., r - S - 1
+  C Rw[3];         // residual at rows r - NU - 2 .. r - NU
+#pragma unroll
+  for (int k = 0; k <= S; ++k) X[k][0] = X[k][1] = X[k][2] = C(0);
+#pragma unroll
+  for (int k = 0; k <= S + 1; ++k) Bw[k] = C(0);
+  Rw[0] = Rw[1] = Rw[2] = C(0);
+#pragma unroll
+  for (int t = 0; t < ROWS; ++t) {
+    const int q = t % PD;
+    const int r = jlo + t;
+    const bool own_r = own && r >= j0 && r < j1;
+    // right-hand side of row r, with Rana's coupling terms
+    C acc = qb[q];
+#pragma unroll
+    for (int l = 0; l < NZ; ++l) {
+      Zw[l][0] = Zw[l][1];
+      Zw[l][1] = Zw[l][2];
+      Zw[l][2] = inr(r + 1) ? qz[l][q] : C(0);
+      const C c0 = Zw[l][1];
+      const C zl = __shfl_up(c0, 1), zr = __shfl_down(c0, 1);
+      const C kz = op.ih2 * (C(4) * c0 - zl - zr - Zw[l][0] - Zw[l][2]);
+      acc -= cpl.c[l] * kz;
+    }
+    const bool din = inr(r);
+    const C bb = din ? acc : C(0);
+    if (t + PD < ROWS) fetch(r + PD, q);
+    if constexpr (NZ > 0)
+      if (own_r) st<TF, C>(cpl.out + inst * cpl.so + (int64_t)r * n + g, bb);
+#pragma unroll
+    for (int k = S + 1; k > 0; --k) Bw[k] = Bw[k - 1];
+    Bw[0] = bb;
+    X[0][0] = X[0][1];
+    X[0][1] = X[0][2];
+    X[0][2] = din ? idc * bb : C(0);
+    // sweep k on row r - k from the window of sweep k - 1
+#pragma unroll
+    for (int k = 1; k <= S; ++k) {
+      const C* w = X[k - 1];
+      const C c = w[1];
+      const C xl = __shfl_up(c, 1), xr = __shfl_down(c, 1);
+      const C Ax = c + op.a * op.ih2 * (C(4) * c - xl - xr - w[0] - w[2]);
+      const C v = c + idc * (Bw[k] - Ax);
+      X[k][0] = X[k][1];
+      X[k][1] = X[k][2];
+      X[k][2] = inr(r - k) ? v : C(0);
+    }
+    // the smoothed iterate of row r - S
+    if (own && r - S >= j0 && r - S < j1) st<TF, C>(xo + (int64_t)(r - S) * n + g, X[S][2]);
+    // residual on row r - NU
+    {
+      const C* w = X[S];
+      const C c = w[1];
+      const C xl = __shfl_up(c, 1), xr = __shfl_down(c, 1);
+      const C Ax = c + op.a * op.ih2 * (C(4) * c - xl - xr - w[0] - w[2]);
+      Rw[0] = Rw[1];
+      Rw[1] = Rw[2];
+      Rw[2] = inr(r - NU) ? Bw[S + 1] - Ax : C(0);
+    }
+    // restriction onto coarse row J = (r - NU) / 2 - 1 (fine row 2J + 1)
+    const int rr = r - NU;
+    if (rr >= 2 && !(rr & 1)) {   // wave-uniform
+      const int J = rr / 2 - 1;
+      const C rl = __shfl_up(Rw[1], 1), rrt = __shfl_down(Rw[1], 1);
+      const C dl = __shfl_up(Rw[0], 1), dr = __shfl_down(Rw[0], 1);
+      const C ul = __shfl_up(Rw[2], 1), ur = __shfl_down(Rw[2], 1);
+      const C v = C(0.25) * bscale * (Rw[1] + C(0.5) * (rl + rrt + Rw[0] + Rw[2]) + C(0.25) * (dl + dr + ul + ur));
+      if (cown && J < nc && 2 * J + 1 >= j0 && 2 * J + 1 < j1) st<TC, C>(bco + (int64_t)J * nc, v);
+    }
+  }
+}
+
 // Exact solve on the coarsest level (at most COARSE_MAX nodes) with its
 // precomputed dense inverse, stored transposed: x_r = sum_c invT[c Nc + r] b_c.
 template <class T, class C>
@@ -2097,6 +2231,29 @@ hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, in
 #define DN(K, NU, TF, NZ, CA) do { if (tall) DN_T(K, NU, TF, NZ, CA, TY0L); else DN_T(K, NU, TF, NZ, CA, TCY); } while (0)
 #define DN_NU(K, TF, NZ, CA) do { if (nu == 1) DN(K, 1, TF, NZ, CA); else if (nu == 2) DN(K, 2, TF, NZ, CA); else DN(K, 3, TF, NZ, CA); } while (0)
 #define DN_Z(K) do { if (nz == 0) DN_NU(K, TI, 0, ca); else if (nz == 1) DN_NU(K, TI, 1, ca); else DN_NU(K, TI, 2, ca); } while (0)
+  if (l == 0 && !h_->fe && !h_->vark && !x0 && B >= h_->tune.tall_min_b) {
+    // level 0 of the constant-coefficient operator from zero, batched: the
+    // row march (segment height chosen as for the up kernel)
+    const int nf = h_->lev_n[0];
+    const int ow = 62 - 2 * (nu + (nz > 0 ? 1 : 0));
+    const int nstrips = (nf + ow - 1) / ow;
+    const bool seg32 = (int64_t)nstrips * ((nf + 15) / 16) * B > 8 * 4 * 256;
+    const int seg = seg32 ? 32 : 16;
+    const int nsegs = (nf + seg - 1) / seg;
+    const int64_t units = (int64_t)nstrips * nsegs * B;
+    const dim3 gm((unsigned)((units + 3) / 4));
+#define DNM(NU, NZ, SEG) hipLaunchKernelGGL((k_down2d_march<NU, TI, TC, C, NZ, SEG>), gm, dim3(256), 0, st_, (const TI*)b.ptr, b.stride, (TI*)xout.ptr, xout.stride, (TC*)bc.ptr, bc.stride, op, nc, omega, nstrips, nsegs, units, ca, bs)
+#define DNM_Z(NU, SEG) do { if (nz == 0) DNM(NU, 0, SEG); else if (nz == 1) DNM(NU, 1, SEG); else DNM(NU, 2, SEG); } while (0)
+#define DNM_NU(SEG) do { if (nu == 1) DNM_Z(1, SEG); else if (nu == 2) DNM_Z(2, SEG); else DNM_Z(3, SEG); } while (0)
+    return typed1(1, [&](auto tc) {
+      using TC = decltype(tc);
+      if (seg32) DNM_NU(32); else DNM_NU(16);
+      return hipGetLastError();
+    });
+#undef DNM_NU
+#undef DNM_Z
+#undef DNM
+  }
   if (l == 0)
     return typed1(1, [&](auto tc) {
       using TC = decltype(tc);

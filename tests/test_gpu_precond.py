@@ -57,6 +57,29 @@ def test_apply_P_one_pass_gram_schmidt_matches_oracle(dim, n, s, nt, precision, 
     assert rel_err(z, precond.apply_preconditioner(ops, r)) <= tol
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-4)])
+@pytest.mark.parametrize("n,s,nt,nu", [(130, 3, 9, 2), (61, 3, 8, 1), (100, 2, 8, 3)])
+def test_apply_P_row_march_equals_tiles(precision, tol, n, s, nt, nu):
+    """The batched Theta-tilde solves (nt blocks per launch) run level 0 of
+    the constant-coefficient operator in the row-marching down and up
+    kernels once a launch has tall_min_b blocks; the down kernel also forms
+    Rana's coupling terms of stages 2 and 3.  tall_min_b = 2^30 keeps every
+    launch on the LDS tiles.  The kernels apply the same arithmetic to every
+    node and the reductions run in a fixed order, so P-tilde is the same
+    bit for bit; the FP64 oracle checks the march."""
+    require_gpu()
+    p, hp, ops, rng = _pair(2, n, s, nt, precision=precision, nu=nu, seed=7 * n)
+    r = rng.standard_normal(p.U)
+    announce("apply_P row march vs tiles", precision, n, s, nt, "nu", nu)
+    hp.set_launch_shapes(1, 0)
+    z_march = to_host(hp.apply_P(to_dev(r)))
+    hp.set_launch_shapes(1 << 30, 0)
+    z_tiles = to_host(hp.apply_P(to_dev(r)))
+    assert np.array_equal(z_march, z_tiles)
+    ref = precond.apply_preconditioner(ops, r)
+    assert rel_err(z_march, ref) <= tol, rel_err(z_march, ref)
+
+
 @pytest.mark.parametrize("dim,n,nt", [(2, 40, 12), (3, 14, 8)])
 def test_solve_with_the_benchmark_settings_reaches_stepping(dim, n, nt):
     """One-pass Gram-Schmidt, one inner iteration in S-tilde and on MGRIT's
