@@ -887,6 +887,24 @@ __global__ __launch_bounds__(256) void k_up2d(const TF* __restrict__ xin, int64_
 // 2m use coarse rows m - 1 (weight 1, resp. 1/2) and m (0, resp. 1/2).
 constexpr int MPD = 4;    // rows fetched ahead
 
+// x neighbours of the march: the value of lane - 1 (wave_shr:1) and of lane
+// + 1 (wave_shl:1) as DPP moves, with no LDS traffic; the lane without a
+// source keeps its own value.
+__device__ __forceinline__ int dpp_left(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_right(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_left(__float_as_int(v))); }
+__device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp_right(__float_as_int(v))); }
+__device__ __forceinline__ double from_left(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_left((int)(b & 0xffffffffll)), hi = dpp_left((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double from_right(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_right((int)(b & 0xffffffffll)), hi = dpp_right((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 template <int NU, class TF, class TE, class C, int SEG>
 __global__ __launch_bounds__(256) void k_up2d_march(const TF* __restrict__ xin, int64_t sxi, const TE* __restrict__ e,
                                                     int64_t se, const TF* __restrict__ b, int64_t sb,
@@ -978,7 +996,7 @@ __global__ __launch_bounds__(256) void k_up2d_march(const TF* __restrict__ xin, 
     for (int k = 1; k <= NU; ++k) {
       const C* w = X[k - 1];
       const C c = w[1];
-      const C xl = __shfl_up(c, 1), xr = __shfl_down(c, 1);
+      const C xl = from_left(c), xr = from_right(c);
       const C Ax = c + op.a * op.ih2 * (C(4) * c - xl - xr - w[0] - w[2]);
       const C v = c + idc * (Bw[k] - Ax);
       const int jr = j - k;
@@ -1077,7 +1095,7 @@ __global__ __launch_bounds__(256) void k_down2d_march(const TF* __restrict__ b, 
       Zw[l][1] = Zw[l][2];
       Zw[l][2] = inr(r + 1) ? qz[l][q] : C(0);
       const C c0 = Zw[l][1];
-      const C zl = __shfl_up(c0, 1), zr = __shfl_down(c0, 1);
+      const C zl = from_left(c0), zr = from_right(c0);
       const C kz = op.ih2 * (C(4) * c0 - zl - zr - Zw[l][0] - Zw[l][2]);
       acc -= cpl.c[l] * kz;
     }
@@ -1097,7 +1115,7 @@ __global__ __launch_bounds__(256) void k_down2d_march(const TF* __restrict__ b, 
     for (int k = 1; k <= S; ++k) {
       const C* w = X[k - 1];
       const C c = w[1];
-      const C xl = __shfl_up(c, 1), xr = __shfl_down(c, 1);
+      const C xl = from_left(c), xr = from_right(c);
       const C Ax = c + op.a * op.ih2 * (C(4) * c - xl - xr - w[0] - w[2]);
       const C v = c + idc * (Bw[k] - Ax);
       X[k][0] = X[k][1];
@@ -1110,7 +1128,7 @@ __global__ __launch_bounds__(256) void k_down2d_march(const TF* __restrict__ b, 
     {
       const C* w = X[S];
       const C c = w[1];
-      const C xl = __shfl_up(c, 1), xr = __shfl_down(c, 1);
+      const C xl = from_left(c), xr = from_right(c);
       const C Ax = c + op.a * op.ih2 * (C(4) * c - xl - xr - w[0] - w[2]);
       Rw[0] = Rw[1];
       Rw[1] = Rw[2];
@@ -1120,9 +1138,9 @@ __global__ __launch_bounds__(256) void k_down2d_march(const TF* __restrict__ b, 
     const int rr = r - NU;
     if (rr >= 2 && !(rr & 1)) {   // wave-uniform
       const int J = rr / 2 - 1;
-      const C rl = __shfl_up(Rw[1], 1), rrt = __shfl_down(Rw[1], 1);
-      const C dl = __shfl_up(Rw[0], 1), dr = __shfl_down(Rw[0], 1);
-      const C ul = __shfl_up(Rw[2], 1), ur = __shfl_down(Rw[2], 1);
+      const C rl = from_left(Rw[1]), rrt = from_right(Rw[1]);
+      const C dl = from_left(Rw[0]), dr = from_right(Rw[0]);
+      const C ul = from_left(Rw[2]), ur = from_right(Rw[2]);
       const C v = C(0.25) * bscale * (Rw[1] + C(0.5) * (rl + rrt + Rw[0] + Rw[2]) + C(0.25) * (dl + dr + ul + ur));
       if (cown && J < nc && 2 * J + 1 >= j0 && 2 * J + 1 < j1) st<TC, C>(bco + (int64_t)J * nc, v);
     }
