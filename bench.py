@@ -304,21 +304,33 @@ def vcycle_kernels(hp, precision, reps):
 
     nu1 = hp.options["nu1"]
 
+    def march_shape(label, B):
+        """(strips, rows of a segment, waves at 16-row segments) of the
+        row-marching kernels for this launch: one wave per strip of
+        64 - 2 nu2 (up) or 62 - 2 nu1 (down) columns."""
+        name, lev = label.split("@")
+        nf = side[int(lev)]
+        ow = 64 - 2 * nu2 if name == "k_up2d" else 62 - 2 * nu1
+        strips = -(-nf // ow)
+        waves16 = strips * -(-nf // 16) * B
+        return strips, (32 if waves16 > 8 * 4 * 256 else 16), waves16
+
     def marches(label, B):
         """Level 0 of the constant-coefficient 2D operator from tall_min
-        blocks runs the row-marching kernels (the profiled cycle starts
-        from zero and forms no coupling terms)."""
-        return (label in ("k_up2d@0", "k_down2d@0") and hp.dim == 2 and hp.disc == "fd"
-                and hp._kappa is None and B >= tall_min)
+        blocks runs the row-marching kernels (the profiled cycle starts from
+        zero and forms no coupling terms), and so do its tensor levels when
+        the launch has 4 waves per SIMD at 16-row segments."""
+        name, lev = label.split("@")
+        if name not in ("k_up2d", "k_down2d") or hp.dim != 2 or hp.disc != "fd" or hp._kappa is not None:
+            return False
+        if B < tall_min:
+            return False
+        return lev == "0" or march_shape(label, B)[2] >= 4 * 4 * 256
 
     def march_grid(label, B):
-        """Workgroups of k_up2d_march / k_down2d_march: four waves, one wave
-        per strip of 64 - 2 nu2 (up) or 62 - 2 nu1 (down) columns and 16 or
-        32 rows of one block."""
-        nf = side[0]
-        ow = 64 - 2 * nu2 if label.startswith("k_up2d") else 62 - 2 * nu1
-        strips = -(-nf // ow)
-        seg = 32 if strips * -(-nf // 16) * B > 8 * 4 * 256 else 16
+        """Workgroups of a row-marching launch: four waves each."""
+        strips, seg, _ = march_shape(label, B)
+        nf = side[int(label.split("@")[1])]
         return -(-(strips * -(-nf // seg) * B) // 4)
 
     def grid_workgroups(label, B):
@@ -365,7 +377,7 @@ def vcycle_kernels(hp, precision, reps):
     def symbol(label, B):
         name, lev = label.split("@")
         if marches(label, B):
-            return name + "_march<level 0>"
+            return name + ("_march<level 0>" if lev == "0" else "_march<coarse levels>")
         sym = name + ("<level 0" if lev == "0" else "<coarse levels")
         if name in ("k_down2d", "k_up2d") and precision != "fp64":
             sym += ", tall tiles" if B >= tall_min else ", short tiles"
@@ -442,14 +454,13 @@ def _counter_rows(path, counter):
 
 
 def _kernel_matches(name, base, level0):
-    """name is an instantiation of the multigrid kernel `base` for level 0
-    (first template argument 0 or 1: the fine-grid kinds) or for the coarse
-    levels (2 or 3: tensor or stored-stencil Galerkin operators)."""
+    """name is an instantiation of the multigrid kernel `base` (tiled or
+    row-marching) for level 0 (first template argument 0 or 1: the fine-grid
+    kinds) or for the coarse levels (2 or 3: tensor or stored-stencil
+    Galerkin operators)."""
     i = name.find(base + "<")
     if i < 0:
         return False
-    if base.endswith("_march"):   # level 0 only
-        return level0
     kind = int(name[i + len(base) + 1:].split(",")[0])
     return (kind <= 1) == level0
 

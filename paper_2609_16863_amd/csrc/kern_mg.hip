@@ -889,7 +889,9 @@ constexpr int MPD = 4;    // rows fetched ahead
 
 // x neighbours of the march: the value of lane - 1 (wave_shr:1) and of lane
 // + 1 (wave_shl:1) as DPP moves, with no LDS traffic; the lane without a
-// source keeps its own value.
+// source keeps its own value.  An inactive source lane also leaves the
+// lane's own value, so these run with every lane of the wave active (never
+// under a lane-dependent condition).
 __device__ __forceinline__ int dpp_left(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
 __device__ __forceinline__ int dpp_right(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
 __device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_left(__float_as_int(v))); }
@@ -905,7 +907,75 @@ __device__ __forceinline__ double from_right(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-template <int NU, class TF, class TE, class C, int SEG>
+// The operator of a row-marching kernel at one lane's column g, with the
+// arithmetic of the tiles.  KIND_FINE: I + a K, K the 5-point Laplacian
+// over h^2.  KIND_TENSOR: the Galerkin level with coefficient
+// M_y(j, dj) (M + a T)_x(g, di) + a T_y(j, dj) M_x(g, di) on x(j + dj, g + di),
+// the 1D factors staged per column (this lane) and per row (a Row, fetched
+// with the row's other loads).  Ax takes the window of rows j - 1, j, j + 1.
+template <int KIND, class C>
+struct MarchOp;
+
+template <class C>
+struct MarchOp<KIND_FINE, C> {
+  struct Row {};
+  C s, idc;
+  __device__ MarchOp(const LevelOp<C>& op, C omega, int, bool)
+      : s(op.a * op.ih2), idc(omega / (C(1) + op.a * op.ih2 * C(4))) {}
+  __device__ Row row(const LevelOp<C>&, int) const { return {}; }
+  __device__ C Ax(const C* w, const Row&) const {
+    const C c = w[1];
+    const C xl = from_left(c), xr = from_right(c);
+    return c + s * (C(4) * c - xl - xr - w[0] - w[2]);
+  }
+  __device__ C inv_diag(const Row&) const { return idc; }
+};
+
+template <class C>
+struct MarchOp<KIND_TENSOR, C> {
+  struct Row { C m[3], t[3]; };   // M_y(j, j + d - 1), a T_y(j, j + d - 1)
+  C xa[3], xm[3];                 // (M + a T)_x(g, g + d - 1), M_x(g, g + d - 1)
+  C omega;
+  __device__ MarchOp(const LevelOp<C>& op, C om, int g, bool colin) : omega(om) {
+    const int gc = colin ? g : 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const C m = op.tri[d * op.n + gc], tt = op.tri[(3 + d) * op.n + gc];
+      xa[d] = colin ? m + op.a * tt : C(0);
+      xm[d] = colin ? m : C(0);
+    }
+  }
+  __device__ Row row(const LevelOp<C>& op, int j) const {
+    Row r;
+    const bool in = j >= 0 && j < op.n;
+    const int jc = in ? j : 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const C m = op.tri[d * op.n + jc], tt = op.tri[(3 + d) * op.n + jc];
+      r.m[d] = in ? m : C(0);
+      r.t[d] = in ? op.a * tt : C(0);
+    }
+    return r;
+  }
+  __device__ C Ax(const C* w, const Row& r) const {
+    C x[3][3];
+#pragma unroll
+    for (int dj = 0; dj < 3; ++dj) {
+      x[dj][0] = from_left(w[dj]);
+      x[dj][1] = w[dj];
+      x[dj][2] = from_right(w[dj]);
+    }
+    C acc = C(0);
+#pragma unroll
+    for (int dj = 0; dj < 3; ++dj)
+#pragma unroll
+      for (int di = 0; di < 3; ++di) acc += (r.m[dj] * xa[di] + r.t[dj] * xm[di]) * x[dj][di];
+    return acc;
+  }
+  __device__ C inv_diag(const Row& r) const { return omega / (r.m[1] * xa[1] + r.t[1] * xm[1]); }
+};
+
+template <int KIND, int NU, class TF, class TE, class C, int SEG>
 __global__ __launch_bounds__(256) void k_up2d_march(const TF* __restrict__ xin, int64_t sxi, const TE* __restrict__ e,
                                                     int64_t se, const TF* __restrict__ b, int64_t sb,
                                                     TF* __restrict__ xout, int64_t sxo, LevelOp<C> op, int nc,
@@ -931,7 +1001,8 @@ __global__ __launch_bounds__(256) void k_up2d_march(const TF* __restrict__ xin, 
   const TF* bi = b + inst * sb;
   const TE* ei = e + inst * se;
   TF* xo = xout + inst * sxo;
-  const C idc = omega / (C(1) + op.a * op.ih2 * C(4));
+  const MarchOp<KIND, C> mop(op, omega, g, colin);
+  using Row = typename MarchOp<KIND, C>::Row;
   // Loads are unconditional from a clamped in-bounds address and masked
   // afterwards, so that no branch (and no wait) separates a fetch from the
   // rows computed meanwhile.  Coarse values stay unscaled until used.
@@ -962,6 +1033,8 @@ __global__ __launch_bounds__(256) void k_up2d_march(const TF* __restrict__ xin, 
   C hlo = hrow(floor_half(jlo - 1)), hhi = hlo;
   C X[NU > 1 ? NU : 1][3];   // X[k]: sweep k at rows j - k - 2, j - k - 1, j - k
   C Bw[NU + 1];              // b at rows j, j - 1, .., j - NU
+  Row Rw[NU + 1];            // operator rows j, j - 1, .., j - NU
+  Row rnext = mop.row(op, jlo);   // operator rows are shared by every strip: one row ahead is enough
 #pragma unroll
   for (int k = 0; k < NU; ++k) X[k][0] = X[k][1] = X[k][2] = C(0);
 #pragma unroll
@@ -985,8 +1058,13 @@ __global__ __launch_bounds__(256) void k_up2d_march(const TF* __restrict__ xin, 
     const bool rin0 = colin && j >= 0 && j < n;
     const C x0 = rin0 ? qx[q] + pe : C(0);
 #pragma unroll
-    for (int k = NU; k > 0; --k) Bw[k] = Bw[k - 1];
+    for (int k = NU; k > 0; --k) {
+      Bw[k] = Bw[k - 1];
+      Rw[k] = Rw[k - 1];
+    }
     Bw[0] = qin[q] ? qb[q] : C(0);
+    Rw[0] = rnext;
+    if (t + 1 < ROWS) rnext = mop.row(op, j + 1);
     if (t + MPD < ROWS) fetch(j + MPD, q);
     X[0][0] = X[0][1];
     X[0][1] = X[0][2];
@@ -996,9 +1074,7 @@ __global__ __launch_bounds__(256) void k_up2d_march(const TF* __restrict__ xin, 
     for (int k = 1; k <= NU; ++k) {
       const C* w = X[k - 1];
       const C c = w[1];
-      const C xl = from_left(c), xr = from_right(c);
-      const C Ax = c + op.a * op.ih2 * (C(4) * c - xl - xr - w[0] - w[2]);
-      const C v = c + idc * (Bw[k] - Ax);
+      const C v = c + mop.inv_diag(Rw[k]) * (Bw[k] - mop.Ax(w, Rw[k]));
       const int jr = j - k;
       const bool rin = colin && jr >= 0 && jr < n;
       const C vk = rin ? v : C(0);
@@ -1026,15 +1102,18 @@ __global__ __launch_bounds__(256) void k_up2d_march(const TF* __restrict__ xin, 
 // NU rows below and NU + 1 above its SEG rows.  OW and SEG are even: strips
 // and segments start at even fine indices, so every coarse node 2I + 1 has
 // its whole stencil in the strip and segment that own it.
-template <int NU, class TF, class TC, class C, int NZ, int SEG>
+template <int KIND, int NU, class TF, class TC, class C, int NZ, int SEG>
 __global__ __launch_bounds__(256) void k_down2d_march(const TF* __restrict__ b, int64_t sb, TF* __restrict__ xout,
                                                       int64_t sxo, TC* __restrict__ bc, int64_t sbc, LevelOp<C> op,
                                                       int nc, C omega, int nstrips, int nsegs, int64_t units,
                                                       CplArgs<TF, C> cpl, C bscale) {
+  static_assert(NZ == 0 || KIND == KIND_FINE, "coupling terms are formed on the finite-difference level 0");
   constexpr int S = NU - 1;   // window sweeps after the pointwise one
   constexpr int HC = NU + (NZ > 0 ? 1 : 0), OW = 62 - 2 * HC;
   constexpr int ROWS = SEG + 2 * NU + 1;
-  constexpr int PD = NZ == 0 ? 2 * MPD : MPD;   // rows fetched ahead (one load per row without coupling)
+  // rows fetched ahead: twice as many with one load per row (no coupling
+  // terms, 5-point operator)
+  constexpr int PD = (NZ == 0 && KIND == KIND_FINE) ? 2 * MPD : MPD;
   const int64_t u = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * 4 + (threadIdx.x >> 6);
   if (u >= units) return;   // whole wave
   const int lane = threadIdx.x & 63;
@@ -1052,7 +1131,8 @@ __global__ __launch_bounds__(256) void k_down2d_march(const TF* __restrict__ b, 
   const TF* bi = b + inst * sb;
   TF* xo = xout + inst * sxo;
   TC* bco = bc + inst * sbc + (cown ? (g - 1) / 2 : 0);
-  const C idc = omega / (C(1) + op.a * op.ih2 * C(4));
+  const MarchOp<KIND, C> mop(op, omega, g, colin);
+  using Row = typename MarchOp<KIND, C>::Row;
   const TF* zi[NZ > 0 ? NZ : 1];
 #pragma unroll
   for (int l = 0; l < NZ; ++l) zi[l] = cpl.z + inst * cpl.sz + l * cpl.zs;
@@ -1076,6 +1156,8 @@ __global__ __launch_bounds__(256) void k_down2d_march(const TF* __restrict__ b, 
   }
   C X[S + 1][3];   // X[k]: sweep k (0: the pointwise one) at rows r - k - 2 .. r - k
   C Bw[S + 2];     // right-hand side at rows r, r - 1, .., r - S - 1
+  Row Ow[S + 2];   // operator rows r, r - 1, .., r - S - 1
+  Row rnext = mop.row(op, jlo);
   C Rw[3];         // residual at rows r - NU - 2 .. r - NU
 #pragma unroll
   for (int k = 0; k <= S; ++k) X[k][0] = X[k][1] = X[k][2] = C(0);
@@ -1101,23 +1183,27 @@ __global__ __launch_bounds__(256) void k_down2d_march(const TF* __restrict__ b, 
     }
     const bool din = inr(r);
     const C bb = din ? acc : C(0);
+    const Row orow = rnext;   // operator rows are shared by every strip: one row ahead is enough
+    if (t + 1 < ROWS) rnext = mop.row(op, r + 1);
     if (t + PD < ROWS) fetch(r + PD, q);
     if constexpr (NZ > 0)
       if (own_r) st<TF, C>(cpl.out + inst * cpl.so + (int64_t)r * n + g, bb);
 #pragma unroll
-    for (int k = S + 1; k > 0; --k) Bw[k] = Bw[k - 1];
+    for (int k = S + 1; k > 0; --k) {
+      Bw[k] = Bw[k - 1];
+      Ow[k] = Ow[k - 1];
+    }
     Bw[0] = bb;
+    Ow[0] = orow;
     X[0][0] = X[0][1];
     X[0][1] = X[0][2];
-    X[0][2] = din ? idc * bb : C(0);
+    X[0][2] = din ? mop.inv_diag(Ow[0]) * bb : C(0);
     // sweep k on row r - k from the window of sweep k - 1
 #pragma unroll
     for (int k = 1; k <= S; ++k) {
       const C* w = X[k - 1];
       const C c = w[1];
-      const C xl = from_left(c), xr = from_right(c);
-      const C Ax = c + op.a * op.ih2 * (C(4) * c - xl - xr - w[0] - w[2]);
-      const C v = c + idc * (Bw[k] - Ax);
+      const C v = c + mop.inv_diag(Ow[k]) * (Bw[k] - mop.Ax(w, Ow[k]));
       X[k][0] = X[k][1];
       X[k][1] = X[k][2];
       X[k][2] = inr(r - k) ? v : C(0);
@@ -1125,15 +1211,11 @@ __global__ __launch_bounds__(256) void k_down2d_march(const TF* __restrict__ b, 
     // the smoothed iterate of row r - S
     if (own && r - S >= j0 && r - S < j1) st<TF, C>(xo + (int64_t)(r - S) * n + g, X[S][2]);
     // residual on row r - NU
-    {
-      const C* w = X[S];
-      const C c = w[1];
-      const C xl = from_left(c), xr = from_right(c);
-      const C Ax = c + op.a * op.ih2 * (C(4) * c - xl - xr - w[0] - w[2]);
-      Rw[0] = Rw[1];
-      Rw[1] = Rw[2];
-      Rw[2] = inr(r - NU) ? Bw[S + 1] - Ax : C(0);
-    }
+    // (Ax outside the select: its DPP moves need every lane active)
+    const C ax = mop.Ax(X[S], Ow[S + 1]);
+    Rw[0] = Rw[1];
+    Rw[1] = Rw[2];
+    Rw[2] = inr(r - NU) ? Bw[S + 1] - ax : C(0);
     // restriction onto coarse row J = (r - NU) / 2 - 1 (fine row 2J + 1)
     const int rr = r - NU;
     if (rr >= 2 && !(rr & 1)) {   // wave-uniform
@@ -2249,27 +2331,50 @@ hipError_t Multigrid<TI, TM>::down2d(int l, int stage, Vec b, const void* x0, in
 #define DN(K, NU, TF, NZ, CA) do { if (tall) DN_T(K, NU, TF, NZ, CA, TY0L); else DN_T(K, NU, TF, NZ, CA, TCY); } while (0)
 #define DN_NU(K, TF, NZ, CA) do { if (nu == 1) DN(K, 1, TF, NZ, CA); else if (nu == 2) DN(K, 2, TF, NZ, CA); else DN(K, 3, TF, NZ, CA); } while (0)
 #define DN_Z(K) do { if (nz == 0) DN_NU(K, TI, 0, ca); else if (nz == 1) DN_NU(K, TI, 1, ca); else DN_NU(K, TI, 2, ca); } while (0)
-  if (l == 0 && !h_->fe && !h_->vark && !x0 && B >= h_->tune.tall_min_b) {
-    // level 0 of the constant-coefficient operator from zero, batched: the
-    // row march (segment height chosen as for the up kernel)
-    const int nf = h_->lev_n[0];
-    const int ow = 62 - 2 * (nu + (nz > 0 ? 1 : 0));
-    const int nstrips = (nf + ow - 1) / ow;
-    const bool seg32 = (int64_t)nstrips * ((nf + 15) / 16) * B > 8 * 4 * 256;
+  // batched cycles from zero: the row march on level 0 of the
+  // constant-coefficient operator (with Rana's coupling terms) and on the
+  // tensor levels (Q1 level 0, Galerkin levels of constant kappa) when
+  // they give the chip 4 waves per SIMD at least (a tensor wave's chain of
+  // rows is long: fewer waves leave it latency-bound, where the tiles are
+  // faster); 16-row segments while one round of waves does not fill the
+  // chip (8 per SIMD), 32-row ones (less halo) beyond
+  const bool fine_const = l == 0 && !h_->fe && !h_->vark;
+  const bool tensor = (l == 0 && h_->fe) || (l > 0 && !h_->vark);
+  const int nf = h_->lev_n[l];
+  const int nzm = fine_const ? nz : 0;
+  const int ow = 62 - 2 * (nu + (nzm > 0 ? 1 : 0));
+  const int nstrips = (nf + ow - 1) / ow;
+  const int64_t waves16 = (int64_t)nstrips * ((nf + 15) / 16) * B;
+  if (!x0 && B >= h_->tune.tall_min_b && (fine_const || (tensor && waves16 >= 4 * 4 * 256))) {
+    const bool seg32 = waves16 > 8 * 4 * 256;
     const int seg = seg32 ? 32 : 16;
     const int nsegs = (nf + seg - 1) / seg;
     const int64_t units = (int64_t)nstrips * nsegs * B;
     const dim3 gm((unsigned)((units + 3) / 4));
-#define DNM(NU, NZ, SEG) hipLaunchKernelGGL((k_down2d_march<NU, TI, TC, C, NZ, SEG>), gm, dim3(256), 0, st_, (const TI*)b.ptr, b.stride, (TI*)xout.ptr, xout.stride, (TC*)bc.ptr, bc.stride, op, nc, omega, nstrips, nsegs, units, ca, bs)
-#define DNM_Z(NU, SEG) do { if (nz == 0) DNM(NU, 0, SEG); else if (nz == 1) DNM(NU, 1, SEG); else DNM(NU, 2, SEG); } while (0)
-#define DNM_NU(SEG) do { if (nu == 1) DNM_Z(1, SEG); else if (nu == 2) DNM_Z(2, SEG); else DNM_Z(3, SEG); } while (0)
-    return typed1(1, [&](auto tc) {
+#define DNM(K, NU, TF, NZ, CA, SEG) hipLaunchKernelGGL((k_down2d_march<K, NU, TF, TC, C, NZ, SEG>), gm, dim3(256), 0, st_, (const TF*)b.ptr, b.stride, (TF*)xout.ptr, xout.stride, (TC*)bc.ptr, bc.stride, op, nc, omega, nstrips, nsegs, units, CA, bs)
+#define DNM_S(K, NU, TF, NZ, CA) do { if (seg32) DNM(K, NU, TF, NZ, CA, 32); else DNM(K, NU, TF, NZ, CA, 16); } while (0)
+#define DNM_NU(K, TF, NZ, CA) do { if (nu == 1) DNM_S(K, 1, TF, NZ, CA); else if (nu == 2) DNM_S(K, 2, TF, NZ, CA); else DNM_S(K, 3, TF, NZ, CA); } while (0)
+    if (fine_const)
+      return typed1(1, [&](auto tc) {
+        using TC = decltype(tc);
+        if (nz == 0) DNM_NU(KIND_FINE, TI, 0, ca); else if (nz == 1) DNM_NU(KIND_FINE, TI, 1, ca); else DNM_NU(KIND_FINE, TI, 2, ca);
+        return hipGetLastError();
+      });
+    if (l == 0)
+      return typed1(1, [&](auto tc) {
+        using TC = decltype(tc);
+        DNM_NU(KIND_TENSOR, TI, 0, ca);
+        return hipGetLastError();
+      });
+    return typed2(l, [&](auto tf, auto tc) {
+      using TF = decltype(tf);
       using TC = decltype(tc);
-      if (seg32) DNM_NU(32); else DNM_NU(16);
+      CplArgs<TF, C> cm{};
+      DNM_NU(KIND_TENSOR, TF, 0, cm);
       return hipGetLastError();
     });
 #undef DNM_NU
-#undef DNM_Z
+#undef DNM_S
 #undef DNM
   }
   if (l == 0)
@@ -2310,27 +2415,36 @@ hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec
 #define UP_T(K, NU, TF, TYV) hipLaunchKernelGGL((k_up2d<K, NU, TF, TC, C, TYV>), g, dim3(256), 0, st_, (const TF*)xin.ptr, xin.stride, (const TC*)ec.ptr, ec.stride, (const TF*)b.ptr, b.stride, (TF*)xout.ptr, xout.stride, op, nc, omega, gx, gy, es)
 #define UP(K, NU, TF) do { if (tall) UP_T(K, NU, TF, TY0L); else UP_T(K, NU, TF, TCY); } while (0)
 #define UP_NU(K, TF) do { if (nu == 1) UP(K, 1, TF); else if (nu == 2) UP(K, 2, TF); else UP(K, 3, TF); } while (0)
-  if (l == 0 && !h_->fe && !h_->vark && B >= h_->tune.tall_min_b) {
-    // level 0 of the constant-coefficient operator, batched: the row march
-    // (the values of the tiles, without their LDS round trips and barriers);
-    // 16-row segments while one round of waves does not fill the chip
-    // (8 per SIMD), 32-row ones (less halo) beyond
-    const int nf = h_->lev_n[0];
-    const int ow = 64 - 2 * nu;
-    const int nstrips = (nf + ow - 1) / ow;
-    const bool seg32 = (int64_t)nstrips * ((nf + 15) / 16) * B > 8 * 4 * 256;
-    const int seg = seg32 ? 32 : 16;
-    const int nsegs = (nf + seg - 1) / seg;
+  // batched: the row march on level 0 of the constant-coefficient operator
+  // and on the tensor levels (the choice and segment height as in down2d)
+  const bool fine_const = l == 0 && !h_->fe && !h_->vark;
+  const bool tensor = (l == 0 && h_->fe) || (l > 0 && !h_->vark);
+  const int nf = h_->lev_n[l];
+  const int ow = 64 - 2 * nu;
+  const int nstrips = (nf + ow - 1) / ow;
+  const int64_t waves16 = (int64_t)nstrips * ((nf + 15) / 16) * B;
+  if (B >= h_->tune.tall_min_b && (fine_const || (tensor && waves16 >= 4 * 4 * 256))) {
+    const bool seg32 = waves16 > 8 * 4 * 256;
+    const int nsegs = (nf + (seg32 ? 32 : 16) - 1) / (seg32 ? 32 : 16);
     const int64_t units = (int64_t)nstrips * nsegs * B;
     const dim3 gm((unsigned)((units + 3) / 4));
-#define UPM(NU, SEG) hipLaunchKernelGGL((k_up2d_march<NU, TI, TC, C, SEG>), gm, dim3(256), 0, st_, (const TI*)xin.ptr, xin.stride, (const TC*)ec.ptr, ec.stride, (const TI*)b.ptr, b.stride, (TI*)xout.ptr, xout.stride, op, nc, omega, nstrips, nsegs, units, es)
-#define UPM_NU(SEG) do { if (nu == 1) UPM(1, SEG); else if (nu == 2) UPM(2, SEG); else UPM(3, SEG); } while (0)
-    return typed1(1, [&](auto tc) {
+#define UPM(K, NU, TF, SEG) hipLaunchKernelGGL((k_up2d_march<K, NU, TF, TC, C, SEG>), gm, dim3(256), 0, st_, (const TF*)xin.ptr, xin.stride, (const TC*)ec.ptr, ec.stride, (const TF*)b.ptr, b.stride, (TF*)xout.ptr, xout.stride, op, nc, omega, nstrips, nsegs, units, es)
+#define UPM_S(K, NU, TF) do { if (seg32) UPM(K, NU, TF, 32); else UPM(K, NU, TF, 16); } while (0)
+#define UPM_NU(K, TF) do { if (nu == 1) UPM_S(K, 1, TF); else if (nu == 2) UPM_S(K, 2, TF); else UPM_S(K, 3, TF); } while (0)
+    if (l == 0)
+      return typed1(1, [&](auto tc) {
+        using TC = decltype(tc);
+        if (fine_const) UPM_NU(KIND_FINE, TI); else UPM_NU(KIND_TENSOR, TI);
+        return hipGetLastError();
+      });
+    return typed2(l, [&](auto tf, auto tc) {
+      using TF = decltype(tf);
       using TC = decltype(tc);
-      if (seg32) UPM_NU(32); else UPM_NU(16);
+      UPM_NU(KIND_TENSOR, TF);
       return hipGetLastError();
     });
 #undef UPM_NU
+#undef UPM_S
 #undef UPM
   }
   if (l == 0)

@@ -137,14 +137,15 @@ def test_apply_mg_fp32_batched_tiles_equal_single_blocks(n, vark):
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
 @pytest.mark.parametrize("n,nu,nt", [(40, 1, 4), (61, 3, 4), (150, 2, 9), (515, 2, 4), (512, 2, 64)])
 def test_apply_mg_level0_row_march_equals_tiles(precision, tol, n, nu, nt):
-    """From tall_min_b blocks on, the up kernel of level 0 of the
-    constant-coefficient 2D operator is the row march (one wave per strip of
-    64 - 2 nu columns and 16 or 32 rows, register windows instead of LDS
-    tiles); tall_min_b = 2^30 sends every launch to the tiles.  Both apply
-    the same arithmetic to every node, so the cycles agree bit for bit:
-    one strip (40), the ragged last strip and segment (61, 150, 515), nu = 1
-    and 3, and 32-row segments (512 with 64 blocks).  Block 0 is checked
-    against the oracle."""
+    """From tall_min_b blocks on, level 0 of the constant-coefficient 2D
+    operator runs the row-marching down and up kernels (one wave per strip
+    of columns and 16 or 32 rows, register windows instead of LDS tiles),
+    and so do its tensor Galerkin levels when a launch has 4 waves per SIMD
+    (level 1 of 512^2 with 64 blocks); tall_min_b = 2^30 sends every launch
+    to the tiles.  Both apply the same arithmetic to every node, so the
+    cycles agree bit for bit: one strip (40), the ragged last strip and
+    segment (61, 150, 515), nu = 1 and 3, and 32-row segments (512 with 64
+    blocks).  Block 0 is checked against the oracle."""
     require_gpu()
     from paper_2609_16863_amd import HeatProblem
     dim, s = 2, 2
@@ -162,6 +163,28 @@ def test_apply_mg_level0_row_march_equals_tiles(precision, tol, n, nu, nt):
     assert np.array_equal(z_march, z_tiles)
     ref = _oracle(p, False, 1, r[:1], 2, nu=nu)
     assert rel_err(z_march[:1], ref) <= tol, rel_err(z_march[:1], ref)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_apply_mg_q1_level0_row_march_equals_tiles(precision):
+    """Q1 elements: level 0 is the tensor operator M1 (x) M1 + a (T (x) M1 +
+    M1 (x) T); with 64 blocks of 255^2 a launch has 4 waves per SIMD, so
+    level 0 runs the tensor row march.  It equals the tiles bit for bit."""
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    n, s, nt = 255, 2, 64
+    hp = HeatProblem(2, n, s, nt, 1.0, disc="q1", length=2.0, precision=precision)
+    rng = np.random.default_rng(41)
+    r = rng.standard_normal((nt, n * n))
+    if precision == "fp32":
+        r = r.astype(np.float32).astype(np.float64)
+    announce("apply_mg q1 row march vs tiles", precision, n, "blocks", nt)
+    hp.set_launch_shapes(1, 0)
+    z_march = _run(hp, r, 1, 1, False)
+    hp.set_launch_shapes(1 << 30, 0)
+    z_tiles = _run(hp, r, 1, 1, False)
+    assert np.isfinite(z_march).all()
+    assert np.array_equal(z_march, z_tiles)
 
 
 # Variable diffusivity: coarse levels are the Galerkin products R A P of the
