@@ -296,6 +296,19 @@ def vcycle_kernels(hp, precision, reps):
             return pl[lev] * 3 * nodes[lev] + pl[lev + 1] * nodes[lev + 1]
         if name in ("k_tail_fast", "k_tail"):
             return 2 * pl[lev] * nodes[lev]
+        if name == "k_down3d_march":   # reads b, writes x2 and r
+            return 3 * pl[lev] * nodes[lev]
+        if name == "k_up3d_march":     # reads x2, b and the correction, writes x
+            return 3 * pl[lev] * nodes[lev] + pl[lev + 1] * nodes[lev + 1]
+        if name == "k_restrict":       # reads r, writes b_{l+1} (and x_{l+1} when that level sweeps)
+            first_sweep = lev + 2 < len(nodes)
+            return pl[lev] * nodes[lev] + (2 if first_sweep else 1) * pl[lev + 1] * nodes[lev + 1]
+        if name == "k_residual":       # reads x and b, writes r
+            return 3 * pl[lev] * nodes[lev]
+        if name == "k_smooth":         # reads x and b, writes x (zero-start sweeps of the coarse
+            return 3 * pl[lev] * nodes[lev]   # levels are formed in the restriction)
+        if name == "k_prolong":        # reads x and the correction, writes x
+            return 2 * pl[lev] * nodes[lev] + pl[lev + 1] * nodes[lev + 1]
         return None
 
     tall_min = hp.tune_state["tall_min_b"] if hp.tune_state else 8
@@ -339,6 +352,15 @@ def vcycle_kernels(hp, precision, reps):
         (short) or 16 x 16 (tall) coarse nodes, 256 threads each, per block;
         the tail runs one workgroup per block."""
         name, lev = label.split("@")
+        if name in ("k_down3d_march", "k_up3d_march"):
+            # 32 x 32-thread tiles with 28 x 28 cores, chunks of 32 planes
+            # (16 when that leaves under 512 workgroups)
+            nf = side[int(lev)]
+            ntx = -(-nf // 28)
+            zlen = nf if nf < 32 else 32
+            if ntx * ntx * -(-nf // zlen) * B < 512 and nf > 16:
+                zlen = 16
+            return ntx * ntx * -(-nf // zlen) * B
         if hp.dim != 2:
             return None
         if marches(label, B):

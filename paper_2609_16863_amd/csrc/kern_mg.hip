@@ -154,7 +154,19 @@ __global__ __launch_bounds__(TPB) void k_smooth(const T* __restrict__ xin, int64
   node_coords<DIM>(p, op.n, i, j, k);
   const C bp = ld<T, C>(b + inst * sb + p);
   C out;
-  if (zero_init) {
+  if constexpr (KIND == KIND_FINE) {
+    // constant diagonal: the weighted inverse omega / d multiplies (the
+    // form the 3D z-marches hoist out of their plane loop)
+    const C wd = omega / level_diag<DIM, KIND, C>(op, p, i, j, k);
+    if (zero_init) {
+      out = wd * bp;
+    } else {
+      const T* x = xin + inst * sxin;
+      C Ax, d;
+      level_apply<DIM, KIND, T, C>(x, op, p, i, j, k, Ax, d);
+      out = ld<T, C>(x + p) + wd * (bp - Ax);
+    }
+  } else if (zero_init) {
     out = omega * bp / level_diag<DIM, KIND, C>(op, p, i, j, k);
   } else {
     const T* x = xin + inst * sxin;
@@ -1932,6 +1944,289 @@ int tail_fast_layout(TailFastArgs<C>& ta, int nls) {
   return ta.ocw + 4 * TF_NCN;
 }
 
+// ---------------------------------------------------------------------------
+// 3D level 0 (constant kappa) as z-marches.  A workgroup owns a 32 x 32
+// thread tile of (x, y) columns -- its 28 x 28 core plus a two-node halo --
+// and walks a chunk of z-planes.  Each plane step runs three pipelined
+// stages (stage 2 on the plane one behind stage 1, stage 3 two behind); a
+// stage's z-neighbours stay in the thread's registers, its (x, y)-neighbours
+// come from the previous step's plane in LDS (two slots per stage, one
+// barrier per step).  Every stencil application shrinks the valid region by
+// one node, so the halo rings compute values only the core consumes.  The
+// arithmetic is that of k_smooth / k_residual / k_prolong, node by node.
+// ---------------------------------------------------------------------------
+constexpr int M3_T = 32;          // threads per tile side
+constexpr int M3_H = 2;           // halo width
+constexpr int M3_C = M3_T - 2 * M3_H;   // core width
+
+struct March3Geo {
+  int n, ntx, nz, zlen;   // grid side, tiles per side, z-chunks, planes per chunk
+};
+
+// Tile, chunk and thread coordinates of this workgroup.  Logical tiles are
+// spread so each XCD walks a contiguous range (xcd_tile).
+struct March3Pos {
+  int i, j, z0, z1;
+  bool inside, core;
+  int tx, ty;
+  __device__ March3Pos(const March3Geo& g) {
+    const int G = g.ntx * g.ntx * g.nz;
+    const int t = xcd_tile((int)blockIdx.x, G);
+    const int zc = t / (g.ntx * g.ntx);
+    const int r = t - zc * g.ntx * g.ntx;
+    const int by = r / g.ntx, bx = r - by * g.ntx;
+    tx = (int)threadIdx.x & (M3_T - 1);
+    ty = (int)threadIdx.x / M3_T;
+    i = bx * M3_C - M3_H + tx;
+    j = by * M3_C - M3_H + ty;
+    z0 = zc * g.zlen;
+    z1 = z0 + g.zlen < g.n ? z0 + g.zlen : g.n;
+    inside = i >= 0 && i < g.n && j >= 0 && j < g.n;
+    core = inside && tx >= M3_H && tx < M3_T - M3_H && ty >= M3_H && ty < M3_T - M3_H;
+  }
+};
+
+// h^2 K at the thread's node of plane slot s: (x, y)-neighbours from the
+// LDS plane (the tile's edge threads read themselves: their results are
+// never used), z-neighbours zm, zp from registers.  Same expression as
+// stencil_K (values past the grid are the zeros the neighbours stored).
+template <class C>
+__device__ __forceinline__ C m3_k(const C* pl, int tx, int ty, C c0, C zm, C zp) {
+  const int xm = tx > 0 ? tx - 1 : tx, xp = tx < M3_T - 1 ? tx + 1 : tx;
+  const int ym = ty > 0 ? ty - 1 : ty, yp = ty < M3_T - 1 ? ty + 1 : ty;
+  C acc = C(6) * c0 - pl[ty * M3_T + xm] - pl[ty * M3_T + xp] - pl[ym * M3_T + tx] - pl[yp * M3_T + tx];
+  acc -= zm + zp;
+  return acc;
+}
+
+// Planes are loaded PF steps before their first stage uses them (a ring of
+// registers), so each step's global loads overlap the steps before it.
+constexpr int M3_PF_DOWN = 4;
+constexpr int M3_PF_UP = 3;   // FP64 takes 2 (more planes in flight spill registers)
+
+// Zero-start pre-smoothing (two weighted Jacobi sweeps, the first
+// pointwise) and the residual: x2 -> xout, r = b - A x2 -> rout.
+template <class T, class C>
+__global__ __launch_bounds__(M3_T * M3_T) void k_down3d_march(const T* __restrict__ b, int64_t sb,
+                                                             T* __restrict__ xout, int64_t sx,
+                                                             T* __restrict__ rout, int64_t sr, March3Geo g,
+                                                             LevelOp<C> op, C omega) {
+  constexpr int PF = M3_PF_DOWN;
+  __shared__ C s1[2][M3_T * M3_T];   // x1 planes
+  __shared__ C s2[2][M3_T * M3_T];   // x2 planes
+  const March3Pos m(g);
+  const int64_t inst = blockIdx.y;
+  const int n = g.n;
+  const int64_t nn = (int64_t)n * n;
+  const int64_t col = (int64_t)(m.inside ? m.j : 0) * n + (m.inside ? m.i : 0);
+  const T* bi = b + inst * sb + col;
+  T* xo = xout + inst * sx + col;
+  T* ro = rout + inst * sr + col;
+  const C wd = omega / level_diag<3, KIND_FINE, C>(op, 0, 0, 0, 0);
+  const int me = m.ty * M3_T + m.tx;
+  const int qlast = m.z1 + 1;
+  auto load_b = [&](int q) { return (m.inside && q >= 0 && q < n && q <= qlast) ? ld<T, C>(bi + (int64_t)q * nn) : C(0); };
+  C pb[PF];   // b of planes q .. q + PF - 1
+#pragma unroll
+  for (int u = 0; u < PF; ++u) pb[u] = load_b(m.z0 - 2 + u);
+  // register windows: b at q-1, q-2; x1 at q-2, q-1, q; x2 at q-3, q-2, q-1
+  C b1 = C(0), b2 = C(0), x1a = C(0), x1b = C(0), x2a = C(0), x2b = C(0);
+  for (int q = m.z0 - 2; q <= qlast; ++q) {
+    const int sl = q & 1;
+    const C bq = pb[0];
+#pragma unroll
+    for (int u = 0; u + 1 < PF; ++u) pb[u] = pb[u + 1];
+    pb[PF - 1] = load_b(q + PF);
+    // stage 1, plane q: x1 = omega b / d
+    const bool in1 = m.inside && q >= 0 && q < n;
+    const C x1q = in1 ? wd * bq : C(0);
+    s1[sl][me] = x1q;
+    // stage 2, plane q - 1: x2 = x1 + omega (b - A x1) / d
+    const int p2 = q - 1;
+    C x2q = C(0);
+    if (m.inside && p2 >= 0 && p2 < n && p2 >= m.z0 - 1) {
+      const C kx = m3_k(s1[sl ^ 1], m.tx, m.ty, x1b, x1a, x1q);
+      const C Ax = x1b + op.a * op.ih2 * kx;
+      x2q = x1b + wd * (b1 - Ax);
+      if (m.core && p2 >= m.z0 && p2 < m.z1) st<T, C>(xo + (int64_t)p2 * nn, x2q);
+    }
+    s2[sl ^ 1][me] = x2q;
+    // stage 3, plane q - 2: r = b - A x2
+    const int p3 = q - 2;
+    if (m.core && p3 >= m.z0 && p3 < m.z1) {
+      const C kx = m3_k(s2[sl], m.tx, m.ty, x2b, x2a, x2q);
+      const C Ax = x2b + op.a * op.ih2 * kx;
+      st<T, C>(ro + (int64_t)p3 * nn, b2 - Ax);
+    }
+    __syncthreads();
+    b2 = b1;
+    b1 = bq;
+    x1a = x1b;
+    x1b = x1q;
+    x2a = x2b;
+    x2b = x2q;
+  }
+}
+
+// Interpolation slots of fine coordinate c from a coarse axis of nc nodes
+// (coarse node I at fine 2I + 1): two indices and weights, the unused slot
+// with weight zero at a valid index.  Slot order matches prolong_at's term
+// order, and a zero-weight term adds an exact zero, so sums agree with it.
+template <class C>
+__device__ __forceinline__ void m3_slots(int c, int nc, int (&ix)[2], C (&w)[2]) {
+  if (c & 1) {
+    ix[0] = ix[1] = (c - 1) >> 1;
+    w[0] = C(1);
+    w[1] = C(0);
+  } else {
+    const int lo = (c >> 1) - 1, hi = c >> 1;
+    ix[0] = lo >= 0 ? lo : 0;
+    ix[1] = hi < nc ? hi : nc - 1;
+    w[0] = lo >= 0 ? C(0.5) : C(0);
+    w[1] = hi < nc ? C(0.5) : C(0);
+  }
+}
+
+// Prolongation and two post-smoothing sweeps: y = xin + es P e, then
+// y1 = y + omega (b - A y) / d and y2 likewise -> xout (xout != xin).
+template <class T, class TE, class C>
+__global__ __launch_bounds__(M3_T * M3_T) void k_up3d_march(const T* __restrict__ xin, int64_t sxi,
+                                                           const TE* __restrict__ e, int64_t se,
+                                                           const T* __restrict__ b, int64_t sb,
+                                                           T* __restrict__ xout, int64_t sxo, March3Geo g, int nc,
+                                                           LevelOp<C> op, C omega, C es) {
+  constexpr int PF = sizeof(C) == 8 ? 2 : M3_PF_UP;
+  static_assert(PF >= 2, "the coarse values are loaded one plane less ahead");
+  __shared__ C s1[2][M3_T * M3_T];   // y planes
+  __shared__ C s2[2][M3_T * M3_T];   // y1 planes
+  const March3Pos m(g);
+  const int64_t inst = blockIdx.y;
+  const int n = g.n;
+  const int64_t nn = (int64_t)n * n;
+  const int64_t col = (int64_t)(m.inside ? m.j : 0) * n + (m.inside ? m.i : 0);
+  const T* xi = xin + inst * sxi + col;
+  const T* bi = b + inst * sb + col;
+  const TE* ei = e + inst * se;
+  T* xo = xout + inst * sxo + col;
+  const C wd = omega / level_diag<3, KIND_FINE, C>(op, 0, 0, 0, 0);
+  const int me = m.ty * M3_T + m.tx;
+  const int qlast = m.z1 + 1;
+  int ixx[2], ixy[2];
+  C wx[2], wy[2];
+  m3_slots<C>(m.inside ? m.i : 0, nc, ixx, wx);
+  m3_slots<C>(m.inside ? m.j : 0, nc, ixy, wy);
+  // raw loads of plane q: x and b PF planes ahead, the eight coarse values
+  // around each node PFE planes ahead (fewer: they take eight registers a plane)
+  constexpr int PFE = PF - 1;
+  struct XB {
+    C x, b;
+  };
+  struct E8 {
+    C e[8];
+  };
+  auto in_plane = [&](int q) { return m.inside && q >= 0 && q < n && q <= qlast; };
+  auto load_xb = [&](int q, XB& r) {
+    if (in_plane(q)) {
+      r.x = ld<T, C>(xi + (int64_t)q * nn);
+      r.b = ld<T, C>(bi + (int64_t)q * nn);
+    } else {
+      r.x = r.b = C(0);
+    }
+  };
+  auto load_e = [&](int q, E8& r) {
+    if (in_plane(q)) {
+      int iz[2];
+      C wz[2];
+      m3_slots<C>(q, nc, iz, wz);
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+            r.e[(c * 2 + bb) * 2 + a] = ld<TE, C>(ei + ((int64_t)iz[c] * nc + ixy[bb]) * nc + ixx[a]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) r.e[u] = C(0);
+    }
+  };
+  XB pr[PF];    // planes q .. q + PF - 1
+  E8 pe[PFE];   // planes q .. q + PFE - 1
+#pragma unroll
+  for (int u = 0; u < PF; ++u) load_xb(m.z0 - 2 + u, pr[u]);
+#pragma unroll
+  for (int u = 0; u < PFE; ++u) load_e(m.z0 - 2 + u, pe[u]);
+  // windows: b at q-1, q-2; y at q-2, q-1, q; y1 at q-3, q-2, q-1
+  C b1 = C(0), b2 = C(0), ya = C(0), yb = C(0), y1a = C(0), y1b = C(0);
+  for (int q = m.z0 - 2; q <= qlast; ++q) {
+    const int sl = q & 1;
+    const XB cur = pr[0];
+    const E8 ce = pe[0];
+#pragma unroll
+    for (int u = 0; u + 1 < PF; ++u) pr[u] = pr[u + 1];
+    load_xb(q + PF, pr[PF - 1]);
+#pragma unroll
+    for (int u = 0; u + 1 < PFE; ++u) pe[u] = pe[u + 1];
+    load_e(q + PFE, pe[PFE - 1]);
+    // stage 1, plane q: y = x + es P e
+    const bool in1 = m.inside && q >= 0 && q < n;
+    const C bq = cur.b;
+    C yq = C(0);
+    if (in1) {
+      int iz[2];
+      C wz[2];
+      m3_slots<C>(q, nc, iz, wz);
+      C acc = C(0);
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+          for (int a = 0; a < 2; ++a) acc += wx[a] * wy[bb] * wz[c] * ce.e[(c * 2 + bb) * 2 + a];
+      yq = cur.x + es * acc;
+    }
+    s1[sl][me] = yq;
+    // stage 2, plane q - 1: first sweep
+    const int p2 = q - 1;
+    C y1q = C(0);
+    if (m.inside && p2 >= 0 && p2 < n && p2 >= m.z0 - 1) {
+      const C kx = m3_k(s1[sl ^ 1], m.tx, m.ty, yb, ya, yq);
+      const C Ax = yb + op.a * op.ih2 * kx;
+      y1q = yb + wd * (b1 - Ax);
+    }
+    s2[sl ^ 1][me] = y1q;
+    // stage 3, plane q - 2: second sweep, stored
+    const int p3 = q - 2;
+    if (m.core && p3 >= m.z0 && p3 < m.z1) {
+      const C kx = m3_k(s2[sl], m.tx, m.ty, y1b, y1a, y1q);
+      const C Ax = y1b + op.a * op.ih2 * kx;
+      st<T, C>(xo + (int64_t)p3 * nn, y1b + wd * (b2 - Ax));
+    }
+    __syncthreads();
+    b2 = b1;
+    b1 = bq;
+    ya = yb;
+    yb = yq;
+    y1a = y1b;
+    y1b = y1q;
+  }
+}
+
+// Launch geometry of the 3D marches: chunks of 32 planes when that gives at
+// least two workgroups per compute unit over the launch, else 16.
+inline March3Geo march3_geo(int n, int B) {
+  March3Geo g{};
+  g.n = n;
+  g.ntx = (n + M3_C - 1) / M3_C;
+  g.zlen = n < 32 ? n : 32;
+  g.nz = (n + g.zlen - 1) / g.zlen;
+  if ((int64_t)g.ntx * g.ntx * g.nz * B < 512 && n > 16) {
+    g.zlen = 16;
+    g.nz = (n + 15) / 16;
+  }
+  return g;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2466,6 +2761,52 @@ hipError_t Multigrid<TI, TM>::up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec
 #undef UP_T
 }
 
+template <class TI, class TM>
+bool Multigrid<TI, TM>::march3d_ok(int l, bool zero_init, bool pre, int B) const {
+  return h_->dim == 3 && l == 0 && zero_init && !pre && !h_->vark && !h_->fe && levels_ > 1 &&
+         h_->opts.nu1 == 2 && h_->opts.nu2 == 2 && std::is_same<TI, C>::value && B >= h_->tune.tall_min_b;
+}
+
+template <class TI, class TM>
+hipError_t Multigrid<TI, TM>::march3d_down(int stage, Vec b, Vec x2, Vec r, Vec bc, Vec xc, bool zero_next, int B) {
+  const LevelOp<C> opf = make_op<C>(h_, 0, a_[stage]);
+  const LevelOp<C> opc = make_op<C>(h_, 1, a_[stage]);
+  const C omega = (C)h_->omega;
+  const March3Geo g = march3_geo(h_->lev_n[0], B);
+  const dim3 grid((unsigned)(g.ntx * g.ntx * g.nz), (unsigned)B);
+  hipLaunchKernelGGL((k_down3d_march<TI, C>), grid, dim3(M3_T * M3_T), 0, st_, (const TI*)b.ptr, b.stride,
+                     (TI*)x2.ptr, x2.stride, (TI*)r.ptr, r.stride, g, opf, omega);
+  MG_TRY(hipGetLastError());
+  MG_TRY(mark("k_down3d_march", 0));
+  const C bs = (C)h_->mg_scale;
+  const int z = (int)zero_next;
+  MG_TRY(typed1(1, [&](auto tc) {
+    using TC = decltype(tc);
+    hipLaunchKernelGGL((k_restrict<3, TI, TC, C>), grid2(opc.N, B), dim3(TPB), 0, st_, (const TI*)r.ptr, r.stride,
+                       (TC*)bc.ptr, bc.stride, (TC*)xc.ptr, xc.stride, opf.n, opc, omega, z, bs);
+    return hipGetLastError();
+  }));
+  return mark("k_restrict", 0);
+}
+
+template <class TI, class TM>
+hipError_t Multigrid<TI, TM>::march3d_up(int stage, Vec x2, Vec ec, Vec b, Vec xout, int B) {
+  const LevelOp<C> op = make_op<C>(h_, 0, a_[stage]);
+  const C omega = (C)h_->omega;
+  const C es = (C)(1.0 / h_->mg_scale);
+  const March3Geo g = march3_geo(h_->lev_n[0], B);
+  const dim3 grid((unsigned)(g.ntx * g.ntx * g.nz), (unsigned)B);
+  const int nc = h_->lev_n[1];
+  MG_TRY(typed1(1, [&](auto tc) {
+    using TC = decltype(tc);
+    hipLaunchKernelGGL((k_up3d_march<TI, TC, C>), grid, dim3(M3_T * M3_T), 0, st_, (const TI*)x2.ptr, x2.stride,
+                       (const TC*)ec.ptr, ec.stride, (const TI*)b.ptr, b.stride, (TI*)xout.ptr, xout.stride, g, nc,
+                       op, omega, es);
+    return hipGetLastError();
+  }));
+  return mark("k_up3d_march", 0);
+}
+
 // One V-cycle on level l.  `pre` = the first (pointwise) sweep from zero was
 // already written into x by the restriction of the level above.
 template <class TI, class TM>
@@ -2524,6 +2865,21 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
     MG_TRY(vcycle(l + 1, stage, xc, bc, true, false, B, &ec));
     MG_TRY(up2d(l, stage, tmp, ec, b, x, B));
     MG_TRY(mark("k_up2d", l));
+    *result = x;
+    return hipSuccess;
+  }
+  if (march3d_ok(l, zero_init, pre, B)) {
+    // z-marches: sweeps and residual -> full weighting -> coarse cycle ->
+    // prolongation and sweeps
+    const int64_t Nc = h_->lev_N[1];
+    Vec r{h_->ws + P.mgR[0], Nl};
+    Vec bc{h_->ws + P.mgB[1], Nc};
+    Vec xc{h_->ws + P.mgX[1], Nc};
+    const bool next_grid = 1 < l0_;
+    MG_TRY(march3d_down(stage, b, tmp, r, bc, xc, next_grid, B));
+    Vec ec{};
+    MG_TRY(vcycle(1, stage, xc, bc, true, next_grid, B, &ec));
+    MG_TRY(march3d_up(stage, tmp, ec, b, x, B));
     *result = x;
     return hipSuccess;
   }

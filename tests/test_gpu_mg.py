@@ -242,3 +242,36 @@ def test_apply_mg_coarse_max_1024(n, tail_max):
             z = _run(hp, r, stage, 2, transpose)
             ref = _oracle(p, transpose, stage, r, 2, coarse_max=1024)
             assert rel_err(z, ref) <= 1e-12, (stage, rel_err(z, ref))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5), ("fp16", 1e-3)])
+@pytest.mark.parametrize("n,nt", [(12, 2), (17, 3), (45, 2), (64, 9)])
+def test_apply_mg_3d_level0_march_equals_grid(precision, tol, n, nt):
+    """From tall_min_b blocks on, a zero-start V-cycle of the 3D operator
+    runs level 0 as two z-marches (32 x 32 column tiles with a two-node halo,
+    chunks of 16 or 32 planes): the first sweep, the second and the residual
+    in one; the prolongation and both post-smoothing sweeps in the other.
+    They apply the grid kernels' arithmetic to every node, so the cycles
+    agree bit for bit with tall_min_b = 2^30 (every launch on the grid
+    kernels): one tile and one chunk (12), a one-plane last chunk (17),
+    ragged tiles and chunks (45), several of each (64).  A second cycle
+    starts from a nonzero iterate and runs the grid kernels on level 0 in
+    both.  Block 0 is checked against the oracle."""
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    dim, s = 3, 2
+    p = allatonce.Problem(n, dim, s, nt, 1.0)
+    hp = HeatProblem(dim, n, s, nt, 1.0, precision=precision)
+    rng = np.random.default_rng(5 * n + nt)
+    r = rng.standard_normal((nt, p.N))
+    if precision != "fp64":
+        r = r.astype(np.float32).astype(np.float64)
+    for cycles in (1, 2):
+        announce("apply_mg 3D march vs grid", precision, n, "blocks", nt, "cycles", cycles)
+        hp.set_launch_shapes(1, 0)
+        z_march = _run(hp, r, 1, cycles, False)
+        hp.set_launch_shapes(1 << 30, 0)
+        z_grid = _run(hp, r, 1, cycles, False)
+        assert np.array_equal(z_march, z_grid), float(np.max(np.abs(z_march - z_grid)))
+        ref = _oracle(p, False, 1, r[:1], cycles)
+        assert rel_err(z_march[:1], ref) <= tol, rel_err(z_march[:1], ref)

@@ -94,3 +94,25 @@ def test_adjoint_solve_matches_oracle(precision):
     lam, st = hp.solve_adjoint(to_dev(g))
     assert st["converged"]
     assert rel_err(to_host(lam), adjoint.solve(p, g)) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_solve_3d_level0_marches_match_stepping(precision):
+    """The 3D solve with level 0 of every zero-start V-cycle on the z-marching
+    kernels (tall_min_b = 1: every launch, single S-tilde steps included),
+    on a grid of two ragged tiles and chunks per side: the forward error
+    against stepping stays within 1e-8."""
+    require_gpu()
+    from paper_2609_16863_amd import HeatProblem
+    dim, n, s, nt = 3, 37, 3, 5
+    p = allatonce.Problem(n, dim, s, nt, 1.0)
+    hp = HeatProblem(dim, n, s, nt, 1.0, tol=1e-11, precision=precision)
+    hp.set_launch_shapes(1, 0)
+    rng = np.random.default_rng(1003)
+    f = heat_inputs.bump_source(rng, n, dim, hp.stage_times())
+    u0 = heat_inputs.smooth_initial(rng, n, dim)
+    announce("solve 3D marches", n, s, nt, precision)
+    x, st = _solve(hp, p, f, u0)
+    assert st["converged"]
+    xs = stepping.solve(p, f, u0)
+    assert rel_err(x, xs) <= 1e-8, st
