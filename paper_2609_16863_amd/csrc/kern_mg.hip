@@ -1986,6 +1986,13 @@ struct March3Pos {
   }
 };
 
+// Barrier for the marches' plane steps: the stages exchange data only
+// through LDS, so a wave waits for its own LDS operations and then for the
+// workgroup.  (__syncthreads also waits for every global load in flight,
+// which would stall each step on the loads issued for planes ahead.)  The
+// memory clobber keeps the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void m3_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // h^2 K at the thread's node of plane slot s: (x, y)-neighbours from the
 // LDS plane (the tile's edge threads read themselves: their results are
 // never used), z-neighbours zm, zp from registers.  Same expression as
@@ -2002,7 +2009,7 @@ __device__ __forceinline__ C m3_k(const C* pl, int tx, int ty, C c0, C zm, C zp)
 // Planes are loaded PF steps before their first stage uses them (a ring of
 // registers), so each step's global loads overlap the steps before it.
 constexpr int M3_PF_DOWN = 4;
-constexpr int M3_PF_UP = 3;   // FP64 takes 2 (more planes in flight spill registers)
+constexpr int M3_PF_UP = 2;
 
 // Zero-start pre-smoothing (two weighted Jacobi sweeps, the first
 // pointwise) and the residual: x2 -> xout, r = b - A x2 -> rout.
@@ -2025,46 +2032,56 @@ __global__ __launch_bounds__(M3_T * M3_T) void k_down3d_march(const T* __restric
   const C wd = omega / level_diag<3, KIND_FINE, C>(op, 0, 0, 0, 0);
   const int me = m.ty * M3_T + m.tx;
   const int qlast = m.z1 + 1;
-  auto load_b = [&](int q) { return (m.inside && q >= 0 && q < n && q <= qlast) ? ld<T, C>(bi + (int64_t)q * nn) : C(0); };
-  C pb[PF];   // b of planes q .. q + PF - 1
+  // every thread loads, at a clamped plane, so the loads are unconditional
+  // and the compiler's wait counts let them stay in flight; each stage reads
+  // its plane's value only where that plane and node are real
+  auto load_b = [&](int q) { return ld<T, C>(bi + (int64_t)min(max(q, 0), n - 1) * nn); };
+  // ring of planes in flight: slot u holds plane q0 + u of the current block
+  // of PF steps; each step consumes its slot and refills it PF planes ahead
+  // (the loop is unrolled by PF, so the ring rotates by renaming)
+  C pb[PF];
 #pragma unroll
   for (int u = 0; u < PF; ++u) pb[u] = load_b(m.z0 - 2 + u);
   // register windows: b at q-1, q-2; x1 at q-2, q-1, q; x2 at q-3, q-2, q-1
   C b1 = C(0), b2 = C(0), x1a = C(0), x1b = C(0), x2a = C(0), x2b = C(0);
-  for (int q = m.z0 - 2; q <= qlast; ++q) {
-    const int sl = q & 1;
-    const C bq = pb[0];
+  // whole blocks of PF steps: steps past qlast write nothing (their planes
+  // lie beyond the chunk's last output)
+  for (int q0 = m.z0 - 2; q0 <= qlast; q0 += PF) {
 #pragma unroll
-    for (int u = 0; u + 1 < PF; ++u) pb[u] = pb[u + 1];
-    pb[PF - 1] = load_b(q + PF);
-    // stage 1, plane q: x1 = omega b / d
-    const bool in1 = m.inside && q >= 0 && q < n;
-    const C x1q = in1 ? wd * bq : C(0);
-    s1[sl][me] = x1q;
-    // stage 2, plane q - 1: x2 = x1 + omega (b - A x1) / d
-    const int p2 = q - 1;
-    C x2q = C(0);
-    if (m.inside && p2 >= 0 && p2 < n && p2 >= m.z0 - 1) {
-      const C kx = m3_k(s1[sl ^ 1], m.tx, m.ty, x1b, x1a, x1q);
-      const C Ax = x1b + op.a * op.ih2 * kx;
-      x2q = x1b + wd * (b1 - Ax);
-      if (m.core && p2 >= m.z0 && p2 < m.z1) st<T, C>(xo + (int64_t)p2 * nn, x2q);
+    for (int u = 0; u < PF; ++u) {
+      const int q = q0 + u;
+      const int sl = q & 1;
+      const C bq = pb[u];
+      pb[u] = load_b(q + PF);
+      // stage 1, plane q: x1 = (omega / d) b
+      const bool in1 = m.inside && q >= 0 && q < n;
+      const C x1q = in1 ? wd * bq : C(0);
+      s1[sl][me] = x1q;
+      // stage 2, plane q - 1: x2 = x1 + (omega / d) (b - A x1)
+      const int p2 = q - 1;
+      C x2q = C(0);
+      if (m.inside && p2 >= 0 && p2 < n && p2 >= m.z0 - 1) {
+        const C kx = m3_k(s1[sl ^ 1], m.tx, m.ty, x1b, x1a, x1q);
+        const C Ax = x1b + op.a * op.ih2 * kx;
+        x2q = x1b + wd * (b1 - Ax);
+        if (m.core && p2 >= m.z0 && p2 < m.z1) st<T, C>(xo + (int64_t)p2 * nn, x2q);
+      }
+      s2[sl ^ 1][me] = x2q;
+      // stage 3, plane q - 2: r = b - A x2
+      const int p3 = q - 2;
+      if (m.core && p3 >= m.z0 && p3 < m.z1) {
+        const C kx = m3_k(s2[sl], m.tx, m.ty, x2b, x2a, x2q);
+        const C Ax = x2b + op.a * op.ih2 * kx;
+        st<T, C>(ro + (int64_t)p3 * nn, b2 - Ax);
+      }
+      m3_sync();
+      b2 = b1;
+      b1 = bq;
+      x1a = x1b;
+      x1b = x1q;
+      x2a = x2b;
+      x2b = x2q;
     }
-    s2[sl ^ 1][me] = x2q;
-    // stage 3, plane q - 2: r = b - A x2
-    const int p3 = q - 2;
-    if (m.core && p3 >= m.z0 && p3 < m.z1) {
-      const C kx = m3_k(s2[sl], m.tx, m.ty, x2b, x2a, x2q);
-      const C Ax = x2b + op.a * op.ih2 * kx;
-      st<T, C>(ro + (int64_t)p3 * nn, b2 - Ax);
-    }
-    __syncthreads();
-    b2 = b1;
-    b1 = bq;
-    x1a = x1b;
-    x1b = x1q;
-    x2a = x2b;
-    x2b = x2q;
   }
 }
 
@@ -2087,18 +2104,28 @@ __device__ __forceinline__ void m3_slots(int c, int nc, int (&ix)[2], C (&w)[2])
   }
 }
 
+// Coarse patch of a tile: the coarse nodes any of its 32 fine columns
+// interpolates from lie in 18 consecutive indices from (o >> 1) - 1, o the
+// fine index of the tile's first thread.
+constexpr int M3_P = 18;
+
 // Prolongation and two post-smoothing sweeps: y = xin + es P e, then
-// y1 = y + omega (b - A y) / d and y2 likewise -> xout (xout != xin).
+// y1 = y + (omega / d) (b - A y) and y2 likewise -> xout (xout != xin).
+// Each coarse plane is staged once per tile as an 18 x 18 patch in LDS
+// (two slots: fine plane q reads coarse planes ceil(q/2) - 1 and floor(q/2));
+// plane m + 1 is written on step 2m + 1, its loads issued four steps before.
 template <class T, class TE, class C>
-__global__ __launch_bounds__(M3_T * M3_T) void k_up3d_march(const T* __restrict__ xin, int64_t sxi,
+__global__ __launch_bounds__(M3_T * M3_T) __attribute__((amdgpu_waves_per_eu(sizeof(C) == 4 ? 8 : 4)))
+void k_up3d_march(const T* __restrict__ xin, int64_t sxi,
                                                            const TE* __restrict__ e, int64_t se,
                                                            const T* __restrict__ b, int64_t sb,
                                                            T* __restrict__ xout, int64_t sxo, March3Geo g, int nc,
                                                            LevelOp<C> op, C omega, C es) {
   constexpr int PF = sizeof(C) == 8 ? 2 : M3_PF_UP;
-  static_assert(PF >= 2, "the coarse values are loaded one plane less ahead");
+  static_assert(PF % 2 == 0, "blocks of PF steps start on even planes");
   __shared__ C s1[2][M3_T * M3_T];   // y planes
   __shared__ C s2[2][M3_T * M3_T];   // y1 planes
+  __shared__ C sc[2][M3_P * M3_P];   // coarse patches
   const March3Pos m(g);
   const int64_t inst = blockIdx.y;
   const int n = g.n;
@@ -2106,109 +2133,115 @@ __global__ __launch_bounds__(M3_T * M3_T) void k_up3d_march(const T* __restrict_
   const int64_t col = (int64_t)(m.inside ? m.j : 0) * n + (m.inside ? m.i : 0);
   const T* xi = xin + inst * sxi + col;
   const T* bi = b + inst * sb + col;
-  const TE* ei = e + inst * se;
   T* xo = xout + inst * sxo + col;
   const C wd = omega / level_diag<3, KIND_FINE, C>(op, 0, 0, 0, 0);
   const int me = m.ty * M3_T + m.tx;
   const int qlast = m.z1 + 1;
+  // this thread's interpolation slots in x and y, as patch offsets
+  const int cx0 = ((m.i - m.tx) >> 1) - 1, cy0 = ((m.j - m.ty) >> 1) - 1;
   int ixx[2], ixy[2];
   C wx[2], wy[2];
   m3_slots<C>(m.inside ? m.i : 0, nc, ixx, wx);
   m3_slots<C>(m.inside ? m.j : 0, nc, ixy, wy);
-  // raw loads of plane q: x and b PF planes ahead, the eight coarse values
-  // around each node PFE planes ahead (fewer: they take eight registers a plane)
-  constexpr int PFE = PF - 1;
-  struct XB {
-    C x, b;
+  int px[2], py[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    px[u] = min(max(ixx[u] - cx0, 0), M3_P - 1);
+    py[u] = min(max(ixy[u] - cy0, 0), M3_P - 1);
+  }
+  // the patch entry this thread loads (threads past the patch load nothing)
+  const int tid = (int)threadIdx.x;
+  const bool loader = tid < M3_P * M3_P;
+  const int lj = loader ? tid / M3_P : 0, li = loader ? tid - lj * M3_P : 0;
+  const int gI = cx0 + li, gJ = cy0 + lj;
+  const bool lin = loader && gI >= 0 && gI < nc && gJ >= 0 && gJ < nc;
+  const TE* ep = e + inst * se + (lin ? (int64_t)gJ * nc + gI : 0);
+  const int64_t ncc = (int64_t)nc * nc;
+  // unconditional (clamped) like load_b: patch entries off the coarse grid,
+  // and planes off it, are read only with zero interpolation weight
+  auto load_c = [&](int K) { return ld<TE, C>(ep + (int64_t)min(max(K, 0), nc - 1) * ncc); };
+  // fine planes start even (z0 is 0 or a multiple of 16): the first step
+  // q0 = 2 m0 reads coarse planes m0 - 1 and m0
+  const int m0 = (m.z0 - 2) >> 1;
+  if (loader) {
+    sc[(m0 - 1) & 1][tid] = load_c(m0 - 1);
+    sc[m0 & 1][tid] = load_c(m0);
+  }
+  // coarse planes in flight: step 2k + 1 writes plane k + 1, and the odd
+  // steps of a block of PF (even) steps take slots 0 .. PF/2 - 1 in turn
+  C pc_[PF / 2];
+#pragma unroll
+  for (int u = 0; u < PF / 2; ++u) pc_[u] = load_c(m0 + 1 + u);
+  auto load_xb = [&](int q, C& x, C& bb) {   // unconditional, as load_b of the down kernel
+    const int64_t o = (int64_t)min(max(q, 0), n - 1) * nn;
+    x = ld<T, C>(xi + o);
+    bb = ld<T, C>(bi + o);
   };
-  struct E8 {
-    C e[8];
-  };
-  auto in_plane = [&](int q) { return m.inside && q >= 0 && q < n && q <= qlast; };
-  auto load_xb = [&](int q, XB& r) {
-    if (in_plane(q)) {
-      r.x = ld<T, C>(xi + (int64_t)q * nn);
-      r.b = ld<T, C>(bi + (int64_t)q * nn);
-    } else {
-      r.x = r.b = C(0);
-    }
-  };
-  auto load_e = [&](int q, E8& r) {
-    if (in_plane(q)) {
-      int iz[2];
-      C wz[2];
-      m3_slots<C>(q, nc, iz, wz);
+  C px_[PF], pb_[PF];   // x and b, as the ring of the down kernel
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-          for (int a = 0; a < 2; ++a)
-            r.e[(c * 2 + bb) * 2 + a] = ld<TE, C>(ei + ((int64_t)iz[c] * nc + ixy[bb]) * nc + ixx[a]);
-    } else {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) r.e[u] = C(0);
-    }
-  };
-  XB pr[PF];    // planes q .. q + PF - 1
-  E8 pe[PFE];   // planes q .. q + PFE - 1
-#pragma unroll
-  for (int u = 0; u < PF; ++u) load_xb(m.z0 - 2 + u, pr[u]);
-#pragma unroll
-  for (int u = 0; u < PFE; ++u) load_e(m.z0 - 2 + u, pe[u]);
+  for (int u = 0; u < PF; ++u) load_xb(m.z0 - 2 + u, px_[u], pb_[u]);
+  m3_sync();
   // windows: b at q-1, q-2; y at q-2, q-1, q; y1 at q-3, q-2, q-1
   C b1 = C(0), b2 = C(0), ya = C(0), yb = C(0), y1a = C(0), y1b = C(0);
-  for (int q = m.z0 - 2; q <= qlast; ++q) {
-    const int sl = q & 1;
-    const XB cur = pr[0];
-    const E8 ce = pe[0];
+  // whole blocks of PF steps: steps past qlast write nothing (their planes
+  // lie beyond the chunk's last output)
+  for (int q0 = m.z0 - 2; q0 <= qlast; q0 += PF) {
 #pragma unroll
-    for (int u = 0; u + 1 < PF; ++u) pr[u] = pr[u + 1];
-    load_xb(q + PF, pr[PF - 1]);
+    for (int u = 0; u < PF; ++u) {
+      const int q = q0 + u;
+      const int sl = q & 1;
+      const C xq = px_[u], bq = pb_[u];
+      load_xb(q + PF, px_[u], pb_[u]);
+      // stage 1, plane q: y = x + es P e (same terms and order as prolong_at)
+      const bool in1 = m.inside && q >= 0 && q < n;
+      C yq = C(0);
+      if (in1) {
+        int iz[2];
+        C wz[2];
+        m3_slots<C>(q, nc, iz, wz);
+        C acc = C(0);
 #pragma unroll
-    for (int u = 0; u + 1 < PFE; ++u) pe[u] = pe[u + 1];
-    load_e(q + PFE, pe[PFE - 1]);
-    // stage 1, plane q: y = x + es P e
-    const bool in1 = m.inside && q >= 0 && q < n;
-    const C bq = cur.b;
-    C yq = C(0);
-    if (in1) {
-      int iz[2];
-      C wz[2];
-      m3_slots<C>(q, nc, iz, wz);
-      C acc = C(0);
+        for (int c = 0; c < 2; ++c) {
+          const C* pc = sc[iz[c] & 1];
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
+          for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-          for (int a = 0; a < 2; ++a) acc += wx[a] * wy[bb] * wz[c] * ce.e[(c * 2 + bb) * 2 + a];
-      yq = cur.x + es * acc;
+            for (int a = 0; a < 2; ++a) acc += wx[a] * wy[bb] * wz[c] * pc[py[bb] * M3_P + px[a]];
+        }
+        yq = xq + es * acc;
+      }
+      s1[sl][me] = yq;
+      // stage 2, plane q - 1: first sweep
+      const int p2 = q - 1;
+      C y1q = C(0);
+      if (m.inside && p2 >= 0 && p2 < n && p2 >= m.z0 - 1) {
+        const C kx = m3_k(s1[sl ^ 1], m.tx, m.ty, yb, ya, yq);
+        const C Ax = yb + op.a * op.ih2 * kx;
+        y1q = yb + wd * (b1 - Ax);
+      }
+      s2[sl ^ 1][me] = y1q;
+      // stage 3, plane q - 2: second sweep, stored
+      const int p3 = q - 2;
+      if (m.core && p3 >= m.z0 && p3 < m.z1) {
+        const C kx = m3_k(s2[sl], m.tx, m.ty, y1b, y1a, y1q);
+        const C Ax = y1b + op.a * op.ih2 * kx;
+        st<T, C>(xo + (int64_t)p3 * nn, y1b + wd * (b2 - Ax));
+      }
+      // odd step 2k + 1 (q0 is even): coarse plane k + 1 into its slot (plane
+      // k - 1's, last read on step 2k), then the slot's next plane
+      if (u & 1) {
+        const int K = (q >> 1) + 1;
+        if (loader) sc[K & 1][tid] = pc_[u >> 1];
+        pc_[u >> 1] = load_c(K + PF / 2);
+      }
+      m3_sync();
+      b2 = b1;
+      b1 = bq;
+      ya = yb;
+      yb = yq;
+      y1a = y1b;
+      y1b = y1q;
     }
-    s1[sl][me] = yq;
-    // stage 2, plane q - 1: first sweep
-    const int p2 = q - 1;
-    C y1q = C(0);
-    if (m.inside && p2 >= 0 && p2 < n && p2 >= m.z0 - 1) {
-      const C kx = m3_k(s1[sl ^ 1], m.tx, m.ty, yb, ya, yq);
-      const C Ax = yb + op.a * op.ih2 * kx;
-      y1q = yb + wd * (b1 - Ax);
-    }
-    s2[sl ^ 1][me] = y1q;
-    // stage 3, plane q - 2: second sweep, stored
-    const int p3 = q - 2;
-    if (m.core && p3 >= m.z0 && p3 < m.z1) {
-      const C kx = m3_k(s2[sl], m.tx, m.ty, y1b, y1a, y1q);
-      const C Ax = y1b + op.a * op.ih2 * kx;
-      st<T, C>(xo + (int64_t)p3 * nn, y1b + wd * (b2 - Ax));
-    }
-    __syncthreads();
-    b2 = b1;
-    b1 = bq;
-    ya = yb;
-    yb = yq;
-    y1a = y1b;
-    y1b = y1q;
   }
 }
 
