@@ -416,9 +416,11 @@ int aao_profile_vcycle(aao_problem* h, int stage, int count, int reps, char* lab
                        double* us_alone, int cap, int* nlaunch, double* total_us);
 
 /* Launch shapes of the multigrid kernels, chosen by aao_autotune.  The
- * tiled level kernels run short tiles or tall ones from tall_min_b blocks
- * per launch on; the register tail takes a 64 x 64 level too when
- * tail_extend.  Neither changes the cycle's arithmetic. */
+ * tiled level kernels run short tiles or tall ones (and level 0 as row
+ * marches) from tall_min_b blocks per launch on; in 3D, level 0 runs as
+ * z-marches from tall_min_b blocks on; the register tail takes a 64 x 64
+ * level too when tail_extend.  None of them changes the cycle's
+ * arithmetic. */
 typedef struct aao_tune {
   int tall_min_b;          /* chosen threshold (1, 8 or 2^30 = never)         */
   int tail_extend;         /* chosen: 1 or 0                                   */
