@@ -296,8 +296,9 @@ def vcycle_kernels(hp, precision, reps):
             return pl[lev] * 3 * nodes[lev] + pl[lev + 1] * nodes[lev + 1]
         if name in ("k_tail_fast", "k_tail"):
             return 2 * pl[lev] * nodes[lev]
-        if name == "k_down3d_march":   # reads b, writes x2 and r
-            return 3 * pl[lev] * nodes[lev]
+        if name == "k_down3d_march":   # reads b, writes x2, b_{l+1} (and x_{l+1} when that level sweeps)
+            first_sweep = lev + 2 < len(nodes)
+            return 2 * pl[lev] * nodes[lev] + (2 if first_sweep else 1) * pl[lev + 1] * nodes[lev + 1]
         if name == "k_up3d_march":     # reads x2, b and the correction, writes x
             return 3 * pl[lev] * nodes[lev] + pl[lev + 1] * nodes[lev + 1]
         if name == "k_restrict":       # reads r, writes b_{l+1} (and x_{l+1} when that level sweeps)
@@ -353,10 +354,10 @@ def vcycle_kernels(hp, precision, reps):
         the tail runs one workgroup per block."""
         name, lev = label.split("@")
         if name in ("k_down3d_march", "k_up3d_march"):
-            # 32 x 32-thread tiles with 28 x 28 cores, chunks of 32 planes
-            # (16 when that leaves under 512 workgroups)
+            # 32 x 32-thread tiles with 26 x 26 (down) or 28 x 28 (up) cores,
+            # chunks of 32 planes (16 when that leaves under 512 workgroups)
             nf = side[int(lev)]
-            ntx = -(-nf // 28)
+            ntx = -(-nf // (26 if name == "k_down3d_march" else 28))
             zlen = nf if nf < 32 else 32
             if ntx * ntx * -(-nf // zlen) * B < 512 and nf > 16:
                 zlen = 16

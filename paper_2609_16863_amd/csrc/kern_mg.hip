@@ -1956,16 +1956,17 @@ int tail_fast_layout(TailFastArgs<C>& ta, int nls) {
 // arithmetic is that of k_smooth / k_residual / k_prolong, node by node.
 // ---------------------------------------------------------------------------
 constexpr int M3_T = 32;          // threads per tile side
-constexpr int M3_H = 2;           // halo width
-constexpr int M3_C = M3_T - 2 * M3_H;   // core width
 
 struct March3Geo {
   int n, ntx, nz, zlen;   // grid side, tiles per side, z-chunks, planes per chunk
 };
 
-// Tile, chunk and thread coordinates of this workgroup.  Logical tiles are
-// spread so each XCD walks a contiguous range (xcd_tile).
+// Tile, chunk and thread coordinates of this workgroup for a halo of H
+// nodes (core width 32 - 2H).  Logical tiles are spread so each XCD walks a
+// contiguous range (xcd_tile).
+template <int H>
 struct March3Pos {
+  static constexpr int CW = M3_T - 2 * H;
   int i, j, z0, z1;
   bool inside, core;
   int tx, ty;
@@ -1977,12 +1978,12 @@ struct March3Pos {
     const int by = r / g.ntx, bx = r - by * g.ntx;
     tx = (int)threadIdx.x & (M3_T - 1);
     ty = (int)threadIdx.x / M3_T;
-    i = bx * M3_C - M3_H + tx;
-    j = by * M3_C - M3_H + ty;
+    i = bx * CW - H + tx;
+    j = by * CW - H + ty;
     z0 = zc * g.zlen;
     z1 = z0 + g.zlen < g.n ? z0 + g.zlen : g.n;
     inside = i >= 0 && i < g.n && j >= 0 && j < g.n;
-    core = inside && tx >= M3_H && tx < M3_T - M3_H && ty >= M3_H && ty < M3_T - M3_H;
+    core = inside && tx >= H && tx < M3_T - H && ty >= H && ty < M3_T - H;
   }
 };
 
@@ -2012,26 +2013,42 @@ constexpr int M3_PF_DOWN = 4;
 constexpr int M3_PF_UP = 2;
 
 // Zero-start pre-smoothing (two weighted Jacobi sweeps, the first
-// pointwise) and the residual: x2 -> xout, r = b - A x2 -> rout.
-template <class T, class C>
+// pointwise), the residual and its full weighting: x2 -> xout; b_c (and,
+// with zero_next, the coarse level's first sweep x_c = omega b_c / D_c) for
+// the coarse nodes centred in the tile's core.  A halo of three nodes leaves
+// the residual valid one node past the core, where the 3 x 3 neighbourhoods
+// of the core's coarse centres reach.  Stage 4 adds plane q - 3 of the
+// residual to its coarse planes term by term in k_restrict's order, so b_c
+// is bitwise k_restrict's.
+template <class T, class TC, class C>
 __global__ __launch_bounds__(M3_T * M3_T) void k_down3d_march(const T* __restrict__ b, int64_t sb,
                                                              T* __restrict__ xout, int64_t sx,
-                                                             T* __restrict__ rout, int64_t sr, March3Geo g,
-                                                             LevelOp<C> op, C omega) {
+                                                             TC* __restrict__ bc, int64_t sbc,
+                                                             TC* __restrict__ xc, int64_t sxc, March3Geo g,
+                                                             LevelOp<C> op, LevelOp<C> opc, C omega, int zero_next,
+                                                             C bscale) {
   constexpr int PF = M3_PF_DOWN;
   __shared__ C s1[2][M3_T * M3_T];   // x1 planes
   __shared__ C s2[2][M3_T * M3_T];   // x2 planes
-  const March3Pos m(g);
+  __shared__ C s3[2][M3_T * M3_T];   // residual planes
+  const March3Pos<3> m(g);
   const int64_t inst = blockIdx.y;
   const int n = g.n;
   const int64_t nn = (int64_t)n * n;
   const int64_t col = (int64_t)(m.inside ? m.j : 0) * n + (m.inside ? m.i : 0);
   const T* bi = b + inst * sb + col;
   T* xo = xout + inst * sx + col;
-  T* ro = rout + inst * sr + col;
   const C wd = omega / level_diag<3, KIND_FINE, C>(op, 0, 0, 0, 0);
   const int me = m.ty * M3_T + m.tx;
-  const int qlast = m.z1 + 1;
+  // coarse owner: a core node at odd (i, j) is the centre of coarse (I, J)
+  const bool owner = m.core && (m.i & 1) && (m.j & 1);
+  const int I = (m.i - 1) >> 1, J = (m.j - 1) >> 1, nc = opc.n;
+  const int zc1 = m.z1 < n ? m.z1 : n;   // coarse planes K with z0 <= 2K + 1 < zc1 are this chunk's
+  const C w3[3] = {C(0.5), C(1), C(0.5)};
+  C acc = C(0);
+  // the last plane the restriction reads is z1 (the + 1 neighbour of the
+  // chunk's last centre plane); stage 4 trails stage 1 by three planes
+  const int qlast = m.z1 + 3;
   // every thread loads, at a clamped plane, so the loads are unconditional
   // and the compiler's wait counts let them stay in flight; each stage reads
   // its plane's value only where that plane and node are real
@@ -2044,8 +2061,7 @@ __global__ __launch_bounds__(M3_T * M3_T) void k_down3d_march(const T* __restric
   for (int u = 0; u < PF; ++u) pb[u] = load_b(m.z0 - 2 + u);
   // register windows: b at q-1, q-2; x1 at q-2, q-1, q; x2 at q-3, q-2, q-1
   C b1 = C(0), b2 = C(0), x1a = C(0), x1b = C(0), x2a = C(0), x2b = C(0);
-  // whole blocks of PF steps: steps past qlast write nothing (their planes
-  // lie beyond the chunk's last output)
+  // whole blocks of PF steps: steps past qlast write nothing
   for (int q0 = m.z0 - 2; q0 <= qlast; q0 += PF) {
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
@@ -2067,12 +2083,41 @@ __global__ __launch_bounds__(M3_T * M3_T) void k_down3d_march(const T* __restric
         if (m.core && p2 >= m.z0 && p2 < m.z1) st<T, C>(xo + (int64_t)p2 * nn, x2q);
       }
       s2[sl ^ 1][me] = x2q;
-      // stage 3, plane q - 2: r = b - A x2
+      // stage 3, plane q - 2: r = b - A x2 (zero off the grid)
       const int p3 = q - 2;
-      if (m.core && p3 >= m.z0 && p3 < m.z1) {
+      C r = C(0);
+      if (m.inside && p3 >= 0 && p3 < n && p3 >= m.z0) {
         const C kx = m3_k(s2[sl], m.tx, m.ty, x2b, x2a, x2q);
         const C Ax = x2b + op.a * op.ih2 * kx;
-        st<T, C>(ro + (int64_t)p3 * nn, b2 - Ax);
+        r = b2 - Ax;
+      }
+      s3[sl][me] = r;
+      // stage 4, plane p = q - 3 (written last step): coarse plane K takes
+      // fine planes 2K, 2K + 1, 2K + 2 with weights w3[dk + 1]
+      const int p4 = q - 3;
+      if (owner && p4 >= m.z0 && p4 <= m.z1) {
+        const C* rp = s3[sl ^ 1];
+        auto add = [&](int dk) {
+#pragma unroll
+          for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+            for (int di = -1; di <= 1; ++di)
+              acc += w3[di + 1] * w3[dj + 1] * w3[dk + 1] * rp[(m.ty + dj) * M3_T + m.tx + di];
+        };
+        if (p4 & 1) {
+          add(0);                                   // centre plane of K = (p - 1) / 2
+        } else {
+          const int K = (p4 >> 1) - 1;              // plane 2K + 2 completes K
+          if (2 * K + 1 >= m.z0 && 2 * K + 1 < zc1) {
+            add(1);
+            const C v = acc * (C(0.125) * bscale);
+            const int64_t pc = ((int64_t)K * nc + J) * nc + I;
+            st<TC, C>(bc + inst * sbc + pc, v);
+            if (zero_next) st<TC, C>(xc + inst * sxc + pc, omega * v / level_diag<3, KIND_TENSOR, C>(opc, (int)pc, I, J, K));
+          }
+          acc = C(0);
+          if (p4 + 1 < zc1) add(-1);                // first plane of K + 1
+        }
       }
       m3_sync();
       b2 = b1;
@@ -2126,7 +2171,7 @@ void k_up3d_march(const T* __restrict__ xin, int64_t sxi,
   __shared__ C s1[2][M3_T * M3_T];   // y planes
   __shared__ C s2[2][M3_T * M3_T];   // y1 planes
   __shared__ C sc[2][M3_P * M3_P];   // coarse patches
-  const March3Pos m(g);
+  const March3Pos<2> m(g);
   const int64_t inst = blockIdx.y;
   const int n = g.n;
   const int64_t nn = (int64_t)n * n;
@@ -2245,12 +2290,14 @@ void k_up3d_march(const T* __restrict__ xin, int64_t sxi,
   }
 }
 
-// Launch geometry of the 3D marches: chunks of 32 planes when that gives at
-// least two workgroups per compute unit over the launch, else 16.
-inline March3Geo march3_geo(int n, int B) {
+// Launch geometry of a 3D march with a halo of h nodes: chunks of 32
+// planes when that gives at least two workgroups per compute unit over the
+// launch, else 16.
+inline March3Geo march3_geo(int n, int B, int h) {
+  const int cw = M3_T - 2 * h;
   March3Geo g{};
   g.n = n;
-  g.ntx = (n + M3_C - 1) / M3_C;
+  g.ntx = (n + cw - 1) / cw;
   g.zlen = n < 32 ? n : 32;
   g.nz = (n + g.zlen - 1) / g.zlen;
   if ((int64_t)g.ntx * g.ntx * g.nz * B < 512 && n > 16) {
@@ -2801,25 +2848,21 @@ bool Multigrid<TI, TM>::march3d_ok(int l, bool zero_init, bool pre, int B) const
 }
 
 template <class TI, class TM>
-hipError_t Multigrid<TI, TM>::march3d_down(int stage, Vec b, Vec x2, Vec r, Vec bc, Vec xc, bool zero_next, int B) {
+hipError_t Multigrid<TI, TM>::march3d_down(int stage, Vec b, Vec x2, Vec bc, Vec xc, bool zero_next, int B) {
   const LevelOp<C> opf = make_op<C>(h_, 0, a_[stage]);
   const LevelOp<C> opc = make_op<C>(h_, 1, a_[stage]);
   const C omega = (C)h_->omega;
-  const March3Geo g = march3_geo(h_->lev_n[0], B);
-  const dim3 grid((unsigned)(g.ntx * g.ntx * g.nz), (unsigned)B);
-  hipLaunchKernelGGL((k_down3d_march<TI, C>), grid, dim3(M3_T * M3_T), 0, st_, (const TI*)b.ptr, b.stride,
-                     (TI*)x2.ptr, x2.stride, (TI*)r.ptr, r.stride, g, opf, omega);
-  MG_TRY(hipGetLastError());
-  MG_TRY(mark("k_down3d_march", 0));
   const C bs = (C)h_->mg_scale;
-  const int z = (int)zero_next;
+  const March3Geo g = march3_geo(h_->lev_n[0], B, 3);
+  const dim3 grid((unsigned)(g.ntx * g.ntx * g.nz), (unsigned)B);
   MG_TRY(typed1(1, [&](auto tc) {
     using TC = decltype(tc);
-    hipLaunchKernelGGL((k_restrict<3, TI, TC, C>), grid2(opc.N, B), dim3(TPB), 0, st_, (const TI*)r.ptr, r.stride,
-                       (TC*)bc.ptr, bc.stride, (TC*)xc.ptr, xc.stride, opf.n, opc, omega, z, bs);
+    hipLaunchKernelGGL((k_down3d_march<TI, TC, C>), grid, dim3(M3_T * M3_T), 0, st_, (const TI*)b.ptr, b.stride,
+                       (TI*)x2.ptr, x2.stride, (TC*)bc.ptr, bc.stride, (TC*)xc.ptr, xc.stride, g, opf, opc, omega,
+                       (int)zero_next, bs);
     return hipGetLastError();
   }));
-  return mark("k_restrict", 0);
+  return mark("k_down3d_march", 0);
 }
 
 template <class TI, class TM>
@@ -2827,7 +2870,7 @@ hipError_t Multigrid<TI, TM>::march3d_up(int stage, Vec x2, Vec ec, Vec b, Vec x
   const LevelOp<C> op = make_op<C>(h_, 0, a_[stage]);
   const C omega = (C)h_->omega;
   const C es = (C)(1.0 / h_->mg_scale);
-  const March3Geo g = march3_geo(h_->lev_n[0], B);
+  const March3Geo g = march3_geo(h_->lev_n[0], B, 2);
   const dim3 grid((unsigned)(g.ntx * g.ntx * g.nz), (unsigned)B);
   const int nc = h_->lev_n[1];
   MG_TRY(typed1(1, [&](auto tc) {
@@ -2902,14 +2945,13 @@ hipError_t Multigrid<TI, TM>::vcycle(int l, int stage, Vec x, Vec b, bool zero_i
     return hipSuccess;
   }
   if (march3d_ok(l, zero_init, pre, B)) {
-    // z-marches: sweeps and residual -> full weighting -> coarse cycle ->
+    // z-marches: sweeps, residual and full weighting -> coarse cycle ->
     // prolongation and sweeps
     const int64_t Nc = h_->lev_N[1];
-    Vec r{h_->ws + P.mgR[0], Nl};
     Vec bc{h_->ws + P.mgB[1], Nc};
     Vec xc{h_->ws + P.mgX[1], Nc};
     const bool next_grid = 1 < l0_;
-    MG_TRY(march3d_down(stage, b, tmp, r, bc, xc, next_grid, B));
+    MG_TRY(march3d_down(stage, b, tmp, bc, xc, next_grid, B));
     Vec ec{};
     MG_TRY(vcycle(1, stage, xc, bc, true, next_grid, B, &ec));
     MG_TRY(march3d_up(stage, tmp, ec, b, x, B));

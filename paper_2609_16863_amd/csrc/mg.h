@@ -73,10 +73,11 @@ class Multigrid {
                     const Coupling* cpl = nullptr);
   hipError_t up2d(int l, int stage, Vec xin, Vec ec, Vec b, Vec xout, int B);
   // 3D level 0 as z-marches (constant kappa, two sweeps each way, zero
-  // start, from tall_min_b blocks per launch on): sweeps and residual, then
-  // the full weighting; prolongation and sweeps into xout (!= x2)
+  // start, from tall_min_b blocks per launch on): sweeps, residual and full
+  // weighting into bc (and the coarse first sweep into xc); prolongation and
+  // sweeps into xout (!= x2)
   bool march3d_ok(int l, bool zero_init, bool pre, int B) const;
-  hipError_t march3d_down(int stage, Vec b, Vec x2, Vec r, Vec bc, Vec xc, bool zero_next, int B);
+  hipError_t march3d_down(int stage, Vec b, Vec x2, Vec bc, Vec xc, bool zero_next, int B);
   hipError_t march3d_up(int stage, Vec x2, Vec ec, Vec b, Vec xout, int B);
   const C* coarse_inv(int stage) const;
 
