@@ -245,16 +245,18 @@ def test_apply_mg_coarse_max_1024(n, tail_max):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5), ("fp16", 1e-3)])
-@pytest.mark.parametrize("n,nt", [(12, 2), (17, 3), (45, 2), (64, 9)])
+@pytest.mark.parametrize("n,nt", [(7, 2), (8, 3), (12, 2), (17, 3), (45, 2), (64, 9)])
 def test_apply_mg_3d_level0_march_equals_grid(precision, tol, n, nt):
     """From tall_min_b blocks on, a zero-start V-cycle of the 3D operator
-    runs level 0 as two z-marches (32 x 32 column tiles with a two-node halo,
-    chunks of 16 or 32 planes): the first sweep, the second and the residual
-    in one; the prolongation and both post-smoothing sweeps in the other.
+    runs level 0 as two z-marches (32 x 32 column tiles with a three- and a
+    two-node halo, chunks of 16 or 32 planes): the first sweep, the second,
+    the residual and its full weighting in one; the prolongation and both
+    post-smoothing sweeps in the other.
     They apply the grid kernels' arithmetic to every node, so the cycles
     agree bit for bit with tall_min_b = 2^30 (every launch on the grid
-    kernels): one tile and one chunk (12), a one-plane last chunk (17),
-    ragged tiles and chunks (45), several of each (64).  A second cycle
+    kernels): the smallest grids that coarsen (7 and 8: coarse sides 3 and
+    4), one tile and one chunk (12), a one-plane last chunk (17), ragged
+    tiles and chunks (45), several of each (64).  A second cycle
     starts from a nonzero iterate and runs the grid kernels on level 0 in
     both.  Block 0 is checked against the oracle."""
     require_gpu()
