@@ -217,7 +217,7 @@ def main():
     del x_mix
 
     # ---- the other workloads (3D in four precisions, the uneven batch) --------
-    extra = None if args.no_extras else extras(args, tune is not None)
+    extra = None if args.no_extras else extras(args, tune is not None and tune["source"] == "autotune")
 
     out = {
         "metric": METRIC, "value": total_s / args.steps, "unit": "s", "n_gpus": 1,
@@ -646,12 +646,15 @@ def extras(args, autotune):
         return (np.arange(nt)[:, None] + tableaux[s][None, :]) * (T / nt)
 
     w3 = heat_inputs.WORKLOADS["heat3d_n128_s3_nt32"]
-    res3 = {}
+    res3, shapes3 = {}, {}
     for prec in ["fp64", "fp32", "bf16", "fp16"]:
         hp = HeatProblem(w3.dim, w3.n, w3.s, w3.nt, w3.T, restart=w3.restart, tol=1e-8, inner_k=args.inner_k,
                          precision=prec, schur=args.schur, mgrit_cf=args.mgrit_cf,
                          mgrit_coarse_k=args.mgrit_coarse_k, schur_k=args.schur_k, inner_orth=args.inner_orth,
                          outer_orth=args.outer_orth)
+        if autotune:   # launch shapes from the library's autotuner, as for the main workload
+            t = hp.autotune(reps=3)
+            shapes3[prec] = {"tall_min_b": t["tall_min_b"], "tail_extend": t["tail_extend"]}
         f, u0 = heat_inputs.workload_inputs(w3, hp.stage_times())
         rhs = hp.assemble_rhs(torch.from_numpy(np.ascontiguousarray(f.ravel())).cuda(), torch.from_numpy(u0).cuda())
         del f
@@ -674,7 +677,7 @@ def extras(args, autotune):
     out[w3.name] = {"unknowns": w3.n ** 3 * (w3.nt * (w3.s + 1) + 1), "restart": w3.restart, "inner_k": args.inner_k,
                     "schur": args.schur, "mgrit_cf": args.mgrit_cf, "mgrit_coarse_k": args.mgrit_coarse_k,
                     "schur_k": args.schur_k, "inner_orth": args.inner_orth, "outer_orth": args.outer_orth,
-                    "solves": res3, "roofline_apply_A": apply3}
+                    "solves": res3, "roofline_apply_A": apply3, "launch_shapes": shapes3 or "library default"}
     specs = heat_inputs.batch_problem_specs()
     data = []
     for sp in specs:
