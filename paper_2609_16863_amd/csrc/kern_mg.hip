@@ -1946,14 +1946,15 @@ int tail_fast_layout(TailFastArgs<C>& ta, int nls) {
 
 // ---------------------------------------------------------------------------
 // 3D level 0 (constant kappa) as z-marches.  A workgroup owns a 32 x 32
-// thread tile of (x, y) columns -- its 28 x 28 core plus a two-node halo --
-// and walks a chunk of z-planes.  Each plane step runs three pipelined
-// stages (stage 2 on the plane one behind stage 1, stage 3 two behind); a
+// thread tile of (x, y) columns -- a core plus a halo of three (down) or two
+// (up) nodes -- and walks a chunk of z-planes.  Each plane step runs
+// pipelined stages, each on the plane one behind the stage before; a
 // stage's z-neighbours stay in the thread's registers, its (x, y)-neighbours
 // come from the previous step's plane in LDS (two slots per stage, one
 // barrier per step).  Every stencil application shrinks the valid region by
 // one node, so the halo rings compute values only the core consumes.  The
-// arithmetic is that of k_smooth / k_residual / k_prolong, node by node.
+// arithmetic is that of k_smooth / k_residual / k_restrict / k_prolong,
+// node by node.
 // ---------------------------------------------------------------------------
 constexpr int M3_T = 32;          // threads per tile side
 
@@ -1994,8 +1995,8 @@ struct March3Pos {
 // memory clobber keeps the compiler from moving LDS accesses across it.
 __device__ __forceinline__ void m3_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// h^2 K at the thread's node of plane slot s: (x, y)-neighbours from the
-// LDS plane (the tile's edge threads read themselves: their results are
+// h^2 K at the thread's node: (x, y)-neighbours from the LDS plane pl
+// (the tile's edge threads read themselves: their results are
 // never used), z-neighbours zm, zp from registers.  Same expression as
 // stencil_K (values past the grid are the zeros the neighbours stored).
 template <class C>
