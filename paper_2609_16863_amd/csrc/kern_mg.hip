@@ -142,6 +142,122 @@ __device__ __forceinline__ void level_apply(const T* __restrict__ x, const Level
          op.a * (ri.t[1] * rj.m[1] * rk.m[1] + ri.m[1] * rj.t[1] * rk.m[1] + ri.m[1] * rj.m[1] * rk.t[1]);
 }
 
+// (A x) and the diagonal at nodes (i, j, k) and (i, j, k + 1) of a 3D
+// Galerkin level (has1: the second node exists).  The two share the row
+// sums of planes k and k + 1, so a thread forms 12 of them instead of 18;
+// each node adds its terms in level_apply's order, so both results are
+// bitwise level_apply's.
+template <class T, class C>
+__device__ __forceinline__ void tensor3_apply2(const T* __restrict__ x, const LevelOp<C>& op, int p, int i, int j,
+                                               int k, bool has1, C (&Ax)[2], C (&diag)[2]) {
+  const int n = op.n, nn = n * n;
+  const Tri3<C> ri = tri_row(op.tri, n, i), rj = tri_row(op.tri, n, j);
+  C mi_at[3], ti_at[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    mi_at[q] = ri.m[q] + op.a * ri.t[q];
+    ti_at[q] = ri.m[q];
+  }
+  // row sums of planes k - 1 .. k + 2, rows j - 1 .. j + 1
+  C pv[4][3], qv[4][3];
+#pragma unroll
+  for (int pk = 0; pk < 4; ++pk) {
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj) {
+      pv[pk][dj + 1] = C(0);
+      qv[pk][dj + 1] = C(0);
+      const int kk = k - 1 + pk, jj = j + dj;
+      if (kk < 0 || kk >= n || jj < 0 || jj >= n) continue;
+      const int base = p + (pk - 1) * nn + dj * n;
+#pragma unroll
+      for (int di = -1; di <= 1; ++di) {
+        const int ii = i + di;
+        if (ii < 0 || ii >= n) continue;
+        const C xv = ld<T, C>(x + base + di);
+        pv[pk][dj + 1] += mi_at[di + 1] * xv;
+        qv[pk][dj + 1] += ti_at[di + 1] * xv;
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    if (u == 1 && !has1) break;
+    const int ku = k + u;
+    const Tri3<C> rk = tri_row(op.tri, n, ku);
+    C acc = C(0);
+#pragma unroll
+    for (int dk = -1; dk <= 1; ++dk) {
+      const int kk = ku + dk;
+      if (kk < 0 || kk >= n) continue;
+#pragma unroll
+      for (int dj = -1; dj <= 1; ++dj) {
+        const int jj = j + dj;
+        if (jj < 0 || jj >= n) continue;
+        const C mm = rj.m[dj + 1] * rk.m[dk + 1];
+        const C tm = rj.t[dj + 1] * rk.m[dk + 1] + rj.m[dj + 1] * rk.t[dk + 1];
+        acc += mm * pv[u + dk + 1][dj + 1] + op.a * tm * qv[u + dk + 1][dj + 1];
+      }
+    }
+    Ax[u] = acc;
+    diag[u] = ri.m[1] * rj.m[1] * rk.m[1] +
+              op.a * (ri.t[1] * rj.m[1] * rk.m[1] + ri.m[1] * rj.t[1] * rk.m[1] + ri.m[1] * rj.m[1] * rk.t[1]);
+  }
+}
+
+// Thread t of a 3D Galerkin level owns nodes (i, j, 2 kp) and (i, j, 2 kp + 1).
+__device__ __forceinline__ bool pair_coords(int t, int n, int& i, int& j, int& k, bool& has1) {
+  const int nn = n * n, kp = t / nn, r = t - kp * nn;
+  j = r / n;
+  i = r - j * n;
+  k = 2 * kp;
+  has1 = k + 1 < n;
+  return k < n;
+}
+
+// k_smooth on a 3D Galerkin level, two nodes (consecutive in z) per thread.
+template <class T, class C>
+__global__ __launch_bounds__(TPB) void k_smooth3t(const T* __restrict__ xin, int64_t sxin, T* xout, int64_t sxout,
+                                                  const T* __restrict__ b, int64_t sb, LevelOp<C> op, C omega,
+                                                  int zero_init) {
+  int i, j, k;
+  bool has1;
+  if (!pair_coords(blockIdx.x * TPB + threadIdx.x, op.n, i, j, k, has1)) return;
+  const int64_t inst = blockIdx.y;
+  const int p = (k * op.n + j) * op.n + i, nn = op.n * op.n;
+  const T* x = xin + inst * sxin;
+  const T* bb = b + inst * sb;
+  T* xo = xout + inst * sxout;
+  if (zero_init) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      if (u == 0 || has1)
+        st<T, C>(xo + p + u * nn, omega * ld<T, C>(bb + p + u * nn) / level_diag<3, KIND_TENSOR, C>(op, p + u * nn, i, j, k + u));
+    return;
+  }
+  C Ax[2], d[2];
+  tensor3_apply2<T, C>(x, op, p, i, j, k, has1, Ax, d);
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+    if (u == 0 || has1)
+      st<T, C>(xo + p + u * nn, ld<T, C>(x + p + u * nn) + omega * (ld<T, C>(bb + p + u * nn) - Ax[u]) / d[u]);
+}
+
+// k_residual on a 3D Galerkin level, two nodes (consecutive in z) per thread.
+template <class T, class C>
+__global__ __launch_bounds__(TPB) void k_residual3t(const T* __restrict__ x, int64_t sx, const T* __restrict__ b,
+                                                    int64_t sb, T* __restrict__ r, int64_t sr, LevelOp<C> op) {
+  int i, j, k;
+  bool has1;
+  if (!pair_coords(blockIdx.x * TPB + threadIdx.x, op.n, i, j, k, has1)) return;
+  const int64_t inst = blockIdx.y;
+  const int p = (k * op.n + j) * op.n + i, nn = op.n * op.n;
+  C Ax[2], d[2];
+  tensor3_apply2<T, C>(x + inst * sx, op, p, i, j, k, has1, Ax, d);
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+    if (u == 0 || has1) st<T, C>(r + inst * sr + p + u * nn, ld<T, C>(b + inst * sb + p + u * nn) - Ax[u]);
+}
+
 // x_out = x_in + omega D^{-1} (b - A x_in);  zero_init: x_out = omega D^{-1} b.
 template <int DIM, int KIND, class T, class C>
 __global__ __launch_bounds__(TPB) void k_smooth(const T* __restrict__ xin, int64_t sxin, T* xout,
@@ -2341,6 +2457,14 @@ LevelOp<C> make_op(const aao_problem* h, int l, double a) {
 }
 
 inline dim3 grid2(int64_t N, int B) { return dim3((unsigned)((N + TPB - 1) / TPB), (unsigned)B); }
+// threads of the two-nodes-per-thread 3D Galerkin kernels: n^2 ceil(n / 2)
+inline int64_t pair_threads(int n) { return (int64_t)n * n * ((n + 1) / 2); }
+// Two nodes per thread pay with FP32 arithmetic on launches of about a
+// million nodes and more (measured on MI355X at 128^3: 64^3 level with 7 to
+// 32 blocks, 32^3 with 32); smaller launches need the threads of one node
+// each, and FP64 the registers.
+template <class C>
+inline bool pairs3(int64_t N, int B) { return sizeof(C) == 4 && N * B >= (int64_t)1 << 20; }
 
 }  // namespace
 
@@ -2481,7 +2605,8 @@ hipError_t Multigrid<TI, TM>::smooth(int l, int stage, Vec xin, Vec xout, Vec b,
   } else {
     return typed1(l, [&](auto t) {
       using TL = decltype(t);
-      if (d3) hipLaunchKernelGGL((k_smooth<3, KIND_TENSOR, TL, C>), g, dim3(TPB), 0, st_, (const TL*)xin.ptr, xin.stride, (TL*)xout.ptr, xout.stride, (const TL*)b.ptr, b.stride, op, omega, (int)zero_init);
+      if (d3 && pairs3<C>(op.N, B)) hipLaunchKernelGGL((k_smooth3t<TL, C>), grid2(pair_threads(op.n), B), dim3(TPB), 0, st_, (const TL*)xin.ptr, xin.stride, (TL*)xout.ptr, xout.stride, (const TL*)b.ptr, b.stride, op, omega, (int)zero_init);
+      else if (d3) hipLaunchKernelGGL((k_smooth<3, KIND_TENSOR, TL, C>), g, dim3(TPB), 0, st_, (const TL*)xin.ptr, xin.stride, (TL*)xout.ptr, xout.stride, (const TL*)b.ptr, b.stride, op, omega, (int)zero_init);
       else hipLaunchKernelGGL((k_smooth<2, KIND_TENSOR, TL, C>), g, dim3(TPB), 0, st_, (const TL*)xin.ptr, xin.stride, (TL*)xout.ptr, xout.stride, (const TL*)b.ptr, b.stride, op, omega, (int)zero_init);
       return hipGetLastError();
     });
@@ -2516,6 +2641,9 @@ hipError_t Multigrid<TI, TM>::resid_restrict(int l, int stage, Vec x, Vec b, Vec
           return hipErrorInvalidValue;
       } else if (l == 0) {
         RES(3, KIND_FINE);
+      } else if (pairs3<C>(opf.N, B)) {
+        hipLaunchKernelGGL((k_residual3t<TF, C>), grid2(pair_threads(opf.n), B), dim3(TPB), 0, st_, (const TF*)x.ptr,
+                           x.stride, (const TF*)b.ptr, b.stride, (TF*)r.ptr, r.stride, opf);
       } else {
         RES(3, KIND_TENSOR);
       }
