@@ -484,8 +484,10 @@ def _kernel_matches(name, base, level0):
     i = name.find(base + "<")
     if i < 0:
         return False
-    kind = int(name[i + len(base) + 1:].split(",")[0])
-    return (kind <= 1) == level0
+    first = name[i + len(base) + 1:].split(",")[0].split(">")[0].strip()
+    if not first.lstrip("-").isdigit():   # no level kind in the template: a level-0 kernel (3D marches)
+        return level0
+    return (int(first) <= 1) == level0
 
 
 def traffic_summary(fetch_csv, write_csv, roof_json):
@@ -501,10 +503,13 @@ def traffic_summary(fetch_csv, write_csv, roof_json):
     nbytes = roof["copy_reference"]["bytes"]
 
     def copy_kib(rows):
+        # the reference copy is the run's last copy dispatch (--roofline-only
+        # times it last; earlier copies, such as the right-hand side's, have
+        # other sizes)
         vals = [v for name, wg, v in rows if "copyBuffer" in name]
         if not vals:
             raise SystemExit("no copy dispatch in the counter run")
-        return max(vals)
+        return vals[-1]
 
     f_scale = nbytes / 1024 / copy_kib(fetch)
     w_scale = nbytes / 1024 / copy_kib(write)
@@ -514,13 +519,15 @@ def traffic_summary(fetch_csv, write_csv, roof_json):
              "| group | launch | blocks | workgroups | launches per P-tilde | FETCH_SIZE KiB | WRITE_SIZE KiB "
              "| scaled bytes | algorithmic bytes | ratio |", "|---|---|---|---|---|---|---|---|---|---|"]
     per_group = {}
+    unmatched = []
     for sym, grp in sorted(prof["by_kernel"].items()):
         base = sym.split("<")[0]
         level0 = "<level 0" in sym
         tot_w = tot_meas = tot_alg = 0.0
+        if any(m["workgroups"] is None or m["bytes_per_launch"] is None for m in grp["members"]):
+            unmatched.append(sym)   # no grid size (3D grid kernels) or no byte count: not matched
+            continue
         for m in grp["members"]:
-            if m["workgroups"] is None:
-                raise SystemExit(f"no grid size known for {m['label']}")
             fv = [v for name, wg, v in fetch if wg == m["workgroups"] and _kernel_matches(name, base, level0)]
             wv = [v for name, wg, v in write if wg == m["workgroups"] and _kernel_matches(name, base, level0)]
             if not fv or not wv:
@@ -534,6 +541,8 @@ def traffic_summary(fetch_csv, write_csv, roof_json):
             tot_meas += m["weight"] * meas
             tot_alg += m["weight"] * alg
         per_group[sym] = (tot_meas / tot_w, tot_alg / tot_w)
+    if unmatched:
+        lines += ["", "groups without a known grid size or byte count (not matched): " + ", ".join(unmatched)]
     lines += ["", "| group | measured bytes per launch | algorithmic bytes per launch | ratio |", "|---|---|---|---|"]
     for sym, (meas, alg) in per_group.items():
         lines.append(f"| {sym} | {meas:,.0f} | {alg:,.0f} | {meas / alg:.3f} |")
